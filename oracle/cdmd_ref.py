@@ -1,0 +1,359 @@
+"""Plain FP64 CPU oracle for compressed DMD background modeling.
+
+TEST INFRASTRUCTURE ONLY.  Only tests/, __graft_entry__.smoke() and bench.py's CPU
+baseline may import this module.  It shares no code with the HIP path and must never
+be used to produce a product result.
+
+Follows Erichson, Brunton and Kutz, "Compressed Dynamic Mode Decomposition for
+Background Modeling":
+
+* snapshot split X, X' (Section 2.1, eq. FullData);
+* sketch Y = C X, Y' = C X' (Section 3.2, eq. (eq:YCX)) with Gaussian, sparse +/-1
+  or single-pixel C (Section 3.3);
+* truncated SVD of Y, A~ = U* Y' V S^-1, eig(A~) = (W, Lambda), full modes
+  Phi = X' V S^-1 W, amplitudes b = lstsq(Phi, x_1) (Section 3.2, Algorithm 1,
+  eq. (eq:b), eq. (Eq:cDMDModes));
+* Vandermonde matrix lambda_j^(t-1) (Section 2.1, the factorisation Phi B V);
+* background L = Re(sum over selected modes b_p phi_p lambda_p^(t-1)) (Section 2.2,
+  eq. (equ:DMDTerms) and its footnote on the real part);
+* sparsity-constrained amplitudes by orthogonal matching pursuit (Section 2.3,
+  eq. (eq:sparsecoding));
+* foreground mask |x_jt - xhat_jt| > tau (Section 4, eq. (eq:thres));
+* recall, precision, F-measure (Section 4).
+
+Numerical route: direct SVD of Y, LAPACK eig, direct least squares and explicit-
+residual OMP, all in float64 / complex128.  Where the paper is silent the readings
+adopted are stated at each function (eigenvector normalisation, canonical mode order,
+OMP ties, rank tolerance, strict threshold).
+
+Pixel values: uint8 frames are scaled by 1/255; float frames are used as they are.
+Frames are given frame-major, D of shape (m, n) (frame t is row t); X = D^T.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import philox
+
+# rank test: sigma_k <= RANK_TOL * sigma_1 is rank deficient (the paper sets no
+# tolerance; 1e-6 is what a Gram-based route can still resolve in float64)
+RANK_TOL = 1e-6
+# ties in OMP correlations and in the canonical order, relative
+TIE_REL = 1e-9
+# OMP stops early when ||r|| <= OMP_STOP_REL * ||x_1||
+OMP_STOP_REL = 1e-12
+# |lambda|^(m-1) above this overflows the Vandermonde matrix
+VANDER_MAX = 1e30
+
+
+class RankDeficient(ValueError):
+    pass
+
+
+class NumericError(ValueError):
+    pass
+
+
+# ---------------------------------------------------------------- data access
+def pixel_rows(D: np.ndarray, scale: float, i0: int = 0, i1: Optional[int] = None,
+               pixels: Optional[np.ndarray] = None) -> np.ndarray:
+    """Rows of the snapshot matrix [x_1 ... x_m] (pixels x frames) in float64:
+    pixel range [i0, i1) or an explicit pixel index list."""
+    if pixels is not None:
+        blk = D[:, np.asarray(pixels)]
+    else:
+        blk = D[:, i0:(D.shape[1] if i1 is None else i1)]
+    return blk.T.astype(np.float64) * scale
+
+
+# ---------------------------------------------------------------- sketches
+def sketch_sparse(D: np.ndarray, scale: float, idx: np.ndarray, sign: np.ndarray):
+    """Y^ = C D for a sparse +/-1 (or single-pixel, weight +1) C given by its index
+    table idx (p, nnz) and signs (p, nnz).  Integer frames are summed exactly in
+    int64 before scaling.  Returns (Y^ float64 (p, m), integer sums or None)."""
+    m, n = D.shape
+    p, nnz = idx.shape
+    if np.issubdtype(D.dtype, np.integer):
+        acc = np.zeros((m, p), dtype=np.int64)
+        for j in range(nnz):
+            acc += D[:, idx[:, j]].astype(np.int64) * sign[:, j].astype(np.int64)[None, :]
+        return acc.T.astype(np.float64) * scale, acc.T.copy()
+    acc = np.zeros((m, p), dtype=np.float64)
+    for j in range(nnz):
+        acc += D[:, idx[:, j]].astype(np.float64) * sign[:, j].astype(np.float64)[None, :]
+    return acc.T * scale, None
+
+
+def gaussian_C(seed: int, p: int, j0: int, j1: int, quantise=None) -> np.ndarray:
+    """Dense Gaussian C restricted to pixel columns [j0, j1): entries N(0, 1/p).
+    ``quantise`` (a callable on float64 arrays) rounds the N(0,1) draws to a storage
+    format before the 1/sqrt(p) scale (the quantised-C reading of a low-precision
+    sketch)."""
+    z = philox.gaussian_block(seed, 0, p, j0, j1)
+    if quantise is not None:
+        z = quantise(z)
+    return z / np.sqrt(p)
+
+
+def sketch_gaussian(D: np.ndarray, scale: float, seed: int, p: int, chunk: int = 8192,
+                    quantise=None, rows: Optional[Sequence[int]] = None) -> np.ndarray:
+    """Y^ = C D with dense Gaussian C, accumulated over pixel chunks in float64.
+    ``rows`` restricts the output to a subset of sketch rows."""
+    m, n = D.shape
+    Y = np.zeros((p if rows is None else len(rows), m))
+    for j0 in range(0, n, chunk):
+        j1 = min(n, j0 + chunk)
+        C = gaussian_C(seed, p, j0, j1, quantise)
+        if rows is not None:
+            C = C[np.asarray(rows)]
+        Y += C @ pixel_rows(D, scale, j0, j1)
+    return Y
+
+
+def _round_sig(z: np.ndarray, mant_bits: int, emin: int) -> np.ndarray:
+    """Round to nearest with ties to even onto a binary format with ``mant_bits``
+    stored mantissa bits and minimum normal exponent ``emin`` (subnormals below),
+    in one rounding step from float64."""
+    z = np.asarray(z, dtype=np.float64)
+    a = np.abs(z)
+    _, E = np.frexp(a)                     # a = f 2^E, f in [0.5, 1)
+    e = np.maximum(E - 1, emin)
+    q = np.ldexp(1.0, e - mant_bits)
+    return np.sign(z) * (np.round(a / q) * q)
+
+
+def round_bf16(z: np.ndarray) -> np.ndarray:
+    """Round float64 to the nearest bfloat16 (8-bit exponent, 7 stored mantissa
+    bits), ties to even."""
+    return _round_sig(z, 7, -126)
+
+
+def round_e4m3(z: np.ndarray) -> np.ndarray:
+    """Round float64 to OCP FP8 e4m3fn (bias 7, 3 mantissa bits, no infinities,
+    largest finite 448), ties to even, saturating to +/-448."""
+    return np.clip(_round_sig(z, 3, -6), -448.0, 448.0)
+
+
+# ---------------------------------------------------------------- fit
+@dataclasses.dataclass
+class Model:
+    lam: np.ndarray          # (k,) complex eigenvalues, canonical order
+    W: np.ndarray            # (k, k) eigenvectors of A~ (columns), normalised
+    sigma: np.ndarray        # (k,) singular values of Y
+    V: np.ndarray            # (m-1, k) right singular vectors of Y
+    Atilde: np.ndarray       # (k, k)
+    G: np.ndarray            # (m-1, k) complex V S^-1 W: Phi = X' G
+    Phi: Optional[np.ndarray]   # (n, k) complex full modes (None when not formed)
+    b: Optional[np.ndarray]     # (k,) complex amplitudes
+    phi_norm: Optional[np.ndarray]
+
+
+def normalise_eigvecs(W: np.ndarray) -> np.ndarray:
+    """Unit 2-norm columns; the largest-modulus entry of each column (lowest index on
+    ties) is made real and positive."""
+    W = W / np.linalg.norm(W, axis=0, keepdims=True)
+    piv = np.argmax(np.abs(W), axis=0)
+    ph = W[piv, np.arange(W.shape[1])]
+    return W * (np.abs(ph) / ph)[None, :]
+
+
+def canonical_order(lam: np.ndarray, key: np.ndarray) -> np.ndarray:
+    """Descending key = |b_j| * ||phi_j||; adjacent keys equal to TIE_REL (conjugate
+    partners) are ordered with the positive-imaginary eigenvalue first."""
+    o = list(np.argsort(-key, kind="stable"))
+    for i in range(len(o) - 1):
+        a, c = o[i], o[i + 1]
+        if abs(key[a] - key[c]) <= TIE_REL * max(key[a], key[c]) and lam[a].imag < lam[c].imag:
+            o[i], o[i + 1] = c, a
+    return np.array(o, dtype=np.int64)
+
+
+def reduced_operator(Yhat: np.ndarray, k: int):
+    """Algorithm 1 steps (1), (4), (6), (7) on the sketch: returns
+    (lam, W, sigma, V, Atilde).  Raises RankDeficient if sigma_k <= RANK_TOL sigma_1."""
+    p, m = Yhat.shape
+    if not (m >= 2 and 1 <= k <= min(p, m - 1)):
+        raise ValueError("need m >= 2 and 1 <= k <= min(p, m-1)")
+    Y, Yp = Yhat[:, :m - 1], Yhat[:, 1:]
+    U, s, Vh = np.linalg.svd(Y, full_matrices=False)
+    if not s[0] > 0 or s[k - 1] <= RANK_TOL * s[0]:
+        raise RankDeficient(f"sigma_k/sigma_1 = {s[k-1] / max(s[0], 1e-300):.3e}")
+    U, s, V = U[:, :k], s[:k], Vh[:k].conj().T
+    Atilde = U.conj().T @ Yp @ (V / s[None, :])
+    lam, W = np.linalg.eig(Atilde)
+    W = normalise_eigvecs(W)
+    return lam, W, s, V, Atilde
+
+
+def lift(D: np.ndarray, scale: float, G: np.ndarray, pixels: Optional[np.ndarray] = None,
+         chunk: int = 65536) -> np.ndarray:
+    """Full modes Phi = X' G (eq. Eq:cDMDModes with G = V S^-1 W), for all pixels or a
+    pixel subset; X' = [x_2 ... x_m]."""
+    if pixels is not None:
+        return pixel_rows(D, scale, pixels=pixels)[:, 1:] @ G
+    n = D.shape[1]
+    out = np.empty((n, G.shape[1]), dtype=np.complex128)
+    for i0 in range(0, n, chunk):
+        i1 = min(n, i0 + chunk)
+        Xp = pixel_rows(D, scale, i0, i1)[:, 1:]
+        out[i0:i1] = Xp @ G.real + 1j * (Xp @ G.imag)
+    return out
+
+
+def fit(D: np.ndarray, scale: float, Yhat: np.ndarray, k: int, form_phi: bool = True) -> Model:
+    """Algorithm 1 (cdmd) given the sketch Y^ = C D: SVD, A~, eig, Phi, b; modes in
+    canonical order."""
+    lam, W, s, V, At = reduced_operator(Yhat, k)
+    G = (V / s[None, :]) @ W
+    if not form_phi:
+        return Model(lam, W, s, V, At, G, None, None, None)
+    Phi = lift(D, scale, G)
+    x1 = D[0].astype(np.float64) * scale
+    b = np.linalg.lstsq(Phi, x1.astype(np.complex128), rcond=None)[0]
+    nrm = np.linalg.norm(Phi, axis=0)
+    o = canonical_order(lam, np.abs(b) * nrm)
+    return Model(lam[o], W[:, o], s, V, At, G[:, o], Phi[:, o], b[o], nrm[o])
+
+
+# ---------------------------------------------------------------- exact DMD (pins)
+def dmd_bruteforce(X: np.ndarray, Xp: np.ndarray):
+    """A^ = X' X^+ formed explicitly (n x n), Section 2.1; returns (eigvals, A^)."""
+    Ahat = Xp @ np.linalg.pinv(X)
+    return np.linalg.eigvals(Ahat), Ahat
+
+
+def dmd_exact(x: np.ndarray, k: int):
+    """Exact DMD on the full snapshot matrix x (n x m): the cDMD steps with C = I."""
+    X, Xp = x[:, :-1], x[:, 1:]
+    U, s, Vh = np.linalg.svd(X, full_matrices=False)
+    U, s, V = U[:, :k], s[:k], Vh[:k].conj().T
+    At = U.conj().T @ Xp @ (V / s[None, :])
+    lam, W = np.linalg.eig(At)
+    W = normalise_eigvecs(W)
+    Phi = Xp @ (V / s[None, :]) @ W
+    b = np.linalg.lstsq(Phi, x[:, 0].astype(np.complex128), rcond=None)[0]
+    return lam, Phi, b
+
+
+# ---------------------------------------------------------------- selection
+def omp(Phi: np.ndarray, x1: np.ndarray, K: int):
+    """Orthogonal matching pursuit for eq. (eq:sparsecoding), explicit residual form:
+    r = x_1; repeat: pick the unselected mode maximising |phi_j^H r| / ||phi_j||
+    (ties within TIE_REL of the maximum go to the lowest index), project x_1 onto the
+    selected modes by least squares, recompute r; stop after min(K, k) atoms or when
+    ||r|| <= OMP_STOP_REL ||x_1||.  Returns (support in selection order, beta_S)."""
+    n, k = Phi.shape
+    x1 = x1.astype(np.complex128)
+    nrm = np.linalg.norm(Phi, axis=0)
+    S: list = []
+    beta = np.zeros(0, dtype=np.complex128)
+    r = x1.copy()
+    x1n = np.linalg.norm(x1)
+    for _ in range(min(K, k)):
+        corr = np.abs(Phi.conj().T @ r) / nrm
+        corr[S] = -1.0
+        best = corr.max()
+        j = int(np.flatnonzero(corr >= best - TIE_REL * best)[0])
+        S.append(j)
+        beta = np.linalg.lstsq(Phi[:, S], x1, rcond=None)[0]
+        r = x1 - Phi[:, S] @ beta
+        if np.linalg.norm(r) <= OMP_STOP_REL * x1n:
+            break
+    return np.array(S, dtype=np.int64), beta
+
+
+def select_zero_mode(lam: np.ndarray) -> np.ndarray:
+    """The single mode with continuous-time eigenvalue closest to the origin,
+    |omega| = |log lambda| with dt = 1 (Section 2.2)."""
+    return np.array([int(np.argmin(np.abs(np.log(lam.astype(np.complex128)))))])
+
+
+def select_omega(lam: np.ndarray, thr: float) -> np.ndarray:
+    """All modes with |log lambda_j| < thr (dt = 1)."""
+    return np.flatnonzero(np.abs(np.log(lam.astype(np.complex128))) < thr)
+
+
+def refit(Phi_S: np.ndarray, x1: np.ndarray) -> np.ndarray:
+    """Least-squares amplitudes of x_1 on a fixed support."""
+    return np.linalg.lstsq(Phi_S, x1.astype(np.complex128), rcond=None)[0]
+
+
+# ---------------------------------------------------------------- reconstruction
+def vandermonde(lam: np.ndarray, t0: int, t1: int) -> np.ndarray:
+    """V[j, t] = lambda_j^(t-1) for frames t = t0+1 .. t1 (1-based), by repeated
+    multiplication (0^0 = 1)."""
+    lam = np.asarray(lam, dtype=np.complex128)
+    if np.any(np.abs(lam) > 1.0) and np.max(np.abs(lam)) ** max(t1 - 1, 0) > VANDER_MAX:
+        raise NumericError("|lambda|^(m-1) overflows")
+    V = np.empty((lam.size, t1), dtype=np.complex128)
+    if t1:
+        V[:, 0] = 1.0
+    for t in range(1, t1):
+        V[:, t] = V[:, t - 1] * lam
+    return V[:, t0:t1]
+
+
+def background(Phi_S: np.ndarray, beta: np.ndarray, lam_S: np.ndarray, t0: int, t1: int,
+               static: bool = False) -> np.ndarray:
+    """L = Re(Phi_S diag(beta) V_S) for frames [t0, t1) (eq. equ:DMDTerms, real part),
+    or the static model Re(Phi_S beta) (Section 2.3) when ``static``."""
+    if static:
+        return (Phi_S @ beta).real
+    return (Phi_S @ (beta[:, None] * vandermonde(lam_S, t0, t1))).real
+
+
+def foreground(x: np.ndarray, L: np.ndarray, tau: float) -> np.ndarray:
+    """eq. (eq:thres): 1 where |x - xhat| > tau (strict); NaN gives 0."""
+    with np.errstate(invalid="ignore"):
+        return np.abs(x - L) > tau
+
+
+def prf(mask: np.ndarray, gt: np.ndarray):
+    """Recall TP/(TP+FN), precision TP/(TP+FP), F = 2PR/(P+R); 0 on empty
+    denominators (Section 4)."""
+    mask = np.asarray(mask, bool)
+    gt = np.asarray(gt, bool)
+    tp = float(np.count_nonzero(mask & gt))
+    fp = float(np.count_nonzero(mask & ~gt))
+    fn = float(np.count_nonzero(~mask & gt))
+    R = tp / (tp + fn) if tp + fn else 0.0
+    P = tp / (tp + fp) if tp + fp else 0.0
+    F = 2 * P * R / (P + R) if P + R else 0.0
+    return R, P, F
+
+
+# ---------------------------------------------------------------- driver
+@dataclasses.dataclass
+class Pipeline:
+    model: Model
+    Yhat: np.ndarray
+    support: np.ndarray
+    beta: np.ndarray
+
+
+def run(D: np.ndarray, scale: float, k: int, *, sketch: str, p: int = 0,
+        idx: Optional[np.ndarray] = None, sign: Optional[np.ndarray] = None,
+        seed: int = 0, K: int = 10, selector: str = "omp") -> Pipeline:
+    """Sketch -> fit -> selection, all in float64 (the stages before the mask)."""
+    if sketch in ("sparse", "spixel"):
+        Yhat, _ = sketch_sparse(D, scale, idx, sign)
+    elif sketch == "gaussian":
+        Yhat = sketch_gaussian(D, scale, seed, p)
+    else:
+        raise ValueError(sketch)
+    mdl = fit(D, scale, Yhat, k)
+    x1 = D[0].astype(np.float64) * scale
+    if selector == "omp":
+        S, beta = omp(mdl.Phi, x1, K)
+    elif selector == "zero_mode":
+        S = select_zero_mode(mdl.lam)
+        beta = mdl.b[S]
+    elif selector == "all":
+        S = np.arange(k)
+        beta = mdl.b
+    else:
+        raise ValueError(selector)
+    return Pipeline(mdl, Yhat, S, beta)

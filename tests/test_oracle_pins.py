@@ -1,0 +1,352 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test checks the oracle against something other than itself: a brute-force
+construction, a closed form, a known input decomposition, an invariance, a textbook
+property or an independent library routine.
+"""
+import os
+
+import numpy as np
+import pytest
+import scipy.stats
+import torch
+
+import synthvideo as sv
+from oracle import cdmd_ref as R
+from oracle import philox
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ helpers (inputs)
+def lowrank_video(n, m, n_pairs, reals=(), seed=0, static=True):
+    """x_t = s + sum_j Re(psi_j mu_j^(t-1)) + sum_r d_r nu_r^(t-1), exactly DMD-
+    representable.  Returns D (m, n), true eigenvalues, true b_j phi_j columns."""
+    rng = np.random.default_rng(seed)
+    lam, cols = [], []
+    X = np.zeros((n, m))
+    t = np.arange(m)
+    if static:
+        s = rng.uniform(0.2, 0.6, n)
+        X += s[:, None]
+        lam.append(1.0 + 0j)
+        cols.append(s.astype(complex))
+    for _ in range(n_pairs):
+        psi = rng.normal(size=n) + 1j * rng.normal(size=n)
+        mu = rng.uniform(0.9, 1.0) * np.exp(1j * rng.uniform(0.05, 1.0))
+        X += (psi[:, None] * mu ** t[None, :]).real
+        lam += [mu, np.conj(mu)]
+        cols += [psi / 2, np.conj(psi) / 2]
+    for nu in reals:
+        d = rng.normal(size=n)
+        X += d[:, None] * nu ** t[None, :]
+        lam.append(complex(nu))
+        cols.append(d.astype(complex))
+    return X.T.copy(), np.array(lam), np.stack(cols, axis=1)
+
+
+def match(a, b):
+    """Optimal matching of two eigenvalue lists (Hungarian on |a_i - b_j|)."""
+    from scipy.optimize import linear_sum_assignment
+    C = np.abs(a[:, None] - b[None, :])
+    r, c = linear_sum_assignment(C)
+    return r, c, C[r, c]
+
+
+def dense_from_table(idx, sign, n):
+    C = np.zeros((idx.shape[0], n))
+    for r in range(idx.shape[0]):
+        C[r, idx[r]] = sign[r]
+    return C
+
+
+# ------------------------------------------------------------------ P9: Philox KAT
+def test_philox_kat_golden():
+    for line in open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        w = [int(x, 16) for x in line.split()]
+        out = philox.philox4x32_10(*w[0:4], w[4], w[5])
+        assert [int(o) for o in out] == w[6:10]
+
+
+def test_box_muller_moments_and_ks():
+    z = philox.gaussian_block(seed=12345, r0=0, r1=200, j0=0, j1=5000).ravel()
+    assert abs(z.mean()) < 5 / np.sqrt(z.size)
+    assert abs(z.var() - 1) < 5 * np.sqrt(2 / z.size)
+    assert scipy.stats.kstest(z, "norm").pvalue > 1e-3
+    # neighbouring pixels / rows are uncorrelated
+    Z = philox.gaussian_block(seed=7, r0=0, r1=400, j0=0, j1=400)
+    assert abs(np.corrcoef(Z[:, :-1].ravel(), Z[:, 1:].ravel())[0, 1]) < 0.02
+    assert abs(np.corrcoef(Z[:-1].ravel(), Z[1:].ravel())[0, 1]) < 0.02
+
+
+def test_gaussian_block_subranges_consistent():
+    full = philox.gaussian_block(99, 0, 9, 0, 37)
+    part = philox.gaussian_block(99, 3, 7, 5, 30)
+    np.testing.assert_array_equal(full[3:7, 5:30], part)
+
+
+# ------------------------------------------------------------------ rounding formats
+def test_round_bf16_matches_torch():
+    z = np.random.default_rng(0).normal(size=20000) * 3.0
+    z = z.astype(np.float32).astype(np.float64)     # torch rounds from float32
+    ref = torch.from_numpy(z.astype(np.float32)).to(torch.bfloat16).float().double().numpy()
+    np.testing.assert_array_equal(R.round_bf16(z), ref)
+
+
+def test_round_e4m3_matches_torch():
+    z = np.random.default_rng(1).normal(size=20000) * 40.0
+    z = z[np.abs(z) < 448]
+    z = np.concatenate([z, [2.0 ** -9, 1.5 * 2.0 ** -9, 0.0, 1.0625, 1.1875]])
+    z = z.astype(np.float32).astype(np.float64)     # torch rounds from float32
+    ref = torch.from_numpy(z.astype(np.float32)).to(torch.float8_e4m3fn).float().double().numpy()
+    np.testing.assert_array_equal(R.round_e4m3(z), ref)
+    assert list(R.round_e4m3(np.array([1e4, -1e4]))) == [448.0, -448.0]
+    # one rounding step from float64 (no detour through float32)
+    assert R.round_e4m3(np.array([2.87499996]))[0] == 2.75
+    assert R.round_bf16(np.array([1.0 + 2.0 ** -8 + 2.0 ** -30]))[0] == 1.0 + 2.0 ** -7
+
+
+# ------------------------------------------------------------------ sketches
+def test_sparse_sketch_equals_dense_product():
+    rng = np.random.default_rng(3)
+    D = rng.integers(0, 256, size=(17, 300), dtype=np.uint8)
+    idx, sign = sv.sparse_table(300, 23, 32, seed=4)
+    Y, Yint = R.sketch_sparse(D, 1 / 255, idx, sign)
+    C = dense_from_table(idx, sign, 300)
+    Yref = C @ D.T.astype(np.float64)
+    np.testing.assert_array_equal(Yint, Yref.astype(np.int64))
+    np.testing.assert_allclose(Y, Yref / 255, rtol=1e-15)
+
+
+def test_gaussian_sketch_equals_dense_product():
+    rng = np.random.default_rng(5)
+    D = rng.random((9, 1000)).astype(np.float32)
+    Y = R.sketch_gaussian(D, 1.0, seed=77, p=30, chunk=128)
+    C = philox.gaussian_block(77, 0, 30, 0, 1000) / np.sqrt(30)
+    np.testing.assert_allclose(Y, C @ D.T.astype(np.float64), rtol=1e-12, atol=1e-12)
+
+
+# ------------------------------------------------------------------ P1: brute-force DMD
+def test_bruteforce_dmd_tiny():
+    rng = np.random.default_rng(11)
+    n, m = 12, 8
+    D = rng.normal(size=(m, n))
+    x = D.T
+    idx = np.arange(n, dtype=np.int32)[:, None]           # C = I
+    Y, _ = R.sketch_sparse(D, 1.0, idx, np.ones((n, 1), np.int8))
+    k = m - 1
+    mdl = R.fit(D, 1.0, Y, k)
+    ev, Ahat = R.dmd_bruteforce(x[:, :-1], x[:, 1:])
+    ev = ev[np.argsort(-np.abs(ev))][:k]                  # the nonzero ones
+    _, _, err = match(mdl.lam, ev)
+    assert err.max() < 1e-10
+    for j in range(k):                                    # A^ phi = lambda phi
+        ph = mdl.Phi[:, j]
+        assert np.linalg.norm(Ahat @ ph - mdl.lam[j] * ph) < 1e-9 * np.linalg.norm(ph)
+
+
+def test_single_pixel_full_permutation_equals_identity():
+    D, lam_true, _ = lowrank_video(60, 15, 3, seed=2)
+    k = 7
+    I = np.arange(60, dtype=np.int32)[:, None]
+    Pm, sgn = sv.single_pixel_table(60, 60, seed=9)
+    a = R.fit(D, 1.0, R.sketch_sparse(D, 1.0, I, np.ones((60, 1), np.int8))[0], k)
+    b = R.fit(D, 1.0, R.sketch_sparse(D, 1.0, Pm, sgn)[0], k)
+    np.testing.assert_allclose(a.lam, b.lam, atol=1e-12)
+    np.testing.assert_allclose(a.Phi * a.b, b.Phi * b.b, atol=1e-10)
+
+
+# ------------------------------------------------------------------ P4: low rank
+@pytest.mark.parametrize("kind", ["gaussian", "sparse"])
+@pytest.mark.parametrize("mult", [1, 2, 10])
+def test_cdmd_equals_dmd_on_exactly_low_rank(kind, mult):
+    n, m = 400, 30
+    D, lam_true, _ = lowrank_video(n, m, 3, reals=(0.97,), seed=21)
+    r = len(lam_true)
+    p = mult * r
+    if kind == "gaussian":
+        Y = R.sketch_gaussian(D, 1.0, seed=5, p=p)
+    else:
+        idx, sign = sv.sparse_table(n, p, 32, seed=6)
+        Y = R.sketch_sparse(D, 1.0, idx, sign)[0]
+    mdl = R.fit(D, 1.0, Y, r)
+    ev, _ = R.dmd_bruteforce(D.T[:, :-1], D.T[:, 1:])
+    ev = ev[np.argsort(-np.abs(ev))][:r]
+    _, _, err = match(mdl.lam, ev)
+    assert err.max() < 1e-9
+    lam_d, Phi_d, b_d = R.dmd_exact(D.T, r)
+    ri, ci, _ = match(mdl.lam, lam_d)
+    np.testing.assert_allclose(mdl.Phi[:, ri] * mdl.b[ri], Phi_d[:, ci] * b_d[ci], atol=1e-8)
+
+
+# ------------------------------------------------------------------ P5: known modes
+def test_recovers_known_modes_from_generator():
+    spec = sv.preset("cfg1", exact=True, out="f64", H=60, W=80, m=60, bump_sigma=6.0,
+                     blur_sigma=3.0, seed=31, drift=(0.97, 0.99))
+    v = sv.make_video(spec)
+    D = v.D.numpy()
+    k = len(v.bg_lambda)
+    Y = R.sketch_gaussian(D, 1.0, seed=8, p=60)
+    mdl = R.fit(D, 1.0, Y, k)
+    ri, ci, err = match(mdl.lam, v.bg_lambda)
+    assert err.max() < 1e-10
+    got = mdl.Phi[:, ri] * mdl.b[ri]
+    np.testing.assert_allclose(got, v.bg_modes[:, ci], atol=1e-9)
+    L = R.background(mdl.Phi, mdl.b, mdl.lam, 0, spec.m)
+    np.testing.assert_allclose(L, D.T, atol=1e-9)
+
+
+def test_recovers_known_modes_lowrank_sparse_sketch():
+    D, lam_true, cols = lowrank_video(3000, 40, 4, reals=(0.95,), seed=41)
+    idx, sign = sv.sparse_table(3000, 120, 32, seed=3)
+    mdl = R.fit(D, 1.0, R.sketch_sparse(D, 1.0, idx, sign)[0], len(lam_true))
+    ri, ci, err = match(mdl.lam, lam_true)
+    assert err.max() < 1e-10
+    np.testing.assert_allclose(mdl.Phi[:, ri] * mdl.b[ri], cols[:, ci], atol=1e-9)
+
+
+# ------------------------------------------------------------------ P7: invariances
+def test_invariance_to_sketch_scale():
+    D, lam_true, _ = lowrank_video(500, 25, 2, seed=51)
+    D = D + 1e-3 * np.random.default_rng(0).normal(size=D.shape)   # full rank
+    Y = R.sketch_gaussian(D, 1.0, seed=3, p=50)
+    a = R.fit(D, 1.0, Y, 8)
+    b = R.fit(D, 1.0, 37.5 * Y, 8)
+    np.testing.assert_allclose(a.lam, b.lam, rtol=1e-12)
+    np.testing.assert_allclose(a.Phi * a.b, b.Phi * b.b, rtol=1e-9, atol=1e-12)
+    np.testing.assert_allclose(a.Phi, 37.5 * b.Phi, rtol=1e-9, atol=1e-12)
+    La = R.background(a.Phi, a.b, a.lam, 0, 25)
+    Lb = R.background(b.Phi, b.b, b.lam, 0, 25)
+    np.testing.assert_allclose(La, Lb, atol=1e-11)
+
+
+def test_rank_deficient_constant_video():
+    D = np.full((10, 200), 100, dtype=np.uint8)
+    idx, sign = sv.sparse_table(200, 20, 8, seed=1)
+    Y = R.sketch_sparse(D, 1 / 255, idx, sign)[0]
+    with pytest.raises(R.RankDeficient):
+        R.fit(D, 1 / 255, Y, 2)
+    R.fit(D, 1 / 255, Y, 1)        # rank one is fine
+
+
+# ------------------------------------------------------------------ P6: OMP
+def test_omp_full_support_equals_lstsq():
+    D, lam_true, _ = lowrank_video(800, 30, 3, seed=61)
+    D = D + 1e-2 * np.random.default_rng(1).normal(size=D.shape)
+    mdl = R.fit(D, 1.0, R.sketch_gaussian(D, 1.0, 2, 60), 10)
+    x1 = D[0]
+    S, beta = R.omp(mdl.Phi, x1, K=10)
+    full = np.zeros(10, complex)
+    full[S] = beta
+    np.testing.assert_allclose(full, mdl.b, rtol=1e-8, atol=1e-10)
+
+
+def test_omp_orthonormal_dictionary_picks_largest_coefficients():
+    rng = np.random.default_rng(5)
+    Q, _ = np.linalg.qr(rng.normal(size=(200, 12)) + 1j * rng.normal(size=(200, 12)))
+    coef = rng.normal(size=12) + 1j * rng.normal(size=12)
+    x = Q @ coef
+    S, beta = R.omp(Q * 3.0, x, K=4)           # column scaling must not matter
+    assert set(S) == set(np.argsort(-np.abs(coef))[:4])
+    np.testing.assert_allclose(3.0 * beta, coef[S], rtol=1e-10)
+
+
+def test_omp_exact_sparse_recovery():
+    rng = np.random.default_rng(8)
+    A = rng.normal(size=(300, 40)) + 1j * rng.normal(size=(300, 40))
+    true = np.array([3, 17, 29])
+    coef = np.array([2.0, -1.5 + 0.5j, 1.0j])
+    x = A[:, true] @ coef
+    S, beta = R.omp(A, x, K=3)
+    assert sorted(S) == sorted(true)
+    np.testing.assert_allclose(beta[np.argsort(S)], coef[np.argsort(true)], rtol=1e-10)
+
+
+def test_omp_tie_rule_lowest_index():
+    e = np.eye(4, dtype=complex)
+    x = np.array([1.0, 1.0, 0.5, 0.0])
+    S, _ = R.omp(e, x, K=1)
+    assert list(S) == [0]
+
+
+# ------------------------------------------------------------------ P11: Vandermonde
+def test_vandermonde_closed_form():
+    rng = np.random.default_rng(3)
+    lam = np.concatenate([np.exp(1j * rng.uniform(0, np.pi, 5)),
+                          rng.uniform(0.99, 1.0, 3) * np.exp(1j * rng.uniform(0, 3, 3)), [0.0, 1.0]])
+    V = R.vandermonde(lam, 0, 1000)
+    np.testing.assert_array_equal(V[:, 0], np.ones(lam.size))
+    np.testing.assert_allclose(np.abs(V[:5]), 1.0, rtol=1e-12)
+    t = np.arange(1000)
+    cf = np.abs(lam)[:, None] ** t[None, :] * np.exp(1j * np.angle(lam)[:, None] * t[None, :])
+    cf[-2, 0] = 1.0
+    np.testing.assert_allclose(V, cf, rtol=1e-11, atol=1e-300)
+    np.testing.assert_array_equal(R.vandermonde(lam, 10, 20), V[:, 10:20])
+    with pytest.raises(R.NumericError):
+        R.vandermonde(np.array([1.2]), 0, 1000)
+
+
+# ------------------------------------------------------------------ P10: mask and metrics
+def test_mask_zero_on_noise_free_background():
+    spec = sv.preset("cfg1", exact=True, out="f64", H=40, W=50, m=30, bump_sigma=5.0,
+                     blur_sigma=2.0, seed=3)
+    v = sv.make_video(spec)
+    D = v.D.numpy()
+    mdl = R.fit(D, 1.0, R.sketch_gaussian(D, 1.0, 1, 40), len(v.bg_lambda))
+    L = R.background(mdl.Phi, mdl.b, mdl.lam, 0, spec.m)
+    assert not R.foreground(D.T, L, 1e-8).any()
+
+
+def test_mask_strict_and_nan():
+    x = np.array([[0.5, 0.6, np.nan, 0.2]])
+    L = np.array([[0.4, 0.5, 0.3, 0.2]])
+    m = R.foreground(x, L, 0.1)
+    # |0.5-0.4| is 0.09999999999999998 in binary, |0.6-0.5| is 0.09999999999999998 too
+    assert list(m[0]) == [abs(0.5 - 0.4) > 0.1, abs(0.6 - 0.5) > 0.1, False, False]
+    assert list(R.foreground(np.array([0.25]), np.array([0.0]), 0.25)) == [False]
+
+
+def test_prf_identities():
+    gt = np.array([1, 1, 0, 0, 1], bool)
+    assert R.prf(gt, gt) == (1.0, 1.0, 1.0)
+    R_, P_, F_ = R.prf(np.array([1, 0, 1, 0, 0], bool), gt)
+    assert (R_, P_) == (1 / 3, 1 / 2)
+    assert abs(F_ - 2 * (1 / 3) * (1 / 2) / (1 / 3 + 1 / 2)) < 1e-15
+    assert R.prf(np.zeros(5, bool), np.zeros(5, bool)) == (0.0, 0.0, 0.0)
+
+
+# ------------------------------------------------------------------ P13: zero mode
+def test_zero_mode_selector_static_video():
+    spec = sv.preset("cfg1", exact=True, out="f64", H=30, W=40, m=20, n_pairs=0, seed=4,
+                     blur_sigma=2.0)
+    v = sv.make_video(spec)
+    D = v.D.numpy() + 1e-4 * np.random.default_rng(0).normal(size=(20, 1200))
+    mdl = R.fit(D, 1.0, R.sketch_gaussian(D, 1.0, 3, 20), 3)
+    S = R.select_zero_mode(mdl.lam)
+    assert abs(mdl.lam[S[0]] - 1.0) < 1e-4
+    L = R.background(mdl.Phi[:, S], mdl.b[S], mdl.lam[S], 0, 20)
+    xhat = R.background(mdl.Phi[:, S], mdl.b[S], mdl.lam[S], 0, 20, static=True)
+    assert np.abs(L - xhat[:, None]).max() < 1e-3
+    np.testing.assert_allclose(xhat, v.D.numpy()[0], atol=1e-3)
+
+
+# ------------------------------------------------------------------ canonical order
+def test_canonical_order_pairs_positive_imag_first():
+    lam = np.array([0.9 - 0.1j, 1.0, 0.9 + 0.1j, 0.5])
+    key = np.array([2.0, 3.0, 2.0 * (1 + 1e-12), 1.0])
+    o = R.canonical_order(lam, key)
+    assert list(o) == [1, 2, 0, 3]
+
+
+def test_eigvec_normalisation():
+    rng = np.random.default_rng(2)
+    W = rng.normal(size=(6, 6)) + 1j * rng.normal(size=(6, 6))
+    Wn = R.normalise_eigvecs(W * np.exp(1j * 0.3))
+    np.testing.assert_allclose(np.linalg.norm(Wn, axis=0), 1.0)
+    piv = np.argmax(np.abs(Wn), axis=0)
+    assert np.all(Wn[piv, range(6)].real > 0) and np.allclose(Wn[piv, range(6)].imag, 0)
+    # same column up to phase
+    ratio = Wn / W
+    assert np.allclose(np.abs(ratio / ratio[0:1]), 1.0)
