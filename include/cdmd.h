@@ -1,0 +1,217 @@
+/*
+ * cdmd.h -- C ABI of the MI355X compressed-DMD (cDMD) background-modeling library.
+ *
+ * The calls follow the problem statement of Erichson, Brunton and Kutz,
+ * "Compressed Dynamic Mode Decomposition for Background Modeling":
+ *
+ *   cdmd_create      the parameters of Algorithm 1 (target rank k, samples p) and the
+ *                    choice of measurement matrix C (Section 3.3); draws/prepares C.
+ *   cdmd_fit         Algorithm 1 steps (1)-(9): sketch Y = C X, Y' = C X'
+ *                    (eq. (eq:YCX)), truncated SVD of Y, A~ = U* Y' V S^-1, eig(A~),
+ *                    full modes Phi = X' V S^-1 W (eq. (Eq:cDMDModes)) and amplitudes
+ *                    b = lstsq(Phi, x_1) (eq. (eq:b)).
+ *   cdmd_modes       returns Lambda, b, the singular values, and optionally Phi.
+ *   cdmd_select      background-mode selection: sparsity-constrained amplitudes by
+ *                    orthogonal matching pursuit (Section 2.3, eq. (eq:sparsecoding)),
+ *                    the zero mode or an |omega| threshold (Section 2.2), or an explicit
+ *                    support.
+ *   cdmd_background  L = Re(Phi_S diag(beta) V_S) (Section 2.2, eq. (equ:DMDTerms)) or
+ *                    the static model Re(Phi_S beta) (Section 2.3).
+ *   cdmd_foreground  mask = |x_jt - L_jt| > tau (Section 4, eq. (eq:thres)).
+ *
+ * Conventions
+ *   Video layout: frame-major.  Frame t (0-based) of a video starts at element t*ld;
+ *     pixel i of that frame is element t*ld + i.  ld >= n.  uint8 pixels are read as
+ *     u/255; float32 pixels as they are.  The paper's X is pixels x frames, the
+ *     transpose of this layout.
+ *   Device pointers ("d_" prefix) are device memory of the current HIP device; host
+ *     pointers ("h_" prefix, or plain arrays) are host memory.  All pointers are
+ *     borrowed for the duration of the call only; the library keeps no reference.
+ *   Streams: `stream` is a hipStream_t passed as void* (NULL = the null stream).  All
+ *     device work of a call is enqueued on it.  Calls that return host results
+ *     synchronise the stream before returning.
+ *   Errors: every call returns a cdmd_status; arguments are validated before any
+ *     device work.  cdmd_last_error() gives a thread-local message for the last
+ *     failing call on the calling thread.  No call aborts or throws.
+ *   Thread safety: one model must not be used by two threads at once; distinct models
+ *     are independent.
+ *   Determinism: the same inputs, configuration and seed give bitwise-identical
+ *     results on the same device.
+ */
+#ifndef CDMD_H
+#define CDMD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CDMD_ABI_VERSION 1
+
+typedef enum {
+  CDMD_OK = 0,
+  CDMD_E_INVALID_ARG = 1,     /* argument or configuration out of range */
+  CDMD_E_UNSUPPORTED = 2,     /* valid request this build does not implement */
+  CDMD_E_OUT_OF_MEMORY = 3,   /* device or host allocation failed */
+  CDMD_E_DEVICE = 4,          /* HIP runtime error, or no usable gfx950 device */
+  CDMD_E_RANK_DEFICIENT = 5,  /* sigma_k <= 1e-6 sigma_1: the rank-k SVD is undefined */
+  CDMD_E_NUMERIC = 6,         /* NaN/Inf, eigensolver failure, |lambda|^(m-1) > 1e30 */
+  CDMD_E_STATE = 7            /* call order violated (e.g. foreground before select) */
+} cdmd_status;
+
+typedef enum { CDMD_U8 = 0, CDMD_F32 = 1 } cdmd_dtype;
+
+/* Measurement matrix C (p x n), Section 3.3 */
+typedef enum {
+  CDMD_SKETCH_GAUSSIAN = 0,   /* i.i.d. N(0, 1/p); entry (r, j) is a pure function of
+                                 (seed, r, j): Philox4x32-10 counter (j>>2, r, 0, 0),
+                                 key (seed lo, seed hi), Box-Muller on output words
+                                 (w0,w1) -> pixels 4(j>>2)+0,1 and (w2,w3) -> +2,3,
+                                 uniforms (w+1) 2^-32; never stored */
+  CDMD_SKETCH_SPARSE = 1,     /* each row holds nnz entries +/-1 at distinct pixels,
+                                 given by the caller's index/sign table */
+  CDMD_SKETCH_SPIXEL = 2      /* single-pixel C = R: p distinct pixels, weight +1
+                                 (nnz = 1), given by the caller's index table */
+} cdmd_sketch;
+
+/* Arithmetic of the sketch and of the mode lift / reconstruction passes.  The
+   SVD, eigensolves and amplitude solves are always float64. */
+typedef enum {
+  CDMD_PREC_FP32 = 0,   /* float32 products, float32 accumulation per tile, float64
+                           across tiles */
+  CDMD_PREC_BF16 = 1,   /* bfloat16 operands (RNE), float32 accumulation (MFMA) */
+  CDMD_PREC_FP8 = 2     /* OCP e4m3fn operands (RNE, saturating), float32
+                           accumulation (MFMA); sketch only */
+} cdmd_prec;
+
+typedef enum {
+  CDMD_SEL_OMP = 0,        /* orthogonal matching pursuit with K atoms on x_1 */
+  CDMD_SEL_ZERO_MODE = 1,  /* the mode with the smallest |log lambda| */
+  CDMD_SEL_OMEGA = 2,      /* all modes with |log lambda| < omega_thr */
+  CDMD_SEL_EXPLICIT = 3,   /* caller-given support; beta refitted by least squares */
+  CDMD_SEL_ALL = 4         /* every mode, beta = b */
+} cdmd_selector;
+
+typedef struct {
+  int64_t n;            /* pixels per frame, n >= m */
+  int64_t m;            /* frames, m >= 2 */
+  int64_t ld;           /* elements between frame starts, ld >= n */
+  int32_t k;            /* target rank, 1 <= k <= min(p, m-1) */
+  int32_t p;            /* sketch rows (samples), p >= k */
+  int32_t nnz;          /* nonzeros per row of a sparse C (1..32); 1 for single-pixel */
+  int32_t dtype;        /* cdmd_dtype of the video */
+  int32_t sketch;       /* cdmd_sketch */
+  int32_t sketch_prec;  /* cdmd_prec of the sketch (sparse/single-pixel: exact integer
+                           sums for uint8 video, float64 for float32 video) */
+  int32_t lift_prec;    /* cdmd_prec of the lift and reconstruction (FP32 or BF16) */
+  uint64_t seed;        /* Gaussian C */
+  const int32_t* sparse_idx;  /* host, p*nnz row-major pixel indices in [0, n),
+                                 distinct within a row (single-pixel: distinct over
+                                 all rows); required for SPARSE and SPIXEL */
+  const int8_t* sparse_sign;  /* host, p*nnz entries +1/-1 (NULL = all +1) */
+} cdmd_config;
+
+/* Opaque, library-owned model: the prepared C, device workspace sized for the
+   configuration, and the results of the last fit (Lambda, W, G = V S^-1 W,
+   H = Phi^H Phi, c = Phi^H x_1, b, the selection). */
+typedef struct cdmd_model cdmd_model;
+
+typedef struct {
+  int32_t fitted;            /* 1 after a successful cdmd_fit */
+  int32_t selected;          /* 1 after a successful cdmd_select */
+  int32_t warn_few_samples;  /* 1 if p < k ln(n/k) (Section 4 guidance), else 0 */
+  int32_t n_selected;        /* |S| */
+  double sigma_ratio;        /* sigma_k / sigma_1 of the last fit */
+  double x1_norm2;           /* ||x_1||^2 */
+  double omp_residual2;      /* ||x_1 - Phi_S beta||^2 after selection */
+  double ms_sketch;          /* host wall time of the last fit: sketch + Gram + copy */
+  double ms_small_la;        /* ... float64 SVD / eigensolves on the host */
+  double ms_lift;            /* ... lift + reduction + copy */
+  double ms_host_post;       /* ... amplitudes and canonical order */
+  int32_t lanczos_steps;     /* Krylov dimension used by the symmetric eigensolver */
+  int32_t timing;            /* 1 if kernel timing is enabled (cdmd_set_timing) */
+  /* Device time (ms, HIP events on the call's stream) of the last launch of each
+     kernel group, valid when timing is enabled: sketch (incl. slot reduction), Gram,
+     lift (incl. partial reduction), reconstruction/threshold. */
+  double gpu_ms_sketch, gpu_ms_gram, gpu_ms_lift, gpu_ms_recon;
+} cdmd_info;
+
+/* Validate `cfg`, prepare C (the sparse table is copied and reordered on the device)
+   and allocate the device workspace on the current device.
+   Errors: INVALID_ARG (constraints above, NULL table for SPARSE/SPIXEL, index out of
+   range, sign not +/-1, k > min(p, m-1), unknown enum), UNSUPPORTED (precision
+   combination not built), DEVICE (no gfx950 device), OUT_OF_MEMORY. */
+cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out);
+
+/* Algorithm 1 steps (1)-(9) on the video d_video (device, layout above, dtype of the
+   configuration).  Synchronises `stream`.  Errors: INVALID_ARG (NULL),
+   RANK_DEFICIENT, NUMERIC, DEVICE. */
+cdmd_status cdmd_fit(cdmd_model* mdl, const void* d_video, void* stream);
+
+/* Results of the last fit, modes in canonical order (descending |b_j| ||phi_j||,
+   conjugate partners with Im lambda > 0 first).  Each output is optional (NULL):
+   lambda[2k] (re, im interleaved), b[2k] (re, im), sigma[k] (singular values of the
+   scaled sketch Y, descending), phi_norm[k] (||phi_j||), and d_phi: device buffer of
+   n*k complex64 (re, im float pairs), mode-contiguous: element (i, j) at j*n + i.
+   Writing d_phi re-runs the lift on d_video (which must be the fitted video) and
+   synchronises `stream`.  Errors: STATE (not fitted), INVALID_ARG. */
+cdmd_status cdmd_modes(const cdmd_model* mdl, double* lambda, double* b, double* sigma,
+                       double* phi_norm, const void* d_video, void* d_phi, void* stream);
+
+/* Select background modes S and their amplitudes beta.
+   selector OMP: K atoms (K >= 1, clamped to k).  OMEGA: threshold omega_thr > 0.
+   EXPLICIT: explicit_idx[n_explicit] distinct canonical indices in [0, k).
+   Outputs (optional): out_idx[k] receives S in selection order, out_n |S|,
+   out_beta[2k] the complex amplitudes (re, im) in the order of out_idx.
+   Errors: STATE (not fitted), INVALID_ARG, NUMERIC. */
+cdmd_status cdmd_select(cdmd_model* mdl, int32_t selector, int32_t K, double omega_thr,
+                        const int32_t* explicit_idx, int32_t n_explicit,
+                        int32_t* out_idx, int32_t* out_n, double* out_beta);
+
+/* Write the background of frames [t0, t1) (0-based, t1 <= m) to d_L (device float32,
+   frame-major, frame t0+s at s*ldL, ldL >= n), or, if static_bg, the static model
+   xhat (n floats) to d_L.  Needs the fitted video again (the modes are recomputed
+   from X' on the fly).  Errors: STATE (not selected), INVALID_ARG, NUMERIC. */
+cdmd_status cdmd_background(const cdmd_model* mdl, const void* d_video, int64_t t0,
+                            int64_t t1, int32_t static_bg, float* d_L, int64_t ldL,
+                            void* stream);
+
+/* Foreground mask of all m frames: mask_jt = |x_jt - L_jt| > tau (strict; NaN -> 0),
+   L the dynamic background of the selected modes, or the static model if static_bg.
+   bitpacked = 1: d_mask holds uint32 words, frame t at t*ceil(n/32), pixel i of the
+   frame in bit (i mod 32) of word i/32 (unused high bits zero).  bitpacked = 0: one
+   uint8 (0/1) per pixel, frame t at t*n.  h_counts (optional, host int64[m]) receives
+   the foreground pixel count per frame.  Enqueued on `stream`; synchronises only if
+   h_counts is given.  Errors: STATE (not selected), INVALID_ARG, NUMERIC. */
+cdmd_status cdmd_foreground(const cdmd_model* mdl, const void* d_video, float tau,
+                            int32_t static_bg, int32_t bitpacked, void* d_mask,
+                            int64_t* h_counts, void* stream);
+
+/* Sketch of the last fit, Y^ = C D (p x m), scaled (u/255 for uint8, 1/sqrt(p) for
+   Gaussian), host float64, frame-major: element (r, t) at t*p + r.  Optional
+   h_int (host int64[p*m]): the exact integer sums of a sparse/single-pixel sketch of
+   a uint8 video before scaling (INVALID_ARG otherwise).  Errors: STATE. */
+cdmd_status cdmd_get_sketch(const cdmd_model* mdl, double* h_Y, int64_t* h_int);
+
+/* Counters and timings of the last calls (see cdmd_info).  Reading gpu_ms_recon waits
+   for the last reconstruction launch to finish. */
+cdmd_status cdmd_info_get(const cdmd_model* mdl, cdmd_info* info);
+
+/* Enable (1) or disable (0) HIP-event timing of the kernel groups of this model. */
+cdmd_status cdmd_set_timing(cdmd_model* mdl, int32_t enable);
+
+/* Release the model and its device memory.  NULL is a no-op. */
+void cdmd_free(cdmd_model* mdl);
+
+/* Thread-local message of the last failing call on this thread ("" if none). */
+const char* cdmd_last_error(void);
+
+int32_t cdmd_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDMD_H */

@@ -1,0 +1,42 @@
+/*
+ * cdmd_debug.h -- host-only entry points of libcdmd.so that expose the float64 small
+ * linear algebra of the fit for testing without a GPU.  They run on the calling thread,
+ * touch no device, and are not part of the hot path's public API.
+ */
+#ifndef CDMD_DEBUG_H
+#define CDMD_DEBUG_H
+
+#include <stdint.h>
+
+#include "cdmd.h"
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Top-k eigenpairs of the symmetric n x n matrix M (host, row-major) by Lanczos with
+   full reorthogonalisation (the route to the truncated SVD of Algorithm 1 step 4).
+   evals[k] descending; evecs n x k column-major.  *steps = Krylov dimension used.
+   Errors: INVALID_ARG, NUMERIC. */
+cdmd_status cdmd_dbg_sym_topk(const double* M, int32_t n, int32_t k, double rtol,
+                              double* evals, double* evecs, int32_t* steps);
+
+/* Eigenvalues and unit eigenvectors of a real k x k matrix A (host, row-major)
+   (Algorithm 1 step 7).  lam[2k] (re, im); W[2k*k] column-major complex (re, im).
+   Errors: INVALID_ARG, NUMERIC. */
+cdmd_status cdmd_dbg_eig_general(const double* A, int32_t k, double* lam, double* W);
+
+/* Orthogonal matching pursuit in coefficient space (Section 2.3) on H = Phi^H Phi
+   (k x k complex, row-major, re/im interleaved), c = Phi^H x_1 (k complex) and
+   x1n2 = ||x_1||^2.  S[k] receives the support in selection order, beta[2k] the
+   amplitudes, *ns = |S|, *resid2 = ||x_1 - Phi_S beta||^2.  Errors: INVALID_ARG,
+   NUMERIC. */
+cdmd_status cdmd_dbg_omp_gram(const double* H, int32_t k, const double* c, double x1n2,
+                              int32_t K, int32_t* S, double* beta, int32_t* ns,
+                              double* resid2);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CDMD_DEBUG_H */

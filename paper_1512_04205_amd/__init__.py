@@ -1,0 +1,13 @@
+"""MI355X-native compressed dynamic mode decomposition (cDMD) for video background
+modeling: a HIP library for gfx950 behind a C ABI (include/cdmd.h), and this thin
+Python binding.  Importing the package loads libcdmd.so and fails if it is not built.
+"""
+from ._binding import (  # noqa: F401
+    CdmdError, Model, load_library, unpack_mask, mask_words, LIB_PATH, EXPORTED,
+    U8, F32, SKETCH_GAUSSIAN, SKETCH_SPARSE, SKETCH_SPIXEL, PREC_FP32, PREC_BF16, PREC_FP8,
+    SEL_OMP, SEL_ZERO_MODE, SEL_OMEGA, SEL_EXPLICIT, SEL_ALL,
+    OK, E_INVALID_ARG, E_UNSUPPORTED, E_OUT_OF_MEMORY, E_DEVICE, E_RANK_DEFICIENT, E_NUMERIC,
+    E_STATE,
+)
+
+load_library()

@@ -1,0 +1,259 @@
+"""ctypes binding of libcdmd.so (include/cdmd.h): argument marshalling only.
+
+Every step of the cDMD path runs inside the library; this module turns torch tensors
+into raw device pointers and streams, numpy arrays into host pointers, and status codes
+into exceptions.  It never computes a result itself and has no fallback: if the library
+is missing, importing the package fails.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libcdmd.so")
+
+# enums (include/cdmd.h)
+OK, E_INVALID_ARG, E_UNSUPPORTED, E_OUT_OF_MEMORY, E_DEVICE, E_RANK_DEFICIENT, E_NUMERIC, E_STATE = range(8)
+U8, F32 = 0, 1
+SKETCH_GAUSSIAN, SKETCH_SPARSE, SKETCH_SPIXEL = 0, 1, 2
+PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
+SEL_OMP, SEL_ZERO_MODE, SEL_OMEGA, SEL_EXPLICIT, SEL_ALL = 0, 1, 2, 3, 4
+
+_STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE",
+                 5: "RANK_DEFICIENT", 6: "NUMERIC", 7: "STATE"}
+
+EXPORTED = [
+    "cdmd_abi_version", "cdmd_last_error", "cdmd_create", "cdmd_fit", "cdmd_modes",
+    "cdmd_select", "cdmd_background", "cdmd_foreground", "cdmd_get_sketch",
+    "cdmd_info_get", "cdmd_set_timing", "cdmd_free",
+]
+
+
+class CdmdError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{_STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Config(ctypes.Structure):
+    _fields_ = [
+        ("n", ctypes.c_int64), ("m", ctypes.c_int64), ("ld", ctypes.c_int64),
+        ("k", ctypes.c_int32), ("p", ctypes.c_int32), ("nnz", ctypes.c_int32),
+        ("dtype", ctypes.c_int32), ("sketch", ctypes.c_int32),
+        ("sketch_prec", ctypes.c_int32), ("lift_prec", ctypes.c_int32),
+        ("seed", ctypes.c_uint64),
+        ("sparse_idx", ctypes.POINTER(ctypes.c_int32)),
+        ("sparse_sign", ctypes.POINTER(ctypes.c_int8)),
+    ]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [
+        ("fitted", ctypes.c_int32), ("selected", ctypes.c_int32),
+        ("warn_few_samples", ctypes.c_int32), ("n_selected", ctypes.c_int32),
+        ("sigma_ratio", ctypes.c_double), ("x1_norm2", ctypes.c_double),
+        ("omp_residual2", ctypes.c_double),
+        ("ms_sketch", ctypes.c_double), ("ms_small_la", ctypes.c_double),
+        ("ms_lift", ctypes.c_double), ("ms_host_post", ctypes.c_double),
+        ("lanczos_steps", ctypes.c_int32), ("timing", ctypes.c_int32),
+        ("gpu_ms_sketch", ctypes.c_double), ("gpu_ms_gram", ctypes.c_double),
+        ("gpu_ms_lift", ctypes.c_double), ("gpu_ms_recon", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {f[0]: getattr(self, f[0]) for f in self._fields_}
+
+
+_lib: Optional[ctypes.CDLL] = None
+
+
+def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libcdmd.so (once).  Raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with `python paper_1512_04205_amd/build.py`")
+    lib = ctypes.CDLL(path)
+    P, I32, I64, D = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_double
+    DP = ctypes.POINTER(ctypes.c_double)
+    lib.cdmd_abi_version.restype = I32
+    lib.cdmd_last_error.restype = ctypes.c_char_p
+    lib.cdmd_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(P)]
+    lib.cdmd_fit.argtypes = [P, P, P]
+    lib.cdmd_modes.argtypes = [P, DP, DP, DP, DP, P, P, P]
+    lib.cdmd_select.argtypes = [P, I32, I32, D, ctypes.POINTER(I32), I32, ctypes.POINTER(I32),
+                                ctypes.POINTER(I32), DP]
+    lib.cdmd_background.argtypes = [P, P, I64, I64, I32, P, I64, P]
+    lib.cdmd_foreground.argtypes = [P, P, ctypes.c_float, I32, I32, P, ctypes.POINTER(I64), P]
+    lib.cdmd_get_sketch.argtypes = [P, DP, ctypes.POINTER(I64)]
+    lib.cdmd_info_get.argtypes = [P, ctypes.POINTER(Info)]
+    lib.cdmd_set_timing.argtypes = [P, I32]
+    lib.cdmd_free.argtypes = [P]
+    lib.cdmd_free.restype = None
+    for name in EXPORTED:
+        if name not in ("cdmd_abi_version", "cdmd_last_error", "cdmd_free"):
+            getattr(lib, name).restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise CdmdError(status, load_library().cdmd_last_error().decode())
+
+
+def _dptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _video_ptr(video, dtype: int, n: int, m: int, ld: int) -> int:
+    import torch
+    if not isinstance(video, torch.Tensor) or not video.is_cuda:
+        raise TypeError("video must be a CUDA (HIP) torch tensor")
+    want = torch.uint8 if dtype == U8 else torch.float32
+    if video.dtype != want:
+        raise TypeError(f"video dtype {video.dtype} does not match the model ({want})")
+    if video.dim() != 2 or video.shape[0] != m or video.shape[1] < n or video.stride(1) != 1 \
+            or video.stride(0) != ld:
+        raise ValueError("video must be (m, >= n) with unit pixel stride and frame stride ld")
+    return video.data_ptr()
+
+
+class Model:
+    """One cDMD model: configuration, prepared sketch matrix, device workspace and the
+    results of the last fit (a thin owner of a cdmd_model*)."""
+
+    def __init__(self, n: int, m: int, k: int, p: int, *, sketch: int = SKETCH_SPARSE,
+                 dtype: int = U8, ld: Optional[int] = None, idx: Optional[np.ndarray] = None,
+                 sign: Optional[np.ndarray] = None, seed: int = 0,
+                 sketch_prec: int = PREC_FP32, lift_prec: int = PREC_FP32):
+        lib = load_library()
+        self.n, self.m, self.k, self.p = int(n), int(m), int(k), int(p)
+        self.ld = int(ld if ld is not None else n)
+        self.dtype = dtype
+        cfg = Config()
+        cfg.n, cfg.m, cfg.ld, cfg.k, cfg.p = self.n, self.m, self.ld, self.k, self.p
+        cfg.dtype, cfg.sketch, cfg.seed = dtype, sketch, seed
+        cfg.sketch_prec, cfg.lift_prec = sketch_prec, lift_prec
+        self._keep = []
+        if idx is not None:
+            idx = np.ascontiguousarray(idx, dtype=np.int32)
+            cfg.nnz = idx.shape[1] if idx.ndim == 2 else 1
+            cfg.sparse_idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            self._keep.append(idx)
+        if sign is not None:
+            sign = np.ascontiguousarray(sign, dtype=np.int8)
+            cfg.sparse_sign = sign.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+            self._keep.append(sign)
+        h = ctypes.c_void_p()
+        _check(lib.cdmd_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._keep = []
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().cdmd_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---- Algorithm 1
+    def fit(self, video, stream=None):
+        _check(load_library().cdmd_fit(self._h, _video_ptr(video, self.dtype, self.n, self.m, self.ld),
+                                       _stream(stream)))
+        return self
+
+    def modes(self, video=None, phi=None, stream=None):
+        """Returns dict(lam, b, sigma, phi_norm) (complex / float64 numpy); fills the
+        device tensor ``phi`` ((k, n) complex64) with the full modes if given."""
+        k = self.k
+        lam, b = np.zeros(2 * k), np.zeros(2 * k)
+        sig, pn = np.zeros(k), np.zeros(k)
+        vptr = _video_ptr(video, self.dtype, self.n, self.m, self.ld) if video is not None else None
+        pptr = None
+        if phi is not None:
+            import torch
+            if phi.dtype != torch.complex64 or tuple(phi.shape) != (k, self.n) or not phi.is_contiguous():
+                raise ValueError("phi must be a contiguous (k, n) complex64 device tensor")
+            pptr = phi.data_ptr()
+        _check(load_library().cdmd_modes(self._h, _dptr(lam), _dptr(b), _dptr(sig), _dptr(pn),
+                                          vptr, pptr, _stream(stream) if pptr else None))
+        return dict(lam=lam[0::2] + 1j * lam[1::2], b=b[0::2] + 1j * b[1::2], sigma=sig, phi_norm=pn)
+
+    def select(self, selector: int = SEL_OMP, K: int = 10, omega_thr: float = 0.0,
+               explicit: Optional[Sequence[int]] = None):
+        k = self.k
+        idx = np.zeros(k, dtype=np.int32)
+        beta = np.zeros(2 * k)
+        nsel = ctypes.c_int32(0)
+        ex = None
+        nex = 0
+        if explicit is not None:
+            ex_arr = np.ascontiguousarray(explicit, dtype=np.int32)
+            ex = ex_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+            nex = len(ex_arr)
+        _check(load_library().cdmd_select(self._h, selector, K, omega_thr, ex, nex,
+                                          idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                          ctypes.byref(nsel), _dptr(beta)))
+        ns = nsel.value
+        return idx[:ns].copy(), (beta[0::2] + 1j * beta[1::2])[:ns].copy()
+
+    def background(self, video, L, t0: int = 0, t1: Optional[int] = None, static: bool = False,
+                   stream=None):
+        t1 = self.m if t1 is None else t1
+        _check(load_library().cdmd_background(
+            self._h, _video_ptr(video, self.dtype, self.n, self.m, self.ld), t0, t1, int(static),
+            L.data_ptr(), L.stride(0) if L.dim() == 2 else self.n, _stream(stream)))
+
+    def foreground(self, video, mask, tau: float, static: bool = False, bitpacked: bool = True,
+                   counts: bool = False, stream=None):
+        cnt = np.zeros(self.m, dtype=np.int64) if counts else None
+        _check(load_library().cdmd_foreground(
+            self._h, _video_ptr(video, self.dtype, self.n, self.m, self.ld), tau, int(static),
+            int(bitpacked), mask.data_ptr(),
+            cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if counts else None,
+            _stream(stream)))
+        return cnt
+
+    def sketch(self, integer: bool = False):
+        Y = np.zeros(self.m * self.p)
+        Yi = np.zeros(self.m * self.p, dtype=np.int64) if integer else None
+        _check(load_library().cdmd_get_sketch(
+            self._h, _dptr(Y), Yi.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if integer else None))
+        Y = Y.reshape(self.m, self.p).T.copy()
+        return (Y, Yi.reshape(self.m, self.p).T.copy()) if integer else Y
+
+    def set_timing(self, enable: bool = True):
+        _check(load_library().cdmd_set_timing(self._h, int(enable)))
+
+    def info(self) -> dict:
+        inf = Info()
+        _check(load_library().cdmd_info_get(self._h, ctypes.byref(inf)))
+        return inf.as_dict()
+
+
+def mask_words(n: int) -> int:
+    return (n + 31) // 32
+
+
+def unpack_mask(words: np.ndarray, n: int) -> np.ndarray:
+    """Bit-packed (m, ceil(n/32)) uint32 mask -> bool (m, n) (host helper)."""
+    w = np.ascontiguousarray(words).view(np.uint8).reshape(words.shape[0], -1)
+    bits = np.unpackbits(w, axis=1, bitorder="little")
+    return bits[:, :n].astype(bool)

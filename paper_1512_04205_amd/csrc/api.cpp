@@ -1,0 +1,904 @@
+// C ABI of the cDMD library: validation, device workspace, kernel orchestration and
+// the float64 host stages of the fit.  The calls and their meaning are documented in
+// include/cdmd.h.
+#include "cdmd.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <complex>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "smallla.hpp"
+
+using cplx = std::complex<double>;
+
+namespace {
+
+thread_local std::string g_err;
+
+cdmd_status fail(cdmd_status s, const std::string& msg) {
+  g_err = msg;
+  return s;
+}
+
+#define HIPCHK(expr)                                                                   \
+  do {                                                                                 \
+    hipError_t _e = (expr);                                                            \
+    if (_e != hipSuccess)                                                              \
+      return fail(_e == hipErrorOutOfMemory ? CDMD_E_OUT_OF_MEMORY : CDMD_E_DEVICE,    \
+                  std::string(#expr) + ": " + hipGetErrorString(_e));                  \
+  } while (0)
+
+// rank test on the Gram eigenvalues: sigma_k <= 1e-6 sigma_1  <=>  mu_k <= 1e-12 mu_1
+constexpr double kRankTol2 = 1e-12;
+constexpr double kTieRel = 1e-9;
+constexpr double kOmpStopRel = 1e-12;
+constexpr double kVanderMax = 1e30;
+constexpr double kLanczosTol = 1e-13;
+
+double now_ms() {
+  using namespace std::chrono;
+  return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
+}
+
+int pad_nc(int v) {  // lift column padding: multiple of 8, 8..80
+  int r = ((v + 7) / 8) * 8;
+  return r < 8 ? 8 : r;
+}
+
+int pad_ns(int v) {  // reconstruction column padding: one of the instantiated widths
+  static const int w[] = {4, 8, 12, 16, 20, 24, 32, 40, 48, 64, 80};
+  for (int x : w)
+    if (v <= x) return x;
+  return -1;
+}
+
+}  // namespace
+
+struct cdmd_model {
+  cdmd_config cfg{};
+  int device = -1;
+  int64_t n = 0, m = 0, ld = 0;
+  int N = 0, k = 0, p = 0;
+  int nc = 0, NC = 0, npair = 0, ne = 0;
+  float xscale = 1.f;
+  double sketch_scale = 1.0;  // Y^ = sketch_scale * (integer or float64 sums)
+  // sparse plan (uint8)
+  int nseg = 0, nslot = 1, max_rows = 0, fpb = 1;
+  int32_t* d_tri_pix = nullptr;
+  uint32_t* d_tri_rs = nullptr;
+  int32_t* d_seg = nullptr;
+  // sparse table (float32 video)
+  int32_t* d_idx = nullptr;
+  int8_t* d_sign = nullptr;
+  // sketch and Gram
+  int32_t* d_Yint = nullptr;
+  int32_t* d_Ypart = nullptr;
+  double* d_Yd = nullptr;
+  double* d_gram = nullptr;
+  // lift
+  float* d_G = nullptr;
+  uint32_t* d_pairs = nullptr;
+  double* d_part = nullptr;
+  double* d_red = nullptr;
+  int lgrid = 0;
+  // reconstruction
+  float* d_Gs = nullptr;
+  float* d_Vc = nullptr;
+  int64_t* d_counts = nullptr;
+  // pinned host staging
+  double* h_gram = nullptr;
+  float* h_G = nullptr;
+  double* h_red = nullptr;
+  float* h_Gs = nullptr;
+  float* h_Vc = nullptr;
+  int64_t* h_counts = nullptr;
+  // results (canonical order)
+  bool fitted = false, selected = false, g_canonical_on_device = false;
+  std::vector<cplx> lam, W, G, H, c, b;
+  std::vector<double> sigma, phinorm;
+  std::vector<int> perm;  // canonical index -> device column
+  double x1n2 = 0.0;
+  std::vector<int> S;
+  std::vector<cplx> beta;
+  cdmd_info info{};
+  // kernel-group timing (HIP events on the call's stream)
+  bool timing = false, recon_pending = false;
+  hipEvent_t ev[8] = {};
+
+  void mark(int i, hipStream_t st) {
+    if (timing) (void)hipEventRecord(ev[i], st);
+  }
+  double span(int a, int b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, ev[a], ev[b]) != hipSuccess) return -1.0;
+    return (double)ms;
+  }
+
+  ~cdmd_model() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+    void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd,
+                   d_gram, d_G, d_pairs, d_part, d_red, d_Gs, d_Vc, d_counts};
+    for (void* q : dev)
+      if (q) (void)hipFree(q);
+    void* host[] = {h_gram, h_G, h_red, h_Gs, h_Vc, h_counts};
+    for (void* q : host)
+      if (q) (void)hipHostFree(q);
+  }
+};
+
+namespace {
+
+template <typename T>
+cdmd_status dalloc(T** p, size_t count) {
+  if (count == 0) count = 1;
+  HIPCHK(hipMalloc((void**)p, count * sizeof(T)));
+  return CDMD_OK;
+}
+template <typename T>
+cdmd_status halloc(T** p, size_t count) {
+  if (count == 0) count = 1;
+  HIPCHK(hipHostMalloc((void**)p, count * sizeof(T), hipHostMallocDefault));
+  return CDMD_OK;
+}
+
+#define TRY(expr)                      \
+  do {                                 \
+    cdmd_status _s = (expr);           \
+    if (_s != CDMD_OK) return _s;      \
+  } while (0)
+
+cdmd_status validate(const cdmd_config* c) {
+  if (!c) return fail(CDMD_E_INVALID_ARG, "config is NULL");
+  if (c->m < 2) return fail(CDMD_E_INVALID_ARG, "need m >= 2 frames");
+  if (c->n < c->m) return fail(CDMD_E_INVALID_ARG, "need n >= m (pixels >= frames)");
+  if (c->ld < c->n) return fail(CDMD_E_INVALID_ARG, "need ld >= n");
+  if (c->p < 1 || c->k < 1) return fail(CDMD_E_INVALID_ARG, "need k, p >= 1");
+  if (c->p < c->k) return fail(CDMD_E_INVALID_ARG, "need p >= k");
+  if ((int64_t)c->k > c->m - 1) return fail(CDMD_E_INVALID_ARG, "need k <= m - 1");
+  if (c->dtype != CDMD_U8 && c->dtype != CDMD_F32) return fail(CDMD_E_INVALID_ARG, "unknown dtype");
+  if (c->sketch < CDMD_SKETCH_GAUSSIAN || c->sketch > CDMD_SKETCH_SPIXEL)
+    return fail(CDMD_E_INVALID_ARG, "unknown sketch");
+  if (c->sketch_prec < CDMD_PREC_FP32 || c->sketch_prec > CDMD_PREC_FP8 ||
+      c->lift_prec < CDMD_PREC_FP32 || c->lift_prec > CDMD_PREC_FP8)
+    return fail(CDMD_E_INVALID_ARG, "unknown precision");
+  if (c->lift_prec == CDMD_PREC_FP8)
+    return fail(CDMD_E_INVALID_ARG, "FP8 is a sketch precision only");
+  if (c->sketch == CDMD_SKETCH_SPARSE || c->sketch == CDMD_SKETCH_SPIXEL) {
+    if (!c->sparse_idx) return fail(CDMD_E_INVALID_ARG, "sparse sketch needs sparse_idx");
+    if (c->nnz < 1 || c->nnz > 32) return fail(CDMD_E_INVALID_ARG, "nnz must be in [1, 32]");
+    if (c->sketch == CDMD_SKETCH_SPIXEL && c->nnz != 1)
+      return fail(CDMD_E_INVALID_ARG, "single-pixel sketch has nnz = 1");
+    if (c->sketch == CDMD_SKETCH_SPIXEL && (int64_t)c->p > c->n)
+      return fail(CDMD_E_INVALID_ARG, "single-pixel sketch needs p <= n");
+    if ((int64_t)c->nnz > c->n) return fail(CDMD_E_INVALID_ARG, "nnz must not exceed n");
+  }
+  if (c->k > 40) return fail(CDMD_E_UNSUPPORTED, "k > 40 is not built");
+  if (c->n >= (int64_t)1 << 31) return fail(CDMD_E_UNSUPPORTED, "n >= 2^31 pixels is not built");
+  if (c->sketch == CDMD_SKETCH_GAUSSIAN)
+    return fail(CDMD_E_UNSUPPORTED, "dense Gaussian sketch is not built in this library version");
+  if (c->sketch_prec != CDMD_PREC_FP32 || c->lift_prec != CDMD_PREC_FP32)
+    return fail(CDMD_E_UNSUPPORTED, "only the FP32 forms are built in this library version");
+  // table contents
+  if (c->sketch != CDMD_SKETCH_GAUSSIAN) {
+    const int64_t p = c->p, z = c->nnz;
+    for (int64_t r = 0; r < p; ++r) {
+      for (int64_t j = 0; j < z; ++j) {
+        const int32_t v = c->sparse_idx[r * z + j];
+        if (v < 0 || (int64_t)v >= c->n) return fail(CDMD_E_INVALID_ARG, "sparse_idx out of range");
+        if (c->sparse_sign) {
+          const int8_t sg = c->sparse_sign[r * z + j];
+          if (sg != 1 && sg != -1) return fail(CDMD_E_INVALID_ARG, "sparse_sign must be +1 or -1");
+          if (c->sketch == CDMD_SKETCH_SPIXEL && sg != 1)
+            return fail(CDMD_E_INVALID_ARG, "single-pixel weights are +1");
+        }
+        for (int64_t q = 0; q < j; ++q)
+          if (c->sparse_idx[r * z + q] == v)
+            return fail(CDMD_E_INVALID_ARG, "sparse_idx repeats a pixel within a row");
+      }
+    }
+    if (c->sketch == CDMD_SKETCH_SPIXEL) {
+      std::vector<int32_t> s(c->sparse_idx, c->sparse_idx + p);
+      std::sort(s.begin(), s.end());
+      if (std::adjacent_find(s.begin(), s.end()) != s.end())
+        return fail(CDMD_E_INVALID_ARG, "single-pixel rows must be distinct pixels");
+    }
+  }
+  return CDMD_OK;
+}
+
+cdmd_status check_device(int* dev) {
+  int count = 0;
+  hipError_t e = hipGetDeviceCount(&count);
+  if (e != hipSuccess || count < 1) return fail(CDMD_E_DEVICE, "no HIP device available");
+  HIPCHK(hipGetDevice(dev));
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, *dev));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(CDMD_E_DEVICE, std::string("device is ") + prop.gcnArchName + ", library is built for gfx950");
+  return CDMD_OK;
+}
+
+// Build the pixel-sorted triple table of a sparse / single-pixel C for the uint8 sketch.
+cdmd_status build_sparse_plan(cdmd_model* M) {
+  const cdmd_config& c = M->cfg;
+  const int p = c.p, z = c.nnz;
+  const int max_rows = std::min(p, 8192);
+  int fpb = 1;
+  while (fpb < 4 && (size_t)(fpb * 2) * max_rows * 4 <= 65536) fpb *= 2;
+  const int nb = (p + max_rows - 1) / max_rows;
+  const int64_t groups = (M->m + fpb - 1) / fpb;
+  int nslot = (int)std::max<int64_t>(1, std::min<int64_t>(16, (1024 + nb * groups - 1) / (nb * groups)));
+  const int64_t T = (int64_t)p * z;
+  if (T / nb / nslot < 512) nslot = (int)std::max<int64_t>(1, T / nb / 512);
+  std::vector<int32_t> pix;
+  std::vector<uint32_t> rs;
+  std::vector<int32_t> seg;
+  pix.reserve(T);
+  rs.reserve(T);
+  std::vector<std::pair<int32_t, uint32_t>> tri;
+  for (int b = 0; b < nb; ++b) {
+    const int r0 = b * max_rows, r1 = std::min(p, r0 + max_rows);
+    tri.clear();
+    for (int r = r0; r < r1; ++r)
+      for (int j = 0; j < z; ++j) {
+        const int32_t v = c.sparse_idx[(int64_t)r * z + j];
+        const bool neg = c.sparse_sign && c.sparse_sign[(int64_t)r * z + j] < 0;
+        tri.emplace_back(v, (uint32_t)(r - r0) | (neg ? 0x80000000u : 0u));
+      }
+    std::stable_sort(tri.begin(), tri.end(),
+                     [](const std::pair<int32_t, uint32_t>& a, const std::pair<int32_t, uint32_t>& b2) {
+                       return a.first < b2.first;
+                     });
+    const int64_t base = (int64_t)pix.size(), cnt = (int64_t)tri.size();
+    for (auto& t : tri) {
+      pix.push_back(t.first);
+      rs.push_back(t.second);
+    }
+    for (int s = 0; s < nslot; ++s) {
+      seg.push_back((int32_t)(base + cnt * s / nslot));
+      seg.push_back((int32_t)(base + cnt * (s + 1) / nslot));
+      seg.push_back(r0);
+      seg.push_back(r1 - r0);
+      seg.push_back(s);
+    }
+  }
+  M->nseg = nb * nslot;
+  M->nslot = nslot;
+  M->max_rows = max_rows;
+  M->fpb = fpb;
+  TRY(dalloc(&M->d_tri_pix, pix.size()));
+  TRY(dalloc(&M->d_tri_rs, rs.size()));
+  TRY(dalloc(&M->d_seg, seg.size()));
+  HIPCHK(hipMemcpy(M->d_tri_pix, pix.data(), pix.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(M->d_tri_rs, rs.data(), rs.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(M->d_seg, seg.data(), seg.size() * 4, hipMemcpyHostToDevice));
+  return CDMD_OK;
+}
+
+// Eigenvector normalisation: unit 2-norm, largest-modulus entry (lowest index on ties)
+// real and positive.
+void normalise_columns(std::vector<cplx>& W, int k) {
+  for (int j = 0; j < k; ++j) {
+    cplx* w = &W[(size_t)j * k];
+    double nr = 0.0;
+    for (int i = 0; i < k; ++i) nr += std::norm(w[i]);
+    nr = std::sqrt(nr);
+    int piv = 0;
+    double best = -1.0;
+    for (int i = 0; i < k; ++i)
+      if (std::abs(w[i]) > best) best = std::abs(w[i]), piv = i;
+    const cplx ph = w[piv] / std::abs(w[piv]);
+    for (int i = 0; i < k; ++i) w[i] = w[i] / (ph * nr);
+    w[piv] = cplx(w[piv].real(), 0.0);
+  }
+}
+
+// Canonical order: descending |b_j| ||phi_j||; adjacent keys equal to kTieRel are put
+// positive imaginary part first.
+std::vector<int> canonical_order(const std::vector<cplx>& lam, const std::vector<double>& key) {
+  const int k = (int)lam.size();
+  std::vector<int> o(k);
+  std::iota(o.begin(), o.end(), 0);
+  std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return key[a] > key[b]; });
+  for (int i = 0; i + 1 < k; ++i) {
+    const int a = o[i], c = o[i + 1];
+    if (std::fabs(key[a] - key[c]) <= kTieRel * std::max(key[a], key[c]) &&
+        lam[a].imag() < lam[c].imag())
+      std::swap(o[i], o[i + 1]);
+  }
+  return o;
+}
+
+hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
+
+// Sketch + Gram + D2H of the Gram.
+cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st) {
+  const cdmd_config& c = M->cfg;
+  M->mark(0, st);
+  if (c.dtype == CDMD_U8) {
+    int32_t* out = M->nslot > 1 ? M->d_Ypart : M->d_Yint;
+    HIPCHK(cdmd::k::sketch_sparse_u8((const uint8_t*)d_video, M->ld, M->m, M->d_tri_pix, M->d_tri_rs,
+                                     M->d_seg, M->nseg, M->p, M->max_rows, M->fpb, out, M->nslot, st));
+    if (M->nslot > 1)
+      HIPCHK(cdmd::k::reduce_slots_i32(M->d_Ypart, M->nslot, (int64_t)M->m * M->p, M->d_Yint, st));
+    M->mark(1, st);
+    HIPCHK(cdmd::k::gram_i32(M->d_Yint, M->p, M->m, M->d_gram, st));
+  } else {
+    HIPCHK(cdmd::k::sketch_sparse_f32((const float*)d_video, M->ld, M->m, M->d_idx, M->d_sign, M->p,
+                                      c.nnz, M->d_Yd, st));
+    M->mark(1, st);
+    HIPCHK(cdmd::k::gram_f64(M->d_Yd, M->p, M->m, M->d_gram, st));
+  }
+  M->mark(2, st);
+  HIPCHK(hipMemcpyAsync(M->h_gram, M->d_gram, sizeof(double) * M->m * M->m, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (M->timing) {
+    M->info.gpu_ms_sketch = M->span(0, 1);
+    M->info.gpu_ms_gram = M->span(1, 2);
+  }
+  return CDMD_OK;
+}
+
+// Steps 4, 6, 7 and G = V S^-1 W on the host in float64.
+cdmd_status small_la(cdmd_model* M, std::vector<double>& V, std::vector<double>& mu) {
+  const int N = M->N, k = M->k;
+  const int64_t m = M->m;
+  const double* Gr = M->h_gram;
+  for (int64_t i = 0; i < m * m; ++i)
+    if (!std::isfinite(Gr[i])) return fail(CDMD_E_NUMERIC, "non-finite value in the sketch Gram");
+  std::vector<double> M11((size_t)N * N);
+  for (int a = 0; a < N; ++a)
+    for (int b2 = 0; b2 < N; ++b2) M11[(size_t)a * N + b2] = Gr[(size_t)a * m + b2];
+  V.assign((size_t)N * k, 0.0);
+  mu.assign(k, 0.0);
+  const int J = cdmd::la::sym_topk(M11.data(), N, k, kLanczosTol, mu.data(), V.data());
+  if (J < 0) return fail(CDMD_E_NUMERIC, "symmetric eigensolver failed");
+  M->info.lanczos_steps = J;
+  if (!(mu[0] > 0.0) || !(mu[k - 1] > kRankTol2 * mu[0]))
+    return fail(CDMD_E_RANK_DEFICIENT, "sigma_k <= 1e-6 sigma_1: target rank exceeds the numerical rank of Y");
+  std::vector<double> s(k);
+  for (int i = 0; i < k; ++i) s[i] = std::sqrt(mu[i]);
+  M->info.sigma_ratio = s[k - 1] / s[0];
+  M->sigma.resize(k);
+  for (int i = 0; i < k; ++i) M->sigma[i] = s[i] * M->sketch_scale;
+  // A~ = S^-1 V^T (Y^T Y') V S^-1 with Y^T Y' = Gram[0:N, 1:m]
+  std::vector<double> T((size_t)N * k, 0.0);  // T = M12 V (N x k, row-major)
+  for (int a = 0; a < N; ++a) {
+    const double* row = Gr + (size_t)a * m + 1;
+    for (int j = 0; j < k; ++j) {
+      const double* v = &V[(size_t)j * N];
+      double acc = 0.0;
+      for (int b2 = 0; b2 < N; ++b2) acc += row[b2] * v[b2];
+      T[(size_t)a * k + j] = acc;
+    }
+  }
+  std::vector<double> At((size_t)k * k);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      const double* v = &V[(size_t)i * N];
+      double acc = 0.0;
+      for (int a = 0; a < N; ++a) acc += v[a] * T[(size_t)a * k + j];
+      At[(size_t)i * k + j] = acc / (s[i] * s[j]);
+    }
+  M->lam.assign(k, 0.0);
+  M->W.assign((size_t)k * k, 0.0);
+  if (!cdmd::la::eig_general(At.data(), k, M->lam.data(), M->W.data()))
+    return fail(CDMD_E_NUMERIC, "eigensolver of A~ failed");
+  normalise_columns(M->W, k);
+  // G = V S^-1 W for the scaled sketch: sigma_scaled = s * sketch_scale
+  M->G.assign((size_t)N * k, 0.0);
+  for (int t = 0; t < N; ++t)
+    for (int j = 0; j < k; ++j) {
+      cplx acc = 0.0;
+      for (int i = 0; i < k; ++i) acc += (V[(size_t)i * N + t] / M->sigma[i]) * M->W[(size_t)j * k + i];
+      M->G[(size_t)t * k + j] = acc;
+    }
+  return CDMD_OK;
+}
+
+// Upload G (columns in `order`) to the device lift buffer, scaled to raw pixel units.
+cdmd_status upload_G(cdmd_model* M, const std::vector<int>& order, hipStream_t st) {
+  const int N = M->N, k = M->k, NC = M->NC;
+  for (int t = 0; t < N; ++t) {
+    float* row = M->h_G + (size_t)t * NC;
+    for (int c = 0; c < NC; ++c) row[c] = 0.f;
+    for (int j = 0; j < k; ++j) {
+      const cplx g = M->G[(size_t)t * k + order[j]] * (double)M->xscale;
+      row[j] = (float)g.real();
+      row[k + j] = (float)g.imag();
+    }
+  }
+  HIPCHK(hipMemcpyAsync(M->d_G, M->h_G, sizeof(float) * N * NC, hipMemcpyHostToDevice, st));
+  return CDMD_OK;
+}
+
+cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
+  M->mark(3, st);
+  HIPCHK(cdmd::k::lift_fp32(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_G, M->NC, M->nc,
+                            M->d_pairs, M->npair, M->d_part, M->lgrid, d_phi, M->k, M->xscale, st));
+  HIPCHK(cdmd::k::reduce_partials(M->d_part, M->lgrid, M->ne, M->d_red, st));
+  M->mark(4, st);
+  HIPCHK(hipMemcpyAsync(M->h_red, M->d_red, sizeof(double) * M->ne, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (M->timing) M->info.gpu_ms_lift = M->span(3, 4);
+  return CDMD_OK;
+}
+
+// H = Phi^H Phi, c = Phi^H x_1 from the real partial Gram of [Re Phi | Im Phi].
+void assemble_H(cdmd_model* M, std::vector<cplx>& H, std::vector<cplx>& cvec) {
+  const int k = M->k, nc = M->nc;
+  std::vector<double> P((size_t)nc * nc);
+  int e = 0;
+  for (int a = 0; a < nc; ++a)
+    for (int b2 = a; b2 < nc; ++b2, ++e) {
+      P[(size_t)a * nc + b2] = M->h_red[e];
+      P[(size_t)b2 * nc + a] = M->h_red[e];
+    }
+  H.assign((size_t)k * k, 0.0);
+  cvec.assign(k, 0.0);
+  for (int j = 0; j < k; ++j)
+    for (int l = 0; l < k; ++l) {
+      const double re = P[(size_t)j * nc + l] + P[(size_t)(k + j) * nc + (k + l)];
+      const double im = P[(size_t)j * nc + (k + l)] - P[(size_t)(k + j) * nc + l];
+      H[(size_t)j * k + l] = cplx(re, im);
+    }
+  for (int j = 0; j < k; ++j) cvec[j] = cplx(M->h_red[M->npair + j], -M->h_red[M->npair + k + j]);
+  M->x1n2 = M->h_red[M->npair + nc];
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t cdmd_abi_version(void) { return CDMD_ABI_VERSION; }
+
+const char* cdmd_last_error(void) { return g_err.c_str(); }
+
+cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
+  g_err.clear();
+  if (!out) return fail(CDMD_E_INVALID_ARG, "out is NULL");
+  *out = nullptr;
+  TRY(validate(cfg));
+  int dev = -1;
+  TRY(check_device(&dev));
+  cdmd_model* M = new (std::nothrow) cdmd_model();
+  if (!M) return fail(CDMD_E_OUT_OF_MEMORY, "host allocation failed");
+  struct Guard {
+    cdmd_model*& m;
+    bool keep = false;
+    ~Guard() {
+      if (!keep) delete m;
+    }
+  } guard{M};
+  M->cfg = *cfg;
+  M->device = dev;
+  M->n = cfg->n;
+  M->m = cfg->m;
+  M->ld = cfg->ld;
+  M->k = cfg->k;
+  M->p = cfg->p;
+  M->N = (int)(cfg->m - 1);
+  M->nc = 2 * cfg->k;
+  M->NC = pad_nc(M->nc);
+  M->npair = M->nc * (M->nc + 1) / 2;
+  M->ne = M->npair + M->nc + 1;
+  M->xscale = cfg->dtype == CDMD_U8 ? 1.0f / 255.0f : 1.0f;
+  M->sketch_scale = cfg->dtype == CDMD_U8 ? 1.0 / 255.0 : 1.0;
+  M->info.warn_few_samples =
+      (double)cfg->p < (double)cfg->k * std::log((double)cfg->n / (double)cfg->k) ? 1 : 0;
+  const int64_t m = M->m, p = M->p;
+  if (cfg->dtype == CDMD_U8) {
+    TRY(build_sparse_plan(M));
+    TRY(dalloc(&M->d_Yint, (size_t)m * p));
+    if (M->nslot > 1) TRY(dalloc(&M->d_Ypart, (size_t)M->nslot * m * p));
+  } else {
+    const size_t T = (size_t)p * cfg->nnz;
+    TRY(dalloc(&M->d_idx, T));
+    TRY(dalloc(&M->d_sign, T));
+    std::vector<int8_t> sg(T, 1);
+    if (cfg->sparse_sign) std::memcpy(sg.data(), cfg->sparse_sign, T);
+    HIPCHK(hipMemcpy(M->d_idx, cfg->sparse_idx, T * 4, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(M->d_sign, sg.data(), T, hipMemcpyHostToDevice));
+    TRY(dalloc(&M->d_Yd, (size_t)m * p));
+  }
+  M->cfg.sparse_idx = nullptr;
+  M->cfg.sparse_sign = nullptr;
+  TRY(dalloc(&M->d_gram, (size_t)m * m));
+  TRY(halloc(&M->h_gram, (size_t)m * m));
+  TRY(dalloc(&M->d_G, (size_t)M->N * M->NC));
+  TRY(halloc(&M->h_G, (size_t)M->N * M->NC));
+  std::vector<uint32_t> pairs;
+  for (int a = 0; a < M->nc; ++a)
+    for (int b2 = a; b2 < M->nc; ++b2) pairs.push_back((uint32_t)a | ((uint32_t)b2 << 16));
+  TRY(dalloc(&M->d_pairs, pairs.size()));
+  HIPCHK(hipMemcpy(M->d_pairs, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
+  M->lgrid = cdmd::k::lift_grid(M->n);
+  TRY(dalloc(&M->d_part, (size_t)M->lgrid * M->ne));
+  TRY(dalloc(&M->d_red, (size_t)M->ne));
+  TRY(halloc(&M->h_red, (size_t)M->ne));
+  TRY(dalloc(&M->d_Gs, (size_t)M->N * 80));
+  TRY(halloc(&M->h_Gs, (size_t)M->N * 80));
+  TRY(dalloc(&M->d_Vc, (size_t)m * 80));
+  TRY(halloc(&M->h_Vc, (size_t)m * 80));
+  TRY(dalloc(&M->d_counts, (size_t)m));
+  TRY(halloc(&M->h_counts, (size_t)m));
+  guard.keep = true;
+  *out = M;
+  return CDMD_OK;
+}
+
+void cdmd_free(cdmd_model* mdl) { delete mdl; }
+
+cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
+  g_err.clear();
+  if (!M || !d_video) return fail(CDMD_E_INVALID_ARG, "NULL model or video");
+  hipStream_t st = as_stream(stream);
+  M->fitted = M->selected = false;
+  M->g_canonical_on_device = false;
+  double t0 = now_ms();
+  TRY(run_sketch(M, d_video, st));
+  double t1 = now_ms();
+  std::vector<double> V, mu;
+  TRY(small_la(M, V, mu));
+  double t2 = now_ms();
+  std::vector<int> ident(M->k);
+  std::iota(ident.begin(), ident.end(), 0);
+  TRY(upload_G(M, ident, st));
+  TRY(run_lift(M, d_video, nullptr, st));
+  double t3 = now_ms();
+  std::vector<cplx> H, cv;
+  assemble_H(M, H, cv);
+  const int k = M->k;
+  std::vector<cplx> b(k);
+  if (!cdmd::la::herm_pd_solve(H.data(), k, k, cv.data(), b.data()))
+    if (!cdmd::la::lu_solve(H.data(), k, cv.data(), b.data()))
+      return fail(CDMD_E_NUMERIC, "amplitude least squares failed (singular Phi^H Phi)");
+  std::vector<double> nrm(k), key(k);
+  for (int j = 0; j < k; ++j) {
+    nrm[j] = std::sqrt(std::max(H[(size_t)j * k + j].real(), 0.0));
+    key[j] = std::abs(b[j]) * nrm[j];
+  }
+  std::vector<int> o = canonical_order(M->lam, key);
+  M->perm = o;
+  std::vector<cplx> lam(k), W((size_t)k * k), G((size_t)M->N * k), Hc((size_t)k * k), cc(k), bc(k);
+  std::vector<double> pn(k);
+  for (int j = 0; j < k; ++j) {
+    const int s = o[j];
+    lam[j] = M->lam[s];
+    for (int i = 0; i < k; ++i) W[(size_t)j * k + i] = M->W[(size_t)s * k + i];
+    for (int t = 0; t < M->N; ++t) G[(size_t)t * k + j] = M->G[(size_t)t * k + s];
+    for (int l = 0; l < k; ++l) Hc[(size_t)j * k + l] = H[(size_t)s * k + o[l]];
+    cc[j] = cv[s];
+    bc[j] = b[s];
+    pn[j] = nrm[s];
+  }
+  M->lam.swap(lam);
+  M->W.swap(W);
+  M->G.swap(G);
+  M->H.swap(Hc);
+  M->c.swap(cc);
+  M->b.swap(bc);
+  M->phinorm.swap(pn);
+  double t4 = now_ms();
+  M->info.ms_sketch = t1 - t0;
+  M->info.ms_small_la = t2 - t1;
+  M->info.ms_lift = t3 - t2;
+  M->info.ms_host_post = t4 - t3;
+  M->info.x1_norm2 = M->x1n2;
+  M->fitted = true;
+  M->info.fitted = 1;
+  M->info.selected = 0;
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_modes(const cdmd_model* Mc, double* lambda, double* b, double* sigma,
+                       double* phi_norm, const void* d_video, void* d_phi, void* stream) {
+  g_err.clear();
+  if (!Mc) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  cdmd_model* M = const_cast<cdmd_model*>(Mc);
+  if (!M->fitted) return fail(CDMD_E_STATE, "model is not fitted");
+  const int k = M->k;
+  for (int j = 0; j < k; ++j) {
+    if (lambda) lambda[2 * j] = M->lam[j].real(), lambda[2 * j + 1] = M->lam[j].imag();
+    if (b) b[2 * j] = M->b[j].real(), b[2 * j + 1] = M->b[j].imag();
+    if (sigma) sigma[j] = M->sigma[j];
+    if (phi_norm) phi_norm[j] = M->phinorm[j];
+  }
+  if (d_phi) {
+    if (!d_video) return fail(CDMD_E_INVALID_ARG, "d_phi needs the fitted video");
+    hipStream_t st = as_stream(stream);
+    std::vector<int> ident(k);
+    std::iota(ident.begin(), ident.end(), 0);
+    TRY(upload_G(M, ident, st));  // M->G is in canonical order
+    // the lift reduction buffers are reused; results of the fit are kept on the host
+    HIPCHK(cdmd::k::lift_fp32(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_G, M->NC, M->nc,
+                              M->d_pairs, M->npair, M->d_part, M->lgrid, (float*)d_phi, k,
+                              M->xscale, st));
+    HIPCHK(hipStreamSynchronize(st));
+  }
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_select(cdmd_model* M, int32_t selector, int32_t K, double omega_thr,
+                        const int32_t* explicit_idx, int32_t n_explicit, int32_t* out_idx,
+                        int32_t* out_n, double* out_beta) {
+  g_err.clear();
+  if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  if (!M->fitted) return fail(CDMD_E_STATE, "model is not fitted");
+  const int k = M->k;
+  std::vector<int> S;
+  std::vector<cplx> beta;
+  double r2 = 0.0;
+  switch (selector) {
+    case CDMD_SEL_OMP: {
+      if (K < 1) return fail(CDMD_E_INVALID_ARG, "OMP needs K >= 1");
+      if (!cdmd::la::omp_gram(M->H.data(), k, M->c.data(), M->x1n2, K, kTieRel, kOmpStopRel, S, beta, &r2))
+        return fail(CDMD_E_NUMERIC, "OMP subsystem singular");
+      break;
+    }
+    case CDMD_SEL_ZERO_MODE: {
+      int best = 0;
+      double bv = 1e300;
+      for (int j = 0; j < k; ++j) {
+        const double w = std::abs(std::log(M->lam[j]));
+        if (w < bv) bv = w, best = j;
+      }
+      S.push_back(best);
+      beta.push_back(M->b[best]);
+      break;
+    }
+    case CDMD_SEL_OMEGA: {
+      if (!(omega_thr > 0.0)) return fail(CDMD_E_INVALID_ARG, "omega_thr must be > 0");
+      for (int j = 0; j < k; ++j)
+        if (std::abs(std::log(M->lam[j])) < omega_thr) S.push_back(j), beta.push_back(M->b[j]);
+      break;
+    }
+    case CDMD_SEL_EXPLICIT: {
+      if (!explicit_idx || n_explicit < 1 || n_explicit > k)
+        return fail(CDMD_E_INVALID_ARG, "explicit support needs 1..k indices");
+      std::vector<char> seen(k, 0);
+      for (int q = 0; q < n_explicit; ++q) {
+        const int j = explicit_idx[q];
+        if (j < 0 || j >= k || seen[j]) return fail(CDMD_E_INVALID_ARG, "explicit index out of range or repeated");
+        seen[j] = 1;
+        S.push_back(j);
+      }
+      const int ns = (int)S.size();
+      std::vector<cplx> Hs((size_t)ns * ns), cs(ns);
+      for (int a = 0; a < ns; ++a) {
+        cs[a] = M->c[S[a]];
+        for (int b2 = 0; b2 < ns; ++b2) Hs[(size_t)a * ns + b2] = M->H[(size_t)S[a] * k + S[b2]];
+      }
+      beta.assign(ns, 0.0);
+      if (!cdmd::la::herm_pd_solve(Hs.data(), ns, ns, cs.data(), beta.data()))
+        if (!cdmd::la::lu_solve(Hs.data(), ns, cs.data(), beta.data()))
+          return fail(CDMD_E_NUMERIC, "explicit support subsystem singular");
+      break;
+    }
+    case CDMD_SEL_ALL: {
+      for (int j = 0; j < k; ++j) S.push_back(j), beta.push_back(M->b[j]);
+      break;
+    }
+    default:
+      return fail(CDMD_E_INVALID_ARG, "unknown selector");
+  }
+  if (selector != CDMD_SEL_OMP) {
+    // ||x_1 - Phi_S beta||^2 = ||x_1||^2 - 2 Re(beta^H c_S) + beta^H H_SS beta
+    const int ns = (int)S.size();
+    cplx q = 0.0, hq = 0.0;
+    for (int a = 0; a < ns; ++a) {
+      q += std::conj(beta[a]) * M->c[S[a]];
+      for (int b2 = 0; b2 < ns; ++b2) hq += std::conj(beta[a]) * M->H[(size_t)S[a] * k + S[b2]] * beta[b2];
+    }
+    r2 = std::max(M->x1n2 - 2.0 * q.real() + hq.real(), 0.0);
+  }
+  M->S = S;
+  M->beta = beta;
+  M->selected = true;
+  M->info.selected = 1;
+  M->info.n_selected = (int)S.size();
+  M->info.omp_residual2 = r2;
+  if (out_n) *out_n = (int32_t)S.size();
+  for (size_t q = 0; q < S.size(); ++q) {
+    if (out_idx) out_idx[q] = S[q];
+    if (out_beta) out_beta[2 * q] = beta[q].real(), out_beta[2 * q + 1] = beta[q].imag();
+  }
+  return CDMD_OK;
+}
+
+namespace {
+
+// Host side of the reconstruction: Gs = [Re(G_S diag beta) | Im(...)] * xscale and the
+// Vandermonde rows Vc[t] = [Re lambda^t | -Im lambda^t] (t = 0..m-1, 0-based).
+cdmd_status prepare_recon(cdmd_model* M, int static_bg, int* NSout, hipStream_t st) {
+  const int ns = (int)M->S.size();
+  const int NS = pad_ns(std::max(2 * ns, 1));
+  if (NS < 0) return fail(CDMD_E_UNSUPPORTED, "more than 40 selected modes");
+  const int N = M->N, k = M->k;
+  const int64_t m = M->m;
+  for (int t = 0; t < N; ++t) {
+    float* row = M->h_Gs + (size_t)t * NS;
+    for (int c = 0; c < NS; ++c) row[c] = 0.f;
+    for (int s = 0; s < ns; ++s) {
+      const cplx g = M->G[(size_t)t * k + M->S[s]] * M->beta[s] * (double)M->xscale;
+      row[s] = (float)g.real();
+      row[ns + s] = (float)g.imag();
+    }
+  }
+  for (int s = 0; s < ns; ++s) {
+    const cplx l = M->lam[M->S[s]];
+    if (!static_bg && std::abs(l) > 1.0 && std::pow(std::abs(l), (double)(m - 1)) > kVanderMax)
+      return fail(CDMD_E_NUMERIC, "|lambda|^(m-1) overflows the Vandermonde matrix");
+  }
+  std::vector<cplx> pw(ns, cplx(1.0, 0.0));
+  for (int64_t t = 0; t < m; ++t) {
+    float* row = M->h_Vc + (size_t)t * NS;
+    for (int c = 0; c < NS; ++c) row[c] = 0.f;
+    for (int s = 0; s < ns; ++s) {
+      row[s] = (float)pw[s].real();
+      row[ns + s] = (float)(-pw[s].imag());
+      if (!static_bg) pw[s] *= M->lam[M->S[s]];
+    }
+  }
+  HIPCHK(hipMemcpyAsync(M->d_Gs, M->h_Gs, sizeof(float) * N * NS, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(M->d_Vc, M->h_Vc, sizeof(float) * m * NS, hipMemcpyHostToDevice, st));
+  *NSout = NS;
+  return CDMD_OK;
+}
+
+}  // namespace
+
+cdmd_status cdmd_background(const cdmd_model* Mc, const void* d_video, int64_t t0, int64_t t1,
+                            int32_t static_bg, float* d_L, int64_t ldL, void* stream) {
+  g_err.clear();
+  if (!Mc || !d_video || !d_L) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  cdmd_model* M = const_cast<cdmd_model*>(Mc);
+  if (!M->selected) return fail(CDMD_E_STATE, "select background modes first");
+  if (static_bg) {
+    t0 = 0;
+    t1 = 1;
+    ldL = M->n;
+  }
+  if (t0 < 0 || t1 > M->m || t0 >= t1) return fail(CDMD_E_INVALID_ARG, "need 0 <= t0 < t1 <= m");
+  if (ldL < M->n) return fail(CDMD_E_INVALID_ARG, "need ldL >= n");
+  hipStream_t st = as_stream(stream);
+  int NS = 0;
+  TRY(prepare_recon(M, static_bg, &NS, st));
+  M->mark(5, st);
+  HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, 0.f,
+                       M->xscale, 2, d_L, t0, t1, ldL, st));
+  M->mark(6, st);
+  M->recon_pending = M->timing;
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_foreground(const cdmd_model* Mc, const void* d_video, float tau,
+                            int32_t static_bg, int32_t bitpacked, void* d_mask,
+                            int64_t* h_counts, void* stream) {
+  g_err.clear();
+  if (!Mc || !d_video || !d_mask) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  cdmd_model* M = const_cast<cdmd_model*>(Mc);
+  if (!M->selected) return fail(CDMD_E_STATE, "select background modes first");
+  if (!(tau >= 0.f)) return fail(CDMD_E_INVALID_ARG, "tau must be >= 0");
+  if (h_counts && !bitpacked) return fail(CDMD_E_INVALID_ARG, "counts need the bit-packed mask");
+  hipStream_t st = as_stream(stream);
+  int NS = 0;
+  TRY(prepare_recon(M, static_bg, &NS, st));
+  M->mark(5, st);
+  HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, tau,
+                       M->xscale, bitpacked ? 0 : 1, d_mask, 0, M->m, 0, st));
+  M->mark(6, st);
+  M->recon_pending = M->timing;
+  if (h_counts) {
+    const int64_t words = (M->n + 31) / 32;
+    HIPCHK(cdmd::k::mask_counts((const uint32_t*)d_mask, words, M->m, M->d_counts, st));
+    HIPCHK(hipMemcpyAsync(M->h_counts, M->d_counts, sizeof(int64_t) * M->m, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    std::memcpy(h_counts, M->h_counts, sizeof(int64_t) * M->m);
+  }
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_get_sketch(const cdmd_model* Mc, double* h_Y, int64_t* h_int) {
+  g_err.clear();
+  if (!Mc) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  const cdmd_model* M = Mc;
+  if (!M->fitted) return fail(CDMD_E_STATE, "model is not fitted");
+  const size_t cnt = (size_t)M->m * M->p;
+  if (M->cfg.dtype == CDMD_U8) {
+    std::vector<int32_t> tmp(cnt);
+    HIPCHK(hipMemcpy(tmp.data(), M->d_Yint, cnt * 4, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < cnt; ++i) {
+      if (h_Y) h_Y[i] = tmp[i] * M->sketch_scale;
+      if (h_int) h_int[i] = tmp[i];
+    }
+  } else {
+    if (h_int) return fail(CDMD_E_INVALID_ARG, "integer sums exist only for uint8 sparse sketches");
+    std::vector<double> tmp(cnt);
+    HIPCHK(hipMemcpy(tmp.data(), M->d_Yd, cnt * 8, hipMemcpyDeviceToHost));
+    for (size_t i = 0; i < cnt; ++i)
+      if (h_Y) h_Y[i] = tmp[i] * M->sketch_scale;
+  }
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_info_get(const cdmd_model* Mc, cdmd_info* info) {
+  g_err.clear();
+  if (!Mc || !info) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  cdmd_model* M = const_cast<cdmd_model*>(Mc);
+  if (M->recon_pending) {
+    HIPCHK(hipEventSynchronize(M->ev[6]));
+    M->info.gpu_ms_recon = M->span(5, 6);
+    M->recon_pending = false;
+  }
+  *info = M->info;
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_set_timing(cdmd_model* M, int32_t enable) {
+  g_err.clear();
+  if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  if (enable && !M->ev[0]) {
+    for (hipEvent_t& e : M->ev) HIPCHK(hipEventCreate(&e));
+  }
+  M->timing = enable != 0;
+  M->info.timing = M->timing ? 1 : 0;
+  return CDMD_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// host-only test entry points (include/cdmd_debug.h)
+#include "cdmd_debug.h"
+
+extern "C" {
+
+cdmd_status cdmd_dbg_sym_topk(const double* M, int32_t n, int32_t k, double rtol, double* evals,
+                              double* evecs, int32_t* steps) {
+  g_err.clear();
+  if (!M || !evals || !evecs || n < 1 || k < 1 || k > n) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  const int J = cdmd::la::sym_topk(M, n, k, rtol, evals, evecs);
+  if (J < 0) return fail(CDMD_E_NUMERIC, "symmetric eigensolver failed");
+  if (steps) *steps = J;
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_eig_general(const double* A, int32_t k, double* lam, double* W) {
+  g_err.clear();
+  if (!A || !lam || !W || k < 1) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  if (!cdmd::la::eig_general(A, k, reinterpret_cast<cplx*>(lam), reinterpret_cast<cplx*>(W)))
+    return fail(CDMD_E_NUMERIC, "eigensolver failed");
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_omp_gram(const double* H, int32_t k, const double* c, double x1n2, int32_t K,
+                              int32_t* S, double* beta, int32_t* ns, double* resid2) {
+  g_err.clear();
+  if (!H || !c || !S || !beta || !ns || k < 1 || K < 1) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  std::vector<int> sv;
+  std::vector<cplx> bv;
+  double r2 = 0.0;
+  if (!cdmd::la::omp_gram(reinterpret_cast<const cplx*>(H), k, reinterpret_cast<const cplx*>(c), x1n2, K,
+                          kTieRel, kOmpStopRel, sv, bv, &r2))
+    return fail(CDMD_E_NUMERIC, "OMP subsystem singular");
+  *ns = (int32_t)sv.size();
+  for (size_t q = 0; q < sv.size(); ++q) {
+    S[q] = sv[q];
+    beta[2 * q] = bv[q].real();
+    beta[2 * q + 1] = bv[q].imag();
+  }
+  if (resid2) *resid2 = r2;
+  return CDMD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Launchers of the cDMD HIP kernels (gfx950).  Every launcher enqueues on `stream`
+// and returns the hipError_t of the launch.  Shapes are validated by the caller
+// (api.cpp); the launchers assume them.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace cdmd {
+namespace k {
+
+// ----- sketch, sparse / single-pixel, uint8 video (exact integer sums) -------------
+// Triples (pixel, row | sign bit 31) grouped by segment; each segment covers rows
+// [seg_r0, seg_r0 + seg_nrows) and triple range [seg_begin, seg_end), its triples
+// sorted by pixel.  seg[4*s + 0..3] = begin, end, r0, nrows; part[s] is the partial
+// slot of the segment inside its row block (0 .. nslot-1).
+// Output: Ypart[slot][t][r] int32 (t < m, r < p) when nslot > 1, else Y directly.
+hipError_t sketch_sparse_u8(const uint8_t* D, int64_t ld, int64_t m, const int32_t* tri_pix,
+                            const uint32_t* tri_rs, const int32_t* seg, int nseg, int p,
+                            int max_rows, int fpb, int32_t* Yout, int nslot,
+                            hipStream_t stream);
+// Y[t][r] = sum_s Ypart[s][t][r]
+hipError_t reduce_slots_i32(const int32_t* Ypart, int nslot, int64_t count, int32_t* Y,
+                            hipStream_t stream);
+
+// ----- sketch, sparse / single-pixel, float32 video (row order, float64 sums) ------
+// Y[t][r] = sum_j sign_rj * D[t][idx_rj], j in row order.
+hipError_t sketch_sparse_f32(const float* D, int64_t ld, int64_t m, const int32_t* idx,
+                             const int8_t* sign, int p, int nnz, double* Y,
+                             hipStream_t stream);
+
+// ----- Gram of the sketch: Gr[a][b] = sum_r Y[a][r] Y[b][r] (m x m, float64) ------
+hipError_t gram_i32(const int32_t* Y, int p, int64_t m, double* Gr, hipStream_t stream);
+hipError_t gram_f64(const double* Y, int p, int64_t m, double* Gr, hipStream_t stream);
+
+// ----- lift: Phi = X' G (fp32) with fused per-block partial Gram of Phi -----------
+// G is (m-1) x NC float row-major (columns >= nc are zero).  Per block, partial sums
+// over its pixels: entries e < npair of Phi[:, pa]^T Phi[:, pb] (pairs[e] = pa | pb<<16),
+// then nc entries Phi[:, a]^T x_1, then ||x_1||^2.  part: [grid][ne] float64.
+// phi (optional): complex64 mode-contiguous store, phi[2*(j*n + i) + 0/1] =
+// Phi[i, j] / Phi[i, k + j] for j < kmodes.
+hipError_t lift_fp32(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, const float* G,
+                     int NC, int nc, const uint32_t* pairs, int npair, double* part,
+                     int grid, float* phi, int kmodes, float xscale, hipStream_t stream);
+int lift_grid(int64_t n);
+// out[e] = sum_b part[b][e]
+hipError_t reduce_partials(const double* part, int grid, int ne, double* out,
+                           hipStream_t stream);
+
+// ----- fused background reconstruction + foreground threshold --------------------
+// T = X' Gs (Gs: (m-1) x NS float, NS = 2|S| padded), then per frame t
+// L_t = sum_c T[:, c] Vc[t][c]; mask = |x_t - L_t| > tau.
+// mode 0: bit-packed mask (uint32 words, ceil(n/32) per frame)
+// mode 1: uint8 mask (n per frame)
+// mode 2: write L (float, frames t0..t1-1 at (t - t0) * ldL)
+hipError_t bgfg(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, const float* Gs,
+                int NS, const float* Vc, float tau, float xscale, int mode, void* out,
+                int64_t t0, int64_t t1, int64_t ldL, hipStream_t stream);
+// counts[t] = number of set bits of frame t of a bit-packed mask
+hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* counts,
+                       hipStream_t stream);
+
+}  // namespace k
+}  // namespace cdmd

@@ -1,0 +1,489 @@
+// Small dense float64 linear algebra of the cDMD fit (host side).  See smallla.hpp.
+#include "smallla.hpp"
+
+#include <algorithm>
+#include <cfloat>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+
+namespace cdmd {
+namespace la {
+
+static inline double sgn1(double x) { return x >= 0.0 ? 1.0 : -1.0; }
+
+static inline double dot(const double* a, const double* b, int n) {
+  double s0 = 0, s1 = 0, s2 = 0, s3 = 0;
+  int i = 0;
+  for (; i + 4 <= n; i += 4) {
+    s0 += a[i] * b[i];
+    s1 += a[i + 1] * b[i + 1];
+    s2 += a[i + 2] * b[i + 2];
+    s3 += a[i + 3] * b[i + 3];
+  }
+  for (; i < n; ++i) s0 += a[i] * b[i];
+  return (s0 + s1) + (s2 + s3);
+}
+
+// ---------------------------------------------------------------------------
+// Symmetric tridiagonal eigenproblem: implicit QR sweeps, Wilkinson shift.
+// A rotation acting on indices (k, k+1) is R = [[c, s], [-s, c]]; the similarity
+// T <- R^T T R is applied to the 2x2 block, the coupling to k-1 (where it annihilates
+// the bulge) and to k+2 (where it creates the next bulge); Z <- Z R.
+bool tridiag_eig(double* d, double* e, int n, double* Z, int R, int row0) {
+  if (n <= 0) return true;
+  for (int r = 0; r < R; ++r)
+    for (int j = 0; j < n; ++j) Z[(size_t)r * n + j] = (row0 + r == j) ? 1.0 : 0.0;
+  const double eps = DBL_EPSILON;
+  int hi = n - 1;
+  long iter = 0;
+  const long maxit = 64L * n + 64;
+  while (hi > 0) {
+    if (std::fabs(e[hi - 1]) <= eps * (std::fabs(d[hi - 1]) + std::fabs(d[hi]))) {
+      e[hi - 1] = 0.0;
+      --hi;
+      continue;
+    }
+    int lo = hi - 1;
+    while (lo > 0 && std::fabs(e[lo - 1]) > eps * (std::fabs(d[lo - 1]) + std::fabs(d[lo]))) --lo;
+    if (lo > 0) e[lo - 1] = 0.0;
+    if (++iter > maxit) return false;
+    const double a = d[hi - 1], b = d[hi], ee = e[hi - 1];
+    const double delta = 0.5 * (a - b);
+    const double den = delta + sgn1(delta) * std::hypot(delta, ee);
+    const double mu = b - ee * (ee / den);
+    double bulge = 0.0;
+    for (int k = lo; k < hi; ++k) {
+      const double u = (k == lo) ? d[lo] - mu : e[k - 1];
+      const double v = (k == lo) ? e[lo] : bulge;
+      const double r = std::hypot(u, v);
+      double c = 1.0, s = 0.0;
+      if (r != 0.0) {
+        c = u / r;
+        s = -v / r;
+      }
+      if (k > lo) e[k - 1] = r;
+      const double a0 = d[k], b0 = d[k + 1], e0 = e[k];
+      const double cc = c * c, ss = s * s, cs = c * s;
+      d[k] = cc * a0 - 2.0 * cs * e0 + ss * b0;
+      d[k + 1] = ss * a0 + 2.0 * cs * e0 + cc * b0;
+      e[k] = cs * (a0 - b0) + (cc - ss) * e0;
+      if (k + 1 < hi) {
+        const double f = e[k + 1];
+        bulge = -s * f;
+        e[k + 1] = c * f;
+      }
+      for (int rr = 0; rr < R; ++rr) {
+        double* zr = Z + (size_t)rr * n;
+        const double zk = zr[k], zk1 = zr[k + 1];
+        zr[k] = c * zk - s * zk1;
+        zr[k + 1] = s * zk + c * zk1;
+      }
+    }
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+// Lanczos with full reorthogonalisation for the top-k eigenpairs.
+int sym_topk(const double* M, int n, int k, double rtol, double* evals, double* evecs) {
+  if (k < 1 || k > n || n < 1) return -1;
+  std::vector<double> Q((size_t)n * (n + 1), 0.0);
+  std::vector<double> alpha(n + 1, 0.0), beta(n + 1, 0.0), w(n), h(n + 1);
+  auto newvec = [&](double* q, int salt) {
+    for (int i = 0; i < n; ++i) q[i] = 1.0 + 0.25 * std::sin(0.7 * (i + 1) + 1.3 * salt);
+  };
+  auto orth = [&](double* v, int J) -> double {  // twice CGS against Q[0..J)
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i < J; ++i) h[i] = dot(&Q[(size_t)i * n], v, n);
+      for (int i = 0; i < J; ++i) {
+        const double* qi = &Q[(size_t)i * n];
+        const double hi = h[i];
+        for (int t = 0; t < n; ++t) v[t] -= hi * qi[t];
+      }
+    }
+    return std::sqrt(dot(v, v, n));
+  };
+  {
+    double* q0 = Q.data();
+    newvec(q0, 0);
+    const double nr = std::sqrt(dot(q0, q0, n));
+    for (int i = 0; i < n; ++i) q0[i] /= nr;
+  }
+  double anorm = 0.0;
+  int J = 0;
+  int next_check = std::min(n, std::max(2 * k, k + 16));
+  std::vector<double> dd, ee, zl;
+  std::vector<int> idx;
+  int restarts = 0;
+  for (int j = 0; j < n; ++j) {
+    const double* qj = &Q[(size_t)j * n];
+    for (int i = 0; i < n; ++i) w[i] = dot(M + (size_t)i * n, qj, n);
+    // projections on all previous vectors, twice; alpha_j is the q_j component
+    double aj = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int i = 0; i <= j; ++i) h[i] = dot(&Q[(size_t)i * n], w.data(), n);
+      aj += h[j];
+      for (int i = 0; i <= j; ++i) {
+        const double* qi = &Q[(size_t)i * n];
+        const double hi = h[i];
+        for (int t = 0; t < n; ++t) w[t] -= hi * qi[t];
+      }
+    }
+    alpha[j] = aj;
+    beta[j] = std::sqrt(dot(w.data(), w.data(), n));
+    J = j + 1;
+    anorm = std::max(anorm, std::fabs(alpha[j]) + beta[j] + (j ? beta[j - 1] : 0.0));
+    const bool breakdown = beta[j] <= 64.0 * DBL_EPSILON * anorm;
+    if (J == next_check || breakdown || J == n) {
+      dd.assign(alpha.begin(), alpha.begin() + J);
+      ee.assign(beta.begin(), beta.begin() + J);
+      zl.assign(J, 0.0);
+      if (!tridiag_eig(dd.data(), ee.data(), J, zl.data(), 1, J - 1)) return -1;
+      idx.resize(J);
+      std::iota(idx.begin(), idx.end(), 0);
+      std::sort(idx.begin(), idx.end(), [&](int a, int b) { return dd[a] > dd[b]; });
+      bool conv = J >= k;
+      if (conv) {
+        const double scale = std::max(std::fabs(dd[idx[0]]), DBL_MIN);
+        for (int i = 0; i < k; ++i)
+          if (beta[j] * std::fabs(zl[idx[i]]) > rtol * scale) conv = false;
+      }
+      if (conv || J == n) break;
+      if (breakdown) {
+        // invariant subspace smaller than k: continue from a fresh orthogonal vector
+        if (++restarts > 8) return -1;
+        double* qn = &Q[(size_t)J * n];
+        newvec(qn, J + 17 * restarts);
+        const double nr = orth(qn, J);
+        if (nr <= 1e-8) return -1;
+        for (int i = 0; i < n; ++i) qn[i] /= nr;
+        beta[j] = 0.0;
+        next_check = std::min(n, J + std::max(16, J / 4));
+        continue;
+      }
+      next_check = std::min(n, J + std::max(16, J / 4));
+    }
+    double* qn = &Q[(size_t)J * n];
+    const double inv = 1.0 / beta[j];
+    for (int i = 0; i < n; ++i) qn[i] = w[i] * inv;
+  }
+  // full eigenvectors of T_J
+  dd.assign(alpha.begin(), alpha.begin() + J);
+  ee.assign(beta.begin(), beta.begin() + J);
+  std::vector<double> Z((size_t)J * J);
+  if (!tridiag_eig(dd.data(), ee.data(), J, Z.data(), J, 0)) return -1;
+  idx.resize(J);
+  std::iota(idx.begin(), idx.end(), 0);
+  std::sort(idx.begin(), idx.end(), [&](int a, int b) { return dd[a] > dd[b]; });
+  if (J < k) return -1;
+  for (int c = 0; c < k; ++c) {
+    const int col = idx[c];
+    evals[c] = dd[col];
+    double* v = evecs + (size_t)c * n;
+    std::fill(v, v + n, 0.0);
+    for (int i = 0; i < J; ++i) {
+      const double zi = Z[(size_t)i * J + col];
+      const double* qi = &Q[(size_t)i * n];
+      for (int t = 0; t < n; ++t) v[t] += zi * qi[t];
+    }
+    const double nr = std::sqrt(dot(v, v, n));
+    for (int t = 0; t < n; ++t) v[t] /= nr;
+  }
+  return J;
+}
+
+// ---------------------------------------------------------------------------
+// General real eigenproblem.
+bool lu_solve(const cplx* A, int n, const cplx* c, cplx* x) {
+  std::vector<cplx> M(A, A + (size_t)n * n);
+  std::vector<cplx> b(c, c + n);
+  double amax = 0;
+  for (int i = 0; i < n * n; ++i) amax = std::max(amax, std::abs(M[i]));
+  const double tiny = std::max(amax, 1e-300) * DBL_EPSILON;
+  for (int j = 0; j < n; ++j) {
+    int piv = j;
+    double best = std::abs(M[(size_t)j * n + j]);
+    for (int i = j + 1; i < n; ++i)
+      if (std::abs(M[(size_t)i * n + j]) > best) best = std::abs(M[(size_t)i * n + j]), piv = i;
+    if (piv != j) {
+      for (int t = 0; t < n; ++t) std::swap(M[(size_t)j * n + t], M[(size_t)piv * n + t]);
+      std::swap(b[j], b[piv]);
+    }
+    cplx p = M[(size_t)j * n + j];
+    if (std::abs(p) < tiny) p = M[(size_t)j * n + j] = cplx(tiny, 0.0);
+    for (int i = j + 1; i < n; ++i) {
+      const cplx f = M[(size_t)i * n + j] / p;
+      if (f == cplx(0.0, 0.0)) continue;
+      M[(size_t)i * n + j] = 0.0;
+      for (int t = j + 1; t < n; ++t) M[(size_t)i * n + t] -= f * M[(size_t)j * n + t];
+      b[i] -= f * b[j];
+    }
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    cplx s = b[i];
+    for (int t = i + 1; t < n; ++t) s -= M[(size_t)i * n + t] * x[t];
+    x[i] = s / M[(size_t)i * n + i];
+    if (!std::isfinite(x[i].real()) || !std::isfinite(x[i].imag())) return false;
+  }
+  return true;
+}
+
+static void hessenberg(std::vector<double>& H, int k) {
+  std::vector<double> v(k);
+  for (int j = 0; j < k - 2; ++j) {
+    double alpha = 0.0;
+    for (int i = j + 1; i < k; ++i) alpha += H[(size_t)i * k + j] * H[(size_t)i * k + j];
+    alpha = std::sqrt(alpha);
+    if (alpha == 0.0) continue;
+    const double x0 = H[(size_t)(j + 1) * k + j];
+    std::fill(v.begin(), v.end(), 0.0);
+    for (int i = j + 1; i < k; ++i) v[i] = H[(size_t)i * k + j];
+    v[j + 1] += sgn1(x0) * alpha;
+    double vv = 0.0;
+    for (int i = j + 1; i < k; ++i) vv += v[i] * v[i];
+    if (vv == 0.0) continue;
+    for (int c = 0; c < k; ++c) {  // left
+      double t = 0.0;
+      for (int i = j + 1; i < k; ++i) t += v[i] * H[(size_t)i * k + c];
+      const double f = 2.0 * t / vv;
+      for (int i = j + 1; i < k; ++i) H[(size_t)i * k + c] -= f * v[i];
+    }
+    for (int r = 0; r < k; ++r) {  // right
+      double t = 0.0;
+      for (int i = j + 1; i < k; ++i) t += H[(size_t)r * k + i] * v[i];
+      const double f = 2.0 * t / vv;
+      for (int i = j + 1; i < k; ++i) H[(size_t)r * k + i] -= f * v[i];
+    }
+    for (int i = j + 2; i < k; ++i) H[(size_t)i * k + j] = 0.0;
+  }
+}
+
+// Apply the reflector I - 2 v v^T / (v^T v) (v of length len at index kk) from the left
+// to columns [c0, c1] and from the right to rows [r0, r1] of H.
+static void reflect(std::vector<double>& H, int k, int kk, int len, const double* v, double vv,
+                    int c0, int c1, int r0, int r1) {
+  for (int c = c0; c <= c1; ++c) {
+    double t = 0.0;
+    for (int i = 0; i < len; ++i) t += v[i] * H[(size_t)(kk + i) * k + c];
+    const double f = 2.0 * t / vv;
+    for (int i = 0; i < len; ++i) H[(size_t)(kk + i) * k + c] -= f * v[i];
+  }
+  for (int r = r0; r <= r1; ++r) {
+    double t = 0.0;
+    for (int i = 0; i < len; ++i) t += H[(size_t)r * k + kk + i] * v[i];
+    const double f = 2.0 * t / vv;
+    for (int i = 0; i < len; ++i) H[(size_t)r * k + kk + i] -= f * v[i];
+  }
+}
+
+static bool francis_eigvals(std::vector<double>& H, int k, std::vector<cplx>& ev) {
+  const double eps = DBL_EPSILON;
+  auto at = [&](int i, int j) -> double& { return H[(size_t)i * k + j]; };
+  double hnorm = 0.0;
+  for (double x : H) hnorm = std::max(hnorm, std::fabs(x));
+  int hi = k - 1, its = 0;
+  long total = 0;
+  ev.clear();
+  while (hi >= 0) {
+    int l = hi;
+    while (l > 0) {
+      double s = std::fabs(at(l - 1, l - 1)) + std::fabs(at(l, l));
+      if (s == 0.0) s = hnorm;
+      if (std::fabs(at(l, l - 1)) <= eps * s) {
+        at(l, l - 1) = 0.0;
+        break;
+      }
+      --l;
+    }
+    if (l == hi) {
+      ev.push_back(cplx(at(hi, hi), 0.0));
+      --hi;
+      its = 0;
+      continue;
+    }
+    if (l == hi - 1) {
+      const double a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+      const double p = 0.5 * (a - d), q = p * p + b * c, mid = 0.5 * (a + d);
+      if (q >= 0.0) {
+        const double z = std::sqrt(q);
+        const double l1 = mid + sgn1(p) * z;
+        const double det = a * d - b * c;
+        const double l2 = (l1 != 0.0) ? det / l1 : mid - sgn1(p) * z;
+        ev.push_back(cplx(l1, 0.0));
+        ev.push_back(cplx(l2, 0.0));
+      } else {
+        const double im = std::sqrt(-q);
+        ev.push_back(cplx(mid, im));
+        ev.push_back(cplx(mid, -im));
+      }
+      hi -= 2;
+      its = 0;
+      continue;
+    }
+    if (++its > 60 || ++total > 60L * k) return false;
+    double s, t;
+    if (its == 10 || its == 20) {
+      const double wv = std::fabs(at(hi, hi - 1)) + std::fabs(at(hi - 1, hi - 2));
+      s = 1.5 * wv;
+      t = wv * wv;
+    } else {
+      s = at(hi - 1, hi - 1) + at(hi, hi);
+      t = at(hi - 1, hi - 1) * at(hi, hi) - at(hi - 1, hi) * at(hi, hi - 1);
+    }
+    double x = at(l, l) * at(l, l) + at(l, l + 1) * at(l + 1, l) - s * at(l, l) + t;
+    double y = at(l + 1, l) * (at(l, l) + at(l + 1, l + 1) - s);
+    double z = at(l + 1, l) * at(l + 2, l + 1);
+    for (int kk = l; kk <= hi - 2; ++kk) {
+      const double alpha = std::sqrt(x * x + y * y + z * z);
+      if (alpha != 0.0) {
+        double v[3] = {x + sgn1(x) * alpha, y, z};
+        const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
+        reflect(H, k, kk, 3, v, vv, std::max(l, kk - 1), hi, l, std::min(kk + 3, hi));
+        if (kk > l) {
+          at(kk + 1, kk - 1) = 0.0;
+          at(kk + 2, kk - 1) = 0.0;
+        }
+      }
+      x = at(kk + 1, kk);
+      y = at(kk + 2, kk);
+      z = (kk < hi - 2) ? at(kk + 3, kk) : 0.0;
+    }
+    {
+      const int kk = hi - 1;
+      const double alpha = std::hypot(x, y);
+      if (alpha != 0.0) {
+        double v[2] = {x + sgn1(x) * alpha, y};
+        const double vv = v[0] * v[0] + v[1] * v[1];
+        reflect(H, k, kk, 2, v, vv, std::max(l, kk - 1), hi, l, hi);
+        if (kk > l) at(kk + 1, kk - 1) = 0.0;
+      }
+    }
+  }
+  return (int)ev.size() == k;
+}
+
+bool eig_general(const double* A, int k, cplx* lam, cplx* W) {
+  if (k < 1) return false;
+  for (int i = 0; i < k * k; ++i)
+    if (!std::isfinite(A[i])) return false;
+  std::vector<double> H(A, A + (size_t)k * k);
+  std::vector<cplx> ev;
+  if (k == 1) {
+    ev.push_back(cplx(A[0], 0.0));
+  } else {
+    hessenberg(H, k);
+    if (!francis_eigvals(H, k, ev)) return false;
+  }
+  if (k == 1) {
+    lam[0] = ev[0];
+    W[0] = cplx(1.0, 0.0);
+    return true;
+  }
+  std::vector<cplx> M((size_t)k * k), b(k), y(k);
+  for (int j = 0; j < k; ++j) {
+    const cplx lj = ev[j];
+    lam[j] = lj;
+    cplx* wj = W + (size_t)j * k;
+    if (lj.imag() < 0.0 && j > 0 && ev[j - 1] == std::conj(lj)) {
+      for (int i = 0; i < k; ++i) wj[i] = std::conj(W[(size_t)(j - 1) * k + i]);
+      continue;
+    }
+    for (int r = 0; r < k; ++r)
+      for (int c = 0; c < k; ++c) M[(size_t)r * k + c] = cplx(A[(size_t)r * k + c], 0.0) - (r == c ? lj : 0.0);
+    for (int i = 0; i < k; ++i) b[i] = cplx(1.0, 0.0);
+    for (int it = 0; it < 3; ++it) {
+      if (!lu_solve(M.data(), k, b.data(), y.data())) return false;
+      double nr = 0.0;
+      for (int i = 0; i < k; ++i) nr += std::norm(y[i]);
+      nr = std::sqrt(nr);
+      if (!(nr > 0.0) || !std::isfinite(nr)) return false;
+      for (int i = 0; i < k; ++i) b[i] = y[i] / nr;
+    }
+    for (int i = 0; i < k; ++i) wj[i] = b[i];
+  }
+  return true;
+}
+
+// ---------------------------------------------------------------------------
+bool herm_pd_solve(const cplx* H, int ldh, int n, const cplx* c, cplx* x) {
+  std::vector<cplx> L((size_t)n * n, cplx(0.0, 0.0));
+  double dmax = 0.0;
+  for (int i = 0; i < n; ++i) dmax = std::max(dmax, H[(size_t)i * ldh + i].real());
+  if (!(dmax > 0.0)) return false;
+  for (int j = 0; j < n; ++j) {
+    double djj = H[(size_t)j * ldh + j].real();
+    for (int p = 0; p < j; ++p) djj -= std::norm(L[(size_t)j * n + p]);
+    if (!(djj > 1e-14 * dmax)) return false;
+    const double ljj = std::sqrt(djj);
+    L[(size_t)j * n + j] = ljj;
+    for (int i = j + 1; i < n; ++i) {
+      cplx s = H[(size_t)i * ldh + j];
+      for (int p = 0; p < j; ++p) s -= L[(size_t)i * n + p] * std::conj(L[(size_t)j * n + p]);
+      L[(size_t)i * n + j] = s / ljj;
+    }
+  }
+  std::vector<cplx> yv(n);
+  for (int i = 0; i < n; ++i) {
+    cplx s = c[i];
+    for (int p = 0; p < i; ++p) s -= L[(size_t)i * n + p] * yv[p];
+    yv[i] = s / L[(size_t)i * n + i].real();
+  }
+  for (int i = n - 1; i >= 0; --i) {
+    cplx s = yv[i];
+    for (int p = i + 1; p < n; ++p) s -= std::conj(L[(size_t)p * n + i]) * x[p];
+    x[i] = s / L[(size_t)i * n + i].real();
+  }
+  return true;
+}
+
+bool omp_gram(const cplx* H, int k, const cplx* c, double x1n2, int K, double tie_rel,
+              double stop_rel, std::vector<int>& S, std::vector<cplx>& beta, double* resid2) {
+  S.clear();
+  beta.clear();
+  std::vector<char> used(k, 0);
+  std::vector<cplx> Hs, cs;
+  double r2 = x1n2;
+  const int steps = std::min(K, k);
+  for (int it = 0; it < steps; ++it) {
+    // correlations alpha_j = c_j - sum_s H[j, S_s] beta_s, normalised by ||phi_j||
+    double best = -1.0;
+    std::vector<double> corr(k, -1.0);
+    for (int j = 0; j < k; ++j) {
+      if (used[j]) continue;
+      cplx a = c[j];
+      for (size_t s = 0; s < S.size(); ++s) a -= H[(size_t)j * k + S[s]] * beta[s];
+      const double hj = H[(size_t)j * k + j].real();
+      corr[j] = std::abs(a) / std::sqrt(std::max(hj, DBL_MIN));
+      best = std::max(best, corr[j]);
+    }
+    int pick = -1;
+    for (int j = 0; j < k; ++j)
+      if (!used[j] && corr[j] >= best - tie_rel * best) {
+        pick = j;
+        break;
+      }
+    if (pick < 0) break;
+    used[pick] = 1;
+    S.push_back(pick);
+    const int ns = (int)S.size();
+    Hs.assign((size_t)ns * ns, cplx(0.0, 0.0));
+    cs.assign(ns, cplx(0.0, 0.0));
+    for (int a = 0; a < ns; ++a) {
+      cs[a] = c[S[a]];
+      for (int b = 0; b < ns; ++b) Hs[(size_t)a * ns + b] = H[(size_t)S[a] * k + S[b]];
+    }
+    beta.assign(ns, cplx(0.0, 0.0));
+    if (!herm_pd_solve(Hs.data(), ns, ns, cs.data(), beta.data()))
+      if (!lu_solve(Hs.data(), ns, cs.data(), beta.data())) return false;
+    double proj = 0.0;
+    for (int a = 0; a < ns; ++a) proj += (std::conj(cs[a]) * beta[a]).real();
+    r2 = std::max(x1n2 - proj, 0.0);
+    if (r2 <= stop_rel * stop_rel * x1n2) break;
+  }
+  if (resid2) *resid2 = r2;
+  return true;
+}
+
+}  // namespace la
+}  // namespace cdmd

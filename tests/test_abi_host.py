@@ -1,0 +1,202 @@
+"""C ABI contract and host logic of libcdmd.so, on the CPU (no GPU needed).
+
+* the library loads and exports every function include/*.h declares;
+* argument validation returns the documented status before any device work;
+* the float64 host linear algebra of the fit (Lanczos top-k, general eigensolver,
+  coefficient-space OMP) agrees with LAPACK and with the oracle's explicit-residual
+  OMP.
+"""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+import torch
+
+import paper_1512_04205_amd as P
+import synthvideo as sv
+from oracle import cdmd_ref as R
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+DP = ctypes.POINTER(ctypes.c_double)
+IP = ctypes.POINTER(ctypes.c_int32)
+
+
+def _lib():
+    lib = P.load_library()
+    lib.cdmd_dbg_sym_topk.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, DP, DP, IP]
+    lib.cdmd_dbg_eig_general.argtypes = [DP, ctypes.c_int32, DP, DP]
+    lib.cdmd_dbg_omp_gram.argtypes = [DP, ctypes.c_int32, DP, ctypes.c_double, ctypes.c_int32, IP,
+                                      DP, IP, DP]
+    return lib
+
+
+def _p(a):
+    return a.ctypes.data_as(DP)
+
+
+def test_exports_every_declared_symbol():
+    lib = P.load_library()
+    names = set()
+    for h in os.listdir(os.path.join(ROOT, "include")):
+        txt = open(os.path.join(ROOT, "include", h)).read()
+        names |= set(re.findall(r"^\s*(?:cdmd_status|void|const char\*|int32_t)\s+(cdmd_\w+)\(", txt, re.M))
+    assert len(names) >= 14
+    for nm in sorted(names):
+        assert hasattr(lib, nm), nm
+
+
+def test_abi_version():
+    assert P.load_library().cdmd_abi_version() == 1
+
+
+def _cfg_kwargs(**kw):
+    idx, sign = sv.sparse_table(1000, 50, 8, 1)
+    base = dict(n=1000, m=20, k=5, p=50, idx=idx, sign=sign)
+    base.update(kw)
+    return base
+
+
+@pytest.mark.parametrize("kw,status", [
+    (dict(n=10), P.E_INVALID_ARG),                       # n < m
+    (dict(m=1), P.E_INVALID_ARG),                        # m < 2
+    (dict(k=25), P.E_INVALID_ARG),                       # k > m - 1
+    (dict(k=60, m=100), P.E_INVALID_ARG),                # p < k
+    (dict(ld=999), P.E_INVALID_ARG),                     # ld < n
+    (dict(dtype=7), P.E_INVALID_ARG),
+    (dict(sketch=9), P.E_INVALID_ARG),
+    (dict(lift_prec=P.PREC_FP8), P.E_INVALID_ARG),
+    (dict(idx=None), P.E_INVALID_ARG),
+    (dict(idx=np.full((50, 8), 1000, np.int32)), P.E_INVALID_ARG),     # out of range
+    (dict(idx=np.zeros((50, 8), np.int32)), P.E_INVALID_ARG),          # repeats in a row
+    (dict(sign=np.full((50, 8), 2, np.int8)), P.E_INVALID_ARG),
+    (dict(sketch=P.SKETCH_SPIXEL), P.E_INVALID_ARG),                  # nnz != 1
+    (dict(sketch=P.SKETCH_SPIXEL, idx=np.zeros((50, 1), np.int32),
+          sign=np.ones((50, 1), np.int8)), P.E_INVALID_ARG),           # repeated pixels
+    (dict(k=41, m=100, p=100, n=1000), P.E_UNSUPPORTED),
+])
+def test_validation_errors(kw, status):
+    with pytest.raises(P.CdmdError) as e:
+        P.Model(**_cfg_kwargs(**kw))
+    assert e.value.status == status
+    assert len(P.load_library().cdmd_last_error()) > 0
+
+
+@pytest.mark.skipif(torch.cuda.is_available(), reason="checks the no-device error path")
+def test_valid_config_without_device_reports_device_error():
+    with pytest.raises(P.CdmdError) as e:
+        P.Model(**_cfg_kwargs())
+    assert e.value.status == P.E_DEVICE
+
+
+def test_null_handles():
+    lib = P.load_library()
+    assert lib.cdmd_fit(None, None, None) == P.E_INVALID_ARG
+    assert lib.cdmd_select(None, 0, 1, 0.0, None, 0, None, None, None) == P.E_INVALID_ARG
+    assert lib.cdmd_create(None, None) == P.E_INVALID_ARG
+    lib.cdmd_free(None)
+
+
+# ------------------------------------------------------------------ host small LA
+@pytest.mark.parametrize("n,k", [(5, 2), (60, 10), (200, 25), (499, 25)])
+def test_lanczos_topk_vs_lapack(n, k):
+    lib = _lib()
+    rng = np.random.default_rng(n)
+    Y = rng.normal(size=(3 * n, n)) * np.logspace(0, -3, n)[None, :]
+    M = np.ascontiguousarray(Y.T @ Y)
+    ev, V, st = np.zeros(k), np.zeros(k * n), ctypes.c_int32(0)
+    assert lib.cdmd_dbg_sym_topk(_p(M), n, k, 1e-13, _p(ev), _p(V), ctypes.byref(st)) == 0
+    w, U = np.linalg.eigh(M)
+    w, U = w[::-1][:k], U[:, ::-1][:, :k]
+    np.testing.assert_allclose(ev, w, rtol=1e-12, atol=1e-13 * w[0])
+    V = V.reshape(k, n).T
+    for j in range(k):
+        assert min(np.linalg.norm(V[:, j] - U[:, j]), np.linalg.norm(V[:, j] + U[:, j])) < 1e-9
+
+
+def test_lanczos_low_rank_restart():
+    """Rank-r matrix with k > r + 1 forces a Krylov breakdown and a restart."""
+    lib = _lib()
+    rng = np.random.default_rng(3)
+    n, r, k = 50, 3, 6
+    A = rng.normal(size=(n, r))
+    M = np.ascontiguousarray(A @ A.T + 1e-3 * np.eye(n))
+    ev, V, st = np.zeros(k), np.zeros(k * n), ctypes.c_int32(0)
+    assert lib.cdmd_dbg_sym_topk(_p(M), n, k, 1e-13, _p(ev), _p(V), ctypes.byref(st)) == 0
+    np.testing.assert_allclose(ev, np.linalg.eigvalsh(M)[::-1][:k], rtol=1e-10)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 25, 40])
+def test_general_eig_vs_lapack(k):
+    lib = _lib()
+    rng = np.random.default_rng(k)
+    A = np.ascontiguousarray(rng.normal(size=(k, k)))
+    lam, W = np.zeros(2 * k), np.zeros(2 * k * k)
+    assert lib.cdmd_dbg_eig_general(_p(A), k, _p(lam), _p(W)) == 0
+    lam = lam[0::2] + 1j * lam[1::2]
+    W = (W[0::2] + 1j * W[1::2]).reshape(k, k).T
+    ref = np.linalg.eigvals(A)
+    from scipy.optimize import linear_sum_assignment
+    C = np.abs(lam[:, None] - ref[None, :])
+    r, c = linear_sum_assignment(C)
+    assert C[r, c].max() < 1e-12 * max(1, np.abs(ref).max())
+    assert np.linalg.norm(A @ W - W * lam[None, :], axis=0).max() < 1e-12
+    # complex eigenvalues of a real matrix come in exactly conjugate pairs
+    for j in range(k):
+        if lam[j].imag > 0:
+            assert np.any(lam == np.conj(lam[j]))
+
+
+def test_general_eig_rotation_block():
+    lib = _lib()
+    th = 0.3
+    A = np.ascontiguousarray(np.array([[np.cos(th), -np.sin(th), 0], [np.sin(th), np.cos(th), 0],
+                                       [0, 0, 0.5]]))
+    lam, W = np.zeros(6), np.zeros(18)
+    assert lib.cdmd_dbg_eig_general(_p(A), 3, _p(lam), _p(W)) == 0
+    got = np.sort_complex(lam[0::2] + 1j * lam[1::2])
+    np.testing.assert_allclose(got, np.sort_complex(np.array([0.5, np.exp(1j * th), np.exp(-1j * th)])),
+                               atol=1e-14)
+
+
+@pytest.mark.parametrize("seed,K", [(1, 1), (2, 4), (3, 8), (4, 30)])
+def test_coefficient_space_omp_equals_explicit_omp(seed, K):
+    """k-space OMP on (Phi^H Phi, Phi^H x_1) selects the same support and amplitudes as
+    the oracle's explicit-residual OMP on (Phi, x_1)."""
+    lib = _lib()
+    rng = np.random.default_rng(seed)
+    n, k = 400, 12
+    Phi = rng.normal(size=(n, k)) + 1j * rng.normal(size=(n, k))
+    Phi *= rng.uniform(0.2, 3, size=k)[None, :]
+    x1 = rng.normal(size=n)
+    H = np.ascontiguousarray(Phi.conj().T @ Phi)
+    c = np.ascontiguousarray(Phi.conj().T @ x1.astype(complex))
+    Hv = H.view(np.float64).ravel()
+    cv = c.view(np.float64).ravel()
+    S, beta, ns, r2 = np.zeros(k, np.int32), np.zeros(2 * k), ctypes.c_int32(0), ctypes.c_double(0)
+    assert lib.cdmd_dbg_omp_gram(_p(Hv), k, _p(cv), float(x1 @ x1), K, S.ctypes.data_as(IP), _p(beta),
+                                 ctypes.byref(ns), ctypes.byref(r2)) == 0
+    Sr, br = R.omp(Phi, x1, K)
+    assert list(S[:ns.value]) == list(Sr)
+    np.testing.assert_allclose(beta[0::2][:ns.value] + 1j * beta[1::2][:ns.value], br, rtol=1e-9, atol=1e-12)
+    res = x1 - Phi[:, Sr] @ br
+    assert abs(r2.value - np.vdot(res, res).real) <= 1e-9 * (x1 @ x1)
+
+
+def test_omp_conjugate_pair_tie_prefers_lower_index():
+    """For real x_1 and a conjugate pair of atoms the first correlations tie exactly;
+    the lower index wins on both sides."""
+    lib = _lib()
+    rng = np.random.default_rng(9)
+    n = 300
+    a = rng.normal(size=n) + 1j * rng.normal(size=n)
+    Phi = np.stack([a, np.conj(a), rng.normal(size=n) + 0j], axis=1)
+    x1 = (2 * a).real + 0.1 * rng.normal(size=n)
+    H = np.ascontiguousarray(Phi.conj().T @ Phi)
+    c = np.ascontiguousarray(Phi.conj().T @ x1.astype(complex))
+    S, beta, ns, r2 = np.zeros(3, np.int32), np.zeros(6), ctypes.c_int32(0), ctypes.c_double(0)
+    assert lib.cdmd_dbg_omp_gram(_p(H.view(np.float64).ravel()), 3, _p(c.view(np.float64).ravel()),
+                                 float(x1 @ x1), 1, S.ctypes.data_as(IP), _p(beta), ctypes.byref(ns),
+                                 ctypes.byref(r2)) == 0
+    assert S[0] == 0 and list(R.omp(Phi, x1, 1)[0]) == [0]
