@@ -1,7 +1,9 @@
 /*
- * cdmd_debug.h -- host-only entry points of libcdmd.so that expose the float64 small
- * linear algebra of the fit for testing without a GPU.  They run on the calling thread,
- * touch no device, and are not part of the hot path's public API.
+ * cdmd_debug.h -- test entry points of libcdmd.so.  The cdmd_dbg_* linear-algebra calls
+ * expose the float64 small linear algebra of the fit for testing without a GPU: they
+ * run on the calling thread and touch no device.  cdmd_dbg_force_valu_lift selects the
+ * float32 vector-ALU lift instead of the MFMA lift so tests can compare the two.  None
+ * of these is part of the hot path's public API.
  */
 #ifndef CDMD_DEBUG_H
 #define CDMD_DEBUG_H
@@ -34,6 +36,11 @@ cdmd_status cdmd_dbg_eig_general(const double* A, int32_t k, double* lam, double
 cdmd_status cdmd_dbg_omp_gram(const double* H, int32_t k, const double* c, double x1n2,
                               int32_t K, int32_t* S, double* beta, int32_t* ns,
                               double* resid2);
+
+/* Force (1) or release (0) the float32 vector-ALU lift for a uint8 video whose FP32
+   lift would otherwise run on MFMA (bf16 terms).  Takes effect at the next cdmd_fit.
+   Errors: INVALID_ARG. */
+cdmd_status cdmd_dbg_force_valu_lift(cdmd_model* mdl, int32_t on);
 
 #ifdef __cplusplus
 }

@@ -161,14 +161,22 @@ def normalise_eigvecs(W: np.ndarray) -> np.ndarray:
 
 
 def canonical_order(lam: np.ndarray, key: np.ndarray) -> np.ndarray:
-    """Descending key = |b_j| * ||phi_j||; adjacent keys equal to TIE_REL (conjugate
-    partners) are ordered with the positive-imaginary eigenvalue first."""
-    o = list(np.argsort(-key, kind="stable"))
-    for i in range(len(o) - 1):
-        a, c = o[i], o[i + 1]
-        if abs(key[a] - key[c]) <= TIE_REL * max(key[a], key[c]) and lam[a].imag < lam[c].imag:
-            o[i], o[i + 1] = c, a
-    return np.array(o, dtype=np.int64)
+    """Mode order: descending key = |b_j| * ||phi_j||.  The two members of a conjugate
+    pair (lambda_b equal to conj(lambda_a) to 1e-12) share one key, the larger of
+    their two, so they are always adjacent, and the member with Im lambda > 0 comes
+    first.  Remaining ties keep the eigensolver's order."""
+    k = len(lam)
+    pk = np.array(key, dtype=np.float64)
+    used = np.zeros(k, dtype=bool)
+    for a in range(k):
+        if lam[a].imag > 0 and not used[a]:
+            cand = [b for b in range(k) if lam[b].imag < 0 and not used[b]
+                    and abs(lam[b] - np.conj(lam[a])) <= 1e-12 * abs(lam[a])]
+            if cand:
+                b = min(cand, key=lambda q: abs(lam[q] - np.conj(lam[a])))
+                used[a] = used[b] = True
+                pk[a] = pk[b] = max(key[a], key[b])
+    return np.array(sorted(range(k), key=lambda j: (-pk[j], lam[j].imag <= 0, j)), dtype=np.int64)
 
 
 def reduced_operator(Yhat: np.ndarray, k: int):

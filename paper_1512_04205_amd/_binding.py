@@ -29,7 +29,7 @@ _STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY"
 EXPORTED = [
     "cdmd_abi_version", "cdmd_last_error", "cdmd_create", "cdmd_fit", "cdmd_modes",
     "cdmd_select", "cdmd_background", "cdmd_foreground", "cdmd_get_sketch",
-    "cdmd_info_get", "cdmd_set_timing", "cdmd_free",
+    "cdmd_info_get", "cdmd_set_timing", "cdmd_free", "cdmd_dbg_force_valu_lift",
 ]
 
 
@@ -93,6 +93,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_get_sketch.argtypes = [P, DP, ctypes.POINTER(I64)]
     lib.cdmd_info_get.argtypes = [P, ctypes.POINTER(Info)]
     lib.cdmd_set_timing.argtypes = [P, I32]
+    lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
     lib.cdmd_free.argtypes = [P]
     lib.cdmd_free.restype = None
     for name in EXPORTED:
@@ -238,6 +239,10 @@ class Model:
             self._h, _dptr(Y), Yi.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)) if integer else None))
         Y = Y.reshape(self.m, self.p).T.copy()
         return (Y, Yi.reshape(self.m, self.p).T.copy()) if integer else Y
+
+    def force_valu_lift(self, on: bool = True):
+        """Test hook: use the float32 vector-ALU lift instead of the MFMA lift."""
+        _check(load_library().cdmd_dbg_force_valu_lift(self._h, int(on)))
 
     def set_timing(self, enable: bool = True):
         _check(load_library().cdmd_set_timing(self._h, int(enable)))

@@ -84,6 +84,10 @@ struct cdmd_model {
   double* d_Yd = nullptr;
   double* d_gram = nullptr;
   // lift
+  bool lift_mfma = false;   // MFMA path (uint8 video, 16-byte aligned frames)
+  int lm_nb = 0, lm_nsplit = 0, lm_nksteps = 0, lm_grid = 0, lm_ne = 0;
+  uint16_t* h_Gp = nullptr;
+  void* d_Gp = nullptr;
   float* d_G = nullptr;
   uint32_t* d_pairs = nullptr;
   double* d_part = nullptr;
@@ -111,6 +115,7 @@ struct cdmd_model {
   cdmd_info info{};
   // kernel-group timing (HIP events on the call's stream)
   bool timing = false, recon_pending = false;
+  bool force_valu_lift = false;  // test hook: use the float32 VALU lift for uint8 video
   hipEvent_t ev[8] = {};
 
   void mark(int i, hipStream_t st) {
@@ -126,10 +131,10 @@ struct cdmd_model {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd,
-                   d_gram, d_G, d_pairs, d_part, d_red, d_Gs, d_Vc, d_counts};
+                   d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Vc, d_counts};
     for (void* q : dev)
       if (q) (void)hipFree(q);
-    void* host[] = {h_gram, h_G, h_red, h_Gs, h_Vc, h_counts};
+    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Vc, h_counts};
     for (void* q : host)
       if (q) (void)hipHostFree(q);
   }
@@ -185,8 +190,10 @@ cdmd_status validate(const cdmd_config* c) {
   if (c->n >= (int64_t)1 << 31) return fail(CDMD_E_UNSUPPORTED, "n >= 2^31 pixels is not built");
   if (c->sketch == CDMD_SKETCH_GAUSSIAN)
     return fail(CDMD_E_UNSUPPORTED, "dense Gaussian sketch is not built in this library version");
-  if (c->sketch_prec != CDMD_PREC_FP32 || c->lift_prec != CDMD_PREC_FP32)
-    return fail(CDMD_E_UNSUPPORTED, "only the FP32 forms are built in this library version");
+  if (c->sketch_prec != CDMD_PREC_FP32)
+    return fail(CDMD_E_UNSUPPORTED, "only the FP32 sketch form is built for sparse sketches");
+  if (c->lift_prec == CDMD_PREC_BF16 && (c->dtype != CDMD_U8 || c->ld % 16 != 0))
+    return fail(CDMD_E_UNSUPPORTED, "the BF16 lift needs a uint8 video with ld % 16 == 0");
   // table contents
   if (c->sketch != CDMD_SKETCH_GAUSSIAN) {
     const int64_t p = c->p, z = c->nnz;
@@ -302,19 +309,35 @@ void normalise_columns(std::vector<cplx>& W, int k) {
   }
 }
 
-// Canonical order: descending |b_j| ||phi_j||; adjacent keys equal to kTieRel are put
-// positive imaginary part first.
+// Canonical order: descending key |b_j| ||phi_j||; the members of a conjugate pair
+// (lambda_b = conj(lambda_a) to 1e-12) share the larger of their keys and the member
+// with Im lambda > 0 comes first; remaining ties keep the eigensolver's order.
 std::vector<int> canonical_order(const std::vector<cplx>& lam, const std::vector<double>& key) {
   const int k = (int)lam.size();
+  std::vector<double> pk(key);
+  std::vector<char> used(k, 0);
+  for (int a = 0; a < k; ++a) {
+    if (!(lam[a].imag() > 0.0) || used[a]) continue;
+    int best = -1;
+    double bd = 0.0;
+    for (int b = 0; b < k; ++b) {
+      if (!(lam[b].imag() < 0.0) || used[b]) continue;
+      const double d = std::abs(lam[b] - std::conj(lam[a]));
+      if (d <= 1e-12 * std::abs(lam[a]) && (best < 0 || d < bd)) best = b, bd = d;
+    }
+    if (best >= 0) {
+      used[a] = used[best] = 1;
+      pk[a] = pk[best] = std::max(key[a], key[best]);
+    }
+  }
   std::vector<int> o(k);
   std::iota(o.begin(), o.end(), 0);
-  std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return key[a] > key[b]; });
-  for (int i = 0; i + 1 < k; ++i) {
-    const int a = o[i], c = o[i + 1];
-    if (std::fabs(key[a] - key[c]) <= kTieRel * std::max(key[a], key[c]) &&
-        lam[a].imag() < lam[c].imag())
-      std::swap(o[i], o[i + 1]);
-  }
+  std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
+    if (pk[a] != pk[b]) return pk[a] > pk[b];
+    const bool pa = lam[a].imag() > 0.0, pb = lam[b].imag() > 0.0;
+    if (pa != pb) return pa;
+    return a < b;
+  });
   return o;
 }
 
@@ -405,9 +428,54 @@ cdmd_status small_la(cdmd_model* M, std::vector<double>& V, std::vector<double>&
   return CDMD_OK;
 }
 
-// Upload G (columns in `order`) to the device lift buffer, scaled to raw pixel units.
+// bfloat16 bits of a float64, round to nearest even (one rounding step)
+uint16_t bf16_bits(double x) {
+  if (x == 0.0) return std::signbit(x) ? 0x8000 : 0;
+  int e;
+  const double f = std::frexp(std::fabs(x), &e);  // |x| = f 2^e, f in [0.5, 1)
+  double q = std::ldexp(std::nearbyint(std::ldexp(f, 8)), e - 8);  // 8 significant bits
+  const float qf = (float)q;                       // exact
+  uint32_t u;
+  std::memcpy(&u, &qf, 4);
+  u >>= 16;
+  return (uint16_t)(u | (x < 0 ? 0x8000u : 0u));
+}
+double bf16_value(uint16_t b) {
+  const uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+// Upload G (columns in `order`) for the lift, scaled to raw pixel units.
 cdmd_status upload_G(cdmd_model* M, const std::vector<int>& order, hipStream_t st) {
   const int N = M->N, k = M->k, NC = M->NC;
+  if (M->lift_mfma) {
+    // B operands [kstep][nb][split][lane][8]: element i of lane l is G row
+    // 16 kstep + 8 (l / 32) + i, column 32 nb + l % 32, split term s.
+    const int NB = M->lm_nb, NS = M->lm_nsplit, KS = M->lm_nksteps;
+    for (int ks = 0; ks < KS; ++ks)
+      for (int nb = 0; nb < NB; ++nb)
+        for (int l = 0; l < 64; ++l) {
+          const int col = 32 * nb + (l & 31);
+          for (int i = 0; i < 8; ++i) {
+            const int row = 16 * ks + 8 * (l >> 5) + i;
+            double g = 0.0;
+            if (row < N && col < 2 * k) {
+              const cplx z = M->G[(size_t)row * k + order[col % k]] * (double)M->xscale;
+              g = col < k ? z.real() : z.imag();
+            }
+            double rem = g;
+            for (int sp = 0; sp < NS; ++sp) {
+              const uint16_t bits = bf16_bits(rem);
+              rem -= bf16_value(bits);
+              M->h_Gp[((((size_t)ks * NB + nb) * NS + sp) * 64 + l) * 8 + i] = bits;
+            }
+          }
+        }
+    HIPCHK(hipMemcpyAsync(M->d_Gp, M->h_Gp, (size_t)KS * NB * NS * 64 * 16, hipMemcpyHostToDevice, st));
+    return CDMD_OK;
+  }
   for (int t = 0; t < N; ++t) {
     float* row = M->h_G + (size_t)t * NC;
     for (int c = 0; c < NC; ++c) row[c] = 0.f;
@@ -421,13 +489,33 @@ cdmd_status upload_G(cdmd_model* M, const std::vector<int>& order, hipStream_t s
   return CDMD_OK;
 }
 
+cdmd_status launch_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
+  if (M->lift_mfma)
+    HIPCHK(cdmd::k::lift_mfma((const uint8_t*)d_video, M->ld, M->n, M->m, M->d_Gp, M->lm_nb,
+                              M->lm_nsplit, M->lm_nksteps, M->nc, M->xscale, M->d_part, M->lm_grid,
+                              d_phi, M->k, st));
+  else
+    HIPCHK(cdmd::k::lift_fp32(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_G, M->NC, M->nc,
+                              M->d_pairs, M->npair, M->d_part, M->lgrid, d_phi, M->k, M->xscale, st));
+  return CDMD_OK;
+}
+
 cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
+  M->lift_mfma = M->cfg.dtype == CDMD_U8 && M->ld % 16 == 0 &&
+                 (reinterpret_cast<uintptr_t>(d_video) & 15) == 0 &&
+                 (M->cfg.lift_prec == CDMD_PREC_BF16 || !M->force_valu_lift);
+  if (M->cfg.lift_prec == CDMD_PREC_BF16 && !M->lift_mfma)
+    return fail(CDMD_E_INVALID_ARG, "the BF16 lift needs a 16-byte aligned uint8 video");
+  std::vector<int> ident(M->k);
+  std::iota(ident.begin(), ident.end(), 0);
+  TRY(upload_G(M, ident, st));
   M->mark(3, st);
-  HIPCHK(cdmd::k::lift_fp32(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_G, M->NC, M->nc,
-                            M->d_pairs, M->npair, M->d_part, M->lgrid, d_phi, M->k, M->xscale, st));
-  HIPCHK(cdmd::k::reduce_partials(M->d_part, M->lgrid, M->ne, M->d_red, st));
+  TRY(launch_lift(M, d_video, d_phi, st));
+  const int grid = M->lift_mfma ? M->lm_grid : M->lgrid;
+  const int ne = M->lift_mfma ? M->lm_ne : M->ne;
+  HIPCHK(cdmd::k::reduce_partials(M->d_part, grid, ne, M->d_red, st));
   M->mark(4, st);
-  HIPCHK(hipMemcpyAsync(M->h_red, M->d_red, sizeof(double) * M->ne, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(M->h_red, M->d_red, sizeof(double) * ne, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (M->timing) M->info.gpu_ms_lift = M->span(3, 4);
   return CDMD_OK;
@@ -435,24 +523,44 @@ cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream
 
 // H = Phi^H Phi, c = Phi^H x_1 from the real partial Gram of [Re Phi | Im Phi].
 void assemble_H(cdmd_model* M, std::vector<cplx>& H, std::vector<cplx>& cvec) {
-  const int k = M->k, nc = M->nc;
-  std::vector<double> P((size_t)nc * nc);
-  int e = 0;
-  for (int a = 0; a < nc; ++a)
-    for (int b2 = a; b2 < nc; ++b2, ++e) {
-      P[(size_t)a * nc + b2] = M->h_red[e];
-      P[(size_t)b2 * nc + a] = M->h_red[e];
-    }
+  const int k = M->k, nc = M->nc, ne1 = nc + 1;
+  // P: (nc+1) x (nc+1) Gram of [Re Phi | Im Phi | x_1]
+  std::vector<double> P((size_t)ne1 * ne1, 0.0);
+  if (M->lift_mfma) {
+    const int NB = M->lm_nb;
+    int q = 0;
+    for (int a = 0; a < NB; ++a)
+      for (int b2 = a; b2 < NB; ++b2, ++q)
+        for (int j = 0; j < 16; ++j)
+          for (int l = 0; l < 64; ++l) {
+            const int r = 32 * a + 8 * (j >> 2) + 4 * (l >> 5) + (j & 3);
+            const int c = 32 * b2 + (l & 31);
+            if (r < ne1 && c < ne1) {
+              const double v = M->h_red[((size_t)q * 16 + j) * 64 + l];
+              P[(size_t)r * ne1 + c] = v;
+              P[(size_t)c * ne1 + r] = v;
+            }
+          }
+  } else {
+    int e = 0;
+    for (int a = 0; a < nc; ++a)
+      for (int b2 = a; b2 < nc; ++b2, ++e) {
+        P[(size_t)a * ne1 + b2] = M->h_red[e];
+        P[(size_t)b2 * ne1 + a] = M->h_red[e];
+      }
+    for (int a = 0; a < nc; ++a) P[(size_t)a * ne1 + nc] = P[(size_t)nc * ne1 + a] = M->h_red[M->npair + a];
+    P[(size_t)nc * ne1 + nc] = M->h_red[M->npair + nc];
+  }
   H.assign((size_t)k * k, 0.0);
   cvec.assign(k, 0.0);
   for (int j = 0; j < k; ++j)
     for (int l = 0; l < k; ++l) {
-      const double re = P[(size_t)j * nc + l] + P[(size_t)(k + j) * nc + (k + l)];
-      const double im = P[(size_t)j * nc + (k + l)] - P[(size_t)(k + j) * nc + l];
+      const double re = P[(size_t)j * ne1 + l] + P[(size_t)(k + j) * ne1 + (k + l)];
+      const double im = P[(size_t)j * ne1 + (k + l)] - P[(size_t)(k + j) * ne1 + l];
       H[(size_t)j * k + l] = cplx(re, im);
     }
-  for (int j = 0; j < k; ++j) cvec[j] = cplx(M->h_red[M->npair + j], -M->h_red[M->npair + k + j]);
-  M->x1n2 = M->h_red[M->npair + nc];
+  for (int j = 0; j < k; ++j) cvec[j] = cplx(P[(size_t)j * ne1 + nc], -P[(size_t)(k + j) * ne1 + nc]);
+  M->x1n2 = P[(size_t)nc * ne1 + nc];
 }
 
 }  // namespace
@@ -522,9 +630,22 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
   TRY(dalloc(&M->d_pairs, pairs.size()));
   HIPCHK(hipMemcpy(M->d_pairs, pairs.data(), pairs.size() * 4, hipMemcpyHostToDevice));
   M->lgrid = cdmd::k::lift_grid(M->n);
-  TRY(dalloc(&M->d_part, (size_t)M->lgrid * M->ne));
-  TRY(dalloc(&M->d_red, (size_t)M->ne));
-  TRY(halloc(&M->h_red, (size_t)M->ne));
+  size_t part_sz = (size_t)M->lgrid * M->ne, red_sz = (size_t)M->ne;
+  if (cfg->dtype == CDMD_U8) {
+    M->lm_nb = (M->nc + 1 + 31) / 32;
+    M->lm_nsplit = cfg->lift_prec == CDMD_PREC_BF16 ? 1 : 3;
+    M->lm_nksteps = (M->N + 15) / 16;
+    M->lm_grid = cdmd::k::lift_mfma_grid(M->n);
+    M->lm_ne = M->lm_nb * (M->lm_nb + 1) / 2 * 16 * 64;
+    const size_t gp = (size_t)M->lm_nksteps * M->lm_nb * M->lm_nsplit * 64 * 8;
+    TRY(dalloc((uint16_t**)&M->d_Gp, gp));
+    TRY(halloc(&M->h_Gp, gp));
+    part_sz = std::max(part_sz, (size_t)M->lm_grid * M->lm_ne);
+    red_sz = std::max(red_sz, (size_t)M->lm_ne);
+  }
+  TRY(dalloc(&M->d_part, part_sz));
+  TRY(dalloc(&M->d_red, red_sz));
+  TRY(halloc(&M->h_red, red_sz));
   TRY(dalloc(&M->d_Gs, (size_t)M->N * 80));
   TRY(halloc(&M->h_Gs, (size_t)M->N * 80));
   TRY(dalloc(&M->d_Vc, (size_t)m * 80));
@@ -550,9 +671,6 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
   std::vector<double> V, mu;
   TRY(small_la(M, V, mu));
   double t2 = now_ms();
-  std::vector<int> ident(M->k);
-  std::iota(ident.begin(), ident.end(), 0);
-  TRY(upload_G(M, ident, st));
   TRY(run_lift(M, d_video, nullptr, st));
   double t3 = now_ms();
   std::vector<cplx> H, cv;
@@ -620,9 +738,7 @@ cdmd_status cdmd_modes(const cdmd_model* Mc, double* lambda, double* b, double* 
     std::iota(ident.begin(), ident.end(), 0);
     TRY(upload_G(M, ident, st));  // M->G is in canonical order
     // the lift reduction buffers are reused; results of the fit are kept on the host
-    HIPCHK(cdmd::k::lift_fp32(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_G, M->NC, M->nc,
-                              M->d_pairs, M->npair, M->d_part, M->lgrid, (float*)d_phi, k,
-                              M->xscale, st));
+    TRY(launch_lift(M, d_video, (float*)d_phi, st));
     HIPCHK(hipStreamSynchronize(st));
   }
   return CDMD_OK;
@@ -862,6 +978,13 @@ cdmd_status cdmd_set_timing(cdmd_model* M, int32_t enable) {
 #include "cdmd_debug.h"
 
 extern "C" {
+
+cdmd_status cdmd_dbg_force_valu_lift(cdmd_model* M, int32_t on) {
+  g_err.clear();
+  if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  M->force_valu_lift = on != 0;
+  return CDMD_OK;
+}
 
 cdmd_status cdmd_dbg_sym_topk(const double* M, int32_t n, int32_t k, double rtol, double* evals,
                               double* evecs, int32_t* steps) {

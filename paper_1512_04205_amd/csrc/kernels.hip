@@ -330,6 +330,258 @@ hipError_t lift_fp32(const void* D, int dtype, int64_t ld, int64_t n, int64_t m,
                        kmodes, xscale, stream);
 }
 
+// ============================================================================
+// lift on MFMA (uint8 video): Phi = X' G with X' exact in bf16 and G given as NSPLIT
+// bf16 terms (1: bf16 lift; 3: 24-bit G, float32-accurate products), float32
+// accumulation.  Block = 4 waves, tile = 256 pixels, wave w owns pixels 64w..64w+63
+// as two 32-row MFMA blocks x NB 32-column blocks.  Frames stream through LDS in
+// chunks of 32 ([frame][pixel] bytes); each lane gathers its 8 frames of one pixel.
+// The fused reduction P = Phi_ext^T Phi_ext (Phi_ext = [Phi | x_1 in column nc]) is
+// computed from the accumulator registers themselves: a lane holds 16 pixel rows of
+// one column, and the same register order is used for both operands, so the pixel
+// order inside a K block is a consistent permutation.  P uses hi/lo bf16 splits
+// (hi*hi + hi*lo + lo*hi), float32 accumulation over the block's pixels.
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ uint32_t pack_u8pair_bf16(uint32_t lo8, uint32_t hi8) {
+  // integers 0..255 are exact in bf16: the high half of their float32 encoding
+  const uint32_t a = __float_as_uint((float)lo8) >> 16;
+  const uint32_t b = __float_as_uint((float)hi8) & 0xffff0000u;
+  return a | b;
+}
+
+__device__ __forceinline__ uint32_t bf16_rne_bits(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// split 8 float32 values into hi and lo bf16 vectors
+__device__ __forceinline__ void split8(const float* v, bf16x8_t& hi, bf16x8_t& lo) {
+  uint32_t h[4], q[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const uint32_t h0 = bf16_rne_bits(v[2 * i]), h1 = bf16_rne_bits(v[2 * i + 1]);
+    const float r0 = v[2 * i] - __uint_as_float(h0 << 16);
+    const float r1 = v[2 * i + 1] - __uint_as_float(h1 << 16);
+    h[i] = h0 | (h1 << 16);
+    q[i] = bf16_rne_bits(r0) | (bf16_rne_bits(r1) << 16);
+  }
+  hi = __builtin_bit_cast(bf16x8_t, make_uint4(h[0], h[1], h[2], h[3]));
+  lo = __builtin_bit_cast(bf16x8_t, make_uint4(q[0], q[1], q[2], q[3]));
+}
+
+constexpr int LM_TILE = 256;
+constexpr int LM_CH = 32;        // frames per LDS chunk
+constexpr int LM_SA = 264;       // LDS row stride (bytes) of a frame row
+
+template <int NB, int NSPLIT>
+__global__ __launch_bounds__(256) void k_lift_mfma(
+    const uint8_t* __restrict__ D, int64_t ld, int64_t n, int64_t m, const uint4* __restrict__ Gp,
+    int nksteps, int nc, float xscale, double* __restrict__ part, float* __restrict__ phi,
+    int kmodes) {
+  constexpr int NP = NB * (NB + 1) / 2;
+  constexpr int BCH = 2 * NB * NSPLIT * 64;  // uint4 B operands per chunk
+  constexpr int RED_BYTES = 4 * NP * 16 * 64 * 4;
+  constexpr int MAIN_BYTES = LM_CH * LM_SA + BCH * 16;
+  constexpr int LDS_BYTES = RED_BYTES > MAIN_BYTES ? RED_BYTES : MAIN_BYTES;
+  __shared__ __align__(16) uint8_t lds[LDS_BYTES];
+  uint8_t(*sA)[LM_SA] = reinterpret_cast<uint8_t(*)[LM_SA]>(lds);
+  uint4* sB = reinterpret_cast<uint4*>(lds + LM_CH * LM_SA);
+
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int64_t N = m - 1;                 // K extent (frames 1..m-1)
+  const int nchunks = (nksteps + 1) / 2;
+  const int64_t ntiles = (n + LM_TILE - 1) / LM_TILE;
+  // A load mapping: frame row fr = tid / 8, pixel segment (tid % 8) * 32 .. + 31
+  const int fr = tid >> 3, seg = (tid & 7) * 32;
+
+  f32x16_t P[NP];
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) P[q][j] = 0.f;
+
+  for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int64_t base = tile * LM_TILE;
+    f32x16_t acc[2][NB];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
+
+    uint4 ra0, ra1;
+    uint4 rb[(BCH + 255) / 256];
+    auto gload = [&](int c) {
+      const int64_t f = 1 + (int64_t)c * LM_CH + fr;      // video frame of this row
+      const int64_t px = base + seg;
+      if (f <= N && px + 32 <= n) {
+        const uint4* src = reinterpret_cast<const uint4*>(D + f * ld + px);
+        ra0 = src[0];
+        ra1 = src[1];
+      } else {
+        uint32_t wds[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          uint32_t v = 0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int64_t pp = px + q * 4 + b;
+            if (f <= N && pp < n) v |= (uint32_t)D[f * ld + pp] << (8 * b);
+          }
+          wds[q] = v;
+        }
+        ra0 = make_uint4(wds[0], wds[1], wds[2], wds[3]);
+        ra1 = make_uint4(wds[4], wds[5], wds[6], wds[7]);
+      }
+#pragma unroll
+      for (int q = 0; q < (BCH + 255) / 256; ++q) {
+        const int e = tid + q * 256;
+        if (e < BCH) {
+          const int ks = 2 * c + e / (NB * NSPLIT * 64);
+          rb[q] = ks < nksteps ? Gp[(int64_t)2 * c * NB * NSPLIT * 64 + e] : make_uint4(0, 0, 0, 0);
+        }
+      }
+    };
+    gload(0);
+    for (int c = 0; c < nchunks; ++c) {
+      __syncthreads();
+      {  // rows are 8-byte aligned (stride 264): four 8-byte stores
+        uint2* dst = reinterpret_cast<uint2*>(&sA[fr][seg]);
+        dst[0] = make_uint2(ra0.x, ra0.y);
+        dst[1] = make_uint2(ra0.z, ra0.w);
+        dst[2] = make_uint2(ra1.x, ra1.y);
+        dst[3] = make_uint2(ra1.z, ra1.w);
+      }
+#pragma unroll
+      for (int q = 0; q < (BCH + 255) / 256; ++q) {
+        const int e = tid + q * 256;
+        if (e < BCH) sB[e] = rb[q];
+      }
+      __syncthreads();
+      if (c + 1 < nchunks) gload(c + 1);
+#pragma unroll
+      for (int ks = 0; ks < 2; ++ks) {
+        bf16x8_t a[2];
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+          const int pxl = 64 * w + 32 * mb + (l & 31);
+          const int k0 = 16 * ks + 8 * (l >> 5);
+          uint32_t wv[4];
+#pragma unroll
+          for (int i = 0; i < 4; ++i)
+            wv[i] = pack_u8pair_bf16(sA[k0 + 2 * i][pxl], sA[k0 + 2 * i + 1][pxl]);
+          a[mb] = __builtin_bit_cast(bf16x8_t, make_uint4(wv[0], wv[1], wv[2], wv[3]));
+        }
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+          for (int s = 0; s < NSPLIT; ++s) {
+            const bf16x8_t b = __builtin_bit_cast(bf16x8_t, sB[((ks * NB + nb) * NSPLIT + s) * 64 + l]);
+#pragma unroll
+            for (int mb = 0; mb < 2; ++mb)
+              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mb], b, acc[mb][nb], 0, 0, 0);
+          }
+      }
+    }
+    // x_1 (scaled) into column nc of Phi_ext
+    if ((l & 31) == (nc & 31)) {
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+          const int64_t px = base + 64 * w + 32 * mb + (j >> 2) * 8 + (l >> 5) * 4 + (j & 3);
+          const float x1 = px < n ? (float)D[px] * xscale : 0.f;
+#pragma unroll
+          for (int nb = 0; nb < NB; ++nb)
+            if (nb == (nc >> 5)) acc[mb][nb][j] = x1;
+        }
+    }
+    if (phi != nullptr) {
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int col = 32 * nb + (l & 31);
+          if (col < 2 * kmodes) {
+            const int mode = col < kmodes ? col : col - kmodes;
+            const int part_im = col < kmodes ? 0 : 1;
+#pragma unroll
+            for (int j = 0; j < 16; ++j) {
+              const int64_t px = base + 64 * w + 32 * mb + (j >> 2) * 8 + (l >> 5) * 4 + (j & 3);
+              if (px < n) phi[2 * ((int64_t)mode * n + px) + part_im] = acc[mb][nb][j];
+            }
+          }
+        }
+    }
+    // P += Phi_ext^T Phi_ext over this wave's 64 pixels
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        bf16x8_t hi[NB], lo[NB];
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          float v[8];
+#pragma unroll
+          for (int i = 0; i < 8; ++i) v[i] = acc[mb][nb][8 * h + i];
+          split8(v, hi[nb], lo[nb]);
+        }
+        int q = 0;
+#pragma unroll
+        for (int a = 0; a < NB; ++a)
+#pragma unroll
+          for (int b = a; b < NB; ++b, ++q) {
+            P[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[a], hi[b], P[q], 0, 0, 0);
+            P[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[a], lo[b], P[q], 0, 0, 0);
+            P[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[a], hi[b], P[q], 0, 0, 0);
+          }
+      }
+  }
+  // reduce the four waves' P in LDS, write the block partial (float64)
+  __syncthreads();
+  float* red = reinterpret_cast<float*>(lds);
+#pragma unroll
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) red[((w * NP + q) * 16 + j) * 64 + l] = P[q][j];
+  __syncthreads();
+  constexpr int NE = NP * 16 * 64;
+  for (int e = tid; e < NE; e += 256) {
+    double s = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < 4; ++ww) s += (double)red[ww * NE + e];
+    part[(int64_t)blockIdx.x * NE + e] = s;
+  }
+}
+
+int lift_mfma_grid(int64_t n) {
+  const int64_t tiles = (n + LM_TILE - 1) / LM_TILE;
+  return (int)(tiles < 512 ? tiles : 512);
+}
+
+hipError_t lift_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const void* Gp, int nb,
+                     int nsplit, int nksteps, int nc, float xscale, double* part, int grid,
+                     float* phi, int kmodes, hipStream_t s) {
+#define LM_CASE(NBV, NSV)                                                                    \
+  if (nb == NBV && nsplit == NSV) {                                                          \
+    hipLaunchKernelGGL((k_lift_mfma<NBV, NSV>), dim3(grid), dim3(256), 0, s, D, ld, n, m,    \
+                       (const uint4*)Gp, nksteps, nc, xscale, part, phi, kmodes);            \
+    return hipGetLastError();                                                                \
+  }
+  LM_CASE(1, 1)
+  LM_CASE(1, 3)
+  LM_CASE(2, 1)
+  LM_CASE(2, 3)
+  LM_CASE(3, 1)
+  LM_CASE(3, 3)
+#undef LM_CASE
+  return hipErrorInvalidValue;
+}
+
 __global__ void k_reduce_partials(const double* __restrict__ part, int grid, int ne,
                                   double* __restrict__ out) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;

@@ -44,6 +44,16 @@ hipError_t lift_fp32(const void* D, int dtype, int64_t ld, int64_t n, int64_t m,
                      int NC, int nc, const uint32_t* pairs, int npair, double* part,
                      int grid, float* phi, int kmodes, float xscale, hipStream_t stream);
 int lift_grid(int64_t n);
+// ----- lift on MFMA (uint8 video, 16-byte aligned frames) -------------------------
+// Gp: B operands pre-arranged as [kstep][nb][split][lane][8 bf16] (kstep = 16 frames of
+// X', nb = 32-column block, split = bf16 term of G), nksteps = ceil((m-1)/16).
+// Column nc of Phi_ext is replaced by x_1 * xscale.  part: [grid][NP*16*64] float64,
+// NP = nb(nb+1)/2 column-block pairs (a <= b); entry (q, j, lane) of pair q = (a, b) is
+// P[32a + 8(j/4) + 4(lane/32) + j%4][32b + lane%32].  nb in {1,2,3}, nsplit in {1,3}.
+hipError_t lift_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const void* Gp, int nb,
+                     int nsplit, int nksteps, int nc, float xscale, double* part, int grid,
+                     float* phi, int kmodes, hipStream_t stream);
+int lift_mfma_grid(int64_t n);
 // out[e] = sum_b part[b][e]
 hipError_t reduce_partials(const double* part, int grid, int ne, double* out,
                            hipStream_t stream);

@@ -252,3 +252,67 @@ def test_error_paths_on_device():
     with pytest.raises(P.CdmdError) as e:
         mdl.foreground(Dg, torch.zeros((10, 13), dtype=torch.int32, device="cuda"), 0.1)
     assert e.value.status == P.E_STATE
+
+
+# ------------------------------------------------------------------ MFMA lift
+@pytest.mark.parametrize("shape", [(40, 52, 45), (72, 100, 60), (30, 64, 130)])
+def test_mfma_lift_matches_valu_lift_and_oracle(shape):
+    """uint8 video: the MFMA lift (3 bf16 terms of G) and the float32 VALU lift give the
+    same amplitudes, Phi and OMP support as the oracle (ragged pixel tiles and frame
+    chunks included)."""
+    H, W, m = shape
+    _say("mfma lift", shape)
+    v = _small_u8(H=H, W=W, m=m, seed=61)
+    D = v.D.numpy()
+    n = D.shape[1]
+    k, p = 10, 300
+    idx, sign = sv.sparse_table(n, p, 32, 7)
+    Dg = torch.from_numpy(D).cuda()
+    ref = R.run(D, v.scale, k, sketch="sparse", idx=idx, sign=sign, K=6)
+    bphi_r = ref.model.Phi * ref.model.b[None, :]
+    out = {}
+    for path in ("mfma", "valu"):
+        mdl = P.Model(n, m, k, p, idx=idx, sign=sign)
+        if path == "valu":
+            mdl.force_valu_lift(True)
+        mdl.fit(Dg)
+        phi = torch.zeros((k, n), dtype=torch.complex64, device="cuda")
+        md = mdl.modes(video=Dg, phi=phi)
+        S, _ = mdl.select(P.SEL_OMP, K=6)
+        bphi = phi.cpu().numpy().T.astype(np.complex128) * md["b"][None, :]
+        out[path] = (md, S, bphi)
+        rel, _, _ = eig_rel_err(md["lam"], ref.model.lam)
+        assert rel.max() <= 1e-6
+        err = np.abs(bphi - bphi_r).max() / np.abs(bphi_r).max()
+        assert err < 2e-5, (path, err)
+        assert list(S) == list(ref.support), (path, S, ref.support)
+    np.testing.assert_allclose(np.abs(out["mfma"][0]["b"]) * out["mfma"][0]["phi_norm"],
+                               np.abs(out["valu"][0]["b"]) * out["valu"][0]["phi_norm"], rtol=2e-5)
+
+
+def test_bf16_lift_form():
+    """BF16 lift (G rounded to bfloat16, MFMA, float32 accumulation): eigenvalues are
+    those of the exact sketch; amplitudes and masks agree with the FP64 oracle to the
+    stated bf16 bounds."""
+    _say("bf16 lift")
+    v = _small_u8(H=64, W=96, m=80, seed=71)
+    D = v.D.numpy()
+    n, m = D.shape[1], D.shape[0]
+    k, p, K, tau = 12, 400, 8, 0.1
+    idx, sign = sv.sparse_table(n, p, 32, 9)
+    Dg = torch.from_numpy(D).cuda()
+    mdl = P.Model(n, m, k, p, idx=idx, sign=sign, lift_prec=P.PREC_BF16)
+    mdl.fit(Dg)
+    ref = R.run(D, v.scale, k, sketch="sparse", idx=idx, sign=sign, K=K)
+    md = mdl.modes()
+    rel, _, _ = eig_rel_err(md["lam"], ref.model.lam)
+    assert rel.max() <= 1e-3
+    key_r = np.abs(ref.model.b) * ref.model.phi_norm
+    np.testing.assert_allclose(np.abs(md["b"]) * md["phi_norm"], key_r, rtol=2e-2, atol=2e-2 * key_r.max())
+    mdl.select(P.SEL_EXPLICIT, explicit=ref.support)
+    mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    mdl.foreground(Dg, mk, tau)
+    mg = P.unpack_mask(mk.cpu().numpy().view(np.uint32), n)
+    Lr = R.background(ref.model.Phi[:, ref.support], ref.beta, ref.model.lam[ref.support], 0, m)
+    mr = R.foreground(D.T.astype(np.float64) / 255, Lr, tau).T
+    assert (mg == mr).mean() >= 0.999

@@ -335,9 +335,13 @@ def test_zero_mode_selector_static_video():
 # ------------------------------------------------------------------ canonical order
 def test_canonical_order_pairs_positive_imag_first():
     lam = np.array([0.9 - 0.1j, 1.0, 0.9 + 0.1j, 0.5])
-    key = np.array([2.0, 3.0, 2.0 * (1 + 1e-12), 1.0])
-    o = R.canonical_order(lam, key)
-    assert list(o) == [1, 2, 0, 3]
+    # conjugate members share the larger key even when their keys differ
+    key = np.array([2.0, 3.0, 2.0 * (1 - 1e-6), 1.0])
+    assert list(R.canonical_order(lam, key)) == [1, 2, 0, 3]
+    # a mode whose key falls between the two members does not split the pair
+    lam2 = np.array([0.9 - 0.1j, 0.7 + 0j, 0.9 + 0.1j])
+    key2 = np.array([2.0, 1.9, 1.8])
+    assert list(R.canonical_order(lam2, key2)) == [2, 0, 1]
 
 
 def test_eigvec_normalisation():
