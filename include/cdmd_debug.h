@@ -37,6 +37,15 @@ cdmd_status cdmd_dbg_omp_gram(const double* H, int32_t k, const double* c, doubl
                               int32_t K, int32_t* S, double* beta, int32_t* ns,
                               double* resid2);
 
+/* The device small linear algebra (Algorithm 1 steps 4, 6, 7 and G = V S^-1 W from the
+   m x m Gram Gr of the unscaled sketch), run by one host thread with the same code the
+   GPU runs per workgroup.  Outputs: mu[k] Gram eigenvalues (descending), sigma[k],
+   lam[2k] (re, im), W[2k*k] (column j at 2*j*k, re/im interleaved), G[2(m-1)k] (row t
+   at 2*t*k), *steps Krylov dimension.  Returns OK, RANK_DEFICIENT or NUMERIC. */
+cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, double rtol,
+                                   double sketch_scale, double* mu, double* sigma, double* lam,
+                                   double* W, double* G, int32_t* steps);
+
 /* Force (1) or release (0) the float32 vector-ALU lift for a uint8 video whose FP32
    lift would otherwise run on MFMA (bf16 terms).  Takes effect at the next cdmd_fit.
    Errors: INVALID_ARG. */

@@ -41,8 +41,10 @@ from . import philox
 # rank test: sigma_k <= RANK_TOL * sigma_1 is rank deficient (the paper sets no
 # tolerance; 1e-6 is what a Gram-based route can still resolve in float64)
 RANK_TOL = 1e-6
-# ties in OMP correlations and in the canonical order, relative
-TIE_REL = 1e-9
+# ties in OMP correlations, relative: after a complete conjugate pair is selected the
+# residual of a real x_1 is real, so the two members of the next pair tie exactly;
+# 1e-6 keeps that tie visible through float32 rounding of Phi
+TIE_REL = 1e-6
 # OMP stops early when ||r|| <= OMP_STOP_REL * ||x_1||
 OMP_STOP_REL = 1e-12
 # |lambda|^(m-1) above this overflows the Vandermonde matrix

@@ -32,6 +32,7 @@ SOURCES = [
     ("kernels.hip", DEVICE),
     ("api.cpp", HOST),
     ("smallla.cpp", HOST),
+    ("team_la_host.cpp", HOST),
 ]
 
 

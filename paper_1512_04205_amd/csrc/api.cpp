@@ -16,6 +16,7 @@
 
 #include "kernels.hpp"
 #include "smallla.hpp"
+#include "team_la_host.hpp"
 
 using cplx = std::complex<double>;
 
@@ -38,7 +39,7 @@ cdmd_status fail(cdmd_status s, const std::string& msg) {
 
 // rank test on the Gram eigenvalues: sigma_k <= 1e-6 sigma_1  <=>  mu_k <= 1e-12 mu_1
 constexpr double kRankTol2 = 1e-12;
-constexpr double kTieRel = 1e-9;
+constexpr double kTieRel = 1e-6;  // OMP correlation ties (relative)
 constexpr double kOmpStopRel = 1e-12;
 constexpr double kVanderMax = 1e30;
 constexpr double kLanczosTol = 1e-13;
@@ -94,6 +95,9 @@ struct cdmd_model {
   double* d_red = nullptr;
   int lgrid = 0;
   // reconstruction
+  void* d_Gsp = nullptr;     // MFMA B operands of [Re G~_S | Im G~_S]
+  uint16_t* h_Gsp = nullptr;
+  bool recon_mfma = false;
   float* d_Gs = nullptr;
   float* d_Vc = nullptr;
   int64_t* d_counts = nullptr;
@@ -131,10 +135,10 @@ struct cdmd_model {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd,
-                   d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Vc, d_counts};
+                   d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts};
     for (void* q : dev)
       if (q) (void)hipFree(q);
-    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Vc, h_counts};
+    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gsp, h_Vc, h_counts};
     for (void* q : host)
       if (q) (void)hipHostFree(q);
   }
@@ -640,6 +644,9 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
     const size_t gp = (size_t)M->lm_nksteps * M->lm_nb * M->lm_nsplit * 64 * 8;
     TRY(dalloc((uint16_t**)&M->d_Gp, gp));
     TRY(halloc(&M->h_Gp, gp));
+    const size_t gsp = (size_t)M->lm_nksteps * M->lm_nsplit * 64 * 8;
+    TRY(dalloc((uint16_t**)&M->d_Gsp, gsp));
+    TRY(halloc(&M->h_Gsp, gsp));
     part_sz = std::max(part_sz, (size_t)M->lm_grid * M->lm_ne);
     red_sz = std::max(red_sz, (size_t)M->lm_ne);
   }
@@ -841,7 +848,31 @@ cdmd_status prepare_recon(cdmd_model* M, int static_bg, int* NSout, hipStream_t 
   if (NS < 0) return fail(CDMD_E_UNSUPPORTED, "more than 40 selected modes");
   const int N = M->N, k = M->k;
   const int64_t m = M->m;
-  for (int t = 0; t < N; ++t) {
+  M->recon_mfma = M->lift_mfma && 2 * ns <= 32;
+  if (M->recon_mfma) {
+    const int NSP = M->lm_nsplit, KS = M->lm_nksteps;
+    for (int ks = 0; ks < KS; ++ks)
+      for (int l = 0; l < 64; ++l) {
+        const int col = l & 31;
+        for (int i = 0; i < 8; ++i) {
+          const int row = 16 * ks + 8 * (l >> 5) + i;
+          double g = 0.0;
+          if (row < N && col < 2 * ns) {
+            const int sidx = col < ns ? col : col - ns;
+            const cplx z = M->G[(size_t)row * k + M->S[sidx]] * M->beta[sidx] * (double)M->xscale;
+            g = col < ns ? z.real() : z.imag();
+          }
+          double rem = g;
+          for (int sp = 0; sp < NSP; ++sp) {
+            const uint16_t bits = bf16_bits(rem);
+            rem -= bf16_value(bits);
+            M->h_Gsp[(((size_t)ks * NSP + sp) * 64 + l) * 8 + i] = bits;
+          }
+        }
+      }
+    HIPCHK(hipMemcpyAsync(M->d_Gsp, M->h_Gsp, (size_t)KS * NSP * 64 * 16, hipMemcpyHostToDevice, st));
+  }
+  for (int t = 0; t < N && !M->recon_mfma; ++t) {
     float* row = M->h_Gs + (size_t)t * NS;
     for (int c = 0; c < NS; ++c) row[c] = 0.f;
     for (int s = 0; s < ns; ++s) {
@@ -890,8 +921,12 @@ cdmd_status cdmd_background(const cdmd_model* Mc, const void* d_video, int64_t t
   int NS = 0;
   TRY(prepare_recon(M, static_bg, &NS, st));
   M->mark(5, st);
-  HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, 0.f,
-                       M->xscale, 2, d_L, t0, t1, ldL, st));
+  if (M->recon_mfma)
+    HIPCHK(cdmd::k::bgfg_mfma((const uint8_t*)d_video, M->ld, M->n, M->m, M->d_Gsp, M->lm_nsplit,
+                              M->lm_nksteps, NS, M->d_Vc, 0.f, M->xscale, 2, d_L, t0, t1, ldL, st));
+  else
+    HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, 0.f,
+                         M->xscale, 2, d_L, t0, t1, ldL, st));
   M->mark(6, st);
   M->recon_pending = M->timing;
   return CDMD_OK;
@@ -910,8 +945,13 @@ cdmd_status cdmd_foreground(const cdmd_model* Mc, const void* d_video, float tau
   int NS = 0;
   TRY(prepare_recon(M, static_bg, &NS, st));
   M->mark(5, st);
-  HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, tau,
-                       M->xscale, bitpacked ? 0 : 1, d_mask, 0, M->m, 0, st));
+  if (M->recon_mfma)
+    HIPCHK(cdmd::k::bgfg_mfma((const uint8_t*)d_video, M->ld, M->n, M->m, M->d_Gsp, M->lm_nsplit,
+                              M->lm_nksteps, NS, M->d_Vc, tau, M->xscale, bitpacked ? 0 : 1, d_mask,
+                              0, M->m, 0, st));
+  else
+    HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, tau,
+                         M->xscale, bitpacked ? 0 : 1, d_mask, 0, M->m, 0, st));
   M->mark(6, st);
   M->recon_pending = M->timing;
   if (h_counts) {
@@ -978,6 +1018,20 @@ cdmd_status cdmd_set_timing(cdmd_model* M, int32_t enable) {
 #include "cdmd_debug.h"
 
 extern "C" {
+
+cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, double rtol,
+                                   double sketch_scale, double* mu, double* sigma, double* lam,
+                                   double* W, double* G, int32_t* steps) {
+  g_err.clear();
+  if (!Gr || !mu || !sigma || !lam || !W || !G || m < 2 || k < 1 || k > m - 1)
+    return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  int J = 0;
+  const int st = cdmd::team_small_la_host(Gr, m, k, rtol, std::min(m - 1, 320), sketch_scale, mu,
+                                          sigma, lam, W, G, &J);
+  if (steps) *steps = J;
+  if (st != 0) return fail((cdmd_status)st, "team small LA failed");
+  return CDMD_OK;
+}
 
 cdmd_status cdmd_dbg_force_valu_lift(cdmd_model* M, int32_t on) {
   g_err.clear();

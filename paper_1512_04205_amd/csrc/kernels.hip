@@ -339,8 +339,9 @@ hipError_t lift_fp32(const void* D, int dtype, int64_t ld, int64_t n, int64_t m,
 // The fused reduction P = Phi_ext^T Phi_ext (Phi_ext = [Phi | x_1 in column nc]) is
 // computed from the accumulator registers themselves: a lane holds 16 pixel rows of
 // one column, and the same register order is used for both operands, so the pixel
-// order inside a K block is a consistent permutation.  P uses hi/lo bf16 splits
-// (hi*hi + hi*lo + lo*hi), float32 accumulation over the block's pixels.
+// order inside a K block is a consistent permutation.  P uses hi/lo bf16 splits and all
+// four products (dropping lo*lo would bias the diagonal by ~2^-18), float32 accumulation
+// over the block's pixels; what remains is the zero-mean rounding of the split.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
@@ -376,27 +377,119 @@ constexpr int LM_TILE = 256;
 constexpr int LM_CH = 32;        // frames per LDS chunk
 constexpr int LM_SA = 264;       // LDS row stride (bytes) of a frame row
 
+// X' G on MFMA for one 256-pixel tile: acc[mb][nb] (wave w, rows 64w + 32mb + ...)
+// Frames 1..m-1 stream through `lds` ([LM_CH][LM_SA] bytes, then the B operands of one
+// chunk).  The caller synchronises before reusing `lds`.
+template <int NB, int NSPLIT>
+__device__ __forceinline__ void xprime_g_tile(const uint8_t* __restrict__ D, int64_t ld, int64_t n,
+                                              int64_t m, const uint4* __restrict__ Gp, int nksteps,
+                                              int64_t base, uint8_t* lds, f32x16_t (&acc)[2][NB]) {
+  constexpr int BCH = 2 * NB * NSPLIT * 64;  // uint4 B operands per chunk
+  uint8_t(*sA)[LM_SA] = reinterpret_cast<uint8_t(*)[LM_SA]>(lds);
+  uint4* sB = reinterpret_cast<uint4*>(lds + LM_CH * LM_SA);
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int64_t N = m - 1;
+  const int nchunks = (nksteps + 1) / 2;
+  const int fr = tid >> 3, seg = (tid & 7) * 32;
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
+  uint4 ra0, ra1;
+  uint4 rb[(BCH + 255) / 256];
+  auto gload = [&](int c) {
+    const int64_t f = 1 + (int64_t)c * LM_CH + fr;
+    const int64_t px = base + seg;
+    if (f <= N && px + 32 <= n) {
+      const uint4* src = reinterpret_cast<const uint4*>(D + f * ld + px);
+      ra0 = src[0];
+      ra1 = src[1];
+    } else {
+      uint32_t wds[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          const int64_t pp = px + q * 4 + b;
+          if (f <= N && pp < n) v |= (uint32_t)D[f * ld + pp] << (8 * b);
+        }
+        wds[q] = v;
+      }
+      ra0 = make_uint4(wds[0], wds[1], wds[2], wds[3]);
+      ra1 = make_uint4(wds[4], wds[5], wds[6], wds[7]);
+    }
+#pragma unroll
+    for (int q = 0; q < (BCH + 255) / 256; ++q) {
+      const int e = tid + q * 256;
+      if (e < BCH) {
+        const int ks = 2 * c + e / (NB * NSPLIT * 64);
+        rb[q] = ks < nksteps ? Gp[(int64_t)2 * c * NB * NSPLIT * 64 + e] : make_uint4(0, 0, 0, 0);
+      }
+    }
+  };
+  gload(0);
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();
+    {  // rows are 8-byte aligned (stride 264): four 8-byte stores
+      uint2* dst = reinterpret_cast<uint2*>(&sA[fr][seg]);
+      dst[0] = make_uint2(ra0.x, ra0.y);
+      dst[1] = make_uint2(ra0.z, ra0.w);
+      dst[2] = make_uint2(ra1.x, ra1.y);
+      dst[3] = make_uint2(ra1.z, ra1.w);
+    }
+#pragma unroll
+    for (int q = 0; q < (BCH + 255) / 256; ++q) {
+      const int e = tid + q * 256;
+      if (e < BCH) sB[e] = rb[q];
+    }
+    __syncthreads();
+    if (c + 1 < nchunks) gload(c + 1);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf16x8_t a[2];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const int pxl = 64 * w + 32 * mb + (l & 31);
+        const int k0 = 16 * ks + 8 * (l >> 5);
+        uint32_t wv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+          wv[i] = pack_u8pair_bf16(sA[k0 + 2 * i][pxl], sA[k0 + 2 * i + 1][pxl]);
+        a[mb] = __builtin_bit_cast(bf16x8_t, make_uint4(wv[0], wv[1], wv[2], wv[3]));
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+        for (int s = 0; s < NSPLIT; ++s) {
+          const bf16x8_t b = __builtin_bit_cast(bf16x8_t, sB[((ks * NB + nb) * NSPLIT + s) * 64 + l]);
+#pragma unroll
+          for (int mb = 0; mb < 2; ++mb)
+            acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mb], b, acc[mb][nb], 0, 0, 0);
+        }
+    }
+  }
+}
+
+template <int NB, int NSPLIT>
+constexpr int xg_lds_bytes() {
+  return LM_CH * LM_SA + 2 * NB * NSPLIT * 64 * 16;
+}
+
 template <int NB, int NSPLIT>
 __global__ __launch_bounds__(256) void k_lift_mfma(
     const uint8_t* __restrict__ D, int64_t ld, int64_t n, int64_t m, const uint4* __restrict__ Gp,
     int nksteps, int nc, float xscale, double* __restrict__ part, float* __restrict__ phi,
     int kmodes) {
   constexpr int NP = NB * (NB + 1) / 2;
-  constexpr int BCH = 2 * NB * NSPLIT * 64;  // uint4 B operands per chunk
   constexpr int RED_BYTES = 4 * NP * 16 * 64 * 4;
-  constexpr int MAIN_BYTES = LM_CH * LM_SA + BCH * 16;
+  constexpr int MAIN_BYTES = xg_lds_bytes<NB, NSPLIT>();
   constexpr int LDS_BYTES = RED_BYTES > MAIN_BYTES ? RED_BYTES : MAIN_BYTES;
   __shared__ __align__(16) uint8_t lds[LDS_BYTES];
-  uint8_t(*sA)[LM_SA] = reinterpret_cast<uint8_t(*)[LM_SA]>(lds);
-  uint4* sB = reinterpret_cast<uint4*>(lds + LM_CH * LM_SA);
-
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int64_t N = m - 1;                 // K extent (frames 1..m-1)
-  const int nchunks = (nksteps + 1) / 2;
   const int64_t ntiles = (n + LM_TILE - 1) / LM_TILE;
-  // A load mapping: frame row fr = tid / 8, pixel segment (tid % 8) * 32 .. + 31
-  const int fr = tid >> 3, seg = (tid & 7) * 32;
-
   f32x16_t P[NP];
 #pragma unroll
   for (int q = 0; q < NP; ++q)
@@ -406,87 +499,7 @@ __global__ __launch_bounds__(256) void k_lift_mfma(
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t base = tile * LM_TILE;
     f32x16_t acc[2][NB];
-#pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
-
-    uint4 ra0, ra1;
-    uint4 rb[(BCH + 255) / 256];
-    auto gload = [&](int c) {
-      const int64_t f = 1 + (int64_t)c * LM_CH + fr;      // video frame of this row
-      const int64_t px = base + seg;
-      if (f <= N && px + 32 <= n) {
-        const uint4* src = reinterpret_cast<const uint4*>(D + f * ld + px);
-        ra0 = src[0];
-        ra1 = src[1];
-      } else {
-        uint32_t wds[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          uint32_t v = 0;
-#pragma unroll
-          for (int b = 0; b < 4; ++b) {
-            const int64_t pp = px + q * 4 + b;
-            if (f <= N && pp < n) v |= (uint32_t)D[f * ld + pp] << (8 * b);
-          }
-          wds[q] = v;
-        }
-        ra0 = make_uint4(wds[0], wds[1], wds[2], wds[3]);
-        ra1 = make_uint4(wds[4], wds[5], wds[6], wds[7]);
-      }
-#pragma unroll
-      for (int q = 0; q < (BCH + 255) / 256; ++q) {
-        const int e = tid + q * 256;
-        if (e < BCH) {
-          const int ks = 2 * c + e / (NB * NSPLIT * 64);
-          rb[q] = ks < nksteps ? Gp[(int64_t)2 * c * NB * NSPLIT * 64 + e] : make_uint4(0, 0, 0, 0);
-        }
-      }
-    };
-    gload(0);
-    for (int c = 0; c < nchunks; ++c) {
-      __syncthreads();
-      {  // rows are 8-byte aligned (stride 264): four 8-byte stores
-        uint2* dst = reinterpret_cast<uint2*>(&sA[fr][seg]);
-        dst[0] = make_uint2(ra0.x, ra0.y);
-        dst[1] = make_uint2(ra0.z, ra0.w);
-        dst[2] = make_uint2(ra1.x, ra1.y);
-        dst[3] = make_uint2(ra1.z, ra1.w);
-      }
-#pragma unroll
-      for (int q = 0; q < (BCH + 255) / 256; ++q) {
-        const int e = tid + q * 256;
-        if (e < BCH) sB[e] = rb[q];
-      }
-      __syncthreads();
-      if (c + 1 < nchunks) gload(c + 1);
-#pragma unroll
-      for (int ks = 0; ks < 2; ++ks) {
-        bf16x8_t a[2];
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) {
-          const int pxl = 64 * w + 32 * mb + (l & 31);
-          const int k0 = 16 * ks + 8 * (l >> 5);
-          uint32_t wv[4];
-#pragma unroll
-          for (int i = 0; i < 4; ++i)
-            wv[i] = pack_u8pair_bf16(sA[k0 + 2 * i][pxl], sA[k0 + 2 * i + 1][pxl]);
-          a[mb] = __builtin_bit_cast(bf16x8_t, make_uint4(wv[0], wv[1], wv[2], wv[3]));
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-          for (int s = 0; s < NSPLIT; ++s) {
-            const bf16x8_t b = __builtin_bit_cast(bf16x8_t, sB[((ks * NB + nb) * NSPLIT + s) * 64 + l]);
-#pragma unroll
-            for (int mb = 0; mb < 2; ++mb)
-              acc[mb][nb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[mb], b, acc[mb][nb], 0, 0, 0);
-          }
-      }
-    }
+    xprime_g_tile<NB, NSPLIT>(D, ld, n, m, Gp, nksteps, base, lds, acc);
     // x_1 (scaled) into column nc of Phi_ext
     if ((l & 31) == (nc & 31)) {
 #pragma unroll
@@ -538,6 +551,7 @@ __global__ __launch_bounds__(256) void k_lift_mfma(
             P[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[a], hi[b], P[q], 0, 0, 0);
             P[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(hi[a], lo[b], P[q], 0, 0, 0);
             P[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[a], hi[b], P[q], 0, 0, 0);
+            P[q] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(lo[a], lo[b], P[q], 0, 0, 0);
           }
       }
   }
@@ -556,6 +570,90 @@ __global__ __launch_bounds__(256) void k_lift_mfma(
     for (int ww = 0; ww < 4; ++ww) s += (double)red[ww * NE + e];
     part[(int64_t)blockIdx.x * NE + e] = s;
   }
+}
+
+// Fused background + foreground with phase 1 on MFMA: T = X' Gs for one 256-pixel
+// tile (Gs: [Re G~_S | Im G~_S] as NSPLIT bf16 terms, 32 columns), T moved through LDS
+// to one pixel per thread, then per frame L = sum_c T_c Vc[t][c] and the threshold as
+// in k_bgfg.
+template <int NSPLIT, int NSV>
+__global__ __launch_bounds__(256) void k_bgfg_mfma(const uint8_t* __restrict__ D, int64_t ld,
+                                                  int64_t n, int64_t m, const uint4* __restrict__ Gp,
+                                                  int nksteps, const float* __restrict__ Vc,
+                                                  float tau, float xscale, int mode,
+                                                  void* __restrict__ out, int64_t t0, int64_t t1,
+                                                  int64_t ldL) {
+  constexpr int MAIN_BYTES = xg_lds_bytes<1, NSPLIT>();
+  constexpr int T_BYTES = 256 * 33 * 4;
+  constexpr int LDS_BYTES = T_BYTES > MAIN_BYTES ? T_BYTES : MAIN_BYTES;
+  __shared__ __align__(16) uint8_t lds[LDS_BYTES];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int64_t base = (int64_t)blockIdx.x * LM_TILE;
+  f32x16_t acc[2][1];
+  xprime_g_tile<1, NSPLIT>(D, ld, n, m, Gp, nksteps, base, lds, acc);
+  __syncthreads();
+  float* sT = reinterpret_cast<float*>(lds);
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      sT[(64 * w + 32 * mb + (j >> 2) * 8 + (l >> 5) * 4 + (j & 3)) * 33 + (l & 31)] = acc[mb][0][j];
+  __syncthreads();
+  float T[NSV];
+#pragma unroll
+  for (int c = 0; c < NSV; ++c) T[c] = sT[tid * 33 + c];
+  const int64_t i = base + tid;
+  const bool valid = i < n;
+  const uint8_t* Dp = D + (valid ? i : 0);
+  const int64_t i0 = i - l;
+  const int64_t words = (n + 31) >> 5;
+  constexpr int PF = 8;  // frames in flight per thread
+  for (int64_t tb = t0; tb < t1; tb += PF) {
+    float xs[PF];
+#pragma unroll
+    for (int u = 0; u < PF; ++u)
+      xs[u] = (valid && mode != 2 && tb + u < t1) ? (float)Dp[(tb + u) * ld] * xscale : 0.f;
+#pragma unroll
+    for (int u = 0; u < PF; ++u) {
+      const int64_t tt = tb + u;
+      if (tt >= t1) break;
+      const float* v = Vc + tt * NSV;
+      float L = 0.f;
+#pragma unroll
+      for (int c = 0; c < NSV; ++c) L = fmaf(T[c], v[c], L);
+      if (mode == 2) {
+        if (valid) reinterpret_cast<float*>(out)[(tt - t0) * ldL + i] = L;
+        continue;
+      }
+      const bool fg = valid && (fabsf(xs[u] - L) > tau);
+      if (mode == 1) {
+        if (valid) reinterpret_cast<uint8_t*>(out)[tt * n + i] = fg ? 1 : 0;
+      } else {
+        const uint64_t bal = __ballot(fg);
+        if (l == 0 && i0 < n) {
+          uint32_t* wd = reinterpret_cast<uint32_t*>(out) + tt * words + (i0 >> 5);
+          wd[0] = (uint32_t)bal;
+          if ((i0 >> 5) + 1 < words) wd[1] = (uint32_t)(bal >> 32);
+        }
+      }
+    }
+  }
+}
+
+hipError_t bgfg_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const void* Gp, int nsplit,
+                     int nksteps, int NS, const float* Vc, float tau, float xscale, int mode,
+                     void* out, int64_t t0, int64_t t1, int64_t ldL, hipStream_t s) {
+  const dim3 grid((unsigned)((n + LM_TILE - 1) / LM_TILE));
+#define BM_CASE(NSP, NSV)                                                                     \
+  if (nsplit == NSP && NS == NSV) {                                                           \
+    hipLaunchKernelGGL((k_bgfg_mfma<NSP, NSV>), grid, dim3(256), 0, s, D, ld, n, m,           \
+                       (const uint4*)Gp, nksteps, Vc, tau, xscale, mode, out, t0, t1, ldL);   \
+    return hipGetLastError();                                                                 \
+  }
+  BM_CASE(1, 4) BM_CASE(1, 8) BM_CASE(1, 12) BM_CASE(1, 16) BM_CASE(1, 20) BM_CASE(1, 24) BM_CASE(1, 32)
+  BM_CASE(3, 4) BM_CASE(3, 8) BM_CASE(3, 12) BM_CASE(3, 16) BM_CASE(3, 20) BM_CASE(3, 24) BM_CASE(3, 32)
+#undef BM_CASE
+  return hipErrorInvalidValue;
 }
 
 int lift_mfma_grid(int64_t n) {
@@ -582,18 +680,28 @@ hipError_t lift_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const v
   return hipErrorInvalidValue;
 }
 
-__global__ void k_reduce_partials(const double* __restrict__ part, int grid, int ne,
-                                  double* __restrict__ out) {
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= ne) return;
+// Deterministic column sums of part[grid][ne]: block = 16 entries x 16 row groups; row
+// group g sums blocks b = g, g+16, ... in order, then the 16 group sums are added in
+// order.
+__global__ __launch_bounds__(256) void k_reduce_partials(const double* __restrict__ part, int grid,
+                                                         int ne, double* __restrict__ out) {
+  __shared__ double red[16][17];
+  const int e = blockIdx.x * 16 + (threadIdx.x & 15), g = threadIdx.x >> 4;
   double s = 0.0;
-  for (int b = 0; b < grid; ++b) s += part[(int64_t)b * ne + e];
-  out[e] = s;
+  if (e < ne)
+    for (int b = g; b < grid; b += 16) s += part[(int64_t)b * ne + e];
+  red[g][threadIdx.x & 15] = s;
+  __syncthreads();
+  if (threadIdx.x < 16 && blockIdx.x * 16 + threadIdx.x < ne) {
+    double t = 0.0;
+    for (int q = 0; q < 16; ++q) t += red[q][threadIdx.x];
+    out[blockIdx.x * 16 + threadIdx.x] = t;
+  }
 }
 
 hipError_t reduce_partials(const double* part, int grid, int ne, double* out,
                            hipStream_t stream) {
-  hipLaunchKernelGGL(k_reduce_partials, dim3((ne + 127) / 128), dim3(128), 0, stream, part, grid,
+  hipLaunchKernelGGL(k_reduce_partials, dim3((ne + 15) / 16), dim3(256), 0, stream, part, grid,
                      ne, out);
   return hipGetLastError();
 }

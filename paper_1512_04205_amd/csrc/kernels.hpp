@@ -67,6 +67,12 @@ hipError_t reduce_partials(const double* part, int grid, int ne, double* out,
 hipError_t bgfg(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, const float* Gs,
                 int NS, const float* Vc, float tau, float xscale, int mode, void* out,
                 int64_t t0, int64_t t1, int64_t ldL, hipStream_t stream);
+// Same, phase 1 on MFMA (uint8 video, 16-byte aligned frames): Gp holds the B operands
+// of [Re G~_S | Im G~_S] as in lift_mfma with one 32-column block (|S| <= 16); NS is the
+// padded 2|S| of Vc (4, 8, 12, 16, 20, 24 or 32); nsplit in {1, 3}.
+hipError_t bgfg_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const void* Gp, int nsplit,
+                     int nksteps, int NS, const float* Vc, float tau, float xscale, int mode,
+                     void* out, int64_t t0, int64_t t1, int64_t ldL, hipStream_t stream);
 // counts[t] = number of set bits of frame t of a bit-packed mask
 hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* counts,
                        hipStream_t stream);
