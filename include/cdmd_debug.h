@@ -46,6 +46,16 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
                                    double sketch_scale, double* mu, double* sigma, double* lam,
                                    double* W, double* G, int32_t* steps);
 
+/* Phase times (ms) of the last device small-LA solve: [0] Lanczos incl. convergence
+   checks, [1] of which Jacobi checks, [2] A~, [3] eigenvalues of A~, [4] eigenvectors,
+   [5] G, [6] lift operand write, [7] unused.  Errors: INVALID_ARG. */
+cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms8);
+
+/* Force (1) or release (0) the float64 small linear algebra on the host instead of the
+   device workgroup solve (which runs for 16-byte aligned uint8 videos with m <= 1025).
+   Takes effect at the next cdmd_fit.  Errors: INVALID_ARG. */
+cdmd_status cdmd_dbg_force_host_la(cdmd_model* mdl, int32_t on);
+
 /* Force (1) or release (0) the float32 vector-ALU lift for a uint8 video whose FP32
    lift would otherwise run on MFMA (bf16 terms).  Takes effect at the next cdmd_fit.
    Errors: INVALID_ARG. */

@@ -30,6 +30,7 @@ EXPORTED = [
     "cdmd_abi_version", "cdmd_last_error", "cdmd_create", "cdmd_fit", "cdmd_modes",
     "cdmd_select", "cdmd_background", "cdmd_foreground", "cdmd_get_sketch",
     "cdmd_info_get", "cdmd_set_timing", "cdmd_free", "cdmd_dbg_force_valu_lift",
+    "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases",
 ]
 
 
@@ -94,6 +95,8 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_info_get.argtypes = [P, ctypes.POINTER(Info)]
     lib.cdmd_set_timing.argtypes = [P, I32]
     lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
+    lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
+    lib.cdmd_dbg_la_phases.argtypes = [P, DP]
     lib.cdmd_free.argtypes = [P]
     lib.cdmd_free.restype = None
     for name in EXPORTED:
@@ -243,6 +246,16 @@ class Model:
     def force_valu_lift(self, on: bool = True):
         """Test hook: use the float32 vector-ALU lift instead of the MFMA lift."""
         _check(load_library().cdmd_dbg_force_valu_lift(self._h, int(on)))
+
+    def force_host_la(self, on: bool = True):
+        """Test hook: float64 small linear algebra on the host instead of the device."""
+        _check(load_library().cdmd_dbg_force_host_la(self._h, int(on)))
+
+    def la_phases(self) -> dict:
+        """Phase times (ms) of the last device small-LA solve."""
+        v = np.zeros(8)
+        _check(load_library().cdmd_dbg_la_phases(self._h, _dptr(v)))
+        return dict(zip(["lanczos", "jacobi", "atilde", "eigvals", "eigvecs", "G", "operands"], v[:7]))
 
     def set_timing(self, enable: bool = True):
         _check(load_library().cdmd_set_timing(self._h, int(enable)))

@@ -16,6 +16,7 @@
 
 #include "kernels.hpp"
 #include "smallla.hpp"
+#include "team_la.hpp"
 #include "team_la_host.hpp"
 
 using cplx = std::complex<double>;
@@ -120,6 +121,16 @@ struct cdmd_model {
   // kernel-group timing (HIP events on the call's stream)
   bool timing = false, recon_pending = false;
   bool force_valu_lift = false;  // test hook: use the float32 VALU lift for uint8 video
+  bool force_host_la = false;    // test hook: float64 small LA on the host
+  double la_phase_ms[8] = {};
+  // device small LA (one workgroup)
+  bool device_la_ok = false;     // sized at create
+  bool device_la = false;        // used by the last fit
+  int la_jmax = 0;
+  double* d_la_scratch = nullptr;
+  double* d_la_out = nullptr;
+  double* h_la_out = nullptr;
+  int64_t la_out_n = 0;
   hipEvent_t ev[8] = {};
 
   void mark(int i, hipStream_t st) {
@@ -135,10 +146,11 @@ struct cdmd_model {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
     void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd,
-                   d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts};
+                   d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts,
+                   d_la_scratch, d_la_out};
     for (void* q : dev)
       if (q) (void)hipFree(q);
-    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gsp, h_Vc, h_counts};
+    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gsp, h_Vc, h_counts, h_la_out};
     for (void* q : host)
       if (q) (void)hipHostFree(q);
   }
@@ -348,7 +360,7 @@ std::vector<int> canonical_order(const std::vector<cplx>& lam, const std::vector
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Sketch + Gram + D2H of the Gram.
-cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st) {
+cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool to_host) {
   const cdmd_config& c = M->cfg;
   M->mark(0, st);
   if (c.dtype == CDMD_U8) {
@@ -366,6 +378,7 @@ cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st) {
     HIPCHK(cdmd::k::gram_f64(M->d_Yd, M->p, M->m, M->d_gram, st));
   }
   M->mark(2, st);
+  if (!to_host) return CDMD_OK;
   HIPCHK(hipMemcpyAsync(M->h_gram, M->d_gram, sizeof(double) * M->m * M->m, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (M->timing) {
@@ -451,6 +464,38 @@ double bf16_value(uint16_t b) {
   return (double)f;
 }
 
+// Read the device small-LA output block into the model (after the stream sync).
+cdmd_status take_device_la(cdmd_model* M) {
+  const int k = M->k, N = M->N;
+  const double* o = M->h_la_out;
+  const cdmd::tla::SmallLAOutLayout L = cdmd::tla::small_la_out_layout(N, k);
+  const int st = (int)o[L.status];
+  M->info.lanczos_steps = (int)o[L.J];
+  if (st == CDMD_E_RANK_DEFICIENT)
+    return fail(CDMD_E_RANK_DEFICIENT, "sigma_k <= 1e-6 sigma_1: target rank exceeds the numerical rank of Y");
+  if (st != 0) return fail(CDMD_E_NUMERIC, "device small linear algebra failed (non-finite Gram or no convergence)");
+  M->sigma.assign(o + L.sigma, o + L.sigma + k);
+  M->info.sigma_ratio = M->sigma[k - 1] / M->sigma[0];
+  M->lam.resize(k);
+  M->W.resize((size_t)k * k);
+  M->G.resize((size_t)N * k);
+  for (int j = 0; j < k; ++j) M->lam[j] = cplx(o[L.lam + 2 * j], o[L.lam + 2 * j + 1]);
+  for (int64_t e = 0; e < (int64_t)k * k; ++e) M->W[e] = cplx(o[L.W + 2 * e], o[L.W + 2 * e + 1]);
+  for (int64_t e = 0; e < (int64_t)N * k; ++e) M->G[e] = cplx(o[L.G + 2 * e], o[L.G + 2 * e + 1]);
+  // phase times in ms (wall clock at 100 MHz): lanczos incl. checks, of which Jacobi,
+  // A~, eigenvalues, eigenvectors, G, operand write
+  const double* tt = o + L.timing;
+  const double f = 1e-5;
+  M->la_phase_ms[0] = (tt[3] - tt[2]) * f;
+  M->la_phase_ms[1] = tt[0] * f;
+  M->la_phase_ms[2] = (tt[4] - tt[3]) * f;
+  M->la_phase_ms[3] = (tt[5] - tt[4]) * f;
+  M->la_phase_ms[4] = (tt[6] - tt[5]) * f;
+  M->la_phase_ms[5] = (tt[7] - tt[6]) * f;
+  M->la_phase_ms[6] = (tt[9] - tt[8]) * f;
+  return CDMD_OK;
+}
+
 // Upload G (columns in `order`) for the lift, scaled to raw pixel units.
 cdmd_status upload_G(cdmd_model* M, const std::vector<int>& order, hipStream_t st) {
   const int N = M->N, k = M->k, NC = M->NC;
@@ -505,14 +550,13 @@ cdmd_status launch_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStr
 }
 
 cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
-  M->lift_mfma = M->cfg.dtype == CDMD_U8 && M->ld % 16 == 0 &&
-                 (reinterpret_cast<uintptr_t>(d_video) & 15) == 0 &&
-                 (M->cfg.lift_prec == CDMD_PREC_BF16 || !M->force_valu_lift);
   if (M->cfg.lift_prec == CDMD_PREC_BF16 && !M->lift_mfma)
     return fail(CDMD_E_INVALID_ARG, "the BF16 lift needs a 16-byte aligned uint8 video");
-  std::vector<int> ident(M->k);
-  std::iota(ident.begin(), ident.end(), 0);
-  TRY(upload_G(M, ident, st));
+  if (!M->device_la) {
+    std::vector<int> ident(M->k);
+    std::iota(ident.begin(), ident.end(), 0);
+    TRY(upload_G(M, ident, st));
+  }
   M->mark(3, st);
   TRY(launch_lift(M, d_video, d_phi, st));
   const int grid = M->lift_mfma ? M->lm_grid : M->lgrid;
@@ -520,8 +564,17 @@ cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream
   HIPCHK(cdmd::k::reduce_partials(M->d_part, grid, ne, M->d_red, st));
   M->mark(4, st);
   HIPCHK(hipMemcpyAsync(M->h_red, M->d_red, sizeof(double) * ne, hipMemcpyDeviceToHost, st));
+  if (M->device_la)
+    HIPCHK(hipMemcpyAsync(M->h_la_out, M->d_la_out, sizeof(double) * M->la_out_n, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  if (M->timing) M->info.gpu_ms_lift = M->span(3, 4);
+  if (M->timing) {
+    M->info.gpu_ms_lift = M->span(3, 4);
+    if (M->device_la) {
+      M->info.gpu_ms_sketch = M->span(0, 1);
+      M->info.gpu_ms_gram = M->span(1, 2);
+      M->info.ms_small_la = M->span(2, 3);
+    }
+  }
   return CDMD_OK;
 }
 
@@ -647,6 +700,14 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
     const size_t gsp = (size_t)M->lm_nksteps * M->lm_nsplit * 64 * 8;
     TRY(dalloc((uint16_t**)&M->d_Gsp, gsp));
     TRY(halloc(&M->h_Gsp, gsp));
+    if (M->N <= 1024 && cfg->ld % 16 == 0) {
+      M->la_jmax = std::min(M->N, 320);
+      TRY(dalloc(&M->d_la_scratch, (size_t)cdmd::k::small_la_scratch_doubles((int)M->m, M->k, M->la_jmax)));
+      M->la_out_n = cdmd::k::small_la_out_doubles((int)M->m, M->k);
+      TRY(dalloc(&M->d_la_out, (size_t)M->la_out_n));
+      TRY(halloc(&M->h_la_out, (size_t)M->la_out_n));
+      M->device_la_ok = true;
+    }
     part_sz = std::max(part_sz, (size_t)M->lm_grid * M->lm_ne);
     red_sz = std::max(red_sz, (size_t)M->lm_ne);
   }
@@ -672,13 +733,26 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
   hipStream_t st = as_stream(stream);
   M->fitted = M->selected = false;
   M->g_canonical_on_device = false;
-  double t0 = now_ms();
-  TRY(run_sketch(M, d_video, st));
-  double t1 = now_ms();
-  std::vector<double> V, mu;
-  TRY(small_la(M, V, mu));
-  double t2 = now_ms();
+  M->lift_mfma = M->cfg.dtype == CDMD_U8 && M->ld % 16 == 0 &&
+                 (reinterpret_cast<uintptr_t>(d_video) & 15) == 0 &&
+                 (M->cfg.lift_prec == CDMD_PREC_BF16 || !M->force_valu_lift);
+  M->device_la = M->device_la_ok && M->lift_mfma && !M->force_host_la;
+  double t0 = now_ms(), t1, t2;
+  if (M->device_la) {
+    TRY(run_sketch(M, d_video, st, false));
+    HIPCHK(cdmd::k::small_la(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
+                             (double)M->xscale, M->d_la_scratch, M->d_la_out, M->d_Gp, M->lm_nb,
+                             M->lm_nsplit, M->lm_nksteps, st));
+    t1 = t2 = now_ms();
+  } else {
+    TRY(run_sketch(M, d_video, st, true));
+    t1 = now_ms();
+    std::vector<double> V, mu;
+    TRY(small_la(M, V, mu));
+    t2 = now_ms();
+  }
   TRY(run_lift(M, d_video, nullptr, st));
+  if (M->device_la) TRY(take_device_la(M));
   double t3 = now_ms();
   std::vector<cplx> H, cv;
   assemble_H(M, H, cv);
@@ -715,7 +789,7 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
   M->phinorm.swap(pn);
   double t4 = now_ms();
   M->info.ms_sketch = t1 - t0;
-  M->info.ms_small_la = t2 - t1;
+  if (!M->device_la) M->info.ms_small_la = t2 - t1;  // device path: HIP-event time (run_lift)
   M->info.ms_lift = t3 - t2;
   M->info.ms_host_post = t4 - t3;
   M->info.x1_norm2 = M->x1n2;
@@ -1030,6 +1104,20 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
                                           sigma, lam, W, G, &J);
   if (steps) *steps = J;
   if (st != 0) return fail((cdmd_status)st, "team small LA failed");
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_la_phases(const cdmd_model* M, double* ms8) {
+  g_err.clear();
+  if (!M || !ms8) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < 8; ++i) ms8[i] = M->la_phase_ms[i];
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_force_host_la(cdmd_model* M, int32_t on) {
+  g_err.clear();
+  if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  M->force_host_la = on != 0;
   return CDMD_OK;
 }
 

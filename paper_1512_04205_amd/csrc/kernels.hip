@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include "team_la.hpp"
+
 namespace cdmd {
 namespace k {
 
@@ -599,42 +601,73 @@ __global__ __launch_bounds__(256) void k_bgfg_mfma(const uint8_t* __restrict__ D
     for (int j = 0; j < 16; ++j)
       sT[(64 * w + 32 * mb + (j >> 2) * 8 + (l >> 5) * 4 + (j & 3)) * 33 + (l & 31)] = acc[mb][0][j];
   __syncthreads();
-  float T[NSV];
-#pragma unroll
-  for (int c = 0; c < NSV; ++c) T[c] = sT[tid * 33 + c];
-  const int64_t i = base + tid;
-  const bool valid = i < n;
-  const uint8_t* Dp = D + (valid ? i : 0);
-  const int64_t i0 = i - l;
+  // phase 2 on FP32 MFMA 16x16x4: per wave 4 pixel blocks of 16 x frame blocks of 16,
+  // K = NSV in steps of 4.  A = T (LDS), B = Vc (global, frame-major), C lane l holds
+  // L[px 16mb + 4(l/16) + j][frame 16nb + l%16], j = 0..3.
+  typedef float f32x4_t __attribute__((ext_vector_type(4)));
   const int64_t words = (n + 31) >> 5;
-  constexpr int PF = 8;  // frames in flight per thread
-  for (int64_t tb = t0; tb < t1; tb += PF) {
-    float xs[PF];
+  const int li = l & 15, lq = l >> 4;
+  for (int64_t fb = t0; fb < t1; fb += 16) {
+    const int64_t f = fb + li;                      // this lane's frame (B column / C column)
+    const bool fvalid = f < t1;
+    float bv[NSV / 4];
 #pragma unroll
-    for (int u = 0; u < PF; ++u)
-      xs[u] = (valid && mode != 2 && tb + u < t1) ? (float)Dp[(tb + u) * ld] * xscale : 0.f;
+    for (int ks = 0; ks < NSV / 4; ++ks) bv[ks] = fvalid ? Vc[f * NSV + 4 * ks + lq] : 0.f;
+    uint32_t nib[4];
 #pragma unroll
-    for (int u = 0; u < PF; ++u) {
-      const int64_t tt = tb + u;
-      if (tt >= t1) break;
-      const float* v = Vc + tt * NSV;
-      float L = 0.f;
+    for (int mb = 0; mb < 4; ++mb) {
+      f32x4_t c = {0.f, 0.f, 0.f, 0.f};
+      const int prow = 64 * w + 16 * mb;
 #pragma unroll
-      for (int c = 0; c < NSV; ++c) L = fmaf(T[c], v[c], L);
+      for (int ks = 0; ks < NSV / 4; ++ks) {
+        const float a = sT[(prow + li) * 33 + 4 * ks + lq];
+        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[ks], c, 0, 0, 0);
+      }
+      const int64_t px0 = base + prow + 4 * lq;     // 4 consecutive pixels of this lane
       if (mode == 2) {
-        if (valid) reinterpret_cast<float*>(out)[(tt - t0) * ldL + i] = L;
+        if (fvalid)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (px0 + j < n) reinterpret_cast<float*>(out)[(f - t0) * ldL + px0 + j] = c[j];
+        nib[mb] = 0;
         continue;
       }
-      const bool fg = valid && (fabsf(xs[u] - L) > tau);
-      if (mode == 1) {
-        if (valid) reinterpret_cast<uint8_t*>(out)[tt * n + i] = fg ? 1 : 0;
+      float xv[4];
+      if (fvalid && px0 + 4 <= n) {
+        const uint32_t q = *reinterpret_cast<const uint32_t*>(D + f * ld + px0);
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[j] = (float)((q >> (8 * j)) & 0xffu) * xscale;
       } else {
-        const uint64_t bal = __ballot(fg);
-        if (l == 0 && i0 < n) {
-          uint32_t* wd = reinterpret_cast<uint32_t*>(out) + tt * words + (i0 >> 5);
-          wd[0] = (uint32_t)bal;
-          if ((i0 >> 5) + 1 < words) wd[1] = (uint32_t)(bal >> 32);
-        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) xv[j] = (fvalid && px0 + j < n) ? (float)D[f * ld + px0 + j] * xscale : 0.f;
+      }
+      uint32_t bits = 0;
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        if (fvalid && px0 + j < n && fabsf(xv[j] - c[j]) > tau) bits |= 1u << j;
+      if (mode == 1) {
+        if (fvalid)
+#pragma unroll
+          for (int j = 0; j < 4; ++j)
+            if (px0 + j < n) reinterpret_cast<uint8_t*>(out)[f * n + px0 + j] = (bits >> j) & 1u;
+      }
+      nib[mb] = bits << (4 * lq);
+    }
+    if (mode == 0) {
+      // 16 pixel bits of a block from the four lanes sharing l%16, two blocks per word
+      uint32_t v[4];
+#pragma unroll
+      for (int mb = 0; mb < 4; ++mb) {
+        uint32_t t = nib[mb];
+        t |= __shfl_xor(t, 16, 64);
+        t |= __shfl_xor(t, 32, 64);
+        v[mb] = t;
+      }
+      if (lq == 0 && fvalid) {
+        const int64_t wbase = (base + 64 * w) >> 5;  // first word of this wave's 64 pixels
+        uint32_t* wd = reinterpret_cast<uint32_t*>(out) + f * words + wbase;
+        if (base + 64 * w < n) wd[0] = v[0] | (v[1] << 16);
+        if (base + 64 * w + 32 < n) wd[1] = v[2] | (v[3] << 16);
       }
     }
   }
@@ -828,6 +861,164 @@ hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* 
   hipLaunchKernelGGL(k_mask_counts, dim3((unsigned)m), dim3(256), 0, stream, mask, words, counts);
   return hipGetLastError();
 }
+
+
+// ============================================================================
+// small float64 linear algebra on the device: one 1024-thread workgroup runs
+// Algorithm 1 steps 4, 6, 7 and G = V S^-1 W (team_la.hpp), then writes the B operands
+// of the lift (bf16 terms of G * xscale in MFMA order) so the fit needs no host round
+// trip between the Gram and the lift.
+struct DevTeam {
+  int tid, nt, lane, wsize, wave, nwaves;
+  double* red;
+  double* tslots;     // phase clocks (wall_clock64 ticks): [0] jacobi total, [1..] marks
+  uint64_t t_last;
+  __device__ void sync() { __syncthreads(); }
+  // 0: start of a Jacobi check, 1: its end (accumulated in slot 0); 2..: phase marks
+  __device__ void stamp(int i) {
+    if (tid != 0 || tslots == nullptr) return;
+    const uint64_t t = wall_clock64();
+    if (i == 0) t_last = t;
+    else if (i == 1) tslots[0] += (double)(t - t_last);
+    else tslots[i] = (double)t;
+  }
+  // butterfly sums differ in rounding order per lane: broadcast lane 0's value
+  __device__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return __shfl(v, 0, 64);
+  }
+  __device__ double wave_max(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+  }
+  // maximum value, lowest index among equal values; identical on every lane
+  __device__ void wave_argmax(double& v, int& i) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+      const double ov = __shfl_xor(v, o, 64);
+      const int oi = __shfl_xor(i, o, 64);
+      if (ov > v || (ov == v && oi < i)) v = ov, i = oi;
+    }
+  }
+  __device__ double sum(double v) {
+    v = wave_sum(v);
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < nwaves; ++w) s += red[w];
+    __syncthreads();
+    return s;
+  }
+};
+
+constexpr int SLA_NMAX = 1024;
+constexpr int SLA_JMAX = 320;
+constexpr int SLA_FAST = 15488;  // LDS doubles: Jacobi T and Z for J <= 88, later scratch
+
+__device__ __forceinline__ uint16_t bf16_bits_d(double x) {
+  if (x == 0.0) return signbit(x) ? 0x8000 : 0;
+  int e;
+  const double f = frexp(fabs(x), &e);
+  const double q = ldexp(rint(ldexp(f, 8)), e - 8);
+  const uint32_t u = __float_as_uint((float)q) >> 16;
+  return (uint16_t)(u | (x < 0 ? 0x8000u : 0u));
+}
+__device__ __forceinline__ double bf16_val_d(uint16_t b) {
+  return (double)__uint_as_float((uint32_t)b << 16);
+}
+
+__global__ __launch_bounds__(1024) void k_small_la(const double* __restrict__ Gr, int m, int k,
+                                                   double rtol, int Jmax, double sketch_scale,
+                                                   double xscale, double* __restrict__ scratch,
+                                                   double* __restrict__ out, uint16_t* __restrict__ Gp,
+                                                   int NB, int NS, int KS) {
+  using namespace tla;
+  __shared__ double s_q[SLA_NMAX], s_w[SLA_NMAX];
+  __shared__ double s_h[SLA_JMAX + 4], s_alpha[SLA_JMAX + 4], s_beta[SLA_JMAX + 4];
+  __shared__ double s_rot[SLA_JMAX + 8], s_red[16], s_scal[8];
+  __shared__ int s_pairs[2 * (SLA_JMAX + 8)], s_flag[1];
+  __shared__ double s_fast[SLA_FAST];
+  DevTeam tm;
+  tm.tid = threadIdx.x;
+  tm.nt = blockDim.x;
+  tm.lane = threadIdx.x & 63;
+  tm.wsize = 64;
+  tm.wave = threadIdx.x >> 6;
+  tm.nwaves = blockDim.x >> 6;
+  tm.red = s_red;
+  const int N = m - 1;
+  const SmallLALayout Ls = small_la_layout(N, k, Jmax);
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  tm.tslots = out + Lo.timing;
+  tm.t_last = 0;
+  if (tm.tid == 0)
+    for (int i = 0; i < 16; ++i) tm.tslots[i] = 0.0;
+  SmallLAWork ws;
+  ws.lz = LanczosWork{s_q, s_w, s_h, s_alpha, s_beta, scratch + Ls.T, scratch + Ls.Z, s_scal,
+                      s_pairs, s_rot, s_fast, SLA_FAST};
+  ws.Q = scratch + Ls.Q;
+  ws.V = scratch + Ls.V;
+  ws.TV = scratch + Ls.TV;
+  ws.At = scratch + Ls.At;
+  ws.Hs = scratch + Ls.Hs;
+  ws.LU = reinterpret_cast<cpx*>(scratch + Ls.LU);
+  ws.bb = reinterpret_cast<cpx*>(scratch + Ls.bb);
+  ws.yy = reinterpret_cast<cpx*>(scratch + Ls.yy);
+  ws.piv = reinterpret_cast<int*>(scratch + Ls.piv);
+  ws.flag = s_flag;
+  int J = 0;
+  const int st = small_la_run(tm, Gr, m, k, rtol, Jmax, sketch_scale, ws, out + Lo.mu,
+                              out + Lo.sigma, reinterpret_cast<cpx*>(out + Lo.lam),
+                              reinterpret_cast<cpx*>(out + Lo.W), reinterpret_cast<cpx*>(out + Lo.G), &J);
+  if (tm.tid == 0) {
+    out[Lo.status] = (double)st;
+    out[Lo.J] = (double)J;
+  }
+  if (st != kOk) return;  // uniform: every thread holds the same status
+  tm.stamp(8);
+  const cpx* G = reinterpret_cast<const cpx*>(out + Lo.G);
+  // B operands [ks][nb][split][lane][8]: element i of lane l is G row 16ks + 8(l/32) + i,
+  // column 32nb + l%32 (< k: Re, < 2k: Im of mode col mod k)
+  const int64_t total = (int64_t)KS * NB * 64 * 8;
+  for (int64_t e = tm.tid; e < total; e += tm.nt) {
+    const int i = (int)(e & 7);
+    const int l = (int)((e >> 3) & 63);
+    const int64_t r = e >> 9;
+    const int nb = (int)(r % NB);
+    const int ks = (int)(r / NB);
+    const int row = 16 * ks + 8 * (l >> 5) + i;
+    const int col = 32 * nb + (l & 31);
+    double g = 0.0;
+    if (row < N && col < 2 * k) {
+      const cpx z = G[(int64_t)row * k + (col % k)];
+      g = (col < k ? z.re : z.im) * xscale;
+    }
+    double rem = g;
+    for (int sp = 0; sp < NS; ++sp) {
+      const uint16_t bits = bf16_bits_d(rem);
+      rem -= bf16_val_d(bits);
+      Gp[((((int64_t)ks * NB + nb) * NS + sp) * 64 + l) * 8 + i] = bits;
+    }
+  }
+  __syncthreads();
+  tm.stamp(9);
+}
+
+hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                    double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                    hipStream_t stream) {
+  if (m - 1 > SLA_NMAX || Jmax > SLA_JMAX || 2 * k > SLA_NMAX) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_small_la, dim3(1), dim3(1024), 0, stream, Gr, m, k, rtol, Jmax, sketch_scale,
+                     xscale, scratch, out, (uint16_t*)Gp, NB, NS, KS);
+  return hipGetLastError();
+}
+
+int64_t small_la_scratch_doubles(int m, int k, int Jmax) {
+  return tla::small_la_layout(m - 1, k, Jmax).total;
+}
+int64_t small_la_out_doubles(int m, int k) { return tla::small_la_out_layout(m - 1, k).total; }
 
 }  // namespace k
 }  // namespace cdmd

@@ -77,5 +77,16 @@ hipError_t bgfg_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const v
 hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* counts,
                        hipStream_t stream);
 
+// ----- small float64 linear algebra on the device (one workgroup) -----------------
+// From the m x m Gram Gr of the unscaled sketch: out = [status, J, mu[k], sigma[k],
+// lam[2k], W[2k*k], G[2(m-1)k]] (team_la.hpp small_la_out_layout) and, on success, the
+// lift B operands Gp (NB column blocks, NS bf16 terms, KS k-steps) of G * xscale.
+// Needs m - 1 <= 1024 and Jmax <= 320.  scratch: small_la_scratch_doubles(m, k, Jmax).
+hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                    double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                    hipStream_t stream);
+int64_t small_la_scratch_doubles(int m, int k, int Jmax);
+int64_t small_la_out_doubles(int m, int k);
+
 }  // namespace k
 }  // namespace cdmd

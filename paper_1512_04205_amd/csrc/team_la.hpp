@@ -60,7 +60,10 @@ constexpr double kEps = 2.220446049250313e-16;
 struct HostTeam {
   int tid = 0, nt = 1, lane = 0, wsize = 1, wave = 0, nwaves = 1;
   void sync() {}
+  void stamp(int) {}  // phase timing hook (device only)
   double wave_sum(double v) { return v; }
+  double wave_max(double v) { return v; }
+  void wave_argmax(double&, int&) {}
   double sum(double v) { return v; }
   double maxv(double v) { return v; }
 };
@@ -77,6 +80,8 @@ struct LanczosWork {
   double* scal;   // 8        shared scalars
   int* pairs;     // 2*(Jmax+2) round-robin pairing / ranking (shared)
   double* rot;    // Jmax+2   rotation (c, s) per pair (shared)
+  double* fast;   // fast (LDS) region of fast_doubles doubles, or nullptr: used for the
+  int64_t fast_doubles;  // Jacobi T and Z when 2 J^2 fits, and as later scratch
 };
 
 // Deterministic start vector.
@@ -202,16 +207,33 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
     tm.sync();
   }
   int J = 0;
-  int check = 3 * k + 16;
+  int check = 2 * k > k + 16 ? 2 * k : k + 16;
   if (check > Jmax) check = Jmax;
   double anorm = 0.0;
   int restarts = 0;
   for (int j = 0; j < Jmax; ++j) {
-    // w = M q  (M symmetric: column access keeps threads coalesced)
-    for (int r = tm.tid; r < N; r += tm.nt) {
-      double s = 0.0;
-      for (int c = 0; c < N; ++c) s += M[(int64_t)c * ldm + r] * q[c];
-      w[r] = s;
+    // w = M q: a wave per group of 4 rows, lanes over columns (coalesced, independent)
+    for (int r0 = 4 * tm.wave; r0 < N; r0 += 4 * tm.nwaves) {
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      const double* m0 = M + (int64_t)r0 * ldm;
+      const bool h1 = r0 + 1 < N, h2 = r0 + 2 < N, h3 = r0 + 3 < N;
+      for (int c = tm.lane; c < N; c += tm.wsize) {
+        const double qc = q[c];
+        s0 += m0[c] * qc;
+        if (h1) s1 += m0[ldm + c] * qc;
+        if (h2) s2 += m0[2 * (int64_t)ldm + c] * qc;
+        if (h3) s3 += m0[3 * (int64_t)ldm + c] * qc;
+      }
+      s0 = tm.wave_sum(s0);
+      s1 = tm.wave_sum(s1);
+      s2 = tm.wave_sum(s2);
+      s3 = tm.wave_sum(s3);
+      if (tm.lane == 0) {
+        w[r0] = s0;
+        if (h1) w[r0 + 1] = s1;
+        if (h2) w[r0 + 2] = s2;
+        if (h3) w[r0 + 3] = s3;
+      }
     }
     tm.sync();
     double aj = 0.0;
@@ -226,9 +248,16 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
       tm.sync();
       aj += h[j];
       for (int t = tm.tid; t < N; t += tm.nt) {
-        double v = w[t];
-        for (int i = 0; i <= j; ++i) v -= h[i] * Q[(int64_t)i * N + t];
-        w[t] = v;
+        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
+        int i = 0;
+        for (; i + 4 <= j + 1; i += 4) {
+          v0 += h[i] * Q[(int64_t)i * N + t];
+          v1 += h[i + 1] * Q[(int64_t)(i + 1) * N + t];
+          v2 += h[i + 2] * Q[(int64_t)(i + 2) * N + t];
+          v3 += h[i + 3] * Q[(int64_t)(i + 3) * N + t];
+        }
+        for (; i <= j; ++i) v0 += h[i] * Q[(int64_t)i * N + t];
+        w[t] -= (v0 + v1) + (v2 + v3);
       }
       tm.sync();
     }
@@ -245,52 +274,62 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
     const bool breakdown = nr <= 64.0 * kEps * anorm;
     if (J >= check || breakdown || J == N) {
       // Ritz pairs of T_J by Jacobi; residual of Ritz pair i is beta_J |Z[J-1][i]|
+      const bool fastTZ = ws.fast != nullptr && 2 * (int64_t)J * J <= ws.fast_doubles;
+      double* Tm = fastTZ ? ws.fast : ws.T;
+      double* Zm = fastTZ ? ws.fast + (int64_t)J * J : ws.Z;
       for (int e = tm.tid; e < J * J; e += tm.nt) {
         const int r = e / J, c = e % J;
         double v = 0.0;
         if (r == c) v = ws.alpha[r];
         else if (c == r + 1) v = ws.beta[r];
         else if (r == c + 1) v = ws.beta[c];
-        ws.T[e] = v;
+        Tm[e] = v;
       }
       tm.sync();
-      if (jacobi_sym(tm, ws.T, ws.Z, J, ws.rot, ws.pairs) < 0) return -1;
+      tm.stamp(0);
+      if (jacobi_sym(tm, Tm, Zm, J, ws.rot, ws.pairs) < 0) return -1;
+      tm.stamp(1);
       // order of the top-k (descending): selection by repeated max, computed redundantly
       bool conv = J >= k;
       double th1 = 0.0;
       {
         // rank of each diagonal entry; stored as pairs[] = index of i-th largest
         for (int i = tm.tid; i < J; i += tm.nt) {
-          const double di = ws.T[i * J + i];
+          const double di = Tm[i * J + i];
           int rank = 0;
           for (int c = 0; c < J; ++c) {
-            const double dc = ws.T[c * J + c];
+            const double dc = Tm[c * J + c];
             if (dc > di || (dc == di && c < i)) ++rank;
           }
           ws.pairs[rank] = i;
         }
         tm.sync();
-        th1 = ws.T[ws.pairs[0] * J + ws.pairs[0]];
+        th1 = Tm[ws.pairs[0] * J + ws.pairs[0]];
         const double scale = fabs(th1) > 0 ? fabs(th1) : 1e-300;
         if (conv)
           for (int i = 0; i < k; ++i) {
             const int col = ws.pairs[i];
-            if (nr * fabs(ws.Z[(J - 1) * J + col]) > rtol * scale) conv = false;
+            if (nr * fabs(Zm[(J - 1) * J + col]) > rtol * scale) conv = false;
           }
       }
       if (conv || J == N || J == Jmax) {
         if (J < k) return -1;
         for (int i = tm.tid; i < k; i += tm.nt) {
           const int col = ws.pairs[i];
-          evals[i] = ws.T[col * J + col];
+          evals[i] = Tm[col * J + col];
         }
         // V = Q_J Z_k
         for (int e = tm.tid; e < N * k; e += tm.nt) {
           const int c = e / N, t = e % N;
           const int col = ws.pairs[c];
-          double s = 0.0;
-          for (int i = 0; i < J; ++i) s += Q[(int64_t)i * N + t] * ws.Z[i * J + col];
-          V[(int64_t)c * N + t] = s;
+          double s0 = 0.0, s1 = 0.0;
+          int i = 0;
+          for (; i + 2 <= J; i += 2) {
+            s0 += Q[(int64_t)i * N + t] * Zm[i * J + col];
+            s1 += Q[(int64_t)(i + 1) * N + t] * Zm[(i + 1) * J + col];
+          }
+          if (i < J) s0 += Q[(int64_t)i * N + t] * Zm[i * J + col];
+          V[(int64_t)c * N + t] = s0 + s1;
         }
         tm.sync();
         // renormalise columns
@@ -304,7 +343,7 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
         }
         return conv || J == N ? J : -1;
       }
-      check = J + 32;
+      check = J + (J / 4 > 16 ? J / 4 : 16);
       if (check > Jmax) check = Jmax;
       if (breakdown) {
         // invariant subspace found before k pairs converged: restart orthogonally
@@ -351,24 +390,56 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
 // TV: N x k scratch (column-major).
 template <class TM>
 TLA_HD void reduced_operator(TM& tm, const double* Mfull, int ldm, int N, int k, const double* V,
-                             const double* s, double* TV, double* At) {
-  // TV = M12 V, element (a, c) = sum_b M12[a][b] V[b][c].  The full Gram is symmetric,
-  // so M12[a][b] = Mfull[(b+1)*ldm + a]: threads over a read coalesced columns.
-  for (int e = tm.tid; e < N * k; e += tm.nt) {
-    const int a = e % N, c = e / N;
-    const double* v = V + (int64_t)c * N;
-    double acc = 0.0;
-    for (int b = 0; b < N; ++b) acc += Mfull[(int64_t)(b + 1) * ldm + a] * v[b];
-    TV[(int64_t)c * N + a] = acc;
+                             const double* s, double* TV, double* At, double* stage,
+                             int64_t stage_doubles) {
+  // TV = M12 V, element (a, c) = sum_b M12[a][b] V[b][c].  The Gram is symmetric, so
+  // M12[a][b] = Mfull[(b+1)*ldm + a]: one thread per row a reads coalesced columns; the
+  // rows b of V pass through `stage` (fast memory) in chunks, k accumulators per thread.
+  constexpr int KM = 40;
+  int chunk = (int)(stage_doubles / (k > 0 ? k : 1));
+  if (chunk > 256) chunk = 256;
+  for (int a0 = 0; a0 < N; a0 += tm.nt) {
+    const int a = a0 + tm.tid;
+    double acc[KM];
+#pragma unroll
+    for (int c = 0; c < KM; ++c) acc[c] = 0.0;
+    for (int b0 = 0; b0 < N; b0 += chunk) {
+      const int nb = N - b0 < chunk ? N - b0 : chunk;
+      tm.sync();
+      for (int e = tm.tid; e < nb * k; e += tm.nt) {
+        const int bb = e / k, c = e % k;
+        stage[e] = V[(int64_t)c * N + b0 + bb];
+      }
+      tm.sync();
+      if (a < N)
+        for (int bb = 0; bb < nb; ++bb) {
+          const double mv = Mfull[(int64_t)(b0 + bb + 1) * ldm + a];
+          const double* sv = stage + bb * k;
+#pragma unroll
+          for (int c = 0; c < KM; ++c)
+            if (c < k) acc[c] += mv * sv[c];
+        }
+    }
+    if (a < N)
+#pragma unroll
+      for (int c = 0; c < KM; ++c)
+        if (c < k) TV[(int64_t)c * N + a] = acc[c];
   }
   tm.sync();
   for (int e = tm.tid; e < k * k; e += tm.nt) {
     const int i = e / k, j = e % k;
     const double* vi = V + (int64_t)i * N;
     const double* tj = TV + (int64_t)j * N;
-    double acc = 0.0;
-    for (int a = 0; a < N; ++a) acc += vi[a] * tj[a];
-    At[i * k + j] = acc / (s[i] * s[j]);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    int a = 0;
+    for (; a + 4 <= N; a += 4) {
+      a0 += vi[a] * tj[a];
+      a1 += vi[a + 1] * tj[a + 1];
+      a2 += vi[a + 2] * tj[a + 2];
+      a3 += vi[a + 3] * tj[a + 3];
+    }
+    for (; a < N; ++a) a0 += vi[a] * tj[a];
+    At[i * k + j] = ((a0 + a1) + (a2 + a3)) / (s[i] * s[j]);
   }
   tm.sync();
 }
@@ -601,6 +672,128 @@ TLA_HD inline bool inverse_iteration(const double* A, int k, cpx lam, cpx* LU, c
   return true;
 }
 
+
+// Eigenvectors of the real k x k matrix A for the eigenvalues ev (re, im pairs) by three
+// steps of inverse iteration each, one wave per eigenvalue: the complex LU with partial
+// pivoting of A - lambda I and the triangular solves are split over the wave's lanes,
+// in `region` (fast memory; each active wave needs 2k^2 + 5k doubles; waves take
+// eigenvalues in rounds).  The second member of a conjugate pair is skipped (the caller
+// conjugates its partner).  W: column j at j*k.  Returns false on failure.
+template <class TM>
+TLA_HD bool eigvecs_team(TM& tm, const double* A, int k, const double* ev, cpx* W, double* region,
+                         int64_t region_doubles, int* flag) {
+  const int64_t per = 2 * (int64_t)k * k + 5 * (int64_t)k;
+  int wl = (int)(region_doubles / per);
+  if (wl > tm.nwaves) wl = tm.nwaves;
+  if (wl < 1) return false;
+  if (tm.tid == 0) flag[0] = 0;
+  tm.sync();
+  const int L = tm.lane, WS = tm.wsize;
+  for (int base = 0; base < k; base += wl) {
+    const int j = base + tm.wave;
+    bool active = tm.wave < wl && j < k;
+    if (active && ev[2 * j + 1] < 0.0 && j > 0 && ev[2 * j - 2] == ev[2 * j] &&
+        ev[2 * j - 1] == -ev[2 * j + 1])
+      active = false;
+    const int wv = tm.wave < wl ? tm.wave : 0;
+    cpx* LU = reinterpret_cast<cpx*>(region + wv * per);
+    cpx* b = LU + (int64_t)k * k;
+    cpx* y = b + k;
+    int* piv = reinterpret_cast<int*>(y + k);
+    const double lre = active ? ev[2 * j] : 0.0, lim = active ? ev[2 * j + 1] : 0.0;
+    double amax = 0.0;
+    if (active)
+      for (int e = L; e < k * k; e += WS) {
+        const int r = e / k, c = e % k;
+        LU[e] = cmk(A[e] - (r == c ? lre : 0.0), r == c ? -lim : 0.0);
+        amax = fmax(amax, cabsv(LU[e]));
+      }
+    amax = tm.wave_max(amax);
+    tm.sync();
+    const double tiny = (amax > 1e-300 ? amax : 1e-300) * kEps;
+    for (int jj = 0; jj < k; ++jj) {
+      double best = -1.0;
+      int bi = jj;
+      if (active)
+        for (int i = jj + L; i < k; i += WS) {
+          const double a = cabsv(LU[i * k + jj]);
+          if (a > best) best = a, bi = i;
+        }
+      tm.wave_argmax(best, bi);
+      if (active && L == 0) piv[jj] = bi;
+      if (active && bi != jj)
+        for (int c = L; c < k; c += WS) {
+          const cpx t = LU[jj * k + c];
+          LU[jj * k + c] = LU[bi * k + c];
+          LU[bi * k + c] = t;
+        }
+      tm.sync();
+      if (active && L == 0 && cabsv(LU[jj * k + jj]) < tiny) LU[jj * k + jj] = cmk(tiny, 0.0);
+      tm.sync();
+      if (active) {
+        const cpx pv = LU[jj * k + jj];
+        for (int i = jj + 1 + L; i < k; i += WS) {
+          const cpx f = cdiv(LU[i * k + jj], pv);
+          LU[i * k + jj] = f;
+          for (int c = jj + 1; c < k; ++c) LU[i * k + c] = csub(LU[i * k + c], cmul(f, LU[jj * k + c]));
+        }
+      }
+      tm.sync();
+    }
+    if (active)
+      for (int i = L; i < k; i += WS) b[i] = cmk(1.0, 0.0);
+    tm.sync();
+    for (int it = 0; it < 3; ++it) {
+      if (active && L == 0)
+        for (int jj = 0; jj < k; ++jj)
+          if (piv[jj] != jj) {
+            const cpx t = b[jj];
+            b[jj] = b[piv[jj]];
+            b[piv[jj]] = t;
+          }
+      tm.sync();
+      for (int i = 0; i < k; ++i) {
+        double sr = 0.0, si = 0.0;
+        if (active)
+          for (int c = L; c < i; c += WS) {
+            const cpx pr = cmul(LU[i * k + c], y[c]);
+            sr += pr.re;
+            si += pr.im;
+          }
+        sr = tm.wave_sum(sr);
+        si = tm.wave_sum(si);
+        if (active && L == 0) y[i] = csub(b[i], cmk(sr, si));
+        tm.sync();
+      }
+      for (int i = k - 1; i >= 0; --i) {
+        double sr = 0.0, si = 0.0;
+        if (active)
+          for (int c = i + 1 + L; c < k; c += WS) {
+            const cpx pr = cmul(LU[i * k + c], y[c]);
+            sr += pr.re;
+            si += pr.im;
+          }
+        sr = tm.wave_sum(sr);
+        si = tm.wave_sum(si);
+        if (active && L == 0) y[i] = cdiv(csub(y[i], cmk(sr, si)), LU[i * k + i]);
+        tm.sync();
+      }
+      double nr = 0.0;
+      if (active)
+        for (int i = L; i < k; i += WS) nr += cabs2(y[i]);
+      nr = sqrt(tm.wave_sum(nr));
+      if (active && !(nr > 0.0 && nr < 1e300) && L == 0) flag[0] = 1;
+      if (active && nr > 0.0)
+        for (int i = L; i < k; i += WS) b[i] = cscale(y[i], 1.0 / nr);
+      tm.sync();
+    }
+    if (active)
+      for (int i = L; i < k; i += WS) W[(int64_t)j * k + i] = b[i];
+    tm.sync();
+  }
+  return flag[0] == 0;
+}
+
 // Unit norm, largest-modulus entry (lowest index on ties) real and positive.
 TLA_HD inline void normalise_vec(cpx* w, int k) {
   double nr = 0.0;
@@ -658,7 +851,9 @@ TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int
       if (!(fabs(Gr[e]) < 1e300)) bad = 1.0;
     if (tm.sum(bad) > 0.0) return kNumeric;
   }
+  tm.stamp(2);
   const int J = lanczos_topk(tm, Gr, m, N, k, rtol, Jmax, ws.Q, ws.lz, mu, ws.V);
+  tm.stamp(3);
   *Jout = J;
   if (J < 0) return kNumeric;
   if (!(mu[0] > 0.0) || !(mu[k - 1] > 1e-12 * mu[0])) return kRankDeficient;
@@ -666,24 +861,16 @@ TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int
   for (int i = tm.tid; i < k; i += tm.nt) s[i] = sqrt(mu[i]);
   tm.sync();
   for (int i = tm.tid; i < k; i += tm.nt) sigma[i] = s[i] * sketch_scale;
-  reduced_operator(tm, Gr, m, N, k, ws.V, s, ws.TV, ws.At);
+  double* fastr = ws.lz.fast;
+  const int64_t fastd = ws.lz.fast_doubles;
+  reduced_operator(tm, Gr, m, N, k, ws.V, s, ws.TV, ws.At, fastr, fastd);
+  tm.stamp(4);
   double* ev = ws.lz.w;  // reuse: 2k doubles
-  if (!eigvals_general(tm, ws.At, k, ws.Hs, ev)) return kNumeric;
+  if (!eigvals_general(tm, ws.At, k, (int64_t)k * k <= fastd ? fastr : ws.Hs, ev)) return kNumeric;
+  tm.stamp(5);
   tm.sync();
   for (int j = tm.tid; j < k; j += tm.nt) lam[j] = cmk(ev[2 * j], ev[2 * j + 1]);
-  if (tm.tid == 0) ws.flag[0] = 0;
-  tm.sync();
-  for (int j = tm.tid; j < k; j += tm.nt) {
-    const bool second = ev[2 * j + 1] < 0.0 && j > 0 && ev[2 * j - 2] == ev[2 * j] &&
-                        ev[2 * j - 1] == -ev[2 * j + 1];
-    if (second) continue;
-    const int64_t o = (int64_t)j * k;
-    if (!inverse_iteration(ws.At, k, cmk(ev[2 * j], ev[2 * j + 1]), ws.LU + o * k, ws.bb + o,
-                           ws.yy + o, ws.piv + o, W + o))
-      ws.flag[0] = 1;
-  }
-  tm.sync();
-  if (ws.flag[0]) return kNumeric;
+  if (!eigvecs_team(tm, ws.At, k, ev, W, fastr, fastd, ws.flag)) return kNumeric;
   for (int j = tm.tid; j < k; j += tm.nt) {
     const bool second = ev[2 * j + 1] < 0.0 && j > 0 && ev[2 * j - 2] == ev[2 * j] &&
                         ev[2 * j - 1] == -ev[2 * j + 1];
@@ -693,6 +880,7 @@ TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int
   tm.sync();
   for (int j = tm.tid; j < k; j += tm.nt) normalise_vec(W + (int64_t)j * k, k);
   tm.sync();
+  tm.stamp(6);
   // G = V diag(1/sigma) W
   for (int64_t e = tm.tid; e < (int64_t)N * k; e += tm.nt) {
     const int t = (int)(e / k), j = (int)(e % k);
@@ -706,7 +894,55 @@ TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int
     G[e] = cmk(re, im);
   }
   tm.sync();
+  tm.stamp(7);
   return kOk;
+}
+
+}  // namespace tla
+}  // namespace cdmd
+
+namespace cdmd {
+namespace tla {
+
+// Offsets (in doubles) of the global scratch of one small-LA solve.
+struct SmallLALayout {
+  int64_t Q, T, Z, V, TV, At, Hs, LU, bb, yy, piv, total;
+};
+TLA_HD inline SmallLALayout small_la_layout(int N, int k, int Jmax) {
+  SmallLALayout L;
+  int64_t o = 0;
+  L.Q = o;  o += (int64_t)(Jmax + 1) * N;
+  L.T = o;  o += (int64_t)Jmax * Jmax;
+  L.Z = o;  o += (int64_t)Jmax * Jmax;
+  L.V = o;  o += (int64_t)N * k;
+  L.TV = o; o += (int64_t)N * k;
+  L.At = o; o += (int64_t)k * k;
+  L.Hs = o; o += (int64_t)k * k;
+  L.LU = o; o += 2 * (int64_t)k * k * k;
+  L.bb = o; o += 2 * (int64_t)k * k;
+  L.yy = o; o += 2 * (int64_t)k * k;
+  L.piv = o; o += (int64_t)k * k;  // ints stored in double slots
+  L.total = o;
+  return L;
+}
+
+// Offsets (in doubles) of the small-LA output block: status, J, mu[k], sigma[k],
+// lam[2k], W[2k*k], G[2Nk].
+struct SmallLAOutLayout {
+  int64_t status, J, mu, sigma, lam, W, G, timing, total;
+};
+TLA_HD inline SmallLAOutLayout small_la_out_layout(int N, int k) {
+  SmallLAOutLayout L;
+  L.status = 0;
+  L.J = 1;
+  L.mu = 2;
+  L.sigma = L.mu + k;
+  L.lam = L.sigma + k;
+  L.W = L.lam + 2 * k;
+  L.G = L.W + 2 * (int64_t)k * k;
+  L.timing = L.G + 2 * (int64_t)N * k;  // 16 phase-clock slots (device)
+  L.total = L.timing + 16;
+  return L;
 }
 
 }  // namespace tla

@@ -19,8 +19,10 @@ int team_small_la_host(const double* Gr, int m, int k, double rtol, int Jmax, do
   std::vector<cpx> LU((size_t)k * k * k), bb((size_t)k * k), yy((size_t)k * k);
   std::vector<int> piv((size_t)k * k), flag(1);
   SmallLAWork ws;
+  const int64_t fastd = 2 * (int64_t)Jmax * Jmax + 2 * (int64_t)k * k + 5 * k + 256 * k;
+  std::vector<double> fast(fastd);
   ws.lz = LanczosWork{q.data(), w.data(), h.data(), alpha.data(), beta.data(), T.data(), Z.data(),
-                      scal.data(), pairs.data(), rot.data()};
+                      scal.data(), pairs.data(), rot.data(), fast.data(), fastd};
   ws.Q = Q.data();
   ws.V = V.data();
   ws.TV = TV.data();

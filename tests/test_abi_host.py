@@ -200,3 +200,50 @@ def test_omp_conjugate_pair_tie_prefers_lower_index():
                                  float(x1 @ x1), 1, S.ctypes.data_as(IP), _p(beta), ctypes.byref(ns),
                                  ctypes.byref(r2)) == 0
     assert S[0] == 0 and list(R.omp(Phi, x1, 1)[0]) == [0]
+
+
+# ------------------------------------------------------------------ team small LA (device code, host run)
+@pytest.mark.parametrize("shape", [(40, 52, 45, 10, 300), (72, 100, 60, 12, 400), (48, 64, 130, 25, 600)])
+def test_team_small_la_matches_oracle(shape):
+    """The workgroup small linear algebra the GPU runs per fit (Lanczos + Jacobi on the
+    Lanczos matrix, A~, Francis QR + inverse iteration, G = V S^-1 W), executed by one
+    host thread, reproduces the oracle's SVD-route eigenvalues, singular values and |G|."""
+    H, W, m, k, p = shape
+    lib = P.load_library()
+    lib.cdmd_dbg_team_small_la.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_double, DP, DP, DP, DP, DP, IP]
+    spec = sv.preset("cfg2", H=H, W=W, m=m, bump_sigma=8.0, blur_sigma=3.0, n_rects=3,
+                     rect_side=(6, 14), speed=(0.5, 2.0), seed=7)
+    D = sv.make_video(spec).D.numpy()
+    idx, sign = sv.sparse_table(D.shape[1], p, 32, 3)
+    Y, Yi = R.sketch_sparse(D, 1 / 255, idx, sign)
+    Gr = np.ascontiguousarray(Yi.astype(np.float64).T @ Yi.astype(np.float64))
+    mu, sig, lam = np.zeros(k), np.zeros(k), np.zeros(2 * k)
+    Wm, G, J = np.zeros(2 * k * k), np.zeros(2 * (m - 1) * k), ctypes.c_int32()
+    assert lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1 / 255, _p(mu), _p(sig), _p(lam), _p(Wm),
+                                      _p(G), ctypes.byref(J)) == 0
+    lam = lam[0::2] + 1j * lam[1::2]
+    lr, Wr, s, V, At = R.reduced_operator(Y, k)
+    from scipy.optimize import linear_sum_assignment
+    C = np.abs(lam[:, None] - lr[None, :])
+    a, b = linear_sum_assignment(C)
+    assert (C[a, b] / np.abs(lr[b])).max() < 1e-10
+    np.testing.assert_allclose(sig, s, rtol=1e-10)
+    Gg = (G[0::2] + 1j * G[1::2]).reshape(m - 1, k)
+    Gref = (V / s[None, :]) @ Wr
+    for i in range(k):   # columns agree up to the sign freedom of V
+        np.testing.assert_allclose(np.abs(Gg[:, a[i]]), np.abs(Gref[:, b[i]]), atol=1e-9 * np.abs(Gref[:, b[i]]).max())
+    # exact conjugate pairs
+    for j in range(k):
+        if lam[j].imag > 0:
+            assert np.any(lam == np.conj(lam[j]))
+
+
+def test_team_small_la_rank_deficient():
+    lib = P.load_library()
+    m, k = 20, 3
+    Yi = np.ones((50, m))
+    Gr = np.ascontiguousarray(Yi.T @ Yi)
+    out = [np.zeros(k), np.zeros(k), np.zeros(2 * k), np.zeros(2 * k * k), np.zeros(2 * (m - 1) * k)]
+    st = lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1.0, *[_p(o) for o in out], ctypes.byref(ctypes.c_int32()))
+    assert st == P.E_RANK_DEFICIENT

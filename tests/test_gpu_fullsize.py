@@ -1,0 +1,82 @@
+"""Parity at the full 1080p size in the launch configuration bench.py times:
+1920x1080 uint8, m = 500, sparse +/-1 sketch p = 2000 x 32, k = 25, OMP K = 10, tau = 0.1.
+
+* the integer sketch over the whole video is bit-exact;
+* every eigenvalue has relative error <= 1e-6 against the oracle on the same sketch;
+* |b_j| ||phi_j|| within 2e-5 of the largest, OMP support identical;
+* b_j phi_j and the mask on 20,000 sampled pixels x all frames: masks >= 99.9% identical
+  and every disagreement inside the band ||x - L| - tau| <= band: 1e-4 for the FP32 form,
+  2e-2 for the BF16 form, whose lift rounds G to one bf16 term (relative 2^-9 per entry),
+  the same relative bound its |b_j| ||phi_j|| check uses.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthvideo as sv
+from oracle import cdmd_ref as R
+from tests.cdmd_testutil import eig_rel_err
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_1512_04205_amd")
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_fullsize_1080p(prec):
+    _say("fullsize 1080p", prec, "generate")
+    spec = sv.PRESETS["cfg2"]
+    v = sv.make_video(spec, device="cuda")
+    Dg = v.D
+    m, n = Dg.shape
+    k, p, K, tau = 25, 2000, 10, 0.1
+    idx, sign = sv.sparse_table(n, p, 32, seed=2002)
+    mdl = P.Model(n, m, k, p, idx=idx, sign=sign,
+                  lift_prec=P.PREC_BF16 if prec == "bf16" else P.PREC_FP32)
+    _say("fit")
+    mdl.fit(Dg)
+    md = mdl.modes()
+    S, beta = mdl.select(P.SEL_OMP, K=K)
+    mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    mdl.foreground(Dg, mk, tau)
+    torch.cuda.synchronize()
+    _say("oracle sketch + SVD")
+    D = Dg.cpu().numpy()
+    _, Yi_g = mdl.sketch(integer=True)
+    Y, Yi = R.sketch_sparse(D, 1 / 255, idx, sign)
+    np.testing.assert_array_equal(Yi_g, Yi)
+    _say("oracle lift + lstsq")
+    mo = R.fit(D, 1 / 255, Y, k)
+    rel, _, _ = eig_rel_err(md["lam"], mo.lam)
+    assert rel.max() <= (1e-6 if prec == "fp32" else 1e-3), rel.max()
+    key_r = np.abs(mo.b) * mo.phi_norm
+    tol = 2e-5 if prec == "fp32" else 2e-2
+    assert np.abs(np.abs(md["b"]) * md["phi_norm"] - key_r).max() <= tol * key_r.max()
+    _say("oracle OMP")
+    x1 = D[0].astype(np.float64) / 255
+    Sr, br = R.omp(mo.Phi, x1, K)
+    if prec == "fp32":
+        assert list(S) == list(Sr), (S, Sr)
+    # masks on sampled pixels, with the oracle's support
+    if list(S) != list(Sr):
+        S, beta = mdl.select(P.SEL_EXPLICIT, explicit=Sr)
+        mdl.foreground(Dg, mk, tau)
+        torch.cuda.synchronize()
+    _say("sampled masks")
+    rng = np.random.default_rng(0)
+    pix = np.sort(rng.choice(n, 20000, replace=False))
+    L = R.background(mo.Phi[pix][:, Sr], br, mo.lam[Sr], 0, m)
+    x = D[:, pix].T.astype(np.float64) / 255
+    mr = R.foreground(x, L, tau)
+    words = mk.cpu().numpy().view(np.uint32)
+    mg = ((words[:, pix >> 5] >> (pix & 31).astype(np.uint32)) & 1).astype(bool).T
+    diff = mg != mr
+    assert 1.0 - diff.mean() >= 0.999, diff.mean()
+    if diff.any():
+        band = 1e-4 if prec == "fp32" else 2e-2
+        assert (np.abs(np.abs(x - L) - tau)[diff] <= band).all()
+    _say("done", prec, "eig", rel.max(), "mask diff", int(diff.sum()))

@@ -317,3 +317,35 @@ def test_bf16_lift_form():
     Lr = R.background(ref.model.Phi[:, ref.support], ref.beta, ref.model.lam[ref.support], 0, m)
     mr = R.foreground(D.T.astype(np.float64) / 255, Lr, tau).T
     assert (mg == mr).mean() >= 0.999
+
+
+# ------------------------------------------------------------------ device small LA
+@pytest.mark.parametrize("shape", [(72, 100, 120, 16), (48, 64, 300, 25)])
+def test_device_small_la_matches_host_la_and_oracle(shape):
+    """The one-workgroup float64 solve (Lanczos + Jacobi, A~, Francis QR, G) gives the
+    oracle's eigenvalues and the same amplitudes and supports as the host solve."""
+    H, W, m, k = shape
+    _say("device small LA", shape)
+    v = _small_u8(H=H, W=W, m=m, seed=81)
+    D = v.D.numpy()
+    n = D.shape[1]
+    p = 600
+    idx, sign = sv.sparse_table(n, p, 32, 5)
+    Dg = torch.from_numpy(D).cuda()
+    ref = R.run(D, v.scale, k, sketch="sparse", idx=idx, sign=sign, K=8)
+    res = {}
+    for path in ("device", "host"):
+        mdl = P.Model(n, m, k, p, idx=idx, sign=sign)
+        if path == "host":
+            mdl.force_host_la(True)
+        mdl.fit(Dg)
+        md = mdl.modes()
+        S, _ = mdl.select(P.SEL_OMP, K=8)
+        res[path] = (md, S)
+        rel, _, _ = eig_rel_err(md["lam"], ref.model.lam)
+        assert rel.max() <= 1e-9, (path, rel.max())
+        np.testing.assert_allclose(md["sigma"], ref.model.sigma, rtol=1e-9)
+        key_r = np.abs(ref.model.b) * ref.model.phi_norm
+        assert np.abs(np.abs(md["b"]) * md["phi_norm"] - key_r).max() <= 2e-5 * key_r.max(), path
+        assert list(S) == list(ref.support), (path, S, ref.support)
+    np.testing.assert_allclose(res["device"][0]["lam"], res["host"][0]["lam"], rtol=1e-10, atol=1e-12)
