@@ -47,9 +47,11 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
                                    double* W, double* G, int32_t* steps);
 
 /* Phase times (ms) of the last device small-LA solve: [0] Lanczos incl. convergence
-   checks, [1] of which Jacobi checks, [2] A~, [3] eigenvalues of A~, [4] eigenvectors,
-   [5] G, [6] lift operand write, [7] unused.  Errors: INVALID_ARG. */
-cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms8);
+   checks, [1] of which the tridiagonal eigen-solves of the checks, [2] A~, [3] eigenvalues
+   of A~, [4] eigenvectors, [5] G, [6] lift operand write, and of [0]: [7] matrix-vector
+   products, [8] reorthogonalisation, [9] norm, checks and next vector; [10], [11] unused.
+   Errors: INVALID_ARG. */
+cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms12);
 
 /* Force (1) or release (0) the float64 small linear algebra on the host instead of the
    device workgroup solve (which runs for 16-byte aligned uint8 videos with m <= 1025).

@@ -253,9 +253,10 @@ class Model:
 
     def la_phases(self) -> dict:
         """Phase times (ms) of the last device small-LA solve."""
-        v = np.zeros(8)
+        v = np.zeros(12)
         _check(load_library().cdmd_dbg_la_phases(self._h, _dptr(v)))
-        return dict(zip(["lanczos", "jacobi", "atilde", "eigvals", "eigvecs", "G", "operands"], v[:7]))
+        return dict(zip(["lanczos", "checks", "atilde", "eigvals", "eigvecs", "G", "operands",
+                         "matvec", "orth", "step_rest"], v[:10]))
 
     def set_timing(self, enable: bool = True):
         _check(load_library().cdmd_set_timing(self._h, int(enable)))

@@ -122,7 +122,7 @@ struct cdmd_model {
   bool timing = false, recon_pending = false;
   bool force_valu_lift = false;  // test hook: use the float32 VALU lift for uint8 video
   bool force_host_la = false;    // test hook: float64 small LA on the host
-  double la_phase_ms[8] = {};
+  double la_phase_ms[12] = {};
   // device small LA (one workgroup)
   bool device_la_ok = false;     // sized at create
   bool device_la = false;        // used by the last fit
@@ -482,8 +482,9 @@ cdmd_status take_device_la(cdmd_model* M) {
   for (int j = 0; j < k; ++j) M->lam[j] = cplx(o[L.lam + 2 * j], o[L.lam + 2 * j + 1]);
   for (int64_t e = 0; e < (int64_t)k * k; ++e) M->W[e] = cplx(o[L.W + 2 * e], o[L.W + 2 * e + 1]);
   for (int64_t e = 0; e < (int64_t)N * k; ++e) M->G[e] = cplx(o[L.G + 2 * e], o[L.G + 2 * e + 1]);
-  // phase times in ms (wall clock at 100 MHz): lanczos incl. checks, of which Jacobi,
-  // A~, eigenvalues, eigenvectors, G, operand write
+  // phase times in ms (wall clock at 100 MHz): lanczos incl. checks, of which the
+  // tridiagonal checks, A~, eigenvalues, eigenvectors, G, operand write; Lanczos matvec,
+  // orthogonalisation, rest of the step (norm, check, next vector)
   const double* tt = o + L.timing;
   const double f = 1e-5;
   M->la_phase_ms[0] = (tt[3] - tt[2]) * f;
@@ -493,6 +494,9 @@ cdmd_status take_device_la(cdmd_model* M) {
   M->la_phase_ms[4] = (tt[6] - tt[5]) * f;
   M->la_phase_ms[5] = (tt[7] - tt[6]) * f;
   M->la_phase_ms[6] = (tt[9] - tt[8]) * f;
+  M->la_phase_ms[7] = tt[10] * f;
+  M->la_phase_ms[8] = tt[11] * f;
+  M->la_phase_ms[9] = tt[12] * f;
   return CDMD_OK;
 }
 
@@ -1107,10 +1111,10 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
   return CDMD_OK;
 }
 
-cdmd_status cdmd_dbg_la_phases(const cdmd_model* M, double* ms8) {
+cdmd_status cdmd_dbg_la_phases(const cdmd_model* M, double* ms12) {
   g_err.clear();
-  if (!M || !ms8) return fail(CDMD_E_INVALID_ARG, "NULL argument");
-  for (int i = 0; i < 8; ++i) ms8[i] = M->la_phase_ms[i];
+  if (!M || !ms12) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < 12; ++i) ms12[i] = M->la_phase_ms[i];
   return CDMD_OK;
 }
 

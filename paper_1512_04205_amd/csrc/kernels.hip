@@ -868,25 +868,39 @@ hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* 
 // Algorithm 1 steps 4, 6, 7 and G = V S^-1 W (team_la.hpp), then writes the B operands
 // of the lift (bf16 terms of G * xscale in MFMA order) so the fit needs no host round
 // trip between the Gram and the lift.
-struct DevTeam {
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+  const uint64_t u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double((long long)(((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo));
+}
+__device__ __forceinline__ double lane_f64(double v, int l) {
+  const uint64_t u = __double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// One wave of a workgroup acting alone: lanes are its threads, and a synchronisation is a
+// wave-level memory fence (the wave's LDS and global accesses then complete in order).
+struct WaveTeam {
   int tid, nt, lane, wsize, wave, nwaves;
-  double* red;
-  double* tslots;     // phase clocks (wall_clock64 ticks): [0] jacobi total, [1..] marks
-  uint64_t t_last;
-  __device__ void sync() { __syncthreads(); }
-  // 0: start of a Jacobi check, 1: its end (accumulated in slot 0); 2..: phase marks
-  __device__ void stamp(int i) {
-    if (tid != 0 || tslots == nullptr) return;
-    const uint64_t t = wall_clock64();
-    if (i == 0) t_last = t;
-    else if (i == 1) tslots[0] += (double)(t - t_last);
-    else tslots[i] = (double)t;
+  __device__ void sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
   }
-  // butterfly sums differ in rounding order per lane: broadcast lane 0's value
+  __device__ void stamp(int) {}
+  __device__ void tick(int) {}
+  // Sum over the wave, the same bits on every lane: within each row of 16 lanes a DPP
+  // butterfly (lane pairs i^1, i^2, then the 8- and 16-lane mirrors; every pair adds the
+  // same two values), then the four row sums are read as scalars and added in fixed order.
   __device__ double wave_sum(double v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return __shfl(v, 0, 64);
+    v += dpp_f64<0xB1>(v);   // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E>(v);   // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141>(v);  // row_half_mirror
+    v += dpp_f64<0x140>(v);  // row_mirror
+    return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
   }
   __device__ double wave_max(double v) {
 #pragma unroll
@@ -902,6 +916,36 @@ struct DevTeam {
       if (ov > v || (ov == v && oi < i)) v = ov, i = oi;
     }
   }
+  __device__ int wave_first(bool b) {
+    const unsigned long long m = __ballot(b);
+    return m ? __ffsll((long long)m) - 1 : 64;
+  }
+  __device__ double sum(double v) { return wave_sum(v); }
+  __device__ double maxv(double v) { return wave_max(v); }
+  __device__ WaveTeam wave_team() { return *this; }
+};
+
+struct DevTeam : WaveTeam {
+  double* red;
+  double* tslots;     // phase clocks (wall_clock64 ticks): [0] tridiagonal checks, [2..9]
+  uint64_t t_last;    // marks, [10..12] Lanczos sub-phases
+  uint64_t t_tick;
+  __device__ void sync() { __syncthreads(); }
+  // 0: start of a convergence check, 1: its end (accumulated in slot 0); 2..: phase marks
+  __device__ void stamp(int i) {
+    if (tid != 0 || tslots == nullptr) return;
+    const uint64_t t = wall_clock64();
+    if (i == 0) t_last = t;
+    else if (i == 1) tslots[0] += (double)(t - t_last);
+    else tslots[i] = (double)t;
+  }
+  // accumulate the time since the previous tick into slot i (i < 0: restart)
+  __device__ void tick(int i) {
+    if (tid != 0 || tslots == nullptr) return;
+    const uint64_t t = wall_clock64();
+    if (i >= 0) tslots[i] += (double)(t - t_tick);
+    t_tick = t;
+  }
   __device__ double sum(double v) {
     v = wave_sum(v);
     if (lane == 0) red[wave] = v;
@@ -911,11 +955,21 @@ struct DevTeam {
     __syncthreads();
     return s;
   }
+  __device__ WaveTeam wave_team() {
+    WaveTeam t;
+    t.tid = lane;
+    t.nt = wsize;
+    t.lane = lane;
+    t.wsize = wsize;
+    t.wave = 0;
+    t.nwaves = 1;
+    return t;
+  }
 };
 
 constexpr int SLA_NMAX = 1024;
 constexpr int SLA_JMAX = 320;
-constexpr int SLA_FAST = 15488;  // LDS doubles: Jacobi T and Z for J <= 88, later scratch
+constexpr int SLA_FAST = 15488;  // LDS doubles: tridiagonal eigen-solve work, later scratch
 
 __device__ __forceinline__ uint16_t bf16_bits_d(double x) {
   if (x == 0.0) return signbit(x) ? 0x8000 : 0;
@@ -937,8 +991,8 @@ __global__ __launch_bounds__(1024) void k_small_la(const double* __restrict__ Gr
   using namespace tla;
   __shared__ double s_q[SLA_NMAX], s_w[SLA_NMAX];
   __shared__ double s_h[SLA_JMAX + 4], s_alpha[SLA_JMAX + 4], s_beta[SLA_JMAX + 4];
-  __shared__ double s_rot[SLA_JMAX + 8], s_red[16], s_scal[8];
-  __shared__ int s_pairs[2 * (SLA_JMAX + 8)], s_flag[1];
+  __shared__ double s_red[16];
+  __shared__ int s_flag[1];
   __shared__ double s_fast[SLA_FAST];
   DevTeam tm;
   tm.tid = threadIdx.x;
@@ -953,11 +1007,11 @@ __global__ __launch_bounds__(1024) void k_small_la(const double* __restrict__ Gr
   const SmallLAOutLayout Lo = small_la_out_layout(N, k);
   tm.tslots = out + Lo.timing;
   tm.t_last = 0;
+  tm.t_tick = 0;
   if (tm.tid == 0)
     for (int i = 0; i < 16; ++i) tm.tslots[i] = 0.0;
   SmallLAWork ws;
-  ws.lz = LanczosWork{s_q, s_w, s_h, s_alpha, s_beta, scratch + Ls.T, scratch + Ls.Z, s_scal,
-                      s_pairs, s_rot, s_fast, SLA_FAST};
+  ws.lz = LanczosWork{s_q, s_w, s_h, s_alpha, s_beta, scratch + Ls.T, s_fast, SLA_FAST};
   ws.Q = scratch + Ls.Q;
   ws.V = scratch + Ls.V;
   ws.TV = scratch + Ls.TV;

@@ -66,6 +66,9 @@ struct HostTeam {
   void wave_argmax(double&, int&) {}
   double sum(double v) { return v; }
   double maxv(double v) { return v; }
+  int wave_first(bool b) { return b ? 0 : 1; }  // lowest lane with b set, or wsize
+  void tick(int) {}                             // sub-phase timing hook (device only)
+  HostTeam wave_team() { return *this; }        // the team of this thread's wave
 };
 
 // --------------------------------------------------------------------------- Lanczos
@@ -75,13 +78,9 @@ struct LanczosWork {
   double* h;      // Jmax+1   projections (shared)
   double* alpha;  // Jmax+1   (shared)
   double* beta;   // Jmax+1   (shared)
-  double* T;      // Jmax*Jmax  Jacobi matrix (global scratch)
-  double* Z;      // Jmax*Jmax  Jacobi eigenvectors (global scratch)
-  double* scal;   // 8        shared scalars
-  int* pairs;     // 2*(Jmax+2) round-robin pairing / ranking (shared)
-  double* rot;    // Jmax+2   rotation (c, s) per pair (shared)
-  double* fast;   // fast (LDS) region of fast_doubles doubles, or nullptr: used for the
-  int64_t fast_doubles;  // Jacobi T and Z when 2 J^2 fits, and as later scratch
+  double* T;      // Jmax + k + 6 Jmax k: tridiagonal eigen-solve work (global scratch)
+  double* fast;   // fast (LDS) region of fast_doubles doubles, or nullptr: the tridiagonal
+  int64_t fast_doubles;  // work when it fits, and later scratch
 };
 
 // Deterministic start vector.
@@ -89,94 +88,177 @@ TLA_HD inline double lanczos_start(int i, int salt) {
   return 1.0 + 0.25 * sin(0.7 * (i + 1) + 1.3 * salt);
 }
 
-// Symmetric eigenproblem of the J x J matrix A (row-major, overwritten by its diagonal
-// form) by cyclic Jacobi with the round-robin parallel ordering: each step applies J/2
-// rotations on disjoint index pairs, first to rows, then to columns, and to the
-// eigenvector matrix Z (J x J, column j = eigenvector of A[j][j]).  Sweeps until the
-// off-diagonal Frobenius norm is <= eps * ||A||_F.  Returns the number of sweeps, or
-// -1 if 40 sweeps did not converge.
+// Number of eigenvalues smaller than x of the symmetric tridiagonal matrix with diagonal a
+// and squared off-diagonal b2 (Sylvester's law of inertia on the LDL^T pivots; a pivot
+// smaller than pivmin in modulus is replaced by -pivmin).
+TLA_HD inline int sturm_count(const double* a, const double* b2, int J, double x, double pivmin) {
+  double q = a[0] - x;
+  if (fabs(q) < pivmin) q = -pivmin;
+  int c = q < 0.0 ? 1 : 0;
+  for (int i = 1; i < J; ++i) {
+    q = (a[i] - x) - b2[i - 1] / q;
+    if (fabs(q) < pivmin) q = -pivmin;
+    c += q < 0.0 ? 1 : 0;
+  }
+  return c;
+}
+
+// The kk largest eigenvalues (descending) of the symmetric tridiagonal (a, b), J x J,
+// b[i] coupling i and i+1; b2 holds b[i]^2.  One wave per eigenvalue: its lanes evaluate
+// the Sturm count at wsize interior points of the current bracket at once (multisection),
+// shrinking the bracket by wsize + 1 per round, down to a width of 2 eps |x| + pivmin.
 template <class TM>
-TLA_HD int jacobi_sym(TM& tm, double* A, double* Z, int J, double* cs, int* pr) {
-  for (int e = tm.tid; e < J * J; e += tm.nt) Z[e] = (e / J == e % J) ? 1.0 : 0.0;
-  tm.sync();
-  const int Je = J + (J & 1);  // even player count (a dummy when J is odd)
-  int sweep = 0;
-  for (; sweep < 40; ++sweep) {
-    double off = 0.0, tot = 0.0;
-    for (int e = tm.tid; e < J * J; e += tm.nt) {
-      const double v = A[e] * A[e];
-      tot += v;
-      if (e / J != e % J) off += v;
-    }
-    off = tm.sum(off);
-    tot = tm.sum(tot);
-    if (off <= kEps * kEps * tot || J < 2) break;
-    for (int step = 0; step < Je - 1; ++step) {
-      // pairs of this step (round robin: player Je-1 fixed, others rotate)
-      for (int s = tm.tid; s < Je / 2; s += tm.nt) {
-        int a, b;
-        if (s == 0) {
-          a = Je - 1;
-          b = step;
-        } else {
-          a = (step + s) % (Je - 1);
-          b = (step - s + (Je - 1)) % (Je - 1);
-        }
-        if (a > b) {
-          const int t = a;
-          a = b;
-          b = t;
-        }
-        pr[2 * s] = a;
-        pr[2 * s + 1] = b;
+TLA_HD void tridiag_topk_values(TM& tm, const double* a, const double* b, const double* b2,
+                                int J, int kk, double* theta, double* tnorm_out) {
+  double gl = a[0], gu = a[0], bmax2 = 0.0;
+  for (int i = 0; i < J; ++i) {
+    const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < J ? fabs(b[i]) : 0.0);
+    gl = fmin(gl, a[i] - r);
+    gu = fmax(gu, a[i] + r);
+    if (i + 1 < J) bmax2 = fmax(bmax2, b2[i]);
+  }
+  const double tnorm = fmax(fabs(gl), fabs(gu));
+  const double pivmin = 2.2250738585072014e-308 * fmax(1.0, bmax2);
+  const double fud = 2.1 * kEps * tnorm * J + 2.1 * pivmin;
+  gl -= fud;
+  gu += fud;
+  *tnorm_out = tnorm;
+  const double np1 = (double)(tm.wsize + 1);
+  for (int r0 = 0; r0 < kk; r0 += tm.nwaves) {
+    const int r = r0 + tm.wave;
+    if (r < kk) {  // uniform over the wave
+      const int s = J - 1 - r;  // rank from the smallest; bracket: cnt(lo) <= s < cnt(hi)
+      double lo = gl, hi = gu;
+      for (int it = 0; it < 256; ++it) {
+        if (hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
+        const double x = lo + (hi - lo) * ((double)(tm.lane + 1) / np1);
+        const int f = tm.wave_first(sturm_count(a, b2, J, x, pivmin) > s);
+        const double nhi = f < tm.wsize ? lo + (hi - lo) * ((double)(f + 1) / np1) : hi;
+        const double nlo = f > 0 ? lo + (hi - lo) * ((double)f / np1) : lo;
+        if (nhi == hi && nlo == lo) break;
+        lo = nlo;
+        hi = nhi;
       }
-      tm.sync();
-      // rotation parameters per pair
-      for (int s = tm.tid; s < Je / 2; s += tm.nt) {
-        const int a = pr[2 * s], b = pr[2 * s + 1];
-        double c = 1.0, sn = 0.0;
-        if (b < J) {
-          const double apq = A[a * J + b];
-          if (apq != 0.0) {
-            const double app = A[a * J + a], aqq = A[b * J + b];
-            const double theta = (aqq - app) / (2.0 * apq);
-            const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            sn = t * c;
-          }
-        }
-        cs[2 * s] = c;
-        cs[2 * s + 1] = sn;
-      }
-      tm.sync();
-      // rows: A <- R^T A for each pair (rows a, b), R = [[c, s], [-s, c]]
-      for (int e = tm.tid; e < (Je / 2) * J; e += tm.nt) {
-        const int s = e / J, col = e % J;
-        const int a = pr[2 * s], b = pr[2 * s + 1];
-        if (b >= J) continue;
-        const double c = cs[2 * s], sn = cs[2 * s + 1];
-        const double xa = A[a * J + col], xb = A[b * J + col];
-        A[a * J + col] = c * xa - sn * xb;
-        A[b * J + col] = sn * xa + c * xb;
-      }
-      tm.sync();
-      // columns: A <- A R, Z <- Z R
-      for (int e = tm.tid; e < (Je / 2) * J; e += tm.nt) {
-        const int s = e / J, row = e % J;
-        const int a = pr[2 * s], b = pr[2 * s + 1];
-        if (b >= J) continue;
-        const double c = cs[2 * s], sn = cs[2 * s + 1];
-        const double xa = A[row * J + a], xb = A[row * J + b];
-        A[row * J + a] = c * xa - sn * xb;
-        A[row * J + b] = sn * xa + c * xb;
-        const double za = Z[row * J + a], zb = Z[row * J + b];
-        Z[row * J + a] = c * za - sn * zb;
-        Z[row * J + b] = sn * za + c * zb;
-      }
-      tm.sync();
+      if (tm.lane == 0) theta[r] = 0.5 * (lo + hi);
     }
   }
-  return sweep < 40 ? sweep : -1;
+  tm.sync();
+}
+
+// Eigenvectors of the symmetric tridiagonal (a, b) for theta[0..kk-1] (descending) by three
+// steps of inverse iteration, each a solve with the LU factors (row interchanges) of
+// T - theta I, one thread per eigenvector, all at once.  Vectors of nearly equal
+// eigenvalues can come out with a small mutual component (of order eps ||T|| / gap);
+// with orth set, one wave then orthonormalises the columns in order (classical
+// Gram-Schmidt, twice), which keeps each in the span of the computed vectors of its
+// cluster.  Unit vectors, largest-modulus component positive.  work: 5 J kk doubles;
+// Z: J x kk, element (i, r) at Z[i*kk + r].
+template <class TM>
+TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int kk,
+                            const double* theta, double tnorm, bool orth, double* work, double* Z) {
+  const double tiny = kEps * (tnorm > 0.0 ? tnorm : 1.0);
+  for (int r = tm.tid; r < kk; r += tm.nt) {
+    const double th = theta[r];
+    double* W = work + r;  // element (i, f) at W[(i*5 + f) * kk]
+    const int64_t st = kk, ys = 5 * st;
+    // factor: pending row (p0, p1) at columns i, i+1
+    double p0 = a[0] - th, p1 = J > 1 ? b[0] : 0.0;
+    for (int i = 0; i + 1 < J; ++i) {
+      const double bi = b[i], dn = a[i + 1] - th, bn = i + 2 < J ? b[i + 1] : 0.0;
+      double* w = W + i * ys;
+      if (fabs(bi) > fabs(p0)) {  // interchange rows i and i+1
+        const double l = p0 / bi;
+        w[0] = bi;
+        w[st] = dn;
+        w[2 * st] = 1.0;
+        w[3 * st] = l;
+        p0 = p1 - l * dn;
+        p1 = -l * bn;
+      } else {
+        if (fabs(p0) < tiny) p0 = p0 < 0.0 ? -tiny : tiny;
+        const double l = bi / p0;
+        w[0] = p0;
+        w[st] = p1;
+        w[2 * st] = 0.0;
+        w[3 * st] = l;
+        p0 = dn - l * p1;
+        p1 = bn;
+      }
+    }
+    if (fabs(p0) < tiny) p0 = p0 < 0.0 ? -tiny : tiny;
+    W[(J - 1) * ys] = p0;
+    double* y = W + 4 * st;  // y_i at y[i*ys]
+    for (int i = 0; i < J; ++i) y[i * ys] = 1.0 + 0.5 * sin(1.7 * (i + 1) + 0.37 * r);
+    for (int it = 0; it < 3; ++it) {
+      double rp = y[0];
+      for (int i = 0; i + 1 < J; ++i) {
+        const double* w = W + i * ys;
+        const double xn = y[(i + 1) * ys], l = w[3 * st];
+        if (w[2 * st] != 0.0) {
+          y[i * ys] = xn;
+          rp -= l * xn;
+        } else {
+          y[i * ys] = rp;
+          rp = xn - l * rp;
+        }
+      }
+      y[(J - 1) * ys] = rp / W[(J - 1) * ys];
+      for (int i = J - 2; i >= 0; --i) {
+        const double* w = W + i * ys;
+        double v = y[i * ys] - w[st] * y[(i + 1) * ys];
+        if (w[2 * st] != 0.0 && i + 2 < J) v -= b[i + 1] * y[(i + 2) * ys];
+        y[i * ys] = v / w[0];
+      }
+      double big = 0.0;
+      for (int i = 0; i < J; ++i) big = fmax(big, fabs(y[i * ys]));
+      // rescale first so that the squares cannot overflow
+      const double sc = big > 0.0 ? 1.0 / big : 1.0;
+      double nr = 0.0;
+      for (int i = 0; i < J; ++i) {
+        const double v = y[i * ys] * sc;
+        y[i * ys] = v;
+        nr += v * v;
+      }
+      const double inv = 1.0 / sqrt(nr);
+      for (int i = 0; i < J; ++i) y[i * ys] *= inv;
+    }
+    for (int i = 0; i < J; ++i) Z[(int64_t)i * kk + r] = y[i * ys];
+  }
+  tm.sync();
+  if (tm.wave == 0) {
+    auto wt = tm.wave_team();
+    for (int r = 0; r < kk; ++r) {
+      double* zr = Z + r;
+      if (orth)
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int q = 0; q < r; ++q) {
+            double d = 0.0;
+            for (int i = wt.lane; i < J; i += wt.wsize) d += Z[(int64_t)i * kk + q] * zr[(int64_t)i * kk];
+            d = wt.wave_sum(d);
+            for (int i = wt.lane; i < J; i += wt.wsize) zr[(int64_t)i * kk] -= d * Z[(int64_t)i * kk + q];
+            wt.sync();
+          }
+          double nr = 0.0;
+          for (int i = wt.lane; i < J; i += wt.wsize) nr += zr[(int64_t)i * kk] * zr[(int64_t)i * kk];
+          const double inv = 1.0 / sqrt(wt.wave_sum(nr));
+          for (int i = wt.lane; i < J; i += wt.wsize) zr[(int64_t)i * kk] *= inv;
+          wt.sync();
+        }
+      // sign: largest-modulus component (lowest index on ties) positive
+      double best = -1.0;
+      int bi = 0;
+      for (int i = wt.lane; i < J; i += wt.wsize) {
+        const double v = fabs(zr[(int64_t)i * kk]);
+        if (v > best) best = v, bi = i;
+      }
+      wt.wave_argmax(best, bi);
+      const double sg = zr[(int64_t)bi * kk] < 0.0 ? -1.0 : 1.0;
+      wt.sync();
+      for (int i = wt.lane; i < J; i += wt.wsize) zr[(int64_t)i * kk] *= sg;
+      wt.sync();
+    }
+  }
+  tm.sync();
 }
 
 // Top-k eigenpairs of the symmetric N x N matrix M (element (r, c) at M[r*ldm + c]).
@@ -212,30 +294,47 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
   double anorm = 0.0;
   int restarts = 0;
   for (int j = 0; j < Jmax; ++j) {
-    // w = M q: a wave per group of 4 rows, lanes over columns (coalesced, independent)
-    for (int r0 = 4 * tm.wave; r0 < N; r0 += 4 * tm.nwaves) {
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      const double* m0 = M + (int64_t)r0 * ldm;
-      const bool h1 = r0 + 1 < N, h2 = r0 + 2 < N, h3 = r0 + 3 < N;
-      for (int c = tm.lane; c < N; c += tm.wsize) {
-        const double qc = q[c];
-        s0 += m0[c] * qc;
-        if (h1) s1 += m0[ldm + c] * qc;
-        if (h2) s2 += m0[2 * (int64_t)ldm + c] * qc;
-        if (h3) s3 += m0[3 * (int64_t)ldm + c] * qc;
+    tm.tick(-1);
+    // w = M q as columns of the symmetric M: thread r of column group g sums
+    // M[c][r] q[c] over its range of c (coalesced over r); groups combine in fixed order
+    {
+      int G = tm.nt / N;
+      if (G > 4) G = 4;
+      if (G < 1) G = 1;
+      double* part = ws.fast != nullptr && (int64_t)(G - 1) * N <= ws.fast_doubles ? ws.fast : nullptr;
+      if (part == nullptr) G = 1;
+      for (int t = tm.tid; t < G * N; t += tm.nt) {
+        const int r = t % N, g = t / N;
+        const int c0 = (int)((int64_t)N * g / G), c1 = (int)((int64_t)N * (g + 1) / G);
+        const double* col = M + r;
+        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
+        int c = c0;
+        for (; c + 8 <= c1; c += 8) {
+          a0 += col[(int64_t)c * ldm] * q[c];
+          a1 += col[(int64_t)(c + 1) * ldm] * q[c + 1];
+          a2 += col[(int64_t)(c + 2) * ldm] * q[c + 2];
+          a3 += col[(int64_t)(c + 3) * ldm] * q[c + 3];
+          a4 += col[(int64_t)(c + 4) * ldm] * q[c + 4];
+          a5 += col[(int64_t)(c + 5) * ldm] * q[c + 5];
+          a6 += col[(int64_t)(c + 6) * ldm] * q[c + 6];
+          a7 += col[(int64_t)(c + 7) * ldm] * q[c + 7];
+        }
+        for (; c < c1; ++c) a0 += col[(int64_t)c * ldm] * q[c];
+        const double acc = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+        if (g == 0) w[r] = acc;
+        else part[(int64_t)(g - 1) * N + r] = acc;
       }
-      s0 = tm.wave_sum(s0);
-      s1 = tm.wave_sum(s1);
-      s2 = tm.wave_sum(s2);
-      s3 = tm.wave_sum(s3);
-      if (tm.lane == 0) {
-        w[r0] = s0;
-        if (h1) w[r0 + 1] = s1;
-        if (h2) w[r0 + 2] = s2;
-        if (h3) w[r0 + 3] = s3;
+      tm.sync();
+      if (G > 1) {
+        for (int r = tm.tid; r < N; r += tm.nt) {
+          double acc = w[r];
+          for (int g = 1; g < G; ++g) acc += part[(int64_t)(g - 1) * N + r];
+          w[r] = acc;
+        }
+        tm.sync();
       }
     }
-    tm.sync();
+    tm.tick(10);
     double aj = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
       for (int i = tm.wave; i <= j; i += tm.nwaves) {
@@ -261,6 +360,7 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
       }
       tm.sync();
     }
+    tm.tick(11);
     double nr = 0.0;
     for (int t = tm.tid; t < N; t += tm.nt) nr += w[t] * w[t];
     nr = sqrt(tm.sum(nr));
@@ -273,74 +373,53 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
     }
     const bool breakdown = nr <= 64.0 * kEps * anorm;
     if (J >= check || breakdown || J == N) {
-      // Ritz pairs of T_J by Jacobi; residual of Ritz pair i is beta_J |Z[J-1][i]|
-      const bool fastTZ = ws.fast != nullptr && 2 * (int64_t)J * J <= ws.fast_doubles;
-      double* Tm = fastTZ ? ws.fast : ws.T;
-      double* Zm = fastTZ ? ws.fast + (int64_t)J * J : ws.Z;
-      for (int e = tm.tid; e < J * J; e += tm.nt) {
-        const int r = e / J, c = e % J;
-        double v = 0.0;
-        if (r == c) v = ws.alpha[r];
-        else if (c == r + 1) v = ws.beta[r];
-        else if (r == c + 1) v = ws.beta[c];
-        Tm[e] = v;
-      }
-      tm.sync();
+      // Ritz values of T_J by multisection, Ritz vectors of T_J by inverse iteration; the
+      // residual of Ritz pair i is beta_J |z_{J-1,i}|
       tm.stamp(0);
-      if (jacobi_sym(tm, Tm, Zm, J, ws.rot, ws.pairs) < 0) return -1;
+      const int kk = k < J ? k : J;
+      const int64_t need = J + kk + 6 * (int64_t)J * kk;
+      double* b2 = ws.fast != nullptr && need <= ws.fast_doubles ? ws.fast : ws.T;
+      double* theta = b2 + J;
+      double* work = theta + kk;
+      double* Zm = work + 5 * (int64_t)J * kk;
+      for (int i = tm.tid; i + 1 < J; i += tm.nt) b2[i] = ws.beta[i] * ws.beta[i];
+      tm.sync();
+      double tnorm = 0.0;
+      tridiag_topk_values(tm, ws.alpha, ws.beta, b2, J, kk, theta, &tnorm);
+      tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, false, work, Zm);
       tm.stamp(1);
-      // order of the top-k (descending): selection by repeated max, computed redundantly
       bool conv = J >= k;
-      double th1 = 0.0;
-      {
-        // rank of each diagonal entry; stored as pairs[] = index of i-th largest
-        for (int i = tm.tid; i < J; i += tm.nt) {
-          const double di = Tm[i * J + i];
-          int rank = 0;
-          for (int c = 0; c < J; ++c) {
-            const double dc = Tm[c * J + c];
-            if (dc > di || (dc == di && c < i)) ++rank;
-          }
-          ws.pairs[rank] = i;
-        }
-        tm.sync();
-        th1 = Tm[ws.pairs[0] * J + ws.pairs[0]];
-        const double scale = fabs(th1) > 0 ? fabs(th1) : 1e-300;
-        if (conv)
-          for (int i = 0; i < k; ++i) {
-            const int col = ws.pairs[i];
-            if (nr * fabs(Zm[(J - 1) * J + col]) > rtol * scale) conv = false;
-          }
-      }
+      const double scale = fabs(theta[0]) > 0 ? fabs(theta[0]) : 1e-300;
+      if (conv)
+        for (int i = 0; i < k; ++i)
+          if (nr * fabs(Zm[(int64_t)(J - 1) * kk + i]) > rtol * scale) conv = false;
       if (conv || J == N || J == Jmax) {
         if (J < k) return -1;
-        for (int i = tm.tid; i < k; i += tm.nt) {
-          const int col = ws.pairs[i];
-          evals[i] = Tm[col * J + col];
-        }
+        // final Ritz vectors: members of eigenvalue clusters orthogonalised
+        tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, true, work, Zm);
+        for (int i = tm.tid; i < k; i += tm.nt) evals[i] = theta[i];
         // V = Q_J Z_k
         for (int e = tm.tid; e < N * k; e += tm.nt) {
           const int c = e / N, t = e % N;
-          const int col = ws.pairs[c];
           double s0 = 0.0, s1 = 0.0;
           int i = 0;
           for (; i + 2 <= J; i += 2) {
-            s0 += Q[(int64_t)i * N + t] * Zm[i * J + col];
-            s1 += Q[(int64_t)(i + 1) * N + t] * Zm[(i + 1) * J + col];
+            s0 += Q[(int64_t)i * N + t] * Zm[(int64_t)i * kk + c];
+            s1 += Q[(int64_t)(i + 1) * N + t] * Zm[(int64_t)(i + 1) * kk + c];
           }
-          if (i < J) s0 += Q[(int64_t)i * N + t] * Zm[i * J + col];
+          if (i < J) s0 += Q[(int64_t)i * N + t] * Zm[(int64_t)i * kk + c];
           V[(int64_t)c * N + t] = s0 + s1;
         }
         tm.sync();
-        // renormalise columns
-        for (int c = 0; c < k; ++c) {
+        // renormalise columns, a wave per column
+        for (int c = tm.wave; c < k; c += tm.nwaves) {
+          double* vc = V + (int64_t)c * N;
           double s = 0.0;
-          for (int t = tm.tid; t < N; t += tm.nt) s += V[(int64_t)c * N + t] * V[(int64_t)c * N + t];
-          s = tm.sum(s);
-          const double inv = 1.0 / sqrt(s);
-          for (int t = tm.tid; t < N; t += tm.nt) V[(int64_t)c * N + t] *= inv;
-          tm.sync();
+          for (int t = tm.lane; t < N; t += tm.wsize) s += vc[t] * vc[t];
+          const double inv = 1.0 / sqrt(tm.wave_sum(s));
+          for (int t = tm.lane; t < N; t += tm.wsize) vc[t] *= inv;
         }
+        tm.sync();
         return conv || J == N ? J : -1;
       }
       check = J + (J / 4 > 16 ? J / 4 : 16);
@@ -381,6 +460,7 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
       Q[(int64_t)J * N + t] = v;
     }
     tm.sync();
+    tm.tick(12);
   }
   return -1;
 }
@@ -426,20 +506,15 @@ TLA_HD void reduced_operator(TM& tm, const double* Mfull, int ldm, int N, int k,
         if (c < k) TV[(int64_t)c * N + a] = acc[c];
   }
   tm.sync();
-  for (int e = tm.tid; e < k * k; e += tm.nt) {
+  // At[i][j] = v_i . tv_j / (s_i s_j): a wave per entry, lanes over the long index
+  for (int e = tm.wave; e < k * k; e += tm.nwaves) {
     const int i = e / k, j = e % k;
     const double* vi = V + (int64_t)i * N;
     const double* tj = TV + (int64_t)j * N;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    int a = 0;
-    for (; a + 4 <= N; a += 4) {
-      a0 += vi[a] * tj[a];
-      a1 += vi[a + 1] * tj[a + 1];
-      a2 += vi[a + 2] * tj[a + 2];
-      a3 += vi[a + 3] * tj[a + 3];
-    }
-    for (; a < N; ++a) a0 += vi[a] * tj[a];
-    At[i * k + j] = ((a0 + a1) + (a2 + a3)) / (s[i] * s[j]);
+    double a0 = 0.0;
+    for (int a = tm.lane; a < N; a += tm.wsize) a0 += vi[a] * tj[a];
+    a0 = tm.wave_sum(a0);
+    if (tm.lane == 0) At[i * k + j] = a0 / (s[i] * s[j]);
   }
   tm.sync();
 }
@@ -611,74 +686,100 @@ TLA_HD bool eigvals_general(TM& tm, const double* A, int k, double* H, double* e
   return nev == k;
 }
 
-// Eigenvector of A for eigenvalue lam by three steps of inverse iteration with a
-// complex LU (partial pivoting) of A - lam I, done by one thread.  LU: k*k cpx scratch,
-// b, y: k cpx scratch.  Unit 2-norm result in w.
-TLA_HD inline bool inverse_iteration(const double* A, int k, cpx lam, cpx* LU, cpx* b, cpx* y,
-                                     int* piv, cpx* w) {
+// Eigenvector of the real k x k matrix A for the eigenvalue (lre, lim) by three steps of
+// inverse iteration, done by one wave team: the complex LU with partial pivoting of
+// A - lambda I and the triangular solves are split over the lanes.  LU: k*k, b, y: k
+// complex, piv: k ints.  Unnormalised result in out (column of W).  Returns false when
+// an iterate is zero or not finite.
+template <class TW>
+TLA_HD bool eigvec_wave(TW& wt, const double* A, int k, double lre, double lim, cpx* LU, cpx* b,
+                        cpx* y, int* piv, cpx* out) {
+  const int L = wt.lane, WS = wt.wsize;
   double amax = 0.0;
-  for (int r = 0; r < k; ++r)
-    for (int c = 0; c < k; ++c) {
-      LU[r * k + c] = cmk(A[r * k + c] - (r == c ? lam.re : 0.0), r == c ? -lam.im : 0.0);
-      amax = fmax(amax, cabsv(LU[r * k + c]));
-    }
-  const double tiny = (amax > 1e-300 ? amax : 1e-300) * kEps;
-  for (int j = 0; j < k; ++j) {
-    int p = j;
-    double best = cabsv(LU[j * k + j]);
-    for (int i = j + 1; i < k; ++i) {
-      const double a = cabsv(LU[i * k + j]);
-      if (a > best) best = a, p = i;
-    }
-    piv[j] = p;
-    if (p != j)
-      for (int c = 0; c < k; ++c) {
-        const cpx t = LU[j * k + c];
-        LU[j * k + c] = LU[p * k + c];
-        LU[p * k + c] = t;
-      }
-    if (cabsv(LU[j * k + j]) < tiny) LU[j * k + j] = cmk(tiny, 0.0);
-    for (int i = j + 1; i < k; ++i) {
-      const cpx f = cdiv(LU[i * k + j], LU[j * k + j]);
-      LU[i * k + j] = f;
-      for (int c = j + 1; c < k; ++c) LU[i * k + c] = csub(LU[i * k + c], cmul(f, LU[j * k + c]));
-    }
+  for (int e = L; e < k * k; e += WS) {
+    const int r = e / k, c = e % k;
+    LU[e] = cmk(A[e] - (r == c ? lre : 0.0), r == c ? -lim : 0.0);
+    amax = fmax(amax, cabsv(LU[e]));
   }
-  for (int i = 0; i < k; ++i) b[i] = cmk(1.0, 0.0);
-  for (int it = 0; it < 3; ++it) {
-    for (int j = 0; j < k; ++j)
-      if (piv[j] != j) {
-        const cpx t = b[j];
-        b[j] = b[piv[j]];
-        b[piv[j]] = t;
-      }
-    for (int i = 0; i < k; ++i) {
-      cpx s = b[i];
-      for (int c = 0; c < i; ++c) s = csub(s, cmul(LU[i * k + c], y[c]));
-      y[i] = s;
+  amax = wt.wave_max(amax);
+  wt.sync();
+  const double tiny = (amax > 1e-300 ? amax : 1e-300) * kEps;
+  for (int jj = 0; jj < k; ++jj) {
+    double best = -1.0;
+    int bi = jj;
+    for (int i = jj + L; i < k; i += WS) {
+      const double a = cabsv(LU[i * k + jj]);
+      if (a > best) best = a, bi = i;
     }
-    for (int i = k - 1; i >= 0; --i) {
-      cpx s = y[i];
-      for (int c = i + 1; c < k; ++c) s = csub(s, cmul(LU[i * k + c], y[c]));
-      y[i] = cdiv(s, LU[i * k + i]);
+    wt.wave_argmax(best, bi);
+    if (L == 0) piv[jj] = bi;
+    if (bi != jj)
+      for (int c = L; c < k; c += WS) {
+        const cpx t = LU[jj * k + c];
+        LU[jj * k + c] = LU[bi * k + c];
+        LU[bi * k + c] = t;
+      }
+    wt.sync();
+    cpx pv = LU[jj * k + jj];
+    if (cabsv(pv) < tiny) pv = cmk(tiny, 0.0);
+    wt.sync();
+    if (L == 0) LU[jj * k + jj] = pv;
+    for (int i = jj + 1 + L; i < k; i += WS) {
+      const cpx f = cdiv(LU[i * k + jj], pv);
+      LU[i * k + jj] = f;
+      for (int c = jj + 1; c < k; ++c) LU[i * k + c] = csub(LU[i * k + c], cmul(f, LU[jj * k + c]));
+    }
+    wt.sync();
+  }
+  for (int i = L; i < k; i += WS) b[i] = cmk(1.0, 0.0);
+  wt.sync();
+  bool ok = true;
+  for (int it = 0; it < 3; ++it) {
+    if (L == 0)
+      for (int jj = 0; jj < k; ++jj)
+        if (piv[jj] != jj) {
+          const cpx t = b[jj];
+          b[jj] = b[piv[jj]];
+          b[piv[jj]] = t;
+        }
+    wt.sync();
+    for (int i = L; i < k; i += WS) y[i] = b[i];
+    wt.sync();
+    // forward substitution with the unit lower factor, by columns
+    for (int c = 0; c + 1 < k; ++c) {
+      const cpx yc = y[c];
+      for (int i = c + 1 + L; i < k; i += WS) y[i] = csub(y[i], cmul(LU[i * k + c], yc));
+      wt.sync();
+    }
+    // back substitution with the upper factor, by columns
+    for (int c = k - 1; c >= 0; --c) {
+      const cpx yc = cdiv(y[c], LU[c * k + c]);
+      wt.sync();
+      if (L == 0) y[c] = yc;
+      for (int i = L; i < c; i += WS) y[i] = csub(y[i], cmul(LU[i * k + c], yc));
+      wt.sync();
     }
     double nr = 0.0;
-    for (int i = 0; i < k; ++i) nr += cabs2(y[i]);
-    nr = sqrt(nr);
-    if (!(nr > 0.0) || !(nr < 1e300)) return false;
-    for (int i = 0; i < k; ++i) b[i] = cscale(y[i], 1.0 / nr);
+    for (int i = L; i < k; i += WS) nr += cabs2(y[i]);
+    nr = sqrt(wt.wave_sum(nr));
+    if (!(nr > 0.0 && nr < 1e300)) {
+      ok = false;
+      break;
+    }
+    for (int i = L; i < k; i += WS) b[i] = cscale(y[i], 1.0 / nr);
+    wt.sync();
   }
-  for (int i = 0; i < k; ++i) w[i] = b[i];
-  return true;
+  if (ok)
+    for (int i = L; i < k; i += WS) out[i] = b[i];
+  wt.sync();
+  return ok;
 }
 
-
-// Eigenvectors of the real k x k matrix A for the eigenvalues ev (re, im pairs) by three
-// steps of inverse iteration each, one wave per eigenvalue: the complex LU with partial
-// pivoting of A - lambda I and the triangular solves are split over the wave's lanes,
-// in `region` (fast memory; each active wave needs 2k^2 + 5k doubles; waves take
-// eigenvalues in rounds).  The second member of a conjugate pair is skipped (the caller
-// conjugates its partner).  W: column j at j*k.  Returns false on failure.
+// Eigenvectors of the real k x k matrix A for the eigenvalues ev (re, im pairs): the
+// waves take eigenvalues in turn, each with its own slice of `region` (fast memory,
+// 2k^2 + 5k doubles per wave) and no block-wide synchronisation.  The second member of a
+// conjugate pair is skipped (the caller conjugates its partner).  W: column j at j*k.
+// Returns false on failure.
 template <class TM>
 TLA_HD bool eigvecs_team(TM& tm, const double* A, int k, const double* ev, cpx* W, double* region,
                          int64_t region_doubles, int* flag) {
@@ -688,109 +789,21 @@ TLA_HD bool eigvecs_team(TM& tm, const double* A, int k, const double* ev, cpx* 
   if (wl < 1) return false;
   if (tm.tid == 0) flag[0] = 0;
   tm.sync();
-  const int L = tm.lane, WS = tm.wsize;
-  for (int base = 0; base < k; base += wl) {
-    const int j = base + tm.wave;
-    bool active = tm.wave < wl && j < k;
-    if (active && ev[2 * j + 1] < 0.0 && j > 0 && ev[2 * j - 2] == ev[2 * j] &&
-        ev[2 * j - 1] == -ev[2 * j + 1])
-      active = false;
-    const int wv = tm.wave < wl ? tm.wave : 0;
-    cpx* LU = reinterpret_cast<cpx*>(region + wv * per);
+  if (tm.wave < wl) {
+    auto wt = tm.wave_team();
+    cpx* LU = reinterpret_cast<cpx*>(region + tm.wave * per);
     cpx* b = LU + (int64_t)k * k;
     cpx* y = b + k;
     int* piv = reinterpret_cast<int*>(y + k);
-    const double lre = active ? ev[2 * j] : 0.0, lim = active ? ev[2 * j + 1] : 0.0;
-    double amax = 0.0;
-    if (active)
-      for (int e = L; e < k * k; e += WS) {
-        const int r = e / k, c = e % k;
-        LU[e] = cmk(A[e] - (r == c ? lre : 0.0), r == c ? -lim : 0.0);
-        amax = fmax(amax, cabsv(LU[e]));
-      }
-    amax = tm.wave_max(amax);
-    tm.sync();
-    const double tiny = (amax > 1e-300 ? amax : 1e-300) * kEps;
-    for (int jj = 0; jj < k; ++jj) {
-      double best = -1.0;
-      int bi = jj;
-      if (active)
-        for (int i = jj + L; i < k; i += WS) {
-          const double a = cabsv(LU[i * k + jj]);
-          if (a > best) best = a, bi = i;
-        }
-      tm.wave_argmax(best, bi);
-      if (active && L == 0) piv[jj] = bi;
-      if (active && bi != jj)
-        for (int c = L; c < k; c += WS) {
-          const cpx t = LU[jj * k + c];
-          LU[jj * k + c] = LU[bi * k + c];
-          LU[bi * k + c] = t;
-        }
-      tm.sync();
-      if (active && L == 0 && cabsv(LU[jj * k + jj]) < tiny) LU[jj * k + jj] = cmk(tiny, 0.0);
-      tm.sync();
-      if (active) {
-        const cpx pv = LU[jj * k + jj];
-        for (int i = jj + 1 + L; i < k; i += WS) {
-          const cpx f = cdiv(LU[i * k + jj], pv);
-          LU[i * k + jj] = f;
-          for (int c = jj + 1; c < k; ++c) LU[i * k + c] = csub(LU[i * k + c], cmul(f, LU[jj * k + c]));
-        }
-      }
-      tm.sync();
+    for (int j = tm.wave; j < k; j += wl) {
+      if (ev[2 * j + 1] < 0.0 && j > 0 && ev[2 * j - 2] == ev[2 * j] && ev[2 * j - 1] == -ev[2 * j + 1])
+        continue;
+      if (!eigvec_wave(wt, A, k, ev[2 * j], ev[2 * j + 1], LU, b, y, piv, W + (int64_t)j * k) &&
+          wt.lane == 0)
+        flag[0] = 1;
     }
-    if (active)
-      for (int i = L; i < k; i += WS) b[i] = cmk(1.0, 0.0);
-    tm.sync();
-    for (int it = 0; it < 3; ++it) {
-      if (active && L == 0)
-        for (int jj = 0; jj < k; ++jj)
-          if (piv[jj] != jj) {
-            const cpx t = b[jj];
-            b[jj] = b[piv[jj]];
-            b[piv[jj]] = t;
-          }
-      tm.sync();
-      for (int i = 0; i < k; ++i) {
-        double sr = 0.0, si = 0.0;
-        if (active)
-          for (int c = L; c < i; c += WS) {
-            const cpx pr = cmul(LU[i * k + c], y[c]);
-            sr += pr.re;
-            si += pr.im;
-          }
-        sr = tm.wave_sum(sr);
-        si = tm.wave_sum(si);
-        if (active && L == 0) y[i] = csub(b[i], cmk(sr, si));
-        tm.sync();
-      }
-      for (int i = k - 1; i >= 0; --i) {
-        double sr = 0.0, si = 0.0;
-        if (active)
-          for (int c = i + 1 + L; c < k; c += WS) {
-            const cpx pr = cmul(LU[i * k + c], y[c]);
-            sr += pr.re;
-            si += pr.im;
-          }
-        sr = tm.wave_sum(sr);
-        si = tm.wave_sum(si);
-        if (active && L == 0) y[i] = cdiv(csub(y[i], cmk(sr, si)), LU[i * k + i]);
-        tm.sync();
-      }
-      double nr = 0.0;
-      if (active)
-        for (int i = L; i < k; i += WS) nr += cabs2(y[i]);
-      nr = sqrt(tm.wave_sum(nr));
-      if (active && !(nr > 0.0 && nr < 1e300) && L == 0) flag[0] = 1;
-      if (active && nr > 0.0)
-        for (int i = L; i < k; i += WS) b[i] = cscale(y[i], 1.0 / nr);
-      tm.sync();
-    }
-    if (active)
-      for (int i = L; i < k; i += WS) W[(int64_t)j * k + i] = b[i];
-    tm.sync();
   }
+  tm.sync();
   return flag[0] == 0;
 }
 
@@ -866,9 +879,16 @@ TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int
   reduced_operator(tm, Gr, m, N, k, ws.V, s, ws.TV, ws.At, fastr, fastd);
   tm.stamp(4);
   double* ev = ws.lz.w;  // reuse: 2k doubles
-  if (!eigvals_general(tm, ws.At, k, (int64_t)k * k <= fastd ? fastr : ws.Hs, ev)) return kNumeric;
-  tm.stamp(5);
+  if (tm.tid == 0) ws.flag[0] = 0;
   tm.sync();
+  if (tm.wave == 0) {  // one wave: the QR sweeps are short and strictly sequential
+    auto wt = tm.wave_team();
+    const bool ok = eigvals_general(wt, ws.At, k, (int64_t)k * k <= fastd ? fastr : ws.Hs, ev);
+    if (!ok && wt.lane == 0) ws.flag[0] = 1;
+  }
+  tm.sync();
+  if (ws.flag[0] != 0) return kNumeric;
+  tm.stamp(5);
   for (int j = tm.tid; j < k; j += tm.nt) lam[j] = cmk(ev[2 * j], ev[2 * j + 1]);
   if (!eigvecs_team(tm, ws.At, k, ev, W, fastr, fastd, ws.flag)) return kNumeric;
   for (int j = tm.tid; j < k; j += tm.nt) {
@@ -906,14 +926,13 @@ namespace tla {
 
 // Offsets (in doubles) of the global scratch of one small-LA solve.
 struct SmallLALayout {
-  int64_t Q, T, Z, V, TV, At, Hs, LU, bb, yy, piv, total;
+  int64_t Q, T, V, TV, At, Hs, LU, bb, yy, piv, total;
 };
 TLA_HD inline SmallLALayout small_la_layout(int N, int k, int Jmax) {
   SmallLALayout L;
   int64_t o = 0;
   L.Q = o;  o += (int64_t)(Jmax + 1) * N;
-  L.T = o;  o += (int64_t)Jmax * Jmax;
-  L.Z = o;  o += (int64_t)Jmax * Jmax;
+  L.T = o;  o += (int64_t)Jmax + k + 6 * (int64_t)Jmax * k;
   L.V = o;  o += (int64_t)N * k;
   L.TV = o; o += (int64_t)N * k;
   L.At = o; o += (int64_t)k * k;

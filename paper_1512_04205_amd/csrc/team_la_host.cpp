@@ -13,16 +13,15 @@ int team_small_la_host(const double* Gr, int m, int k, double rtol, int Jmax, do
   const int N = m - 1;
   if (Jmax > N) Jmax = N;
   std::vector<double> q(N), w(N > 2 * k ? N : 2 * k), h(Jmax + 2), alpha(Jmax + 2), beta(Jmax + 2);
-  std::vector<double> T((size_t)Jmax * Jmax), Z((size_t)Jmax * Jmax), scal(8), rot(Jmax + 4);
-  std::vector<int> pairs(2 * (Jmax + 4));
+  std::vector<double> T((size_t)Jmax + k + 6 * (size_t)Jmax * k);
   std::vector<double> Q((size_t)(Jmax + 1) * N), V((size_t)N * k), TV((size_t)N * k), At(k * k), Hs(k * k);
   std::vector<cpx> LU((size_t)k * k * k), bb((size_t)k * k), yy((size_t)k * k);
   std::vector<int> piv((size_t)k * k), flag(1);
   SmallLAWork ws;
-  const int64_t fastd = 2 * (int64_t)Jmax * Jmax + 2 * (int64_t)k * k + 5 * k + 256 * k;
+  const int64_t fastd = 15488;  // as the device's LDS region
   std::vector<double> fast(fastd);
-  ws.lz = LanczosWork{q.data(), w.data(), h.data(), alpha.data(), beta.data(), T.data(), Z.data(),
-                      scal.data(), pairs.data(), rot.data(), fast.data(), fastd};
+  ws.lz = LanczosWork{q.data(), w.data(), h.data(), alpha.data(), beta.data(), T.data(),
+                      fast.data(), fastd};
   ws.Q = Q.data();
   ws.V = V.data();
   ws.TV = TV.data();

@@ -247,3 +247,35 @@ def test_team_small_la_rank_deficient():
     out = [np.zeros(k), np.zeros(k), np.zeros(2 * k), np.zeros(2 * k * k), np.zeros(2 * (m - 1) * k)]
     st = lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1.0, *[_p(o) for o in out], ctypes.byref(ctypes.c_int32()))
     assert st == P.E_RANK_DEFICIENT
+
+
+def test_team_small_la_clustered_spectrum():
+    """Singular values of Y that repeat exactly, or nearly (1e-9 apart), inside the top k:
+    the Lanczos Ritz vectors of a cluster must come out orthonormal, so the Gram
+    eigenvalues are s^2 and the eigenvalues of A~ (which depend only on the invariant
+    subspace of the top k) agree with the oracle's SVD route."""
+    lib = P.load_library()
+    lib.cdmd_dbg_team_small_la.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_double, DP, DP, DP, DP, DP, IP]
+    rng = np.random.default_rng(11)
+    p, m, k = 300, 120, 12
+    N = m - 1
+    s = np.array([40.0, 20.0, 9.0 * (1 + 1e-9), 9.0, 9.0, 6.0, 4.0, 4.0, 3.0, 2.0, 1.5, 1.2]
+                 + list(0.5 * 0.9 ** np.arange(N - 12)))
+    U, _ = np.linalg.qr(rng.standard_normal((p, N)))
+    V, _ = np.linalg.qr(rng.standard_normal((N, N)))
+    Yh = np.empty((p, m))
+    Yh[:, :N] = (U * s) @ V.T
+    Yh[:, N] = Yh[:, :N] @ rng.standard_normal(N) / N
+    Gr = np.ascontiguousarray(Yh.T @ Yh)
+    mu, sig, lam = np.zeros(k), np.zeros(k), np.zeros(2 * k)
+    Wm, G, J = np.zeros(2 * k * k), np.zeros(2 * N * k), ctypes.c_int32()
+    assert lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1.0, _p(mu), _p(sig), _p(lam), _p(Wm),
+                                      _p(G), ctypes.byref(J)) == 0
+    np.testing.assert_allclose(mu, s[:k] ** 2, rtol=1e-11)
+    lam = lam[0::2] + 1j * lam[1::2]
+    lr = R.reduced_operator(Yh, k)[0]
+    from scipy.optimize import linear_sum_assignment
+    C = np.abs(lam[:, None] - lr[None, :])
+    a, b = linear_sum_assignment(C)
+    assert (C[a, b] / np.abs(lr[b]).max()).max() < 1e-9
