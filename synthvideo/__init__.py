@@ -288,3 +288,16 @@ def single_pixel_table(n: int, p: int, seed: int) -> Tuple[np.ndarray, np.ndarra
     rng = np.random.default_rng(seed)
     idx = rng.choice(n, size=p, replace=False).astype(np.int32)[:, None]
     return idx, np.ones((p, 1), dtype=np.int8)
+
+
+def mlp_init(seed: int) -> np.ndarray:
+    """Initial parameters of the 6-64-64-1 selector network as one flat vector in the
+    order W1 (64 x 6), b1, W2 (64 x 64), b2, w3 (64), b3: weights uniform in
+    +-1/sqrt(fan_in), biases zero; float32-representable values in a float64 array."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((6, 64), (64, 64), (64, 1)):
+        lim = 1.0 / np.sqrt(fan_in)
+        parts.append(rng.uniform(-lim, lim, size=fan_in * fan_out))
+        parts.append(np.zeros(fan_out))
+    return np.concatenate(parts).astype(np.float32).astype(np.float64)
