@@ -189,6 +189,58 @@ cdmd_status cdmd_foreground(const cdmd_model* mdl, const void* d_video, float ta
                             int32_t static_bg, int32_t bitpacked, void* d_mask,
                             int64_t* h_counts, void* stream);
 
+/* ---- learned background selector -------------------------------------------------
+   A 6-64-64-1 network with GELU activations (exact erf) maps per-mode features to the
+   logit of "sparse coding selects this mode"; the paper suggests learning the background
+   amplitude profile instead of a fixed rule (discussion in Section "Sparsity-promoting
+   DMD").  Parameters: one flat float32 vector of CDMD_MLP_NPARAM numbers, W1 (64 x 6
+   row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3.  Features of mode j (canonical
+   order, k modes, m frames): |lambda_j|, |arg lambda_j|, log|b_j|, ||phi_j||,
+   (1/m) sum_t |b_j|^2 |lambda_j|^{2t} ||phi_j||^2 / ||x_1||^2, j / k.
+   All pointers named d_* are device memory owned by the caller; work goes on `stream`
+   (NULL = default stream) and the calls return after enqueueing unless stated. */
+#define CDMD_MLP_NPARAM 4673
+
+/* Features of the k modes of the last fit into d_feats (float32, k x 6 row-major).
+   Errors: STATE (not fitted), INVALID_ARG, DEVICE. */
+cdmd_status cdmd_mode_features(const cdmd_model* mdl, float* d_feats, void* stream);
+
+/* Mean binary cross-entropy with logits over n samples (d_X: n x 6, d_y: n labels in
+   {0, 1}) and its gradient with respect to the parameters: d_grad[CDMD_MLP_NPARAM],
+   d_loss[1] (either may be NULL).  Deterministic (fixed-order sums).  Synchronises
+   `stream`.  Errors: INVALID_ARG (n < 1, NULL inputs), OUT_OF_MEMORY, DEVICE. */
+cdmd_status cdmd_mlp_grad(const float* d_params, const float* d_X, const float* d_y, int32_t n,
+                          float* d_grad, float* d_loss, void* stream);
+
+/* `steps` Adam steps (beta1 0.9, beta2 0.999, eps 1e-8, learning rate lr) on batches of
+   `batch` samples: step s uses the rows d_batch_idx[s*batch .. s*batch + batch - 1] of
+   d_X / d_y (n_samples rows; device int32 indices, caller-drawn; an index outside
+   [0, n_samples) contributes nothing).  d_adam_m, d_adam_v: the moment vectors
+   (CDMD_MLP_NPARAM each, zero before the first step); step0: Adam steps already taken
+   (bias correction).  d_losses (optional): the mean batch loss of every step.
+   Synchronises `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+cdmd_status cdmd_mlp_train(float* d_params, float* d_adam_m, float* d_adam_v, const float* d_X,
+                           const float* d_y, int64_t n_samples, const int32_t* d_batch_idx,
+                           int32_t batch, int32_t steps, float lr, int64_t step0, float* d_losses,
+                           void* stream);
+
+/* Logits of n samples (d_X: n x 6) into d_logits; bf16 != 0 rounds weights, inputs and
+   hidden activations to bfloat16 (float32 accumulation).  Errors: INVALID_ARG, DEVICE. */
+cdmd_status cdmd_mlp_forward(const float* d_params, const float* d_X, int32_t n, int32_t bf16,
+                             float* d_logits, void* stream);
+
+/* Learned selection for the last fit: the network (bfloat16 inference) gives each mode a
+   probability p_j; when every mode is confident, max(p_j, 1 - p_j) >= confidence, the
+   support is {j : p_j >= 1/2} with beta refitted by least squares (as EXPLICIT);
+   otherwise, or when that support is empty, orthogonal matching pursuit with K_fallback
+   atoms decides (*used_fallback = 1).  Outputs as cdmd_select; prob (optional, host
+   float64[k]) receives p.  Synchronises `stream`.  Errors: STATE, INVALID_ARG, NUMERIC,
+   DEVICE. */
+cdmd_status cdmd_select_learned(cdmd_model* mdl, const float* d_params, double confidence,
+                                int32_t K_fallback, int32_t* out_idx, int32_t* out_n,
+                                double* out_beta, double* prob, int32_t* used_fallback,
+                                void* stream);
+
 /* Sketch of the last fit, Y^ = C D (p x m), scaled (u/255 for uint8, 1/sqrt(p) for
    Gaussian), host float64, frame-major: element (r, t) at t*p + r.  Optional
    h_int (host int64[p*m]): the exact integer sums of a sparse/single-pixel sketch of

@@ -367,3 +367,16 @@ def run(D: np.ndarray, scale: float, k: int, *, sketch: str, p: int = 0,
     else:
         raise ValueError(selector)
     return Pipeline(mdl, Yhat, S, beta)
+
+
+def f_measure(mask: np.ndarray, gt: np.ndarray) -> float:
+    """F-measure of a foreground mask against ground truth (Section "Results" evaluation:
+    recall TP/(TP+FN), precision TP/(TP+FP), F = 2PR/(P+R)); a zero denominator gives 0."""
+    mask = np.asarray(mask, dtype=bool)
+    gt = np.asarray(gt, dtype=bool)
+    tp = float(np.count_nonzero(mask & gt))
+    fp = float(np.count_nonzero(mask & ~gt))
+    fn = float(np.count_nonzero(~mask & gt))
+    rec = tp / (tp + fn) if tp + fn > 0 else 0.0
+    pre = tp / (tp + fp) if tp + fp > 0 else 0.0
+    return 2 * pre * rec / (pre + rec) if pre + rec > 0 else 0.0

@@ -31,7 +31,10 @@ EXPORTED = [
     "cdmd_select", "cdmd_background", "cdmd_foreground", "cdmd_get_sketch",
     "cdmd_info_get", "cdmd_set_timing", "cdmd_free", "cdmd_dbg_force_valu_lift",
     "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases",
+    "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_forward",
+    "cdmd_select_learned",
 ]
+MLP_NPARAM = 4673
 
 
 class CdmdError(RuntimeError):
@@ -97,6 +100,12 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
     lib.cdmd_dbg_la_phases.argtypes = [P, DP]
+    lib.cdmd_mode_features.argtypes = [P, P, P]
+    lib.cdmd_mlp_grad.argtypes = [P, P, P, I32, P, P, P]
+    lib.cdmd_mlp_train.argtypes = [P, P, P, P, P, I64, P, I32, I32, ctypes.c_float, I64, P, P]
+    lib.cdmd_mlp_forward.argtypes = [P, P, I32, I32, P, P]
+    lib.cdmd_select_learned.argtypes = [P, P, D, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), DP, DP,
+                                        ctypes.POINTER(I32), P]
     lib.cdmd_free.argtypes = [P]
     lib.cdmd_free.restype = None
     for name in EXPORTED:
@@ -218,6 +227,28 @@ class Model:
         ns = nsel.value
         return idx[:ns].copy(), (beta[0::2] + 1j * beta[1::2])[:ns].copy()
 
+    def select_learned(self, params, confidence: float = 0.9, K_fallback: int = 10, stream=None):
+        """Learned selection with the network parameters `params` (device float32 tensor
+        of MLP_NPARAM).  Returns (S, beta, probabilities, used_fallback)."""
+        k = self.k
+        idx = np.zeros(k, dtype=np.int32)
+        beta = np.zeros(2 * k)
+        prob = np.zeros(k)
+        nsel, fb = ctypes.c_int32(0), ctypes.c_int32(0)
+        _check(load_library().cdmd_select_learned(
+            self._h, _tensor_ptr(params, MLP_NPARAM), confidence, K_fallback,
+            idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), ctypes.byref(nsel), _dptr(beta),
+            _dptr(prob), ctypes.byref(fb), _stream(stream)))
+        ns = nsel.value
+        return idx[:ns].copy(), (beta[0::2] + 1j * beta[1::2])[:ns].copy(), prob, bool(fb.value)
+
+    def mode_features(self, out=None, stream=None):
+        """Per-mode features (k x 6 float32 device tensor) of the last fit."""
+        import torch
+        out = torch.empty((self.k, 6), dtype=torch.float32, device="cuda") if out is None else out
+        _check(load_library().cdmd_mode_features(self._h, _tensor_ptr(out, 6 * self.k), _stream(stream)))
+        return out
+
     def background(self, video, L, t0: int = 0, t1: Optional[int] = None, static: bool = False,
                    stream=None):
         t1 = self.m if t1 is None else t1
@@ -265,6 +296,49 @@ class Model:
         inf = Info()
         _check(load_library().cdmd_info_get(self._h, ctypes.byref(inf)))
         return inf.as_dict()
+
+
+def _tensor_ptr(t, numel: int):
+    """Device pointer of a contiguous float32/int32 CUDA tensor of at least `numel` elements."""
+    if not (t.is_cuda and t.is_contiguous() and t.numel() >= numel):
+        raise ValueError("expected a contiguous device tensor with enough elements")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def mlp_grad(params, X, y, stream=None):
+    """Mean loss and gradient of the selector network on (X, y) (device tensors)."""
+    import torch
+    n = X.shape[0]
+    grad = torch.empty(MLP_NPARAM, dtype=torch.float32, device="cuda")
+    loss = torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(load_library().cdmd_mlp_grad(_tensor_ptr(params, MLP_NPARAM), _tensor_ptr(X, 6 * n),
+                                        _tensor_ptr(y, n), n, _tensor_ptr(grad, MLP_NPARAM),
+                                        _tensor_ptr(loss, 1), _stream(stream)))
+    return float(loss.item()), grad
+
+
+def mlp_train(params, adam_m, adam_v, X, y, batch_idx, batch: int, lr: float = 1e-3, step0: int = 0,
+              stream=None):
+    """Adam steps over the batches in batch_idx (device int32, steps x batch); updates
+    params / adam_m / adam_v in place and returns the per-step losses (device)."""
+    import torch
+    steps = batch_idx.numel() // batch
+    losses = torch.empty(max(steps, 1), dtype=torch.float32, device="cuda")
+    _check(load_library().cdmd_mlp_train(
+        _tensor_ptr(params, MLP_NPARAM), _tensor_ptr(adam_m, MLP_NPARAM), _tensor_ptr(adam_v, MLP_NPARAM),
+        _tensor_ptr(X, 6 * X.shape[0]), _tensor_ptr(y, X.shape[0]), X.shape[0],
+        _tensor_ptr(batch_idx, steps * batch), batch, steps,
+        lr, step0, _tensor_ptr(losses, max(steps, 1)), _stream(stream)))
+    return losses[:steps]
+
+
+def mlp_forward(params, X, bf16: bool = False, stream=None):
+    import torch
+    n = X.shape[0]
+    z = torch.empty(max(n, 1), dtype=torch.float32, device="cuda")
+    _check(load_library().cdmd_mlp_forward(_tensor_ptr(params, MLP_NPARAM), _tensor_ptr(X, 6 * n), n,
+                                           int(bf16), _tensor_ptr(z, max(n, 1)), _stream(stream)))
+    return z[:n]
 
 
 def mask_words(n: int) -> int:

@@ -30,6 +30,8 @@ HOST = ["-x", "c++", "-march=x86-64-v3", "-D__HIP_PLATFORM_AMD__", "-I", "/opt/r
 
 SOURCES = [
     ("kernels.hip", DEVICE),
+    ("sketch_gauss.hip", DEVICE),
+    ("mlp.hip", DEVICE),
     ("api.cpp", HOST),
     ("smallla.cpp", HOST),
     ("team_la_host.cpp", HOST),

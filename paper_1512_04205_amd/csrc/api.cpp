@@ -84,6 +84,9 @@ struct cdmd_model {
   int32_t* d_Yint = nullptr;
   int32_t* d_Ypart = nullptr;
   double* d_Yd = nullptr;
+  bool gauss = false;               // dense Gaussian sketch
+  cdmd::k::GaussPlan gplan{};
+  float* d_gpart = nullptr;         // per-slice partial sketches
   double* d_gram = nullptr;
   // lift
   bool lift_mfma = false;   // MFMA path (uint8 video, 16-byte aligned frames)
@@ -102,6 +105,9 @@ struct cdmd_model {
   float* d_Gs = nullptr;
   float* d_Vc = nullptr;
   int64_t* d_counts = nullptr;
+  double* d_modes = nullptr;   // lam[2k], b[2k], phi norms[k] for the feature kernel
+  float* d_feats = nullptr;    // k x 6
+  float* d_logits = nullptr;   // k
   // pinned host staging
   double* h_gram = nullptr;
   float* h_G = nullptr;
@@ -145,8 +151,9 @@ struct cdmd_model {
   ~cdmd_model() {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
-    void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd,
-                   d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts,
+    void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart,
+                   d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts, d_modes,
+                   d_feats, d_logits,
                    d_la_scratch, d_la_out};
     for (void* q : dev)
       if (q) (void)hipFree(q);
@@ -204,10 +211,16 @@ cdmd_status validate(const cdmd_config* c) {
   }
   if (c->k > 40) return fail(CDMD_E_UNSUPPORTED, "k > 40 is not built");
   if (c->n >= (int64_t)1 << 31) return fail(CDMD_E_UNSUPPORTED, "n >= 2^31 pixels is not built");
-  if (c->sketch == CDMD_SKETCH_GAUSSIAN)
-    return fail(CDMD_E_UNSUPPORTED, "dense Gaussian sketch is not built in this library version");
-  if (c->sketch_prec != CDMD_PREC_FP32)
-    return fail(CDMD_E_UNSUPPORTED, "only the FP32 sketch form is built for sparse sketches");
+  if (c->sketch == CDMD_SKETCH_GAUSSIAN) {
+    if (c->sketch_prec == CDMD_PREC_FP8)
+      return fail(CDMD_E_UNSUPPORTED, "the FP8 Gaussian sketch is not built in this library version");
+    if (c->sketch_prec == CDMD_PREC_BF16 && (c->dtype != CDMD_U8 || c->ld % 16 != 0))
+      return fail(CDMD_E_UNSUPPORTED, "the BF16 Gaussian sketch needs a uint8 video with ld % 16 == 0");
+    if ((int64_t)c->p * c->m > ((int64_t)1 << 31))
+      return fail(CDMD_E_UNSUPPORTED, "p * m >= 2^31 is not built");
+  } else if (c->sketch_prec != CDMD_PREC_FP32) {
+    return fail(CDMD_E_UNSUPPORTED, "sparse and single-pixel sketches are exact: sketch precision must be FP32");
+  }
   if (c->lift_prec == CDMD_PREC_BF16 && (c->dtype != CDMD_U8 || c->ld % 16 != 0))
     return fail(CDMD_E_UNSUPPORTED, "the BF16 lift needs a uint8 video with ld % 16 == 0");
   // table contents
@@ -363,7 +376,14 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool to_host) {
   const cdmd_config& c = M->cfg;
   M->mark(0, st);
-  if (c.dtype == CDMD_U8) {
+  if (M->gauss) {
+    if (c.sketch_prec == CDMD_PREC_BF16 && (reinterpret_cast<uintptr_t>(d_video) & 15) != 0)
+      return fail(CDMD_E_UNSUPPORTED, "the BF16 Gaussian sketch needs a 16-byte aligned video");
+    HIPCHK(cdmd::k::sketch_gauss(d_video, c.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p, c.seed,
+                                 c.sketch_prec == CDMD_PREC_BF16 ? 1 : 0, M->gplan, M->d_gpart, M->d_Yd, st));
+    M->mark(1, st);
+    HIPCHK(cdmd::k::gram_f64(M->d_Yd, M->p, M->m, M->d_gram, st));
+  } else if (c.dtype == CDMD_U8) {
     int32_t* out = M->nslot > 1 ? M->d_Ypart : M->d_Yint;
     HIPCHK(cdmd::k::sketch_sparse_u8((const uint8_t*)d_video, M->ld, M->m, M->d_tri_pix, M->d_tri_rs,
                                      M->d_seg, M->nseg, M->p, M->max_rows, M->fpb, out, M->nslot, st));
@@ -665,7 +685,12 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
   M->info.warn_few_samples =
       (double)cfg->p < (double)cfg->k * std::log((double)cfg->n / (double)cfg->k) ? 1 : 0;
   const int64_t m = M->m, p = M->p;
-  if (cfg->dtype == CDMD_U8) {
+  if (cfg->sketch == CDMD_SKETCH_GAUSSIAN) {
+    M->gauss = true;
+    M->gplan = cdmd::k::gauss_plan(M->n, m, (int)p, cfg->sketch_prec == CDMD_PREC_BF16 ? 1 : 0);
+    TRY(dalloc(&M->d_gpart, (size_t)M->gplan.nsplit * m * p));
+    TRY(dalloc(&M->d_Yd, (size_t)m * p));
+  } else if (cfg->dtype == CDMD_U8) {
     TRY(build_sparse_plan(M));
     TRY(dalloc(&M->d_Yint, (size_t)m * p));
     if (M->nslot > 1) TRY(dalloc(&M->d_Ypart, (size_t)M->nslot * m * p));
@@ -723,6 +748,9 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
   TRY(dalloc(&M->d_Vc, (size_t)m * 80));
   TRY(halloc(&M->h_Vc, (size_t)m * 80));
   TRY(dalloc(&M->d_counts, (size_t)m));
+  TRY(dalloc(&M->d_modes, (size_t)5 * M->k));
+  TRY(dalloc(&M->d_feats, (size_t)6 * M->k));
+  TRY(dalloc(&M->d_logits, (size_t)M->k));
   TRY(halloc(&M->h_counts, (size_t)m));
   guard.keep = true;
   *out = M;
@@ -1042,13 +1070,122 @@ cdmd_status cdmd_foreground(const cdmd_model* Mc, const void* d_video, float tau
   return CDMD_OK;
 }
 
+// ------------------------------------------------------------------ learned selector
+static cdmd_status upload_mode_features(const cdmd_model* M, hipStream_t st) {
+  const int k = M->k;
+  std::vector<double> h((size_t)5 * k);
+  for (int j = 0; j < k; ++j) {
+    h[2 * j] = M->lam[j].real();
+    h[2 * j + 1] = M->lam[j].imag();
+    h[2 * k + 2 * j] = M->b[j].real();
+    h[2 * k + 2 * j + 1] = M->b[j].imag();
+    h[4 * k + j] = M->phinorm[j];
+  }
+  HIPCHK(hipMemcpyAsync(M->d_modes, h.data(), sizeof(double) * h.size(), hipMemcpyHostToDevice, st));
+  HIPCHK(cdmd::k::mode_features(M->d_modes, M->d_modes + 2 * k, M->d_modes + 4 * k, M->x1n2, M->m, k,
+                                M->d_feats, st));
+  // the host vector must outlive the copy
+  HIPCHK(hipStreamSynchronize(st));
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_mode_features(const cdmd_model* M, float* d_feats, void* stream) {
+  g_err.clear();
+  if (!M || !d_feats) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  if (!M->fitted) return fail(CDMD_E_STATE, "model is not fitted");
+  hipStream_t st = as_stream(stream);
+  TRY(upload_mode_features(M, st));
+  HIPCHK(hipMemcpyAsync(d_feats, M->d_feats, sizeof(float) * 6 * M->k, hipMemcpyDeviceToDevice, st));
+  return CDMD_OK;
+}
+
+namespace {
+struct DevBuf {
+  void* p = nullptr;
+  ~DevBuf() {
+    if (p) (void)hipFree(p);
+  }
+};
+}  // namespace
+
+cdmd_status cdmd_mlp_grad(const float* d_params, const float* d_X, const float* d_y, int32_t n,
+                          float* d_grad, float* d_loss, void* stream) {
+  g_err.clear();
+  if (!d_params || !d_X || !d_y || n < 1) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  hipStream_t st = as_stream(stream);
+  const int np = cdmd::k::mlp_nparts(n);
+  DevBuf part, lpart;
+  HIPCHK(hipMalloc(&part.p, sizeof(float) * (size_t)np * CDMD_MLP_NPARAM));
+  HIPCHK(hipMalloc(&lpart.p, sizeof(float) * (size_t)np));
+  HIPCHK(cdmd::k::mlp_grad(d_params, d_X, d_y, nullptr, n, (float*)part.p, (float*)lpart.p, d_grad, d_loss, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_mlp_train(float* d_params, float* d_adam_m, float* d_adam_v, const float* d_X,
+                           const float* d_y, int64_t n_samples, const int32_t* d_batch_idx,
+                           int32_t batch, int32_t steps, float lr, int64_t step0, float* d_losses,
+                           void* stream) {
+  g_err.clear();
+  if (!d_params || !d_adam_m || !d_adam_v || !d_X || !d_y || !d_batch_idx || batch < 1 || steps < 0 ||
+      step0 < 0 || n_samples < 1 || !(lr > 0.0f))
+    return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  hipStream_t st = as_stream(stream);
+  const int np = cdmd::k::mlp_nparts(batch);
+  DevBuf part, lpart;
+  HIPCHK(hipMalloc(&part.p, sizeof(float) * (size_t)np * CDMD_MLP_NPARAM));
+  HIPCHK(hipMalloc(&lpart.p, sizeof(float) * (size_t)np));
+  HIPCHK(cdmd::k::mlp_train(d_params, d_adam_m, d_adam_v, d_X, d_y, n_samples, d_batch_idx, batch, steps, lr, step0,
+                            (float*)part.p, (float*)lpart.p, d_losses, st));
+  HIPCHK(hipStreamSynchronize(st));
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_mlp_forward(const float* d_params, const float* d_X, int32_t n, int32_t bf16,
+                             float* d_logits, void* stream) {
+  g_err.clear();
+  if (!d_params || !d_X || !d_logits || n < 0) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  HIPCHK(cdmd::k::mlp_forward(d_params, d_X, n, bf16 != 0, d_logits, as_stream(stream)));
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_select_learned(cdmd_model* M, const float* d_params, double confidence,
+                                int32_t K_fallback, int32_t* out_idx, int32_t* out_n,
+                                double* out_beta, double* prob, int32_t* used_fallback,
+                                void* stream) {
+  g_err.clear();
+  if (!M || !d_params) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  if (!M->fitted) return fail(CDMD_E_STATE, "model is not fitted");
+  if (!(confidence >= 0.5 && confidence <= 1.0)) return fail(CDMD_E_INVALID_ARG, "confidence must be in [0.5, 1]");
+  if (K_fallback < 1) return fail(CDMD_E_INVALID_ARG, "K_fallback must be >= 1");
+  hipStream_t st = as_stream(stream);
+  const int k = M->k;
+  TRY(upload_mode_features(M, st));
+  HIPCHK(cdmd::k::mlp_forward(d_params, M->d_feats, k, 1, M->d_logits, st));
+  std::vector<float> z(k);
+  HIPCHK(hipMemcpyAsync(z.data(), M->d_logits, sizeof(float) * k, hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  std::vector<int32_t> S;
+  bool confident = true;
+  for (int j = 0; j < k; ++j) {
+    const double pj = 1.0 / (1.0 + std::exp(-(double)z[j]));
+    if (prob) prob[j] = pj;
+    if (std::max(pj, 1.0 - pj) < confidence) confident = false;
+    if (pj >= 0.5) S.push_back(j);
+  }
+  const bool fb = !confident || S.empty();
+  if (used_fallback) *used_fallback = fb ? 1 : 0;
+  if (fb) return cdmd_select(M, CDMD_SEL_OMP, K_fallback, 0.0, nullptr, 0, out_idx, out_n, out_beta);
+  return cdmd_select(M, CDMD_SEL_EXPLICIT, 0, 0.0, S.data(), (int32_t)S.size(), out_idx, out_n, out_beta);
+}
+
 cdmd_status cdmd_get_sketch(const cdmd_model* Mc, double* h_Y, int64_t* h_int) {
   g_err.clear();
   if (!Mc) return fail(CDMD_E_INVALID_ARG, "NULL model");
   const cdmd_model* M = Mc;
   if (!M->fitted) return fail(CDMD_E_STATE, "model is not fitted");
   const size_t cnt = (size_t)M->m * M->p;
-  if (M->cfg.dtype == CDMD_U8) {
+  if (M->cfg.dtype == CDMD_U8 && !M->gauss) {
     std::vector<int32_t> tmp(cnt);
     HIPCHK(hipMemcpy(tmp.data(), M->d_Yint, cnt * 4, hipMemcpyDeviceToHost));
     for (size_t i = 0; i < cnt; ++i) {
@@ -1056,7 +1193,7 @@ cdmd_status cdmd_get_sketch(const cdmd_model* Mc, double* h_Y, int64_t* h_int) {
       if (h_int) h_int[i] = tmp[i];
     }
   } else {
-    if (h_int) return fail(CDMD_E_INVALID_ARG, "integer sums exist only for uint8 sparse sketches");
+    if (h_int) return fail(CDMD_E_INVALID_ARG, "integer sums exist only for sparse sketches of uint8 videos");
     std::vector<double> tmp(cnt);
     HIPCHK(hipMemcpy(tmp.data(), M->d_Yd, cnt * 8, hipMemcpyDeviceToHost));
     for (size_t i = 0; i < cnt; ++i)

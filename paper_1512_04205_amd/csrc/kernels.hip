@@ -923,6 +923,12 @@ struct WaveTeam {
   __device__ double sum(double v) { return wave_sum(v); }
   __device__ double maxv(double v) { return wave_max(v); }
   __device__ WaveTeam wave_team() { return *this; }
+  // 1/x from the hardware estimate and two Newton steps (x normal and finite)
+  __device__ double recip(double x) {
+    double r = __builtin_amdgcn_rcp(x);
+    r = fma(r, fma(-x, r, 1.0), r);
+    return fma(r, fma(-x, r, 1.0), r);
+  }
 };
 
 struct DevTeam : WaveTeam {

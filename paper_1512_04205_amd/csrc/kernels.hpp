@@ -30,6 +30,32 @@ hipError_t sketch_sparse_f32(const float* D, int64_t ld, int64_t m, const int32_
                              const int8_t* sign, int p, int nnz, double* Y,
                              hipStream_t stream);
 
+// ----- sketch, dense Gaussian (entries drawn on the fly) --------------------------
+// prec 0: FP32 form (float64 Box-Muller rounded to float32, FP32 MFMA; dtype 0 uint8 or
+// 1 float32 video); prec 1: BF16 form (float32 Box-Muller rounded to bfloat16, BF16
+// MFMA; uint8 video with 16-byte aligned frames only).  part: nsplit * m * p floats of
+// per-slice partial sums; Y[t][r] = (1/sqrt(p)) * sum over slices (float64, m x p).
+struct GaussPlan {
+  int nrt, nft, nsplit, frames;
+  int64_t pps, blocks;
+};
+GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec);
+hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, int p,
+                        uint64_t seed, int prec, const GaussPlan& g, float* part, double* Y,
+                        hipStream_t stream);
+
+// ----- learned selector (mlp.hip) -------------------------------------------------
+int mlp_nparts(int batch);
+// grad / loss (either may be null) of the mean loss over nb samples (rows idx[q], or q)
+hipError_t mlp_grad(const float* th, const float* X, const float* y, const int32_t* idx, int nb, float* part,
+                    float* lpart, float* grad, float* loss, hipStream_t stream);
+hipError_t mlp_train(float* th, float* am, float* av, const float* X, const float* y, int64_t nsamp,
+                     const int32_t* idx, int batch, int steps, float lr, int64_t t0, float* part, float* lpart,
+                     float* losses, hipStream_t stream);
+hipError_t mlp_forward(const float* th, const float* X, int n, int round_bf16, float* logits, hipStream_t stream);
+hipError_t mode_features(const double* lam, const double* b, const double* phin, double x1n2, int64_t m, int k,
+                         float* F, hipStream_t stream);
+
 // ----- Gram of the sketch: Gr[a][b] = sum_r Y[a][r] Y[b][r] (m x m, float64) ------
 hipError_t gram_i32(const int32_t* Y, int p, int64_t m, double* Gr, hipStream_t stream);
 hipError_t gram_f64(const double* Y, int p, int64_t m, double* Gr, hipStream_t stream);

@@ -1,0 +1,434 @@
+// Dense Gaussian sketch Y^ = C X (Algorithm 1 step 1 with a Gaussian measurement matrix,
+// Section "Measurement Matrices"), C never stored: every entry is a pure function of
+// (seed, row, pixel), drawn by the workgroup that needs it.
+//
+// Entry definition: for row r and pixel j, Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
+// SC'11) with key (seed mod 2^32, seed >> 32) on the counter (j >> 2, r, 0, 0) gives four
+// words w0..w3; u = (w + 1) 2^-32; Box-Muller on (w0, w1) gives the normals of pixels
+// 4(j >> 2) + 0, 1 and on (w2, w3) those of + 2, 3.  The sums are scaled by 1/sqrt(p)
+// after accumulation.
+//
+// Forms:
+//  * FP32: the normals are computed in float64 and rounded once to float32; products on
+//    FP32 MFMA (16x16x4), float32 accumulation inside a workgroup's pixel slice, float64
+//    across slices.
+//  * BF16: the normals are computed in float32 with the hardware log/sqrt/sin/cos and
+//    rounded to bfloat16 (ties to even); uint8 pixels are exact in bfloat16; products on
+//    BF16 MFMA (32x32x16) with float32 accumulation, float64 across slices.
+//
+// Work split: a workgroup owns 64 sketch rows x a tile of frames x a slice of pixels.
+// It draws its 64-row C tile once per pixel step into LDS (each entry drawn once per
+// frame tile) and reads the video bytes straight into MFMA operands.  Block b serves
+// (slice, frame tile) combination b mod combos and row tile b / combos, so the row tiles
+// of one combination run on one XCD (blocks are dealt to the XCDs in turn) and share
+// its video tiles through that XCD's L2.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.hpp"
+
+namespace cdmd {
+namespace k {
+
+namespace {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+struct Words4 {
+  uint32_t w0, w1, w2, w3;
+};
+
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1) {
+  uint32_t c2 = 0u, c3 = 0u;
+#pragma unroll
+  for (int rnd = 0; rnd < 10; ++rnd) {
+    if (rnd) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c1 = (uint32_t)p1;
+    c3 = (uint32_t)p0;
+    c0 = n0;
+    c2 = n2;
+  }
+  return Words4{c0, c1, c2, c3};
+}
+
+// Box-Muller in float64, each normal rounded once to float32
+__device__ __forceinline__ void box_muller_f64(uint32_t wa, uint32_t wb, float& z0, float& z1) {
+  const double u1 = ((double)wa + 1.0) * 0x1p-32;
+  const double u2 = ((double)wb + 1.0) * 0x1p-32;
+  const double r = sqrt(-2.0 * log(u1));
+  const double ang = (2.0 * 3.141592653589793) * u2;
+  z0 = (float)(r * cos(ang));
+  z1 = (float)(r * sin(ang));
+}
+
+// Box-Muller in float32 with the hardware transcendentals (v_log_f32 is log2,
+// v_sin_f32 / v_cos_f32 take the angle in turns)
+__device__ __forceinline__ void box_muller_f32(uint32_t wa, uint32_t wb, float& z0, float& z1) {
+  const float u1 = ((float)wa + 1.0f) * 0x1p-32f;
+  const float u2 = ((float)wb + 1.0f) * 0x1p-32f;
+  const float r = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+  z0 = r * __builtin_amdgcn_cosf(u2);
+  z1 = r * __builtin_amdgcn_sinf(u2);
+}
+
+__device__ __forceinline__ uint32_t bf16_bits_rne(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return u >> 16;
+}
+
+// 8 bytes (pixels 0..7, little-endian) -> 8 exact bfloat16
+__device__ __forceinline__ bf16x8_t u8x8_to_bf16(uint32_t lo, uint32_t hi) {
+  uint32_t q[4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const uint32_t v = i ? hi : lo;
+    const uint32_t b0 = __float_as_uint((float)(v & 0xffu)) >> 16;
+    const uint32_t b1 = __float_as_uint((float)((v >> 8) & 0xffu)) & 0xffff0000u;
+    const uint32_t b2 = __float_as_uint((float)((v >> 16) & 0xffu)) >> 16;
+    const uint32_t b3 = __float_as_uint((float)(v >> 24)) & 0xffff0000u;
+    q[2 * i] = b0 | b1;
+    q[2 * i + 1] = b2 | b3;
+  }
+  return __builtin_bit_cast(bf16x8_t, make_uint4(q[0], q[1], q[2], q[3]));
+}
+
+// ------------------------------------------------------------------------ BF16 form
+constexpr int GB_ROWS = 64;  // sketch rows per workgroup (2 MFMA row blocks)
+constexpr int GB_KT = 32;    // pixels per step (2 MFMA k-steps)
+constexpr int GB_AS = 40;    // LDS row stride of the C tile (bf16 elements)
+
+// NFB: 32-frame blocks per wave (frames per workgroup = 128 NFB).  Video: uint8,
+// frames 16-byte aligned (ld % 16 == 0, aligned base).  K order inside a step: lane half h
+// of a wave reads pixels [16h, 16h + 16) of its frame with one 16-byte load; k-step ks
+// takes pixels 16h + 8ks + (0..7).  The C tile uses the same order.
+template <int NFB>
+__global__ __launch_bounds__(256) void k_sketch_gauss_bf16(const uint8_t* __restrict__ D, int64_t ld,
+                                                          int64_t n, int64_t m, int p, uint64_t seed,
+                                                          int64_t pps, int nft, int nsplit,
+                                                          float* __restrict__ part) {
+  constexpr int FRAMES = 128 * NFB;
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][GB_ROWS * GB_AS];
+  const int combos = nft * nsplit;
+  const int cidx = blockIdx.x % combos, rt = blockIdx.x / combos;
+  const int s = cidx / nft, ft = cidx % nft;
+  const int r0 = rt * GB_ROWS;
+  const int64_t t0 = (int64_t)ft * FRAMES;
+  const int64_t jb = (int64_t)s * pps;
+  int64_t je = jb + pps;
+  if (je > n) je = n;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int h = l >> 5, lc = l & 31;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  // drawing role: row gr, pixels 8 gg .. 8 gg + 7 of the step
+  const int gr = tid >> 2, gg = tid & 3;
+  const int grow = r0 + gr;
+
+  auto draw = [&](int buf, int64_t j0) {
+    const int64_t j = j0 + 8 * gg;
+    uint32_t q[4] = {0u, 0u, 0u, 0u};
+    if (grow < p && j < je) {
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const Words4 wd = philox4x32_10((uint32_t)((j >> 2) + half), (uint32_t)grow, k0, k1);
+        float z[4];
+        box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
+        box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (j + 4 * half + e >= je) z[e] = 0.f;
+        q[2 * half] = bf16_bits_rne(z[0]) | (bf16_bits_rne(z[1]) << 16);
+        q[2 * half + 1] = bf16_bits_rne(z[2]) | (bf16_bits_rne(z[3]) << 16);
+      }
+    }
+    // row gr, pixels 8 gg .. +7 -> stored at their k position (identity: 8 gg is
+    // 16 h + 8 ks with h = gg / 2, ks = gg % 2)
+    *reinterpret_cast<uint4*>(&sA[buf][gr * GB_AS + 8 * gg]) = make_uint4(q[0], q[1], q[2], q[3]);
+  };
+
+  // this lane's frames: t0 + 32 NFB w + 32 fb + lc (wave w owns 32 NFB frames)
+  uint4 bcur[NFB], bnext[NFB];
+  auto load_b = [&](uint4* dst, int64_t j0) {
+    const int64_t j = j0 + 16 * h;
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb) {
+      const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
+      uint4 v = make_uint4(0u, 0u, 0u, 0u);
+      if (t < m && j < je) {
+        const uint8_t* src = D + t * ld + j;
+        if (j + 16 <= je) {
+          v = *reinterpret_cast<const uint4*>(src);
+        } else {
+          uint32_t wv[4] = {0u, 0u, 0u, 0u};
+          for (int e = 0; e < 16 && j + e < je; ++e) wv[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+          v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        }
+      }
+      dst[fb] = v;
+    }
+  };
+
+  f32x16_t acc[2][NFB];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[rb][fb][e] = 0.f;
+
+  const int64_t nsteps = je > jb ? (je - jb + GB_KT - 1) / GB_KT : 0;
+  if (nsteps > 0) {
+    draw(0, jb);
+    load_b(bcur, jb);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const int buf = (int)(st & 1);
+    const int64_t jn = jb + (st + 1) * GB_KT;
+    const bool more = st + 1 < nsteps;
+    if (more) load_b(bnext, jn);
+#pragma unroll
+    for (int ks = 0; ks < 2; ++ks) {
+      bf16x8_t a[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+        a[rb] = *reinterpret_cast<const bf16x8_t*>(&sA[buf][(32 * rb + lc) * GB_AS + 16 * h + 8 * ks]);
+#pragma unroll
+      for (int fb = 0; fb < NFB; ++fb) {
+        const bf16x8_t b = ks ? u8x8_to_bf16(bcur[fb].z, bcur[fb].w) : u8x8_to_bf16(bcur[fb].x, bcur[fb].y);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb)
+          acc[rb][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b, acc[rb][fb], 0, 0, 0);
+      }
+    }
+    if (more) draw(buf ^ 1, jn);
+    __syncthreads();
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb) bcur[fb] = bnext[fb];
+  }
+  // accumulators: lane l, register e -> row 32 rb + 8 (e / 4) + 4 h + e % 4, frame lc
+  float* out = part + (int64_t)s * m * p;
+#pragma unroll
+  for (int fb = 0; fb < NFB; ++fb) {
+    const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
+    if (t >= m) continue;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int r = r0 + 32 * rb + 8 * (e >> 2) + 4 * h + (e & 3);
+        if (r < p) out[t * p + r] = acc[rb][fb][e];
+      }
+  }
+}
+
+// ------------------------------------------------------------------------ FP32 form
+constexpr int GF_ROWS = 64;  // sketch rows per workgroup (4 MFMA row blocks of 16)
+constexpr int GF_KT = 16;    // pixels per step (4 MFMA k-steps)
+constexpr int GF_AS = 20;    // LDS row stride of the C tile (floats)
+
+// Each wave: 64 rows x 64 frames (16 accumulator blocks of 16 x 16); workgroup 256
+// frames.  K order inside a step: lane quarter q (= l / 16) reads pixels 4q .. 4q + 3 of
+// its frame; k-step ks takes pixel 4q + ks.  Tin: uint8 (raw 0..255) or float.
+template <typename Tin, bool VEC>
+__global__ __launch_bounds__(256) void k_sketch_gauss_f32(const Tin* __restrict__ D, int64_t ld,
+                                                         int64_t n, int64_t m, int p, uint64_t seed,
+                                                         int64_t pps, int nft, int nsplit,
+                                                         float* __restrict__ part) {
+  constexpr int FRAMES = 256;
+  __shared__ __attribute__((aligned(16))) float sA[2][GF_ROWS * GF_AS];
+  const int combos = nft * nsplit;
+  const int cidx = blockIdx.x % combos, rt = blockIdx.x / combos;
+  const int s = cidx / nft, ft = cidx % nft;
+  const int r0 = rt * GF_ROWS;
+  const int64_t t0 = (int64_t)ft * FRAMES;
+  const int64_t jb = (int64_t)s * pps;
+  int64_t je = jb + pps;
+  if (je > n) je = n;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int q = l >> 4, lc = l & 15;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const int gr = tid >> 2, gg = tid & 3;
+  const int grow = r0 + gr;
+
+  auto draw = [&](int buf, int64_t j0) {
+    const int64_t j = j0 + 4 * gg;
+    float z[4] = {0.f, 0.f, 0.f, 0.f};
+    if (grow < p && j < je) {
+      const Words4 wd = philox4x32_10((uint32_t)(j >> 2), (uint32_t)grow, k0, k1);
+      box_muller_f64(wd.w0, wd.w1, z[0], z[1]);
+      box_muller_f64(wd.w2, wd.w3, z[2], z[3]);
+#pragma unroll
+      for (int e = 0; e < 4; ++e)
+        if (j + e >= je) z[e] = 0.f;
+    }
+    *reinterpret_cast<float4*>(&sA[buf][gr * GF_AS + 4 * gg]) = make_float4(z[0], z[1], z[2], z[3]);
+  };
+
+  float4 bcur[4], bnext[4];
+  auto load_b = [&](float4* dst, int64_t j0) {
+    const int64_t j = j0 + 4 * q;
+#pragma unroll
+    for (int fb = 0; fb < 4; ++fb) {
+      const int64_t t = t0 + 64 * w + 16 * fb + lc;
+      float v[4] = {0.f, 0.f, 0.f, 0.f};
+      if (t < m && j < je) {
+        const Tin* src = D + t * ld + j;
+        if (VEC && j + 4 <= je) {
+          if constexpr (sizeof(Tin) == 1) {
+            const uint32_t u = *reinterpret_cast<const uint32_t*>(src);
+#pragma unroll
+            for (int e = 0; e < 4; ++e) v[e] = (float)((u >> (8 * e)) & 0xffu);
+          } else {
+            const float4 f = *reinterpret_cast<const float4*>(src);
+            v[0] = f.x;
+            v[1] = f.y;
+            v[2] = f.z;
+            v[3] = f.w;
+          }
+        } else {
+          for (int e = 0; e < 4 && j + e < je; ++e) v[e] = (float)src[e];
+        }
+      }
+      dst[fb] = make_float4(v[0], v[1], v[2], v[3]);
+    }
+  };
+
+  f32x4_t acc[4][4];
+#pragma unroll
+  for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+    for (int fb = 0; fb < 4; ++fb) acc[rb][fb] = f32x4_t{0.f, 0.f, 0.f, 0.f};
+
+  const int64_t nsteps = je > jb ? (je - jb + GF_KT - 1) / GF_KT : 0;
+  if (nsteps > 0) {
+    draw(0, jb);
+    load_b(bcur, jb);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const int buf = (int)(st & 1);
+    const int64_t jn = jb + (st + 1) * GF_KT;
+    const bool more = st + 1 < nsteps;
+    if (more) load_b(bnext, jn);
+    float4 a[4];
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb) a[rb] = *reinterpret_cast<const float4*>(&sA[buf][(16 * rb + lc) * GF_AS + 4 * q]);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+      for (int fb = 0; fb < 4; ++fb) {
+        const float b = ks == 0 ? bcur[fb].x : ks == 1 ? bcur[fb].y : ks == 2 ? bcur[fb].z : bcur[fb].w;
+#pragma unroll
+        for (int rb = 0; rb < 4; ++rb) {
+          const float av = ks == 0 ? a[rb].x : ks == 1 ? a[rb].y : ks == 2 ? a[rb].z : a[rb].w;
+          acc[rb][fb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, b, acc[rb][fb], 0, 0, 0);
+        }
+      }
+    if (more) draw(buf ^ 1, jn);
+    __syncthreads();
+#pragma unroll
+    for (int fb = 0; fb < 4; ++fb) bcur[fb] = bnext[fb];
+  }
+  // accumulators: lane l, register e -> row 16 rb + 4 q + e, frame lc
+  float* out = part + (int64_t)s * m * p;
+#pragma unroll
+  for (int fb = 0; fb < 4; ++fb) {
+    const int64_t t = t0 + 64 * w + 16 * fb + lc;
+    if (t >= m) continue;
+#pragma unroll
+    for (int rb = 0; rb < 4; ++rb)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int r = r0 + 16 * rb + 4 * q + e;
+        if (r < p) out[t * p + r] = acc[rb][fb][e];
+      }
+  }
+}
+
+// Y[t][r] = scale * sum_s part[s][t][r], float64, slices in order
+__global__ __launch_bounds__(256) void k_reduce_gauss(const float* __restrict__ part, int nsplit,
+                                                     int64_t count, double scale, double* __restrict__ Y) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    double acc = 0.0;
+    for (int s = 0; s < nsplit; ++s) acc += (double)part[(int64_t)s * count + e];
+    Y[e] = acc * scale;
+  }
+}
+
+}  // namespace
+
+GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec) {
+  GaussPlan g{};
+  const bool bf = prec == 1;
+  const int rows = bf ? GB_ROWS : GF_ROWS;
+  const int kt = bf ? GB_KT : GF_KT;
+  int frames = 256;
+  if (bf) frames = m <= 128 ? 128 : m <= 256 ? 256 : 512;
+  g.frames = frames;
+  g.nrt = (p + rows - 1) / rows;
+  g.nft = (int)((m + frames - 1) / frames);
+  // about four workgroups per compute unit, slices of at least 64 steps
+  const int64_t tiles = (int64_t)g.nrt * g.nft;
+  int64_t ns = (1024 + tiles - 1) / tiles;
+  const int64_t maxs = (n + 64 * kt - 1) / (64 * kt);
+  if (ns > maxs) ns = maxs;
+  if (ns < 1) ns = 1;
+  const int64_t steps = (n + kt - 1) / kt;
+  const int64_t sps = (steps + ns - 1) / ns;
+  g.pps = sps * kt;
+  g.nsplit = (int)((n + g.pps - 1) / g.pps);
+  g.blocks = (int64_t)g.nrt * g.nft * g.nsplit;
+  return g;
+}
+
+hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, int p,
+                        uint64_t seed, int prec, const GaussPlan& g, float* part, double* Y,
+                        hipStream_t stream) {
+  const dim3 grid((unsigned)g.blocks), block(256);
+  if (prec == 1) {
+    const uint8_t* d = static_cast<const uint8_t*>(D);
+    if (g.frames == 128)
+      hipLaunchKernelGGL(k_sketch_gauss_bf16<1>, grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    else if (g.frames == 256)
+      hipLaunchKernelGGL(k_sketch_gauss_bf16<2>, grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    else
+      hipLaunchKernelGGL(k_sketch_gauss_bf16<4>, grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+  } else if (dtype == 0) {
+    const uint8_t* d = static_cast<const uint8_t*>(D);
+    const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 3) == 0;
+    if (vec)
+      hipLaunchKernelGGL((k_sketch_gauss_f32<uint8_t, true>), grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    else
+      hipLaunchKernelGGL((k_sketch_gauss_f32<uint8_t, false>), grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+  } else {
+    const float* d = static_cast<const float*>(D);
+    const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
+    if (vec)
+      hipLaunchKernelGGL((k_sketch_gauss_f32<float, true>), grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    else
+      hipLaunchKernelGGL((k_sketch_gauss_f32<float, false>), grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t count = m * (int64_t)p;
+  int64_t nb = (count + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_reduce_gauss, dim3((unsigned)nb), dim3(256), 0, stream, part, g.nsplit, count,
+                     1.0 / sqrt((double)p), Y);
+  return hipGetLastError();
+}
+
+}  // namespace k
+}  // namespace cdmd

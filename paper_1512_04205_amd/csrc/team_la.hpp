@@ -67,6 +67,7 @@ struct HostTeam {
   double sum(double v) { return v; }
   double maxv(double v) { return v; }
   int wave_first(bool b) { return b ? 0 : 1; }  // lowest lane with b set, or wsize
+  double recip(double x) { return 1.0 / x; }
   void tick(int) {}                             // sub-phase timing hook (device only)
   HostTeam wave_team() { return *this; }        // the team of this thread's wave
 };
@@ -91,12 +92,16 @@ TLA_HD inline double lanczos_start(int i, int salt) {
 // Number of eigenvalues smaller than x of the symmetric tridiagonal matrix with diagonal a
 // and squared off-diagonal b2 (Sylvester's law of inertia on the LDL^T pivots; a pivot
 // smaller than pivmin in modulus is replaced by -pivmin).
-TLA_HD inline int sturm_count(const double* a, const double* b2, int J, double x, double pivmin) {
+// The count is insensitive to small relative errors in each pivot (they amount to tiny
+// perturbations of the matrix), so the team may supply a fast reciprocal.
+template <class TM>
+TLA_HD inline int sturm_count(TM& tm, const double* a, const double* b2, int J, double x,
+                              double pivmin) {
   double q = a[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int c = q < 0.0 ? 1 : 0;
   for (int i = 1; i < J; ++i) {
-    q = (a[i] - x) - b2[i - 1] / q;
+    q = (a[i] - x) - b2[i - 1] * tm.recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0 ? 1 : 0;
   }
@@ -132,7 +137,7 @@ TLA_HD void tridiag_topk_values(TM& tm, const double* a, const double* b, const 
       for (int it = 0; it < 256; ++it) {
         if (hi - lo <= 2.0 * kEps * fmax(fabs(lo), fabs(hi)) + pivmin) break;
         const double x = lo + (hi - lo) * ((double)(tm.lane + 1) / np1);
-        const int f = tm.wave_first(sturm_count(a, b2, J, x, pivmin) > s);
+        const int f = tm.wave_first(sturm_count(tm, a, b2, J, x, pivmin) > s);
         const double nhi = f < tm.wsize ? lo + (hi - lo) * ((double)(f + 1) / np1) : hi;
         const double nlo = f > 0 ? lo + (hi - lo) * ((double)f / np1) : lo;
         if (nhi == hi && nlo == lo) break;
@@ -346,19 +351,43 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
       }
       tm.sync();
       aj += h[j];
-      for (int t = tm.tid; t < N; t += tm.nt) {
-        double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0;
-        int i = 0;
-        for (; i + 4 <= j + 1; i += 4) {
-          v0 += h[i] * Q[(int64_t)i * N + t];
-          v1 += h[i + 1] * Q[(int64_t)(i + 1) * N + t];
-          v2 += h[i + 2] * Q[(int64_t)(i + 2) * N + t];
-          v3 += h[i + 3] * Q[(int64_t)(i + 3) * N + t];
+      // w -= Q h: thread t of group g sums over its range of vectors; fixed-order combine
+      {
+        int G = tm.nt / N;
+        if (G > 4) G = 4;
+        double* part = ws.fast != nullptr && 4 * (int64_t)N <= ws.fast_doubles ? ws.fast : nullptr;
+        if (G < 1 || part == nullptr) G = 1;
+        for (int e = tm.tid; e < G * N; e += tm.nt) {
+          const int t = e % N, g = e / N;
+          const int i0 = (j + 1) * g / G, i1 = (j + 1) * (g + 1) / G;
+          double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, v5 = 0.0, v6 = 0.0, v7 = 0.0;
+          int i = i0;
+          for (; i + 8 <= i1; i += 8) {
+            v0 += h[i] * Q[(int64_t)i * N + t];
+            v1 += h[i + 1] * Q[(int64_t)(i + 1) * N + t];
+            v2 += h[i + 2] * Q[(int64_t)(i + 2) * N + t];
+            v3 += h[i + 3] * Q[(int64_t)(i + 3) * N + t];
+            v4 += h[i + 4] * Q[(int64_t)(i + 4) * N + t];
+            v5 += h[i + 5] * Q[(int64_t)(i + 5) * N + t];
+            v6 += h[i + 6] * Q[(int64_t)(i + 6) * N + t];
+            v7 += h[i + 7] * Q[(int64_t)(i + 7) * N + t];
+          }
+          for (; i < i1; ++i) v0 += h[i] * Q[(int64_t)i * N + t];
+          const double acc = ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7));
+          if (G == 1) w[t] -= acc;
+          else if (g == 0) part[3 * N + t] = acc;
+          else part[(int64_t)(g - 1) * N + t] = acc;
         }
-        for (; i <= j; ++i) v0 += h[i] * Q[(int64_t)i * N + t];
-        w[t] -= (v0 + v1) + (v2 + v3);
+        tm.sync();
+        if (G > 1) {
+          for (int t = tm.tid; t < N; t += tm.nt) {
+            double acc = part[3 * N + t];
+            for (int g = 1; g < G; ++g) acc += part[(int64_t)(g - 1) * N + t];
+            w[t] -= acc;
+          }
+          tm.sync();
+        }
       }
-      tm.sync();
     }
     tm.tick(11);
     double nr = 0.0;
@@ -473,37 +502,56 @@ TLA_HD void reduced_operator(TM& tm, const double* Mfull, int ldm, int N, int k,
                              const double* s, double* TV, double* At, double* stage,
                              int64_t stage_doubles) {
   // TV = M12 V, element (a, c) = sum_b M12[a][b] V[b][c].  The Gram is symmetric, so
-  // M12[a][b] = Mfull[(b+1)*ldm + a]: one thread per row a reads coalesced columns; the
-  // rows b of V pass through `stage` (fast memory) in chunks, k accumulators per thread.
-  constexpr int KM = 40;
+  // M12[a][b] = Mfull[(b+1)*ldm + a]: thread (a, block of KB columns) reads coalesced
+  // columns of the Gram, eight loads in flight; the rows b of V pass through `stage` (fast
+  // memory) in chunks.
+  constexpr int KB = 8;
+  const int CB = (k + KB - 1) / KB;
   int chunk = (int)(stage_doubles / (k > 0 ? k : 1));
   if (chunk > 256) chunk = 256;
-  for (int a0 = 0; a0 < N; a0 += tm.nt) {
-    const int a = a0 + tm.tid;
-    double acc[KM];
+  const int tasks = N * CB;
+  for (int base = 0; base < tasks; base += tm.nt) {
+    const int e = base + tm.tid;
+    const bool act = e < tasks;
+    const int a = act ? e % N : 0, c0 = act ? (e / N) * KB : 0;
+    double acc[KB];
 #pragma unroll
-    for (int c = 0; c < KM; ++c) acc[c] = 0.0;
+    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
     for (int b0 = 0; b0 < N; b0 += chunk) {
       const int nb = N - b0 < chunk ? N - b0 : chunk;
       tm.sync();
-      for (int e = tm.tid; e < nb * k; e += tm.nt) {
-        const int bb = e / k, c = e % k;
-        stage[e] = V[(int64_t)c * N + b0 + bb];
+      for (int f = tm.tid; f < nb * k; f += tm.nt) {
+        const int bb = f / k, c = f % k;
+        stage[f] = V[(int64_t)c * N + b0 + bb];
       }
       tm.sync();
-      if (a < N)
-        for (int bb = 0; bb < nb; ++bb) {
-          const double mv = Mfull[(int64_t)(b0 + bb + 1) * ldm + a];
-          const double* sv = stage + bb * k;
+      if (act) {
+        int bb = 0;
+        for (; bb + 8 <= nb; bb += 8) {
+          double mv[8];
 #pragma unroll
-          for (int c = 0; c < KM; ++c)
-            if (c < k) acc[c] += mv * sv[c];
+          for (int u = 0; u < 8; ++u) mv[u] = Mfull[(int64_t)(b0 + bb + u + 1) * ldm + a];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const double* sv = stage + (bb + u) * k + c0;
+#pragma unroll
+            for (int c = 0; c < KB; ++c)
+              if (c0 + c < k) acc[c] += mv[u] * sv[c];
+          }
         }
-    }
-    if (a < N)
+        for (; bb < nb; ++bb) {
+          const double mv = Mfull[(int64_t)(b0 + bb + 1) * ldm + a];
+          const double* sv = stage + bb * k + c0;
 #pragma unroll
-      for (int c = 0; c < KM; ++c)
-        if (c < k) TV[(int64_t)c * N + a] = acc[c];
+          for (int c = 0; c < KB; ++c)
+            if (c0 + c < k) acc[c] += mv * sv[c];
+        }
+      }
+    }
+    if (act)
+#pragma unroll
+      for (int c = 0; c < KB; ++c)
+        if (c0 + c < k) TV[(int64_t)(c0 + c) * N + a] = acc[c];
   }
   tm.sync();
   // At[i][j] = v_i . tv_j / (s_i s_j): a wave per entry, lanes over the long index
@@ -551,17 +599,17 @@ TLA_HD bool eigvals_general(TM& tm, const double* A, int k, double* H, double* e
   double v[3];
   // Householder reduction to Hessenberg form
   for (int j = 0; j < k - 2; ++j) {
-    double alpha = 0.0;
-    for (int i = j + 1; i < k; ++i) alpha += H[i * k + j] * H[i * k + j];
-    alpha = sqrt(alpha);
+    double tail = 0.0;  // sum of squares below the subdiagonal
+    for (int i = j + 2 + tm.lane; i < k; i += tm.wsize) tail += H[i * k + j] * H[i * k + j];
+    tail = tm.wave_sum(tail);
+    const double x0 = H[(j + 1) * k + j];
+    const double alpha = sqrt(x0 * x0 + tail);
     if (alpha == 0.0) continue;
     // reflector on rows/cols j+1..k-1; long vector kept in H's column below the diagonal
     // is not reused, so compute the update directly
-    const double x0 = H[(j + 1) * k + j];
     const double sg = x0 >= 0 ? 1.0 : -1.0;
     const double v0 = x0 + sg * alpha;
-    double vv = v0 * v0;
-    for (int i = j + 2; i < k; ++i) vv += H[i * k + j] * H[i * k + j];
+    const double vv = v0 * v0 + tail;
     // snapshot of the vector (column j below the diagonal) before it is overwritten
     // left update of columns j..k-1
     for (int c = j + tm.tid; c < k; c += tm.nt) {
@@ -590,15 +638,26 @@ TLA_HD bool eigvals_general(TM& tm, const double* A, int k, double* H, double* e
   }
   // Francis double-shift QR
   double hnorm = 0.0;
-  for (int e = 0; e < k * k; ++e) hnorm = fmax(hnorm, fabs(H[e]));
+  for (int e = tm.lane; e < k * k; e += tm.wsize) hnorm = fmax(hnorm, fabs(H[e]));
+  hnorm = tm.wave_max(hnorm);
   int hi = k - 1, its = 0, total = 0, nev = 0;
   while (hi >= 0) {
-    int l = hi;
-    while (l > 0) {
-      double s = fabs(H[(l - 1) * k + l - 1]) + fabs(H[l * k + l]);
-      if (s == 0.0) s = hnorm;
-      if (fabs(H[l * k + l - 1]) <= kEps * s) break;
-      --l;
+    // l = largest index <= hi with a negligible subdiagonal entry H[l][l-1] (0 if none);
+    // the lanes test hi - lane, hi - lane - wsize, ... together
+    int l = 0;
+    for (int top = hi; top > 0; top -= tm.wsize) {
+      const int c = top - tm.lane;
+      bool small = false;
+      if (c > 0) {
+        double s = fabs(H[(c - 1) * k + c - 1]) + fabs(H[c * k + c]);
+        if (s == 0.0) s = hnorm;
+        small = fabs(H[c * k + c - 1]) <= kEps * s;
+      }
+      const int f = tm.wave_first(small);
+      if (f < tm.wsize && top - f > 0) {
+        l = top - f;
+        break;
+      }
     }
     tm.sync();
     if (l > 0 && tm.tid == 0) H[l * k + l - 1] = 0.0;

@@ -75,6 +75,10 @@ def _cfg_kwargs(**kw):
     (dict(sketch=P.SKETCH_SPIXEL, idx=np.zeros((50, 1), np.int32),
           sign=np.ones((50, 1), np.int8)), P.E_INVALID_ARG),           # repeated pixels
     (dict(k=41, m=100, p=100, n=1000), P.E_UNSUPPORTED),
+    (dict(sketch_prec=P.PREC_BF16), P.E_UNSUPPORTED),                  # sparse sums are exact
+    (dict(sketch=P.SKETCH_GAUSSIAN, idx=None, sketch_prec=P.PREC_FP8), P.E_UNSUPPORTED),
+    (dict(sketch=P.SKETCH_GAUSSIAN, idx=None, sketch_prec=P.PREC_BF16, dtype=P.F32), P.E_UNSUPPORTED),
+    (dict(sketch=P.SKETCH_GAUSSIAN, idx=None, sketch_prec=P.PREC_BF16, ld=1004), P.E_UNSUPPORTED),
 ])
 def test_validation_errors(kw, status):
     with pytest.raises(P.CdmdError) as e:

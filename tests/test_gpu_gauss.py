@@ -1,0 +1,174 @@
+"""Dense Gaussian sketch on the GPU vs the FP64 oracle, through the C ABI.
+
+C is drawn on the device from the same counter-based definition the oracle uses
+(Philox4x32-10 + Box-Muller).  Comparisons use the oracle's quantised-C sketch: the
+FP64 normals rounded to the form's storage type, then Y^ = C X in float64.
+
+Tolerances
+* FP32 form: the device computes the normals in float64 and rounds once to float32, so
+  C is the oracle's; products and sums are float32 within a pixel slice of <= 1024 steps
+  of 4, float64 across slices.  Per entry |Y_gpu - Y_ref| <= 2^-16 (|C| |X|)_rt, the
+  worst-case float32 accumulation bound for 256 additions (256 * 2^-24), with margin.
+* BF16 form: the device computes the normals in float32 with the hardware
+  transcendentals (relative error ~1e-6), so about 1 in 4000 entries rounds to the
+  neighbouring bfloat16 (2^-8 relative); ||Y_gpu - Y_ref||_F <= 1e-4 ||Y_ref||_F.
+* eigenvalues against the unquantised FP64 oracle: <= 1e-6 (FP32 form), <= 1e-3
+  (BF16 form), the per-form targets.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthvideo as sv
+from oracle import cdmd_ref as R
+from oracle import philox
+from tests.cdmd_testutil import eig_rel_err, mask_agreement
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1512_04205_amd")
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _round_f32(z):
+    return np.asarray(z, dtype=np.float64).astype(np.float32).astype(np.float64)
+
+
+def _ref_sketch(D, scale, seed, p, quant):
+    m, n = D.shape
+    C = quant(philox.gaussian_block(seed, 0, p, 0, n))
+    X = D.astype(np.float64).T * scale
+    Y = C @ X / np.sqrt(p)
+    Yabs = np.abs(C) @ np.abs(X) / np.sqrt(p)
+    return Y, Yabs
+
+
+@pytest.mark.parametrize("case", [
+    ("u8", 90, 160, 40, 100),        # dtype, H, W, m, p: 14400 pixels, ragged row tile
+    ("u8", 37, 53, 21, 70),          # ragged pixel tail (1961 pixels), m < frame tile
+    ("f32", 60, 80, 50, 300),
+    ("u8_ld", 30, 50, 30, 64),       # frames with a stride ld > n, not a multiple of 4
+])
+def test_gaussian_sketch_fp32_form(case):
+    kind, H, W, m, p = case
+    _say("gauss fp32 sketch", case)
+    rng = np.random.default_rng(3)
+    n = H * W
+    seed = 0x1234_5678_9ABC
+    if kind == "f32":
+        D = rng.random((m, n), dtype=np.float32)
+        dtype, scale, ld = P.F32, 1.0, n
+        Dg = torch.from_numpy(D).cuda()
+    else:
+        D = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+        dtype, scale = P.U8, 1 / 255
+        ld = n + 3 if kind == "u8_ld" else n
+        buf = torch.zeros((m, ld), dtype=torch.uint8)
+        buf[:, :n] = torch.from_numpy(D)
+        Dg = buf.cuda()
+    mdl = P.Model(n, m, min(5, m - 1), p, sketch=P.SKETCH_GAUSSIAN, dtype=dtype, ld=ld, seed=seed)
+    mdl.fit(Dg)
+    Yg = mdl.sketch()
+    Y, Yabs = _ref_sketch(D, scale, seed, p, _round_f32)
+    err = np.abs(Yg - Y)
+    assert (err <= 2.0 ** -16 * Yabs + 1e-300).all(), (err / Yabs).max()
+
+
+@pytest.mark.parametrize("case", [(90, 160, 40, 100), (37, 64, 21, 70), (48, 96, 300, 130),
+                                  (40, 64, 200, 70), (30, 32, 129, 65)])
+def test_gaussian_sketch_bf16_form(case):
+    H, W, m, p = case
+    _say("gauss bf16 sketch", case)
+    rng = np.random.default_rng(4)
+    n = H * W
+    seed = 99
+    D = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+    mdl = P.Model(n, m, min(5, m - 1), p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=seed,
+                  sketch_prec=P.PREC_BF16)
+    mdl.fit(torch.from_numpy(D).cuda())
+    Yg = mdl.sketch()
+    Y, _ = _ref_sketch(D, 1 / 255, seed, p, R.round_bf16)
+    rel = np.linalg.norm(Yg - Y) / np.linalg.norm(Y)
+    assert rel <= 1e-4, rel
+
+
+def test_gaussian_bf16_needs_aligned_uint8():
+    with pytest.raises(P.CdmdError) as e:
+        P.Model(1000, 20, 5, 50, sketch=P.SKETCH_GAUSSIAN, dtype=P.F32, sketch_prec=P.PREC_BF16)
+    assert e.value.status == P.E_UNSUPPORTED
+    mdl = P.Model(1024, 20, 5, 50, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, sketch_prec=P.PREC_BF16)
+    buf = torch.zeros(20 * 1024 + 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.CdmdError) as e:
+        mdl.fit(buf[1:1 + 20 * 1024].view(20, 1024))
+    assert e.value.status == P.E_UNSUPPORTED
+
+
+def _fit_gauss(v, k, p, seed, prec, K=6):
+    D = v.D.numpy() if v.D.device.type == "cpu" else v.D.cpu().numpy()
+    n, m = D.shape[1], D.shape[0]
+    dtype = P.U8 if D.dtype == np.uint8 else P.F32
+    Dg = torch.from_numpy(D).cuda()
+    mdl = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, dtype=dtype, seed=seed, sketch_prec=prec)
+    mdl.fit(Dg)
+    ref = R.run(D, v.scale, k, sketch="gaussian", p=p, seed=seed, K=K)
+    return D, Dg, mdl, ref
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+def test_gaussian_fit_and_mask_parity(prec):
+    """Small cfg-1-like video (float32 for the FP32 form, uint8 for the BF16 form): modes
+    against the unquantised FP64 oracle, then OMP support and masks."""
+    _say("gauss fit", prec)
+    out = "f32" if prec == "fp32" else "u8"
+    spec = sv.preset("cfg1", H=60, W=80, m=60, bump_sigma=6.0, blur_sigma=3.0, seed=17,
+                     rect_side=(8, 8), out=out)
+    v = sv.make_video(spec)
+    pr = P.PREC_FP32 if prec == "fp32" else P.PREC_BF16
+    D, Dg, mdl, ref = _fit_gauss(v, k=10, p=300, seed=5, prec=pr)
+    md = mdl.modes()
+    rel, _, _ = eig_rel_err(md["lam"], ref.model.lam)
+    assert rel.max() <= (1e-6 if prec == "fp32" else 1e-3), rel.max()
+    S, beta = mdl.select(P.SEL_OMP, K=6)
+    if prec == "fp32":
+        assert sorted(S) == sorted(ref.support)
+    # masks with the oracle's support
+    S, beta = mdl.select(P.SEL_EXPLICIT, explicit=ref.support)
+    n, m = D.shape[1], D.shape[0]
+    mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    tau = 0.1
+    mdl.foreground(Dg, mk, tau)
+    L = R.background(ref.model.Phi[:, ref.support], ref.beta, ref.model.lam[ref.support], 0, m)
+    x = D.T.astype(np.float64) * v.scale
+    mr = R.foreground(x, L, tau)
+    words = mk.cpu().numpy().view(np.uint32)
+    pix = np.arange(n)
+    mg = ((words[:, pix >> 5] >> (pix & 31).astype(np.uint32)) & 1).astype(bool).T
+    agree = 1.0 - (mg != mr).mean()
+    assert agree >= 0.999, agree
+
+
+@pytest.mark.slow
+@pytest.mark.timeout(600)
+def test_gaussian_cfg1_full_size():
+    """The 320x240x200 float32 workload with p = 500, k = 10 (FP32 form): eigenvalues
+    within 1e-6 of the FP64 oracle, OMP support identical, masks >= 99.9% identical."""
+    _say("gauss cfg1 full size")
+    v = sv.make_video(sv.PRESETS["cfg1"])
+    D, Dg, mdl, ref = _fit_gauss(v, k=10, p=500, seed=1, prec=P.PREC_FP32, K=10)
+    md = mdl.modes()
+    rel, _, _ = eig_rel_err(md["lam"], ref.model.lam)
+    assert rel.max() <= 1e-6, rel.max()
+    S, beta = mdl.select(P.SEL_OMP, K=10)
+    assert sorted(S) == sorted(ref.support)
+    n, m = D.shape[1], D.shape[0]
+    mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    mdl.foreground(Dg, mk, 0.1)
+    L = R.background(ref.model.Phi[:, ref.support], ref.beta, ref.model.lam[ref.support], 0, m)
+    mr = R.foreground(D.T.astype(np.float64) * v.scale, L, 0.1)
+    words = mk.cpu().numpy().view(np.uint32)
+    pix = np.arange(n)
+    mg = ((words[:, pix >> 5] >> (pix & 31).astype(np.uint32)) & 1).astype(bool).T
+    assert 1.0 - (mg != mr).mean() >= 0.999

@@ -354,3 +354,13 @@ def test_eigvec_normalisation():
     # same column up to phase
     ratio = Wn / W
     assert np.allclose(np.abs(ratio / ratio[0:1]), 1.0)
+
+
+def test_f_measure_definition():
+    """Recall, precision and F on a hand-counted example; degenerate cases give 0."""
+    gt = np.array([1, 1, 1, 0, 0, 0, 0, 1], dtype=bool)
+    mk = np.array([1, 1, 0, 1, 0, 0, 0, 0], dtype=bool)
+    # TP 2, FP 1, FN 2: P = 2/3, R = 1/2, F = 2 (1/3) / (7/6) = 4/7
+    assert abs(R.f_measure(mk, gt) - 4 / 7) < 1e-15
+    assert R.f_measure(np.zeros(8, bool), gt) == 0.0
+    assert R.f_measure(gt, gt) == 1.0
