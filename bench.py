@@ -8,6 +8,11 @@ atoms, threshold tau = 0.1, bit-packed mask.  One step = one cdmd_fit + cdmd_sel
 + cdmd_foreground over the whole video.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--prec both|fp32|bf16] [--no-cpu-baseline]
+                    [--workload cfg2|cfg1|cfg3] [--copy-ref-mib N]
+
+--workload cfg1 times the FP32 form of the dense Gaussian sketch on the 320x240x200
+float32 video (p = 500, k = 10); cfg3 the BF16 form on the 3840x2160x1000 uint8 video
+(p = 4000, k = 40).  The default line is the 1080p workload above.
 """
 from __future__ import annotations
 
@@ -90,16 +95,70 @@ def cpu_baseline(D_dev, spec, k, p, nnz, K, tau, band_rows):
     }
 
 
+WORKLOADS = {
+    # the headline: sparse sketch of a 1080p uint8 video
+    "cfg2": dict(preset="cfg2", sketch="sparse", k=25, p=2000, nnz=32, K=10, tau=0.1,
+                 desc="1920x1080 uint8 video, m=500, sparse +/-1 sketch p=2000 x 32, k=25, OMP K=10, "
+                      "tau=0.1, fp64 small LA"),
+    # FP32 form of the dense Gaussian sketch on the 320x240x200 float32 video
+    "cfg1": dict(preset="cfg1", sketch="gaussian", k=10, p=500, nnz=0, K=10, tau=0.1, seed=1,
+                 desc="320x240 float32 video, m=200, dense Gaussian sketch p=500 (FP32 form), k=10, "
+                      "OMP K=10, tau=0.1, fp64 small LA"),
+    # BF16 form of the dense Gaussian sketch on the 3840x2160x1000 uint8 video
+    "cfg3": dict(preset="cfg3", sketch="gaussian", k=40, p=4000, nnz=0, K=10, tau=0.1, seed=3,
+                 desc="3840x2160 uint8 video, m=1000, dense Gaussian sketch p=4000 (BF16 form), k=40, "
+                      "OMP K=10, tau=0.1, fp64 small LA"),
+}
+
+
+def sources_sha256():
+    """Hash of the HIP/C++ sources of the library (kernels and host code)."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1512_04205_amd", "csrc")
+    for s in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.hpp"))
+                    + glob.glob(os.path.join(csrc, "*.cpp"))):
+        h.update(os.path.basename(s).encode())
+        with open(s, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload):
+    """HBM bytes per launch (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size)
+    from the committed counter summary, if it was taken on the current sources."""
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("sources_sha256") != sources_sha256():
+        return {}
+    return {q: d["fetch_bytes"] + d["write_bytes"] for q, d in t["kernels"].items()}
+
+
+def la_flops(N, k, J):
+    """Algorithmic float64 work of the small linear algebra: J Lanczos steps (matvec with
+    the N x N Gram, two classical Gram-Schmidt passes against j vectors), the reduced
+    operator (M12 V and V^T (M12 V)) and the Ritz vectors Q Z."""
+    return 2.0 * J * N * N + 4.0 * N * J * J + 2.0 * N * N * k + 2.0 * N * k * k + 2.0 * N * J * k
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
     ap.add_argument("--prec", default="both", choices=["fp32", "bf16", "both"],
-                    help="lift/reconstruction form; 'both' times FP32 (the reported value) "
+                    help="lift/reconstruction form (cfg2); 'both' times FP32 (the reported value) "
                          "and BF16 side by side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-band-rows", type=int, default=68)
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="run a device-to-device copy of this many MiB first (the reference "
+                         "kernel for scaling HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
@@ -112,21 +171,39 @@ def main():
     import paper_1512_04205_amd as P
     import synthvideo as sv
 
-    spec = sv.PRESETS["cfg2"]
-    k, p, nnz, K, tau = 25, 2000, 32, 10, 0.1
-    log("generating 1920x1080x500 uint8 video on the GPU")
+    wl = WORKLOADS[args.workload]
+    if args.copy_ref_mib > 0:
+        a = torch.empty(args.copy_ref_mib << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        log(f"copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written")
+        del a, b
+    spec = sv.PRESETS[wl["preset"]]
+    k, p, nnz, K, tau = wl["k"], wl["p"], wl["nnz"], wl["K"], wl["tau"]
+    gauss = wl["sketch"] == "gaussian"
+    log(f"generating {spec.W}x{spec.H}x{spec.m} {spec.out} video on the GPU")
     v = sv.make_video(spec, device="cuda")
     D = v.D
     m, n = D.shape
-    idx, sign = sv.sparse_table(n, p, nnz, seed=2002)
+    u8 = D.dtype == torch.uint8
+    if gauss:
+        idx = sign = None
+    else:
+        idx, sign = sv.sparse_table(n, p, nnz, seed=2002)
     mask = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
-    sect = sector_bytes(idx, n, n, m)
-    video_bytes = float(n) * m
+    sect = sector_bytes(idx, n, n, m) if not gauss else 0
+    video_bytes = float(n) * m * (1 if u8 else 4)
 
     def run_form(prec: str):
         lp = P.PREC_BF16 if prec == "bf16" else P.PREC_FP32
-        mdl = P.Model(n, m, k, p, sketch=P.SKETCH_SPARSE, dtype=P.U8, idx=idx, sign=sign,
-                      lift_prec=lp)
+        if gauss:
+            sp = P.PREC_BF16 if args.workload == "cfg3" else P.PREC_FP32
+            mdl = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8 if u8 else P.F32,
+                          seed=wl["seed"], sketch_prec=sp, lift_prec=lp)
+        else:
+            mdl = P.Model(n, m, k, p, sketch=P.SKETCH_SPARSE, dtype=P.U8, idx=idx, sign=sign,
+                          lift_prec=lp)
         mdl.set_timing(True)
 
         def step():
@@ -156,38 +233,73 @@ def main():
         inf = mdl.info()
         log(f"[{prec}] per-step ms", {kk: round(vv, 4) for kk, vv in avg.items()}, "total", round(ms, 3))
         S_n = inf["n_selected"]
+        J = inf["lanczos_steps"]
+        N = m - 1
         # algorithmic work per launch: (bytes that must cross HBM, useful flops, flop peak)
         fl_peak = PEAK["bf16"] if prec == "bf16" else PEAK["fp32"]
+        if gauss:
+            sk_peak = PEAK["bf16"] if args.workload == "cfg3" else PEAK["fp32"]
+            sk = (video_bytes + 4.0 * p * m, 2.0 * p * n * m, sk_peak)
+        else:
+            sk = (sect + idx.size * 8 + 4.0 * p * m, 2.0 * idx.size * m, PEAK["fp32"])
         work = {
-            "sketch": (sect + idx.size * 8 + 4.0 * p * m, 2.0 * idx.size * m, PEAK["fp32"]),
+            "sketch": sk,
             "gram": (4.0 * p * m + 8.0 * m * m, 2.0 * p * m * m, PEAK["fp64"]),
             "lift": (video_bytes, 4.0 * n * (m - 1) * k, fl_peak),
             "recon": (2.0 * video_bytes + n * m / 8.0, 8.0 * n * m * S_n, PEAK["fp32"]),
+            # one workgroup: the float64 rate of one of the 256 compute units
+            "small_la": (8.0 * m * m, la_flops(N, k, J), PEAK["fp64"] / 256.0),
         }
         kernels = {}
         for q, (byt, fl, fpk) in work.items():
             sec = avg[q] / 1e3
             gbs, tfs = byt / sec / 1e9, fl / sec / 1e12
             hb, fb = gbs / PEAK["hbm"], tfs / fpk
-            bound = "hbm" if hb >= fb else ("mfma" if (q == "lift" and prec == "bf16") else "alu")
-            kernels[q] = {"ms": round(avg[q], 4), "GB/s": round(gbs, 1), "TFLOP/s": round(tfs, 2),
+            if q == "small_la":
+                bound = "alu"
+            elif hb >= fb:
+                bound = "hbm"
+            else:
+                bound = "mfma" if (q in ("lift", "sketch") and fpk >= PEAK["bf16"]) else "alu"
+            kernels[q] = {"ms": round(avg[q], 4), "GB/s": round(gbs, 1), "TFLOP/s": round(tfs, 4),
                           "hbm_frac": round(hb, 4), "flop_frac": round(fb, 4), "bound": bound,
                           "bytes": byt, "flops": fl, "flop_peak": fpk}
-        # eigenvalue error against the FP64 oracle on the exact sketch of this video
         lam = mdl.modes()["lam"]
         return {"ms": ms, "fps": m / (ms / 1e3), "avg": avg, "kernels": kernels, "lam": lam,
-                "lanczos": inf["lanczos_steps"], "n_sel": S_n}
+                "lanczos": J, "n_sel": S_n}
 
-    forms = ["fp32", "bf16"] if args.prec == "both" else [args.prec]
+    if args.workload == "cfg2":
+        forms = ["fp32", "bf16"] if args.prec == "both" else [args.prec]
+    else:
+        forms = ["bf16"] if args.workload == "cfg3" else ["fp32"]
     res = {f: run_form(f) for f in forms}
 
-    log("oracle eigenvalues from the exact sketch")
-    from oracle import cdmd_ref as R
     from scipy.optimize import linear_sum_assignment
-    Dh = D.cpu().numpy()
-    Yr, _ = R.sketch_sparse(Dh, 1.0 / 255.0, idx, sign)
-    lam_r = R.reduced_operator(Yr, k)[0]
-    del Dh
+    lam_r, ref_kind = None, None
+    if args.workload == "cfg2":
+        log("oracle eigenvalues from the exact sketch")
+        from oracle import cdmd_ref as R
+        Dh = D.cpu().numpy()
+        Yr, _ = R.sketch_sparse(Dh, 1.0 / 255.0, idx, sign)
+        lam_r = R.reduced_operator(Yr, k)[0]
+        ref_kind = "FP64 oracle on the same (exact integer) sketch"
+        del Dh
+    elif args.workload == "cfg1":
+        log("oracle eigenvalues (FP64 Gaussian sketch)")
+        from oracle import cdmd_ref as R
+        Dh = D.cpu().numpy()
+        Yr = R.sketch_gaussian(Dh, v.scale, wl["seed"], p)
+        lam_r = R.reduced_operator(Yr, k)[0]
+        ref_kind = "FP64 oracle, unquantised Gaussian C"
+        del Dh
+    else:
+        log("FP32-form GPU eigenvalues as the reference (the FP64 oracle would take hours here)")
+        ref = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=wl["seed"],
+                      sketch_prec=P.PREC_FP32)
+        ref.fit(D)
+        lam_r = ref.modes()["lam"]
+        ref_kind = "FP32 form of the same sketch on the GPU (float64 normals)"
+        del ref
     for f, r in res.items():
         C = np.abs(r["lam"][:, None] - lam_r[None, :])
         a, b = linear_sum_assignment(C)
@@ -195,14 +307,20 @@ def main():
 
     head = res[forms[0]]
     dom = max(head["kernels"], key=lambda q: head["kernels"][q]["ms"])
-    kd = head["kernels"][dom]
-    if kd["bound"] == "hbm":
-        roof = {"bound": "hbm", "achieved": kd["GB/s"], "peak": PEAK["hbm"], "unit": "GB/s",
-                "frac": kd["hbm_frac"]}
-    else:
-        roof = {"bound": kd["bound"], "achieved": kd["TFLOP/s"], "peak": kd["flop_peak"],
+
+    def roof_of(kd):
+        if kd["bound"] == "hbm":
+            return {"bound": "hbm", "achieved": kd["GB/s"], "peak": PEAK["hbm"], "unit": "GB/s",
+                    "frac": kd["hbm_frac"]}
+        return {"bound": kd["bound"], "achieved": kd["TFLOP/s"], "peak": kd["flop_peak"],
                 "unit": "TFLOP/s", "frac": kd["flop_frac"]}
-    roof.update({"kernel": dom, "traffic": None})
+
+    traffic = measured_traffic({"cfg2": "1080p_m500"}.get(args.workload, args.workload)) \
+        if forms[0] == "fp32" else {}
+    roof = roof_of(head["kernels"][dom])
+    roof.update({"kernel": dom, "traffic": traffic.get(dom)})
+    streaming = {q: dict(roof_of(head["kernels"][q]), ms=head["kernels"][q]["ms"], traffic=traffic.get(q))
+                 for q in ("sketch", "lift", "recon")}
     out = {
         "metric": "frames/sec cDMD fit+fg mask, 1080p, BF16 vs FP32 at stated eig err; HBM GB/s",
         "value": head["fps"],
@@ -214,21 +332,21 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if forms[0] == "fp32" else "bf16",
         "data": "synthetic",
-        "config": {"workload": "1920x1080 uint8 video, m=500, sparse +/-1 sketch p=2000 x 32, "
-                               "k=25, OMP K=10, tau=0.1, fp64 small LA",
-                   "n": n, "m": m, "k": k, "p": p, "nnz": nnz, "K": K, "tau": tau,
-                   "lift_prec": forms[0]},
+        "config": {"workload": wl["desc"], "n": n, "m": m, "k": k, "p": p, "nnz": nnz, "K": K,
+                   "tau": tau, "lift_prec": forms[0]},
         "roofline": roof,
+        "streaming_rooflines": streaming,
         "sketch_hbm_gbps": head["kernels"]["sketch"]["GB/s"],
         "eig_rel_err_max": head["eig_rel_err_max"],
+        "eig_reference": ref_kind,
         "forms": {f: {"fps": r["fps"], "ms_per_step": r["ms"], "eig_rel_err_max": r["eig_rel_err_max"],
-                      "host_small_la_ms": round(r["avg"]["small_la"], 3), "lanczos_steps": r["lanczos"],
+                      "small_la_ms": round(r["avg"]["small_la"], 3), "lanczos_steps": r["lanczos"],
                       "n_selected": r["n_sel"],
                       "kernels": {q: {kk: vv for kk, vv in d.items() if kk not in ("bytes", "flops")}
                                   for q, d in r["kernels"].items()}}
                   for f, r in res.items()},
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and args.workload == "cfg2":
         log("CPU baseline (FP64 oracle on a band of the video)")
         out["cpu_baseline"] = cpu_baseline(D, spec, k, p, nnz, K, tau, args.cpu_band_rows)
     print(json.dumps(out), flush=True)
