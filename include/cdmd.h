@@ -136,6 +136,8 @@ typedef struct {
      kernel group, valid when timing is enabled: sketch (incl. slot reduction), Gram,
      lift (incl. partial reduction), reconstruction/threshold. */
   double gpu_ms_sketch, gpu_ms_gram, gpu_ms_lift, gpu_ms_recon;
+  int32_t lift_grid;         /* persistent lift workgroups in use (cdmd_autotune may change it) */
+  int32_t sketch_slices;     /* pixel slices of the dense Gaussian sketch (0 otherwise) */
 } cdmd_info;
 
 /* Validate `cfg`, prepare C (the sparse table is copied and reordered on the device)
@@ -188,6 +190,35 @@ cdmd_status cdmd_background(const cdmd_model* mdl, const void* d_video, int64_t 
 cdmd_status cdmd_foreground(const cdmd_model* mdl, const void* d_video, float tau,
                             int32_t static_bg, int32_t bitpacked, void* d_mask,
                             int64_t* h_counts, void* stream);
+
+/* ---- tile shapes and batches ---------------------------------------------------------
+   cdmd_autotune times candidate tile shapes of the model's size class on d_video (the
+   number of persistent lift workgroups; for the dense Gaussian sketch the number of
+   pixel slices), keeps the fastest for the model and caches the choice per size class
+   for the process.  Synchronises `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+cdmd_status cdmd_autotune(cdmd_model* mdl, const void* d_video, void* stream);
+
+/* A batch fits many models (streams of different resolution, frame count, rank and
+   sketch) with one graph launch: the sketch and Gram of every model and then its lift run
+   on a pool of streams, and the small linear algebra of all models is one launch with a
+   workgroup per model (Algorithm 1 for each stream; the paper processes independent
+   200-frame batches the same way, Section 4).  The graph is captured on the first
+   cdmd_batch_fit (after cdmd_autotune of every model not yet tuned) and replayed while
+   the video pointers and the stream stay the same.  Models whose fit needs the host small
+   linear algebra (float32 videos, unaligned frames, m > 1025) are fitted one after the
+   other after the graph.  The batch borrows the models (free them after the batch). */
+typedef struct cdmd_batch cdmd_batch;
+/* Errors: INVALID_ARG (NULL or repeated model, n < 1), OUT_OF_MEMORY, DEVICE. */
+cdmd_status cdmd_batch_create(cdmd_model* const* models, int32_t n, cdmd_batch** out);
+/* d_videos[i] is the video of models[i].  per_model (optional, n entries) receives each
+   model's status (STATE for a model not attempted because the batch failed first); the
+   call returns OK when all succeed, else the first failure.  The graph runs on a stream
+   of the batch's own, after the work already enqueued on `stream`.
+   Synchronises `stream`.  Errors: INVALID_ARG, DEVICE, and the per-model errors of
+   cdmd_fit. */
+cdmd_status cdmd_batch_fit(cdmd_batch* batch, const void* const* d_videos, void* stream,
+                           cdmd_status* per_model);
+void cdmd_batch_free(cdmd_batch* batch);
 
 /* ---- learned background selector -------------------------------------------------
    A 6-64-64-1 network with GELU activations (exact erf) maps per-mode features to the

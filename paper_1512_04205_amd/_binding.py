@@ -32,7 +32,8 @@ EXPORTED = [
     "cdmd_info_get", "cdmd_set_timing", "cdmd_free", "cdmd_dbg_force_valu_lift",
     "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_forward",
-    "cdmd_select_learned",
+    "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
+    "cdmd_batch_free",
 ]
 MLP_NPARAM = 4673
 
@@ -66,6 +67,7 @@ class Info(ctypes.Structure):
         ("lanczos_steps", ctypes.c_int32), ("timing", ctypes.c_int32),
         ("gpu_ms_sketch", ctypes.c_double), ("gpu_ms_gram", ctypes.c_double),
         ("gpu_ms_lift", ctypes.c_double), ("gpu_ms_recon", ctypes.c_double),
+        ("lift_grid", ctypes.c_int32), ("sketch_slices", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -106,10 +108,15 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_mlp_forward.argtypes = [P, P, I32, I32, P, P]
     lib.cdmd_select_learned.argtypes = [P, P, D, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), DP, DP,
                                         ctypes.POINTER(I32), P]
+    lib.cdmd_autotune.argtypes = [P, P, P]
+    lib.cdmd_batch_create.argtypes = [ctypes.POINTER(P), I32, ctypes.POINTER(P)]
+    lib.cdmd_batch_fit.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(I32)]
+    lib.cdmd_batch_free.argtypes = [P]
+    lib.cdmd_batch_free.restype = None
     lib.cdmd_free.argtypes = [P]
     lib.cdmd_free.restype = None
     for name in EXPORTED:
-        if name not in ("cdmd_abi_version", "cdmd_last_error", "cdmd_free"):
+        if name not in ("cdmd_abi_version", "cdmd_last_error", "cdmd_free", "cdmd_batch_free"):
             getattr(lib, name).restype = ctypes.c_int
     _lib = lib
     return lib
@@ -242,6 +249,11 @@ class Model:
         ns = nsel.value
         return idx[:ns].copy(), (beta[0::2] + 1j * beta[1::2])[:ns].copy(), prob, bool(fb.value)
 
+    def autotune(self, video, stream=None):
+        """Pick the tile shapes of this model's size class by timing them on `video`."""
+        _check(load_library().cdmd_autotune(self._h, _video_ptr(video, self.dtype, self.n, self.m, self.ld),
+                                            _stream(stream)))
+
     def mode_features(self, out=None, stream=None):
         """Per-mode features (k x 6 float32 device tensor) of the last fit."""
         import torch
@@ -296,6 +308,47 @@ class Model:
         inf = Info()
         _check(load_library().cdmd_info_get(self._h, ctypes.byref(inf)))
         return inf.as_dict()
+
+
+class Batch:
+    """Many models fitted by one graph launch (cdmd_batch_*).  Keeps the models alive."""
+
+    def __init__(self, models):
+        self.models = list(models)
+        arr = (ctypes.c_void_p * len(self.models))(*[m._h.value for m in self.models])
+        h = ctypes.c_void_p()
+        _check(load_library().cdmd_batch_create(arr, len(self.models), ctypes.byref(h)))
+        self._h = h
+
+    def fit(self, videos, stream=None):
+        """Fit models[i] on videos[i]; returns the per-model status list (raises when any
+        model failed, after every model has been attempted)."""
+        vp = (ctypes.c_void_p * len(self.models))(
+            *[_video_ptr(v, m.dtype, m.n, m.m, m.ld) for v, m in zip(videos, self.models)])
+        st = (ctypes.c_int32 * len(self.models))()
+        rc = load_library().cdmd_batch_fit(self._h, vp, _stream(stream), st)
+        if rc != OK:
+            raise CdmdError(rc, load_library().cdmd_last_error().decode())
+        return list(st)
+
+    def statuses(self, videos, stream=None):
+        """Like fit, but returns the statuses without raising."""
+        vp = (ctypes.c_void_p * len(self.models))(
+            *[_video_ptr(v, m.dtype, m.n, m.m, m.ld) for v, m in zip(videos, self.models)])
+        st = (ctypes.c_int32 * len(self.models))()
+        load_library().cdmd_batch_fit(self._h, vp, _stream(stream), st)
+        return list(st)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().cdmd_batch_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _tensor_ptr(t, numel: int):

@@ -10,8 +10,12 @@
 #include <cmath>
 #include <complex>
 #include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
 #include <numeric>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "kernels.hpp"
@@ -87,10 +91,12 @@ struct cdmd_model {
   bool gauss = false;               // dense Gaussian sketch
   cdmd::k::GaussPlan gplan{};
   float* d_gpart = nullptr;         // per-slice partial sketches
+  size_t gpart_cap = 0;             // floats allocated at d_gpart
   double* d_gram = nullptr;
   // lift
   bool lift_mfma = false;   // MFMA path (uint8 video, 16-byte aligned frames)
   int lm_nb = 0, lm_nsplit = 0, lm_nksteps = 0, lm_grid = 0, lm_ne = 0;
+  int lm_grid_max = 0;            // largest lift grid the partial buffer holds
   uint16_t* h_Gp = nullptr;
   void* d_Gp = nullptr;
   float* d_G = nullptr;
@@ -139,8 +145,10 @@ struct cdmd_model {
   int64_t la_out_n = 0;
   hipEvent_t ev[8] = {};
 
+  bool capturing = false;         // inside a graph capture: no timing events
+  bool tuned = false;             // autotuner choices applied
   void mark(int i, hipStream_t st) {
-    if (timing) (void)hipEventRecord(ev[i], st);
+    if (timing && !capturing) (void)hipEventRecord(ev[i], st);
   }
   double span(int a, int b) {
     float ms = 0.f;
@@ -573,7 +581,9 @@ cdmd_status launch_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStr
   return CDMD_OK;
 }
 
-cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
+// Lift, reduction of its partials and the copies of the results to pinned host memory,
+// enqueued without waiting (with the device small LA, G is already on the device).
+cdmd_status enqueue_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
   if (M->cfg.lift_prec == CDMD_PREC_BF16 && !M->lift_mfma)
     return fail(CDMD_E_INVALID_ARG, "the BF16 lift needs a 16-byte aligned uint8 video");
   if (!M->device_la) {
@@ -590,6 +600,11 @@ cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream
   HIPCHK(hipMemcpyAsync(M->h_red, M->d_red, sizeof(double) * ne, hipMemcpyDeviceToHost, st));
   if (M->device_la)
     HIPCHK(hipMemcpyAsync(M->h_la_out, M->d_la_out, sizeof(double) * M->la_out_n, hipMemcpyDeviceToHost, st));
+  return CDMD_OK;
+}
+
+cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
+  TRY(enqueue_lift(M, d_video, d_phi, st));
   HIPCHK(hipStreamSynchronize(st));
   if (M->timing) {
     M->info.gpu_ms_lift = M->span(3, 4);
@@ -687,8 +702,9 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
   const int64_t m = M->m, p = M->p;
   if (cfg->sketch == CDMD_SKETCH_GAUSSIAN) {
     M->gauss = true;
-    M->gplan = cdmd::k::gauss_plan(M->n, m, (int)p, cfg->sketch_prec == CDMD_PREC_BF16 ? 1 : 0);
-    TRY(dalloc(&M->d_gpart, (size_t)M->gplan.nsplit * m * p));
+    M->gplan = cdmd::k::gauss_plan(M->n, m, (int)p, cfg->sketch_prec == CDMD_PREC_BF16 ? 1 : 0, 1024);
+    M->gpart_cap = (size_t)M->gplan.nsplit * m * p;
+    TRY(dalloc(&M->d_gpart, M->gpart_cap));
     TRY(dalloc(&M->d_Yd, (size_t)m * p));
   } else if (cfg->dtype == CDMD_U8) {
     TRY(build_sparse_plan(M));
@@ -722,6 +738,7 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
     M->lm_nsplit = cfg->lift_prec == CDMD_PREC_BF16 ? 1 : 3;
     M->lm_nksteps = (M->N + 15) / 16;
     M->lm_grid = cdmd::k::lift_mfma_grid(M->n);
+    M->lm_grid_max = (int)std::min<int64_t>((M->n + 255) / 256, 1024);
     M->lm_ne = M->lm_nb * (M->lm_nb + 1) / 2 * 16 * 64;
     const size_t gp = (size_t)M->lm_nksteps * M->lm_nb * M->lm_nsplit * 64 * 8;
     TRY(dalloc((uint16_t**)&M->d_Gp, gp));
@@ -737,7 +754,7 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
       TRY(halloc(&M->h_la_out, (size_t)M->la_out_n));
       M->device_la_ok = true;
     }
-    part_sz = std::max(part_sz, (size_t)M->lm_grid * M->lm_ne);
+    part_sz = std::max(part_sz, (size_t)std::max(M->lm_grid, M->lm_grid_max) * M->lm_ne);
     red_sz = std::max(red_sz, (size_t)M->lm_ne);
   }
   TRY(dalloc(&M->d_part, part_sz));
@@ -759,16 +776,24 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
 
 void cdmd_free(cdmd_model* mdl) { delete mdl; }
 
+// Which path a fit of d_video takes: the MFMA lift needs 16-byte aligned uint8 frames;
+// the device small LA needs the MFMA lift (it writes the lift operands).
+void plan_fit(cdmd_model* M, const void* d_video) {
+  M->lift_mfma = M->cfg.dtype == CDMD_U8 && M->ld % 16 == 0 &&
+                 (reinterpret_cast<uintptr_t>(d_video) & 15) == 0 &&
+                 (M->cfg.lift_prec == CDMD_PREC_BF16 || !M->force_valu_lift);
+  M->device_la = M->device_la_ok && M->lift_mfma && !M->force_host_la;
+}
+
+cdmd_status post_fit(cdmd_model* M, double t0, double t1, double t2);
+
 cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
   g_err.clear();
   if (!M || !d_video) return fail(CDMD_E_INVALID_ARG, "NULL model or video");
   hipStream_t st = as_stream(stream);
   M->fitted = M->selected = false;
   M->g_canonical_on_device = false;
-  M->lift_mfma = M->cfg.dtype == CDMD_U8 && M->ld % 16 == 0 &&
-                 (reinterpret_cast<uintptr_t>(d_video) & 15) == 0 &&
-                 (M->cfg.lift_prec == CDMD_PREC_BF16 || !M->force_valu_lift);
-  M->device_la = M->device_la_ok && M->lift_mfma && !M->force_host_la;
+  plan_fit(M, d_video);
   double t0 = now_ms(), t1, t2;
   if (M->device_la) {
     TRY(run_sketch(M, d_video, st, false));
@@ -784,6 +809,12 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
     t2 = now_ms();
   }
   TRY(run_lift(M, d_video, nullptr, st));
+  return post_fit(M, t0, t1, t2);
+}
+
+// Host part of a fit once its device results are in pinned memory: the device small-LA
+// results, H = Phi^H Phi and c, the amplitudes (step 9) and the canonical mode order.
+cdmd_status post_fit(cdmd_model* M, double t0, double t1, double t2) {
   if (M->device_la) TRY(take_device_la(M));
   double t3 = now_ms();
   std::vector<cplx> H, cv;
@@ -854,6 +885,310 @@ cdmd_status cdmd_modes(const cdmd_model* Mc, double* lambda, double* b, double* 
     TRY(launch_lift(M, d_video, (float*)d_phi, st));
     HIPCHK(hipStreamSynchronize(st));
   }
+  return CDMD_OK;
+}
+
+// ------------------------------------------------------------------ autotuner
+// Tile shapes chosen by timing the candidates on the caller's video, once per size
+// class (process-wide cache): the number of persistent lift workgroups, and for the dense
+// Gaussian sketch the number of pixel slices.
+extern "C++" {
+namespace {
+struct TuneKey {
+  int64_t n, m;
+  int k, p, sketch, sprec, lprec, dtype;
+  bool operator<(const TuneKey& o) const {
+    return std::tie(n, m, k, p, sketch, sprec, lprec, dtype) <
+           std::tie(o.n, o.m, o.k, o.p, o.sketch, o.sprec, o.lprec, o.dtype);
+  }
+};
+struct TuneChoice {
+  int lift_grid = 0;
+  int gauss_target = 0;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneChoice> g_tune;
+
+TuneKey tune_key(const cdmd_model* M) {
+  const cdmd_config& c = M->cfg;
+  return TuneKey{M->n, M->m, M->k, M->p, (int)c.sketch, (int)c.sketch_prec, (int)c.lift_prec, (int)c.dtype};
+}
+
+template <class F>
+cdmd_status time_ms(hipStream_t st, int reps, F&& launch, double* ms) {
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  if (hipEventCreate(&b) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    return fail(CDMD_E_DEVICE, "hipEventCreate failed");
+  }
+  cdmd_status r = launch();  // warm-up
+  if (r == CDMD_OK) {
+    (void)hipEventRecord(a, st);
+    for (int i = 0; i < reps && r == CDMD_OK; ++i) r = launch();
+    (void)hipEventRecord(b, st);
+    (void)hipEventSynchronize(b);
+    float t = 0.f;
+    (void)hipEventElapsedTime(&t, a, b);
+    *ms = t / reps;
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return r;
+}
+
+cdmd_status apply_gauss_target(cdmd_model* M, int target) {
+  cdmd::k::GaussPlan g = cdmd::k::gauss_plan(M->n, M->m, (int)M->p,
+                                             M->cfg.sketch_prec == CDMD_PREC_BF16 ? 1 : 0, target);
+  const size_t need = (size_t)g.nsplit * M->m * M->p;
+  if (need > M->gpart_cap) {
+    float* np = nullptr;
+    TRY(dalloc(&np, need));
+    (void)hipFree(M->d_gpart);
+    M->d_gpart = np;
+    M->gpart_cap = need;
+  }
+  M->gplan = g;
+  return CDMD_OK;
+}
+}  // namespace
+}  // extern "C++"
+
+cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
+  g_err.clear();
+  if (!M || !d_video) return fail(CDMD_E_INVALID_ARG, "NULL model or video");
+  hipStream_t st = as_stream(stream);
+  plan_fit(M, d_video);
+  const TuneKey key = tune_key(M);
+  TuneChoice ch;
+  bool cached = false;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(key);
+    if (it != g_tune.end()) ch = it->second, cached = true;
+  }
+  if (!cached) {
+    if (M->lift_mfma) {
+      double best = 1e300;
+      for (int g : {128, 256, 512, 1024}) {
+        if (g > M->lm_grid_max) continue;
+        M->lm_grid = g;
+        double ms = 0.0;
+        TRY(time_ms(st, 3, [&] { return launch_lift(M, d_video, nullptr, st); }, &ms));
+        if (ms < best) best = ms, ch.lift_grid = g;
+      }
+    }
+    if (M->gauss) {
+      double best = 1e300;
+      for (int target : {512, 1024, 2048}) {
+        TRY(apply_gauss_target(M, target));
+        double ms = 0.0;
+        TRY(time_ms(st, 2, [&] {
+          HIPCHK(cdmd::k::sketch_gauss(d_video, M->cfg.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p,
+                                       M->cfg.seed, M->cfg.sketch_prec == CDMD_PREC_BF16 ? 1 : 0, M->gplan,
+                                       M->d_gpart, M->d_Yd, st));
+          return CDMD_OK;
+        }, &ms));
+        if (ms < best) best = ms, ch.gauss_target = target;
+      }
+    }
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[key] = ch;
+  }
+  if (ch.lift_grid > 0) M->lm_grid = ch.lift_grid;
+  if (ch.gauss_target > 0) TRY(apply_gauss_target(M, ch.gauss_target));
+  M->tuned = true;
+  M->info.lift_grid = M->lm_grid;
+  M->info.sketch_slices = M->gauss ? M->gplan.nsplit : 0;
+  return CDMD_OK;
+}
+
+// ------------------------------------------------------------------ batched fits
+// Many models fitted by one graph launch: the sketch + Gram and the lift of every model
+// run on a pool of streams (fork/join through events), and the device small LA of all
+// of them is one launch with a workgroup per model.  The graph is captured on the first
+// call and replayed while the videos stay the same.  Models whose fit needs the host small
+// LA (float32 videos, unaligned frames, m > 1025) are fitted one after the other after the
+// graph.
+struct cdmd_batch {
+  std::vector<cdmd_model*> models;
+  std::vector<const void*> videos;  // of the captured graph
+  std::vector<int> dev;             // models on the graph
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  std::vector<hipStream_t> pool;
+  hipEvent_t fork1 = nullptr, fork2 = nullptr;
+  std::vector<hipEvent_t> join1, join2;
+  cdmd::k::SLADesc* d_desc = nullptr;
+  hipStream_t cap = nullptr;        // the graph's own stream (capture needs a non-null stream)
+  hipEvent_t entry = nullptr;       // caller's stream -> cap
+
+  void drop_graph() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    videos.clear();
+  }
+  ~cdmd_batch() {
+    drop_graph();
+    for (hipStream_t s : pool) (void)hipStreamDestroy(s);
+    for (hipEvent_t e : join1) (void)hipEventDestroy(e);
+    for (hipEvent_t e : join2) (void)hipEventDestroy(e);
+    if (fork1) (void)hipEventDestroy(fork1);
+    if (fork2) (void)hipEventDestroy(fork2);
+    if (entry) (void)hipEventDestroy(entry);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (d_desc) (void)hipFree(d_desc);
+  }
+};
+
+cdmd_status cdmd_batch_create(cdmd_model* const* models, int32_t n, cdmd_batch** out) {
+  g_err.clear();
+  if (!models || !out || n < 1) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  for (int i = 0; i < n; ++i) {
+    if (!models[i]) return fail(CDMD_E_INVALID_ARG, "NULL model in the batch");
+    for (int j = 0; j < i; ++j)
+      if (models[j] == models[i]) return fail(CDMD_E_INVALID_ARG, "a model appears twice in the batch");
+  }
+  std::unique_ptr<cdmd_batch> B(new (std::nothrow) cdmd_batch());
+  if (!B) return fail(CDMD_E_OUT_OF_MEMORY, "host allocation failed");
+  B->models.assign(models, models + n);
+  const int P = std::min(n, 8);
+  for (int i = 0; i < P; ++i) {
+    hipStream_t s;
+    HIPCHK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+    B->pool.push_back(s);
+    hipEvent_t e1, e2;
+    HIPCHK(hipEventCreateWithFlags(&e1, hipEventDisableTiming));
+    B->join1.push_back(e1);
+    HIPCHK(hipEventCreateWithFlags(&e2, hipEventDisableTiming));
+    B->join2.push_back(e2);
+  }
+  HIPCHK(hipEventCreateWithFlags(&B->fork1, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&B->fork2, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&B->entry, hipEventDisableTiming));
+  HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
+  TRY(dalloc(&B->d_desc, (size_t)n));
+  *out = B.release();
+  return CDMD_OK;
+}
+
+void cdmd_batch_free(cdmd_batch* B) { delete B; }
+
+namespace {
+cdmd_status capture_batch(cdmd_batch* B, hipStream_t st) {
+  const int P = (int)B->pool.size();
+  HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+  cdmd_status r = CDMD_OK;
+  auto guard = [&](cdmd_status x) {
+    if (r == CDMD_OK) r = x;
+  };
+  auto hip = [&](hipError_t e) {
+    if (e != hipSuccess && r == CDMD_OK) r = fail(CDMD_E_DEVICE, hipGetErrorString(e));
+  };
+  hip(hipEventRecord(B->fork1, st));
+  for (int q = 0; q < P; ++q) hip(hipStreamWaitEvent(B->pool[q], B->fork1, 0));
+  for (size_t i = 0; i < B->dev.size() && r == CDMD_OK; ++i) {
+    cdmd_model* M = B->models[B->dev[i]];
+    guard(run_sketch(M, B->videos[B->dev[i]], B->pool[i % P], false));
+  }
+  for (int q = 0; q < P; ++q) {
+    hip(hipEventRecord(B->join1[q], B->pool[q]));
+    hip(hipStreamWaitEvent(st, B->join1[q], 0));
+  }
+  hip(cdmd::k::small_la_batch(B->d_desc, (int)B->dev.size(), st));
+  hip(hipEventRecord(B->fork2, st));
+  for (int q = 0; q < P; ++q) hip(hipStreamWaitEvent(B->pool[q], B->fork2, 0));
+  for (size_t i = 0; i < B->dev.size() && r == CDMD_OK; ++i) {
+    cdmd_model* M = B->models[B->dev[i]];
+    guard(enqueue_lift(M, B->videos[B->dev[i]], nullptr, B->pool[i % P]));
+  }
+  for (int q = 0; q < P; ++q) {
+    hip(hipEventRecord(B->join2[q], B->pool[q]));
+    hip(hipStreamWaitEvent(st, B->join2[q], 0));
+  }
+  hipGraph_t g = nullptr;
+  const hipError_t ee = hipStreamEndCapture(st, &g);
+  if (r != CDMD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return r;
+  }
+  if (ee != hipSuccess) return fail(CDMD_E_DEVICE, hipGetErrorString(ee));
+  B->graph = g;
+  HIPCHK(hipGraphInstantiate(&B->exec, g, nullptr, nullptr, 0));
+  return CDMD_OK;
+}
+}  // namespace
+
+cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* stream,
+                           cdmd_status* per_model) {
+  g_err.clear();
+  if (!B || !d_videos) return fail(CDMD_E_INVALID_ARG, "NULL batch or videos");
+  const int n = (int)B->models.size();
+  for (int i = 0; i < n; ++i)
+    if (!d_videos[i]) return fail(CDMD_E_INVALID_ARG, "NULL video in the batch");
+  hipStream_t st = as_stream(stream);
+  if (per_model)
+    for (int i = 0; i < n; ++i) per_model[i] = CDMD_E_STATE;  // not attempted
+  const bool same = B->exec && (int)B->videos.size() == n &&
+                    std::equal(B->videos.begin(), B->videos.end(), d_videos, d_videos + n);
+  if (!same) {
+    B->drop_graph();
+    B->videos.assign(d_videos, d_videos + n);
+    B->dev.clear();
+    std::vector<cdmd::k::SLADesc> desc;
+    for (int i = 0; i < n; ++i) {
+      cdmd_model* M = B->models[i];
+      plan_fit(M, d_videos[i]);
+      if (!M->device_la) continue;
+      if (!M->tuned) TRY(cdmd_autotune(M, d_videos[i], stream));
+      plan_fit(M, d_videos[i]);
+      B->dev.push_back(i);
+      desc.push_back(cdmd::k::SLADesc{M->d_gram, M->d_la_scratch, M->d_la_out, (uint16_t*)M->d_Gp, kLanczosTol,
+                                      M->sketch_scale, (double)M->xscale, (int)M->m, M->k, M->la_jmax,
+                                      M->lm_nb, M->lm_nsplit, M->lm_nksteps});
+    }
+    if (!desc.empty()) {
+      HIPCHK(hipMemcpy(B->d_desc, desc.data(), sizeof(desc[0]) * desc.size(), hipMemcpyHostToDevice));
+      for (int i : B->dev) B->models[i]->capturing = true;
+      const cdmd_status r = capture_batch(B, B->cap);
+      for (int i : B->dev) B->models[i]->capturing = false;
+      if (r != CDMD_OK) {
+        B->drop_graph();
+        return r;
+      }
+    }
+  }
+  cdmd_status first = CDMD_OK;
+  const double t0 = now_ms();
+  for (int i : B->dev) {
+    B->models[i]->fitted = B->models[i]->selected = false;
+    B->models[i]->g_canonical_on_device = false;
+  }
+  if (B->exec) {
+    // the graph runs on the batch's stream after the work already on the caller's stream
+    HIPCHK(hipEventRecord(B->entry, st));
+    HIPCHK(hipStreamWaitEvent(B->cap, B->entry, 0));
+    HIPCHK(hipGraphLaunch(B->exec, B->cap));
+    HIPCHK(hipStreamSynchronize(B->cap));
+  }
+  const double t1 = now_ms();
+  std::vector<char> on_graph(n, 0);
+  for (int i : B->dev) on_graph[i] = 1;
+  for (int i = 0; i < n; ++i) {
+    cdmd_model* M = B->models[i];
+    cdmd_status r;
+    if (on_graph[i]) {
+      plan_fit(M, d_videos[i]);
+      r = post_fit(M, t0, t1, t1);
+    } else {
+      r = cdmd_fit(M, d_videos[i], stream);
+    }
+    if (per_model) per_model[i] = r;
+    if (r != CDMD_OK && first == CDMD_OK) first = r;
+  }
+  if (first != CDMD_OK) return fail(first, "at least one model of the batch failed (see per_model)");
   return CDMD_OK;
 }
 

@@ -989,12 +989,15 @@ __device__ __forceinline__ double bf16_val_d(uint16_t b) {
   return (double)__uint_as_float((uint32_t)b << 16);
 }
 
-__global__ __launch_bounds__(1024) void k_small_la(const double* __restrict__ Gr, int m, int k,
-                                                   double rtol, int Jmax, double sketch_scale,
-                                                   double xscale, double* __restrict__ scratch,
-                                                   double* __restrict__ out, uint16_t* __restrict__ Gp,
-                                                   int NB, int NS, int KS) {
+// One small-LA solve by the whole (1024-thread) workgroup.
+__device__ void small_la_block(const SLADesc& d) {
   using namespace tla;
+  const double* __restrict__ Gr = d.Gr;
+  const int m = d.m, k = d.k, Jmax = d.Jmax, NB = d.NB, NS = d.NS, KS = d.KS;
+  const double rtol = d.rtol, sketch_scale = d.sketch_scale, xscale = d.xscale;
+  double* __restrict__ scratch = d.scratch;
+  double* __restrict__ out = d.out;
+  uint16_t* __restrict__ Gp = d.Gp;
   __shared__ double s_q[SLA_NMAX], s_w[SLA_NMAX];
   __shared__ double s_h[SLA_JMAX + 4], s_alpha[SLA_JMAX + 4], s_beta[SLA_JMAX + 4];
   __shared__ double s_red[16];
@@ -1066,12 +1069,30 @@ __global__ __launch_bounds__(1024) void k_small_la(const double* __restrict__ Gr
   tm.stamp(9);
 }
 
+__global__ __launch_bounds__(1024) void k_small_la(SLADesc d) { small_la_block(d); }
+
+// One workgroup per solve: the solves of a batch run side by side, one per compute unit.
+__global__ __launch_bounds__(1024) void k_small_la_batch(const SLADesc* __restrict__ ds) {
+  const SLADesc d = ds[blockIdx.x];
+  small_la_block(d);
+}
+
+bool small_la_fits(int m, int k, int Jmax) {
+  return m - 1 <= SLA_NMAX && Jmax <= SLA_JMAX && 2 * k <= SLA_NMAX;
+}
+
 hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
                     double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
                     hipStream_t stream) {
-  if (m - 1 > SLA_NMAX || Jmax > SLA_JMAX || 2 * k > SLA_NMAX) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_small_la, dim3(1), dim3(1024), 0, stream, Gr, m, k, rtol, Jmax, sketch_scale,
-                     xscale, scratch, out, (uint16_t*)Gp, NB, NS, KS);
+  if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
+  const SLADesc d{Gr, scratch, out, (uint16_t*)Gp, rtol, sketch_scale, xscale, m, k, Jmax, NB, NS, KS};
+  hipLaunchKernelGGL(k_small_la, dim3(1), dim3(1024), 0, stream, d);
+  return hipGetLastError();
+}
+
+hipError_t small_la_batch(const SLADesc* d_descs, int count, hipStream_t stream) {
+  if (count < 1) return hipSuccess;
+  hipLaunchKernelGGL(k_small_la_batch, dim3(count), dim3(1024), 0, stream, d_descs);
   return hipGetLastError();
 }
 

@@ -39,7 +39,8 @@ struct GaussPlan {
   int nrt, nft, nsplit, frames;
   int64_t pps, blocks;
 };
-GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec);
+// target: about how many workgroups to spread over (pixel slices are added until then)
+GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target);
 hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, int p,
                         uint64_t seed, int prec, const GaussPlan& g, float* part, double* Y,
                         hipStream_t stream);
@@ -112,6 +113,18 @@ hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, doubl
                     double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
                     hipStream_t stream);
 int64_t small_la_scratch_doubles(int m, int k, int Jmax);
+// A batch of independent solves in one launch (one workgroup each); d_descs is device
+// memory holding `count` descriptors, each valid for small_la (small_la_fits).
+struct SLADesc {
+  const double* Gr;
+  double* scratch;
+  double* out;
+  uint16_t* Gp;
+  double rtol, sketch_scale, xscale;
+  int m, k, Jmax, NB, NS, KS;
+};
+bool small_la_fits(int m, int k, int Jmax);
+hipError_t small_la_batch(const SLADesc* d_descs, int count, hipStream_t stream);
 int64_t small_la_out_doubles(int m, int k);
 
 }  // namespace k

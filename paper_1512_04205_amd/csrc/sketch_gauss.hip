@@ -369,7 +369,7 @@ __global__ __launch_bounds__(256) void k_reduce_gauss(const float* __restrict__ 
 
 }  // namespace
 
-GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec) {
+GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target) {
   GaussPlan g{};
   const bool bf = prec == 1;
   const int rows = bf ? GB_ROWS : GF_ROWS;
@@ -379,9 +379,9 @@ GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec) {
   g.frames = frames;
   g.nrt = (p + rows - 1) / rows;
   g.nft = (int)((m + frames - 1) / frames);
-  // about four workgroups per compute unit, slices of at least 64 steps
+  // about `target` workgroups, slices of at least 64 steps
   const int64_t tiles = (int64_t)g.nrt * g.nft;
-  int64_t ns = (1024 + tiles - 1) / tiles;
+  int64_t ns = (target + tiles - 1) / tiles;
   const int64_t maxs = (n + 64 * kt - 1) / (64 * kt);
   if (ns > maxs) ns = maxs;
   if (ns < 1) ns = 1;

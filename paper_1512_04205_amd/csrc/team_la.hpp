@@ -84,9 +84,18 @@ struct LanczosWork {
   int64_t fast_doubles;  // work when it fits, and later scratch
 };
 
-// Deterministic start vector.
+// Deterministic start vectors: entry i of vector `salt` is 1 + u - 1/2 with u in [0, 1)
+// from an integer hash of (i, salt) (the splitmix64 finaliser), so vectors of different
+// salts are independent (restarts after a breakdown need a fresh direction each time)
+// and host and device produce the same bits.
 TLA_HD inline double lanczos_start(int i, int salt) {
-  return 1.0 + 0.25 * sin(0.7 * (i + 1) + 1.3 * salt);
+  uint64_t x = (uint64_t)(uint32_t)i * 0x9E3779B97F4A7C15ull + (uint64_t)(uint32_t)salt * 0xD1B54A32D192ED03ull;
+  x ^= x >> 30;
+  x *= 0xBF58476D1CE4E5B9ull;
+  x ^= x >> 27;
+  x *= 0x94D049BB133111EBull;
+  x ^= x >> 31;
+  return 0.5 + (double)(x >> 11) * 0x1p-53;
 }
 
 // Number of eigenvalues smaller than x of the symmetric tridiagonal matrix with diagonal a
@@ -455,7 +464,8 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
       if (check > Jmax) check = Jmax;
       if (breakdown) {
         // invariant subspace found before k pairs converged: restart orthogonally
-        if (++restarts > 8) return -1;
+        // (bounded by the Krylov limit: a matrix of low rank restarts once per null vector)
+        if (++restarts > Jmax) return -1;
         for (int t = tm.tid; t < N; t += tm.nt) w[t] = lanczos_start(t, J + 17 * restarts);
         tm.sync();
         for (int pass = 0; pass < 2; ++pass) {

@@ -283,3 +283,19 @@ def test_team_small_la_clustered_spectrum():
     C = np.abs(lam[:, None] - lr[None, :])
     a, b = linear_sum_assignment(C)
     assert (C[a, b] / np.abs(lr[b]).max()).max() < 1e-9
+
+
+@pytest.mark.parametrize("m,k", [(40, 6), (120, 12)])
+def test_team_small_la_rank_one_gram(m, k):
+    """A constant video gives a rank-one Gram: the Lanczos process breaks down at once and
+    restarts in the null space; the solve must end with zero Ritz values and report rank
+    deficiency (not a numerical failure)."""
+    lib = P.load_library()
+    lib.cdmd_dbg_team_small_la.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_double, DP, DP, DP, DP, DP, IP]
+    Yi = np.full((200, m), 77.0 * 32)
+    Gr = np.ascontiguousarray(Yi.T @ Yi)
+    out = [np.zeros(k), np.zeros(k), np.zeros(2 * k), np.zeros(2 * k * k), np.zeros(2 * (m - 1) * k)]
+    st = lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1 / 255, *[_p(o) for o in out],
+                                    ctypes.byref(ctypes.c_int32()))
+    assert st == P.E_RANK_DEFICIENT
