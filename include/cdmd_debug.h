@@ -49,9 +49,10 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
 /* Phase times (ms) of the last device small-LA solve: [0] Lanczos incl. convergence
    checks, [1] of which the tridiagonal eigen-solves of the checks, [2] A~, [3] eigenvalues
    of A~, [4] eigenvectors, [5] G, [6] lift operand write, and of [0]: [7] matrix-vector
-   products, [8] reorthogonalisation, [9] norm, checks and next vector; [10], [11] unused.
+   products, [8] reorthogonalisation, [9] norm and next vector, [10] multisection of the
+   checks, [11] tridiagonal inverse iteration, [12] Ritz vectors Q Z; [13..15] unused.
    Errors: INVALID_ARG. */
-cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms12);
+cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms16);
 
 /* Force (1) or release (0) the float64 small linear algebra on the host instead of the
    device workgroup solve (which runs for 16-byte aligned uint8 videos with m <= 1025).

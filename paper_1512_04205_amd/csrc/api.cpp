@@ -134,7 +134,7 @@ struct cdmd_model {
   bool timing = false, recon_pending = false;
   bool force_valu_lift = false;  // test hook: use the float32 VALU lift for uint8 video
   bool force_host_la = false;    // test hook: float64 small LA on the host
-  double la_phase_ms[12] = {};
+  double la_phase_ms[16] = {};
   // device small LA (one workgroup)
   bool device_la_ok = false;     // sized at create
   bool device_la = false;        // used by the last fit
@@ -525,6 +525,9 @@ cdmd_status take_device_la(cdmd_model* M) {
   M->la_phase_ms[7] = tt[10] * f;
   M->la_phase_ms[8] = tt[11] * f;
   M->la_phase_ms[9] = tt[12] * f;
+  M->la_phase_ms[10] = tt[13] * f;
+  M->la_phase_ms[11] = tt[14] * f;
+  M->la_phase_ms[12] = tt[15] * f;
   return CDMD_OK;
 }
 
@@ -909,9 +912,14 @@ struct TuneChoice {
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice> g_tune;
 
+// Size class: the frame size, frames in steps of 128, ranks in steps of 8, sketch rows by
+// octave, and the sketch / precision / pixel type.
 TuneKey tune_key(const cdmd_model* M) {
   const cdmd_config& c = M->cfg;
-  return TuneKey{M->n, M->m, M->k, M->p, (int)c.sketch, (int)c.sketch_prec, (int)c.lift_prec, (int)c.dtype};
+  int po = 0;
+  while ((1 << (po + 1)) <= M->p) ++po;
+  return TuneKey{M->n, (M->m + 127) / 128, (M->k + 7) / 8, po, (int)c.sketch, (int)c.sketch_prec,
+                 (int)c.lift_prec, (int)c.dtype};
 }
 
 template <class F>
@@ -983,7 +991,7 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
       for (int target : {512, 1024, 2048}) {
         TRY(apply_gauss_target(M, target));
         double ms = 0.0;
-        TRY(time_ms(st, 2, [&] {
+        TRY(time_ms(st, 1, [&] {
           HIPCHK(cdmd::k::sketch_gauss(d_video, M->cfg.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p,
                                        M->cfg.seed, M->cfg.sketch_prec == CDMD_PREC_BF16 ? 1 : 0, M->gplan,
                                        M->d_gpart, M->d_Yd, st));
@@ -1583,10 +1591,10 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
   return CDMD_OK;
 }
 
-cdmd_status cdmd_dbg_la_phases(const cdmd_model* M, double* ms12) {
+cdmd_status cdmd_dbg_la_phases(const cdmd_model* M, double* ms16) {
   g_err.clear();
-  if (!M || !ms12) return fail(CDMD_E_INVALID_ARG, "NULL argument");
-  for (int i = 0; i < 12; ++i) ms12[i] = M->la_phase_ms[i];
+  if (!M || !ms16) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  for (int i = 0; i < 16; ++i) ms16[i] = M->la_phase_ms[i];
   return CDMD_OK;
 }
 

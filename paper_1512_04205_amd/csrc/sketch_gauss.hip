@@ -16,7 +16,8 @@
 //    rounded to bfloat16 (ties to even); uint8 pixels are exact in bfloat16; products on
 //    BF16 MFMA (32x32x16) with float32 accumulation, float64 across slices.
 //
-// Work split: a workgroup owns 64 sketch rows x a tile of frames x a slice of pixels.
+// Work split: a workgroup owns 64 sketch rows x a tile of frames (up to 1024) x a slice
+// of pixels.
 // It draws its 64-row C tile once per pixel step into LDS (each entry drawn once per
 // frame tile) and reads the video bytes straight into MFMA operands.  Block b serves
 // (slice, frame tile) combination b mod combos and row tile b / combos, so the row tiles
@@ -104,20 +105,22 @@ __device__ __forceinline__ bf16x8_t u8x8_to_bf16(uint32_t lo, uint32_t hi) {
 }
 
 // ------------------------------------------------------------------------ BF16 form
-constexpr int GB_ROWS = 64;  // sketch rows per workgroup (2 MFMA row blocks)
-constexpr int GB_KT = 32;    // pixels per step (2 MFMA k-steps)
-constexpr int GB_AS = 40;    // LDS row stride of the C tile (bf16 elements)
+constexpr int GB_ROWS = 64;   // sketch rows per workgroup (2 MFMA row blocks)
+constexpr int GB_KT = 64;     // pixels per step (4 MFMA k-steps)
+constexpr int GB_AS = 72;     // LDS row stride of the C tile (bf16 elements)
+constexpr int GB_NW = 8;      // waves per workgroup
 
-// NFB: 32-frame blocks per wave (frames per workgroup = 128 NFB).  Video: uint8,
+// NFB: 32-frame blocks per wave (frames per workgroup = 32 NFB GB_NW).  Video: uint8,
 // frames 16-byte aligned (ld % 16 == 0, aligned base).  K order inside a step: lane half h
-// of a wave reads pixels [16h, 16h + 16) of its frame with one 16-byte load; k-step ks
-// takes pixels 16h + 8ks + (0..7).  The C tile uses the same order.
+// of a wave reads pixels [32h, 32h + 32) of its frame with two 16-byte loads; k-step ks
+// takes pixels 32h + 8ks + (0..7).  The C tile is stored in pixel order, so the A
+// fragment of (row, h, ks) is the 16 bytes at pixel 32h + 8ks.
 template <int NFB>
-__global__ __launch_bounds__(256) void k_sketch_gauss_bf16(const uint8_t* __restrict__ D, int64_t ld,
-                                                          int64_t n, int64_t m, int p, uint64_t seed,
-                                                          int64_t pps, int nft, int nsplit,
-                                                          float* __restrict__ part) {
-  constexpr int FRAMES = 128 * NFB;
+__global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t* __restrict__ D, int64_t ld,
+                                                                 int64_t n, int64_t m, int p, uint64_t seed,
+                                                                 int64_t pps, int nft, int nsplit,
+                                                                 float* __restrict__ part) {
+  constexpr int FRAMES = 32 * NFB * GB_NW;
   __shared__ __attribute__((aligned(16))) uint16_t sA[2][GB_ROWS * GB_AS];
   const int combos = nft * nsplit;
   const int cidx = blockIdx.x % combos, rt = blockIdx.x / combos;
@@ -131,7 +134,7 @@ __global__ __launch_bounds__(256) void k_sketch_gauss_bf16(const uint8_t* __rest
   const int h = l >> 5, lc = l & 31;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
   // drawing role: row gr, pixels 8 gg .. 8 gg + 7 of the step
-  const int gr = tid >> 2, gg = tid & 3;
+  const int gr = tid >> 3, gg = tid & 7;
   const int grow = r0 + gr;
 
   auto draw = [&](int buf, int64_t j0) {
@@ -151,30 +154,32 @@ __global__ __launch_bounds__(256) void k_sketch_gauss_bf16(const uint8_t* __rest
         q[2 * half + 1] = bf16_bits_rne(z[2]) | (bf16_bits_rne(z[3]) << 16);
       }
     }
-    // row gr, pixels 8 gg .. +7 -> stored at their k position (identity: 8 gg is
-    // 16 h + 8 ks with h = gg / 2, ks = gg % 2)
     *reinterpret_cast<uint4*>(&sA[buf][gr * GB_AS + 8 * gg]) = make_uint4(q[0], q[1], q[2], q[3]);
   };
 
   // this lane's frames: t0 + 32 NFB w + 32 fb + lc (wave w owns 32 NFB frames)
-  uint4 bcur[NFB], bnext[NFB];
-  auto load_b = [&](uint4* dst, int64_t j0) {
-    const int64_t j = j0 + 16 * h;
+  uint4 bcur[NFB][2], bnext[NFB][2];
+  auto load_b = [&](uint4 (*dst)[2], int64_t j0) {
+    const int64_t j = j0 + 32 * h;
 #pragma unroll
     for (int fb = 0; fb < NFB; ++fb) {
       const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
-      uint4 v = make_uint4(0u, 0u, 0u, 0u);
-      if (t < m && j < je) {
-        const uint8_t* src = D + t * ld + j;
-        if (j + 16 <= je) {
-          v = *reinterpret_cast<const uint4*>(src);
-        } else {
-          uint32_t wv[4] = {0u, 0u, 0u, 0u};
-          for (int e = 0; e < 16 && j + e < je; ++e) wv[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
-          v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int64_t ju = j + 16 * u;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (t < m && ju < je) {
+          const uint8_t* src = D + t * ld + ju;
+          if (ju + 16 <= je) {
+            v = *reinterpret_cast<const uint4*>(src);
+          } else {
+            uint32_t wv[4] = {0u, 0u, 0u, 0u};
+            for (int e = 0; e < 16 && ju + e < je; ++e) wv[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+            v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+          }
         }
+        dst[fb][u] = v;
       }
-      dst[fb] = v;
     }
   };
 
@@ -198,14 +203,15 @@ __global__ __launch_bounds__(256) void k_sketch_gauss_bf16(const uint8_t* __rest
     const bool more = st + 1 < nsteps;
     if (more) load_b(bnext, jn);
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
+    for (int ks = 0; ks < 4; ++ks) {
       bf16x8_t a[2];
 #pragma unroll
       for (int rb = 0; rb < 2; ++rb)
-        a[rb] = *reinterpret_cast<const bf16x8_t*>(&sA[buf][(32 * rb + lc) * GB_AS + 16 * h + 8 * ks]);
+        a[rb] = *reinterpret_cast<const bf16x8_t*>(&sA[buf][(32 * rb + lc) * GB_AS + 32 * h + 8 * ks]);
 #pragma unroll
       for (int fb = 0; fb < NFB; ++fb) {
-        const bf16x8_t b = ks ? u8x8_to_bf16(bcur[fb].z, bcur[fb].w) : u8x8_to_bf16(bcur[fb].x, bcur[fb].y);
+        const uint4 v = bcur[fb][ks >> 1];
+        const bf16x8_t b = (ks & 1) ? u8x8_to_bf16(v.z, v.w) : u8x8_to_bf16(v.x, v.y);
 #pragma unroll
         for (int rb = 0; rb < 2; ++rb)
           acc[rb][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b, acc[rb][fb], 0, 0, 0);
@@ -214,7 +220,10 @@ __global__ __launch_bounds__(256) void k_sketch_gauss_bf16(const uint8_t* __rest
     if (more) draw(buf ^ 1, jn);
     __syncthreads();
 #pragma unroll
-    for (int fb = 0; fb < NFB; ++fb) bcur[fb] = bnext[fb];
+    for (int fb = 0; fb < NFB; ++fb) {
+      bcur[fb][0] = bnext[fb][0];
+      bcur[fb][1] = bnext[fb][1];
+    }
   }
   // accumulators: lane l, register e -> row 32 rb + 8 (e / 4) + 4 h + e % 4, frame lc
   float* out = part + (int64_t)s * m * p;
@@ -375,7 +384,7 @@ GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target) {
   const int rows = bf ? GB_ROWS : GF_ROWS;
   const int kt = bf ? GB_KT : GF_KT;
   int frames = 256;
-  if (bf) frames = m <= 128 ? 128 : m <= 256 ? 256 : 512;
+  if (bf) frames = m <= 256 ? 256 : m <= 512 ? 512 : 1024;
   g.frames = frames;
   g.nrt = (p + rows - 1) / rows;
   g.nft = (int)((m + frames - 1) / frames);
@@ -399,12 +408,13 @@ hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t
   const dim3 grid((unsigned)g.blocks), block(256);
   if (prec == 1) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
-    if (g.frames == 128)
-      hipLaunchKernelGGL(k_sketch_gauss_bf16<1>, grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
-    else if (g.frames == 256)
-      hipLaunchKernelGGL(k_sketch_gauss_bf16<2>, grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    const dim3 bb(64 * GB_NW);
+    if (g.frames == 256)
+      hipLaunchKernelGGL(k_sketch_gauss_bf16<1>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    else if (g.frames == 512)
+      hipLaunchKernelGGL(k_sketch_gauss_bf16<2>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
     else
-      hipLaunchKernelGGL(k_sketch_gauss_bf16<4>, grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+      hipLaunchKernelGGL(k_sketch_gauss_bf16<4>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
   } else if (dtype == 0) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
     const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 3) == 0;

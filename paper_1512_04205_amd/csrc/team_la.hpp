@@ -84,11 +84,14 @@ struct LanczosWork {
   int64_t fast_doubles;  // work when it fits, and later scratch
 };
 
-// Deterministic start vectors: entry i of vector `salt` is 1 + u - 1/2 with u in [0, 1)
-// from an integer hash of (i, salt) (the splitmix64 finaliser), so vectors of different
-// salts are independent (restarts after a breakdown need a fresh direction each time)
-// and host and device produce the same bits.
+// Deterministic start vectors.  The first (salt 0) is the smooth profile
+// 1 + sin(0.7 (i + 1)) / 4: the Gram is indexed by frames and its leading eigenvectors are
+// slow functions of time, which such a vector overlaps well.  Restart vectors (salt > 0)
+// take entry i as 1 + u - 1/2 with u in [0, 1) from an integer hash of (i, salt) (the
+// splitmix64 finaliser), so each restart brings a fresh independent direction; host and
+// device produce the same bits.
 TLA_HD inline double lanczos_start(int i, int salt) {
+  if (salt == 0) return 1.0 + 0.25 * sin(0.7 * (i + 1));
   uint64_t x = (uint64_t)(uint32_t)i * 0x9E3779B97F4A7C15ull + (uint64_t)(uint32_t)salt * 0xD1B54A32D192ED03ull;
   x ^= x >> 30;
   x *= 0xBF58476D1CE4E5B9ull;
@@ -109,12 +112,55 @@ TLA_HD inline int sturm_count(TM& tm, const double* a, const double* b2, int J, 
   double q = a[0] - x;
   if (fabs(q) < pivmin) q = -pivmin;
   int c = q < 0.0 ? 1 : 0;
-  for (int i = 1; i < J; ++i) {
+  int i = 1;
+  for (; i + 4 <= J; i += 4) {  // operands of four steps loaded ahead of the pivot chain
+    double av[4], bv[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      av[u] = a[i + u] - x;
+      bv[u] = b2[i + u - 1];
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      q = av[u] - bv[u] * tm.recip(q);
+      if (fabs(q) < pivmin) q = -pivmin;
+      c += q < 0.0 ? 1 : 0;
+    }
+  }
+  for (; i < J; ++i) {
     q = (a[i] - x) - b2[i - 1] * tm.recip(q);
     if (fabs(q) < pivmin) q = -pivmin;
     c += q < 0.0 ? 1 : 0;
   }
   return c;
+}
+
+// Modulus of the last component of the unit eigenvector of the symmetric tridiagonal
+// (a, b2 = squared off-diagonals) for its eigenvalue th: z_J^2 = d_{J-1}(th) / d_J'(th)
+// with d_i the characteristic polynomial of the leading i x i block (the residue of
+// ((x - T)^-1)_{JJ} = d_{J-1}(x) / d_J(x) at th).  Forward three-term recurrences for d
+// and d', rescaled together (the ratio is unchanged) to stay in range.
+TLA_HD inline double tridiag_last_component(const double* a, const double* b2, int J, double th) {
+  double dm = 1.0, d = th - a[0];   // d_{i-1}, d_i
+  double pm = 0.0, pd = 1.0;        // d'_{i-1}, d'_i
+  for (int i = 1; i < J; ++i) {
+    const double xa = th - a[i], bb = b2[i - 1];
+    const double dn = xa * d - bb * dm;
+    const double pn = d + xa * pd - bb * pm;
+    dm = d;
+    d = dn;
+    pm = pd;
+    pd = pn;
+    const double big = fmax(fmax(fabs(d), fabs(dm)), fmax(fabs(pd), fabs(pm)));
+    if (big > 1e150) {
+      dm *= 1e-150; d *= 1e-150; pm *= 1e-150; pd *= 1e-150;
+    } else if (big < 1e-150 && big > 0.0) {
+      dm *= 1e150; d *= 1e150; pm *= 1e150; pd *= 1e150;
+    }
+  }
+  if (!(pd != 0.0)) return 1.0;  // repeated eigenvalue: no estimate, not converged
+  const double z2 = fabs(dm / pd);
+  return z2 >= 1.0 ? 1.0 : sqrt(z2);
 }
 
 // The kk largest eigenvalues (descending) of the symmetric tridiagonal (a, b), J x J,
@@ -414,6 +460,7 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
       // Ritz values of T_J by multisection, Ritz vectors of T_J by inverse iteration; the
       // residual of Ritz pair i is beta_J |z_{J-1,i}|
       tm.stamp(0);
+      tm.tick(12);
       const int kk = k < J ? k : J;
       const int64_t need = J + kk + 6 * (int64_t)J * kk;
       double* b2 = ws.fast != nullptr && need <= ws.fast_doubles ? ws.fast : ws.T;
@@ -424,17 +471,31 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
       tm.sync();
       double tnorm = 0.0;
       tridiag_topk_values(tm, ws.alpha, ws.beta, b2, J, kk, theta, &tnorm);
-      tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, false, work, Zm);
-      tm.stamp(1);
-      bool conv = J >= k;
+      tm.tick(13);
+      // Residual of Ritz pair i: beta_J |z_{J-1,i}|.  The closed form of the last
+      // components is exact where they are large but has an absolute floor near
+      // sqrt(eps): it can show that a pair has not converged, not that it has.  Only
+      // when it cannot decide are the Ritz vectors of T_J computed (inverse iteration).
       const double scale = fabs(theta[0]) > 0 ? fabs(theta[0]) : 1e-300;
-      if (conv)
+      double* zl = Zm;
+      for (int r = tm.tid; r < kk; r += tm.nt) zl[r] = tridiag_last_component(ws.alpha, b2, J, theta[r]);
+      tm.sync();
+      bool conv = J >= k;
+      for (int i = 0; i < kk && conv; ++i)
+        if (zl[i] > 1e-6 && nr * zl[i] > rtol * scale) conv = false;
+      tm.sync();
+      if (conv) {
+        tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, false, work, Zm);
         for (int i = 0; i < k; ++i)
           if (nr * fabs(Zm[(int64_t)(J - 1) * kk + i]) > rtol * scale) conv = false;
+      }
+      tm.tick(14);
+      tm.stamp(1);
       if (conv || J == N || J == Jmax) {
         if (J < k) return -1;
         // final Ritz vectors: members of eigenvalue clusters orthogonalised
         tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, true, work, Zm);
+        tm.tick(14);
         for (int i = tm.tid; i < k; i += tm.nt) evals[i] = theta[i];
         // V = Q_J Z_k
         for (int e = tm.tid; e < N * k; e += tm.nt) {
@@ -458,9 +519,10 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
           for (int t = tm.lane; t < N; t += tm.wsize) vc[t] *= inv;
         }
         tm.sync();
+        tm.tick(15);
         return conv || J == N ? J : -1;
       }
-      check = J + (J / 4 > 16 ? J / 4 : 16);
+      check = J + 8;
       if (check > Jmax) check = Jmax;
       if (breakdown) {
         // invariant subspace found before k pairs converged: restart orthogonally

@@ -78,7 +78,8 @@ def test_gaussian_sketch_fp32_form(case):
 
 
 @pytest.mark.parametrize("case", [(90, 160, 40, 100), (37, 64, 21, 70), (48, 96, 300, 130),
-                                  (40, 64, 200, 70), (30, 32, 129, 65)])
+                                  (40, 64, 200, 70), (30, 32, 129, 65), (20, 48, 560, 64),
+                                  (16, 80, 1000, 130)])
 def test_gaussian_sketch_bf16_form(case):
     H, W, m, p = case
     _say("gauss bf16 sketch", case)
