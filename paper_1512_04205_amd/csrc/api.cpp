@@ -192,6 +192,11 @@ cdmd_status halloc(T** p, size_t count) {
     if (_s != CDMD_OK) return _s;      \
   } while (0)
 
+// Gaussian sketch form for the kernels: 0 FP32, 1 BF16, 2 FP8.
+int gauss_prec(const cdmd_config& c) {
+  return c.sketch_prec == CDMD_PREC_BF16 ? 1 : c.sketch_prec == CDMD_PREC_FP8 ? 2 : 0;
+}
+
 cdmd_status validate(const cdmd_config* c) {
   if (!c) return fail(CDMD_E_INVALID_ARG, "config is NULL");
   if (c->m < 2) return fail(CDMD_E_INVALID_ARG, "need m >= 2 frames");
@@ -220,10 +225,8 @@ cdmd_status validate(const cdmd_config* c) {
   if (c->k > 40) return fail(CDMD_E_UNSUPPORTED, "k > 40 is not built");
   if (c->n >= (int64_t)1 << 31) return fail(CDMD_E_UNSUPPORTED, "n >= 2^31 pixels is not built");
   if (c->sketch == CDMD_SKETCH_GAUSSIAN) {
-    if (c->sketch_prec == CDMD_PREC_FP8)
-      return fail(CDMD_E_UNSUPPORTED, "the FP8 Gaussian sketch is not built in this library version");
-    if (c->sketch_prec == CDMD_PREC_BF16 && (c->dtype != CDMD_U8 || c->ld % 16 != 0))
-      return fail(CDMD_E_UNSUPPORTED, "the BF16 Gaussian sketch needs a uint8 video with ld % 16 == 0");
+    if (c->sketch_prec != CDMD_PREC_FP32 && (c->dtype != CDMD_U8 || c->ld % 16 != 0))
+      return fail(CDMD_E_UNSUPPORTED, "the BF16 / FP8 Gaussian sketch needs a uint8 video with ld % 16 == 0");
     if ((int64_t)c->p * c->m > ((int64_t)1 << 31))
       return fail(CDMD_E_UNSUPPORTED, "p * m >= 2^31 is not built");
   } else if (c->sketch_prec != CDMD_PREC_FP32) {
@@ -385,10 +388,10 @@ cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool 
   const cdmd_config& c = M->cfg;
   M->mark(0, st);
   if (M->gauss) {
-    if (c.sketch_prec == CDMD_PREC_BF16 && (reinterpret_cast<uintptr_t>(d_video) & 15) != 0)
-      return fail(CDMD_E_UNSUPPORTED, "the BF16 Gaussian sketch needs a 16-byte aligned video");
+    if (c.sketch_prec != CDMD_PREC_FP32 && (reinterpret_cast<uintptr_t>(d_video) & 15) != 0)
+      return fail(CDMD_E_UNSUPPORTED, "the BF16 / FP8 Gaussian sketch needs a 16-byte aligned video");
     HIPCHK(cdmd::k::sketch_gauss(d_video, c.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p, c.seed,
-                                 c.sketch_prec == CDMD_PREC_BF16 ? 1 : 0, M->gplan, M->d_gpart, M->d_Yd, st));
+                                 gauss_prec(c), M->gplan, M->d_gpart, M->d_Yd, st));
     M->mark(1, st);
     HIPCHK(cdmd::k::gram_f64(M->d_Yd, M->p, M->m, M->d_gram, st));
   } else if (c.dtype == CDMD_U8) {
@@ -705,7 +708,7 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
   const int64_t m = M->m, p = M->p;
   if (cfg->sketch == CDMD_SKETCH_GAUSSIAN) {
     M->gauss = true;
-    M->gplan = cdmd::k::gauss_plan(M->n, m, (int)p, cfg->sketch_prec == CDMD_PREC_BF16 ? 1 : 0, 1024);
+    M->gplan = cdmd::k::gauss_plan(M->n, m, (int)p, gauss_prec(*cfg), 1024);
     M->gpart_cap = (size_t)M->gplan.nsplit * m * p;
     TRY(dalloc(&M->d_gpart, M->gpart_cap));
     TRY(dalloc(&M->d_Yd, (size_t)m * p));
@@ -946,8 +949,7 @@ cdmd_status time_ms(hipStream_t st, int reps, F&& launch, double* ms) {
 }
 
 cdmd_status apply_gauss_target(cdmd_model* M, int target) {
-  cdmd::k::GaussPlan g = cdmd::k::gauss_plan(M->n, M->m, (int)M->p,
-                                             M->cfg.sketch_prec == CDMD_PREC_BF16 ? 1 : 0, target);
+  cdmd::k::GaussPlan g = cdmd::k::gauss_plan(M->n, M->m, (int)M->p, gauss_prec(M->cfg), target);
   const size_t need = (size_t)g.nsplit * M->m * M->p;
   if (need > M->gpart_cap) {
     float* np = nullptr;
@@ -993,8 +995,7 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
         double ms = 0.0;
         TRY(time_ms(st, 1, [&] {
           HIPCHK(cdmd::k::sketch_gauss(d_video, M->cfg.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p,
-                                       M->cfg.seed, M->cfg.sketch_prec == CDMD_PREC_BF16 ? 1 : 0, M->gplan,
-                                       M->d_gpart, M->d_Yd, st));
+                                       M->cfg.seed, gauss_prec(M->cfg), M->gplan, M->d_gpart, M->d_Yd, st));
           return CDMD_OK;
         }, &ms));
         if (ms < best) best = ms, ch.gauss_target = target;

@@ -33,7 +33,8 @@ hipError_t sketch_sparse_f32(const float* D, int64_t ld, int64_t m, const int32_
 // ----- sketch, dense Gaussian (entries drawn on the fly) --------------------------
 // prec 0: FP32 form (float64 Box-Muller rounded to float32, FP32 MFMA; dtype 0 uint8 or
 // 1 float32 video); prec 1: BF16 form (float32 Box-Muller rounded to bfloat16, BF16
-// MFMA; uint8 video with 16-byte aligned frames only).  part: nsplit * m * p floats of
+// MFMA); prec 2: FP8 form (rounded to e4m3, pixel bytes split into two exact e4m3
+// operands, FP8 MFMA).  BF16 and FP8: uint8 video with 16-byte aligned frames only.  part: nsplit * m * p floats of
 // per-slice partial sums; Y[t][r] = (1/sqrt(p)) * sum over slices (float64, m x p).
 struct GaussPlan {
   int nrt, nft, nsplit, frames;

@@ -15,6 +15,8 @@
 //  * BF16: the normals are computed in float32 with the hardware log/sqrt/sin/cos and
 //    rounded to bfloat16 (ties to even); uint8 pixels are exact in bfloat16; products on
 //    BF16 MFMA (32x32x16) with float32 accumulation, float64 across slices.
+//  * FP8: as BF16 with the normals rounded to OCP e4m3 and each pixel byte split into
+//    two exact e4m3 operands (16 hi, lo) on FP8 MFMA.
 //
 // Work split: a workgroup owns 64 sketch rows x a tile of frames (up to 1024) x a slice
 // of pixels.
@@ -241,6 +243,170 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
   }
 }
 
+// ------------------------------------------------------------------------ FP8 form
+// OCP e4m3fn (bias 7, 3 mantissa bits, largest finite 448, no infinities): round to
+// nearest, ties to even, saturating to +-448; below 2^-6 the subnormal grid of 2^-9.
+__device__ __forceinline__ uint32_t e4m3_rne(float x) {
+  const uint32_t sign = (__float_as_uint(x) >> 24) & 0x80u;
+  const float a = fabsf(x);
+  if (!(a < 448.0f)) return sign | 0x7Eu;
+  if (a < 0x1p-6f) return sign | (uint32_t)rintf(a * 512.0f);  // 8 gives 0x08 = 2^-6
+  uint32_t u = __float_as_uint(a);
+  u += 0x7ffffu + ((u >> 20) & 1u);  // round the float mantissa to 3 bits
+  const uint32_t e = (u >> 23) - 127u + 7u, mant = (u >> 20) & 7u;
+  return sign | (e << 3) | mant;
+}
+
+// e4m3 codes of the integers v (lut_lo) and 16 v (lut_hi), v = 0..15, as byte tables
+// for v_perm_b32: entries 0..7 in (t0h:t0l), 8..15 in (t1h:t1l).
+__device__ __forceinline__ uint32_t nibble_codes(uint32_t nib4, uint32_t t0l, uint32_t t0h, uint32_t t1l,
+                                                 uint32_t t1h) {
+  const uint32_t idx = nib4 & 0x07070707u;
+  const uint32_t r0 = __builtin_amdgcn_perm(t0h, t0l, idx);
+  const uint32_t r1 = __builtin_amdgcn_perm(t1h, t1l, idx);
+  const uint32_t m = ((nib4 >> 3) & 0x01010101u) * 0xFFu;
+  return (r1 & m) | (r0 & ~m);
+}
+
+// As the BF16 form with C rounded to e4m3 and each video byte u = 16 hi + lo split into
+// two exact e4m3 operands (16 hi and lo), multiplied by two FP8 MFMAs (32x32x16) into the
+// same float32 accumulator: only C is quantised.
+template <int NFB>
+__global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* __restrict__ D, int64_t ld,
+                                                                int64_t n, int64_t m, int p, uint64_t seed,
+                                                                int64_t pps, int nft, int nsplit,
+                                                                float* __restrict__ part) {
+  constexpr int FRAMES = 32 * NFB * GB_NW;
+  constexpr int AS = 80;  // LDS row stride of the C tile (bytes)
+  __shared__ __attribute__((aligned(16))) uint8_t sA[2][GB_ROWS * AS];
+  const int combos = nft * nsplit;
+  const int cidx = blockIdx.x % combos, rt = blockIdx.x / combos;
+  const int s = cidx / nft, ft = cidx % nft;
+  const int r0 = rt * GB_ROWS;
+  const int64_t t0 = (int64_t)ft * FRAMES;
+  const int64_t jb = (int64_t)s * pps;
+  int64_t je = jb + pps;
+  if (je > n) je = n;
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int h = l >> 5, lc = l & 31;
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const int gr = tid >> 3, gg = tid & 7;
+  const int grow = r0 + gr;
+  // code tables: v -> e4m3(v) and v -> e4m3(16 v)
+  const uint32_t L0l = 0x44403800u, L0h = 0x4E4C4A48u, L1l = 0x53525150u, L1h = 0x57565554u;
+  const uint32_t H0l = 0x64605800u, H0h = 0x6E6C6A68u, H1l = 0x73727170u, H1h = 0x77767574u;
+
+  auto draw = [&](int buf, int64_t j0) {
+    const int64_t j = j0 + 8 * gg;
+    uint32_t q[2] = {0u, 0u};
+    if (grow < p && j < je) {
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const Words4 wd = philox4x32_10((uint32_t)((j >> 2) + half), (uint32_t)grow, k0, k1);
+        float z[4];
+        box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
+        box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+        uint32_t word = 0u;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t c = j + 4 * half + e >= je ? 0u : e4m3_rne(z[e]);
+          word |= c << (8 * e);
+        }
+        q[half] = word;
+      }
+    }
+    *reinterpret_cast<uint2*>(&sA[buf][gr * AS + 8 * gg]) = make_uint2(q[0], q[1]);
+  };
+
+  uint4 bcur[NFB][2], bnext[NFB][2];
+  auto load_b = [&](uint4 (*dst)[2], int64_t j0) {
+    const int64_t j = j0 + 32 * h;
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb) {
+      const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const int64_t ju = j + 16 * u;
+        uint4 v = make_uint4(0u, 0u, 0u, 0u);
+        if (t < m && ju < je) {
+          const uint8_t* src = D + t * ld + ju;
+          if (ju + 16 <= je) {
+            v = *reinterpret_cast<const uint4*>(src);
+          } else {
+            uint32_t wv[4] = {0u, 0u, 0u, 0u};
+            for (int e = 0; e < 16 && ju + e < je; ++e) wv[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+            v = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+          }
+        }
+        dst[fb][u] = v;
+      }
+    }
+  };
+
+  f32x16_t acc[2][NFB];
+#pragma unroll
+  for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) acc[rb][fb][e] = 0.f;
+
+  const int64_t nsteps = je > jb ? (je - jb + GB_KT - 1) / GB_KT : 0;
+  if (nsteps > 0) {
+    draw(0, jb);
+    load_b(bcur, jb);
+  }
+  __syncthreads();
+  for (int64_t st = 0; st < nsteps; ++st) {
+    const int buf = (int)(st & 1);
+    const int64_t jn = jb + (st + 1) * GB_KT;
+    const bool more = st + 1 < nsteps;
+    if (more) load_b(bnext, jn);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      long a[2];
+#pragma unroll
+      for (int rb = 0; rb < 2; ++rb)
+        a[rb] = *reinterpret_cast<const long*>(&sA[buf][(32 * rb + lc) * AS + 32 * h + 8 * ks]);
+#pragma unroll
+      for (int fb = 0; fb < NFB; ++fb) {
+        const uint4 v = bcur[fb][ks >> 1];
+        const uint32_t w0 = (ks & 1) ? v.z : v.x, w1 = (ks & 1) ? v.w : v.y;
+        const uint32_t lo0 = nibble_codes(w0 & 0x0F0F0F0Fu, L0l, L0h, L1l, L1h);
+        const uint32_t lo1 = nibble_codes(w1 & 0x0F0F0F0Fu, L0l, L0h, L1l, L1h);
+        const uint32_t hi0 = nibble_codes((w0 >> 4) & 0x0F0F0F0Fu, H0l, H0h, H1l, H1h);
+        const uint32_t hi1 = nibble_codes((w1 >> 4) & 0x0F0F0F0Fu, H0l, H0h, H1l, H1h);
+        const long blo = (long)(((uint64_t)lo1 << 32) | lo0), bhi = (long)(((uint64_t)hi1 << 32) | hi0);
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+          acc[rb][fb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a[rb], bhi, acc[rb][fb], 0, 0, 0);
+          acc[rb][fb] = __builtin_amdgcn_mfma_f32_32x32x16_fp8_fp8(a[rb], blo, acc[rb][fb], 0, 0, 0);
+        }
+      }
+    }
+    if (more) draw(buf ^ 1, jn);
+    __syncthreads();
+#pragma unroll
+    for (int fb = 0; fb < NFB; ++fb) {
+      bcur[fb][0] = bnext[fb][0];
+      bcur[fb][1] = bnext[fb][1];
+    }
+  }
+  float* out = part + (int64_t)s * m * p;
+#pragma unroll
+  for (int fb = 0; fb < NFB; ++fb) {
+    const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
+    if (t >= m) continue;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+      for (int e = 0; e < 16; ++e) {
+        const int r = r0 + 32 * rb + 8 * (e >> 2) + 4 * h + (e & 3);
+        if (r < p) out[t * p + r] = acc[rb][fb][e];
+      }
+  }
+}
+
 // ------------------------------------------------------------------------ FP32 form
 constexpr int GF_ROWS = 64;  // sketch rows per workgroup (4 MFMA row blocks of 16)
 constexpr int GF_KT = 16;    // pixels per step (4 MFMA k-steps)
@@ -380,7 +546,7 @@ __global__ __launch_bounds__(256) void k_reduce_gauss(const float* __restrict__ 
 
 GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target) {
   GaussPlan g{};
-  const bool bf = prec == 1;
+  const bool bf = prec == 1 || prec == 2;
   const int rows = bf ? GB_ROWS : GF_ROWS;
   const int kt = bf ? GB_KT : GF_KT;
   int frames = 256;
@@ -415,6 +581,15 @@ hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t
       hipLaunchKernelGGL(k_sketch_gauss_bf16<2>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
     else
       hipLaunchKernelGGL(k_sketch_gauss_bf16<4>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+  } else if (prec == 2) {
+    const uint8_t* d = static_cast<const uint8_t*>(D);
+    const dim3 bb(64 * GB_NW);
+    if (g.frames == 256)
+      hipLaunchKernelGGL(k_sketch_gauss_fp8<1>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    else if (g.frames == 512)
+      hipLaunchKernelGGL(k_sketch_gauss_fp8<2>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    else
+      hipLaunchKernelGGL(k_sketch_gauss_fp8<4>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
   } else if (dtype == 0) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
     const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 3) == 0;

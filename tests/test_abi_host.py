@@ -76,7 +76,7 @@ def _cfg_kwargs(**kw):
           sign=np.ones((50, 1), np.int8)), P.E_INVALID_ARG),           # repeated pixels
     (dict(k=41, m=100, p=100, n=1000), P.E_UNSUPPORTED),
     (dict(sketch_prec=P.PREC_BF16), P.E_UNSUPPORTED),                  # sparse sums are exact
-    (dict(sketch=P.SKETCH_GAUSSIAN, idx=None, sketch_prec=P.PREC_FP8), P.E_UNSUPPORTED),
+    (dict(sketch=P.SKETCH_GAUSSIAN, idx=None, sketch_prec=P.PREC_FP8, dtype=P.F32), P.E_UNSUPPORTED),
     (dict(sketch=P.SKETCH_GAUSSIAN, idx=None, sketch_prec=P.PREC_BF16, dtype=P.F32), P.E_UNSUPPORTED),
     (dict(sketch=P.SKETCH_GAUSSIAN, idx=None, sketch_prec=P.PREC_BF16, ld=1004), P.E_UNSUPPORTED),
 ])

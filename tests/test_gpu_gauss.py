@@ -96,6 +96,49 @@ def test_gaussian_sketch_bf16_form(case):
     assert rel <= 1e-4, rel
 
 
+@pytest.mark.parametrize("case", [(90, 160, 40, 100), (37, 64, 21, 70), (20, 48, 560, 64)])
+def test_gaussian_sketch_fp8_form(case):
+    """FP8 form: C rounded to e4m3 (the oracle's round_e4m3 of the float64 normals), pixel
+    bytes exact (two e4m3 halves).  About 2e-5 of the entries round to the neighbouring
+    e4m3 value (2^-3 relative) because the device normals are float32:
+    ||Y_gpu - Y_ref||_F <= 3e-3 ||Y_ref||_F."""
+    H, W, m, p = case
+    _say("gauss fp8 sketch", case)
+    rng = np.random.default_rng(6)
+    n = H * W
+    D = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+    mdl = P.Model(n, m, min(5, m - 1), p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=31,
+                  sketch_prec=P.PREC_FP8)
+    mdl.fit(torch.from_numpy(D).cuda())
+    Yg = mdl.sketch()
+    Y, _ = _ref_sketch(D, 1 / 255, 31, p, R.round_e4m3)
+    rel = np.linalg.norm(Yg - Y) / np.linalg.norm(Y)
+    assert rel <= 3e-3, rel
+
+
+def test_gaussian_fp8_fit():
+    """Eigenvalues of the FP8 form against the oracle on the same e4m3-quantised C
+    (arithmetic error only: <= 1e-3), and the error the quantisation itself causes against
+    the unquantised float64 oracle (reported; below 5e-2 here)."""
+    _say("gauss fp8 fit")
+    spec = sv.preset("cfg1", H=60, W=80, m=60, bump_sigma=6.0, blur_sigma=3.0, seed=17, rect_side=(8, 8),
+                     out="u8")
+    v = sv.make_video(spec)
+    D = v.D.numpy()
+    n, m = D.shape[1], D.shape[0]
+    mdl = P.Model(n, m, 10, 300, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=5, sketch_prec=P.PREC_FP8)
+    mdl.fit(torch.from_numpy(D).cuda())
+    lam = mdl.modes()["lam"]
+    Yq = R.sketch_gaussian(D, v.scale, 5, 300, quantise=R.round_e4m3)
+    lam_q = R.fit(D, v.scale, Yq, 10).lam
+    rel_q, _, _ = eig_rel_err(lam, lam_q)
+    lam_64 = R.run(D, v.scale, 10, sketch="gaussian", p=300, seed=5).model.lam
+    rel_64, _, _ = eig_rel_err(lam, lam_64)
+    _say("fp8 eig err vs quantised-C oracle", rel_q.max(), "vs float64 oracle", rel_64.max())
+    assert rel_q.max() <= 1e-3
+    assert rel_64.max() <= 5e-2
+
+
 def test_gaussian_bf16_needs_aligned_uint8():
     with pytest.raises(P.CdmdError) as e:
         P.Model(1000, 20, 5, 50, sketch=P.SKETCH_GAUSSIAN, dtype=P.F32, sketch_prec=P.PREC_BF16)

@@ -136,6 +136,10 @@ def test_learned_selector_trained_on_omp_labels():
     X = np.concatenate(feats)
     y = np.concatenate(labels)
     _say("training modes", len(y), "positives", int(y.sum()))
+    # train on standardised features, then fold the standardisation into the first layer
+    # so that the network reads the raw features the library computes
+    mu, sd = X.mean(axis=0), X.std(axis=0) + 1e-6
+    X = (X - mu) / sd
     th = _dev(sv.mlp_init(7))
     am = torch.zeros(P.MLP_NPARAM, device="cuda")
     av = torch.zeros(P.MLP_NPARAM, device="cuda")
@@ -145,7 +149,12 @@ def test_learned_selector_trained_on_omp_labels():
     losses = P.mlp_train(th, am, av, _dev(X), _dev(y), bi, batch, lr=3e-3).cpu().numpy()
     _say("loss", float(losses[:20].mean()), "->", float(losses[-100:].mean()))
     assert losses[-100:].mean() < 0.85 * losses[:20].mean()
-    f_omp, f_lrn, fallbacks, trials = [], [], 0, 0
+    theta = th.cpu().numpy().astype(np.float64)
+    W1 = theta[:384].reshape(64, 6) / sd[None, :]
+    theta[384:448] -= W1 @ mu
+    theta[:384] = W1.ravel()
+    th = _dev(theta)
+    f_omp, f_lrn, f_raw, fallbacks, trials = [], [], [], 0, 0
     for s in range(12):
         v = _video(9000 + s)
         m, n = v.D.shape
@@ -165,6 +174,11 @@ def test_learned_selector_trained_on_omp_labels():
         fallbacks += int(fb)
         mdl.foreground(v.D, mk, tau)
         f_lrn.append(R.f_measure(P.unpack_mask(mk.cpu().numpy(), n), gt))
-    _say("F omp", np.mean(f_omp), "F learned", np.mean(f_lrn), "fallbacks", fallbacks, "/", trials)
+        # the network alone (confidence 0.5: never falls back unless it selects nothing)
+        S_raw, _, _, fb_raw = mdl.select_learned(th, confidence=0.5, K_fallback=K)
+        mdl.foreground(v.D, mk, tau)
+        f_raw.append(R.f_measure(P.unpack_mask(mk.cpu().numpy(), n), gt))
+    _say("F omp", np.mean(f_omp), "F learned (0.9 + fallback)", np.mean(f_lrn),
+         "F network alone", np.mean(f_raw), "fallbacks", fallbacks, "/", trials)
     assert trials >= 8
     assert np.mean(f_lrn) >= np.mean(f_omp) - 0.02
