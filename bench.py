@@ -241,6 +241,8 @@ def main():
                     help="lift/reconstruction form (cfg2); 'both' times FP32 (the reported value) "
                          "and BF16 side by side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="skip cdmd_autotune before the warm-up (default tile shapes)")
     ap.add_argument("--cpu-band-rows", type=int, default=68)
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run a device-to-device copy of this many MiB first (the reference "
@@ -294,6 +296,10 @@ def main():
             mdl = P.Model(n, m, k, p, sketch=P.SKETCH_SPARSE, dtype=P.U8, idx=idx, sign=sign,
                           lift_prec=lp)
         mdl.set_timing(True)
+        if not args.no_autotune:
+            mdl.autotune(D)
+            log(f"[{prec}] autotuned: lift workgroups {mdl.info()['lift_grid']}, sparse form "
+                f"{mdl.info()['sparse_form']}, Gaussian slices {mdl.info()['sketch_slices']}")
 
         def step():
             mdl.fit(D)
@@ -355,7 +361,9 @@ def main():
                           "bytes": byt, "flops": fl, "flop_peak": fpk}
         lam = mdl.modes()["lam"]
         return {"ms": ms, "fps": m / (ms / 1e3), "avg": avg, "kernels": kernels, "lam": lam,
-                "lanczos": J, "n_sel": S_n}
+                "lanczos": J, "n_sel": S_n,
+                "tiles": {"lift_grid": inf["lift_grid"], "sparse_form": inf["sparse_form"],
+                          "sketch_slices": inf["sketch_slices"]}}
 
     if args.workload == "cfg2":
         forms = ["fp32", "bf16"] if args.prec == "both" else [args.prec]
@@ -430,7 +438,7 @@ def main():
         "eig_reference": ref_kind,
         "forms": {f: {"fps": r["fps"], "ms_per_step": r["ms"], "eig_rel_err_max": r["eig_rel_err_max"],
                       "small_la_ms": round(r["avg"]["small_la"], 3), "lanczos_steps": r["lanczos"],
-                      "n_selected": r["n_sel"],
+                      "n_selected": r["n_sel"], "tiles": r["tiles"],
                       "kernels": {q: {kk: vv for kk, vv in d.items() if kk not in ("bytes", "flops")}
                                   for q, d in r["kernels"].items()}}
                   for f, r in res.items()},

@@ -138,6 +138,9 @@ typedef struct {
   double gpu_ms_sketch, gpu_ms_gram, gpu_ms_lift, gpu_ms_recon;
   int32_t lift_grid;         /* persistent lift workgroups in use (cdmd_autotune may change it) */
   int32_t sketch_slices;     /* pixel slices of the dense Gaussian sketch (0 otherwise) */
+  int32_t sparse_form;       /* after cdmd_autotune: uint8 sparse sketch form, -1 gather
+                                (byte loads per triple), 10 F + V streaming (F frames per
+                                group, V 16-byte vectors per thread); 0 not tuned */
 } cdmd_info;
 
 /* Validate `cfg`, prepare C (the sparse table is copied and reordered on the device)
@@ -194,8 +197,9 @@ cdmd_status cdmd_foreground(const cdmd_model* mdl, const void* d_video, float ta
 /* ---- tile shapes and batches ---------------------------------------------------------
    cdmd_autotune times candidate tile shapes of the model's size class on d_video (the
    number of persistent lift workgroups; for the dense Gaussian sketch the number of
-   pixel slices), keeps the fastest for the model and caches the choice per size class
-   for the process.  Synchronises `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
+   pixel slices; for the sparse sketch of an aligned uint8 video the gather or streaming
+   form and its shape), keeps the fastest for the model and caches the choice per size
+   class for the process.  Synchronises `stream`.  Errors: INVALID_ARG, OUT_OF_MEMORY, DEVICE. */
 cdmd_status cdmd_autotune(cdmd_model* mdl, const void* d_video, void* stream);
 
 /* A batch fits many models (streams of different resolution, frame count, rank and

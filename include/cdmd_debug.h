@@ -54,6 +54,12 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
    Errors: INVALID_ARG. */
 cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms16);
 
+/* Force (1) or release (0) the gather form of the sparse sketch of a uint8 video (one
+   byte load per triple and frame) where the streaming form (coalesced 16-byte loads of
+   every frame, 16-byte aligned frames) would run.  Takes effect at the next cdmd_fit.
+   Errors: INVALID_ARG. */
+cdmd_status cdmd_dbg_force_gather_sketch(cdmd_model* mdl, int32_t on);
+
 /* Force (1) or release (0) the float64 small linear algebra on the host instead of the
    device workgroup solve (which runs for 16-byte aligned uint8 videos with m <= 1025).
    Takes effect at the next cdmd_fit.  Errors: INVALID_ARG. */

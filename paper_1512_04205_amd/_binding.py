@@ -31,6 +31,7 @@ EXPORTED = [
     "cdmd_select", "cdmd_background", "cdmd_foreground", "cdmd_get_sketch",
     "cdmd_info_get", "cdmd_set_timing", "cdmd_free", "cdmd_dbg_force_valu_lift",
     "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases",
+    "cdmd_dbg_force_gather_sketch",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
     "cdmd_batch_free",
@@ -68,6 +69,7 @@ class Info(ctypes.Structure):
         ("gpu_ms_sketch", ctypes.c_double), ("gpu_ms_gram", ctypes.c_double),
         ("gpu_ms_lift", ctypes.c_double), ("gpu_ms_recon", ctypes.c_double),
         ("lift_grid", ctypes.c_int32), ("sketch_slices", ctypes.c_int32),
+        ("sparse_form", ctypes.c_int32),
     ]
 
     def as_dict(self):
@@ -101,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_set_timing.argtypes = [P, I32]
     lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
+    lib.cdmd_dbg_force_gather_sketch.argtypes = [P, I32]
     lib.cdmd_dbg_la_phases.argtypes = [P, DP]
     lib.cdmd_mode_features.argtypes = [P, P, P]
     lib.cdmd_mlp_grad.argtypes = [P, P, P, I32, P, P, P]
@@ -289,6 +292,10 @@ class Model:
     def force_valu_lift(self, on: bool = True):
         """Test hook: use the float32 vector-ALU lift instead of the MFMA lift."""
         _check(load_library().cdmd_dbg_force_valu_lift(self._h, int(on)))
+
+    def force_gather_sketch(self, on: bool = True):
+        """Test hook: gather form of the sparse sketch instead of the streaming form."""
+        _check(load_library().cdmd_dbg_force_gather_sketch(self._h, int(on)))
 
     def force_host_la(self, on: bool = True):
         """Test hook: float64 small linear algebra on the host instead of the device."""

@@ -91,6 +91,11 @@ struct cdmd_model {
   bool gauss = false;               // dense Gaussian sketch
   cdmd::k::GaussPlan gplan{};
   float* d_gpart = nullptr;         // per-slice partial sketches
+  // streaming sparse sketch (16-byte aligned frames)
+  int32_t* d_chunk_off = nullptr;   // [row block][chunk + 1] first triple of each chunk
+  int32_t* d_rblk = nullptr;        // [row block] (first row, rows)
+  int sk_nchunk = 0, sk_nrange = 0, sk_F = 0, sk_V = 1, sk_nblk = 0;
+  int sk_slots_cap = 0;             // partial slots allocated at d_Ypart
   size_t gpart_cap = 0;             // floats allocated at d_gpart
   double* d_gram = nullptr;
   // lift
@@ -146,6 +151,7 @@ struct cdmd_model {
   hipEvent_t ev[8] = {};
 
   bool capturing = false;         // inside a graph capture: no timing events
+  bool force_gather_sketch = false;  // test hook: gather form of the sparse sketch
   bool tuned = false;             // autotuner choices applied
   void mark(int i, hipStream_t st) {
     if (timing && !capturing) (void)hipEventRecord(ev[i], st);
@@ -159,7 +165,7 @@ struct cdmd_model {
   ~cdmd_model() {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
-    void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart,
+    void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart, d_chunk_off, d_rblk,
                    d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts, d_modes,
                    d_feats, d_logits,
                    d_la_scratch, d_la_out};
@@ -275,6 +281,13 @@ cdmd_status check_device(int* dev) {
 }
 
 // Build the pixel-sorted triple table of a sparse / single-pixel C for the uint8 sketch.
+// Pixel ranges of the streaming sketch: about 1024 workgroups in all.
+int stream_nrange(const cdmd_model* M, int F, int V) {
+  const int64_t fgroups = (M->m + F - 1) / F;
+  const int64_t nck = (M->sk_nchunk + V - 1) / V;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(nck, (1024 + fgroups * M->sk_nblk - 1) / (fgroups * M->sk_nblk)));
+}
+
 cdmd_status build_sparse_plan(cdmd_model* M) {
   const cdmd_config& c = M->cfg;
   const int p = c.p, z = c.nnz;
@@ -322,6 +335,35 @@ cdmd_status build_sparse_plan(cdmd_model* M) {
   M->nslot = nslot;
   M->max_rows = max_rows;
   M->fpb = fpb;
+  // streaming form: per row block, the first triple of every chunk of pixels
+  const int CH = cdmd::k::sketch_stream_chunk();
+  const int nchunk = (int)((M->n + CH - 1) / CH);
+  std::vector<int32_t> coff((size_t)nb * (nchunk + 1)), rblk(2 * (size_t)nb);
+  for (int b = 0; b < nb; ++b) {
+    const int r0 = b * max_rows, r1 = std::min(p, r0 + max_rows);
+    rblk[2 * b] = r0;
+    rblk[2 * b + 1] = r1 - r0;
+    const int64_t base = (int64_t)b * max_rows * z;  // row blocks are full except the last
+    const int64_t cnt = (int64_t)(r1 - r0) * z;
+    int64_t e = base;
+    for (int c = 0; c <= nchunk; ++c) {
+      const int64_t lim = (int64_t)c * CH;
+      while (e < base + cnt && pix[e] < lim) ++e;
+      coff[(size_t)b * (nchunk + 1) + c] = (int32_t)e;
+    }
+  }
+  int F = 4;
+  while (F > 1 && !cdmd::k::sketch_stream_fits(F, 1, max_rows)) F /= 2;
+  M->sk_nchunk = nchunk;
+  M->sk_nblk = nb;
+  M->sk_F = F;
+  M->sk_V = 1;
+  M->sk_nrange = stream_nrange(M, F, 1);
+  M->sk_slots_cap = std::max(M->nslot, M->sk_nrange);
+  TRY(dalloc(&M->d_chunk_off, coff.size()));
+  TRY(dalloc(&M->d_rblk, rblk.size()));
+  HIPCHK(hipMemcpy(M->d_chunk_off, coff.data(), coff.size() * 4, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(M->d_rblk, rblk.data(), rblk.size() * 4, hipMemcpyHostToDevice));
   TRY(dalloc(&M->d_tri_pix, pix.size()));
   TRY(dalloc(&M->d_tri_rs, rs.size()));
   TRY(dalloc(&M->d_seg, seg.size()));
@@ -394,6 +436,14 @@ cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool 
                                  gauss_prec(c), M->gplan, M->d_gpart, M->d_Yd, st));
     M->mark(1, st);
     HIPCHK(cdmd::k::gram_f64(M->d_Yd, M->p, M->m, M->d_gram, st));
+  } else if (c.dtype == CDMD_U8 && M->ld % 16 == 0 && (reinterpret_cast<uintptr_t>(d_video) & 15) == 0 &&
+             !M->force_gather_sketch) {
+    HIPCHK(cdmd::k::sketch_stream_u8((const uint8_t*)d_video, M->ld, M->n, M->m, M->d_tri_pix, M->d_tri_rs,
+                                     M->d_chunk_off, M->sk_nchunk, M->d_rblk, M->sk_nblk, M->sk_nrange, M->p,
+                                     M->max_rows, M->sk_F, M->sk_V, M->d_Ypart, st));
+    HIPCHK(cdmd::k::reduce_slots_i32(M->d_Ypart, M->sk_nrange, (int64_t)M->m * M->p, M->d_Yint, st));
+    M->mark(1, st);
+    HIPCHK(cdmd::k::gram_i32(M->d_Yint, M->p, M->m, M->d_gram, st));
   } else if (c.dtype == CDMD_U8) {
     int32_t* out = M->nslot > 1 ? M->d_Ypart : M->d_Yint;
     HIPCHK(cdmd::k::sketch_sparse_u8((const uint8_t*)d_video, M->ld, M->m, M->d_tri_pix, M->d_tri_rs,
@@ -715,7 +765,7 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
   } else if (cfg->dtype == CDMD_U8) {
     TRY(build_sparse_plan(M));
     TRY(dalloc(&M->d_Yint, (size_t)m * p));
-    if (M->nslot > 1) TRY(dalloc(&M->d_Ypart, (size_t)M->nslot * m * p));
+    TRY(dalloc(&M->d_Ypart, (size_t)M->sk_slots_cap * m * p));
   } else {
     const size_t T = (size_t)p * cfg->nnz;
     TRY(dalloc(&M->d_idx, T));
@@ -911,6 +961,7 @@ struct TuneKey {
 struct TuneChoice {
   int lift_grid = 0;
   int gauss_target = 0;
+  int sparse_form = 0;  // 0 untuned, -1 gather, else 10 F + V (streaming)
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice> g_tune;
@@ -946,6 +997,21 @@ cdmd_status time_ms(hipStream_t st, int reps, F&& launch, double* ms) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   return r;
+}
+
+cdmd_status apply_sparse_form(cdmd_model* M, int form) {
+  if (form < 0) {
+    M->force_gather_sketch = true;
+    return CDMD_OK;
+  }
+  const int F = form / 10, V = form % 10;
+  if (!cdmd::k::sketch_stream_fits(F, V, M->max_rows) || stream_nrange(M, F, V) > M->sk_slots_cap)
+    return fail(CDMD_E_INVALID_ARG, "streaming sketch form does not fit");
+  M->force_gather_sketch = false;
+  M->sk_F = F;
+  M->sk_V = V;
+  M->sk_nrange = stream_nrange(M, F, V);
+  return CDMD_OK;
 }
 
 cdmd_status apply_gauss_target(cdmd_model* M, int target) {
@@ -1001,14 +1067,29 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
         if (ms < best) best = ms, ch.gauss_target = target;
       }
     }
+    if (!M->gauss && M->cfg.dtype == CDMD_U8 && M->ld % 16 == 0 && (reinterpret_cast<uintptr_t>(d_video) & 15) == 0) {
+      // sparse sketch: the gather form, or streaming with (frames per group, vectors per thread)
+      double best = 1e300;
+      const int forms[] = {-1, 41, 21, 22, 11, 12, 14};
+      for (int f : forms) {
+        if (f > 0 && !cdmd::k::sketch_stream_fits(f / 10, f % 10, M->max_rows)) continue;
+        if (f > 0 && stream_nrange(M, f / 10, f % 10) > M->sk_slots_cap) continue;
+        TRY(apply_sparse_form(M, f));
+        double ms = 0.0;
+        TRY(time_ms(st, 3, [&] { return run_sketch(M, d_video, st, false); }, &ms));
+        if (ms < best) best = ms, ch.sparse_form = f;
+      }
+    }
     std::lock_guard<std::mutex> lk(g_tune_mu);
     g_tune[key] = ch;
   }
+  if (ch.sparse_form != 0) TRY(apply_sparse_form(M, ch.sparse_form));
   if (ch.lift_grid > 0) M->lm_grid = ch.lift_grid;
   if (ch.gauss_target > 0) TRY(apply_gauss_target(M, ch.gauss_target));
   M->tuned = true;
   M->info.lift_grid = M->lm_grid;
   M->info.sketch_slices = M->gauss ? M->gplan.nsplit : 0;
+  M->info.sparse_form = M->gauss ? 0 : (M->force_gather_sketch ? -1 : 10 * M->sk_F + M->sk_V);
   return CDMD_OK;
 }
 
@@ -1596,6 +1677,13 @@ cdmd_status cdmd_dbg_la_phases(const cdmd_model* M, double* ms16) {
   g_err.clear();
   if (!M || !ms16) return fail(CDMD_E_INVALID_ARG, "NULL argument");
   for (int i = 0; i < 16; ++i) ms16[i] = M->la_phase_ms[i];
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_force_gather_sketch(cdmd_model* M, int32_t on) {
+  g_err.clear();
+  if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  M->force_gather_sketch = on != 0;
   return CDMD_OK;
 }
 

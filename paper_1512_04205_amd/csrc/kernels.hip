@@ -97,6 +97,119 @@ hipError_t sketch_sparse_u8(const uint8_t* D, int64_t ld, int64_t m, const int32
   return hipGetLastError();
 }
 
+// Streaming form for 16-byte aligned frames: block (pixel range, frame group, row block)
+// reads its pixel range of SK_F frames in chunks of SK_CH bytes with coalesced 16-byte
+// loads (each video byte read once in total) into LDS, then the triples of the chunk
+// (pixel-sorted, located by chunk_off) add the staged bytes into per-row LDS sums.
+// Integer sums, so the atomic order does not matter.  Output: Ypart[range][t][r].
+constexpr int SK_CH = 8192;   // finest chunk: 512 threads x 16 bytes (chunk_off granularity)
+constexpr int SK_NT = 512;
+
+// V: 16-byte vectors per thread and frame, chunk = V * SK_CH bytes.
+template <int F, int V>
+__global__ __launch_bounds__(SK_NT) void k_sketch_stream_u8(
+    const uint8_t* __restrict__ D, int64_t ld, int64_t n, int64_t m, const int32_t* __restrict__ tri_pix,
+    const uint32_t* __restrict__ tri_rs, const int32_t* __restrict__ chunk_off, int nchunk,
+    const int32_t* __restrict__ rblk, int cpr, int p, int max_rows, int32_t* __restrict__ Ypart) {
+  constexpr int CH = V * SK_CH;
+  extern __shared__ int32_t lds[];
+  int32_t* acc = lds;                                                    // [F][nrows]
+  uint8_t* stage = reinterpret_cast<uint8_t*>(lds + F * max_rows);       // [F][CH]
+  const int pr = blockIdx.x, b = blockIdx.z;
+  const int64_t t0 = (int64_t)blockIdx.y * F;
+  const int nf = (int)((m - t0) < F ? (m - t0) : F);
+  const int r0 = rblk[2 * b], nrows = rblk[2 * b + 1];
+  const int c_begin = pr * cpr, c_end = (pr + 1) * cpr < nchunk ? (pr + 1) * cpr : nchunk;
+  const int* off = chunk_off + (int64_t)b * (nchunk + 1);
+  for (int i = threadIdx.x; i < F * nrows; i += SK_NT) acc[i] = 0;
+  const int tid = threadIdx.x;
+  // chunk c covers bytes [c CH, (c+1) CH); vector u of thread tid is at 16 (u SK_NT + tid)
+  auto load = [&](int c, uint4 (*v)[V]) {
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int u = 0; u < V; ++u) {
+        const int64_t j = (int64_t)c * CH + 16 * (u * SK_NT + tid);
+        uint4 x = make_uint4(0u, 0u, 0u, 0u);
+        if (f < nf && j < n) {
+          const uint8_t* src = D + (t0 + f) * ld + j;
+          if (j + 16 <= n) {
+            x = *reinterpret_cast<const uint4*>(src);
+          } else {
+            uint32_t w[4] = {0u, 0u, 0u, 0u};
+            for (int e = 0; j + e < n; ++e) w[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+            x = make_uint4(w[0], w[1], w[2], w[3]);
+          }
+        }
+        v[f][u] = x;
+      }
+  };
+  const int nck = (nchunk + V - 1) / V;  // chunks of this size
+  const int cb = c_begin, ce = c_end < nck ? c_end : nck;
+  uint4 cur[F][V];
+  if (cb < ce) load(cb, cur);
+  for (int c = cb; c < ce; ++c) {
+    __syncthreads();  // previous chunk's triples are done with the stage
+#pragma unroll
+    for (int f = 0; f < F; ++f)
+#pragma unroll
+      for (int u = 0; u < V; ++u)
+        *reinterpret_cast<uint4*>(stage + f * CH + 16 * (u * SK_NT + tid)) = cur[f][u];
+    __syncthreads();
+    if (c + 1 < ce) load(c + 1, cur);  // next chunk in flight while this one is summed
+    const int fe = (c + 1) * V < nchunk ? (c + 1) * V : nchunk;
+    const int e0 = off[c * V], e1 = off[fe];
+    const int64_t c0 = (int64_t)c * CH;
+    for (int e = e0 + tid; e < e1; e += SK_NT) {
+      const int px = (int)(tri_pix[e] - c0);
+      const uint32_t rs = tri_rs[e];
+      const int row = (int)(rs & 0x7fffffffu);
+      const bool neg = (rs >> 31) != 0;
+#pragma unroll
+      for (int f = 0; f < F; ++f)
+        if (f < nf) {
+          const int v = (int)stage[f * CH + px];
+          atomicAdd(&acc[f * nrows + row], neg ? -v : v);
+        }
+    }
+  }
+  __syncthreads();
+  int32_t* Y = Ypart + (int64_t)pr * m * p;
+  for (int i = threadIdx.x; i < nf * nrows; i += SK_NT) {
+    const int f = i / nrows, r = i - f * nrows;
+    Y[(t0 + f) * p + r0 + r] = acc[i];
+  }
+}
+
+bool sketch_stream_fits(int F, int V, int max_rows) {
+  return (size_t)F * max_rows * sizeof(int32_t) + (size_t)F * V * SK_CH <= 65536;
+}
+
+hipError_t sketch_stream_u8(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const int32_t* tri_pix,
+                            const uint32_t* tri_rs, const int32_t* chunk_off, int nchunk, const int32_t* rblk,
+                            int nblk, int nrange, int p, int max_rows, int F, int V, int32_t* Ypart,
+                            hipStream_t stream) {
+  if (!sketch_stream_fits(F, V, max_rows)) return hipErrorInvalidValue;
+  const int nck = (nchunk + V - 1) / V;
+  const int cpr = (nck + nrange - 1) / nrange;
+  const dim3 grid((unsigned)nrange, (unsigned)((m + F - 1) / F), (unsigned)nblk);
+  const size_t lds = (size_t)F * max_rows * sizeof(int32_t) + (size_t)F * V * SK_CH;
+#define SK_LAUNCH(FF, VV)                                                                                  \
+  hipLaunchKernelGGL((k_sketch_stream_u8<FF, VV>), grid, dim3(SK_NT), lds, stream, D, ld, n, m, tri_pix, \
+                     tri_rs, chunk_off, nchunk, rblk, cpr, p, max_rows, Ypart)
+  if (F == 4 && V == 1) SK_LAUNCH(4, 1);
+  else if (F == 2 && V == 1) SK_LAUNCH(2, 1);
+  else if (F == 2 && V == 2) SK_LAUNCH(2, 2);
+  else if (F == 1 && V == 1) SK_LAUNCH(1, 1);
+  else if (F == 1 && V == 2) SK_LAUNCH(1, 2);
+  else if (F == 1 && V == 4) SK_LAUNCH(1, 4);
+  else return hipErrorInvalidValue;
+#undef SK_LAUNCH
+  return hipGetLastError();
+}
+
+int sketch_stream_chunk() { return SK_CH; }
+
 __global__ void k_reduce_slots(const int32_t* __restrict__ Yp, int nslot, int64_t count,
                                int32_t* __restrict__ Y) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;

@@ -20,6 +20,19 @@ hipError_t sketch_sparse_u8(const uint8_t* D, int64_t ld, int64_t m, const int32
                             const uint32_t* tri_rs, const int32_t* seg, int nseg, int p,
                             int max_rows, int fpb, int32_t* Yout, int nslot,
                             hipStream_t stream);
+// Streaming form (16-byte aligned frames): grid (nrange pixel ranges, frame groups of F,
+// nblk row blocks).  Triples of row block b are sorted by pixel; chunk_off[b*(nchunk+1) + c]
+// is the first triple of b with pixel >= c * chunk (chunk = sketch_stream_chunk()), and
+// rblk[2b], rblk[2b+1] its first row and row count.  Output Ypart[range][t][r] (every
+// range writes all its rows); LDS F * (4 max_rows + V chunk) bytes.
+// V: 16-byte vectors per thread and frame (chunk V * sketch_stream_chunk() bytes);
+// (F, V) in {(4,1), (2,1), (2,2), (1,1), (1,2), (1,4)} with sketch_stream_fits.
+bool sketch_stream_fits(int F, int V, int max_rows);
+hipError_t sketch_stream_u8(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const int32_t* tri_pix,
+                            const uint32_t* tri_rs, const int32_t* chunk_off, int nchunk, const int32_t* rblk,
+                            int nblk, int nrange, int p, int max_rows, int F, int V, int32_t* Ypart,
+                            hipStream_t stream);
+int sketch_stream_chunk();
 // Y[t][r] = sum_s Ypart[s][t][r]
 hipError_t reduce_slots_i32(const int32_t* Ypart, int nslot, int64_t count, int32_t* Y,
                             hipStream_t stream);

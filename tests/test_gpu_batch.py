@@ -131,3 +131,21 @@ def test_autotune_keeps_results():
     rel, _, _ = eig_rel_err(lam, ref[0])
     # the sketch slices may differ: float32 partial sums regrouped (BF16 products)
     assert rel.max() <= 1e-5
+
+
+def test_autotune_sparse_sketch_stays_exact():
+    """Whichever sparse-sketch form the autotuner picks, the integer sketch is exact."""
+    _say("autotune sparse")
+    rng = np.random.default_rng(12)
+    H, W, m, p = 64, 96, 50, 700
+    n = H * W
+    D = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+    idx, sign = sv.sparse_table(n, p, 32, seed=9)
+    mdl = P.Model(n, m, 6, p, idx=idx, sign=sign)
+    Dg = torch.from_numpy(D).cuda()
+    mdl.autotune(Dg)
+    mdl.fit(Dg)
+    assert mdl.info()["sparse_form"] != 0
+    _, Yi = mdl.sketch(integer=True)
+    _, Yiref = R.sketch_sparse(D, 1 / 255, idx, sign)
+    np.testing.assert_array_equal(Yi, Yiref)

@@ -51,6 +51,8 @@ def _fit_both(v, k, p, nnz, K=6, table_seed=3, spixel=False):
 @pytest.mark.parametrize("shape", [(40, 50, 33, 700, 32), (48, 64, 64, 300, 7),
                                    (30, 41, 17, 9000, 3), (64, 64, 40, 1000, 32)])
 def test_sparse_sketch_bit_exact(shape):
+    """Both forms of the uint8 sparse sketch (streaming for 16-byte aligned frames, gather
+    otherwise or when forced) give the exact integer sums."""
     H, W, m, p, nnz = shape
     _say("sketch", shape)
     rng = np.random.default_rng(1)
@@ -58,12 +60,30 @@ def test_sparse_sketch_bit_exact(shape):
     D = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
     idx, sign = sv.sparse_table(n, p, nnz, seed=5)
     k = min(4, m - 1)
-    mdl = P.Model(n, m, k, p, idx=idx, sign=sign)
-    mdl.fit(torch.from_numpy(D).cuda())
-    Y, Yi = mdl.sketch(integer=True)
     Yref, Yiref = R.sketch_sparse(D, 1 / 255, idx, sign)
+    for gather in (False, True):
+        mdl = P.Model(n, m, k, p, idx=idx, sign=sign)
+        mdl.force_gather_sketch(gather)
+        mdl.fit(torch.from_numpy(D).cuda())
+        Y, Yi = mdl.sketch(integer=True)
+        np.testing.assert_array_equal(Yi, Yiref)
+        np.testing.assert_allclose(Y, Yref, rtol=1e-15, atol=0)
+
+
+def test_sparse_sketch_streaming_large_p():
+    """Several row blocks (p > 8192), frame groups of one, a pixel count that is not a
+    multiple of the 8 KB chunk: streaming form, exact."""
+    _say("sketch large p")
+    rng = np.random.default_rng(2)
+    H, W, m, p, nnz = 96, 176, 37, 9000, 4
+    n = H * W
+    D = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+    idx, sign = sv.sparse_table(n, p, nnz, seed=8)
+    mdl = P.Model(n, m, 4, p, idx=idx, sign=sign)
+    mdl.fit(torch.from_numpy(D).cuda())
+    _, Yi = mdl.sketch(integer=True)
+    _, Yiref = R.sketch_sparse(D, 1 / 255, idx, sign)
     np.testing.assert_array_equal(Yi, Yiref)
-    np.testing.assert_allclose(Y, Yref, rtol=1e-15, atol=0)
 
 
 def test_single_pixel_sketch_bit_exact():
