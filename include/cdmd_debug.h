@@ -47,10 +47,12 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
                                    double* W, double* G, int32_t* steps);
 
 /* Phase times (ms) of the last device small-LA solve: [0] Lanczos incl. convergence
-   checks, [1] of which the tridiagonal eigen-solves of the checks, [2] A~, [3] eigenvalues
-   of A~, [4] eigenvectors, [5] G, [6] lift operand write, and of [0]: [7] matrix-vector
-   products, [8] reorthogonalisation, [9] norm and next vector, [10] multisection of the
-   checks, [11] tridiagonal inverse iteration, [12] Ritz vectors Q Z; [13..15] unused.
+   checks, [1] of which the tridiagonal eigen-solves of the checks, [2] Ritz vectors
+   V = Q Z, M12 V and A~ (from the end of [0]), [3] eigenvalues of A~, [4] eigenvectors,
+   [5] G, [6] lift operand write, and of [0]: [7] matrix-vector products, [8]
+   reorthogonalisation, [9] norm and next vector, [10] multisection of the checks, [11]
+   tridiagonal inverse iteration, [12] hand-over of the Ritz vectors of T_J; [13..15]
+   unused.
    Errors: INVALID_ARG. */
 cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms16);
 

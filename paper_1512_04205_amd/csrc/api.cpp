@@ -1110,6 +1110,7 @@ struct cdmd_batch {
   hipEvent_t fork1 = nullptr, fork2 = nullptr;
   std::vector<hipEvent_t> join1, join2;
   cdmd::k::SLADesc* d_desc = nullptr;
+  int la_nmax = 0, la_gmax = 0;     // grid extents of the small-LA row kernels
   hipStream_t cap = nullptr;        // the graph's own stream (capture needs a non-null stream)
   hipEvent_t entry = nullptr;       // caller's stream -> cap
 
@@ -1187,7 +1188,7 @@ cdmd_status capture_batch(cdmd_batch* B, hipStream_t st) {
     hip(hipEventRecord(B->join1[q], B->pool[q]));
     hip(hipStreamWaitEvent(st, B->join1[q], 0));
   }
-  hip(cdmd::k::small_la_batch(B->d_desc, (int)B->dev.size(), st));
+  hip(cdmd::k::small_la_batch(B->d_desc, (int)B->dev.size(), B->la_nmax, B->la_gmax, st));
   hip(hipEventRecord(B->fork2, st));
   for (int q = 0; q < P; ++q) hip(hipStreamWaitEvent(B->pool[q], B->fork2, 0));
   for (size_t i = 0; i < B->dev.size() && r == CDMD_OK; ++i) {
@@ -1228,6 +1229,7 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
     B->videos.assign(d_videos, d_videos + n);
     B->dev.clear();
     std::vector<cdmd::k::SLADesc> desc;
+    B->la_nmax = B->la_gmax = 0;
     for (int i = 0; i < n; ++i) {
       cdmd_model* M = B->models[i];
       plan_fit(M, d_videos[i]);
@@ -1238,6 +1240,8 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
       desc.push_back(cdmd::k::SLADesc{M->d_gram, M->d_la_scratch, M->d_la_out, (uint16_t*)M->d_Gp, kLanczosTol,
                                       M->sketch_scale, (double)M->xscale, (int)M->m, M->k, M->la_jmax,
                                       M->lm_nb, M->lm_nsplit, M->lm_nksteps});
+      B->la_nmax = std::max(B->la_nmax, (int)M->m - 1);
+      B->la_gmax = std::max(B->la_gmax, std::max((int)M->m - 1, 16 * M->lm_nksteps));
     }
     if (!desc.empty()) {
       HIPCHK(hipMemcpy(B->d_desc, desc.data(), sizeof(desc[0]) * desc.size(), hipMemcpyHostToDevice));

@@ -1102,41 +1102,46 @@ __device__ __forceinline__ double bf16_val_d(uint16_t b) {
   return (double)__uint_as_float((uint32_t)b << 16);
 }
 
-// One small-LA solve by the whole (1024-thread) workgroup.
-__device__ void small_la_block(const SLADesc& d) {
-  using namespace tla;
-  const double* __restrict__ Gr = d.Gr;
-  const int m = d.m, k = d.k, Jmax = d.Jmax, NB = d.NB, NS = d.NS, KS = d.KS;
-  const double rtol = d.rtol, sketch_scale = d.sketch_scale, xscale = d.xscale;
-  double* __restrict__ scratch = d.scratch;
-  double* __restrict__ out = d.out;
-  uint16_t* __restrict__ Gp = d.Gp;
-  __shared__ double s_q[SLA_NMAX], s_w[SLA_NMAX];
-  __shared__ double s_h[SLA_JMAX + 4], s_alpha[SLA_JMAX + 4], s_beta[SLA_JMAX + 4];
-  __shared__ double s_red[16];
-  __shared__ int s_flag[1];
-  __shared__ double s_fast[SLA_FAST];
-  DevTeam tm;
+// The small linear algebra of one solve runs as five kernels, each with a grid row
+// (blockIdx.y, or blockIdx.x for the one-workgroup kernels) per solve of a batch:
+//   k_la_a     one workgroup: non-finite check, Lanczos, Ritz vectors Z of T_J
+//   k_la_ritz  a workgroup per kLaRows rows: V = Q_J Z
+//   k_la_tv    a workgroup per kLaRows rows: TV = M12 V and the block partials of V^T TV
+//   k_la_b     one workgroup: A~ from the partials, its eigenvalues and eigenvectors
+//   k_la_g     a workgroup per kLaRows rows: G = V S^-1 W and the lift's bf16 operands
+// Every kernel after the first returns at once when the solve's status is not OK.
+constexpr int SLA_ROWS_NT = 512;
+constexpr int SLA_STAGE = 8192;  // LDS doubles of the row kernels
+
+__device__ __forceinline__ const SLADesc& la_desc(const SLADesc& d1, const SLADesc* ds, int q) {
+  return ds != nullptr ? ds[q] : d1;
+}
+
+__device__ __forceinline__ void la_team(DevTeam& tm, double* red, double* tslots) {
   tm.tid = threadIdx.x;
   tm.nt = blockDim.x;
   tm.lane = threadIdx.x & 63;
   tm.wsize = 64;
   tm.wave = threadIdx.x >> 6;
   tm.nwaves = blockDim.x >> 6;
-  tm.red = s_red;
-  const int N = m - 1;
-  const SmallLALayout Ls = small_la_layout(N, k, Jmax);
-  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
-  tm.tslots = out + Lo.timing;
+  tm.red = red;
+  tm.tslots = tslots;
   tm.t_last = 0;
   tm.t_tick = 0;
-  if (tm.tid == 0)
-    for (int i = 0; i < 16; ++i) tm.tslots[i] = 0.0;
-  SmallLAWork ws;
+}
+
+__device__ void la_work(tla::SmallLAWork& ws, const SLADesc& d, double* s_q, double* s_w, double* s_h,
+                        double* s_alpha, double* s_beta, double* s_fast, int* s_flag) {
+  using namespace tla;
+  const SmallLALayout Ls = small_la_layout(d.m - 1, d.k, d.Jmax);
+  double* scratch = d.scratch;
   ws.lz = LanczosWork{s_q, s_w, s_h, s_alpha, s_beta, scratch + Ls.T, s_fast, SLA_FAST};
   ws.Q = scratch + Ls.Q;
   ws.V = scratch + Ls.V;
+  ws.Z = scratch + Ls.Z;
   ws.TV = scratch + Ls.TV;
+  ws.P = scratch + Ls.P;
+  ws.nu = scratch + Ls.nu;
   ws.At = scratch + Ls.At;
   ws.Hs = scratch + Ls.Hs;
   ws.LU = reinterpret_cast<cpx*>(scratch + Ls.LU);
@@ -1144,32 +1149,131 @@ __device__ void small_la_block(const SLADesc& d) {
   ws.yy = reinterpret_cast<cpx*>(scratch + Ls.yy);
   ws.piv = reinterpret_cast<int*>(scratch + Ls.piv);
   ws.flag = s_flag;
+}
+
+// Lanczos and the Ritz vectors of T_J (one 1024-thread workgroup per solve).
+__global__ __launch_bounds__(1024) void k_la_a(SLADesc d1, const SLADesc* __restrict__ ds) {
+  using namespace tla;
+  const SLADesc& d = la_desc(d1, ds, blockIdx.x);
+  __shared__ double s_q[SLA_NMAX], s_w[SLA_NMAX];
+  __shared__ double s_h[SLA_JMAX + 4], s_alpha[SLA_JMAX + 4], s_beta[SLA_JMAX + 4];
+  __shared__ double s_red[16];
+  __shared__ int s_flag[1];
+  __shared__ double s_fast[SLA_FAST];
+  const int m = d.m, k = d.k, N = m - 1;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  double* out = d.out;
+  DevTeam tm;
+  la_team(tm, s_red, out + Lo.timing);
+  if (tm.tid == 0)
+    for (int i = 0; i < 16; ++i) tm.tslots[i] = 0.0;
+  SmallLAWork ws;
+  la_work(ws, d, s_q, s_w, s_h, s_alpha, s_beta, s_fast, s_flag);
   int J = 0;
-  const int st = small_la_run(tm, Gr, m, k, rtol, Jmax, sketch_scale, ws, out + Lo.mu,
-                              out + Lo.sigma, reinterpret_cast<cpx*>(out + Lo.lam),
-                              reinterpret_cast<cpx*>(out + Lo.W), reinterpret_cast<cpx*>(out + Lo.G), &J);
+  const int st = small_la_phase_a(tm, d.Gr, m, k, d.rtol, d.Jmax, ws, out + Lo.mu, ws.Z, &J);
   if (tm.tid == 0) {
     out[Lo.status] = (double)st;
     out[Lo.J] = (double)J;
   }
-  if (st != kOk) return;  // uniform: every thread holds the same status
+}
+
+// V = Q_J Z over the workgroup's kLaRows rows.
+__global__ __launch_bounds__(SLA_ROWS_NT) void k_la_ritz(SLADesc d1, const SLADesc* __restrict__ ds) {
+  using namespace tla;
+  const SLADesc& d = la_desc(d1, ds, blockIdx.y);
+  const int N = d.m - 1, k = d.k;
+  const int t0 = blockIdx.x * kLaRows;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  if (t0 >= N || d.out[Lo.status] != 0.0) return;  // uniform over the workgroup
+  __shared__ double s_red[SLA_ROWS_NT / 64];
+  DevTeam tm;
+  la_team(tm, s_red, nullptr);
+  const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
+  const int J = (int)d.out[Lo.J];
+  ritz_rows(tm, d.scratch + Ls.Q, N, J, d.scratch + Ls.Z, k, d.scratch + Ls.V, t0,
+            t0 + kLaRows < N ? t0 + kLaRows : N);
+}
+
+// TV = M12 V over the workgroup's rows, and the block's partials of V^T TV and |v_i|^2.
+__global__ __launch_bounds__(SLA_ROWS_NT) void k_la_tv(SLADesc d1, const SLADesc* __restrict__ ds) {
+  using namespace tla;
+  const SLADesc& d = la_desc(d1, ds, blockIdx.y);
+  const int m = d.m, N = m - 1, k = d.k;
+  const int t0 = blockIdx.x * kLaRows;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  if (t0 >= N || d.out[Lo.status] != 0.0) return;
+  __shared__ double s_red[SLA_ROWS_NT / 64];
+  __shared__ double s_stage[SLA_STAGE];
+  DevTeam tm;
+  la_team(tm, s_red, nullptr);
+  const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
+  const int t1 = t0 + kLaRows < N ? t0 + kLaRows : N;
+  double* V = d.scratch + Ls.V;
+  double* TV = d.scratch + Ls.TV;
+  m12v_rows(tm, d.Gr, m, N, k, V, TV, t0, t1, s_stage, SLA_STAGE);
+  block_gram(tm, V, TV, N, k, t0, t1, d.scratch + Ls.P + (int64_t)blockIdx.x * ((int64_t)k * k + k), s_stage,
+             SLA_STAGE);
+}
+
+// A~ from the block partials, its eigenvalues and eigenvectors (one workgroup per solve).
+__global__ __launch_bounds__(1024) void k_la_b(SLADesc d1, const SLADesc* __restrict__ ds) {
+  using namespace tla;
+  const SLADesc& d = la_desc(d1, ds, blockIdx.x);
+  const int N = d.m - 1, k = d.k;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  double* out = d.out;
+  if (out[Lo.status] != 0.0) return;
+  __shared__ double s_w[SLA_NMAX];
+  __shared__ double s_red[16];
+  __shared__ int s_flag[1];
+  __shared__ double s_fast[SLA_FAST];
+  DevTeam tm;
+  la_team(tm, s_red, out + Lo.timing);
+  SmallLAWork ws;
+  la_work(ws, d, nullptr, s_w, nullptr, nullptr, nullptr, s_fast, s_flag);
+  const int nblk = (N + kLaRows - 1) / kLaRows;
+  const int st = small_la_phase_b(tm, N, k, d.sketch_scale, ws, nblk, out + Lo.mu, out + Lo.sigma,
+                                  reinterpret_cast<cpx*>(out + Lo.lam), reinterpret_cast<cpx*>(out + Lo.W));
+  if (tm.tid == 0 && st != kOk) out[Lo.status] = (double)st;
+}
+
+// G = V S^-1 W over the workgroup's rows, then the lift's B operands of the 16-row groups
+// inside them: [ks][nb][split][lane][8], element i of lane l is G row 16ks + 8(l/32) + i,
+// column 32nb + l%32 (< k: Re, < 2k: Im of mode column mod k), times xscale, split into
+// NS bf16 terms.
+__global__ __launch_bounds__(SLA_ROWS_NT) void k_la_g(SLADesc d1, const SLADesc* __restrict__ ds) {
+  using namespace tla;
+  const SLADesc& d = la_desc(d1, ds, blockIdx.y);
+  const int N = d.m - 1, k = d.k, NB = d.NB, NS = d.NS, KS = d.KS;
+  const int t0 = blockIdx.x * kLaRows;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  double* out = d.out;
+  if ((t0 >= N && t0 >= 16 * KS) || out[Lo.status] != 0.0) return;
+  __shared__ double s_red[SLA_ROWS_NT / 64];
+  DevTeam tm;
+  la_team(tm, s_red, blockIdx.x == 0 ? out + Lo.timing : nullptr);
+  const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
+  cpx* G = reinterpret_cast<cpx*>(out + Lo.G);
+  if (t0 < N)
+    g_rows(tm, d.scratch + Ls.V, N, k, d.scratch + Ls.nu, out + Lo.sigma, reinterpret_cast<const cpx*>(out + Lo.W),
+           G, t0, t0 + kLaRows < N ? t0 + kLaRows : N);
+  tm.stamp(7);
   tm.stamp(8);
-  const cpx* G = reinterpret_cast<const cpx*>(out + Lo.G);
-  // B operands [ks][nb][split][lane][8]: element i of lane l is G row 16ks + 8(l/32) + i,
-  // column 32nb + l%32 (< k: Re, < 2k: Im of mode col mod k)
-  const int64_t total = (int64_t)KS * NB * 64 * 8;
+  const int ks0 = t0 / 16, ks1 = (t0 + kLaRows) / 16 < KS ? (t0 + kLaRows) / 16 : KS;
+  const int64_t total = (int64_t)(ks1 - ks0) * NB * 64 * 8;
+  uint16_t* __restrict__ Gp = d.Gp;
   for (int64_t e = tm.tid; e < total; e += tm.nt) {
     const int i = (int)(e & 7);
     const int l = (int)((e >> 3) & 63);
     const int64_t r = e >> 9;
     const int nb = (int)(r % NB);
-    const int ks = (int)(r / NB);
+    const int ks = ks0 + (int)(r / NB);
     const int row = 16 * ks + 8 * (l >> 5) + i;
     const int col = 32 * nb + (l & 31);
     double g = 0.0;
     if (row < N && col < 2 * k) {
       const cpx z = G[(int64_t)row * k + (col % k)];
-      g = (col < k ? z.re : z.im) * xscale;
+      g = (col < k ? z.re : z.im) * d.xscale;
     }
     double rem = g;
     for (int sp = 0; sp < NS; ++sp) {
@@ -1182,12 +1286,16 @@ __device__ void small_la_block(const SLADesc& d) {
   tm.stamp(9);
 }
 
-__global__ __launch_bounds__(1024) void k_small_la(SLADesc d) { small_la_block(d); }
-
-// One workgroup per solve: the solves of a batch run side by side, one per compute unit.
-__global__ __launch_bounds__(1024) void k_small_la_batch(const SLADesc* __restrict__ ds) {
-  const SLADesc d = ds[blockIdx.x];
-  small_la_block(d);
+static hipError_t launch_la(const SLADesc& d1, const SLADesc* ds, int count, int nmax, int gmax,
+                            hipStream_t stream) {
+  const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
+  const int gb = (gmax + tla::kLaRows - 1) / tla::kLaRows;
+  hipLaunchKernelGGL(k_la_a, dim3(count), dim3(1024), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_ritz, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_b, dim3(count), dim3(1024), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_g, dim3(gb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
+  return hipGetLastError();
 }
 
 bool small_la_fits(int m, int k, int Jmax) {
@@ -1199,14 +1307,13 @@ hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, doubl
                     hipStream_t stream) {
   if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
   const SLADesc d{Gr, scratch, out, (uint16_t*)Gp, rtol, sketch_scale, xscale, m, k, Jmax, NB, NS, KS};
-  hipLaunchKernelGGL(k_small_la, dim3(1), dim3(1024), 0, stream, d);
-  return hipGetLastError();
+  return launch_la(d, nullptr, 1, m - 1, std::max(m - 1, 16 * KS), stream);
 }
 
-hipError_t small_la_batch(const SLADesc* d_descs, int count, hipStream_t stream) {
+hipError_t small_la_batch(const SLADesc* d_descs, int count, int nmax, int gmax, hipStream_t stream) {
   if (count < 1) return hipSuccess;
-  hipLaunchKernelGGL(k_small_la_batch, dim3(count), dim3(1024), 0, stream, d_descs);
-  return hipGetLastError();
+  const SLADesc none{};
+  return launch_la(none, d_descs, count, nmax, gmax, stream);
 }
 
 int64_t small_la_scratch_doubles(int m, int k, int Jmax) {

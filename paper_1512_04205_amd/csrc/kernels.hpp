@@ -138,7 +138,8 @@ struct SLADesc {
   int m, k, Jmax, NB, NS, KS;
 };
 bool small_la_fits(int m, int k, int Jmax);
-hipError_t small_la_batch(const SLADesc* d_descs, int count, hipStream_t stream);
+// nmax: the largest m - 1 of the batch; gmax: the largest max(m - 1, 16 KS).
+hipError_t small_la_batch(const SLADesc* d_descs, int count, int nmax, int gmax, hipStream_t stream);
 int64_t small_la_out_doubles(int m, int k);
 
 }  // namespace k

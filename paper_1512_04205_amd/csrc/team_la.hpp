@@ -323,12 +323,14 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
 
 // Top-k eigenpairs of the symmetric N x N matrix M (element (r, c) at M[r*ldm + c]).
 // Q: (Jmax+1) x N scratch (vector-contiguous).  On return evals[k] descending and
-// V (N x k, column-major) the unit Ritz vectors; the return value is the Krylov
-// dimension J, or -1 on failure.  Converged when every top-k Ritz residual
+// V (N x k, column-major) the unit Ritz vectors, or, when Zout is given, instead the
+// Ritz vectors of T_J in Zout (J x k, element (i, c) at i*k + c); the return value is the
+// Krylov dimension J, or -1 on failure.  Converged when every top-k Ritz residual
 // beta_J |z_J| <= rtol * theta_1, or J = N.
 template <class TM>
 TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double rtol, int Jmax,
-                        double* Q, const LanczosWork& ws, double* evals, double* V) {
+                        double* Q, const LanczosWork& ws, double* evals, double* V,
+                        double* Zout = nullptr) {
   if (Jmax > N) Jmax = N;
   double* q = ws.q;
   double* w = ws.w;
@@ -497,6 +499,12 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
         tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, true, work, Zm);
         tm.tick(14);
         for (int i = tm.tid; i < k; i += tm.nt) evals[i] = theta[i];
+        if (Zout != nullptr) {  // the caller forms V = Q_J Z_k (ritz_rows)
+          for (int e = tm.tid; e < J * k; e += tm.nt) Zout[e] = Zm[e];
+          tm.sync();
+          tm.tick(15);
+          return conv || J == N ? J : -1;
+        }
         // V = Q_J Z_k
         for (int e = tm.tid; e < N * k; e += tm.nt) {
           const int c = e / N, t = e % N;
@@ -564,79 +572,6 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
     tm.tick(12);
   }
   return -1;
-}
-
-// --------------------------------------------------------------------------- A~
-// At = S^-1 V^T M12 V S^-1 with M12[a][b] = Mfull[a*ldm + b + 1] (a, b < N), s = sqrt(mu).
-// TV: N x k scratch (column-major).
-template <class TM>
-TLA_HD void reduced_operator(TM& tm, const double* Mfull, int ldm, int N, int k, const double* V,
-                             const double* s, double* TV, double* At, double* stage,
-                             int64_t stage_doubles) {
-  // TV = M12 V, element (a, c) = sum_b M12[a][b] V[b][c].  The Gram is symmetric, so
-  // M12[a][b] = Mfull[(b+1)*ldm + a]: thread (a, block of KB columns) reads coalesced
-  // columns of the Gram, eight loads in flight; the rows b of V pass through `stage` (fast
-  // memory) in chunks.
-  constexpr int KB = 8;
-  const int CB = (k + KB - 1) / KB;
-  int chunk = (int)(stage_doubles / (k > 0 ? k : 1));
-  if (chunk > 256) chunk = 256;
-  const int tasks = N * CB;
-  for (int base = 0; base < tasks; base += tm.nt) {
-    const int e = base + tm.tid;
-    const bool act = e < tasks;
-    const int a = act ? e % N : 0, c0 = act ? (e / N) * KB : 0;
-    double acc[KB];
-#pragma unroll
-    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
-    for (int b0 = 0; b0 < N; b0 += chunk) {
-      const int nb = N - b0 < chunk ? N - b0 : chunk;
-      tm.sync();
-      for (int f = tm.tid; f < nb * k; f += tm.nt) {
-        const int bb = f / k, c = f % k;
-        stage[f] = V[(int64_t)c * N + b0 + bb];
-      }
-      tm.sync();
-      if (act) {
-        int bb = 0;
-        for (; bb + 8 <= nb; bb += 8) {
-          double mv[8];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) mv[u] = Mfull[(int64_t)(b0 + bb + u + 1) * ldm + a];
-#pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            const double* sv = stage + (bb + u) * k + c0;
-#pragma unroll
-            for (int c = 0; c < KB; ++c)
-              if (c0 + c < k) acc[c] += mv[u] * sv[c];
-          }
-        }
-        for (; bb < nb; ++bb) {
-          const double mv = Mfull[(int64_t)(b0 + bb + 1) * ldm + a];
-          const double* sv = stage + bb * k + c0;
-#pragma unroll
-          for (int c = 0; c < KB; ++c)
-            if (c0 + c < k) acc[c] += mv * sv[c];
-        }
-      }
-    }
-    if (act)
-#pragma unroll
-      for (int c = 0; c < KB; ++c)
-        if (c0 + c < k) TV[(int64_t)(c0 + c) * N + a] = acc[c];
-  }
-  tm.sync();
-  // At[i][j] = v_i . tv_j / (s_i s_j): a wave per entry, lanes over the long index
-  for (int e = tm.wave; e < k * k; e += tm.nwaves) {
-    const int i = e / k, j = e % k;
-    const double* vi = V + (int64_t)i * N;
-    const double* tj = TV + (int64_t)j * N;
-    double a0 = 0.0;
-    for (int a = tm.lane; a < N; a += tm.wsize) a0 += vi[a] * tj[a];
-    a0 = tm.wave_sum(a0);
-    if (tm.lane == 0) At[i * k + j] = a0 / (s[i] * s[j]);
-  }
-  tm.sync();
 }
 
 // --------------------------------------------------------------------------- eig(A~)
@@ -966,7 +901,10 @@ struct SmallLAWork {
   LanczosWork lz;
   double* Q;    // (Jmax+1) x N
   double* V;    // N x k
+  double* Z;    // Jmax x k  Ritz vectors of T_J
   double* TV;   // N x k
+  double* P;    // nblk x (k*k + k)  block partials of V^T M12 V and |v_i|^2
+  double* nu;   // 2k  column norms of V, then sqrt(mu)
   double* At;   // k x k
   double* Hs;   // k x k
   cpx* LU;      // k x k x k
@@ -976,19 +914,161 @@ struct SmallLAWork {
   int* flag;    // 1 (shared)
 };
 
+// Rows per block of the row-range steps below (the device runs a workgroup per block).
+constexpr int kLaRows = 64;
+
+// V[c*N + t] = sum_{i < J} Q[i*N + t] Z[i*k + c] for rows t in [t0, t1): the Ritz
+// vectors of M from those of T_J (not normalised).  Thread (t, block of 8 columns); each
+// entry is one sum in the order of i, whatever the team.
+template <class TM>
+TLA_HD void ritz_rows(TM& tm, const double* Q, int N, int J, const double* Z, int k, double* V, int t0,
+                      int t1) {
+  constexpr int KB = 8;
+  const int nr = t1 - t0, CB = (k + KB - 1) / KB;
+  for (int e = tm.tid; e < nr * CB; e += tm.nt) {
+    const int t = t0 + e % nr, c0 = (e / nr) * KB;
+    double acc[KB];
+#pragma unroll
+    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    for (int i = 0; i < J; ++i) {
+      const double q = Q[(int64_t)i * N + t];
+      const double* zi = Z + (int64_t)i * k + c0;
+#pragma unroll
+      for (int c = 0; c < KB; ++c)
+        if (c0 + c < k) acc[c] += q * zi[c];
+    }
+#pragma unroll
+    for (int c = 0; c < KB; ++c)
+      if (c0 + c < k) V[(int64_t)(c0 + c) * N + t] = acc[c];
+  }
+  tm.sync();
+}
+
+// TV[c*N + a] = sum_b M12[a][b] V[c*N + b] for rows a in [a0, a1), M12[a][b] =
+// Mfull[(b+1)*ldm + a] (symmetric Gram): thread (a, block of 8 columns), eight Gram loads
+// in flight; the rows b of V pass through `stage` in chunks.  Each entry is one sum in the
+// order of b, whatever the team.
+template <class TM>
+TLA_HD void m12v_rows(TM& tm, const double* Mfull, int ldm, int N, int k, const double* V, double* TV,
+                      int a0, int a1, double* stage, int64_t stage_doubles) {
+  constexpr int KB = 8;
+  const int CB = (k + KB - 1) / KB;
+  int chunk = (int)(stage_doubles / (k > 0 ? k : 1));
+  if (chunk > 256) chunk = 256;
+  const int nr = a1 - a0;
+  const int tasks = nr * CB;
+  for (int base = 0; base < tasks; base += tm.nt) {
+    const int e = base + tm.tid;
+    const bool act = e < tasks;
+    const int a = act ? a0 + e % nr : a0, c0 = act ? (e / nr) * KB : 0;
+    double acc[KB];
+#pragma unroll
+    for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    for (int b0 = 0; b0 < N; b0 += chunk) {
+      const int nb = N - b0 < chunk ? N - b0 : chunk;
+      tm.sync();
+      for (int f = tm.tid; f < nb * k; f += tm.nt) {
+        const int bb = f / k, c = f % k;
+        stage[f] = V[(int64_t)c * N + b0 + bb];
+      }
+      tm.sync();
+      if (act) {
+        int bb = 0;
+        for (; bb + 8 <= nb; bb += 8) {
+          double mv[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) mv[u] = Mfull[(int64_t)(b0 + bb + u + 1) * ldm + a];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            const double* sv = stage + (bb + u) * k + c0;
+#pragma unroll
+            for (int c = 0; c < KB; ++c)
+              if (c0 + c < k) acc[c] += mv[u] * sv[c];
+          }
+        }
+        for (; bb < nb; ++bb) {
+          const double mv = Mfull[(int64_t)(b0 + bb + 1) * ldm + a];
+          const double* sv = stage + bb * k + c0;
+#pragma unroll
+          for (int c = 0; c < KB; ++c)
+            if (c0 + c < k) acc[c] += mv * sv[c];
+        }
+      }
+    }
+    if (act)
+#pragma unroll
+      for (int c = 0; c < KB; ++c)
+        if (c0 + c < k) TV[(int64_t)(c0 + c) * N + a] = acc[c];
+  }
+  tm.sync();
+}
+
+// The block [a0, a1) share of V^T M12 V and of the squared column norms of V:
+// P[i*k + j] = sum_a V[i*N + a] TV[j*N + a], P[k*k + i] = sum_a V[i*N + a]^2 over a in the
+// block, in the order of a.  The block's rows of V and TV pass through `stage`.
+template <class TM>
+TLA_HD void block_gram(TM& tm, const double* V, const double* TV, int N, int k, int a0, int a1, double* P,
+                       double* stage, int64_t stage_doubles) {
+  int rc = (int)(stage_doubles / (2 * (int64_t)k));
+  const int nr = a1 - a0;
+  if (rc > nr) rc = nr;
+  const int ne = k * k + k;
+  for (int base = 0; base < ne; base += tm.nt) {
+    const int e = base + tm.tid;
+    const int i = e < k * k ? e / k : e - k * k, j = e < k * k ? e % k : i;
+    const bool act = e < ne;
+    const bool sq = e >= k * k;
+    double acc = 0.0;
+    for (int r0 = 0; r0 < nr; r0 += rc) {
+      const int nb = nr - r0 < rc ? nr - r0 : rc;
+      tm.sync();
+      for (int f = tm.tid; f < nb * k; f += tm.nt) {
+        const int c = f / nb, r = f % nb;
+        stage[c * rc + r] = V[(int64_t)c * N + a0 + r0 + r];
+        stage[(k + c) * rc + r] = TV[(int64_t)c * N + a0 + r0 + r];
+      }
+      tm.sync();
+      if (act) {
+        const double* vi = stage + i * rc;
+        const double* tj = sq ? stage + i * rc : stage + (k + j) * rc;
+        for (int r = 0; r < nb; ++r) acc += vi[r] * tj[r];
+      }
+    }
+    if (act) P[e] = acc;
+  }
+  tm.sync();
+}
+
+// G[t*k + j] = sum_i (V[i*N + t] / nu[i] / sigma[i]) W[j*k + i] for rows t in [t0, t1):
+// G = V S^-1 W with the columns of V normalised by nu.
+template <class TM>
+TLA_HD void g_rows(TM& tm, const double* V, int N, int k, const double* nu, const double* sigma, const cpx* W,
+                   cpx* G, int t0, int t1) {
+  const int nr = t1 - t0;
+  for (int64_t e = tm.tid; e < (int64_t)nr * k; e += tm.nt) {
+    const int t = t0 + (int)(e / k), j = (int)(e % k);
+    double re = 0.0, im = 0.0;
+    for (int i = 0; i < k; ++i) {
+      const double v = V[(int64_t)i * N + t] / nu[i] / sigma[i];
+      const cpx wv = W[(int64_t)j * k + i];
+      re += v * wv.re;
+      im += v * wv.im;
+    }
+    G[(int64_t)t * k + j] = cmk(re, im);
+  }
+  tm.sync();
+}
+
 // Status codes (match cdmd_status).
 constexpr int kOk = 0, kRankDeficient = 5, kNumeric = 6;
 
-// Algorithm 1 steps 4, 6, 7 and G = V S^-1 W from the Gram Gr (m x m, symmetric) of the
-// unscaled sketch.  sketch_scale multiplies the sketch (so sigma = sqrt(mu) * scale).
-// Outputs: mu[k] (Gram eigenvalues), sigma[k], lam[k] and W (k x k, column j at j*k)
-// as cpx, G (N x k, row t at t*k) as cpx.  Returns the status; *Jout = Krylov size.
+// Algorithm 1 step 4, first part: the top-k eigenpairs of the Gram Gr[0:N, 0:N] (N = m-1)
+// of the unscaled sketch by Lanczos; mu[k] the eigenvalues, Z (J x k) the Ritz vectors of
+// T_J (V = Q_J Z is formed by ritz_rows).  Returns the status; *Jout = Krylov size.
 template <class TM>
-TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int Jmax,
-                        double sketch_scale, const SmallLAWork& ws, double* mu, double* sigma,
-                        cpx* lam, cpx* W, cpx* G, int* Jout) {
+TLA_HD int small_la_phase_a(TM& tm, const double* Gr, int m, int k, double rtol, int Jmax,
+                            const SmallLAWork& ws, double* mu, double* Z, int* Jout) {
   const int N = m - 1;
-  // non-finite input
   {
     double bad = 0.0;
     for (int64_t e = tm.tid; e < (int64_t)m * m; e += tm.nt)
@@ -996,19 +1076,42 @@ TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int
     if (tm.sum(bad) > 0.0) return kNumeric;
   }
   tm.stamp(2);
-  const int J = lanczos_topk(tm, Gr, m, N, k, rtol, Jmax, ws.Q, ws.lz, mu, ws.V);
+  const int J = lanczos_topk(tm, Gr, m, N, k, rtol, Jmax, ws.Q, ws.lz, mu, ws.V, Z);
   tm.stamp(3);
   *Jout = J;
   if (J < 0) return kNumeric;
   if (!(mu[0] > 0.0) || !(mu[k - 1] > 1e-12 * mu[0])) return kRankDeficient;
-  double* s = ws.lz.h;  // reuse: sqrt(mu)
-  for (int i = tm.tid; i < k; i += tm.nt) s[i] = sqrt(mu[i]);
+  return kOk;
+}
+
+// Algorithm 1 steps 4 (end), 6 and 7, given the block partials P (nblk blocks of k*k + k,
+// from block_gram over V = Q_J Z and TV = M12 V): nu the column norms of V, sigma =
+// sqrt(mu) * sketch_scale, A~ = S^-1 Vn^T M12 Vn S^-1 with Vn = V diag(1/nu), its
+// eigenvalues lam and eigenvectors W (column j at j*k, unit, largest entry real positive).
+template <class TM>
+TLA_HD int small_la_phase_b(TM& tm, int N, int k, double sketch_scale, const SmallLAWork& ws, int nblk,
+                            const double* mu, double* sigma, cpx* lam, cpx* W) {
+  double* nu = ws.nu;
+  double* s = ws.nu + k;  // sqrt(mu)
+  const int64_t ne = (int64_t)k * k + k;
+  for (int i = tm.tid; i < k; i += tm.nt) {
+    s[i] = sqrt(mu[i]);
+    sigma[i] = s[i] * sketch_scale;
+    double q = 0.0;
+    for (int b = 0; b < nblk; ++b) q += ws.P[b * ne + (int64_t)k * k + i];
+    nu[i] = sqrt(q);
+  }
   tm.sync();
-  for (int i = tm.tid; i < k; i += tm.nt) sigma[i] = s[i] * sketch_scale;
+  for (int e = tm.tid; e < k * k; e += tm.nt) {
+    const int i = e / k, j = e % k;
+    double a0 = 0.0;
+    for (int b = 0; b < nblk; ++b) a0 += ws.P[b * ne + e];
+    ws.At[e] = a0 / (nu[i] * nu[j] * s[i] * s[j]);
+  }
+  tm.sync();
+  tm.stamp(4);
   double* fastr = ws.lz.fast;
   const int64_t fastd = ws.lz.fast_doubles;
-  reduced_operator(tm, Gr, m, N, k, ws.V, s, ws.TV, ws.At, fastr, fastd);
-  tm.stamp(4);
   double* ev = ws.lz.w;  // reuse: 2k doubles
   if (tm.tid == 0) ws.flag[0] = 0;
   tm.sync();
@@ -1032,19 +1135,36 @@ TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int
   for (int j = tm.tid; j < k; j += tm.nt) normalise_vec(W + (int64_t)j * k, k);
   tm.sync();
   tm.stamp(6);
-  // G = V diag(1/sigma) W
-  for (int64_t e = tm.tid; e < (int64_t)N * k; e += tm.nt) {
-    const int t = (int)(e / k), j = (int)(e % k);
-    double re = 0.0, im = 0.0;
-    for (int i = 0; i < k; ++i) {
-      const double v = ws.V[(int64_t)i * N + t] / sigma[i];
-      const cpx wv = W[(int64_t)j * k + i];
-      re += v * wv.re;
-      im += v * wv.im;
-    }
-    G[e] = cmk(re, im);
+  return kOk;
+}
+
+// Algorithm 1 steps 4, 6, 7 and G = V S^-1 W from the Gram Gr (m x m, symmetric) of the
+// unscaled sketch, by one team: phase A, V = Q Z, TV = M12 V, phase B, G.  sketch_scale
+// multiplies the sketch (so sigma = sqrt(mu) * scale).  Outputs: mu[k] (Gram eigenvalues),
+// sigma[k], lam[k] and W (k x k, column j at j*k) as cpx, G (N x k, row t at t*k) as cpx.
+// Returns the status; *Jout = Krylov size.  (The device runs the same phases as separate
+// kernels, the row-range steps on many workgroups.)
+template <class TM>
+TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int Jmax,
+                        double sketch_scale, const SmallLAWork& ws, double* mu, double* sigma,
+                        cpx* lam, cpx* W, cpx* G, int* Jout) {
+  const int N = m - 1;
+  int st = small_la_phase_a(tm, Gr, m, k, rtol, Jmax, ws, mu, ws.Z, Jout);
+  if (st != kOk) return st;
+  const int nblk = (N + kLaRows - 1) / kLaRows;
+  const int64_t ne = (int64_t)k * k + k;
+  for (int b = 0; b < nblk; ++b) {
+    const int t1 = (b + 1) * kLaRows < N ? (b + 1) * kLaRows : N;
+    ritz_rows(tm, ws.Q, N, *Jout, ws.Z, k, ws.V, b * kLaRows, t1);
   }
-  tm.sync();
+  for (int b = 0; b < nblk; ++b) {
+    const int t1 = (b + 1) * kLaRows < N ? (b + 1) * kLaRows : N;
+    m12v_rows(tm, Gr, m, N, k, ws.V, ws.TV, b * kLaRows, t1, ws.lz.fast, ws.lz.fast_doubles);
+    block_gram(tm, ws.V, ws.TV, N, k, b * kLaRows, t1, ws.P + b * ne, ws.lz.fast, ws.lz.fast_doubles);
+  }
+  st = small_la_phase_b(tm, N, k, sketch_scale, ws, nblk, mu, sigma, lam, W);
+  if (st != kOk) return st;
+  g_rows(tm, ws.V, N, k, ws.nu, sigma, W, G, 0, N);
   tm.stamp(7);
   return kOk;
 }
@@ -1057,7 +1177,7 @@ namespace tla {
 
 // Offsets (in doubles) of the global scratch of one small-LA solve.
 struct SmallLALayout {
-  int64_t Q, T, V, TV, At, Hs, LU, bb, yy, piv, total;
+  int64_t Q, T, V, Z, TV, P, nu, At, Hs, LU, bb, yy, piv, total;
 };
 TLA_HD inline SmallLALayout small_la_layout(int N, int k, int Jmax) {
   SmallLALayout L;
@@ -1065,7 +1185,10 @@ TLA_HD inline SmallLALayout small_la_layout(int N, int k, int Jmax) {
   L.Q = o;  o += (int64_t)(Jmax + 1) * N;
   L.T = o;  o += (int64_t)Jmax + k + 6 * (int64_t)Jmax * k;
   L.V = o;  o += (int64_t)N * k;
+  L.Z = o;  o += (int64_t)Jmax * k;
   L.TV = o; o += (int64_t)N * k;
+  L.P = o;  o += (int64_t)((N + kLaRows - 1) / kLaRows) * ((int64_t)k * k + k);
+  L.nu = o; o += 2 * (int64_t)k;
   L.At = o; o += (int64_t)k * k;
   L.Hs = o; o += (int64_t)k * k;
   L.LU = o; o += 2 * (int64_t)k * k * k;

@@ -13,24 +13,26 @@ int team_small_la_host(const double* Gr, int m, int k, double rtol, int Jmax, do
   const int N = m - 1;
   if (Jmax > N) Jmax = N;
   std::vector<double> q(N), w(N > 2 * k ? N : 2 * k), h(Jmax + 2), alpha(Jmax + 2), beta(Jmax + 2);
-  std::vector<double> T((size_t)Jmax + k + 6 * (size_t)Jmax * k);
-  std::vector<double> Q((size_t)(Jmax + 1) * N), V((size_t)N * k), TV((size_t)N * k), At(k * k), Hs(k * k);
-  std::vector<cpx> LU((size_t)k * k * k), bb((size_t)k * k), yy((size_t)k * k);
-  std::vector<int> piv((size_t)k * k), flag(1);
+  const SmallLALayout L = small_la_layout(N, k, Jmax);
+  std::vector<double> scr((size_t)L.total);
+  std::vector<int> flag(1);
   SmallLAWork ws;
   const int64_t fastd = 15488;  // as the device's LDS region
   std::vector<double> fast(fastd);
-  ws.lz = LanczosWork{q.data(), w.data(), h.data(), alpha.data(), beta.data(), T.data(),
-                      fast.data(), fastd};
-  ws.Q = Q.data();
-  ws.V = V.data();
-  ws.TV = TV.data();
-  ws.At = At.data();
-  ws.Hs = Hs.data();
-  ws.LU = LU.data();
-  ws.bb = bb.data();
-  ws.yy = yy.data();
-  ws.piv = piv.data();
+  double* sp = scr.data();
+  ws.lz = LanczosWork{q.data(), w.data(), h.data(), alpha.data(), beta.data(), sp + L.T, fast.data(), fastd};
+  ws.Q = sp + L.Q;
+  ws.V = sp + L.V;
+  ws.Z = sp + L.Z;
+  ws.TV = sp + L.TV;
+  ws.P = sp + L.P;
+  ws.nu = sp + L.nu;
+  ws.At = sp + L.At;
+  ws.Hs = sp + L.Hs;
+  ws.LU = reinterpret_cast<cpx*>(sp + L.LU);
+  ws.bb = reinterpret_cast<cpx*>(sp + L.bb);
+  ws.yy = reinterpret_cast<cpx*>(sp + L.yy);
+  ws.piv = reinterpret_cast<int*>(sp + L.piv);
   ws.flag = flag.data();
   HostTeam tm;
   return small_la_run(tm, Gr, m, k, rtol, Jmax, scale, ws, mu, sigma, reinterpret_cast<cpx*>(lam),
