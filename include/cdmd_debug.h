@@ -38,13 +38,15 @@ cdmd_status cdmd_dbg_omp_gram(const double* H, int32_t k, const double* c, doubl
                               double* resid2);
 
 /* The device small linear algebra (Algorithm 1 steps 4, 6, 7 and G = V S^-1 W from the
-   m x m Gram Gr of the unscaled sketch), run by one host thread with the same code the
-   GPU runs per workgroup.  Outputs: mu[k] Gram eigenvalues (descending), sigma[k],
-   lam[2k] (re, im), W[2k*k] (column j at 2*j*k, re/im interleaved), G[2(m-1)k] (row t
-   at 2*t*k), *steps Krylov dimension.  Returns OK, RANK_DEFICIENT or NUMERIC. */
+   m x m Gram Gr of the unscaled sketch), run on the host with the same code the GPU runs:
+   groups = 1 by one thread; groups = 2..32 with the Lanczos vectors split by rows over that
+   many host threads, which exchange their shares as the GPU's workgroups do.  Outputs:
+   mu[k] Gram eigenvalues (descending), sigma[k], lam[2k] (re, im), W[2k*k] (column j at
+   2*j*k, re/im interleaved), G[2(m-1)k] (row t at 2*t*k), *steps Krylov dimension.
+   Returns OK, RANK_DEFICIENT, NUMERIC, or INVALID_ARG for a bad argument. */
 cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, double rtol,
-                                   double sketch_scale, double* mu, double* sigma, double* lam,
-                                   double* W, double* G, int32_t* steps);
+                                   double sketch_scale, int32_t groups, double* mu, double* sigma,
+                                   double* lam, double* W, double* G, int32_t* steps);
 
 /* Phase times (ms) of the last device small-LA solve: [0] Lanczos incl. convergence
    checks, [1] of which the tridiagonal eigen-solves of the checks, [2] Ritz vectors
@@ -66,6 +68,11 @@ cdmd_status cdmd_dbg_force_gather_sketch(cdmd_model* mdl, int32_t on);
    device workgroup solve (which runs for 16-byte aligned uint8 videos with m <= 1025).
    Takes effect at the next cdmd_fit.  Errors: INVALID_ARG. */
 cdmd_status cdmd_dbg_force_host_la(cdmd_model* mdl, int32_t on);
+
+/* Split the Lanczos vectors of the device small-LA solve over at most `groups` row groups
+   (workgroups; 0 = as many as the rows call for: one per 32 rows, at most 32).  Takes
+   effect at the next cdmd_fit.  Errors: INVALID_ARG (groups outside [0, 32]). */
+cdmd_status cdmd_dbg_la_groups(cdmd_model* mdl, int32_t groups);
 
 /* Force (1) or release (0) the float32 vector-ALU lift for a uint8 video whose FP32
    lift would otherwise run on MFMA (bf16 terms).  Takes effect at the next cdmd_fit.

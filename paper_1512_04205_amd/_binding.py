@@ -30,7 +30,7 @@ EXPORTED = [
     "cdmd_abi_version", "cdmd_last_error", "cdmd_create", "cdmd_fit", "cdmd_modes",
     "cdmd_select", "cdmd_background", "cdmd_foreground", "cdmd_get_sketch",
     "cdmd_info_get", "cdmd_set_timing", "cdmd_free", "cdmd_dbg_force_valu_lift",
-    "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases",
+    "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases", "cdmd_dbg_la_groups",
     "cdmd_dbg_force_gather_sketch",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
@@ -103,6 +103,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_set_timing.argtypes = [P, I32]
     lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
+    lib.cdmd_dbg_la_groups.argtypes = [P, I32]
     lib.cdmd_dbg_force_gather_sketch.argtypes = [P, I32]
     lib.cdmd_dbg_la_phases.argtypes = [P, DP]
     lib.cdmd_mode_features.argtypes = [P, P, P]
@@ -300,6 +301,10 @@ class Model:
     def force_host_la(self, on: bool = True):
         """Test hook: float64 small linear algebra on the host instead of the device."""
         _check(load_library().cdmd_dbg_force_host_la(self._h, int(on)))
+
+    def la_groups(self, groups: int):
+        """Test hook: at most `groups` Lanczos row groups in the device solve (0: auto)."""
+        _check(load_library().cdmd_dbg_la_groups(self._h, int(groups)))
 
     def la_phases(self) -> dict:
         """Phase times (ms) of the last device small-LA solve."""

@@ -139,6 +139,7 @@ struct cdmd_model {
   bool timing = false, recon_pending = false;
   bool force_valu_lift = false;  // test hook: use the float32 VALU lift for uint8 video
   bool force_host_la = false;    // test hook: float64 small LA on the host
+  int la_groups = 0;             // test hook: Lanczos row groups of the device solve (0: auto)
   double la_phase_ms[16] = {};
   // device small LA (one workgroup)
   bool device_la_ok = false;     // sized at create
@@ -855,7 +856,7 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
     TRY(run_sketch(M, d_video, st, false));
     HIPCHK(cdmd::k::small_la(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
                              (double)M->xscale, M->d_la_scratch, M->d_la_out, M->d_Gp, M->lm_nb,
-                             M->lm_nsplit, M->lm_nksteps, st));
+                             M->lm_nsplit, M->lm_nksteps, M->la_groups, st));
     t1 = t2 = now_ms();
   } else {
     TRY(run_sketch(M, d_video, st, true));
@@ -1239,7 +1240,7 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
       B->dev.push_back(i);
       desc.push_back(cdmd::k::SLADesc{M->d_gram, M->d_la_scratch, M->d_la_out, (uint16_t*)M->d_Gp, kLanczosTol,
                                       M->sketch_scale, (double)M->xscale, (int)M->m, M->k, M->la_jmax,
-                                      M->lm_nb, M->lm_nsplit, M->lm_nksteps});
+                                      M->lm_nb, M->lm_nsplit, M->lm_nksteps, M->la_groups});
       B->la_nmax = std::max(B->la_nmax, (int)M->m - 1);
       B->la_gmax = std::max(B->la_gmax, std::max((int)M->m - 1, 16 * M->lm_nksteps));
     }
@@ -1664,13 +1665,14 @@ cdmd_status cdmd_set_timing(cdmd_model* M, int32_t enable) {
 extern "C" {
 
 cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, double rtol,
-                                   double sketch_scale, double* mu, double* sigma, double* lam,
-                                   double* W, double* G, int32_t* steps) {
+                                   double sketch_scale, int32_t groups, double* mu, double* sigma,
+                                   double* lam, double* W, double* G, int32_t* steps) {
   g_err.clear();
-  if (!Gr || !mu || !sigma || !lam || !W || !G || m < 2 || k < 1 || k > m - 1)
+  if (!Gr || !mu || !sigma || !lam || !W || !G || m < 2 || k < 1 || k > m - 1 || groups < 1 ||
+      groups > 32)
     return fail(CDMD_E_INVALID_ARG, "bad arguments");
   int J = 0;
-  const int st = cdmd::team_small_la_host(Gr, m, k, rtol, std::min(m - 1, 320), sketch_scale, mu,
+  const int st = cdmd::team_small_la_host(Gr, m, k, rtol, std::min(m - 1, 320), sketch_scale, groups, mu,
                                           sigma, lam, W, G, &J);
   if (steps) *steps = J;
   if (st != 0) return fail((cdmd_status)st, "team small LA failed");
@@ -1695,6 +1697,13 @@ cdmd_status cdmd_dbg_force_host_la(cdmd_model* M, int32_t on) {
   g_err.clear();
   if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
   M->force_host_la = on != 0;
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_la_groups(cdmd_model* M, int32_t groups) {
+  g_err.clear();
+  if (!M || groups < 0 || groups > 32) return fail(CDMD_E_INVALID_ARG, "groups must be in [0, 32]");
+  M->la_groups = groups;
   return CDMD_OK;
 }
 

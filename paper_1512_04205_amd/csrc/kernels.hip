@@ -1151,29 +1151,132 @@ __device__ void la_work(tla::SmallLAWork& ws, const SLADesc& d, double* s_q, dou
   ws.flag = s_flag;
 }
 
-// Lanczos and the Ritz vectors of T_J (one 1024-thread workgroup per solve).
-__global__ __launch_bounds__(1024) void k_la_a(SLADesc d1, const SLADesc* __restrict__ ds) {
+// Exchange between the workgroups of one solve (the row groups of the Lanczos vectors).
+// The shares travel through global memory as device-scope (agent) atomic stores and loads,
+// which are performed at the device's coherence point, so no cache write-back or
+// invalidation is needed: each wave waits for its stores to complete, one thread arrives
+// at a counter and waits for all groups, then every wave loads the shares.  The wait is
+// bounded: past kSpinLimit polls the exchange reports failure and the kernel returns.
+constexpr unsigned kSpinLimit = 1u << 21;
+
+__device__ __forceinline__ void st_dev(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double ld_dev(const double* p) {
+  return __hip_atomic_load(const_cast<double*>(p), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+struct GridX {
+  int g, G, r0, r1, N, NQ, PS;
+  double* xb;       // two buffers of G*PS partials and an NQ-vector (128-byte aligned)
+  unsigned* bar;    // arrivals (zeroed before the launch)
+  unsigned nx;      // exchanges so far
+  int* s_ok;        // LDS: the wait's outcome
+  __device__ bool exchange(DevTeam& tm, const double* part, int n, double* sum, const double* slice,
+                           double* full) {
+    tm.sync();
+    if (G == 1) {
+      if (sum != part)
+        for (int i = tm.tid; i < n; i += tm.nt) sum[i] = part[i];
+      if (slice != nullptr && full != slice)
+        for (int t = r0 + tm.tid; t < r1; t += tm.nt) full[t] = slice[t];
+      tm.sync();
+      return true;
+    }
+    // consecutive exchanges use alternate buffers: a buffer is written again only after
+    // every group has passed the exchange in between, so after all have read it
+    double* base = xb + (int64_t)(nx & 1u) * ((int64_t)G * PS + NQ);
+    for (int i = tm.tid; i < n; i += tm.nt) st_dev(&base[(int64_t)g * PS + i], part[i]);
+    if (slice != nullptr)
+      for (int t = r0 + tm.tid; t < r1; t += tm.nt) st_dev(&base[(int64_t)G * PS + t], slice[t]);
+    ++nx;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
+    __syncthreads();
+    if (tm.tid == 0) {
+      const unsigned target = nx * (unsigned)G;
+      __hip_atomic_fetch_add(bar, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      int ok = 1;
+      unsigned spins = 0;
+      while (__hip_atomic_load(bar, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (++spins > kSpinLimit) {
+          ok = 0;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+      }
+      s_ok[0] = ok;
+    }
+    __syncthreads();
+    if (s_ok[0] == 0) return false;  // uniform
+    for (int i = tm.tid; i < n; i += tm.nt) {
+      double v = 0.0;
+      for (int q = 0; q < G; ++q) v += ld_dev(&base[(int64_t)q * PS + i]);
+      sum[i] = v;
+    }
+    if (full != nullptr)
+      for (int t = tm.tid; t < N; t += tm.nt) full[t] = ld_dev(&base[(int64_t)G * PS + t]);
+    tm.sync();
+    return true;
+  }
+};
+
+// Clears a solve's status, Krylov size, phase clocks and exchange counter.
+__global__ __launch_bounds__(64) void k_la_prep(SLADesc d1, const SLADesc* __restrict__ ds) {
   using namespace tla;
   const SLADesc& d = la_desc(d1, ds, blockIdx.x);
+  const int N = d.m - 1;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, d.k);
+  const SmallLALayout Ls = small_la_layout(N, d.k, d.Jmax);
+  const int t = threadIdx.x;
+  if (t < 16) d.out[Lo.timing + t] = 0.0;
+  if (t == 0) {
+    d.out[Lo.status] = 0.0;
+    d.out[Lo.J] = 0.0;
+    *reinterpret_cast<unsigned*>(d.scratch + Ls.X) = 0u;
+  }
+}
+
+// Lanczos and the Ritz vectors of T_J: la_groups(N) 1024-thread workgroups per solve
+// (blockIdx.x), each owning a range of rows of the Lanczos vectors; group 0 runs the
+// convergence checks and writes the results.
+__global__ __launch_bounds__(1024) void k_la_a(SLADesc d1, const SLADesc* __restrict__ ds) {
+  using namespace tla;
+  const SLADesc& d = la_desc(d1, ds, blockIdx.y);
+  const int m = d.m, k = d.k, N = m - 1;
+  const int G = d.groups > 0 && d.groups < la_groups(N) ? d.groups : la_groups(N), g = blockIdx.x;
+  if (g >= G) return;  // uniform: this solve needs fewer groups than the grid has
   __shared__ double s_q[SLA_NMAX], s_w[SLA_NMAX];
   __shared__ double s_h[SLA_JMAX + 4], s_alpha[SLA_JMAX + 4], s_beta[SLA_JMAX + 4];
   __shared__ double s_red[16];
-  __shared__ int s_flag[1];
+  __shared__ int s_flag[1], s_ok[1];
   __shared__ double s_fast[SLA_FAST];
-  const int m = d.m, k = d.k, N = m - 1;
   const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
   double* out = d.out;
   DevTeam tm;
-  la_team(tm, s_red, out + Lo.timing);
-  if (tm.tid == 0)
-    for (int i = 0; i < 16; ++i) tm.tslots[i] = 0.0;
+  la_team(tm, s_red, g == 0 ? out + Lo.timing : nullptr);
   SmallLAWork ws;
   la_work(ws, d, s_q, s_w, s_h, s_alpha, s_beta, s_fast, s_flag);
+  GridX xg;
+  xg.g = g;
+  xg.G = G;
+  la_group_rows(N, G, g, &xg.r0, &xg.r1);
+  xg.N = N;
+  xg.NQ = la_ldq(N);
+  xg.PS = la_xps(d.Jmax);
+  xg.bar = reinterpret_cast<unsigned*>(d.scratch + Ls.X);
+  xg.xb = d.scratch + Ls.X + 16;
+  xg.nx = 0;
+  xg.s_ok = s_ok;
   int J = 0;
-  const int st = small_la_phase_a(tm, d.Gr, m, k, d.rtol, d.Jmax, ws, out + Lo.mu, ws.Z, &J);
+  const int st = small_la_phase_a(tm, xg, d.Gr, m, k, d.rtol, d.Jmax, ws, out + Lo.mu, ws.Z, &J);
   if (tm.tid == 0) {
-    out[Lo.status] = (double)st;
-    out[Lo.J] = (double)J;
+    if (g == 0) {
+      out[Lo.status] = (double)st;
+      out[Lo.J] = (double)J;
+    } else if (st == kDevice) {
+      out[Lo.status] = (double)st;
+    }
   }
 }
 
@@ -1290,7 +1393,8 @@ static hipError_t launch_la(const SLADesc& d1, const SLADesc* ds, int count, int
                             hipStream_t stream) {
   const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
   const int gb = (gmax + tla::kLaRows - 1) / tla::kLaRows;
-  hipLaunchKernelGGL(k_la_a, dim3(count), dim3(1024), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_prep, dim3(count), dim3(64), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_a, dim3(tla::la_groups(nmax), count), dim3(1024), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_ritz, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_b, dim3(count), dim3(1024), 0, stream, d1, ds);
@@ -1303,10 +1407,10 @@ bool small_la_fits(int m, int k, int Jmax) {
 }
 
 hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
-                    double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                    double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS, int groups,
                     hipStream_t stream) {
   if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
-  const SLADesc d{Gr, scratch, out, (uint16_t*)Gp, rtol, sketch_scale, xscale, m, k, Jmax, NB, NS, KS};
+  const SLADesc d{Gr, scratch, out, (uint16_t*)Gp, rtol, sketch_scale, xscale, m, k, Jmax, NB, NS, KS, groups};
   return launch_la(d, nullptr, 1, m - 1, std::max(m - 1, 16 * KS), stream);
 }
 

@@ -123,8 +123,9 @@ hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* 
 // lam[2k], W[2k*k], G[2(m-1)k]] (team_la.hpp small_la_out_layout) and, on success, the
 // lift B operands Gp (NB column blocks, NS bf16 terms, KS k-steps) of G * xscale.
 // Needs m - 1 <= 1024 and Jmax <= 320.  scratch: small_la_scratch_doubles(m, k, Jmax).
+// groups: Lanczos row groups (workgroups), 0 = as many as the rows call for.
 hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
-                    double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                    double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS, int groups,
                     hipStream_t stream);
 int64_t small_la_scratch_doubles(int m, int k, int Jmax);
 // A batch of independent solves in one launch (one workgroup each); d_descs is device
@@ -136,6 +137,7 @@ struct SLADesc {
   uint16_t* Gp;
   double rtol, sketch_scale, xscale;
   int m, k, Jmax, NB, NS, KS;
+  int groups;  // Lanczos row groups (workgroups); 0: as many as the rows call for
 };
 bool small_la_fits(int m, int k, int Jmax);
 // nmax: the largest m - 1 of the batch; gmax: the largest max(m - 1, 16 KS).

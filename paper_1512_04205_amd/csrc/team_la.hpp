@@ -76,7 +76,7 @@ struct HostTeam {
 struct LanczosWork {
   double* q;      // N        current vector (shared)
   double* w;      // N        (shared)
-  double* h;      // Jmax+1   projections (shared)
+  double* h;      // Jmax+2   projections (shared)
   double* alpha;  // Jmax+1   (shared)
   double* beta;   // Jmax+1   (shared)
   double* T;      // Jmax + k + 6 Jmax k: tridiagonal eigen-solve work (global scratch)
@@ -321,21 +321,134 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
   tm.sync();
 }
 
-// Top-k eigenpairs of the symmetric N x N matrix M (element (r, c) at M[r*ldm + c]).
-// Q: (Jmax+1) x N scratch (vector-contiguous).  On return evals[k] descending and
-// V (N x k, column-major) the unit Ritz vectors, or, when Zout is given, instead the
-// Ritz vectors of T_J in Zout (J x k, element (i, c) at i*k + c); the return value is the
-// Krylov dimension J, or -1 on failure.  Converged when every top-k Ritz residual
-// beta_J |z_J| <= rtol * theta_1, or J = N.
+// --------------------------------------------------------------------------- row groups
+// The Lanczos vectors are split by rows over G groups (workgroups of one grid on the
+// device; one group on the host).  Group g owns rows [r0, r1) of every vector, computes
+// its share of each dot product, and the groups combine their shares through an
+// exchange X, which provides
+//   int g, G, r0, r1;
+//   bool exchange(TM& tm, const double* part, int n, double* sum, const double* slice,
+//                 double* full);
+// Every group publishes part[0, n) and, when slice is given, slice[r0, r1); once all have,
+// sum[i] is the sum over groups, in the order 0..G-1, of their part[i] (the same value in
+// every group), and full[0, N) the published rows of every group.  part and sum may be
+// the same array, as may slice and full.  False means the exchange could not complete
+// (the caller stops).  Rows of group g: la_group_rows.
+
+// Rows per group and the most groups of the device's split.
+constexpr int kLaGroupRows = 32, kLaGroupsMax = 32;
+TLA_HD inline int la_groups(int N) {
+  const int G = (N + kLaGroupRows - 1) / kLaGroupRows;
+  return G < 1 ? 1 : (G > kLaGroupsMax ? kLaGroupsMax : G);
+}
+// Row stride of the Lanczos basis Q: N rounded up to 16 doubles (128 bytes), so that with
+// group boundaries at multiples of 16 rows no cache line holds rows of two groups (the
+// groups may run behind different, non-coherent caches).
+TLA_HD inline int la_ldq(int N) { return (N + 15) & ~15; }
+// Stride of a group's partial array in the exchange buffers (Jmax + 2 rounded to 16).
+TLA_HD inline int la_xps(int Jmax) { return (Jmax + 2 + 15) & ~15; }
+// Rows [r0, r1) of group g of G: blocks of a multiple of 16 rows (the last shorter or
+// empty).
+TLA_HD inline void la_group_rows(int N, int G, int g, int* r0, int* r1) {
+  const int per = (((N + G - 1) / G) + 15) & ~15;
+  const int a = g * per, b = (g + 1) * per;
+  *r0 = a < N ? a : N;
+  *r1 = b < N ? b : N;
+}
+
+// The exchange of a single group.
+struct LocalX {
+  int g = 0, G = 1, r0 = 0, r1 = 0;
+  template <class TM>
+  TLA_HD bool exchange(TM& tm, const double* part, int n, double* sum, const double* slice, double* full) {
+    tm.sync();
+    if (sum != part)
+      for (int i = tm.tid; i < n; i += tm.nt) sum[i] = part[i];
+    if (slice != nullptr && full != slice)
+      for (int t = r0 + tm.tid; t < r1; t += tm.nt) full[t] = slice[t];
+    tm.sync();
+    return true;
+  }
+};
+
+// y[r] = sum_{i < n} x[i] A[i*lda + r] (or y[r] -= that sum) for r in [r0, r1): thread
+// (r, group of i), eight loads in flight; the groups' partial sums (in `part`) combine in
+// the order of the groups.
 template <class TM>
-TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double rtol, int Jmax,
-                        double* Q, const LanczosWork& ws, double* evals, double* V,
-                        double* Zout = nullptr) {
+TLA_HD void colsum_rows(TM& tm, const double* A, int64_t lda, const double* x, int n, int r0, int r1, double* y,
+                        bool subtract, double* part, int64_t part_doubles) {
+  const int nr = r1 - r0;
+  if (nr <= 0) {
+    tm.sync();
+    return;
+  }
+  int G = tm.nt / nr;
+  if (G > 32) G = 32;
+  if (G < 1 || part == nullptr || (int64_t)G * nr > part_doubles) G = 1;
+  for (int e = tm.tid; e < G * nr; e += tm.nt) {
+    const int r = r0 + e % nr, g = e / nr;
+    const int i0 = (int)((int64_t)n * g / G), i1 = (int)((int64_t)n * (g + 1) / G);
+    const double* col = A + r;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
+    int i = i0;
+    for (; i + 8 <= i1; i += 8) {
+      a0 += col[(int64_t)i * lda] * x[i];
+      a1 += col[(int64_t)(i + 1) * lda] * x[i + 1];
+      a2 += col[(int64_t)(i + 2) * lda] * x[i + 2];
+      a3 += col[(int64_t)(i + 3) * lda] * x[i + 3];
+      a4 += col[(int64_t)(i + 4) * lda] * x[i + 4];
+      a5 += col[(int64_t)(i + 5) * lda] * x[i + 5];
+      a6 += col[(int64_t)(i + 6) * lda] * x[i + 6];
+      a7 += col[(int64_t)(i + 7) * lda] * x[i + 7];
+    }
+    for (; i < i1; ++i) a0 += col[(int64_t)i * lda] * x[i];
+    const double acc = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
+    if (G == 1) y[r] = subtract ? y[r] - acc : acc;
+    else part[(int64_t)g * nr + (r - r0)] = acc;
+  }
+  tm.sync();
+  if (G > 1) {
+    for (int r = r0 + tm.tid; r < r1; r += tm.nt) {
+      double acc = part[r - r0];
+      for (int g = 1; g < G; ++g) acc += part[(int64_t)g * nr + (r - r0)];
+      y[r] = subtract ? y[r] - acc : acc;
+    }
+    tm.sync();
+  }
+}
+
+// h[i] = sum over the group's rows of Q[i*ldq + t] w[t], i < n (this group's share): a
+// wave per i, lanes over the rows.
+template <class TM>
+TLA_HD void dots_rows(TM& tm, const double* Q, int ldq, const double* w, int n, int r0, int r1, double* h) {
+  for (int i = tm.wave; i < n; i += tm.nwaves) {
+    const double* qi = Q + (int64_t)i * ldq;
+    double s = 0.0;
+    for (int t = r0 + tm.lane; t < r1; t += tm.wsize) s += qi[t] * w[t];
+    s = tm.wave_sum(s);
+    if (tm.lane == 0) h[i] = s;
+  }
+  tm.sync();
+}
+
+// Top-k eigenpairs of the symmetric N x N matrix M (element (r, c) at M[r*ldm + c]) by
+// Lanczos with full reorthogonalisation (classical Gram-Schmidt, twice), the rows split
+// over the groups of X.  Q: Jmax+1 vectors of stride la_ldq(N) (each group touches its
+// rows).  ws.q, ws.w: N (the group's own copies), ws.h: Jmax+2, ws.alpha, ws.beta: Jmax+1.
+// Converged when every top-k Ritz residual beta_J |z_J| <= rtol * theta_1, or J = N.  The
+// convergence checks run on group 0, which alone writes evals[k] (descending) and Z (J x k,
+// the Ritz vectors of T_J, element (i, c) at i*k + c).  Returns J, -1 on failure, -2 when
+// an exchange could not complete.
+template <class TM, class X>
+TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, double rtol, int Jmax,
+                        double* Q, const LanczosWork& ws, double* evals, double* Z) {
   if (Jmax > N) Jmax = N;
   double* q = ws.q;
   double* w = ws.w;
   double* h = ws.h;
-  // q_0
+  const int r0 = xg.r0, r1 = xg.r1, ldq = la_ldq(N);
+  const bool lead = xg.g == 0;
+  // q_0: every group forms the whole (deterministic) start vector
   {
     double s = 0.0;
     for (int i = tm.tid; i < N; i += tm.nt) {
@@ -344,10 +457,9 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
     }
     s = tm.sum(s);
     const double inv = 1.0 / sqrt(s);
-    for (int i = tm.tid; i < N; i += tm.nt) {
-      q[i] = lanczos_start(i, 0) * inv;
-      Q[i] = q[i];
-    }
+    for (int i = tm.tid; i < N; i += tm.nt) q[i] = lanczos_start(i, 0) * inv;
+    // (recomputed rather than read back from q: another thread wrote q[i])
+    for (int i = r0 + tm.tid; i < r1; i += tm.nt) Q[i] = lanczos_start(i, 0) * inv;
     tm.sync();
   }
   int J = 0;
@@ -355,103 +467,43 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
   if (check > Jmax) check = Jmax;
   double anorm = 0.0;
   int restarts = 0;
+  // w[rows] -= Q_n h[0, n): classical Gram-Schmidt against the first n vectors, twice;
+  // h[n-1] of both passes is added to *hsum (the Lanczos alpha)
+  auto orthogonalise = [&](int n, double* hsum) -> bool {
+    for (int pass = 0; pass < 2; ++pass) {
+      dots_rows(tm, Q, ldq, w, n, r0, r1, h);
+      if (!xg.exchange(tm, h, n, h, nullptr, nullptr)) return false;
+      if (hsum != nullptr) *hsum += h[n - 1];
+      colsum_rows(tm, Q, ldq, h, n, r0, r1, w, true, ws.fast, ws.fast_doubles);
+    }
+    return true;
+  };
+  // the squared norm of w and the whole of w, in every group
+  auto gather_norm = [&](double* nrm) -> bool {
+    double s = 0.0;
+    for (int t = r0 + tm.tid; t < r1; t += tm.nt) s += w[t] * w[t];
+    s = tm.sum(s);
+    if (tm.tid == 0) h[0] = s;
+    if (!xg.exchange(tm, h, 1, h, w, w)) return false;
+    *nrm = sqrt(h[0]);
+    tm.sync();
+    return true;
+  };
   for (int j = 0; j < Jmax; ++j) {
     tm.tick(-1);
-    // w = M q as columns of the symmetric M: thread r of column group g sums
-    // M[c][r] q[c] over its range of c (coalesced over r); groups combine in fixed order
-    {
-      int G = tm.nt / N;
-      if (G > 4) G = 4;
-      if (G < 1) G = 1;
-      double* part = ws.fast != nullptr && (int64_t)(G - 1) * N <= ws.fast_doubles ? ws.fast : nullptr;
-      if (part == nullptr) G = 1;
-      for (int t = tm.tid; t < G * N; t += tm.nt) {
-        const int r = t % N, g = t / N;
-        const int c0 = (int)((int64_t)N * g / G), c1 = (int)((int64_t)N * (g + 1) / G);
-        const double* col = M + r;
-        double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
-        int c = c0;
-        for (; c + 8 <= c1; c += 8) {
-          a0 += col[(int64_t)c * ldm] * q[c];
-          a1 += col[(int64_t)(c + 1) * ldm] * q[c + 1];
-          a2 += col[(int64_t)(c + 2) * ldm] * q[c + 2];
-          a3 += col[(int64_t)(c + 3) * ldm] * q[c + 3];
-          a4 += col[(int64_t)(c + 4) * ldm] * q[c + 4];
-          a5 += col[(int64_t)(c + 5) * ldm] * q[c + 5];
-          a6 += col[(int64_t)(c + 6) * ldm] * q[c + 6];
-          a7 += col[(int64_t)(c + 7) * ldm] * q[c + 7];
-        }
-        for (; c < c1; ++c) a0 += col[(int64_t)c * ldm] * q[c];
-        const double acc = ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7));
-        if (g == 0) w[r] = acc;
-        else part[(int64_t)(g - 1) * N + r] = acc;
-      }
-      tm.sync();
-      if (G > 1) {
-        for (int r = tm.tid; r < N; r += tm.nt) {
-          double acc = w[r];
-          for (int g = 1; g < G; ++g) acc += part[(int64_t)(g - 1) * N + r];
-          w[r] = acc;
-        }
-        tm.sync();
-      }
-    }
+    // w = M q over the group's rows, as columns of the symmetric M (coalesced over rows)
+    colsum_rows(tm, M, ldm, q, N, r0, r1, w, false, ws.fast, ws.fast_doubles);
     tm.tick(10);
     double aj = 0.0;
-    for (int pass = 0; pass < 2; ++pass) {
-      for (int i = tm.wave; i <= j; i += tm.nwaves) {
-        const double* qi = Q + (int64_t)i * N;
-        double s = 0.0;
-        for (int t = tm.lane; t < N; t += tm.wsize) s += qi[t] * w[t];
-        s = tm.wave_sum(s);
-        if (tm.lane == 0) h[i] = s;
-      }
-      tm.sync();
-      aj += h[j];
-      // w -= Q h: thread t of group g sums over its range of vectors; fixed-order combine
-      {
-        int G = tm.nt / N;
-        if (G > 4) G = 4;
-        double* part = ws.fast != nullptr && 4 * (int64_t)N <= ws.fast_doubles ? ws.fast : nullptr;
-        if (G < 1 || part == nullptr) G = 1;
-        for (int e = tm.tid; e < G * N; e += tm.nt) {
-          const int t = e % N, g = e / N;
-          const int i0 = (j + 1) * g / G, i1 = (j + 1) * (g + 1) / G;
-          double v0 = 0.0, v1 = 0.0, v2 = 0.0, v3 = 0.0, v4 = 0.0, v5 = 0.0, v6 = 0.0, v7 = 0.0;
-          int i = i0;
-          for (; i + 8 <= i1; i += 8) {
-            v0 += h[i] * Q[(int64_t)i * N + t];
-            v1 += h[i + 1] * Q[(int64_t)(i + 1) * N + t];
-            v2 += h[i + 2] * Q[(int64_t)(i + 2) * N + t];
-            v3 += h[i + 3] * Q[(int64_t)(i + 3) * N + t];
-            v4 += h[i + 4] * Q[(int64_t)(i + 4) * N + t];
-            v5 += h[i + 5] * Q[(int64_t)(i + 5) * N + t];
-            v6 += h[i + 6] * Q[(int64_t)(i + 6) * N + t];
-            v7 += h[i + 7] * Q[(int64_t)(i + 7) * N + t];
-          }
-          for (; i < i1; ++i) v0 += h[i] * Q[(int64_t)i * N + t];
-          const double acc = ((v0 + v1) + (v2 + v3)) + ((v4 + v5) + (v6 + v7));
-          if (G == 1) w[t] -= acc;
-          else if (g == 0) part[3 * N + t] = acc;
-          else part[(int64_t)(g - 1) * N + t] = acc;
-        }
-        tm.sync();
-        if (G > 1) {
-          for (int t = tm.tid; t < N; t += tm.nt) {
-            double acc = part[3 * N + t];
-            for (int g = 1; g < G; ++g) acc += part[(int64_t)(g - 1) * N + t];
-            w[t] -= acc;
-          }
-          tm.sync();
-        }
-      }
-    }
+    if (!orthogonalise(j + 1, &aj)) return -2;
     tm.tick(11);
     double nr = 0.0;
-    for (int t = tm.tid; t < N; t += tm.nt) nr += w[t] * w[t];
-    nr = sqrt(tm.sum(nr));
-    ws.alpha[j] = aj;  // identical value on every thread
-    ws.beta[j] = nr;
+    if (!gather_norm(&nr)) return -2;
+    if (tm.tid == 0) {
+      ws.alpha[j] = aj;  // the same value in every group
+      ws.beta[j] = nr;
+    }
+    tm.sync();
     J = j + 1;
     {
       const double an = fabs(aj) + nr + (j ? ws.beta[j - 1] : 0.0);
@@ -459,76 +511,64 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
     }
     const bool breakdown = nr <= 64.0 * kEps * anorm;
     if (J >= check || breakdown || J == N) {
-      // Ritz values of T_J by multisection, Ritz vectors of T_J by inverse iteration; the
-      // residual of Ritz pair i is beta_J |z_{J-1,i}|
-      tm.stamp(0);
-      tm.tick(12);
+      // group 0: Ritz values of T_J by multisection, Ritz vectors of T_J by inverse
+      // iteration; the residual of Ritz pair i is beta_J |z_{J-1,i}|.  Decision: 0 go on,
+      // 1 converged (or J = N), 2 failed.
       const int kk = k < J ? k : J;
       const int64_t need = J + kk + 6 * (int64_t)J * kk;
       double* b2 = ws.fast != nullptr && need <= ws.fast_doubles ? ws.fast : ws.T;
       double* theta = b2 + J;
       double* work = theta + kk;
       double* Zm = work + 5 * (int64_t)J * kk;
-      for (int i = tm.tid; i + 1 < J; i += tm.nt) b2[i] = ws.beta[i] * ws.beta[i];
-      tm.sync();
       double tnorm = 0.0;
-      tridiag_topk_values(tm, ws.alpha, ws.beta, b2, J, kk, theta, &tnorm);
-      tm.tick(13);
-      // Residual of Ritz pair i: beta_J |z_{J-1,i}|.  The closed form of the last
-      // components is exact where they are large but has an absolute floor near
-      // sqrt(eps): it can show that a pair has not converged, not that it has.  Only
-      // when it cannot decide are the Ritz vectors of T_J computed (inverse iteration).
-      const double scale = fabs(theta[0]) > 0 ? fabs(theta[0]) : 1e-300;
-      double* zl = Zm;
-      for (int r = tm.tid; r < kk; r += tm.nt) zl[r] = tridiag_last_component(ws.alpha, b2, J, theta[r]);
-      tm.sync();
-      bool conv = J >= k;
-      for (int i = 0; i < kk && conv; ++i)
-        if (zl[i] > 1e-6 && nr * zl[i] > rtol * scale) conv = false;
-      tm.sync();
-      if (conv) {
-        tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, false, work, Zm);
-        for (int i = 0; i < k; ++i)
-          if (nr * fabs(Zm[(int64_t)(J - 1) * kk + i]) > rtol * scale) conv = false;
-      }
-      tm.tick(14);
-      tm.stamp(1);
-      if (conv || J == N || J == Jmax) {
-        if (J < k) return -1;
-        // final Ritz vectors: members of eigenvalue clusters orthogonalised
-        tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, true, work, Zm);
+      int decision = 0;
+      if (lead) {
+        tm.stamp(0);
+        tm.tick(12);
+        for (int i = tm.tid; i + 1 < J; i += tm.nt) b2[i] = ws.beta[i] * ws.beta[i];
+        tm.sync();
+        tridiag_topk_values(tm, ws.alpha, ws.beta, b2, J, kk, theta, &tnorm);
+        tm.tick(13);
+        // The closed form of the last components is exact where they are large but has
+        // an absolute floor near sqrt(eps): it can show that a pair has not converged,
+        // not that it has.  Only when it cannot decide are the Ritz vectors of T_J
+        // computed (inverse iteration).
+        const double scale = fabs(theta[0]) > 0 ? fabs(theta[0]) : 1e-300;
+        double* zl = Zm;
+        for (int r = tm.tid; r < kk; r += tm.nt) zl[r] = tridiag_last_component(ws.alpha, b2, J, theta[r]);
+        tm.sync();
+        bool conv = J >= k;
+        for (int i = 0; i < kk && conv; ++i)
+          if (zl[i] > 1e-6 && nr * zl[i] > rtol * scale) conv = false;
+        tm.sync();
+        if (conv) {
+          tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, false, work, Zm);
+          for (int i = 0; i < k; ++i)
+            if (nr * fabs(Zm[(int64_t)(J - 1) * kk + i]) > rtol * scale) conv = false;
+        }
         tm.tick(14);
-        for (int i = tm.tid; i < k; i += tm.nt) evals[i] = theta[i];
-        if (Zout != nullptr) {  // the caller forms V = Q_J Z_k (ritz_rows)
-          for (int e = tm.tid; e < J * k; e += tm.nt) Zout[e] = Zm[e];
+        tm.stamp(1);
+        if (conv || J == N) decision = J >= k ? 1 : 2;
+        else if (J == Jmax) decision = 2;
+        if (tm.tid == 0) h[0] = (double)decision;
+      } else if (tm.tid == 0) {
+        h[0] = 0.0;
+      }
+      if (!xg.exchange(tm, h, 1, h, nullptr, nullptr)) return -2;
+      decision = (int)h[0];
+      tm.sync();
+      if (decision == 2) return -1;
+      if (decision == 1) {
+        if (lead) {
+          // final Ritz vectors: members of eigenvalue clusters orthogonalised (kk = k)
+          tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, true, work, Zm);
+          tm.tick(14);
+          for (int i = tm.tid; i < k; i += tm.nt) evals[i] = theta[i];
+          for (int e = tm.tid; e < J * k; e += tm.nt) Z[e] = Zm[e];
           tm.sync();
           tm.tick(15);
-          return conv || J == N ? J : -1;
         }
-        // V = Q_J Z_k
-        for (int e = tm.tid; e < N * k; e += tm.nt) {
-          const int c = e / N, t = e % N;
-          double s0 = 0.0, s1 = 0.0;
-          int i = 0;
-          for (; i + 2 <= J; i += 2) {
-            s0 += Q[(int64_t)i * N + t] * Zm[(int64_t)i * kk + c];
-            s1 += Q[(int64_t)(i + 1) * N + t] * Zm[(int64_t)(i + 1) * kk + c];
-          }
-          if (i < J) s0 += Q[(int64_t)i * N + t] * Zm[(int64_t)i * kk + c];
-          V[(int64_t)c * N + t] = s0 + s1;
-        }
-        tm.sync();
-        // renormalise columns, a wave per column
-        for (int c = tm.wave; c < k; c += tm.nwaves) {
-          double* vc = V + (int64_t)c * N;
-          double s = 0.0;
-          for (int t = tm.lane; t < N; t += tm.wsize) s += vc[t] * vc[t];
-          const double inv = 1.0 / sqrt(tm.wave_sum(s));
-          for (int t = tm.lane; t < N; t += tm.wsize) vc[t] *= inv;
-        }
-        tm.sync();
-        tm.tick(15);
-        return conv || J == N ? J : -1;
+        return J;
       }
       check = J + 8;
       if (check > Jmax) check = Jmax;
@@ -536,38 +576,19 @@ TLA_HD int lanczos_topk(TM& tm, const double* M, int ldm, int N, int k, double r
         // invariant subspace found before k pairs converged: restart orthogonally
         // (bounded by the Krylov limit: a matrix of low rank restarts once per null vector)
         if (++restarts > Jmax) return -1;
-        for (int t = tm.tid; t < N; t += tm.nt) w[t] = lanczos_start(t, J + 17 * restarts);
+        for (int t = r0 + tm.tid; t < r1; t += tm.nt) w[t] = lanczos_start(t, J + 17 * restarts);
         tm.sync();
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int i = tm.wave; i < J; i += tm.nwaves) {
-            const double* qi = Q + (int64_t)i * N;
-            double s = 0.0;
-            for (int t = tm.lane; t < N; t += tm.wsize) s += qi[t] * w[t];
-            s = tm.wave_sum(s);
-            if (tm.lane == 0) h[i] = s;
-          }
-          tm.sync();
-          for (int t = tm.tid; t < N; t += tm.nt) {
-            double v = w[t];
-            for (int i = 0; i < J; ++i) v -= h[i] * Q[(int64_t)i * N + t];
-            w[t] = v;
-          }
-          tm.sync();
-        }
+        if (!orthogonalise(J, nullptr)) return -2;
         double n2 = 0.0;
-        for (int t = tm.tid; t < N; t += tm.nt) n2 += w[t] * w[t];
-        n2 = sqrt(tm.sum(n2));
+        if (!gather_norm(&n2)) return -2;
         if (n2 <= 1e-8) return -1;
-        ws.beta[j] = 0.0;
+        if (tm.tid == 0) ws.beta[j] = 0.0;
         nr = n2;
       }
     }
     const double inv = 1.0 / nr;
-    for (int t = tm.tid; t < N; t += tm.nt) {
-      const double v = w[t] * inv;
-      q[t] = v;
-      Q[(int64_t)J * N + t] = v;
-    }
+    for (int t = tm.tid; t < N; t += tm.nt) q[t] = w[t] * inv;
+    for (int t = r0 + tm.tid; t < r1; t += tm.nt) Q[(int64_t)J * ldq + t] = w[t] * inv;
     tm.sync();
     tm.tick(12);
   }
@@ -917,8 +938,8 @@ struct SmallLAWork {
 // Rows per block of the row-range steps below (the device runs a workgroup per block).
 constexpr int kLaRows = 64;
 
-// V[c*N + t] = sum_{i < J} Q[i*N + t] Z[i*k + c] for rows t in [t0, t1): the Ritz
-// vectors of M from those of T_J (not normalised).  Thread (t, block of 8 columns); each
+// V[c*N + t] = sum_{i < J} Q[i*ldq + t] Z[i*k + c] (ldq = la_ldq(N)) for rows t in
+// [t0, t1): the Ritz vectors of M from those of T_J (not normalised).  Thread (t, block of 8 columns); each
 // entry is one sum in the order of i, whatever the team.
 template <class TM>
 TLA_HD void ritz_rows(TM& tm, const double* Q, int N, int J, const double* Z, int k, double* V, int t0,
@@ -930,8 +951,9 @@ TLA_HD void ritz_rows(TM& tm, const double* Q, int N, int J, const double* Z, in
     double acc[KB];
 #pragma unroll
     for (int c = 0; c < KB; ++c) acc[c] = 0.0;
+    const int ldq = la_ldq(N);
     for (int i = 0; i < J; ++i) {
-      const double q = Q[(int64_t)i * N + t];
+      const double q = Q[(int64_t)i * ldq + t];
       const double* zi = Z + (int64_t)i * k + c0;
 #pragma unroll
       for (int c = 0; c < KB; ++c)
@@ -1060,26 +1082,36 @@ TLA_HD void g_rows(TM& tm, const double* V, int N, int k, const double* nu, cons
 }
 
 // Status codes (match cdmd_status).
-constexpr int kOk = 0, kRankDeficient = 5, kNumeric = 6;
+constexpr int kOk = 0, kDevice = 4, kRankDeficient = 5, kNumeric = 6;
 
 // Algorithm 1 step 4, first part: the top-k eigenpairs of the Gram Gr[0:N, 0:N] (N = m-1)
-// of the unscaled sketch by Lanczos; mu[k] the eigenvalues, Z (J x k) the Ritz vectors of
-// T_J (V = Q_J Z is formed by ritz_rows).  Returns the status; *Jout = Krylov size.
-template <class TM>
-TLA_HD int small_la_phase_a(TM& tm, const double* Gr, int m, int k, double rtol, int Jmax,
+// of the unscaled sketch by Lanczos, the rows split over the groups of X; group 0 holds
+// mu[k] the eigenvalues and Z (J x k) the Ritz vectors of T_J (V = Q_J Z is formed by
+// ritz_rows).  Returns the status (the same in every group); *Jout = Krylov size.
+template <class TM, class X>
+TLA_HD int small_la_phase_a(TM& tm, X& xg, const double* Gr, int m, int k, double rtol, int Jmax,
                             const SmallLAWork& ws, double* mu, double* Z, int* Jout) {
   const int N = m - 1;
   {
     double bad = 0.0;
-    for (int64_t e = tm.tid; e < (int64_t)m * m; e += tm.nt)
+    const int64_t mm = (int64_t)m * m;
+    const int64_t e0 = mm * xg.g / xg.G, e1 = mm * (xg.g + 1) / xg.G;
+    for (int64_t e = e0 + tm.tid; e < e1; e += tm.nt)
       if (!(fabs(Gr[e]) < 1e300)) bad = 1.0;
-    if (tm.sum(bad) > 0.0) return kNumeric;
+    bad = tm.sum(bad);
+    if (tm.tid == 0) ws.lz.h[0] = bad;
+    if (!xg.exchange(tm, ws.lz.h, 1, ws.lz.h, nullptr, nullptr)) return kDevice;
+    const bool any = ws.lz.h[0] > 0.0;
+    tm.sync();
+    if (any) return kNumeric;
   }
   tm.stamp(2);
-  const int J = lanczos_topk(tm, Gr, m, N, k, rtol, Jmax, ws.Q, ws.lz, mu, ws.V, Z);
+  const int J = lanczos_topk(tm, xg, Gr, m, N, k, rtol, Jmax, ws.Q, ws.lz, mu, Z);
   tm.stamp(3);
   *Jout = J;
+  if (J == -2) return kDevice;
   if (J < 0) return kNumeric;
+  if (xg.g != 0) return kOk;
   if (!(mu[0] > 0.0) || !(mu[k - 1] > 1e-12 * mu[0])) return kRankDeficient;
   return kOk;
 }
@@ -1138,36 +1170,47 @@ TLA_HD int small_la_phase_b(TM& tm, int N, int k, double sketch_scale, const Sma
   return kOk;
 }
 
-// Algorithm 1 steps 4, 6, 7 and G = V S^-1 W from the Gram Gr (m x m, symmetric) of the
-// unscaled sketch, by one team: phase A, V = Q Z, TV = M12 V, phase B, G.  sketch_scale
-// multiplies the sketch (so sigma = sqrt(mu) * scale).  Outputs: mu[k] (Gram eigenvalues),
-// sigma[k], lam[k] and W (k x k, column j at j*k) as cpx, G (N x k, row t at t*k) as cpx.
-// Returns the status; *Jout = Krylov size.  (The device runs the same phases as separate
-// kernels, the row-range steps on many workgroups.)
+// After phase A (Krylov size J, Ritz vectors Z of T_J in ws.Z): V = Q Z, TV = M12 V and
+// the block partials, phase B, then G, over row blocks of kLaRows.
 template <class TM>
-TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int Jmax,
-                        double sketch_scale, const SmallLAWork& ws, double* mu, double* sigma,
-                        cpx* lam, cpx* W, cpx* G, int* Jout) {
+TLA_HD int small_la_tail(TM& tm, const double* Gr, int m, int k, int J, double sketch_scale,
+                         const SmallLAWork& ws, const double* mu, double* sigma, cpx* lam, cpx* W, cpx* G) {
   const int N = m - 1;
-  int st = small_la_phase_a(tm, Gr, m, k, rtol, Jmax, ws, mu, ws.Z, Jout);
-  if (st != kOk) return st;
   const int nblk = (N + kLaRows - 1) / kLaRows;
   const int64_t ne = (int64_t)k * k + k;
   for (int b = 0; b < nblk; ++b) {
     const int t1 = (b + 1) * kLaRows < N ? (b + 1) * kLaRows : N;
-    ritz_rows(tm, ws.Q, N, *Jout, ws.Z, k, ws.V, b * kLaRows, t1);
+    ritz_rows(tm, ws.Q, N, J, ws.Z, k, ws.V, b * kLaRows, t1);
   }
   for (int b = 0; b < nblk; ++b) {
     const int t1 = (b + 1) * kLaRows < N ? (b + 1) * kLaRows : N;
     m12v_rows(tm, Gr, m, N, k, ws.V, ws.TV, b * kLaRows, t1, ws.lz.fast, ws.lz.fast_doubles);
     block_gram(tm, ws.V, ws.TV, N, k, b * kLaRows, t1, ws.P + b * ne, ws.lz.fast, ws.lz.fast_doubles);
   }
-  st = small_la_phase_b(tm, N, k, sketch_scale, ws, nblk, mu, sigma, lam, W);
+  const int st = small_la_phase_b(tm, N, k, sketch_scale, ws, nblk, mu, sigma, lam, W);
   if (st != kOk) return st;
   g_rows(tm, ws.V, N, k, ws.nu, sigma, W, G, 0, N);
   tm.stamp(7);
   return kOk;
 }
+
+// Algorithm 1 steps 4, 6, 7 and G = V S^-1 W from the Gram Gr (m x m, symmetric) of the
+// unscaled sketch, by one team: phase A (one row group), then the tail.  sketch_scale
+// multiplies the sketch (so sigma = sqrt(mu) * scale).  Outputs: mu[k] (Gram eigenvalues),
+// sigma[k], lam[k] and W (k x k, column j at j*k) as cpx, G (N x k, row t at t*k) as cpx.
+// Returns the status; *Jout = Krylov size.  (The device runs the same steps as separate
+// kernels, the row-range steps on many workgroups.)
+template <class TM>
+TLA_HD int small_la_run(TM& tm, const double* Gr, int m, int k, double rtol, int Jmax,
+                        double sketch_scale, const SmallLAWork& ws, double* mu, double* sigma,
+                        cpx* lam, cpx* W, cpx* G, int* Jout) {
+  LocalX xg;
+  xg.r1 = m - 1;
+  const int st = small_la_phase_a(tm, xg, Gr, m, k, rtol, Jmax, ws, mu, ws.Z, Jout);
+  if (st != kOk) return st;
+  return small_la_tail(tm, Gr, m, k, *Jout, sketch_scale, ws, mu, sigma, lam, W, G);
+}
+
 
 }  // namespace tla
 }  // namespace cdmd
@@ -1177,12 +1220,12 @@ namespace tla {
 
 // Offsets (in doubles) of the global scratch of one small-LA solve.
 struct SmallLALayout {
-  int64_t Q, T, V, Z, TV, P, nu, At, Hs, LU, bb, yy, piv, total;
+  int64_t Q, T, V, Z, TV, P, nu, At, Hs, LU, bb, yy, piv, X, total;
 };
 TLA_HD inline SmallLALayout small_la_layout(int N, int k, int Jmax) {
   SmallLALayout L;
   int64_t o = 0;
-  L.Q = o;  o += (int64_t)(Jmax + 1) * N;
+  L.Q = o;  o += (int64_t)(Jmax + 1) * la_ldq(N);
   L.T = o;  o += (int64_t)Jmax + k + 6 * (int64_t)Jmax * k;
   L.V = o;  o += (int64_t)N * k;
   L.Z = o;  o += (int64_t)Jmax * k;
@@ -1195,6 +1238,10 @@ TLA_HD inline SmallLALayout small_la_layout(int N, int k, int Jmax) {
   L.bb = o; o += 2 * (int64_t)k * k;
   L.yy = o; o += 2 * (int64_t)k * k;
   L.piv = o; o += (int64_t)k * k;  // ints stored in double slots
+  // exchange of the row groups, 128-byte aligned: an arrival counter (a line of its own),
+  // then two buffers of kLaGroupsMax partial arrays (la_xps) and a vector (la_ldq)
+  o = (o + 15) & ~(int64_t)15;
+  L.X = o;  o += 16 + 2 * ((int64_t)kLaGroupsMax * la_xps(Jmax) + la_ldq(N));
   L.total = o;
   return L;
 }

@@ -207,15 +207,17 @@ def test_omp_conjugate_pair_tie_prefers_lower_index():
 
 
 # ------------------------------------------------------------------ team small LA (device code, host run)
+@pytest.mark.parametrize("groups", [1, 3, 16])
 @pytest.mark.parametrize("shape", [(40, 52, 45, 10, 300), (72, 100, 60, 12, 400), (48, 64, 130, 25, 600)])
-def test_team_small_la_matches_oracle(shape):
+def test_team_small_la_matches_oracle(shape, groups):
     """The workgroup small linear algebra the GPU runs per fit (Lanczos + Jacobi on the
     Lanczos matrix, A~, Francis QR + inverse iteration, G = V S^-1 W), executed by one
-    host thread, reproduces the oracle's SVD-route eigenvalues, singular values and |G|."""
+    host thread, or with Lanczos split over row groups as the GPU's workgroups split it,
+    reproduces the oracle's SVD-route eigenvalues, singular values and |G|."""
     H, W, m, k, p = shape
     lib = P.load_library()
     lib.cdmd_dbg_team_small_la.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                           ctypes.c_double, DP, DP, DP, DP, DP, IP]
+                                           ctypes.c_double, ctypes.c_int32, DP, DP, DP, DP, DP, IP]
     spec = sv.preset("cfg2", H=H, W=W, m=m, bump_sigma=8.0, blur_sigma=3.0, n_rects=3,
                      rect_side=(6, 14), speed=(0.5, 2.0), seed=7)
     D = sv.make_video(spec).D.numpy()
@@ -224,8 +226,8 @@ def test_team_small_la_matches_oracle(shape):
     Gr = np.ascontiguousarray(Yi.astype(np.float64).T @ Yi.astype(np.float64))
     mu, sig, lam = np.zeros(k), np.zeros(k), np.zeros(2 * k)
     Wm, G, J = np.zeros(2 * k * k), np.zeros(2 * (m - 1) * k), ctypes.c_int32()
-    assert lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1 / 255, _p(mu), _p(sig), _p(lam), _p(Wm),
-                                      _p(G), ctypes.byref(J)) == 0
+    assert lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1 / 255, groups, _p(mu), _p(sig), _p(lam),
+                                      _p(Wm), _p(G), ctypes.byref(J)) == 0
     lam = lam[0::2] + 1j * lam[1::2]
     lr, Wr, s, V, At = R.reduced_operator(Y, k)
     from scipy.optimize import linear_sum_assignment
@@ -243,24 +245,29 @@ def test_team_small_la_matches_oracle(shape):
             assert np.any(lam == np.conj(lam[j]))
 
 
-def test_team_small_la_rank_deficient():
+@pytest.mark.parametrize("groups", [1, 4])
+def test_team_small_la_rank_deficient(groups):
     lib = P.load_library()
+    lib.cdmd_dbg_team_small_la.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int32, DP, DP, DP, DP, DP, IP]
     m, k = 20, 3
     Yi = np.ones((50, m))
     Gr = np.ascontiguousarray(Yi.T @ Yi)
     out = [np.zeros(k), np.zeros(k), np.zeros(2 * k), np.zeros(2 * k * k), np.zeros(2 * (m - 1) * k)]
-    st = lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1.0, *[_p(o) for o in out], ctypes.byref(ctypes.c_int32()))
+    st = lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1.0, groups, *[_p(o) for o in out],
+                                    ctypes.byref(ctypes.c_int32()))
     assert st == P.E_RANK_DEFICIENT
 
 
-def test_team_small_la_clustered_spectrum():
+@pytest.mark.parametrize("groups", [1, 5])
+def test_team_small_la_clustered_spectrum(groups):
     """Singular values of Y that repeat exactly, or nearly (1e-9 apart), inside the top k:
     the Lanczos Ritz vectors of a cluster must come out orthonormal, so the Gram
     eigenvalues are s^2 and the eigenvalues of A~ (which depend only on the invariant
     subspace of the top k) agree with the oracle's SVD route."""
     lib = P.load_library()
     lib.cdmd_dbg_team_small_la.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                           ctypes.c_double, DP, DP, DP, DP, DP, IP]
+                                           ctypes.c_double, ctypes.c_int32, DP, DP, DP, DP, DP, IP]
     rng = np.random.default_rng(11)
     p, m, k = 300, 120, 12
     N = m - 1
@@ -274,7 +281,7 @@ def test_team_small_la_clustered_spectrum():
     Gr = np.ascontiguousarray(Yh.T @ Yh)
     mu, sig, lam = np.zeros(k), np.zeros(k), np.zeros(2 * k)
     Wm, G, J = np.zeros(2 * k * k), np.zeros(2 * N * k), ctypes.c_int32()
-    assert lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1.0, _p(mu), _p(sig), _p(lam), _p(Wm),
+    assert lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1.0, groups, _p(mu), _p(sig), _p(lam), _p(Wm),
                                       _p(G), ctypes.byref(J)) == 0
     np.testing.assert_allclose(mu, s[:k] ** 2, rtol=1e-11)
     lam = lam[0::2] + 1j * lam[1::2]
@@ -285,17 +292,36 @@ def test_team_small_la_clustered_spectrum():
     assert (C[a, b] / np.abs(lr[b]).max()).max() < 1e-9
 
 
+@pytest.mark.parametrize("groups", [1, 4])
 @pytest.mark.parametrize("m,k", [(40, 6), (120, 12)])
-def test_team_small_la_rank_one_gram(m, k):
+def test_team_small_la_rank_one_gram(m, k, groups):
     """A constant video gives a rank-one Gram: the Lanczos process breaks down at once and
     restarts in the null space; the solve must end with zero Ritz values and report rank
     deficiency (not a numerical failure)."""
     lib = P.load_library()
     lib.cdmd_dbg_team_small_la.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                           ctypes.c_double, DP, DP, DP, DP, DP, IP]
+                                           ctypes.c_double, ctypes.c_int32, DP, DP, DP, DP, DP, IP]
     Yi = np.full((200, m), 77.0 * 32)
     Gr = np.ascontiguousarray(Yi.T @ Yi)
     out = [np.zeros(k), np.zeros(k), np.zeros(2 * k), np.zeros(2 * k * k), np.zeros(2 * (m - 1) * k)]
-    st = lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1 / 255, *[_p(o) for o in out],
+    st = lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1 / 255, groups, *[_p(o) for o in out],
                                     ctypes.byref(ctypes.c_int32()))
     assert st == P.E_RANK_DEFICIENT
+
+
+@pytest.mark.parametrize("groups", [1, 3])
+def test_team_small_la_non_finite_gram(groups):
+    """A NaN anywhere in the Gram (here in the row of the last frame, which only the last
+    row group checks) is a numerical failure in every group."""
+    lib = P.load_library()
+    lib.cdmd_dbg_team_small_la.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_double, ctypes.c_int32, DP, DP, DP, DP, DP, IP]
+    rng = np.random.default_rng(4)
+    m, k = 30, 4
+    Yi = rng.standard_normal((80, m))
+    Gr = np.ascontiguousarray(Yi.T @ Yi)
+    Gr[m - 1, m - 2] = np.nan
+    out = [np.zeros(k), np.zeros(k), np.zeros(2 * k), np.zeros(2 * k * k), np.zeros(2 * (m - 1) * k)]
+    st = lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1.0, groups, *[_p(o) for o in out],
+                                    ctypes.byref(ctypes.c_int32()))
+    assert st == P.E_NUMERIC

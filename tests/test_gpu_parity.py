@@ -340,6 +340,31 @@ def test_bf16_lift_form():
 
 
 # ------------------------------------------------------------------ device small LA
+def test_device_lanczos_row_groups_agree():
+    """The device Lanczos split over 1, 2, 3, 7 or the default number of row groups
+    (workgroups exchanging their shares through global memory) gives the same Krylov size,
+    singular values and eigenvalues, up to the reordering of float64 sums."""
+    _say("device Lanczos row groups")
+    v = _small_u8(H=64, W=96, m=300, seed=83)
+    D = v.D.numpy()
+    n, m, k, p = D.shape[1], D.shape[0], 25, 900
+    idx, sign = sv.sparse_table(n, p, 32, 6)
+    Dg = torch.from_numpy(D).cuda()
+    ref = None
+    for groups in (1, 2, 3, 7, 0):
+        mdl = P.Model(n, m, k, p, idx=idx, sign=sign)
+        mdl.la_groups(groups)
+        mdl.fit(Dg)
+        md, J = mdl.modes(), mdl.info()["lanczos_steps"]
+        if ref is None:
+            ref = (md, J)
+            continue
+        assert J == ref[1], (groups, J, ref[1])
+        np.testing.assert_allclose(md["sigma"], ref[0]["sigma"], rtol=1e-12, err_msg=f"groups {groups}")
+        rel, _, _ = eig_rel_err(md["lam"], ref[0]["lam"])
+        assert rel.max() <= 1e-10, (groups, rel.max())
+
+
 @pytest.mark.parametrize("shape", [(72, 100, 120, 16), (48, 64, 300, 25)])
 def test_device_small_la_matches_host_la_and_oracle(shape):
     """The one-workgroup float64 solve (Lanczos + Jacobi, A~, Francis QR, G) gives the
