@@ -207,12 +207,11 @@ TLA_HD void tridiag_topk_values(TM& tm, const double* a, const double* b, const 
 
 // Eigenvectors of the symmetric tridiagonal (a, b) for theta[0..kk-1] (descending) by three
 // steps of inverse iteration, each a solve with the LU factors (row interchanges) of
-// T - theta I, one thread per eigenvector, all at once.  Vectors of nearly equal
-// eigenvalues can come out with a small mutual component (of order eps ||T|| / gap);
-// with orth set, one wave then orthonormalises the columns in order (classical
-// Gram-Schmidt, twice), which keeps each in the span of the computed vectors of its
-// cluster.  Unit vectors, largest-modulus component positive.  work: 5 J kk doubles;
-// Z: J x kk, element (i, r) at Z[i*kk + r].
+// T - theta I, one thread per eigenvector, all at once: unit vectors.  Vectors of nearly
+// equal eigenvalues can come out with a small mutual component (of order eps ||T|| / gap);
+// with orth set, the columns are then orthonormalised in order (which keeps each in the
+// span of the computed vectors of its cluster) and signed so that the largest-modulus
+// component is positive.  work: 5 J kk doubles; Z: J x kk, element (i, r) at Z[i*kk + r].
 template <class TM>
 TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int kk,
                             const double* theta, double tnorm, bool orth, double* work, double* Z) {
@@ -285,38 +284,61 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
     for (int i = 0; i < J; ++i) Z[(int64_t)i * kk + r] = y[i * ys];
   }
   tm.sync();
-  if (tm.wave == 0) {
-    auto wt = tm.wave_team();
-    for (int r = 0; r < kk; ++r) {
-      double* zr = Z + r;
-      if (orth)
-        for (int pass = 0; pass < 2; ++pass) {
-          for (int q = 0; q < r; ++q) {
-            double d = 0.0;
-            for (int i = wt.lane; i < J; i += wt.wsize) d += Z[(int64_t)i * kk + q] * zr[(int64_t)i * kk];
-            d = wt.wave_sum(d);
-            for (int i = wt.lane; i < J; i += wt.wsize) zr[(int64_t)i * kk] -= d * Z[(int64_t)i * kk + q];
-            wt.sync();
-          }
-          double nr = 0.0;
-          for (int i = wt.lane; i < J; i += wt.wsize) nr += zr[(int64_t)i * kk] * zr[(int64_t)i * kk];
-          const double inv = 1.0 / sqrt(wt.wave_sum(nr));
-          for (int i = wt.lane; i < J; i += wt.wsize) zr[(int64_t)i * kk] *= inv;
-          wt.sync();
-        }
-      // sign: largest-modulus component (lowest index on ties) positive
-      double best = -1.0;
-      int bi = 0;
-      for (int i = wt.lane; i < J; i += wt.wsize) {
-        const double v = fabs(zr[(int64_t)i * kk]);
-        if (v > best) best = v, bi = i;
-      }
-      wt.wave_argmax(best, bi);
-      const double sg = zr[(int64_t)bi * kk] < 0.0 ? -1.0 : 1.0;
-      wt.sync();
-      for (int i = wt.lane; i < J; i += wt.wsize) zr[(int64_t)i * kk] *= sg;
-      wt.sync();
+  if (!orth) return;
+  // Orthonormalise the columns in order by Cholesky QR, twice: C = Z^T Z = R^T R, then
+  // Z <- Z R^-1 (the Q factor of Z, which Gram-Schmidt in column order would also give;
+  // the columns are close to orthonormal, so C is well conditioned and the second pass
+  // brings them to working accuracy).  C and R share `work` (free after the solves).
+  double* C = work;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int e = tm.tid; e < kk * kk; e += tm.nt) {
+      const int p = e / kk, q = e % kk;
+      if (p > q) continue;
+      double d = 0.0;
+      for (int i = 0; i < J; ++i) d += Z[(int64_t)i * kk + p] * Z[(int64_t)i * kk + q];
+      C[p * kk + q] = d;
     }
+    tm.sync();
+    // R (upper, in C's upper triangle), row by row on one wave: R_pp = sqrt(C_pp - sum
+    // R_ip^2), R_pq = (C_pq - sum R_ip R_iq) / R_pp
+    if (tm.wave == 0) {
+      auto wt = tm.wave_team();
+      for (int p = 0; p < kk; ++p) {
+        double dg = C[p * kk + p];
+        for (int i = 0; i < p; ++i) dg -= C[i * kk + p] * C[i * kk + p];
+        const double rpp = sqrt(dg > 0.0 ? dg : 1e-300);
+        for (int q = p + 1 + wt.lane; q < kk; q += wt.wsize) {
+          double v = C[p * kk + q];
+          for (int i = 0; i < p; ++i) v -= C[i * kk + p] * C[i * kk + q];
+          C[p * kk + q] = v / rpp;
+        }
+        wt.sync();
+        if (wt.lane == 0) C[p * kk + p] = rpp;
+        wt.sync();
+      }
+    }
+    tm.sync();
+    // each row z of Z: z <- z R^-1 (forward substitution over the columns)
+    for (int i = tm.tid; i < J; i += tm.nt) {
+      double* zi = Z + (int64_t)i * kk;
+      for (int q = 0; q < kk; ++q) {
+        double v = zi[q];
+        for (int p = 0; p < q; ++p) v -= zi[p] * C[p * kk + q];
+        zi[q] = v / C[q * kk + q];
+      }
+    }
+    tm.sync();
+  }
+  // sign: largest-modulus component (lowest index on ties) positive; a thread per column
+  for (int r = tm.tid; r < kk; r += tm.nt) {
+    double best = -1.0;
+    int bi = 0;
+    for (int i = 0; i < J; ++i) {
+      const double v = fabs(Z[(int64_t)i * kk + r]);
+      if (v > best) best = v, bi = i;
+    }
+    if (Z[(int64_t)bi * kk + r] < 0.0)
+      for (int i = 0; i < J; ++i) Z[(int64_t)i * kk + r] = -Z[(int64_t)i * kk + r];
   }
   tm.sync();
 }
@@ -467,18 +489,15 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
   if (check > Jmax) check = Jmax;
   double anorm = 0.0;
   int restarts = 0;
-  // w[rows] -= Q_n h[0, n): classical Gram-Schmidt against the first n vectors, twice;
-  // h[n-1] of both passes is added to *hsum (the Lanczos alpha)
-  auto orthogonalise = [&](int n, double* hsum) -> bool {
-    for (int pass = 0; pass < 2; ++pass) {
-      dots_rows(tm, Q, ldq, w, n, r0, r1, h);
-      if (!xg.exchange(tm, h, n, h, nullptr, nullptr)) return false;
-      if (hsum != nullptr) *hsum += h[n - 1];
-      colsum_rows(tm, Q, ldq, h, n, r0, r1, w, true, ws.fast, ws.fast_doubles);
-    }
+  // One classical Gram-Schmidt pass of w[rows] against the first n vectors; the
+  // coefficients stay in h[0, n).
+  auto orth_pass = [&](int n) -> bool {
+    dots_rows(tm, Q, ldq, w, n, r0, r1, h);
+    if (!xg.exchange(tm, h, n, h, nullptr, nullptr)) return false;
+    colsum_rows(tm, Q, ldq, h, n, r0, r1, w, true, ws.fast, ws.fast_doubles);
     return true;
   };
-  // the squared norm of w and the whole of w, in every group
+  // The squared norm of w and the whole of w, in every group
   auto gather_norm = [&](double* nrm) -> bool {
     double s = 0.0;
     for (int t = r0 + tm.tid; t < r1; t += tm.nt) s += w[t] * w[t];
@@ -489,16 +508,38 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
     tm.sync();
     return true;
   };
+  // Each step exchanges twice: the first Gram-Schmidt pass, then the second pass together
+  // with the squared norm and the rows of w as they are before the second pass (w^).  The
+  // stored basis vector q_{j+1} = (w^ - Q h2) / beta takes the second-pass correction on
+  // the group's own rows; the next product is formed from x = w^ / beta, which differs
+  // from q_{j+1} by Q h2 / beta.  By the Lanczos relation M q_i = beta_{i-1} q_{i-1} +
+  // alpha_i q_i + beta_i q_{i+1}, M x - M q_{j+1} lies in the span of q_0..q_{j+1} (so the
+  // first pass removes it) with component h2_j on q_{j+1}, which is taken off alpha_{j+1}
+  // (corr).  beta^2 = |w^|^2 - |h2|^2 since Q^T w^ = h2 and Q^T Q = I.
+  double corr = 0.0;
   for (int j = 0; j < Jmax; ++j) {
     tm.tick(-1);
-    // w = M q over the group's rows, as columns of the symmetric M (coalesced over rows)
+    // w = M x over the group's rows, as columns of the symmetric M (coalesced over rows)
     colsum_rows(tm, M, ldm, q, N, r0, r1, w, false, ws.fast, ws.fast_doubles);
     tm.tick(10);
-    double aj = 0.0;
-    if (!orthogonalise(j + 1, &aj)) return -2;
+    if (!orth_pass(j + 1)) return -2;
+    double aj = h[j] - corr;
+    dots_rows(tm, Q, ldq, w, j + 1, r0, r1, h);
+    {
+      double s = 0.0;
+      for (int t = r0 + tm.tid; t < r1; t += tm.nt) s += w[t] * w[t];
+      s = tm.sum(s);
+      if (tm.tid == 0) h[j + 1] = s;
+    }
+    if (!xg.exchange(tm, h, j + 2, h, w, q)) return -2;  // q <- w^ (every row)
+    aj += h[j];
+    corr = h[j];
+    double h2sq = 0.0;
+    for (int i = 0; i <= j; ++i) h2sq += h[i] * h[i];
+    const double nsq = h[j + 1] - h2sq;
+    double nr = sqrt(nsq > 0.0 ? nsq : 0.0);
+    colsum_rows(tm, Q, ldq, h, j + 1, r0, r1, w, true, ws.fast, ws.fast_doubles);
     tm.tick(11);
-    double nr = 0.0;
-    if (!gather_norm(&nr)) return -2;
     if (tm.tid == 0) {
       ws.alpha[j] = aj;  // the same value in every group
       ws.beta[j] = nr;
@@ -578,16 +619,19 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
         if (++restarts > Jmax) return -1;
         for (int t = r0 + tm.tid; t < r1; t += tm.nt) w[t] = lanczos_start(t, J + 17 * restarts);
         tm.sync();
-        if (!orthogonalise(J, nullptr)) return -2;
+        if (!orth_pass(J) || !orth_pass(J)) return -2;
         double n2 = 0.0;
-        if (!gather_norm(&n2)) return -2;
+        if (!gather_norm(&n2)) return -2;  // w: every row
         if (n2 <= 1e-8) return -1;
         if (tm.tid == 0) ws.beta[j] = 0.0;
         nr = n2;
+        corr = 0.0;
+        for (int t = tm.tid; t < N; t += tm.nt) q[t] = w[t];
+        tm.sync();
       }
     }
     const double inv = 1.0 / nr;
-    for (int t = tm.tid; t < N; t += tm.nt) q[t] = w[t] * inv;
+    for (int t = tm.tid; t < N; t += tm.nt) q[t] *= inv;
     for (int t = r0 + tm.tid; t < r1; t += tm.nt) Q[(int64_t)J * ldq + t] = w[t] * inv;
     tm.sync();
     tm.tick(12);
