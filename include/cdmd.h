@@ -141,6 +141,8 @@ typedef struct {
   int32_t sparse_form;       /* after cdmd_autotune: uint8 sparse sketch form, -1 gather
                                 (byte loads per triple), 10 F + V streaming (F frames per
                                 group, V 16-byte vectors per thread); 0 not tuned */
+  double gpu_ms_lanczos;     /* device small LA, timing enabled: its Lanczos kernels alone
+                                (part of ms_small_la) */
 } cdmd_info;
 
 /* Validate `cfg`, prepare C (the sparse table is copied and reordered on the device)

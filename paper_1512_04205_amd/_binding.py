@@ -69,7 +69,7 @@ class Info(ctypes.Structure):
         ("gpu_ms_sketch", ctypes.c_double), ("gpu_ms_gram", ctypes.c_double),
         ("gpu_ms_lift", ctypes.c_double), ("gpu_ms_recon", ctypes.c_double),
         ("lift_grid", ctypes.c_int32), ("sketch_slices", ctypes.c_int32),
-        ("sparse_form", ctypes.c_int32),
+        ("sparse_form", ctypes.c_int32), ("gpu_ms_lanczos", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -669,6 +669,7 @@ cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream
       M->info.gpu_ms_sketch = M->span(0, 1);
       M->info.gpu_ms_gram = M->span(1, 2);
       M->info.ms_small_la = M->span(2, 3);
+      M->info.gpu_ms_lanczos = M->span(2, 7);
     }
   }
   return CDMD_OK;
@@ -856,7 +857,8 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
     TRY(run_sketch(M, d_video, st, false));
     HIPCHK(cdmd::k::small_la(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
                              (double)M->xscale, M->d_la_scratch, M->d_la_out, M->d_Gp, M->lm_nb,
-                             M->lm_nsplit, M->lm_nksteps, M->la_groups, st));
+                             M->lm_nsplit, M->lm_nksteps, M->la_groups, st,
+                             M->timing && !M->capturing ? M->ev[7] : nullptr));
     t1 = t2 = now_ms();
   } else {
     TRY(run_sketch(M, d_video, st, true));

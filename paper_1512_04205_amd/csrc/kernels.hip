@@ -1390,11 +1390,12 @@ __global__ __launch_bounds__(SLA_ROWS_NT) void k_la_g(SLADesc d1, const SLADesc*
 }
 
 static hipError_t launch_la(const SLADesc& d1, const SLADesc* ds, int count, int nmax, int gmax,
-                            hipStream_t stream) {
+                            hipStream_t stream, hipEvent_t after_lanczos = nullptr) {
   const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
   const int gb = (gmax + tla::kLaRows - 1) / tla::kLaRows;
   hipLaunchKernelGGL(k_la_prep, dim3(count), dim3(64), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_a, dim3(tla::la_groups(nmax), count), dim3(1024), 0, stream, d1, ds);
+  if (after_lanczos != nullptr) (void)hipEventRecord(after_lanczos, stream);
   hipLaunchKernelGGL(k_la_ritz, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_b, dim3(count), dim3(1024), 0, stream, d1, ds);
@@ -1408,10 +1409,10 @@ bool small_la_fits(int m, int k, int Jmax) {
 
 hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
                     double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS, int groups,
-                    hipStream_t stream) {
+                    hipStream_t stream, hipEvent_t after_lanczos) {
   if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
   const SLADesc d{Gr, scratch, out, (uint16_t*)Gp, rtol, sketch_scale, xscale, m, k, Jmax, NB, NS, KS, groups};
-  return launch_la(d, nullptr, 1, m - 1, std::max(m - 1, 16 * KS), stream);
+  return launch_la(d, nullptr, 1, m - 1, std::max(m - 1, 16 * KS), stream, after_lanczos);
 }
 
 hipError_t small_la_batch(const SLADesc* d_descs, int count, int nmax, int gmax, hipStream_t stream) {

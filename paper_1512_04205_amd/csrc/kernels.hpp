@@ -124,9 +124,10 @@ hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* 
 // lift B operands Gp (NB column blocks, NS bf16 terms, KS k-steps) of G * xscale.
 // Needs m - 1 <= 1024 and Jmax <= 320.  scratch: small_la_scratch_doubles(m, k, Jmax).
 // groups: Lanczos row groups (workgroups), 0 = as many as the rows call for.
+// after_lanczos: if given, recorded on the stream once the Lanczos kernel is queued.
 hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
                     double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS, int groups,
-                    hipStream_t stream);
+                    hipStream_t stream, hipEvent_t after_lanczos = nullptr);
 int64_t small_la_scratch_doubles(int m, int k, int Jmax);
 // A batch of independent solves in one launch (one workgroup each); d_descs is device
 // memory holding `count` descriptors, each valid for small_la (small_la_fits).
