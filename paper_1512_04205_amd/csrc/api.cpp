@@ -102,6 +102,11 @@ struct cdmd_model {
   bool lift_mfma = false;   // MFMA path (uint8 video, 16-byte aligned frames)
   int lm_nb = 0, lm_nsplit = 0, lm_nksteps = 0, lm_grid = 0, lm_ne = 0;
   int lm_grid_max = 0;            // largest lift grid the partial buffer holds
+  // real-basis lift (device small LA): Phi' = X' V S^-1, k columns + x_1; W applied on the host
+  bool lift_real = false;
+  int lr_nb = 0, lr_ne = 0;
+  hipStream_t st2 = nullptr;      // the A~ eigen-solve beside the lift
+  hipEvent_t e_fork = nullptr, e_join = nullptr;
   uint16_t* h_Gp = nullptr;
   void* d_Gp = nullptr;
   float* d_G = nullptr;
@@ -166,6 +171,9 @@ struct cdmd_model {
   ~cdmd_model() {
     for (hipEvent_t e : ev)
       if (e) (void)hipEventDestroy(e);
+    if (e_fork) (void)hipEventDestroy(e_fork);
+    if (e_join) (void)hipEventDestroy(e_join);
+    if (st2) (void)hipStreamDestroy(st2);
     void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart, d_chunk_off, d_rblk,
                    d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts, d_modes,
                    d_feats, d_logits,
@@ -627,19 +635,22 @@ cdmd_status upload_G(cdmd_model* M, const std::vector<int>& order, hipStream_t s
   return CDMD_OK;
 }
 
-cdmd_status launch_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
+// real: the operands in d_Gp are those of the real basis V S^-1 (k columns; no modes are
+// written), else of the complex G (2k columns).
+cdmd_status launch_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st, bool real) {
   if (M->lift_mfma)
-    HIPCHK(cdmd::k::lift_mfma((const uint8_t*)d_video, M->ld, M->n, M->m, M->d_Gp, M->lm_nb,
-                              M->lm_nsplit, M->lm_nksteps, M->nc, M->xscale, M->d_part, M->lm_grid,
-                              d_phi, M->k, st));
+    HIPCHK(cdmd::k::lift_mfma((const uint8_t*)d_video, M->ld, M->n, M->m, M->d_Gp, real ? M->lr_nb : M->lm_nb,
+                              M->lm_nsplit, M->lm_nksteps, real ? M->k : M->nc, M->xscale, M->d_part,
+                              M->lm_grid, real ? nullptr : d_phi, M->k, st));
   else
     HIPCHK(cdmd::k::lift_fp32(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_G, M->NC, M->nc,
                               M->d_pairs, M->npair, M->d_part, M->lgrid, d_phi, M->k, M->xscale, st));
   return CDMD_OK;
 }
 
-// Lift, reduction of its partials and the copies of the results to pinned host memory,
-// enqueued without waiting (with the device small LA, G is already on the device).
+// Lift, reduction of its partials and the copy of the reduced partials to pinned host
+// memory, enqueued without waiting (with the device small LA, the operands of the real
+// basis V S^-1 are already on the device).
 cdmd_status enqueue_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
   if (M->cfg.lift_prec == CDMD_PREC_BF16 && !M->lift_mfma)
     return fail(CDMD_E_INVALID_ARG, "the BF16 lift needs a 16-byte aligned uint8 video");
@@ -649,19 +660,27 @@ cdmd_status enqueue_lift(cdmd_model* M, const void* d_video, float* d_phi, hipSt
     TRY(upload_G(M, ident, st));
   }
   M->mark(3, st);
-  TRY(launch_lift(M, d_video, d_phi, st));
+  TRY(launch_lift(M, d_video, d_phi, st, M->lift_real));
   const int grid = M->lift_mfma ? M->lm_grid : M->lgrid;
-  const int ne = M->lift_mfma ? M->lm_ne : M->ne;
+  const int ne = M->lift_mfma ? (M->lift_real ? M->lr_ne : M->lm_ne) : M->ne;
   HIPCHK(cdmd::k::reduce_partials(M->d_part, grid, ne, M->d_red, st));
   M->mark(4, st);
   HIPCHK(hipMemcpyAsync(M->h_red, M->d_red, sizeof(double) * ne, hipMemcpyDeviceToHost, st));
-  if (M->device_la)
-    HIPCHK(hipMemcpyAsync(M->h_la_out, M->d_la_out, sizeof(double) * M->la_out_n, hipMemcpyDeviceToHost, st));
+  return CDMD_OK;
+}
+
+// The tail of the device small LA and the copy of its results to pinned memory, on `st`.
+cdmd_status enqueue_la_tail(cdmd_model* M, hipStream_t st) {
+  HIPCHK(cdmd::k::small_la_tail(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
+                                (double)M->xscale, M->d_la_scratch, M->d_la_out, M->d_Gp, M->lr_nb,
+                                M->lm_nsplit, M->lm_nksteps, M->la_groups, st));
+  HIPCHK(hipMemcpyAsync(M->h_la_out, M->d_la_out, sizeof(double) * M->la_out_n, hipMemcpyDeviceToHost, st));
   return CDMD_OK;
 }
 
 cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream_t st) {
   TRY(enqueue_lift(M, d_video, d_phi, st));
+  if (M->device_la) HIPCHK(hipStreamWaitEvent(st, M->e_join, 0));
   HIPCHK(hipStreamSynchronize(st));
   if (M->timing) {
     M->info.gpu_ms_lift = M->span(3, 4);
@@ -675,8 +694,56 @@ cdmd_status run_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStream
   return CDMD_OK;
 }
 
+// H = Phi^H Phi, c = Phi^H x_1.  Real-basis lift: from the partial Gram of
+// [Phi' | x_1] with Phi' = X' V S^-1, as H = W^H (Phi'^T Phi') W and c = W^H Phi'^T x_1
+// (Phi = Phi' W).
+void assemble_H_real(cdmd_model* M, std::vector<cplx>& H, std::vector<cplx>& cvec) {
+  const int k = M->k, ne1 = k + 1, NB = M->lr_nb;
+  std::vector<double> P((size_t)ne1 * ne1, 0.0);
+  int q = 0;
+  for (int a = 0; a < NB; ++a)
+    for (int b2 = a; b2 < NB; ++b2, ++q)
+      for (int j = 0; j < 16; ++j)
+        for (int l = 0; l < 64; ++l) {
+          const int r = 32 * a + 8 * (j >> 2) + 4 * (l >> 5) + (j & 3);
+          const int c = 32 * b2 + (l & 31);
+          if (r < ne1 && c < ne1) {
+            const double v = M->h_red[((size_t)q * 16 + j) * 64 + l];
+            P[(size_t)r * ne1 + c] = v;
+            P[(size_t)c * ne1 + r] = v;
+          }
+        }
+  // T = (Phi'^T Phi') W, then H = W^H T; W column j at j*k
+  const std::vector<cplx>& W = M->W;
+  std::vector<cplx> T((size_t)k * k);
+  for (int p2 = 0; p2 < k; ++p2)
+    for (int l = 0; l < k; ++l) {
+      cplx s = 0.0;
+      for (int q2 = 0; q2 < k; ++q2) s += P[(size_t)p2 * ne1 + q2] * W[(size_t)l * k + q2];
+      T[(size_t)p2 * k + l] = s;
+    }
+  H.assign((size_t)k * k, 0.0);
+  cvec.assign(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    for (int l = j; l < k; ++l) {  // upper triangle, mirrored: H is Hermitian
+      cplx s = 0.0;
+      for (int p2 = 0; p2 < k; ++p2) s += std::conj(W[(size_t)j * k + p2]) * T[(size_t)p2 * k + l];
+      H[(size_t)j * k + l] = l == j ? cplx(s.real(), 0.0) : s;
+      H[(size_t)l * k + j] = l == j ? cplx(s.real(), 0.0) : std::conj(s);
+    }
+    cplx c = 0.0;
+    for (int p2 = 0; p2 < k; ++p2) c += std::conj(W[(size_t)j * k + p2]) * P[(size_t)p2 * ne1 + k];
+    cvec[j] = c;
+  }
+  M->x1n2 = P[(size_t)k * ne1 + k];
+}
+
 // H = Phi^H Phi, c = Phi^H x_1 from the real partial Gram of [Re Phi | Im Phi].
 void assemble_H(cdmd_model* M, std::vector<cplx>& H, std::vector<cplx>& cvec) {
+  if (M->lift_real) {
+    assemble_H_real(M, H, cvec);
+    return;
+  }
   const int k = M->k, nc = M->nc, ne1 = nc + 1;
   // P: (nc+1) x (nc+1) Gram of [Re Phi | Im Phi | x_1]
   std::vector<double> P((size_t)ne1 * ne1, 0.0);
@@ -804,7 +871,12 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
     const size_t gsp = (size_t)M->lm_nksteps * M->lm_nsplit * 64 * 8;
     TRY(dalloc((uint16_t**)&M->d_Gsp, gsp));
     TRY(halloc(&M->h_Gsp, gsp));
+    M->lr_nb = (M->k + 1 + 31) / 32;
+    M->lr_ne = M->lr_nb * (M->lr_nb + 1) / 2 * 16 * 64;
     if (M->N <= 1024 && cfg->ld % 16 == 0) {
+      HIPCHK(hipStreamCreateWithFlags(&M->st2, hipStreamNonBlocking));
+      HIPCHK(hipEventCreateWithFlags(&M->e_fork, hipEventDisableTiming));
+      HIPCHK(hipEventCreateWithFlags(&M->e_join, hipEventDisableTiming));
       M->la_jmax = std::min(M->N, 320);
       TRY(dalloc(&M->d_la_scratch, (size_t)cdmd::k::small_la_scratch_doubles((int)M->m, M->k, M->la_jmax)));
       M->la_out_n = cdmd::k::small_la_out_doubles((int)M->m, M->k);
@@ -841,6 +913,7 @@ void plan_fit(cdmd_model* M, const void* d_video) {
                  (reinterpret_cast<uintptr_t>(d_video) & 15) == 0 &&
                  (M->cfg.lift_prec == CDMD_PREC_BF16 || !M->force_valu_lift);
   M->device_la = M->device_la_ok && M->lift_mfma && !M->force_host_la;
+  M->lift_real = M->device_la;
 }
 
 cdmd_status post_fit(cdmd_model* M, double t0, double t1, double t2);
@@ -855,10 +928,19 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
   double t0 = now_ms(), t1, t2;
   if (M->device_la) {
     TRY(run_sketch(M, d_video, st, false));
-    HIPCHK(cdmd::k::small_la(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
-                             (double)M->xscale, M->d_la_scratch, M->d_la_out, M->d_Gp, M->lm_nb,
-                             M->lm_nsplit, M->lm_nksteps, M->la_groups, st,
-                             M->timing && !M->capturing ? M->ev[7] : nullptr));
+    HIPCHK(cdmd::k::small_la_head(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
+                                  (double)M->xscale, M->d_la_scratch, M->d_la_out, M->d_Gp, M->lr_nb,
+                                  M->lm_nsplit, M->lm_nksteps, M->la_groups, st,
+                                  M->timing && !M->capturing ? M->ev[7] : nullptr));
+    // the A~ eigen-solve and G on the side stream, queued before the lift's operands so
+    // that its workgroup is resident before the lift fills the device
+    HIPCHK(hipEventRecord(M->e_fork, st));
+    HIPCHK(hipStreamWaitEvent(M->st2, M->e_fork, 0));
+    TRY(enqueue_la_tail(M, M->st2));
+    HIPCHK(hipEventRecord(M->e_join, M->st2));
+    HIPCHK(cdmd::k::small_la_gp(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
+                                (double)M->xscale, M->d_la_scratch, M->d_la_out, M->d_Gp, M->lr_nb,
+                                M->lm_nsplit, M->lm_nksteps, M->la_groups, st));
     t1 = t2 = now_ms();
   } else {
     TRY(run_sketch(M, d_video, st, true));
@@ -941,7 +1023,7 @@ cdmd_status cdmd_modes(const cdmd_model* Mc, double* lambda, double* b, double* 
     std::iota(ident.begin(), ident.end(), 0);
     TRY(upload_G(M, ident, st));  // M->G is in canonical order
     // the lift reduction buffers are reused; results of the fit are kept on the host
-    TRY(launch_lift(M, d_video, (float*)d_phi, st));
+    TRY(launch_lift(M, d_video, (float*)d_phi, st, false));
     HIPCHK(hipStreamSynchronize(st));
   }
   return CDMD_OK;
@@ -1053,7 +1135,7 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
         if (g > M->lm_grid_max) continue;
         M->lm_grid = g;
         double ms = 0.0;
-        TRY(time_ms(st, 3, [&] { return launch_lift(M, d_video, nullptr, st); }, &ms));
+        TRY(time_ms(st, 3, [&] { return launch_lift(M, d_video, nullptr, st, M->lift_real); }, &ms));
         if (ms < best) best = ms, ch.lift_grid = g;
       }
     }
@@ -1110,7 +1192,7 @@ struct cdmd_batch {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   std::vector<hipStream_t> pool;
-  hipEvent_t fork1 = nullptr, fork2 = nullptr;
+  hipEvent_t fork1 = nullptr, fork2 = nullptr, fork_tail = nullptr;
   std::vector<hipEvent_t> join1, join2;
   cdmd::k::SLADesc* d_desc = nullptr;
   int la_nmax = 0, la_gmax = 0;     // grid extents of the small-LA row kernels
@@ -1130,6 +1212,7 @@ struct cdmd_batch {
     for (hipEvent_t e : join1) (void)hipEventDestroy(e);
     for (hipEvent_t e : join2) (void)hipEventDestroy(e);
     if (fork1) (void)hipEventDestroy(fork1);
+    if (fork_tail) (void)hipEventDestroy(fork_tail);
     if (fork2) (void)hipEventDestroy(fork2);
     if (entry) (void)hipEventDestroy(entry);
     if (cap) (void)hipStreamDestroy(cap);
@@ -1160,6 +1243,7 @@ cdmd_status cdmd_batch_create(cdmd_model* const* models, int32_t n, cdmd_batch**
     B->join2.push_back(e2);
   }
   HIPCHK(hipEventCreateWithFlags(&B->fork1, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&B->fork_tail, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&B->fork2, hipEventDisableTiming));
   HIPCHK(hipEventCreateWithFlags(&B->entry, hipEventDisableTiming));
   HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
@@ -1191,12 +1275,25 @@ cdmd_status capture_batch(cdmd_batch* B, hipStream_t st) {
     hip(hipEventRecord(B->join1[q], B->pool[q]));
     hip(hipStreamWaitEvent(st, B->join1[q], 0));
   }
-  hip(cdmd::k::small_la_batch(B->d_desc, (int)B->dev.size(), B->la_nmax, B->la_gmax, st));
+  hip(cdmd::k::small_la_batch_head(B->d_desc, (int)B->dev.size(), B->la_nmax, st));
+  // the A~ eigen-solves and G of every model on pool stream 0, queued before the lift
+  // operands so that their workgroups are resident before the lifts fill the device; the
+  // lifts on the other pool streams
+  hip(hipEventRecord(B->fork_tail, st));
+  hip(hipStreamWaitEvent(B->pool[0], B->fork_tail, 0));
+  hip(cdmd::k::small_la_batch_tail(B->d_desc, (int)B->dev.size(), B->la_nmax, B->pool[0]));
+  for (size_t i = 0; i < B->dev.size() && r == CDMD_OK; ++i) {
+    cdmd_model* M = B->models[B->dev[i]];
+    hip(hipMemcpyAsync(M->h_la_out, M->d_la_out, sizeof(double) * M->la_out_n, hipMemcpyDeviceToHost,
+                       B->pool[0]));
+  }
+  hip(cdmd::k::small_la_batch_gp(B->d_desc, (int)B->dev.size(), B->la_gmax, st));
   hip(hipEventRecord(B->fork2, st));
+  const int PL = P > 1 ? P - 1 : 1;  // lift streams: pool[1..P-1] (pool[0] if there is one stream)
   for (int q = 0; q < P; ++q) hip(hipStreamWaitEvent(B->pool[q], B->fork2, 0));
   for (size_t i = 0; i < B->dev.size() && r == CDMD_OK; ++i) {
     cdmd_model* M = B->models[B->dev[i]];
-    guard(enqueue_lift(M, B->videos[B->dev[i]], nullptr, B->pool[i % P]));
+    guard(enqueue_lift(M, B->videos[B->dev[i]], nullptr, B->pool[P > 1 ? 1 + (int)(i % PL) : 0]));
   }
   for (int q = 0; q < P; ++q) {
     hip(hipEventRecord(B->join2[q], B->pool[q]));
@@ -1242,7 +1339,7 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
       B->dev.push_back(i);
       desc.push_back(cdmd::k::SLADesc{M->d_gram, M->d_la_scratch, M->d_la_out, (uint16_t*)M->d_Gp, kLanczosTol,
                                       M->sketch_scale, (double)M->xscale, (int)M->m, M->k, M->la_jmax,
-                                      M->lm_nb, M->lm_nsplit, M->lm_nksteps, M->la_groups});
+                                      M->lr_nb, M->lm_nsplit, M->lm_nksteps, M->la_groups});
       B->la_nmax = std::max(B->la_nmax, (int)M->m - 1);
       B->la_gmax = std::max(B->la_gmax, std::max((int)M->m - 1, 16 * M->lm_nksteps));
     }

@@ -1340,32 +1340,56 @@ __global__ __launch_bounds__(1024) void k_la_b(SLADesc d1, const SLADesc* __rest
   if (tm.tid == 0 && st != kOk) out[Lo.status] = (double)st;
 }
 
-// G = V S^-1 W over the workgroup's rows, then the lift's B operands of the 16-row groups
-// inside them: [ks][nb][split][lane][8], element i of lane l is G row 16ks + 8(l/32) + i,
-// column 32nb + l%32 (< k: Re, < 2k: Im of mode column mod k), times xscale, split into
-// NS bf16 terms.
+// G = V S^-1 W over the workgroup's rows.
 __global__ __launch_bounds__(SLA_ROWS_NT) void k_la_g(SLADesc d1, const SLADesc* __restrict__ ds) {
+  using namespace tla;
+  const SLADesc& d = la_desc(d1, ds, blockIdx.y);
+  const int N = d.m - 1, k = d.k;
+  const int t0 = blockIdx.x * kLaRows;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  double* out = d.out;
+  if (t0 >= N || out[Lo.status] != 0.0) return;
+  __shared__ double s_red[SLA_ROWS_NT / 64];
+  DevTeam tm;
+  la_team(tm, s_red, blockIdx.x == 0 ? out + Lo.timing : nullptr);
+  const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
+  g_rows(tm, d.scratch + Ls.V, N, k, d.scratch + Ls.nu, out + Lo.sigma, reinterpret_cast<const cpx*>(out + Lo.W),
+         reinterpret_cast<cpx*>(out + Lo.G), t0, t0 + kLaRows < N ? t0 + kLaRows : N);
+  tm.stamp(7);
+}
+
+// The lift's B operands of the real basis V S^-1 (the modes are (X' V S^-1) W; the lift
+// forms X' V S^-1 and W is applied to its k x k products in float64 on the host), for the
+// 16-row groups of the workgroup's 64 rows: [ks][nb][split][lane][8], element i of lane l
+// is row 16ks + 8(l/32) + i, column 32nb + l%32 (< k) of V S^-1, times xscale, split into
+// NS bf16 terms; other columns zero.  nu and sigma are formed as in phase B (the column
+// norms of V from the block partials, sigma = sqrt(mu) * sketch_scale), so this kernel
+// needs nothing from the A~ eigen-solve and runs beside it.
+__global__ __launch_bounds__(SLA_ROWS_NT) void k_la_gp(SLADesc d1, const SLADesc* __restrict__ ds) {
   using namespace tla;
   const SLADesc& d = la_desc(d1, ds, blockIdx.y);
   const int N = d.m - 1, k = d.k, NB = d.NB, NS = d.NS, KS = d.KS;
   const int t0 = blockIdx.x * kLaRows;
   const SmallLAOutLayout Lo = small_la_out_layout(N, k);
-  double* out = d.out;
+  const double* out = d.out;
   if ((t0 >= N && t0 >= 16 * KS) || out[Lo.status] != 0.0) return;
-  __shared__ double s_red[SLA_ROWS_NT / 64];
-  DevTeam tm;
-  la_team(tm, s_red, blockIdx.x == 0 ? out + Lo.timing : nullptr);
+  __shared__ double s_nu[SLA_NMAX / 2], s_sig[SLA_NMAX / 2];
   const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
-  cpx* G = reinterpret_cast<cpx*>(out + Lo.G);
-  if (t0 < N)
-    g_rows(tm, d.scratch + Ls.V, N, k, d.scratch + Ls.nu, out + Lo.sigma, reinterpret_cast<const cpx*>(out + Lo.W),
-           G, t0, t0 + kLaRows < N ? t0 + kLaRows : N);
-  tm.stamp(7);
-  tm.stamp(8);
+  const double* P = d.scratch + Ls.P;
+  const double* V = d.scratch + Ls.V;
+  const int nblk = (N + kLaRows - 1) / kLaRows;
+  const int64_t ne = (int64_t)k * k + k;
+  for (int i = threadIdx.x; i < k; i += blockDim.x) {
+    double q = 0.0;
+    for (int b = 0; b < nblk; ++b) q += P[b * ne + (int64_t)k * k + i];
+    s_nu[i] = sqrt(q);
+    s_sig[i] = sqrt(out[Lo.mu + i]) * d.sketch_scale;
+  }
+  __syncthreads();
   const int ks0 = t0 / 16, ks1 = (t0 + kLaRows) / 16 < KS ? (t0 + kLaRows) / 16 : KS;
   const int64_t total = (int64_t)(ks1 - ks0) * NB * 64 * 8;
   uint16_t* __restrict__ Gp = d.Gp;
-  for (int64_t e = tm.tid; e < total; e += tm.nt) {
+  for (int64_t e = threadIdx.x; e < total; e += blockDim.x) {
     const int i = (int)(e & 7);
     const int l = (int)((e >> 3) & 63);
     const int64_t r = e >> 9;
@@ -1374,10 +1398,7 @@ __global__ __launch_bounds__(SLA_ROWS_NT) void k_la_g(SLADesc d1, const SLADesc*
     const int row = 16 * ks + 8 * (l >> 5) + i;
     const int col = 32 * nb + (l & 31);
     double g = 0.0;
-    if (row < N && col < 2 * k) {
-      const cpx z = G[(int64_t)row * k + (col % k)];
-      g = (col < k ? z.re : z.im) * d.xscale;
-    }
+    if (row < N && col < k) g = V[(int64_t)col * N + row] / s_nu[col] / s_sig[col] * d.xscale;
     double rem = g;
     for (int sp = 0; sp < NS; ++sp) {
       const uint16_t bits = bf16_bits_d(rem);
@@ -1385,21 +1406,32 @@ __global__ __launch_bounds__(SLA_ROWS_NT) void k_la_g(SLADesc d1, const SLADesc*
       Gp[((((int64_t)ks * NB + nb) * NS + sp) * 64 + l) * 8 + i] = bits;
     }
   }
-  __syncthreads();
-  tm.stamp(9);
 }
 
-static hipError_t launch_la(const SLADesc& d1, const SLADesc* ds, int count, int nmax, int gmax,
-                            hipStream_t stream, hipEvent_t after_lanczos = nullptr) {
+// The small LA in three parts: the head (Lanczos, V, M12 V), then side by side the lift's
+// operands (followed by the lift) and the tail (the A~ eigen-solve and G).
+static hipError_t launch_la_head(const SLADesc& d1, const SLADesc* ds, int count, int nmax,
+                                 hipStream_t stream, hipEvent_t after_lanczos) {
   const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
-  const int gb = (gmax + tla::kLaRows - 1) / tla::kLaRows;
   hipLaunchKernelGGL(k_la_prep, dim3(count), dim3(64), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_a, dim3(tla::la_groups(nmax), count), dim3(1024), 0, stream, d1, ds);
   if (after_lanczos != nullptr) (void)hipEventRecord(after_lanczos, stream);
   hipLaunchKernelGGL(k_la_ritz, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
+  return hipGetLastError();
+}
+
+static hipError_t launch_la_gp(const SLADesc& d1, const SLADesc* ds, int count, int gmax, hipStream_t stream) {
+  const int gb = (gmax + tla::kLaRows - 1) / tla::kLaRows;
+  hipLaunchKernelGGL(k_la_gp, dim3(gb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
+  return hipGetLastError();
+}
+
+static hipError_t launch_la_tail(const SLADesc& d1, const SLADesc* ds, int count, int nmax,
+                                 hipStream_t stream) {
+  const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
   hipLaunchKernelGGL(k_la_b, dim3(count), dim3(1024), 0, stream, d1, ds);
-  hipLaunchKernelGGL(k_la_g, dim3(gb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_g, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   return hipGetLastError();
 }
 
@@ -1407,18 +1439,52 @@ bool small_la_fits(int m, int k, int Jmax) {
   return m - 1 <= SLA_NMAX && Jmax <= SLA_JMAX && 2 * k <= SLA_NMAX;
 }
 
-hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
-                    double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS, int groups,
-                    hipStream_t stream, hipEvent_t after_lanczos) {
-  if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
-  const SLADesc d{Gr, scratch, out, (uint16_t*)Gp, rtol, sketch_scale, xscale, m, k, Jmax, NB, NS, KS, groups};
-  return launch_la(d, nullptr, 1, m - 1, std::max(m - 1, 16 * KS), stream, after_lanczos);
+static SLADesc la_desc_of(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                          double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                          int groups) {
+  return SLADesc{Gr, scratch, out, (uint16_t*)Gp, rtol, sketch_scale, xscale, m, k, Jmax, NB, NS, KS, groups};
 }
 
-hipError_t small_la_batch(const SLADesc* d_descs, int count, int nmax, int gmax, hipStream_t stream) {
+hipError_t small_la_head(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                         double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                         int groups, hipStream_t stream, hipEvent_t after_lanczos) {
+  if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
+  const SLADesc d = la_desc_of(Gr, m, k, rtol, Jmax, sketch_scale, xscale, scratch, out, Gp, NB, NS, KS, groups);
+  return launch_la_head(d, nullptr, 1, m - 1, stream, after_lanczos);
+}
+
+hipError_t small_la_gp(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                       double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                       int groups, hipStream_t stream) {
+  if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
+  const SLADesc d = la_desc_of(Gr, m, k, rtol, Jmax, sketch_scale, xscale, scratch, out, Gp, NB, NS, KS, groups);
+  return launch_la_gp(d, nullptr, 1, std::max(m - 1, 16 * KS), stream);
+}
+
+hipError_t small_la_tail(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                         double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                         int groups, hipStream_t stream) {
+  if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
+  const SLADesc d = la_desc_of(Gr, m, k, rtol, Jmax, sketch_scale, xscale, scratch, out, Gp, NB, NS, KS, groups);
+  return launch_la_tail(d, nullptr, 1, m - 1, stream);
+}
+
+hipError_t small_la_batch_head(const SLADesc* d_descs, int count, int nmax, hipStream_t stream) {
   if (count < 1) return hipSuccess;
   const SLADesc none{};
-  return launch_la(none, d_descs, count, nmax, gmax, stream);
+  return launch_la_head(none, d_descs, count, nmax, stream, nullptr);
+}
+
+hipError_t small_la_batch_gp(const SLADesc* d_descs, int count, int gmax, hipStream_t stream) {
+  if (count < 1) return hipSuccess;
+  const SLADesc none{};
+  return launch_la_gp(none, d_descs, count, gmax, stream);
+}
+
+hipError_t small_la_batch_tail(const SLADesc* d_descs, int count, int nmax, hipStream_t stream) {
+  if (count < 1) return hipSuccess;
+  const SLADesc none{};
+  return launch_la_tail(none, d_descs, count, nmax, stream);
 }
 
 int64_t small_la_scratch_doubles(int m, int k, int Jmax) {

@@ -118,19 +118,28 @@ hipError_t bgfg_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const v
 hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* counts,
                        hipStream_t stream);
 
-// ----- small float64 linear algebra on the device (one workgroup) -----------------
+// ----- small float64 linear algebra on the device ---------------------------------
 // From the m x m Gram Gr of the unscaled sketch: out = [status, J, mu[k], sigma[k],
-// lam[2k], W[2k*k], G[2(m-1)k]] (team_la.hpp small_la_out_layout) and, on success, the
-// lift B operands Gp (NB column blocks, NS bf16 terms, KS k-steps) of G * xscale.
-// Needs m - 1 <= 1024 and Jmax <= 320.  scratch: small_la_scratch_doubles(m, k, Jmax).
-// groups: Lanczos row groups (workgroups), 0 = as many as the rows call for.
-// after_lanczos: if given, recorded on the stream once the Lanczos kernel is queued.
-hipError_t small_la(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
-                    double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS, int groups,
-                    hipStream_t stream, hipEvent_t after_lanczos = nullptr);
+// lam[2k], W[2k*k], G[2(m-1)k]] (team_la.hpp small_la_out_layout), in three parts:
+// head: Lanczos, V and M12 V; after_lanczos, if given, is recorded once the Lanczos kernel
+// is queued.
+// gp (after the head): the lift's bf16 operands of the real basis V S^-1 * xscale in Gp
+// (NB column blocks, NS terms, KS 16-row steps).
+// tail (after the head, beside gp and the lift): eig(A~), W and G.
+// groups: Lanczos row groups (workgroups), 0 = as many as the rows call for.  Needs
+// m - 1 <= 1024 and Jmax <= 320.  scratch: small_la_scratch_doubles(m, k, Jmax).
+hipError_t small_la_head(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                         double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                         int groups, hipStream_t stream, hipEvent_t after_lanczos = nullptr);
+hipError_t small_la_gp(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                       double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                       int groups, hipStream_t stream);
+hipError_t small_la_tail(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                         double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
+                         int groups, hipStream_t stream);
 int64_t small_la_scratch_doubles(int m, int k, int Jmax);
-// A batch of independent solves in one launch (one workgroup each); d_descs is device
-// memory holding `count` descriptors, each valid for small_la (small_la_fits).
+// A batch of independent solves in one set of launches (a grid row each); d_descs is
+// device memory holding `count` descriptors, each valid for small_la_head (small_la_fits).
 struct SLADesc {
   const double* Gr;
   double* scratch;
@@ -142,7 +151,9 @@ struct SLADesc {
 };
 bool small_la_fits(int m, int k, int Jmax);
 // nmax: the largest m - 1 of the batch; gmax: the largest max(m - 1, 16 KS).
-hipError_t small_la_batch(const SLADesc* d_descs, int count, int nmax, int gmax, hipStream_t stream);
+hipError_t small_la_batch_head(const SLADesc* d_descs, int count, int nmax, hipStream_t stream);
+hipError_t small_la_batch_gp(const SLADesc* d_descs, int count, int gmax, hipStream_t stream);
+hipError_t small_la_batch_tail(const SLADesc* d_descs, int count, int nmax, hipStream_t stream);
 int64_t small_la_out_doubles(int m, int k);
 
 }  // namespace k
