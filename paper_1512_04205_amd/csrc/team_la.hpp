@@ -167,9 +167,12 @@ TLA_HD inline double tridiag_last_component(const double* a, const double* b2, i
 // b[i] coupling i and i+1; b2 holds b[i]^2.  One wave per eigenvalue: its lanes evaluate
 // the Sturm count at wsize interior points of the current bracket at once (multisection),
 // shrinking the bracket by wsize + 1 per round, down to a width of 2 eps |x| + pivmin.
+// With nparts > 1 only ranks r = part (mod nparts), and rank 0, are computed (theta[r] of
+// the other ranks is left as it is).
 template <class TM>
 TLA_HD void tridiag_topk_values(TM& tm, const double* a, const double* b, const double* b2,
-                                int J, int kk, double* theta, double* tnorm_out) {
+                                int J, int kk, double* theta, double* tnorm_out, int part = 0,
+                                int nparts = 1) {
   double gl = a[0], gu = a[0], bmax2 = 0.0;
   for (int i = 0; i < J; ++i) {
     const double r = (i > 0 ? fabs(b[i - 1]) : 0.0) + (i + 1 < J ? fabs(b[i]) : 0.0);
@@ -184,9 +187,13 @@ TLA_HD void tridiag_topk_values(TM& tm, const double* a, const double* b, const 
   gu += fud;
   *tnorm_out = tnorm;
   const double np1 = (double)(tm.wsize + 1);
-  for (int r0 = 0; r0 < kk; r0 += tm.nwaves) {
-    const int r = r0 + tm.wave;
-    if (r < kk) {  // uniform over the wave
+  // slot s -> rank: part 0 takes 0, nparts, 2 nparts, ...; part p > 0 takes 0, p, p + nparts, ...
+  const int own = part < kk ? (kk - 1 - part) / nparts + 1 : 0;
+  const int nslots = part == 0 ? own : 1 + own;
+  for (int s0 = 0; s0 < nslots; s0 += tm.nwaves) {
+    const int sl = s0 + tm.wave;
+    const int r = part == 0 ? sl * nparts : (sl == 0 ? 0 : part + (sl - 1) * nparts);
+    if (sl < nslots) {  // uniform over the wave
       const int s = J - 1 - r;  // rank from the smallest; bracket: cnt(lo) <= s < cnt(hi)
       double lo = gl, hi = gu;
       for (int it = 0; it < 256; ++it) {
@@ -552,35 +559,45 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
     }
     const bool breakdown = nr <= 64.0 * kEps * anorm;
     if (J >= check || breakdown || J == N) {
-      // group 0: Ritz values of T_J by multisection, Ritz vectors of T_J by inverse
-      // iteration; the residual of Ritz pair i is beta_J |z_{J-1,i}|.  Decision: 0 go on,
-      // 1 converged (or J = N), 2 failed.
+      // Ritz values of T_J by multisection, Ritz vectors of T_J by inverse iteration; the
+      // residual of Ritz pair i is beta_J |z_{J-1,i}|.  Decision: 0 go on, 1 converged (or
+      // J = N), 2 failed.  When the work fits in fast memory every group computes the Ritz
+      // values of its share of the ranks (and rank 0, the scale), they meet in one
+      // exchange, and every group then reaches the same decision; otherwise group 0 alone
+      // checks and sends its decision.
       const int kk = k < J ? k : J;
       const int64_t need = J + kk + 6 * (int64_t)J * kk;
-      double* b2 = ws.fast != nullptr && need <= ws.fast_doubles ? ws.fast : ws.T;
+      const bool spread = ws.fast != nullptr && need <= ws.fast_doubles;  // the same in every group
+      double* b2 = spread ? ws.fast : ws.T;
       double* theta = b2 + J;
       double* work = theta + kk;
       double* Zm = work + 5 * (int64_t)J * kk;
       double tnorm = 0.0;
       int decision = 0;
-      if (lead) {
+      // The closed form of the last components is exact where they are large but has an
+      // absolute floor near sqrt(eps): it can show that a pair has not converged, not that
+      // it has.  Only when it cannot decide are the Ritz vectors of T_J computed (inverse
+      // iteration).
+      if (spread) {
         tm.stamp(0);
         tm.tick(12);
         for (int i = tm.tid; i + 1 < J; i += tm.nt) b2[i] = ws.beta[i] * ws.beta[i];
+        for (int r = tm.tid; r < kk; r += tm.nt) theta[r] = 0.0;
         tm.sync();
-        tridiag_topk_values(tm, ws.alpha, ws.beta, b2, J, kk, theta, &tnorm);
+        tridiag_topk_values(tm, ws.alpha, ws.beta, b2, J, kk, theta, &tnorm, xg.g, xg.G);
         tm.tick(13);
-        // The closed form of the last components is exact where they are large but has
-        // an absolute floor near sqrt(eps): it can show that a pair has not converged,
-        // not that it has.  Only when it cannot decide are the Ritz vectors of T_J
-        // computed (inverse iteration).
         const double scale = fabs(theta[0]) > 0 ? fabs(theta[0]) : 1e-300;
-        double* zl = Zm;
-        for (int r = tm.tid; r < kk; r += tm.nt) zl[r] = tridiag_last_component(ws.alpha, b2, J, theta[r]);
-        tm.sync();
-        bool conv = J >= k;
-        for (int i = 0; i < kk && conv; ++i)
-          if (zl[i] > 1e-6 && nr * zl[i] > rtol * scale) conv = false;
+        double open = 0.0;
+        for (int r = xg.g + tm.tid * xg.G; r < kk; r += tm.nt * xg.G) {
+          const double zl = tridiag_last_component(ws.alpha, b2, J, theta[r]);
+          if (zl > 1e-6 && nr * zl > rtol * scale) open = 1.0;
+        }
+        open = tm.sum(open);
+        for (int r = tm.tid; r < kk; r += tm.nt) h[r] = r % xg.G == xg.g ? theta[r] : 0.0;
+        if (tm.tid == 0) h[kk] = open;
+        if (!xg.exchange(tm, h, kk + 1, h, nullptr, nullptr)) return -2;
+        for (int r = tm.tid; r < kk; r += tm.nt) theta[r] = h[r];
+        bool conv = J >= k && h[kk] == 0.0;
         tm.sync();
         if (conv) {
           tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, false, work, Zm);
@@ -591,13 +608,39 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
         tm.stamp(1);
         if (conv || J == N) decision = J >= k ? 1 : 2;
         else if (J == Jmax) decision = 2;
-        if (tm.tid == 0) h[0] = (double)decision;
-      } else if (tm.tid == 0) {
-        h[0] = 0.0;
+      } else {
+        if (lead) {
+          tm.stamp(0);
+          tm.tick(12);
+          for (int i = tm.tid; i + 1 < J; i += tm.nt) b2[i] = ws.beta[i] * ws.beta[i];
+          tm.sync();
+          tridiag_topk_values(tm, ws.alpha, ws.beta, b2, J, kk, theta, &tnorm);
+          tm.tick(13);
+          const double scale = fabs(theta[0]) > 0 ? fabs(theta[0]) : 1e-300;
+          double* zl = Zm;
+          for (int r = tm.tid; r < kk; r += tm.nt) zl[r] = tridiag_last_component(ws.alpha, b2, J, theta[r]);
+          tm.sync();
+          bool conv = J >= k;
+          for (int i = 0; i < kk && conv; ++i)
+            if (zl[i] > 1e-6 && nr * zl[i] > rtol * scale) conv = false;
+          tm.sync();
+          if (conv) {
+            tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, false, work, Zm);
+            for (int i = 0; i < k; ++i)
+              if (nr * fabs(Zm[(int64_t)(J - 1) * kk + i]) > rtol * scale) conv = false;
+          }
+          tm.tick(14);
+          tm.stamp(1);
+          if (conv || J == N) decision = J >= k ? 1 : 2;
+          else if (J == Jmax) decision = 2;
+          if (tm.tid == 0) h[0] = (double)decision;
+        } else if (tm.tid == 0) {
+          h[0] = 0.0;
+        }
+        if (!xg.exchange(tm, h, 1, h, nullptr, nullptr)) return -2;
+        decision = (int)h[0];
+        tm.sync();
       }
-      if (!xg.exchange(tm, h, 1, h, nullptr, nullptr)) return -2;
-      decision = (int)h[0];
-      tm.sync();
       if (decision == 2) return -1;
       if (decision == 1) {
         if (lead) {
