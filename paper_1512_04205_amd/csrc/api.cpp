@@ -1531,7 +1531,8 @@ cdmd_status prepare_recon(cdmd_model* M, int static_bg, int* NSout, hipStream_t 
       if (!static_bg) pw[s] *= M->lam[M->S[s]];
     }
   }
-  HIPCHK(hipMemcpyAsync(M->d_Gs, M->h_Gs, sizeof(float) * N * NS, hipMemcpyHostToDevice, st));
+  if (!M->recon_mfma)
+    HIPCHK(hipMemcpyAsync(M->d_Gs, M->h_Gs, sizeof(float) * N * NS, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(M->d_Vc, M->h_Vc, sizeof(float) * m * NS, hipMemcpyHostToDevice, st));
   *NSout = NS;
   return CDMD_OK;

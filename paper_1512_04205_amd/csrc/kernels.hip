@@ -715,28 +715,44 @@ __global__ __launch_bounds__(256) void k_bgfg_mfma(const uint8_t* __restrict__ D
       sT[(64 * w + 32 * mb + (j >> 2) * 8 + (l >> 5) * 4 + (j & 3)) * 33 + (l & 31)] = acc[mb][0][j];
   __syncthreads();
   // phase 2 on FP32 MFMA 16x16x4: per wave 4 pixel blocks of 16 x frame blocks of 16,
-  // K = NSV in steps of 4.  A = T (LDS), B = Vc (global, frame-major), C lane l holds
-  // L[px 16mb + 4(l/16) + j][frame 16nb + l%16], j = 0..3.
+  // K = NSV in steps of 4.  A = T (held in registers for the whole frame loop), B = Vc
+  // (global, frame-major), C lane l holds L[px 16mb + 4(l/16) + j][frame 16nb + l%16],
+  // j = 0..3.  The next frame block's Vc values and video words are loaded while the
+  // current one is computed.
   typedef float f32x4_t __attribute__((ext_vector_type(4)));
   const int64_t words = (n + 31) >> 5;
   const int li = l & 15, lq = l >> 4;
+  float areg[4][NSV / 4];
+#pragma unroll
+  for (int mb = 0; mb < 4; ++mb)
+#pragma unroll
+    for (int ks = 0; ks < NSV / 4; ++ks) areg[mb][ks] = sT[(64 * w + 16 * mb + li) * 33 + 4 * ks + lq];
+  const int64_t pxl = base + 64 * w + 4 * lq;      // + 16 mb: this lane's 4 pixels of block mb
+  const bool full = base + 64 * w + 64 <= n;       // all 64 pixels of the wave exist (uniform)
+  const bool want_x = mode != 2;
+  float bv[NSV / 4], bn[NSV / 4];
+  uint32_t qv[4], qn[4];
+  auto load_next = [&](int64_t fb, float* b, uint32_t* q) {
+    const int64_t f = fb + li;
+    const bool fv = f < t1;
+#pragma unroll
+    for (int ks = 0; ks < NSV / 4; ++ks) b[ks] = fv ? Vc[f * NSV + 4 * ks + lq] : 0.f;
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb)
+      q[mb] = (want_x && fv && full) ? *reinterpret_cast<const uint32_t*>(D + f * ld + pxl + 16 * mb) : 0u;
+  };
+  load_next(t0, bv, qv);
   for (int64_t fb = t0; fb < t1; fb += 16) {
     const int64_t f = fb + li;                      // this lane's frame (B column / C column)
     const bool fvalid = f < t1;
-    float bv[NSV / 4];
-#pragma unroll
-    for (int ks = 0; ks < NSV / 4; ++ks) bv[ks] = fvalid ? Vc[f * NSV + 4 * ks + lq] : 0.f;
+    if (fb + 16 < t1) load_next(fb + 16, bn, qn);
     uint32_t nib[4];
 #pragma unroll
     for (int mb = 0; mb < 4; ++mb) {
       f32x4_t c = {0.f, 0.f, 0.f, 0.f};
-      const int prow = 64 * w + 16 * mb;
 #pragma unroll
-      for (int ks = 0; ks < NSV / 4; ++ks) {
-        const float a = sT[(prow + li) * 33 + 4 * ks + lq];
-        c = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bv[ks], c, 0, 0, 0);
-      }
-      const int64_t px0 = base + prow + 4 * lq;     // 4 consecutive pixels of this lane
+      for (int ks = 0; ks < NSV / 4; ++ks) c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[mb][ks], bv[ks], c, 0, 0, 0);
+      const int64_t px0 = pxl + 16 * mb;            // 4 consecutive pixels of this lane
       if (mode == 2) {
         if (fvalid)
 #pragma unroll
@@ -746,18 +762,17 @@ __global__ __launch_bounds__(256) void k_bgfg_mfma(const uint8_t* __restrict__ D
         continue;
       }
       float xv[4];
-      if (fvalid && px0 + 4 <= n) {
-        const uint32_t q = *reinterpret_cast<const uint32_t*>(D + f * ld + px0);
+      if (full) {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) xv[j] = (float)((q >> (8 * j)) & 0xffu) * xscale;
+        for (int j = 0; j < 4; ++j) xv[j] = (float)((qv[mb] >> (8 * j)) & 0xffu);
       } else {
 #pragma unroll
-        for (int j = 0; j < 4; ++j) xv[j] = (fvalid && px0 + j < n) ? (float)D[f * ld + px0 + j] * xscale : 0.f;
+        for (int j = 0; j < 4; ++j) xv[j] = (fvalid && px0 + j < n) ? (float)D[f * ld + px0 + j] : 0.f;
       }
       uint32_t bits = 0;
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        if (fvalid && px0 + j < n && fabsf(xv[j] - c[j]) > tau) bits |= 1u << j;
+        if (fvalid && px0 + j < n && fabsf(fmaf(xv[j], xscale, -c[j])) > tau) bits |= 1u << j;
       if (mode == 1) {
         if (fvalid)
 #pragma unroll
@@ -783,6 +798,10 @@ __global__ __launch_bounds__(256) void k_bgfg_mfma(const uint8_t* __restrict__ D
         if (base + 64 * w + 32 < n) wd[1] = v[2] | (v[3] << 16);
       }
     }
+#pragma unroll
+    for (int ks = 0; ks < NSV / 4; ++ks) bv[ks] = bn[ks];
+#pragma unroll
+    for (int mb = 0; mb < 4; ++mb) qv[mb] = qn[mb];
   }
 }
 
