@@ -1484,6 +1484,36 @@ cdmd_status prepare_recon(cdmd_model* M, int static_bg, int* NSout, hipStream_t 
   const int N = M->N, k = M->k;
   const int64_t m = M->m;
   M->recon_mfma = M->lift_mfma && 2 * ns <= 32;
+  for (int s = 0; s < ns; ++s) {
+    const cplx l = M->lam[M->S[s]];
+    if (!static_bg && std::abs(l) > 1.0 && std::pow(std::abs(l), (double)(m - 1)) > kVanderMax)
+      return fail(CDMD_E_NUMERIC, "|lambda|^(m-1) overflows the Vandermonde matrix");
+  }
+  if (M->recon_mfma && M->device_la) {
+    // from the device solve's G (column order of the solve: canonical index c is column
+    // perm[c]); nothing is built on the host
+    cdmd::k::ReconPrep rp{};
+    rp.ns = ns;
+    rp.NS = NS;
+    rp.NSP = M->lm_nsplit;
+    rp.KS = M->lm_nksteps;
+    rp.N = N;
+    rp.k = k;
+    rp.static_bg = static_bg ? 1 : 0;
+    rp.m = m;
+    rp.xscale = (double)M->xscale;
+    for (int s = 0; s < ns; ++s) {
+      rp.col[s] = M->perm[M->S[s]];
+      rp.beta[2 * s] = M->beta[s].real();
+      rp.beta[2 * s + 1] = M->beta[s].imag();
+      rp.lam[2 * s] = M->lam[M->S[s]].real();
+      rp.lam[2 * s + 1] = M->lam[M->S[s]].imag();
+    }
+    const cdmd::tla::SmallLAOutLayout L = cdmd::tla::small_la_out_layout(N, k);
+    HIPCHK(cdmd::k::recon_prep(M->d_la_out + L.G, rp, M->d_Gsp, M->d_Vc, st));
+    *NSout = NS;
+    return CDMD_OK;
+  }
   if (M->recon_mfma) {
     const int NSP = M->lm_nsplit, KS = M->lm_nksteps;
     for (int ks = 0; ks < KS; ++ks)
@@ -1515,11 +1545,6 @@ cdmd_status prepare_recon(cdmd_model* M, int static_bg, int* NSout, hipStream_t 
       row[s] = (float)g.real();
       row[ns + s] = (float)g.imag();
     }
-  }
-  for (int s = 0; s < ns; ++s) {
-    const cplx l = M->lam[M->S[s]];
-    if (!static_bg && std::abs(l) > 1.0 && std::pow(std::abs(l), (double)(m - 1)) > kVanderMax)
-      return fail(CDMD_E_NUMERIC, "|lambda|^(m-1) overflows the Vandermonde matrix");
   }
   std::vector<cplx> pw(ns, cplx(1.0, 0.0));
   for (int64_t t = 0; t < m; ++t) {

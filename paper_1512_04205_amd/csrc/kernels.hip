@@ -22,6 +22,19 @@ __device__ __forceinline__ float ldx(const T* p) {
   return static_cast<float>(*p);
 }
 
+// x rounded to the nearest bf16 (8 significant bits, ties to even), as bits; and back.
+__device__ __forceinline__ uint16_t bf16_bits_d(double x) {
+  if (x == 0.0) return signbit(x) ? 0x8000 : 0;
+  int e;
+  const double f = frexp(fabs(x), &e);
+  const double q = ldexp(rint(ldexp(f, 8)), e - 8);
+  const uint32_t u = __float_as_uint((float)q) >> 16;
+  return (uint16_t)(u | (x < 0 ? 0x8000u : 0u));
+}
+__device__ __forceinline__ double bf16_val_d(uint16_t b) {
+  return (double)__uint_as_float((uint32_t)b << 16);
+}
+
 // ============================================================================
 // sparse sketch, uint8 video
 // One block = one segment of pixel-sorted (pixel, row, sign) triples x FPB frames.
@@ -805,6 +818,66 @@ __global__ __launch_bounds__(256) void k_bgfg_mfma(const uint8_t* __restrict__ D
   }
 }
 
+// Operands of the reconstruction from the device solve's G (N x k complex, row t at t*k,
+// column order of the solve): the B operands of G~_S = [Re | Im] of G[:, col_s] beta_s
+// xscale ([ks][split][lane][8], element i of lane l is row 16ks + 8(l/32) + i, column
+// l%32 < 2 ns, NSP bf16 terms) and the rows of Vc (m x NS floats: lambda_s^t, then
+// -Im, zero-padded; lambda^t by repeated float64 multiplication, 1 when static_bg).
+__global__ __launch_bounds__(256) void k_recon_prep(const double* __restrict__ G, ReconPrep rp,
+                                                    uint16_t* __restrict__ Gsp, float* __restrict__ Vc) {
+  const int ns = rp.ns, NSP = rp.NSP, N = rp.N, k = rp.k;
+  const int64_t total = (int64_t)rp.KS * 64 * 8;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+    const int i = (int)(e & 7);
+    const int l = (int)((e >> 3) & 63);
+    const int ks = (int)(e >> 9);
+    const int row = 16 * ks + 8 * (l >> 5) + i;
+    const int col = l & 31;
+    double g = 0.0;
+    if (row < N && col < 2 * ns) {
+      const int s = col < ns ? col : col - ns;
+      const double* z = G + 2 * ((int64_t)row * k + rp.col[s]);
+      const double br = rp.beta[2 * s], bi = rp.beta[2 * s + 1];
+      const double zr = (z[0] * br - z[1] * bi) * rp.xscale, zi = (z[0] * bi + z[1] * br) * rp.xscale;
+      g = col < ns ? zr : zi;
+    }
+    double rem = g;
+    for (int sp = 0; sp < NSP; ++sp) {
+      const uint16_t bits = bf16_bits_d(rem);
+      rem -= bf16_val_d(bits);
+      Gsp[(((int64_t)ks * NSP + sp) * 64 + l) * 8 + i] = bits;
+    }
+  }
+  if (blockIdx.x == 0) {
+    const int t = threadIdx.x, NS = rp.NS;
+    const int64_t m = rp.m;
+    if (t < ns) {
+      const double lr = rp.lam[2 * t], li = rp.lam[2 * t + 1];
+      double pr = 1.0, pi = 0.0;
+      for (int64_t f = 0; f < m; ++f) {
+        Vc[f * NS + t] = (float)pr;
+        Vc[f * NS + ns + t] = (float)(-pi);
+        if (!rp.static_bg) {
+          const double nr = pr * lr - pi * li, ni = pr * li + pi * lr;
+          pr = nr;
+          pi = ni;
+        }
+      }
+    } else if (t < ns + (NS - 2 * ns)) {
+      const int c = 2 * ns + (t - ns);
+      for (int64_t f = 0; f < m; ++f) Vc[f * NS + c] = 0.f;
+    }
+  }
+}
+
+hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gsp, float* Vc, hipStream_t s) {
+  if (rp.ns < 1 || rp.ns > 16 || 2 * rp.ns > rp.NS || rp.NS > 32) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)rp.KS * 64 * 8;
+  const int grid = (int)std::min<int64_t>((total + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_recon_prep, dim3(grid), dim3(256), 0, s, G, rp, (uint16_t*)Gsp, Vc);
+  return hipGetLastError();
+}
+
 hipError_t bgfg_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const void* Gp, int nsplit,
                      int nksteps, int NS, const float* Vc, float tau, float xscale, int mode,
                      void* out, int64_t t0, int64_t t1, int64_t ldL, hipStream_t s) {
@@ -1109,17 +1182,6 @@ constexpr int SLA_NMAX = 1024;
 constexpr int SLA_JMAX = 320;
 constexpr int SLA_FAST = 15488;  // LDS doubles: tridiagonal eigen-solve work, later scratch
 
-__device__ __forceinline__ uint16_t bf16_bits_d(double x) {
-  if (x == 0.0) return signbit(x) ? 0x8000 : 0;
-  int e;
-  const double f = frexp(fabs(x), &e);
-  const double q = ldexp(rint(ldexp(f, 8)), e - 8);
-  const uint32_t u = __float_as_uint((float)q) >> 16;
-  return (uint16_t)(u | (x < 0 ? 0x8000u : 0u));
-}
-__device__ __forceinline__ double bf16_val_d(uint16_t b) {
-  return (double)__uint_as_float((uint32_t)b << 16);
-}
 
 // The small linear algebra of one solve runs as five kernels, each with a grid row
 // (blockIdx.y, or blockIdx.x for the one-workgroup kernels) per solve of a batch:

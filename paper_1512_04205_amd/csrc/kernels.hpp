@@ -114,6 +114,16 @@ hipError_t bgfg(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, cons
 hipError_t bgfg_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const void* Gp, int nsplit,
                      int nksteps, int NS, const float* Vc, float tau, float xscale, int mode,
                      void* out, int64_t t0, int64_t t1, int64_t ldL, hipStream_t stream);
+// Reconstruction operands from the device solve's G (see k_recon_prep): ns <= 16 selected
+// modes, device columns col[s], amplitudes beta (re, im), eigenvalues lam (re, im).
+struct ReconPrep {
+  int ns, NS, NSP, KS, N, k, static_bg;
+  int64_t m;
+  double xscale;
+  int col[16];
+  double beta[32], lam[32];
+};
+hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gsp, float* Vc, hipStream_t stream);
 // counts[t] = number of set bits of frame t of a bit-packed mask
 hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* counts,
                        hipStream_t stream);
