@@ -48,13 +48,13 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
                                    double sketch_scale, int32_t groups, double* mu, double* sigma,
                                    double* lam, double* W, double* G, int32_t* steps);
 
-/* Phase times (ms) of the last device small-LA solve: [0] Lanczos incl. convergence
-   checks, [1] of which the tridiagonal eigen-solves of the checks, [2] Ritz vectors
-   V = Q Z, M12 V and A~ (from the end of [0]), [3] eigenvalues of A~, [4] eigenvectors,
-   [5] G, [6] lift operand write, and of [0]: [7] matrix-vector products, [8]
-   reorthogonalisation, [9] norm and next vector, [10] multisection of the checks, [11]
-   tridiagonal inverse iteration, [12] hand-over of the Ritz vectors of T_J; [13..15]
-   unused.
+/* Phase times (ms) of the last device small-LA solve (group 0's clock): [0] Lanczos incl.
+   convergence checks, [1] of which the checks, [2] Ritz vectors V = Q Z, M12 V and A~
+   (from the end of [0]), [3] eigenvalues of A~, [4] eigenvectors, [5] G, and of [0]:
+   [6] waits at the exchanges between the row groups, [7] matrix-vector products, [8]
+   Gram-Schmidt work, [9] norm and next vector, [10] multisection of the checks, [11]
+   tridiagonal inverse iteration, [12] hand-over of the Ritz vectors of T_J, [13] loads of
+   the exchanged shares; [14..15] unused.
    Errors: INVALID_ARG. */
 cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms16);
 

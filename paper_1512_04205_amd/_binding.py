@@ -310,8 +310,9 @@ class Model:
         """Phase times (ms) of the last device small-LA solve."""
         v = np.zeros(16)
         _check(load_library().cdmd_dbg_la_phases(self._h, _dptr(v)))
-        return dict(zip(["lanczos", "checks", "atilde", "eigvals", "eigvecs", "G", "operands",
-                         "matvec", "orth", "step_rest", "multisection", "tri_vectors", "ritz_QZ"], v[:13]))
+        return dict(zip(["lanczos", "checks", "atilde", "eigvals", "eigvecs", "G", "xchg_wait",
+                         "matvec", "orth", "step_rest", "multisection", "tri_vectors", "ritz_QZ",
+                         "xchg_read"], v[:14]))
 
     def set_timing(self, enable: bool = True):
         _check(load_library().cdmd_set_timing(self._h, int(enable)))

@@ -583,13 +583,14 @@ cdmd_status take_device_la(cdmd_model* M) {
   M->la_phase_ms[3] = (tt[5] - tt[4]) * f;
   M->la_phase_ms[4] = (tt[6] - tt[5]) * f;
   M->la_phase_ms[5] = (tt[7] - tt[6]) * f;
-  M->la_phase_ms[6] = (tt[9] - tt[8]) * f;
+  M->la_phase_ms[6] = tt[8] * f;
   M->la_phase_ms[7] = tt[10] * f;
   M->la_phase_ms[8] = tt[11] * f;
   M->la_phase_ms[9] = tt[12] * f;
   M->la_phase_ms[10] = tt[13] * f;
   M->la_phase_ms[11] = tt[14] * f;
   M->la_phase_ms[12] = tt[15] * f;
+  M->la_phase_ms[13] = tt[9] * f;
   return CDMD_OK;
 }
 

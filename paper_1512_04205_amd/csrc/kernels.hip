@@ -1107,6 +1107,15 @@ struct WaveTeam {
     v += dpp_f64<0x140>(v);  // row_mirror
     return (lane_f64(v, 0) + lane_f64(v, 16)) + (lane_f64(v, 32) + lane_f64(v, 48));
   }
+  // the sums over lanes 0..31 (lo) and 32..63 (hi), the same bits on every lane
+  __device__ void half_sums(double v, double& lo, double& hi) {
+    v += dpp_f64<0xB1>(v);
+    v += dpp_f64<0x4E>(v);
+    v += dpp_f64<0x141>(v);
+    v += dpp_f64<0x140>(v);
+    lo = lane_f64(v, 0) + lane_f64(v, 16);
+    hi = lane_f64(v, 32) + lane_f64(v, 48);
+  }
   __device__ double wave_max(double v) {
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
@@ -1271,6 +1280,7 @@ struct GridX {
     if (slice != nullptr)
       for (int t = r0 + tm.tid; t < r1; t += tm.nt) st_dev(&base[(int64_t)G * PS + t], slice[t]);
     ++nx;
+    tm.tick(11);  // phase clock: the work before the exchange
     __builtin_amdgcn_s_waitcnt(0);  // this wave's stores have completed
     __syncthreads();
     if (tm.tid == 0) {
@@ -1289,14 +1299,23 @@ struct GridX {
     }
     __syncthreads();
     if (s_ok[0] == 0) return false;  // uniform
+    tm.tick(8);  // the wait
     for (int i = tm.tid; i < n; i += tm.nt) {
-      double v = 0.0;
-      for (int q = 0; q < G; ++q) v += ld_dev(&base[(int64_t)q * PS + i]);
+      double v = 0.0;  // in group order; eight loads in flight
+      for (int q0 = 0; q0 < G; q0 += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) x[u] = q0 + u < G ? ld_dev(&base[(int64_t)(q0 + u) * PS + i]) : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (q0 + u < G) v += x[u];
+      }
       sum[i] = v;
     }
     if (full != nullptr)
       for (int t = tm.tid; t < N; t += tm.nt) full[t] = ld_dev(&base[(int64_t)G * PS + t]);
     tm.sync();
+    tm.tick(9);  // the loads of the shares
     return true;
   }
 };
@@ -1317,10 +1336,12 @@ __global__ __launch_bounds__(64) void k_la_prep(SLADesc d1, const SLADesc* __res
   }
 }
 
-// Lanczos and the Ritz vectors of T_J: la_groups(N) 1024-thread workgroups per solve
+// Lanczos and the Ritz vectors of T_J: la_groups(N) workgroups of SLA_A_NT threads per solve
 // (blockIdx.x), each owning a range of rows of the Lanczos vectors; group 0 runs the
 // convergence checks and writes the results.
-__global__ __launch_bounds__(1024) void k_la_a(SLADesc d1, const SLADesc* __restrict__ ds) {
+constexpr int SLA_A_NT = 512;  // Lanczos workgroup size: 256 registers per thread, no spills
+
+__global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __restrict__ ds) {
   using namespace tla;
   const SLADesc& d = la_desc(d1, ds, blockIdx.y);
   const int m = d.m, k = d.k, N = m - 1;
@@ -1495,7 +1516,7 @@ static hipError_t launch_la_head(const SLADesc& d1, const SLADesc* ds, int count
                                  hipStream_t stream, hipEvent_t after_lanczos) {
   const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
   hipLaunchKernelGGL(k_la_prep, dim3(count), dim3(64), 0, stream, d1, ds);
-  hipLaunchKernelGGL(k_la_a, dim3(tla::la_groups(nmax), count), dim3(1024), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_a, dim3(tla::la_groups(nmax), count), dim3(SLA_A_NT), 0, stream, d1, ds);
   if (after_lanczos != nullptr) (void)hipEventRecord(after_lanczos, stream);
   hipLaunchKernelGGL(k_la_ritz, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);

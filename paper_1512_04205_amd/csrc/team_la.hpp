@@ -62,6 +62,7 @@ struct HostTeam {
   void sync() {}
   void stamp(int) {}  // phase timing hook (device only)
   double wave_sum(double v) { return v; }
+  void half_sums(double v, double& lo, double& hi) { lo = v, hi = 0.0; }  // (wsize 64 only)
   double wave_max(double v) { return v; }
   void wave_argmax(double&, int&) {}
   double sum(double v) { return v; }
@@ -405,14 +406,14 @@ struct LocalX {
 // the order of the groups.
 template <class TM>
 TLA_HD void colsum_rows(TM& tm, const double* A, int64_t lda, const double* x, int n, int r0, int r1, double* y,
-                        bool subtract, double* part, int64_t part_doubles) {
+                        bool subtract, double* part, int64_t part_doubles, int gmax = 32) {
   const int nr = r1 - r0;
   if (nr <= 0) {
     tm.sync();
     return;
   }
   int G = tm.nt / nr;
-  if (G > 32) G = 32;
+  if (G > gmax) G = gmax;
   if (G < 1 || part == nullptr || (int64_t)G * nr > part_doubles) G = 1;
   for (int e = tm.tid; e < G * nr; e += tm.nt) {
     const int r = r0 + e % nr, g = e / nr;
@@ -450,6 +451,31 @@ TLA_HD void colsum_rows(TM& tm, const double* A, int64_t lda, const double* x, i
 // wave per i, lanes over the rows.
 template <class TM>
 TLA_HD void dots_rows(TM& tm, const double* Q, int ldq, const double* w, int n, int r0, int r1, double* h) {
+  if (tm.wsize == 64 && r1 - r0 <= 32) {
+    // a half-wave per vector, lanes over the rows; four vectors' loads in flight per lane
+    const int half = tm.lane >> 5, t = r0 + (tm.lane & 31);
+    const bool rv = t < r1;
+    const double wt = rv ? w[t] : 0.0;
+    const int slots = 2 * tm.nwaves;
+    for (int i0 = 0; i0 < n; i0 += 4 * slots) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int i = i0 + u * slots + 2 * tm.wave + half;
+        v[u] = rv && i < n ? Q[(int64_t)i * ldq + t] * wt : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        double lo, hi;
+        tm.half_sums(v[u], lo, hi);
+        const int ib = i0 + u * slots + 2 * tm.wave;
+        if (tm.lane == 0 && ib < n) h[ib] = lo;
+        if (tm.lane == 0 && ib + 1 < n) h[ib + 1] = hi;
+      }
+    }
+    tm.sync();
+    return;
+  }
   for (int i = tm.wave; i < n; i += tm.nwaves) {
     const double* qi = Q + (int64_t)i * ldq;
     double s = 0.0;
@@ -501,7 +527,7 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
   auto orth_pass = [&](int n) -> bool {
     dots_rows(tm, Q, ldq, w, n, r0, r1, h);
     if (!xg.exchange(tm, h, n, h, nullptr, nullptr)) return false;
-    colsum_rows(tm, Q, ldq, h, n, r0, r1, w, true, ws.fast, ws.fast_doubles);
+    colsum_rows(tm, Q, ldq, h, n, r0, r1, w, true, ws.fast, ws.fast_doubles, 8);
     return true;
   };
   // The squared norm of w and the whole of w, in every group
@@ -545,7 +571,7 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
     for (int i = 0; i <= j; ++i) h2sq += h[i] * h[i];
     const double nsq = h[j + 1] - h2sq;
     double nr = sqrt(nsq > 0.0 ? nsq : 0.0);
-    colsum_rows(tm, Q, ldq, h, j + 1, r0, r1, w, true, ws.fast, ws.fast_doubles);
+    colsum_rows(tm, Q, ldq, h, j + 1, r0, r1, w, true, ws.fast, ws.fast_doubles, 8);
     tm.tick(11);
     if (tm.tid == 0) {
       ws.alpha[j] = aj;  // the same value in every group
