@@ -69,9 +69,9 @@ cdmd_status cdmd_dbg_force_gather_sketch(cdmd_model* mdl, int32_t on);
    Takes effect at the next cdmd_fit.  Errors: INVALID_ARG. */
 cdmd_status cdmd_dbg_force_host_la(cdmd_model* mdl, int32_t on);
 
-/* Split the Lanczos vectors of the device small-LA solve over at most `groups` row groups
-   (workgroups; 0 = as many as the rows call for: one per 32 rows, at most 32).  Takes
-   effect at the next cdmd_fit.  Errors: INVALID_ARG (groups outside [0, 32]). */
+/* Split the Lanczos vectors of the device small-LA solve over `groups` row groups
+   (workgroups, at most m - 1; 0 = as many as the rows call for: one per 32 rows, at most
+   32).  Takes effect at the next cdmd_fit.  Errors: INVALID_ARG (groups outside [0, 32]). */
 cdmd_status cdmd_dbg_la_groups(cdmd_model* mdl, int32_t groups);
 
 /* Force (1) or release (0) the float32 vector-ALU lift for a uint8 video whose FP32

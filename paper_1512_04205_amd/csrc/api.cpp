@@ -1197,6 +1197,7 @@ struct cdmd_batch {
   std::vector<hipEvent_t> join1, join2;
   cdmd::k::SLADesc* d_desc = nullptr;
   int la_nmax = 0, la_gmax = 0;     // grid extents of the small-LA row kernels
+  int la_ngroups = 0;               // Lanczos workgroups per solve in the grid
   hipStream_t cap = nullptr;        // the graph's own stream (capture needs a non-null stream)
   hipEvent_t entry = nullptr;       // caller's stream -> cap
 
@@ -1276,7 +1277,7 @@ cdmd_status capture_batch(cdmd_batch* B, hipStream_t st) {
     hip(hipEventRecord(B->join1[q], B->pool[q]));
     hip(hipStreamWaitEvent(st, B->join1[q], 0));
   }
-  hip(cdmd::k::small_la_batch_head(B->d_desc, (int)B->dev.size(), B->la_nmax, st));
+  hip(cdmd::k::small_la_batch_head(B->d_desc, (int)B->dev.size(), B->la_nmax, B->la_ngroups, st));
   // the A~ eigen-solves and G of every model on pool stream 0, queued before the lift
   // operands so that their workgroups are resident before the lifts fill the device; the
   // lifts on the other pool streams
@@ -1330,7 +1331,7 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
     B->videos.assign(d_videos, d_videos + n);
     B->dev.clear();
     std::vector<cdmd::k::SLADesc> desc;
-    B->la_nmax = B->la_gmax = 0;
+    B->la_nmax = B->la_gmax = B->la_ngroups = 0;
     for (int i = 0; i < n; ++i) {
       cdmd_model* M = B->models[i];
       plan_fit(M, d_videos[i]);
@@ -1343,6 +1344,8 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
                                       M->lr_nb, M->lm_nsplit, M->lm_nksteps, M->la_groups});
       B->la_nmax = std::max(B->la_nmax, (int)M->m - 1);
       B->la_gmax = std::max(B->la_gmax, std::max((int)M->m - 1, 16 * M->lm_nksteps));
+      B->la_ngroups = std::max(B->la_ngroups, M->la_groups > 0 ? std::min(M->la_groups, (int)M->m - 1)
+                                                                : cdmd::tla::la_groups((int)M->m - 1));
     }
     if (!desc.empty()) {
       HIPCHK(hipMemcpy(B->d_desc, desc.data(), sizeof(desc[0]) * desc.size(), hipMemcpyHostToDevice));

@@ -1345,7 +1345,7 @@ __global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __
   using namespace tla;
   const SLADesc& d = la_desc(d1, ds, blockIdx.y);
   const int m = d.m, k = d.k, N = m - 1;
-  const int G = d.groups > 0 && d.groups < la_groups(N) ? d.groups : la_groups(N), g = blockIdx.x;
+  const int G = d.groups > 0 ? (d.groups < N ? d.groups : N) : la_groups(N), g = blockIdx.x;
   if (g >= G) return;  // uniform: this solve needs fewer groups than the grid has
   __shared__ double s_q[SLA_NMAX], s_w[SLA_NMAX];
   __shared__ double s_h[SLA_JMAX + 4], s_alpha[SLA_JMAX + 4], s_beta[SLA_JMAX + 4];
@@ -1357,6 +1357,7 @@ __global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __
   double* out = d.out;
   DevTeam tm;
   la_team(tm, s_red, g == 0 ? out + Lo.timing : nullptr);
+  tm.tick(-1);
   SmallLAWork ws;
   la_work(ws, d, s_q, s_w, s_h, s_alpha, s_beta, s_fast, s_flag);
   GridX xg;
@@ -1513,10 +1514,10 @@ __global__ __launch_bounds__(SLA_ROWS_NT) void k_la_gp(SLADesc d1, const SLADesc
 // The small LA in three parts: the head (Lanczos, V, M12 V), then side by side the lift's
 // operands (followed by the lift) and the tail (the A~ eigen-solve and G).
 static hipError_t launch_la_head(const SLADesc& d1, const SLADesc* ds, int count, int nmax,
-                                 hipStream_t stream, hipEvent_t after_lanczos) {
+                                 hipStream_t stream, hipEvent_t after_lanczos, int ngroups) {
   const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
   hipLaunchKernelGGL(k_la_prep, dim3(count), dim3(64), 0, stream, d1, ds);
-  hipLaunchKernelGGL(k_la_a, dim3(tla::la_groups(nmax), count), dim3(SLA_A_NT), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_a, dim3(ngroups, count), dim3(SLA_A_NT), 0, stream, d1, ds);
   if (after_lanczos != nullptr) (void)hipEventRecord(after_lanczos, stream);
   hipLaunchKernelGGL(k_la_ritz, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
@@ -1552,7 +1553,7 @@ hipError_t small_la_head(const double* Gr, int m, int k, double rtol, int Jmax, 
                          int groups, hipStream_t stream, hipEvent_t after_lanczos) {
   if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
   const SLADesc d = la_desc_of(Gr, m, k, rtol, Jmax, sketch_scale, xscale, scratch, out, Gp, NB, NS, KS, groups);
-  return launch_la_head(d, nullptr, 1, m - 1, stream, after_lanczos);
+  return launch_la_head(d, nullptr, 1, m - 1, stream, after_lanczos, groups > 0 ? std::min(groups, m - 1) : tla::la_groups(m - 1));
 }
 
 hipError_t small_la_gp(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
@@ -1571,10 +1572,10 @@ hipError_t small_la_tail(const double* Gr, int m, int k, double rtol, int Jmax, 
   return launch_la_tail(d, nullptr, 1, m - 1, stream);
 }
 
-hipError_t small_la_batch_head(const SLADesc* d_descs, int count, int nmax, hipStream_t stream) {
+hipError_t small_la_batch_head(const SLADesc* d_descs, int count, int nmax, int ngroups, hipStream_t stream) {
   if (count < 1) return hipSuccess;
   const SLADesc none{};
-  return launch_la_head(none, d_descs, count, nmax, stream, nullptr);
+  return launch_la_head(none, d_descs, count, nmax, stream, nullptr, ngroups);
 }
 
 hipError_t small_la_batch_gp(const SLADesc* d_descs, int count, int gmax, hipStream_t stream) {

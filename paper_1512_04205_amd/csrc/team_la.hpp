@@ -213,6 +213,9 @@ TLA_HD void tridiag_topk_values(TM& tm, const double* a, const double* b, const 
   tm.sync();
 }
 
+template <class TM>
+TLA_HD void tridiag_orthonormalise(TM& tm, int J, int kk, double* work, double* Z);
+
 // Eigenvectors of the symmetric tridiagonal (a, b) for theta[0..kk-1] (descending) by three
 // steps of inverse iteration, each a solve with the LU factors (row interchanges) of
 // T - theta I, one thread per eigenvector, all at once: unit vectors.  Vectors of nearly
@@ -292,7 +295,13 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
     for (int i = 0; i < J; ++i) Z[(int64_t)i * kk + r] = y[i * ys];
   }
   tm.sync();
-  if (!orth) return;
+  if (orth) tridiag_orthonormalise(tm, J, kk, work, Z);
+}
+
+// The columns of Z (J x kk, element (i, r) at Z[i*kk + r]) orthonormalised in order and
+// signed so that the largest-modulus component is positive.  work: kk^2 doubles.
+template <class TM>
+TLA_HD void tridiag_orthonormalise(TM& tm, int J, int kk, double* work, double* Z) {
   // Orthonormalise the columns in order by Cholesky QR, twice: C = Z^T Z = R^T R, then
   // Z <- Z R^-1 (the Q factor of Z, which Gram-Schmidt in column order would also give;
   // the columns are close to orthonormal, so C is well conditioned and the second pass
@@ -447,6 +456,48 @@ TLA_HD void colsum_rows(TM& tm, const double* A, int64_t lda, const double* x, i
   }
 }
 
+// y[r] = sum_{c < n} M[r*ldm + c] x[c] for r in [r0, r1), M symmetric (so this is also the
+// column sum of colsum_rows).  With 64-lane waves: each wave takes four rows at a time,
+// its lanes over the columns (coalesced rows, eight loads in flight per lane), then a wave
+// sum per row; otherwise colsum_rows.
+template <class TM>
+TLA_HD void symv_rows(TM& tm, const double* M, int64_t ldm, const double* x, int n, int r0, int r1, double* y,
+                      double* part, int64_t part_doubles) {
+  if (tm.wsize != 64) {
+    colsum_rows(tm, M, ldm, x, n, r0, r1, y, false, part, part_doubles);
+    return;
+  }
+  for (int rb = r0 + 4 * tm.wave; rb < r1; rb += 4 * tm.nwaves) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    const double* row[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) row[u] = M + (int64_t)(rb + u < r1 ? rb + u : rb) * ldm;
+    int c = tm.lane;
+    for (; c + 64 < n; c += 128) {
+      const double x0 = x[c], x1 = x[c + 64];
+      double v[8];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        v[2 * u] = row[u][c];
+        v[2 * u + 1] = row[u][c + 64];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += v[2 * u] * x0 + v[2 * u + 1] * x1;
+    }
+    if (c < n) {
+      const double x0 = x[c];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc[u] += row[u][c] * x0;
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const double sum = tm.wave_sum(acc[u]);
+      if (tm.lane == 0 && rb + u < r1) y[rb + u] = sum;
+    }
+  }
+  tm.sync();
+}
+
 // h[i] = sum over the group's rows of Q[i*ldq + t] w[t], i < n (this group's share): a
 // wave per i, lanes over the rows.
 template <class TM>
@@ -552,8 +603,8 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
   double corr = 0.0;
   for (int j = 0; j < Jmax; ++j) {
     tm.tick(-1);
-    // w = M x over the group's rows, as columns of the symmetric M (coalesced over rows)
-    colsum_rows(tm, M, ldm, q, N, r0, r1, w, false, ws.fast, ws.fast_doubles);
+    // w = M x over the group's rows
+    symv_rows(tm, M, ldm, q, N, r0, r1, w, ws.fast, ws.fast_doubles);
     tm.tick(10);
     if (!orth_pass(j + 1)) return -2;
     double aj = h[j] - corr;
@@ -600,6 +651,7 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
       double* Zm = work + 5 * (int64_t)J * kk;
       double tnorm = 0.0;
       int decision = 0;
+      bool have_z = false;  // Zm holds the (not yet orthonormalised) Ritz vectors of T_J
       // The closed form of the last components is exact where they are large but has an
       // absolute floor near sqrt(eps): it can show that a pair has not converged, not that
       // it has.  Only when it cannot decide are the Ritz vectors of T_J computed (inverse
@@ -627,6 +679,7 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
         tm.sync();
         if (conv) {
           tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, false, work, Zm);
+          have_z = true;
           for (int i = 0; i < k; ++i)
             if (nr * fabs(Zm[(int64_t)(J - 1) * kk + i]) > rtol * scale) conv = false;
         }
@@ -652,6 +705,7 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
           tm.sync();
           if (conv) {
             tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, false, work, Zm);
+            have_z = true;
             for (int i = 0; i < k; ++i)
               if (nr * fabs(Zm[(int64_t)(J - 1) * kk + i]) > rtol * scale) conv = false;
           }
@@ -671,7 +725,8 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
       if (decision == 1) {
         if (lead) {
           // final Ritz vectors: members of eigenvalue clusters orthogonalised (kk = k)
-          tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, true, work, Zm);
+          if (have_z) tridiag_orthonormalise(tm, J, kk, work, Zm);
+          else tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, true, work, Zm);
           tm.tick(14);
           for (int i = tm.tid; i < k; i += tm.nt) evals[i] = theta[i];
           for (int e = tm.tid; e < J * k; e += tm.nt) Z[e] = Zm[e];
