@@ -1383,32 +1383,83 @@ __global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __
   }
 }
 
+// Dense products of the small LA on FP64 MFMA (v_mfma_f64_16x16x4f64: lane l supplies
+// A[l%16][l/16] and B[l/16][l%16]; item r of lane l is D[4r + l/16][l%16]).  A workgroup
+// of 4 waves takes kLaRows = 64 rows, a wave 16 rows x up to 64 columns (four 16-column
+// tiles), the inner dimension 4 at a time with its loads issued ahead.
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+constexpr int SLA_MM_NT = 256;
+
+// out[c*ldo + r] = sum_{q < K} A(r, q) B(q, c) for rows r in [r0, r0 + 16) (< R) and
+// columns c < C (<= 64), with A(r, q) = pa[q*lda + r] and B(q, c) = pb[q*ldb + c*cstride].
+__device__ __forceinline__ void mfma_rows16(const double* __restrict__ pa, int64_t lda, const double* __restrict__ pb,
+                                            int64_t ldb, int64_t cstride, int K, int r0, int R, int C,
+                                            double* __restrict__ out, int64_t ldo) {
+  const int l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
+  const int CT = (C + 15) >> 4;
+  f64x4_t acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+  const int r = r0 + i;
+  for (int q0 = 0; q0 < K; q0 += 16) {
+    double av[4], bv[4][4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int q = q0 + 4 * u + kq;
+      av[u] = r < R && q < K ? pa[(int64_t)q * lda + r] : 0.0;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct) {
+        const int c = 16 * ct + i;
+        bv[u][ct] = ct < CT && q < K && c < C ? pb[(int64_t)q * ldb + (int64_t)c * cstride] : 0.0;
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+        if (ct < CT) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][ct], acc[ct], 0, 0, 0);
+  }
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int ro = r0 + 4 * rr + kq, c = 16 * ct + i;
+      if (ct < CT && ro < R && c < C) out[(int64_t)c * ldo + ro] = acc[ct][rr];
+    }
+}
+
 // V = Q_J Z over the workgroup's kLaRows rows.
-__global__ __launch_bounds__(SLA_ROWS_NT) void k_la_ritz(SLADesc d1, const SLADesc* __restrict__ ds) {
+__global__ __launch_bounds__(SLA_MM_NT) void k_la_ritz(SLADesc d1, const SLADesc* __restrict__ ds) {
   using namespace tla;
   const SLADesc& d = la_desc(d1, ds, blockIdx.y);
   const int N = d.m - 1, k = d.k;
   const int t0 = blockIdx.x * kLaRows;
   const SmallLAOutLayout Lo = small_la_out_layout(N, k);
   if (t0 >= N || d.out[Lo.status] != 0.0) return;  // uniform over the workgroup
-  __shared__ double s_red[SLA_ROWS_NT / 64];
-  DevTeam tm;
-  la_team(tm, s_red, nullptr);
   const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
   const int J = (int)d.out[Lo.J];
+  if (k <= 64) {
+    // V(t, c) = sum_i Q(i, t) Z(i, c): A(t, i) = Q[i*ldq + t], B(i, c) = Z[i*k + c]
+    mfma_rows16(d.scratch + Ls.Q, la_ldq(N), d.scratch + Ls.Z, k, 1, J, t0 + 16 * (threadIdx.x >> 6), N, k,
+                d.scratch + Ls.V, N);
+    return;
+  }
+  __shared__ double s_red[SLA_MM_NT / 64];
+  DevTeam tm;
+  la_team(tm, s_red, nullptr);
   ritz_rows(tm, d.scratch + Ls.Q, N, J, d.scratch + Ls.Z, k, d.scratch + Ls.V, t0,
             t0 + kLaRows < N ? t0 + kLaRows : N);
 }
 
 // TV = M12 V over the workgroup's rows, and the block's partials of V^T TV and |v_i|^2.
-__global__ __launch_bounds__(SLA_ROWS_NT) void k_la_tv(SLADesc d1, const SLADesc* __restrict__ ds) {
+__global__ __launch_bounds__(SLA_MM_NT) void k_la_tv(SLADesc d1, const SLADesc* __restrict__ ds) {
   using namespace tla;
   const SLADesc& d = la_desc(d1, ds, blockIdx.y);
   const int m = d.m, N = m - 1, k = d.k;
   const int t0 = blockIdx.x * kLaRows;
   const SmallLAOutLayout Lo = small_la_out_layout(N, k);
   if (t0 >= N || d.out[Lo.status] != 0.0) return;
-  __shared__ double s_red[SLA_ROWS_NT / 64];
+  __shared__ double s_red[SLA_MM_NT / 64];
   __shared__ double s_stage[SLA_STAGE];
   DevTeam tm;
   la_team(tm, s_red, nullptr);
@@ -1416,7 +1467,14 @@ __global__ __launch_bounds__(SLA_ROWS_NT) void k_la_tv(SLADesc d1, const SLADesc
   const int t1 = t0 + kLaRows < N ? t0 + kLaRows : N;
   double* V = d.scratch + Ls.V;
   double* TV = d.scratch + Ls.TV;
-  m12v_rows(tm, d.Gr, m, N, k, V, TV, t0, t1, s_stage, SLA_STAGE);
+  if (k <= 64) {
+    // TV(a, c) = sum_b M12(a, b) V(b, c) with M12(a, b) = Gram[(b+1)*m + a] (symmetric):
+    // A(a, b) = Gr[(b+1)*m + a], B(b, c) = V[c*N + b]
+    mfma_rows16(d.Gr + m, m, V, 1, N, N, t0 + 16 * (threadIdx.x >> 6), N, k, TV, N);
+    __syncthreads();
+  } else {
+    m12v_rows(tm, d.Gr, m, N, k, V, TV, t0, t1, s_stage, SLA_STAGE);
+  }
   block_gram(tm, V, TV, N, k, t0, t1, d.scratch + Ls.P + (int64_t)blockIdx.x * ((int64_t)k * k + k), s_stage,
              SLA_STAGE);
 }
@@ -1519,8 +1577,8 @@ static hipError_t launch_la_head(const SLADesc& d1, const SLADesc* ds, int count
   hipLaunchKernelGGL(k_la_prep, dim3(count), dim3(64), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_a, dim3(ngroups, count), dim3(SLA_A_NT), 0, stream, d1, ds);
   if (after_lanczos != nullptr) (void)hipEventRecord(after_lanczos, stream);
-  hipLaunchKernelGGL(k_la_ritz, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
-  hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_ritz, dim3(rb, count), dim3(SLA_MM_NT), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_MM_NT), 0, stream, d1, ds);
   return hipGetLastError();
 }
 
