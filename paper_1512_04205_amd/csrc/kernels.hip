@@ -22,6 +22,8 @@ __device__ __forceinline__ float ldx(const T* p) {
   return static_cast<float>(*p);
 }
 
+typedef double f64x4_t __attribute__((ext_vector_type(4)));
+
 // x rounded to the nearest bf16 (8 significant bits, ties to even), as bits; and back.
 __device__ __forceinline__ uint16_t bf16_bits_d(double x) {
   if (x == 0.0) return signbit(x) ? 0x8000 : 0;
@@ -267,56 +269,59 @@ hipError_t sketch_sparse_f32(const float* D, int64_t ld, int64_t m, const int32_
   return hipGetLastError();
 }
 
-// ============================================================================
-// Gram of the sketch, float64: 32x32 output tiles, upper triangle of tiles computed
-// and mirrored.  Each thread owns a 2x2 sub-tile.
+// Gram of the sketch on FP64 MFMA 16x16x4: a workgroup per 16 x 16 tile of the upper
+// triangle (mirrored); its 4 waves take interleaved 64-row chunks of the inner (sketch-row)
+// index and their partial tiles are added in wave order.  Within a chunk the inner index
+// is permuted so that lane (i, q) reads runs of four consecutive rows, the same
+// permutation for both operands (the sum runs over the same terms).  For an integer sketch
+// every partial sum is an integer below 2^53, so the result is exact in any order.
 template <typename T>
-__global__ __launch_bounds__(256) void k_gram(const T* __restrict__ Y, int p, int64_t m,
-                                              double* __restrict__ Gr) {
+__global__ __launch_bounds__(256) void k_gram_mfma(const T* __restrict__ Y, int p, int64_t m,
+                                                   double* __restrict__ Gr) {
   if (blockIdx.y < blockIdx.x) return;
-  __shared__ double sa[32][33];
-  __shared__ double sb[32][33];
-  const int64_t a0 = (int64_t)blockIdx.x * 32, b0 = (int64_t)blockIdx.y * 32;
-  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
-  double c00 = 0, c01 = 0, c10 = 0, c11 = 0;
-  for (int r0 = 0; r0 < p; r0 += 32) {
-    for (int q = threadIdx.x; q < 32 * 32; q += 256) {
-      const int fr = q >> 5, rr = q & 31;
-      const int r = r0 + rr;
-      sa[fr][rr] = (a0 + fr < m && r < p) ? (double)Y[(a0 + fr) * p + r] : 0.0;
-      sb[fr][rr] = (b0 + fr < m && r < p) ? (double)Y[(b0 + fr) * p + r] : 0.0;
+  __shared__ f64x4_t s_part[4][64];
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
+  const int64_t a0 = (int64_t)blockIdx.x * 16, b0 = (int64_t)blockIdx.y * 16;
+  const int64_t a = a0 + i, b = b0 + i;
+  const T* ya = Y + (a < m ? a : 0) * (int64_t)p;
+  const T* yb = Y + (b < m ? b : 0) * (int64_t)p;
+  f64x4_t acc = {0.0, 0.0, 0.0, 0.0};
+  for (int r0 = 64 * w; r0 < p; r0 += 256) {  // 16 steps per chunk, all loads issued first
+    double av[16], bv[16];
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int r = r0 + 16 * (u >> 2) + 4 * kq + (u & 3);
+      av[u] = a < m && r < p ? (double)ya[r] : 0.0;
+      bv[u] = b < m && r < p ? (double)yb[r] : 0.0;
     }
-    __syncthreads();
-#pragma unroll 8
-    for (int rr = 0; rr < 32; ++rr) {
-      const double x0 = sa[ty][rr], x1 = sa[ty + 16][rr];
-      const double y0 = sb[tx][rr], y1 = sb[tx + 16][rr];
-      c00 = fma(x0, y0, c00);
-      c01 = fma(x0, y1, c01);
-      c10 = fma(x1, y0, c10);
-      c11 = fma(x1, y1, c11);
-    }
-    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 16; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u], acc, 0, 0, 0);
   }
-  const double cv[2][2] = {{c00, c01}, {c10, c11}};
-  for (int u = 0; u < 2; ++u)
-    for (int v = 0; v < 2; ++v) {
-      const int64_t a = a0 + ty + 16 * u, b = b0 + tx + 16 * v;
-      if (a < m && b < m) {
-        Gr[a * m + b] = cv[u][v];
-        Gr[b * m + a] = cv[u][v];
+  s_part[w][l] = acc;
+  __syncthreads();
+  if (w == 0) {
+    f64x4_t t = s_part[0][l];
+#pragma unroll
+    for (int q = 1; q < 4; ++q) t += s_part[q][l];
+#pragma unroll
+    for (int rr = 0; rr < 4; ++rr) {
+      const int64_t ra = a0 + 4 * rr + kq, cb = b0 + i;
+      if (ra < m && cb < m) {
+        Gr[ra * m + cb] = t[rr];
+        Gr[cb * m + ra] = t[rr];
       }
     }
+  }
 }
 
 hipError_t gram_i32(const int32_t* Y, int p, int64_t m, double* Gr, hipStream_t stream) {
-  const unsigned t = (unsigned)((m + 31) / 32);
-  hipLaunchKernelGGL(k_gram<int32_t>, dim3(t, t), dim3(256), 0, stream, Y, p, m, Gr);
+  const unsigned t = (unsigned)((m + 15) / 16);
+  hipLaunchKernelGGL(k_gram_mfma<int32_t>, dim3(t, t), dim3(256), 0, stream, Y, p, m, Gr);
   return hipGetLastError();
 }
 hipError_t gram_f64(const double* Y, int p, int64_t m, double* Gr, hipStream_t stream) {
-  const unsigned t = (unsigned)((m + 31) / 32);
-  hipLaunchKernelGGL(k_gram<double>, dim3(t, t), dim3(256), 0, stream, Y, p, m, Gr);
+  const unsigned t = (unsigned)((m + 15) / 16);
+  hipLaunchKernelGGL(k_gram_mfma<double>, dim3(t, t), dim3(256), 0, stream, Y, p, m, Gr);
   return hipGetLastError();
 }
 
@@ -1387,7 +1392,6 @@ __global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __
 // A[l%16][l/16] and B[l/16][l%16]; item r of lane l is D[4r + l/16][l%16]).  A workgroup
 // of 4 waves takes kLaRows = 64 rows, a wave 16 rows x up to 64 columns (four 16-column
 // tiles), the inner dimension 4 at a time with its loads issued ahead.
-typedef double f64x4_t __attribute__((ext_vector_type(4)));
 constexpr int SLA_MM_NT = 256;
 
 // out[c*ldo + r] = sum_{q < K} A(r, q) B(q, c) for rows r in [r0, r0 + 16) (< R) and
