@@ -136,7 +136,7 @@ typedef struct {
      kernel group, valid when timing is enabled: sketch (incl. slot reduction), Gram,
      lift (incl. partial reduction), reconstruction/threshold. */
   double gpu_ms_sketch, gpu_ms_gram, gpu_ms_lift, gpu_ms_recon;
-  int32_t lift_grid;         /* persistent lift workgroups in use (cdmd_autotune may change it) */
+  int32_t lift_grid;         /* lift workgroups in use (cdmd_autotune may change it) */
   int32_t sketch_slices;     /* pixel slices of the dense Gaussian sketch (0 otherwise) */
   int32_t sparse_form;       /* after cdmd_autotune: uint8 sparse sketch form, -1 gather
                                 (byte loads per triple), 10 F + V streaming (F frames per

@@ -102,6 +102,9 @@ struct cdmd_model {
   bool lift_mfma = false;   // MFMA path (uint8 video, 16-byte aligned frames)
   int lm_nb = 0, lm_nsplit = 0, lm_nksteps = 0, lm_grid = 0, lm_ne = 0;
   int lm_grid_max = 0;            // largest lift grid the partial buffer holds
+  // real-basis lift grid: many short workgroups, so that the dispatcher balances them
+  // around the compute unit the A~ eigen-solve holds
+  int lr_grid = 0;
   // real-basis lift (device small LA): Phi' = X' V S^-1, k columns + x_1; W applied on the host
   bool lift_real = false;
   int lr_nb = 0, lr_ne = 0;
@@ -642,7 +645,7 @@ cdmd_status launch_lift(cdmd_model* M, const void* d_video, float* d_phi, hipStr
   if (M->lift_mfma)
     HIPCHK(cdmd::k::lift_mfma((const uint8_t*)d_video, M->ld, M->n, M->m, M->d_Gp, real ? M->lr_nb : M->lm_nb,
                               M->lm_nsplit, M->lm_nksteps, real ? M->k : M->nc, M->xscale, M->d_part,
-                              M->lm_grid, real ? nullptr : d_phi, M->k, st));
+                              real ? M->lr_grid : M->lm_grid, real ? nullptr : d_phi, M->k, st));
   else
     HIPCHK(cdmd::k::lift_fp32(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_G, M->NC, M->nc,
                               M->d_pairs, M->npair, M->d_part, M->lgrid, d_phi, M->k, M->xscale, st));
@@ -662,7 +665,7 @@ cdmd_status enqueue_lift(cdmd_model* M, const void* d_video, float* d_phi, hipSt
   }
   M->mark(3, st);
   TRY(launch_lift(M, d_video, d_phi, st, M->lift_real));
-  const int grid = M->lift_mfma ? M->lm_grid : M->lgrid;
+  const int grid = M->lift_mfma ? (M->lift_real ? M->lr_grid : M->lm_grid) : M->lgrid;
   const int ne = M->lift_mfma ? (M->lift_real ? M->lr_ne : M->lm_ne) : M->ne;
   HIPCHK(cdmd::k::reduce_partials(M->d_part, grid, ne, M->d_red, st));
   M->mark(4, st);
@@ -885,7 +888,9 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
       TRY(halloc(&M->h_la_out, (size_t)M->la_out_n));
       M->device_la_ok = true;
     }
+    M->lr_grid = (int)std::min<int64_t>((M->n + 255) / 256, 2048);
     part_sz = std::max(part_sz, (size_t)std::max(M->lm_grid, M->lm_grid_max) * M->lm_ne);
+    part_sz = std::max(part_sz, (size_t)M->lr_grid * M->lr_ne);
     red_sz = std::max(red_sz, (size_t)M->lm_ne);
   }
   TRY(dalloc(&M->d_part, part_sz));
@@ -1130,7 +1135,7 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
     if (it != g_tune.end()) ch = it->second, cached = true;
   }
   if (!cached) {
-    if (M->lift_mfma) {
+    if (M->lift_mfma && !M->lift_real) {
       double best = 1e300;
       for (int g : {128, 256, 512, 1024}) {
         if (g > M->lm_grid_max) continue;
@@ -1173,7 +1178,7 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
   if (ch.lift_grid > 0) M->lm_grid = ch.lift_grid;
   if (ch.gauss_target > 0) TRY(apply_gauss_target(M, ch.gauss_target));
   M->tuned = true;
-  M->info.lift_grid = M->lm_grid;
+  M->info.lift_grid = M->lift_real ? M->lr_grid : M->lm_grid;
   M->info.sketch_slices = M->gauss ? M->gplan.nsplit : 0;
   M->info.sparse_form = M->gauss ? 0 : (M->force_gather_sketch ? -1 : 10 * M->sk_F + M->sk_V);
   return CDMD_OK;
@@ -1198,6 +1203,7 @@ struct cdmd_batch {
   cdmd::k::SLADesc* d_desc = nullptr;
   int la_nmax = 0, la_gmax = 0;     // grid extents of the small-LA row kernels
   int la_ngroups = 0;               // Lanczos workgroups per solve in the grid
+  int la_kmax = 0;                  // largest k of the batch
   hipStream_t cap = nullptr;        // the graph's own stream (capture needs a non-null stream)
   hipEvent_t entry = nullptr;       // caller's stream -> cap
 
@@ -1283,7 +1289,7 @@ cdmd_status capture_batch(cdmd_batch* B, hipStream_t st) {
   // lifts on the other pool streams
   hip(hipEventRecord(B->fork_tail, st));
   hip(hipStreamWaitEvent(B->pool[0], B->fork_tail, 0));
-  hip(cdmd::k::small_la_batch_tail(B->d_desc, (int)B->dev.size(), B->la_nmax, B->pool[0]));
+  hip(cdmd::k::small_la_batch_tail(B->d_desc, (int)B->dev.size(), B->la_nmax, B->la_kmax, B->pool[0]));
   for (size_t i = 0; i < B->dev.size() && r == CDMD_OK; ++i) {
     cdmd_model* M = B->models[B->dev[i]];
     hip(hipMemcpyAsync(M->h_la_out, M->d_la_out, sizeof(double) * M->la_out_n, hipMemcpyDeviceToHost,
@@ -1331,7 +1337,7 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
     B->videos.assign(d_videos, d_videos + n);
     B->dev.clear();
     std::vector<cdmd::k::SLADesc> desc;
-    B->la_nmax = B->la_gmax = B->la_ngroups = 0;
+    B->la_nmax = B->la_gmax = B->la_ngroups = B->la_kmax = 0;
     for (int i = 0; i < n; ++i) {
       cdmd_model* M = B->models[i];
       plan_fit(M, d_videos[i]);
@@ -1344,6 +1350,7 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
                                       M->lr_nb, M->lm_nsplit, M->lm_nksteps, M->la_groups});
       B->la_nmax = std::max(B->la_nmax, (int)M->m - 1);
       B->la_gmax = std::max(B->la_gmax, std::max((int)M->m - 1, 16 * M->lm_nksteps));
+      B->la_kmax = std::max(B->la_kmax, M->k);
       B->la_ngroups = std::max(B->la_ngroups, M->la_groups > 0 ? std::min(M->la_groups, (int)M->m - 1)
                                                                 : cdmd::tla::la_groups((int)M->m - 1));
     }

@@ -1483,7 +1483,7 @@ __global__ __launch_bounds__(SLA_MM_NT) void k_la_tv(SLADesc d1, const SLADesc* 
              SLA_STAGE);
 }
 
-// A~ from the block partials, its eigenvalues and eigenvectors (one workgroup per solve).
+// A~ from the block partials and its eigenvalues (one workgroup per solve).
 __global__ __launch_bounds__(1024) void k_la_b(SLADesc d1, const SLADesc* __restrict__ ds) {
   using namespace tla;
   const SLADesc& d = la_desc(d1, ds, blockIdx.x);
@@ -1500,9 +1500,62 @@ __global__ __launch_bounds__(1024) void k_la_b(SLADesc d1, const SLADesc* __rest
   SmallLAWork ws;
   la_work(ws, d, nullptr, s_w, nullptr, nullptr, nullptr, s_fast, s_flag);
   const int nblk = (N + kLaRows - 1) / kLaRows;
-  const int st = small_la_phase_b(tm, N, k, d.sketch_scale, ws, nblk, out + Lo.mu, out + Lo.sigma,
-                                  reinterpret_cast<cpx*>(out + Lo.lam), reinterpret_cast<cpx*>(out + Lo.W));
+  const int st = small_la_phase_b1(tm, N, k, d.sketch_scale, ws, nblk, out + Lo.mu, out + Lo.sigma,
+                                   reinterpret_cast<cpx*>(out + Lo.lam));
   if (tm.tid == 0 && st != kOk) out[Lo.status] = (double)st;
+}
+
+// One eigenvector of A~ per single-wave workgroup (blockIdx.x = its index), so that the
+// inverse iterations run on separate compute units; the second member of a conjugate pair
+// is left to k_la_b3.  LU work in LDS for k <= 64, else in the solve's global scratch.
+constexpr int SLA_V_LDS = 2 * 64 * 64 + 5 * 64;
+
+__global__ __launch_bounds__(64) void k_la_v(SLADesc d1, const SLADesc* __restrict__ ds) {
+  using namespace tla;
+  const SLADesc& d = la_desc(d1, ds, blockIdx.y);
+  const int N = d.m - 1, k = d.k, j = blockIdx.x;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  double* out = d.out;
+  if (j >= k || out[Lo.status] != 0.0) return;
+  const cpx* lam = reinterpret_cast<const cpx*>(out + Lo.lam);
+  if (conj_second(lam, j)) return;
+  __shared__ double s_lu[SLA_V_LDS];
+  const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
+  WaveTeam wt;
+  wt.tid = wt.lane = threadIdx.x;
+  wt.nt = wt.wsize = 64;
+  wt.wave = 0;
+  wt.nwaves = 1;
+  cpx *LU, *b, *y;
+  int* piv;
+  if (k <= 64) {
+    LU = reinterpret_cast<cpx*>(s_lu);
+    b = LU + (int64_t)k * k;
+    y = b + k;
+    piv = reinterpret_cast<int*>(y + k);
+  } else {
+    LU = reinterpret_cast<cpx*>(d.scratch + Ls.LU) + (int64_t)j * k * k;
+    b = reinterpret_cast<cpx*>(d.scratch + Ls.bb) + (int64_t)j * k;
+    y = reinterpret_cast<cpx*>(d.scratch + Ls.yy) + (int64_t)j * k;
+    piv = reinterpret_cast<int*>(d.scratch + Ls.piv) + (int64_t)j * k;
+  }
+  const bool ok = eigvec_wave(wt, d.scratch + Ls.At, k, lam[j].re, lam[j].im, LU, b, y, piv,
+                              reinterpret_cast<cpx*>(out + Lo.W) + (int64_t)j * k);
+  if (!ok && threadIdx.x == 0) out[Lo.status] = (double)kNumeric;
+}
+
+// The conjugate partners and the normalisation of W (one workgroup per solve).
+__global__ __launch_bounds__(256) void k_la_b3(SLADesc d1, const SLADesc* __restrict__ ds) {
+  using namespace tla;
+  const SLADesc& d = la_desc(d1, ds, blockIdx.x);
+  const int N = d.m - 1, k = d.k;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  double* out = d.out;
+  if (out[Lo.status] != 0.0) return;
+  __shared__ double s_red[4];
+  DevTeam tm;
+  la_team(tm, s_red, out + Lo.timing);
+  small_la_phase_b3(tm, k, reinterpret_cast<const cpx*>(out + Lo.lam), reinterpret_cast<cpx*>(out + Lo.W));
 }
 
 // G = V S^-1 W over the workgroup's rows.
@@ -1592,10 +1645,12 @@ static hipError_t launch_la_gp(const SLADesc& d1, const SLADesc* ds, int count, 
   return hipGetLastError();
 }
 
-static hipError_t launch_la_tail(const SLADesc& d1, const SLADesc* ds, int count, int nmax,
+static hipError_t launch_la_tail(const SLADesc& d1, const SLADesc* ds, int count, int nmax, int kmax,
                                  hipStream_t stream) {
   const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
   hipLaunchKernelGGL(k_la_b, dim3(count), dim3(1024), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_v, dim3(kmax, count), dim3(64), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_b3, dim3(count), dim3(256), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_g, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   return hipGetLastError();
 }
@@ -1631,7 +1686,7 @@ hipError_t small_la_tail(const double* Gr, int m, int k, double rtol, int Jmax, 
                          int groups, hipStream_t stream) {
   if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
   const SLADesc d = la_desc_of(Gr, m, k, rtol, Jmax, sketch_scale, xscale, scratch, out, Gp, NB, NS, KS, groups);
-  return launch_la_tail(d, nullptr, 1, m - 1, stream);
+  return launch_la_tail(d, nullptr, 1, m - 1, k, stream);
 }
 
 hipError_t small_la_batch_head(const SLADesc* d_descs, int count, int nmax, int ngroups, hipStream_t stream) {
@@ -1646,10 +1701,10 @@ hipError_t small_la_batch_gp(const SLADesc* d_descs, int count, int gmax, hipStr
   return launch_la_gp(none, d_descs, count, gmax, stream);
 }
 
-hipError_t small_la_batch_tail(const SLADesc* d_descs, int count, int nmax, hipStream_t stream) {
+hipError_t small_la_batch_tail(const SLADesc* d_descs, int count, int nmax, int kmax, hipStream_t stream) {
   if (count < 1) return hipSuccess;
   const SLADesc none{};
-  return launch_la_tail(none, d_descs, count, nmax, stream);
+  return launch_la_tail(none, d_descs, count, nmax, kmax, stream);
 }
 
 int64_t small_la_scratch_doubles(int m, int k, int Jmax) {

@@ -164,7 +164,7 @@ bool small_la_fits(int m, int k, int Jmax);
 // ngroups: the grid's Lanczos workgroups per solve, at least the groups any solve uses.
 hipError_t small_la_batch_head(const SLADesc* d_descs, int count, int nmax, int ngroups, hipStream_t stream);
 hipError_t small_la_batch_gp(const SLADesc* d_descs, int count, int gmax, hipStream_t stream);
-hipError_t small_la_batch_tail(const SLADesc* d_descs, int count, int nmax, hipStream_t stream);
+hipError_t small_la_batch_tail(const SLADesc* d_descs, int count, int nmax, int kmax, hipStream_t stream);
 int64_t small_la_out_doubles(int m, int k);
 
 }  // namespace k

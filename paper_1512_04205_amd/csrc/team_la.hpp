@@ -1284,13 +1284,13 @@ TLA_HD int small_la_phase_a(TM& tm, X& xg, const double* Gr, int m, int k, doubl
   return kOk;
 }
 
-// Algorithm 1 steps 4 (end), 6 and 7, given the block partials P (nblk blocks of k*k + k,
+// Algorithm 1 steps 4 (end) and 6, given the block partials P (nblk blocks of k*k + k,
 // from block_gram over V = Q_J Z and TV = M12 V): nu the column norms of V, sigma =
-// sqrt(mu) * sketch_scale, A~ = S^-1 Vn^T M12 Vn S^-1 with Vn = V diag(1/nu), its
-// eigenvalues lam and eigenvectors W (column j at j*k, unit, largest entry real positive).
+// sqrt(mu) * sketch_scale, A~ = S^-1 Vn^T M12 Vn S^-1 with Vn = V diag(1/nu), and its
+// eigenvalues lam (step 7, first part).
 template <class TM>
-TLA_HD int small_la_phase_b(TM& tm, int N, int k, double sketch_scale, const SmallLAWork& ws, int nblk,
-                            const double* mu, double* sigma, cpx* lam, cpx* W) {
+TLA_HD int small_la_phase_b1(TM& tm, int N, int k, double sketch_scale, const SmallLAWork& ws, int nblk,
+                             const double* mu, double* sigma, cpx* lam) {
   double* nu = ws.nu;
   double* s = ws.nu + k;  // sqrt(mu)
   const int64_t ne = (int64_t)k * k + k;
@@ -1324,17 +1324,40 @@ TLA_HD int small_la_phase_b(TM& tm, int N, int k, double sketch_scale, const Sma
   if (ws.flag[0] != 0) return kNumeric;
   tm.stamp(5);
   for (int j = tm.tid; j < k; j += tm.nt) lam[j] = cmk(ev[2 * j], ev[2 * j + 1]);
-  if (!eigvecs_team(tm, ws.At, k, ev, W, fastr, fastd, ws.flag)) return kNumeric;
-  for (int j = tm.tid; j < k; j += tm.nt) {
-    const bool second = ev[2 * j + 1] < 0.0 && j > 0 && ev[2 * j - 2] == ev[2 * j] &&
-                        ev[2 * j - 1] == -ev[2 * j + 1];
-    if (second)
+  tm.sync();
+  return kOk;
+}
+
+// True when lam[j] is the second member of a conjugate pair (its eigenvector is the
+// conjugate of its partner's).
+TLA_HD inline bool conj_second(const cpx* lam, int j) {
+  return lam[j].im < 0.0 && j > 0 && lam[j - 1].re == lam[j].re && lam[j - 1].im == -lam[j].im;
+}
+
+// Step 7, end: the second members of conjugate pairs take their partners' conjugates, and
+// every column of W is made unit with its largest entry real and positive.
+template <class TM>
+TLA_HD void small_la_phase_b3(TM& tm, int k, const cpx* lam, cpx* W) {
+  for (int j = tm.tid; j < k; j += tm.nt)
+    if (conj_second(lam, j))
       for (int i = 0; i < k; ++i) W[(int64_t)j * k + i] = cconj(W[(int64_t)(j - 1) * k + i]);
-  }
   tm.sync();
   for (int j = tm.tid; j < k; j += tm.nt) normalise_vec(W + (int64_t)j * k, k);
   tm.sync();
   tm.stamp(6);
+}
+
+// Steps 4 (end), 6 and 7 by one team: phase B1, the eigenvectors W of A~ (column j at
+// j*k), phase B3.
+template <class TM>
+TLA_HD int small_la_phase_b(TM& tm, int N, int k, double sketch_scale, const SmallLAWork& ws, int nblk,
+                            const double* mu, double* sigma, cpx* lam, cpx* W) {
+  const int st = small_la_phase_b1(tm, N, k, sketch_scale, ws, nblk, mu, sigma, lam);
+  if (st != kOk) return st;
+  if (!eigvecs_team(tm, ws.At, k, reinterpret_cast<const double*>(lam), W, ws.lz.fast, ws.lz.fast_doubles,
+                    ws.flag))
+    return kNumeric;
+  small_la_phase_b3(tm, k, lam, W);
   return kOk;
 }
 
