@@ -1507,8 +1507,9 @@ __global__ __launch_bounds__(1024) void k_la_b(SLADesc d1, const SLADesc* __rest
 
 // One eigenvector of A~ per single-wave workgroup (blockIdx.x = its index), so that the
 // inverse iterations run on separate compute units; the second member of a conjugate pair
-// is left to k_la_b3.  LU work in LDS for k <= 64, else in the solve's global scratch.
-constexpr int SLA_V_LDS = 2 * 64 * 64 + 5 * 64;
+// is left to k_la_b3.  LU work in LDS (dynamic, 2k^2 + 5k doubles for the largest k of
+// the launch, so the workgroup fits beside others) for k <= 64, else in the solve's
+// global scratch.
 
 __global__ __launch_bounds__(64) void k_la_v(SLADesc d1, const SLADesc* __restrict__ ds) {
   using namespace tla;
@@ -1519,7 +1520,7 @@ __global__ __launch_bounds__(64) void k_la_v(SLADesc d1, const SLADesc* __restri
   if (j >= k || out[Lo.status] != 0.0) return;
   const cpx* lam = reinterpret_cast<const cpx*>(out + Lo.lam);
   if (conj_second(lam, j)) return;
-  __shared__ double s_lu[SLA_V_LDS];
+  extern __shared__ double s_lu[];
   const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
   WaveTeam wt;
   wt.tid = wt.lane = threadIdx.x;
@@ -1649,7 +1650,8 @@ static hipError_t launch_la_tail(const SLADesc& d1, const SLADesc* ds, int count
                                  hipStream_t stream) {
   const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
   hipLaunchKernelGGL(k_la_b, dim3(count), dim3(1024), 0, stream, d1, ds);
-  hipLaunchKernelGGL(k_la_v, dim3(kmax, count), dim3(64), 0, stream, d1, ds);
+  const size_t vlds = kmax <= 64 ? sizeof(double) * (2 * (size_t)kmax * kmax + 5 * (size_t)kmax) : 0;
+  hipLaunchKernelGGL(k_la_v, dim3(kmax, count), dim3(64), vlds, stream, d1, ds);
   hipLaunchKernelGGL(k_la_b3, dim3(count), dim3(256), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_g, dim3(rb, count), dim3(SLA_ROWS_NT), 0, stream, d1, ds);
   return hipGetLastError();
