@@ -468,7 +468,8 @@ hipError_t lift_fp32(const void* D, int dtype, int64_t ld, int64_t n, int64_t m,
 // bf16 terms (1: bf16 lift; 3: 24-bit G, float32-accurate products), float32
 // accumulation.  Block = 4 waves, tile = 256 pixels, wave w owns pixels 64w..64w+63
 // as two 32-row MFMA blocks x NB 32-column blocks.  Frames stream through LDS in
-// chunks of 32 ([frame][pixel] bytes); each lane gathers its 8 frames of one pixel.
+// chunks of 32 or 64 ([frame][pixel] bytes); per k-step each lane gathers its 8 frames of
+// one pixel.
 // The fused reduction P = Phi_ext^T Phi_ext (Phi_ext = [Phi | x_1 in column nc]) is
 // computed from the accumulator registers themselves: a lane holds 16 pixel rows of
 // one column, and the same register order is used for both operands, so the pixel
@@ -507,71 +508,78 @@ __device__ __forceinline__ void split8(const float* v, bf16x8_t& hi, bf16x8_t& l
 }
 
 constexpr int LM_TILE = 256;
-constexpr int LM_CH = 32;        // frames per LDS chunk
 constexpr int LM_SA = 264;       // LDS row stride (bytes) of a frame row
 
 // X' G on MFMA for one 256-pixel tile: acc[mb][nb] (wave w, rows 64w + 32mb + ...)
-// Frames 1..m-1 stream through `lds` ([LM_CH][LM_SA] bytes, then the B operands of one
-// chunk).  The caller synchronises before reusing `lds`.
-template <int NB, int NSPLIT>
+// Frames 1..m-1 stream through `lds` in chunks of 16 KPC frames ([16 KPC][LM_SA] bytes,
+// then the B operands of one chunk; KPC = 2 or 4, each thread loads 16 KPC bytes of one
+// frame row per chunk).  The caller synchronises before reusing `lds`.
+template <int NB, int NSPLIT, int KPC>
 __device__ __forceinline__ void xprime_g_tile(const uint8_t* __restrict__ D, int64_t ld, int64_t n,
                                               int64_t m, const uint4* __restrict__ Gp, int nksteps,
                                               int64_t base, uint8_t* lds, f32x16_t (&acc)[2][NB]) {
-  constexpr int BCH = 2 * NB * NSPLIT * 64;  // uint4 B operands per chunk
+  static_assert(KPC == 2 || KPC == 4, "16 KPC frames per chunk, 16 KPC bytes per thread");
+  constexpr int LM_CH = 16 * KPC;                 // frames per chunk
+  constexpr int NV = KPC;                         // 16-byte loads per thread and chunk
+  constexpr int TPR = 16 / KPC;                   // threads per 256-byte frame row
+  constexpr int BCH = KPC * NB * NSPLIT * 64;     // uint4 B operands per chunk
   uint8_t(*sA)[LM_SA] = reinterpret_cast<uint8_t(*)[LM_SA]>(lds);
   uint4* sB = reinterpret_cast<uint4*>(lds + LM_CH * LM_SA);
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int64_t N = m - 1;
-  const int nchunks = (nksteps + 1) / 2;
-  const int fr = tid >> 3, seg = (tid & 7) * 32;
+  const int nchunks = (nksteps + KPC - 1) / KPC;
+  const int fr = tid / TPR, seg = (tid % TPR) * (16 * NV);
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int nb = 0; nb < NB; ++nb)
 #pragma unroll
       for (int j = 0; j < 16; ++j) acc[mb][nb][j] = 0.f;
-  uint4 ra0, ra1;
+  uint4 ra[NV];
   uint4 rb[(BCH + 255) / 256];
   auto gload = [&](int c) {
     const int64_t f = 1 + (int64_t)c * LM_CH + fr;
     const int64_t px = base + seg;
-    if (f <= N && px + 32 <= n) {
+    if (f <= N && px + 16 * NV <= n) {
       const uint4* src = reinterpret_cast<const uint4*>(D + f * ld + px);
-      ra0 = src[0];
-      ra1 = src[1];
+#pragma unroll
+      for (int q = 0; q < NV; ++q) ra[q] = src[q];
     } else {
-      uint32_t wds[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        uint32_t v = 0;
+      for (int q = 0; q < NV; ++q) {
+        uint32_t wds[4];
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          const int64_t pp = px + q * 4 + b;
-          if (f <= N && pp < n) v |= (uint32_t)D[f * ld + pp] << (8 * b);
+        for (int r = 0; r < 4; ++r) {
+          uint32_t v = 0;
+#pragma unroll
+          for (int b = 0; b < 4; ++b) {
+            const int64_t pp = px + 16 * q + 4 * r + b;
+            if (f <= N && pp < n) v |= (uint32_t)D[f * ld + pp] << (8 * b);
+          }
+          wds[r] = v;
         }
-        wds[q] = v;
+        ra[q] = make_uint4(wds[0], wds[1], wds[2], wds[3]);
       }
-      ra0 = make_uint4(wds[0], wds[1], wds[2], wds[3]);
-      ra1 = make_uint4(wds[4], wds[5], wds[6], wds[7]);
     }
 #pragma unroll
     for (int q = 0; q < (BCH + 255) / 256; ++q) {
       const int e = tid + q * 256;
       if (e < BCH) {
-        const int ks = 2 * c + e / (NB * NSPLIT * 64);
-        rb[q] = ks < nksteps ? Gp[(int64_t)2 * c * NB * NSPLIT * 64 + e] : make_uint4(0, 0, 0, 0);
+        const int ks = KPC * c + e / (NB * NSPLIT * 64);
+        rb[q] = ks < nksteps ? Gp[(int64_t)KPC * c * NB * NSPLIT * 64 + e] : make_uint4(0, 0, 0, 0);
       }
     }
   };
   gload(0);
   for (int c = 0; c < nchunks; ++c) {
     __syncthreads();
-    {  // rows are 8-byte aligned (stride 264): four 8-byte stores
+    {  // rows are 8-byte aligned (stride 264): 8-byte stores
       uint2* dst = reinterpret_cast<uint2*>(&sA[fr][seg]);
-      dst[0] = make_uint2(ra0.x, ra0.y);
-      dst[1] = make_uint2(ra0.z, ra0.w);
-      dst[2] = make_uint2(ra1.x, ra1.y);
-      dst[3] = make_uint2(ra1.z, ra1.w);
+#pragma unroll
+      for (int q = 0; q < NV; ++q) {
+        dst[2 * q] = make_uint2(ra[q].x, ra[q].y);
+        dst[2 * q + 1] = make_uint2(ra[q].z, ra[q].w);
+      }
     }
 #pragma unroll
     for (int q = 0; q < (BCH + 255) / 256; ++q) {
@@ -581,7 +589,7 @@ __device__ __forceinline__ void xprime_g_tile(const uint8_t* __restrict__ D, int
     __syncthreads();
     if (c + 1 < nchunks) gload(c + 1);
 #pragma unroll
-    for (int ks = 0; ks < 2; ++ks) {
+    for (int ks = 0; ks < KPC; ++ks) {
       bf16x8_t a[2];
 #pragma unroll
       for (int mb = 0; mb < 2; ++mb) {
@@ -606,19 +614,22 @@ __device__ __forceinline__ void xprime_g_tile(const uint8_t* __restrict__ D, int
   }
 }
 
-template <int NB, int NSPLIT>
+template <int NB, int NSPLIT, int KPC>
 constexpr int xg_lds_bytes() {
-  return LM_CH * LM_SA + 2 * NB * NSPLIT * 64 * 16;
+  return 16 * KPC * LM_SA + KPC * NB * NSPLIT * 64 * 16;
 }
 
+// The occupancy hints keep the accumulators in the unified register file at the wave
+// count that still needs no spills (checked with the compiler's resource report): more
+// resident waves keep more of the video in flight.
 template <int NB, int NSPLIT>
-__global__ __launch_bounds__(256) void k_lift_mfma(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3 : NB == 2 ? 2 : 1))) void k_lift_mfma(
     const uint8_t* __restrict__ D, int64_t ld, int64_t n, int64_t m, const uint4* __restrict__ Gp,
     int nksteps, int nc, float xscale, double* __restrict__ part, float* __restrict__ phi,
     int kmodes) {
   constexpr int NP = NB * (NB + 1) / 2;
   constexpr int RED_BYTES = 4 * NP * 16 * 64 * 4;
-  constexpr int MAIN_BYTES = xg_lds_bytes<NB, NSPLIT>();
+  constexpr int MAIN_BYTES = xg_lds_bytes<NB, NSPLIT, 4>();
   constexpr int LDS_BYTES = RED_BYTES > MAIN_BYTES ? RED_BYTES : MAIN_BYTES;
   __shared__ __align__(16) uint8_t lds[LDS_BYTES];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
@@ -632,7 +643,7 @@ __global__ __launch_bounds__(256) void k_lift_mfma(
   for (int64_t tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int64_t base = tile * LM_TILE;
     f32x16_t acc[2][NB];
-    xprime_g_tile<NB, NSPLIT>(D, ld, n, m, Gp, nksteps, base, lds, acc);
+    xprime_g_tile<NB, NSPLIT, 4>(D, ld, n, m, Gp, nksteps, base, lds, acc);
     // x_1 (scaled) into column nc of Phi_ext
     if ((l & 31) == (nc & 31)) {
 #pragma unroll
@@ -716,14 +727,14 @@ __global__ __launch_bounds__(256) void k_bgfg_mfma(const uint8_t* __restrict__ D
                                                   float tau, float xscale, int mode,
                                                   void* __restrict__ out, int64_t t0, int64_t t1,
                                                   int64_t ldL) {
-  constexpr int MAIN_BYTES = xg_lds_bytes<1, NSPLIT>();
+  constexpr int MAIN_BYTES = xg_lds_bytes<1, NSPLIT, 2>();
   constexpr int T_BYTES = 256 * 33 * 4;
   constexpr int LDS_BYTES = T_BYTES > MAIN_BYTES ? T_BYTES : MAIN_BYTES;
   __shared__ __align__(16) uint8_t lds[LDS_BYTES];
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int64_t base = (int64_t)blockIdx.x * LM_TILE;
   f32x16_t acc[2][1];
-  xprime_g_tile<1, NSPLIT>(D, ld, n, m, Gp, nksteps, base, lds, acc);
+  xprime_g_tile<1, NSPLIT, 2>(D, ld, n, m, Gp, nksteps, base, lds, acc);
   __syncthreads();
   float* sT = reinterpret_cast<float*>(lds);
 #pragma unroll
@@ -1157,7 +1168,7 @@ struct DevTeam : WaveTeam {
   uint64_t t_tick;
   __device__ void sync() { __syncthreads(); }
   // 0: start of a convergence check, 1: its end (accumulated in slot 0); 2..: phase marks
-  __device__ void stamp(int i) {
+  __device__ __forceinline__ void stamp(int i) {
     if (tid != 0 || tslots == nullptr) return;
     const uint64_t t = wall_clock64();
     if (i == 0) t_last = t;
@@ -1165,13 +1176,13 @@ struct DevTeam : WaveTeam {
     else tslots[i] = (double)t;
   }
   // accumulate the time since the previous tick into slot i (i < 0: restart)
-  __device__ void tick(int i) {
+  __device__ __forceinline__ void tick(int i) {
     if (tid != 0 || tslots == nullptr) return;
     const uint64_t t = wall_clock64();
     if (i >= 0) tslots[i] += (double)(t - t_tick);
     t_tick = t;
   }
-  __device__ double sum(double v) {
+  __device__ __forceinline__ double sum(double v) {
     v = wave_sum(v);
     if (lane == 0) red[wave] = v;
     __syncthreads();
@@ -1194,7 +1205,7 @@ struct DevTeam : WaveTeam {
 
 constexpr int SLA_NMAX = 1024;
 constexpr int SLA_JMAX = 320;
-constexpr int SLA_FAST = 15488;  // LDS doubles: tridiagonal eigen-solve work, later scratch
+constexpr int SLA_FAST = tla::kLaFast;  // LDS doubles: tridiagonal eigen-solve work, later scratch
 
 
 // The small linear algebra of one solve runs as five kernels, each with a grid row
@@ -1226,11 +1237,12 @@ __device__ __forceinline__ void la_team(DevTeam& tm, double* red, double* tslots
 }
 
 __device__ void la_work(tla::SmallLAWork& ws, const SLADesc& d, double* s_q, double* s_w, double* s_h,
-                        double* s_alpha, double* s_beta, double* s_fast, int* s_flag) {
+                        double* s_alpha, double* s_beta, double* s_fast, int* s_flag, double* s_qc = nullptr) {
   using namespace tla;
   const SmallLALayout Ls = small_la_layout(d.m - 1, d.k, d.Jmax);
   double* scratch = d.scratch;
-  ws.lz = LanczosWork{s_q, s_w, s_h, s_alpha, s_beta, scratch + Ls.T, s_fast, SLA_FAST};
+  ws.lz = LanczosWork{s_q, s_w, s_h, s_alpha, s_beta, scratch + Ls.T, s_fast, SLA_FAST, s_qc,
+                      s_qc != nullptr ? tla::kLaQCache : 0};
   ws.Q = scratch + Ls.Q;
   ws.V = scratch + Ls.V;
   ws.Z = scratch + Ls.Z;
@@ -1267,8 +1279,8 @@ struct GridX {
   unsigned* bar;    // arrivals (zeroed before the launch)
   unsigned nx;      // exchanges so far
   int* s_ok;        // LDS: the wait's outcome
-  __device__ bool exchange(DevTeam& tm, const double* part, int n, double* sum, const double* slice,
-                           double* full) {
+  __device__ __forceinline__ bool exchange(DevTeam& tm, const double* part, int n, double* sum, const double* slice,
+                                           double* full) {
     tm.sync();
     if (G == 1) {
       if (sum != part)
@@ -1357,6 +1369,7 @@ __global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __
   __shared__ double s_red[16];
   __shared__ int s_flag[1], s_ok[1];
   __shared__ double s_fast[SLA_FAST];
+  __shared__ double s_qc[tla::kLaQCache];
   const SmallLAOutLayout Lo = small_la_out_layout(N, k);
   const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
   double* out = d.out;
@@ -1364,7 +1377,7 @@ __global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __
   la_team(tm, s_red, g == 0 ? out + Lo.timing : nullptr);
   tm.tick(-1);
   SmallLAWork ws;
-  la_work(ws, d, s_q, s_w, s_h, s_alpha, s_beta, s_fast, s_flag);
+  la_work(ws, d, s_q, s_w, s_h, s_alpha, s_beta, s_fast, s_flag, s_qc);
   GridX xg;
   xg.g = g;
   xg.G = G;

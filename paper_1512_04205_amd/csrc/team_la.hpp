@@ -28,6 +28,9 @@
 #else
 #define TLA_HD
 #endif
+// for the Lanczos loop and its per-step routines: a device call would keep the team in
+// scratch memory and spill the caller's registers there
+#define TLA_INLINE inline __attribute__((always_inline))
 
 namespace cdmd {
 namespace tla {
@@ -83,7 +86,12 @@ struct LanczosWork {
   double* T;      // Jmax + k + 6 Jmax k: tridiagonal eigen-solve work (global scratch)
   double* fast;   // fast (LDS) region of fast_doubles doubles, or nullptr: the tridiagonal
   int64_t fast_doubles;  // work when it fits, and later scratch
+  double* qc;     // fast (LDS) copy of the group's rows of the first basis vectors, or nullptr
+  int64_t qc_doubles;
 };
+// Sizes (doubles) of the fast regions of a Lanczos workgroup: the work region and the copy
+// of the group's rows of the basis (120 vectors of 32 rows).
+constexpr int kLaFast = 13440, kLaQCache = 3840;
 
 // Deterministic start vectors.  The first (salt 0) is the smooth profile
 // 1 + sin(0.7 (i + 1)) / 4: the Gram is indexed by frames and its leading eigenvectors are
@@ -412,10 +420,12 @@ struct LocalX {
 
 // y[r] = sum_{i < n} x[i] A[i*lda + r] (or y[r] -= that sum) for r in [r0, r1): thread
 // (r, group of i), eight loads in flight; the groups' partial sums (in `part`) combine in
-// the order of the groups.
+// the order of the groups.  Rows i < acap of A are read from the copy Ac (element (i, r)
+// at Ac[i*(r1 - r0) + r - r0]) instead.
 template <class TM>
-TLA_HD void colsum_rows(TM& tm, const double* A, int64_t lda, const double* x, int n, int r0, int r1, double* y,
-                        bool subtract, double* part, int64_t part_doubles, int gmax = 32) {
+TLA_HD TLA_INLINE void colsum_rows(TM& tm, const double* A, int64_t lda, const double* x, int n, int r0, int r1, double* y,
+                        bool subtract, double* part, int64_t part_doubles, int gmax = 32,
+                        const double* Ac = nullptr, int acap = 0) {
   const int nr = r1 - r0;
   if (nr <= 0) {
     tm.sync();
@@ -430,6 +440,21 @@ TLA_HD void colsum_rows(TM& tm, const double* A, int64_t lda, const double* x, i
     const double* col = A + r;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0, a4 = 0.0, a5 = 0.0, a6 = 0.0, a7 = 0.0;
     int i = i0;
+    if (Ac != nullptr) {
+      const double* cc = Ac + (r - r0);
+      const int ic = i1 < acap ? i1 : acap;
+      for (; i + 8 <= ic; i += 8) {
+        a0 += cc[(int64_t)i * nr] * x[i];
+        a1 += cc[(int64_t)(i + 1) * nr] * x[i + 1];
+        a2 += cc[(int64_t)(i + 2) * nr] * x[i + 2];
+        a3 += cc[(int64_t)(i + 3) * nr] * x[i + 3];
+        a4 += cc[(int64_t)(i + 4) * nr] * x[i + 4];
+        a5 += cc[(int64_t)(i + 5) * nr] * x[i + 5];
+        a6 += cc[(int64_t)(i + 6) * nr] * x[i + 6];
+        a7 += cc[(int64_t)(i + 7) * nr] * x[i + 7];
+      }
+      for (; i < ic; ++i) a0 += cc[(int64_t)i * nr] * x[i];
+    }
     for (; i + 8 <= i1; i += 8) {
       a0 += col[(int64_t)i * lda] * x[i];
       a1 += col[(int64_t)(i + 1) * lda] * x[i + 1];
@@ -461,7 +486,7 @@ TLA_HD void colsum_rows(TM& tm, const double* A, int64_t lda, const double* x, i
 // its lanes over the columns (coalesced rows, eight loads in flight per lane), then a wave
 // sum per row; otherwise colsum_rows.
 template <class TM>
-TLA_HD void symv_rows(TM& tm, const double* M, int64_t ldm, const double* x, int n, int r0, int r1, double* y,
+TLA_HD TLA_INLINE void symv_rows(TM& tm, const double* M, int64_t ldm, const double* x, int n, int r0, int r1, double* y,
                       double* part, int64_t part_doubles) {
   if (tm.wsize != 64) {
     colsum_rows(tm, M, ldm, x, n, r0, r1, y, false, part, part_doubles);
@@ -498,39 +523,49 @@ TLA_HD void symv_rows(TM& tm, const double* M, int64_t ldm, const double* x, int
   tm.sync();
 }
 
-// h[i] = sum over the group's rows of Q[i*ldq + t] w[t], i < n (this group's share): a
-// wave per i, lanes over the rows.
+// h[i] = sum over the group's rows of Q[i*ldq + t] w[t], i < n (this group's share), and
+// with `self` also h[n] = the group's share of |w|^2: a wave (or half-wave) per i, lanes
+// over the rows.  Rows i < qcap of Q are read from the copy Qc (element (i, t) at
+// Qc[i*(r1 - r0) + t - r0]) instead.
 template <class TM>
-TLA_HD void dots_rows(TM& tm, const double* Q, int ldq, const double* w, int n, int r0, int r1, double* h) {
-  if (tm.wsize == 64 && r1 - r0 <= 32) {
+TLA_HD TLA_INLINE void dots_rows(TM& tm, const double* Q, int ldq, const double* w, int n, int r0, int r1, double* h,
+                      const double* Qc = nullptr, int qcap = 0, bool self = false) {
+  const int nr = r1 - r0, nd = n + (self ? 1 : 0);
+  if (Qc == nullptr) qcap = 0;
+  if (tm.wsize == 64 && nr <= 32) {
     // a half-wave per vector, lanes over the rows; four vectors' loads in flight per lane
     const int half = tm.lane >> 5, t = r0 + (tm.lane & 31);
     const bool rv = t < r1;
     const double wt = rv ? w[t] : 0.0;
     const int slots = 2 * tm.nwaves;
-    for (int i0 = 0; i0 < n; i0 += 4 * slots) {
+    for (int i0 = 0; i0 < nd; i0 += 4 * slots) {
       double v[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int i = i0 + u * slots + 2 * tm.wave + half;
-        v[u] = rv && i < n ? Q[(int64_t)i * ldq + t] * wt : 0.0;
+        double x = 0.0;
+        if (rv && i < n) x = i < qcap ? Qc[(int64_t)i * nr + (t - r0)] : Q[(int64_t)i * ldq + t];
+        else if (rv && i == n && self) x = wt;
+        v[u] = x * wt;
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         double lo, hi;
         tm.half_sums(v[u], lo, hi);
         const int ib = i0 + u * slots + 2 * tm.wave;
-        if (tm.lane == 0 && ib < n) h[ib] = lo;
-        if (tm.lane == 0 && ib + 1 < n) h[ib + 1] = hi;
+        if (tm.lane == 0 && ib < nd) h[ib] = lo;
+        if (tm.lane == 0 && ib + 1 < nd) h[ib + 1] = hi;
       }
     }
     tm.sync();
     return;
   }
-  for (int i = tm.wave; i < n; i += tm.nwaves) {
-    const double* qi = Q + (int64_t)i * ldq;
+  for (int i = tm.wave; i < nd; i += tm.nwaves) {
     double s = 0.0;
-    for (int t = r0 + tm.lane; t < r1; t += tm.wsize) s += qi[t] * w[t];
+    for (int t = r0 + tm.lane; t < r1; t += tm.wsize) {
+      const double x = i == n ? w[t] : (i < qcap ? Qc[(int64_t)i * nr + (t - r0)] : Q[(int64_t)i * ldq + t]);
+      s += x * w[t];
+    }
     s = tm.wave_sum(s);
     if (tm.lane == 0) h[i] = s;
   }
@@ -546,7 +581,7 @@ TLA_HD void dots_rows(TM& tm, const double* Q, int ldq, const double* w, int n, 
 // the Ritz vectors of T_J, element (i, c) at i*k + c).  Returns J, -1 on failure, -2 when
 // an exchange could not complete.
 template <class TM, class X>
-TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, double rtol, int Jmax,
+TLA_HD TLA_INLINE int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, double rtol, int Jmax,
                         double* Q, const LanczosWork& ws, double* evals, double* Z) {
   if (Jmax > N) Jmax = N;
   double* q = ws.q;
@@ -554,6 +589,18 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
   double* h = ws.h;
   const int r0 = xg.r0, r1 = xg.r1, ldq = la_ldq(N);
   const bool lead = xg.g == 0;
+  // the group's rows of the first qcap basis vectors are also kept in fast memory
+  // (element (i, t) at qc[i*(r1 - r0) + t - r0]); the products read them from there
+  double* qc = ws.qc;
+  int qcap = 0;
+  if (qc != nullptr && r1 > r0) {
+    const int64_t c = ws.qc_doubles / (r1 - r0);
+    qcap = c < Jmax + 1 ? (int)c : Jmax + 1;
+  }
+  auto store_q = [&](int i, int t, double v) {
+    Q[(int64_t)i * ldq + t] = v;
+    if (i < qcap) qc[(int64_t)i * (r1 - r0) + (t - r0)] = v;
+  };
   // q_0: every group forms the whole (deterministic) start vector
   {
     double s = 0.0;
@@ -565,7 +612,7 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
     const double inv = 1.0 / sqrt(s);
     for (int i = tm.tid; i < N; i += tm.nt) q[i] = lanczos_start(i, 0) * inv;
     // (recomputed rather than read back from q: another thread wrote q[i])
-    for (int i = r0 + tm.tid; i < r1; i += tm.nt) Q[i] = lanczos_start(i, 0) * inv;
+    for (int i = r0 + tm.tid; i < r1; i += tm.nt) store_q(0, i, lanczos_start(i, 0) * inv);
     tm.sync();
   }
   int J = 0;
@@ -575,10 +622,13 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
   int restarts = 0;
   // One classical Gram-Schmidt pass of w[rows] against the first n vectors; the
   // coefficients stay in h[0, n).
-  auto orth_pass = [&](int n) -> bool {
-    dots_rows(tm, Q, ldq, w, n, r0, r1, h);
+  // h[n - 1] is returned in *last (read before the pass's final synchronisation, so that
+  // the next writes of h cannot overtake it).
+  auto orth_pass = [&](int n, double* last) -> bool {
+    dots_rows(tm, Q, ldq, w, n, r0, r1, h, qc, qcap);
     if (!xg.exchange(tm, h, n, h, nullptr, nullptr)) return false;
-    colsum_rows(tm, Q, ldq, h, n, r0, r1, w, true, ws.fast, ws.fast_doubles, 8);
+    if (last != nullptr) *last = h[n - 1];
+    colsum_rows(tm, Q, ldq, h, n, r0, r1, w, true, ws.fast, ws.fast_doubles, 8, qc, qcap);
     return true;
   };
   // The squared norm of w and the whole of w, in every group
@@ -606,23 +656,20 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
     // w = M x over the group's rows
     symv_rows(tm, M, ldm, q, N, r0, r1, w, ws.fast, ws.fast_doubles);
     tm.tick(10);
-    if (!orth_pass(j + 1)) return -2;
-    double aj = h[j] - corr;
-    dots_rows(tm, Q, ldq, w, j + 1, r0, r1, h);
-    {
-      double s = 0.0;
-      for (int t = r0 + tm.tid; t < r1; t += tm.nt) s += w[t] * w[t];
-      s = tm.sum(s);
-      if (tm.tid == 0) h[j + 1] = s;
-    }
+    double h1j = 0.0;
+    if (!orth_pass(j + 1, &h1j)) return -2;
+    double aj = h1j - corr;
+    // second pass coefficients and the squared norm of w^ (h[j + 1])
+    dots_rows(tm, Q, ldq, w, j + 1, r0, r1, h, qc, qcap, true);
     if (!xg.exchange(tm, h, j + 2, h, w, q)) return -2;  // q <- w^ (every row)
     aj += h[j];
     corr = h[j];
-    double h2sq = 0.0;
-    for (int i = 0; i <= j; ++i) h2sq += h[i] * h[i];
+    double h2sq = 0.0;  // |h2|^2: lanes over the coefficients, the same bits in every wave
+    for (int i = tm.lane; i <= j; i += tm.wsize) h2sq += h[i] * h[i];
+    h2sq = tm.wave_sum(h2sq);
     const double nsq = h[j + 1] - h2sq;
     double nr = sqrt(nsq > 0.0 ? nsq : 0.0);
-    colsum_rows(tm, Q, ldq, h, j + 1, r0, r1, w, true, ws.fast, ws.fast_doubles, 8);
+    colsum_rows(tm, Q, ldq, h, j + 1, r0, r1, w, true, ws.fast, ws.fast_doubles, 8, qc, qcap);
     tm.tick(11);
     if (tm.tid == 0) {
       ws.alpha[j] = aj;  // the same value in every group
@@ -743,7 +790,7 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
         if (++restarts > Jmax) return -1;
         for (int t = r0 + tm.tid; t < r1; t += tm.nt) w[t] = lanczos_start(t, J + 17 * restarts);
         tm.sync();
-        if (!orth_pass(J) || !orth_pass(J)) return -2;
+        if (!orth_pass(J, nullptr) || !orth_pass(J, nullptr)) return -2;
         double n2 = 0.0;
         if (!gather_norm(&n2)) return -2;  // w: every row
         if (n2 <= 1e-8) return -1;
@@ -756,7 +803,7 @@ TLA_HD int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int N, int k, d
     }
     const double inv = 1.0 / nr;
     for (int t = tm.tid; t < N; t += tm.nt) q[t] *= inv;
-    for (int t = r0 + tm.tid; t < r1; t += tm.nt) Q[(int64_t)J * ldq + t] = w[t] * inv;
+    for (int t = r0 + tm.tid; t < r1; t += tm.nt) store_q(J, t, w[t] * inv);
     tm.sync();
     tm.tick(12);
   }
@@ -1257,7 +1304,7 @@ constexpr int kOk = 0, kDevice = 4, kRankDeficient = 5, kNumeric = 6;
 // mu[k] the eigenvalues and Z (J x k) the Ritz vectors of T_J (V = Q_J Z is formed by
 // ritz_rows).  Returns the status (the same in every group); *Jout = Krylov size.
 template <class TM, class X>
-TLA_HD int small_la_phase_a(TM& tm, X& xg, const double* Gr, int m, int k, double rtol, int Jmax,
+TLA_HD TLA_INLINE int small_la_phase_a(TM& tm, X& xg, const double* Gr, int m, int k, double rtol, int Jmax,
                             const SmallLAWork& ws, double* mu, double* Z, int* Jout) {
   const int N = m - 1;
   {

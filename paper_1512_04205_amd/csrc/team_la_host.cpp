@@ -55,9 +55,10 @@ struct HostGridX {
 
 // Per-group vectors of the Lanczos work (the device's LDS arrays).
 struct GroupVectors {
-  std::vector<double> q, w, h, alpha, beta, fast;
+  std::vector<double> q, w, h, alpha, beta, fast, qc;
   GroupVectors(int N, int k, int Jmax, int64_t fastd)
-      : q(N), w(N > 2 * k ? N : 2 * k), h(Jmax + 2), alpha(Jmax + 2), beta(Jmax + 2), fast(fastd) {}
+      : q(N), w(N > 2 * k ? N : 2 * k), h(Jmax + 2), alpha(Jmax + 2), beta(Jmax + 2), fast(fastd),
+        qc(kLaQCache) {}
 };
 
 }  // namespace
@@ -71,12 +72,12 @@ int team_small_la_host(const double* Gr, int m, int k, double rtol, int Jmax, do
   const SmallLALayout L = small_la_layout(N, k, Jmax);
   std::vector<double> scr((size_t)L.total);
   std::vector<int> flag(1);
-  const int64_t fastd = 15488;  // as the device's LDS region
+  const int64_t fastd = kLaFast;  // as the device's LDS regions
   double* sp = scr.data();
   auto work = [&](GroupVectors& v) {
     SmallLAWork ws;
     ws.lz = LanczosWork{v.q.data(), v.w.data(), v.h.data(), v.alpha.data(), v.beta.data(), sp + L.T,
-                        v.fast.data(), fastd};
+                        v.fast.data(), fastd, v.qc.data(), (int64_t)v.qc.size()};
     ws.Q = sp + L.Q;
     ws.V = sp + L.V;
     ws.Z = sp + L.Z;
