@@ -53,8 +53,9 @@ cdmd_status cdmd_dbg_team_small_la(const double* Gr, int32_t m, int32_t k, doubl
    (from the end of [0]), [3] eigenvalues of A~, [4] eigenvectors, [5] G, and of [0]:
    [6] waits at the exchanges between the row groups, [7] matrix-vector products, [8]
    Gram-Schmidt work, [9] norm and next vector, [10] multisection of the checks, [11]
-   tridiagonal inverse iteration, [12] hand-over of the Ritz vectors of T_J, [13] loads of
-   the exchanged shares; [14..15] unused.
+   the rest of the checks (closed-form test, tridiagonal inverse iteration), [12] hand-over
+   of the Ritz vectors of T_J, [13] loads of the exchanged shares, [14] orthonormalisation
+   of the final Ritz vectors of T_J; [15] unused.
    Errors: INVALID_ARG. */
 cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms16);
 

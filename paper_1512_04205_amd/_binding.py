@@ -312,7 +312,7 @@ class Model:
         _check(load_library().cdmd_dbg_la_phases(self._h, _dptr(v)))
         return dict(zip(["lanczos", "checks", "atilde", "eigvals", "eigvecs", "G", "xchg_wait",
                          "matvec", "orth", "step_rest", "multisection", "tri_vectors", "ritz_QZ",
-                         "xchg_read"], v[:14]))
+                         "xchg_read", "final_vectors"], v[:15]))
 
     def set_timing(self, enable: bool = True):
         _check(load_library().cdmd_set_timing(self._h, int(enable)))

@@ -577,7 +577,8 @@ cdmd_status take_device_la(cdmd_model* M) {
   for (int64_t e = 0; e < (int64_t)N * k; ++e) M->G[e] = cplx(o[L.G + 2 * e], o[L.G + 2 * e + 1]);
   // phase times in ms (wall clock at 100 MHz): lanczos incl. checks, of which the
   // tridiagonal checks, A~, eigenvalues, eigenvectors, G, operand write; Lanczos matvec,
-  // orthogonalisation, rest of the step (norm, check, next vector)
+  // orthogonalisation, rest of the step (norm, check, next vector), multisection, check
+  // vectors, Ritz vectors Q Z, exchange reads, final orthonormalisation
   const double* tt = o + L.timing;
   const double f = 1e-5;
   M->la_phase_ms[0] = (tt[3] - tt[2]) * f;
@@ -594,6 +595,7 @@ cdmd_status take_device_la(cdmd_model* M) {
   M->la_phase_ms[11] = tt[14] * f;
   M->la_phase_ms[12] = tt[15] * f;
   M->la_phase_ms[13] = tt[9] * f;
+  M->la_phase_ms[14] = tt[1] * f;
   return CDMD_OK;
 }
 

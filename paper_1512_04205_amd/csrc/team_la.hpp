@@ -239,14 +239,14 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
     const double th = theta[r];
     double* W = work + r;  // element (i, f) at W[(i*5 + f) * kk]
     const int64_t st = kk, ys = 5 * st;
-    // factor: pending row (p0, p1) at columns i, i+1
+    // factor: pending row (p0, p1) at columns i, i+1; the pivots are kept as reciprocals
     double p0 = a[0] - th, p1 = J > 1 ? b[0] : 0.0;
     for (int i = 0; i + 1 < J; ++i) {
       const double bi = b[i], dn = a[i + 1] - th, bn = i + 2 < J ? b[i + 1] : 0.0;
       double* w = W + i * ys;
       if (fabs(bi) > fabs(p0)) {  // interchange rows i and i+1
-        const double l = p0 / bi;
-        w[0] = bi;
+        const double inv = 1.0 / bi, l = p0 * inv;
+        w[0] = inv;
         w[st] = dn;
         w[2 * st] = 1.0;
         w[3 * st] = l;
@@ -254,8 +254,8 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
         p1 = -l * bn;
       } else {
         if (fabs(p0) < tiny) p0 = p0 < 0.0 ? -tiny : tiny;
-        const double l = bi / p0;
-        w[0] = p0;
+        const double inv = 1.0 / p0, l = bi * inv;
+        w[0] = inv;
         w[st] = p1;
         w[2 * st] = 0.0;
         w[3 * st] = l;
@@ -264,12 +264,35 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
       }
     }
     if (fabs(p0) < tiny) p0 = p0 < 0.0 ? -tiny : tiny;
-    W[(J - 1) * ys] = p0;
+    W[(J - 1) * ys] = 1.0 / p0;
     double* y = W + 4 * st;  // y_i at y[i*ys]
     for (int i = 0; i < J; ++i) y[i * ys] = 1.0 + 0.5 * sin(1.7 * (i + 1) + 0.37 * r);
     for (int it = 0; it < 3; ++it) {
+      // forward (L, with the interchanges): four steps per round, their loads first (step
+      // i reads y_{i+1} before step i+1 overwrites it)
       double rp = y[0];
-      for (int i = 0; i + 1 < J; ++i) {
+      int i = 0;
+      for (; i + 4 < J; i += 4) {
+        double xn[4], lv[4], fv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const double* w = W + (i + u) * ys;
+          xn[u] = y[(i + u + 1) * ys];
+          lv[u] = w[3 * st];
+          fv[u] = w[2 * st];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          if (fv[u] != 0.0) {
+            y[(i + u) * ys] = xn[u];
+            rp -= lv[u] * xn[u];
+          } else {
+            y[(i + u) * ys] = rp;
+            rp = xn[u] - lv[u] * rp;
+          }
+        }
+      }
+      for (; i + 1 < J; ++i) {
         const double* w = W + i * ys;
         const double xn = y[(i + 1) * ys], l = w[3 * st];
         if (w[2 * st] != 0.0) {
@@ -280,12 +303,41 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
           rp = xn - l * rp;
         }
       }
-      y[(J - 1) * ys] = rp / W[(J - 1) * ys];
-      for (int i = J - 2; i >= 0; --i) {
+      // backward (U), y_{i+1} and y_{i+2} carried in registers
+      double y1 = rp * W[(J - 1) * ys], y2 = 0.0;
+      y[(J - 1) * ys] = y1;
+      i = J - 2;
+      for (; i >= 3; i -= 4) {
+        double yv[4], sv[4], fv[4], pv[4], bv[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ii = i - u;
+          const double* w = W + ii * ys;
+          yv[u] = y[ii * ys];
+          sv[u] = w[st];
+          fv[u] = w[2 * st];
+          pv[u] = w[0];
+          bv[u] = ii + 2 < J ? b[ii + 1] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int ii = i - u;
+          double v = yv[u] - sv[u] * y1;
+          if (fv[u] != 0.0 && ii + 2 < J) v -= bv[u] * y2;
+          v *= pv[u];
+          y[ii * ys] = v;
+          y2 = y1;
+          y1 = v;
+        }
+      }
+      for (; i >= 0; --i) {
         const double* w = W + i * ys;
-        double v = y[i * ys] - w[st] * y[(i + 1) * ys];
-        if (w[2 * st] != 0.0 && i + 2 < J) v -= b[i + 1] * y[(i + 2) * ys];
-        y[i * ys] = v / w[0];
+        double v = y[i * ys] - w[st] * y1;
+        if (w[2 * st] != 0.0 && i + 2 < J) v -= b[i + 1] * y2;
+        v *= w[0];
+        y[i * ys] = v;
+        y2 = y1;
+        y1 = v;
       }
       double big = 0.0;
       for (int i = 0; i < J; ++i) big = fmax(big, fabs(y[i * ys]));
@@ -774,7 +826,7 @@ TLA_HD TLA_INLINE int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int 
           // final Ritz vectors: members of eigenvalue clusters orthogonalised (kk = k)
           if (have_z) tridiag_orthonormalise(tm, J, kk, work, Zm);
           else tridiag_vectors(tm, ws.alpha, ws.beta, J, kk, theta, tnorm, true, work, Zm);
-          tm.tick(14);
+          tm.tick(1);
           for (int i = tm.tid; i < k; i += tm.nt) evals[i] = theta[i];
           for (int e = tm.tid; e < J * k; e += tm.nt) Z[e] = Zm[e];
           tm.sync();
@@ -812,22 +864,27 @@ TLA_HD TLA_INLINE int lanczos_topk(TM& tm, X& xg, const double* M, int ldm, int 
 
 // --------------------------------------------------------------------------- eig(A~)
 // Work: H (k*k), v (4), ev (2k doubles: re, im), status (int shared via scal[0]).
+// The reflector I - 2 v v^T / vv applied to rows r0..r0+len-1 (columns c0..c1) from the
+// left, then to those columns (rows rr0..rr1) from the right.  With zcol >= 0, the
+// entries of column zcol below row r0, which the reflector annihilates, are set to zero.
 template <class TM>
 TLA_HD void hess_reflect(TM& tm, double* H, int k, int r0, int len, const double* v, double vv,
-                         int c0, int c1, int rr0, int rr1) {
+                         int c0, int c1, int rr0, int rr1, int zcol = -1) {
+  const double tv = 2.0 / vv;
   // left: rows r0..r0+len-1, columns c0..c1
   for (int c = c0 + tm.tid; c <= c1; c += tm.nt) {
     double t = 0.0;
     for (int i = 0; i < len; ++i) t += v[i] * H[(r0 + i) * k + c];
-    const double f = 2.0 * t / vv;
-    for (int i = 0; i < len; ++i) H[(r0 + i) * k + c] -= f * v[i];
+    const double f = t * tv;
+    H[r0 * k + c] -= f * v[0];
+    for (int i = 1; i < len; ++i) H[(r0 + i) * k + c] = c == zcol ? 0.0 : H[(r0 + i) * k + c] - f * v[i];
   }
   tm.sync();
   // right: columns r0..r0+len-1, rows rr0..rr1
   for (int r = rr0 + tm.tid; r <= rr1; r += tm.nt) {
     double t = 0.0;
     for (int i = 0; i < len; ++i) t += H[r * k + r0 + i] * v[i];
-    const double f = 2.0 * t / vv;
+    const double f = t * tv;
     for (int i = 0; i < len; ++i) H[r * k + r0 + i] -= f * v[i];
   }
   tm.sync();
@@ -960,12 +1017,7 @@ TLA_HD bool eigvals_general(TM& tm, const double* A, int k, double* H, double* e
         const double vv = v[0] * v[0] + v[1] * v[1] + v[2] * v[2];
         const int c0 = kk - 1 > l ? kk - 1 : l;
         const int rr1 = kk + 3 < hi ? kk + 3 : hi;
-        hess_reflect(tm, H, k, kk, 3, v, vv, c0, hi, l, rr1);
-        if (kk > l && tm.tid == 0) {
-          H[(kk + 1) * k + kk - 1] = 0.0;
-          H[(kk + 2) * k + kk - 1] = 0.0;
-        }
-        tm.sync();
+        hess_reflect(tm, H, k, kk, 3, v, vv, c0, hi, l, rr1, kk > l ? kk - 1 : -1);
       }
       x = H[(kk + 1) * k + kk];
       y = H[(kk + 2) * k + kk];
@@ -979,9 +1031,7 @@ TLA_HD bool eigvals_general(TM& tm, const double* A, int k, double* H, double* e
         v[1] = y;
         const double vv = v[0] * v[0] + v[1] * v[1];
         const int c0 = kk - 1 > l ? kk - 1 : l;
-        hess_reflect(tm, H, k, kk, 2, v, vv, c0, hi, l, hi);
-        if (kk > l && tm.tid == 0) H[(kk + 1) * k + kk - 1] = 0.0;
-        tm.sync();
+        hess_reflect(tm, H, k, kk, 2, v, vv, c0, hi, l, hi, kk > l ? kk - 1 : -1);
       }
     }
   }
