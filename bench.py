@@ -341,8 +341,9 @@ def main():
         S_n = inf["n_selected"]
         J = inf["lanczos_steps"]
         N = m - 1
-        # algorithmic work per launch: (bytes that must cross HBM, useful flops, flop peak)
-        fl_peak = PEAK["bf16"] if prec == "bf16" else PEAK["fp32"]
+        # algorithmic work per launch: (bytes that must cross HBM, useful flops, flop peak).
+        # The lift is Phi' = X' (V S^-1) (k real columns) with the fused Gram of [Phi' | x_1],
+        # on bf16 MFMA in both forms (the FP32 form splits V S^-1 into three bf16 terms).
         if gauss:
             sk_peak = PEAK["bf16"] if args.workload == "cfg3" else PEAK["fp32"]
             sk = (video_bytes + 4.0 * p * m, 2.0 * p * n * m, sk_peak)
@@ -351,7 +352,7 @@ def main():
         work = {
             "sketch": sk,
             "gram": (4.0 * p * m + 8.0 * m * m, 2.0 * p * m * m, PEAK["fp64"]),
-            "lift": (video_bytes, 4.0 * n * (m - 1) * k, fl_peak),
+            "lift": (video_bytes, 2.0 * n * (m - 1) * k + 2.0 * n * (k + 1) ** 2, PEAK["bf16"]),
             "recon": (2.0 * video_bytes + n * m / 8.0, 8.0 * n * m * S_n, PEAK["fp32"]),
             # the Lanczos workgroups, one per compute unit: their share of the float64 rate
             "lanczos": (8.0 * m * m, lanczos_flops(N, J), PEAK["fp64"] * la_groups(N) / 256.0),
@@ -368,7 +369,7 @@ def main():
             elif hb >= fb:
                 bound = "hbm"
             else:
-                bound = "mfma" if (q in ("lift", "sketch") and fpk >= PEAK["bf16"]) else "alu"
+                bound = "mfma" if (q in ("lift", "recon") or fpk >= PEAK["bf16"]) else "alu"
             kernels[q] = {"ms": round(avg[q], 4), "GB/s": round(gbs, 1), "TFLOP/s": round(tfs, 4),
                           "hbm_frac": round(hb, 4), "flop_frac": round(fb, 4), "bound": bound,
                           "bytes": byt, "flops": fl, "flop_peak": fpk}
