@@ -17,7 +17,8 @@ Background Modeling":
 * background L = Re(sum over selected modes b_p phi_p lambda_p^(t-1)) (Section 2.2,
   eq. (equ:DMDTerms) and its footnote on the real part);
 * sparsity-constrained amplitudes by orthogonal matching pursuit (Section 2.3,
-  eq. (eq:sparsecoding));
+  eq. (eq:sparsecoding)), on the full modes or, by Remark 3 of Section 3.2, on the
+  compressed modes Phi_Y = Y' V S^-1 W and the first compressed frame y_1;
 * foreground mask |x_jt - xhat_jt| > tau (Section 4, eq. (eq:thres));
 * recall, precision, F-measure (Section 4).
 
@@ -226,6 +227,23 @@ def fit(D: np.ndarray, scale: float, Yhat: np.ndarray, k: int, form_phi: bool = 
     nrm = np.linalg.norm(Phi, axis=0)
     o = canonical_order(lam, np.abs(b) * nrm)
     return Model(lam[o], W[:, o], s, V, At, G[:, o], Phi[:, o], b[o], nrm[o])
+
+
+def fit_compressed(Yhat: np.ndarray, k: int) -> Model:
+    """Algorithm 1 with the amplitudes of Remark 3 (Section 3.2): the compressed modes
+    Phi_Y = Y' V S^-1 W (the eigenvector matrix applied to the compressed snapshots) and
+    b = argmin ||y_1 - Phi_Y b|| with y_1 the first compressed frame (column 0 of the
+    sketch); the same OMP on (Phi_Y, y_1) gives the sparse amplitudes.  Modes in canonical
+    order by |b_j| ||phi_Y,j||; the returned Phi is Phi_Y (p x k), phi_norm its column
+    norms.  The full modes of the background are still X' G with the returned G."""
+    lam, W, s, V, At = reduced_operator(Yhat, k)
+    G = (V / s[None, :]) @ W
+    PhiY = Yhat[:, 1:] @ G
+    y1 = Yhat[:, 0].astype(np.complex128)
+    b = np.linalg.lstsq(PhiY, y1, rcond=None)[0]
+    nrm = np.linalg.norm(PhiY, axis=0)
+    o = canonical_order(lam, np.abs(b) * nrm)
+    return Model(lam[o], W[:, o], s, V, At, G[:, o], PhiY[:, o], b[o], nrm[o])
 
 
 # ---------------------------------------------------------------- exact DMD (pins)

@@ -207,6 +207,45 @@ def test_recovers_known_modes_lowrank_sparse_sketch():
     np.testing.assert_allclose(mdl.Phi[:, ri] * mdl.b[ri], cols[:, ci], atol=1e-9)
 
 
+# ------------------------------------------------------------------ Remark 3: compressed modes
+def test_compressed_amplitudes_identity_sketch_equal_full():
+    """With C = I (p = n, every pixel sampled once, sign +1) the compressed modes are the
+    full modes and y_1 = x_1, so Remark 3 changes nothing: same order, modes, amplitudes
+    and OMP support as the full fit."""
+    D, _, _ = lowrank_video(80, 20, 3, reals=(0.96,), seed=61)
+    D = D + 1e-3 * np.random.default_rng(1).normal(size=D.shape)
+    I = np.arange(80, dtype=np.int32)[:, None]
+    Y = R.sketch_sparse(D, 1.0, I, np.ones((80, 1), np.int8))[0]
+    full = R.fit(D, 1.0, Y, 9)
+    comp = R.fit_compressed(Y, 9)
+    np.testing.assert_allclose(comp.lam, full.lam, atol=1e-12)
+    np.testing.assert_allclose(comp.Phi, full.Phi, atol=1e-10)
+    np.testing.assert_allclose(comp.b, full.b, atol=1e-10)
+    Sf, bf = R.omp(full.Phi, D[0], 4)
+    Sc, bc = R.omp(comp.Phi, Y[:, 0], 4)
+    assert list(Sf) == list(Sc)
+    np.testing.assert_allclose(bc, bf, atol=1e-10)
+
+
+def test_compressed_modes_are_sketched_full_modes():
+    """Phi_Y = Y' V S^-1 W = C X' V S^-1 W = C Phi for the same V, S, W, and on exactly
+    DMD-representable data b_j phi_Y,j = C (b_j phi_j) for the generator's modes (the
+    sketch of a mode's contribution to x_1)."""
+    n, m = 3000, 40
+    D, lam_true, cols = lowrank_video(n, m, 4, reals=(0.95,), seed=41)
+    idx, sign = sv.sparse_table(n, 120, 32, seed=3)
+    C = dense_from_table(idx, sign, n)
+    Y = R.sketch_sparse(D, 1.0, idx, sign)[0]
+    r = len(lam_true)
+    comp = R.fit_compressed(Y, r)   # (its canonical order may differ from the full fit's)
+    ri, ci, err = match(comp.lam, lam_true)
+    assert err.max() < 1e-10
+    np.testing.assert_allclose(comp.Phi[:, ri] * comp.b[ri], C @ cols[:, ci], atol=1e-8)
+    # the compressed modes are C times the full modes built from the same G
+    Phi_full_same_G = D.T[:, 1:] @ comp.G
+    np.testing.assert_allclose(comp.Phi, C @ Phi_full_same_G, atol=1e-8)
+
+
 # ------------------------------------------------------------------ P7: invariances
 def test_invariance_to_sketch_scale():
     D, lam_true, _ = lowrank_video(500, 25, 2, seed=51)
