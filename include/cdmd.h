@@ -86,6 +86,13 @@ typedef enum {
                            accumulation (MFMA); sketch only */
 } cdmd_prec;
 
+/* Modes the amplitudes b and the selection are computed on. */
+typedef enum {
+  CDMD_AMP_FULL = 0,       /* the full modes Phi = X' V S^-1 W and x_1 (step 9) */
+  CDMD_AMP_COMPRESSED = 1  /* the compressed modes Phi_Y = Y' V S^-1 W and the first
+                              compressed frame y_1 (Remark 3, Section 3.2) */
+} cdmd_amp_space;
+
 typedef enum {
   CDMD_SEL_OMP = 0,        /* orthogonal matching pursuit with K atoms on x_1 */
   CDMD_SEL_ZERO_MODE = 1,  /* the mode with the smallest |log lambda| */
@@ -156,6 +163,21 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out);
    configuration).  Synchronises `stream`.  Errors: INVALID_ARG (NULL),
    RANK_DEFICIENT, NUMERIC, DEVICE. */
 cdmd_status cdmd_fit(cdmd_model* mdl, const void* d_video, void* stream);
+
+/* Remark 3 (Section 3.2): amplitudes and selection on the compressed modes instead of the
+   full modes.  space = CDMD_AMP_COMPRESSED: the next cdmd_fit computes no lift (the video
+   is read twice per fit: the sketch, then the background / mask); b = argmin ||y_1 -
+   Phi_Y b|| with Phi_Y = Y' V S^-1 W formed from the Gram of the sketch on the device,
+   the canonical order uses |b_j| ||phi_Y,j||, cdmd_modes' phi_norm returns ||phi_Y,j||,
+   and cdmd_select works on (Phi_Y, y_1) (x1_norm2 and omp_residual2 of cdmd_info then
+   refer to y_1).  The background and mask still use the full modes X' G_S.  d_phi of
+   cdmd_modes still gives the full modes.  CDMD_AMP_FULL (the default) restores step 9.
+   Takes effect at the next cdmd_fit (the model is marked unfitted).  Batches accept only
+   models on the full modes.
+   Errors: INVALID_ARG (NULL, unknown space), UNSUPPORTED (the model cannot use the device
+   small linear algebra; a fit of a video that cannot, e.g. float32 or unaligned frames,
+   also returns UNSUPPORTED), OUT_OF_MEMORY. */
+cdmd_status cdmd_set_amplitudes(cdmd_model* mdl, int32_t space);
 
 /* Results of the last fit, modes in canonical order (descending |b_j| ||phi_j||,
    conjugate partners with Im lambda > 0 first).  Each output is optional (NULL):

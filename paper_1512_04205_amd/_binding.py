@@ -22,6 +22,7 @@ U8, F32 = 0, 1
 SKETCH_GAUSSIAN, SKETCH_SPARSE, SKETCH_SPIXEL = 0, 1, 2
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
 SEL_OMP, SEL_ZERO_MODE, SEL_OMEGA, SEL_EXPLICIT, SEL_ALL = 0, 1, 2, 3, 4
+AMP_FULL, AMP_COMPRESSED = 0, 1
 
 _STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY", 4: "DEVICE",
                  5: "RANK_DEFICIENT", 6: "NUMERIC", 7: "STATE"}
@@ -29,7 +30,7 @@ _STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY"
 EXPORTED = [
     "cdmd_abi_version", "cdmd_last_error", "cdmd_create", "cdmd_fit", "cdmd_modes",
     "cdmd_select", "cdmd_background", "cdmd_foreground", "cdmd_get_sketch",
-    "cdmd_info_get", "cdmd_set_timing", "cdmd_free", "cdmd_dbg_force_valu_lift",
+    "cdmd_info_get", "cdmd_set_timing", "cdmd_set_amplitudes", "cdmd_free", "cdmd_dbg_force_valu_lift",
     "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases", "cdmd_dbg_la_groups",
     "cdmd_dbg_force_gather_sketch",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_forward",
@@ -101,6 +102,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_get_sketch.argtypes = [P, DP, ctypes.POINTER(I64)]
     lib.cdmd_info_get.argtypes = [P, ctypes.POINTER(Info)]
     lib.cdmd_set_timing.argtypes = [P, I32]
+    lib.cdmd_set_amplitudes.argtypes = [P, I32]
     lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
     lib.cdmd_dbg_la_groups.argtypes = [P, I32]
@@ -316,6 +318,11 @@ class Model:
 
     def set_timing(self, enable: bool = True):
         _check(load_library().cdmd_set_timing(self._h, int(enable)))
+
+    def set_amplitudes(self, space: int):
+        """AMP_FULL (step 9) or AMP_COMPRESSED (Remark 3: amplitudes and selection on the
+        compressed modes; the next fit computes no lift)."""
+        _check(load_library().cdmd_set_amplitudes(self._h, int(space)))
 
     def info(self) -> dict:
         inf = Info()

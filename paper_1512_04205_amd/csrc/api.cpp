@@ -158,6 +158,11 @@ struct cdmd_model {
   double* h_la_out = nullptr;
   int64_t la_out_n = 0;
   hipEvent_t ev[8] = {};
+  // amplitudes and selection on the compressed modes (Remark 3): no lift in the fit
+  bool amp_compressed = false;
+  double* d_py = nullptr;   // k_la_py block partials, then their sum
+  double* d_pyred = nullptr;
+  double* h_py = nullptr;
 
   bool capturing = false;         // inside a graph capture: no timing events
   bool force_gather_sketch = false;  // test hook: gather form of the sparse sketch
@@ -180,10 +185,10 @@ struct cdmd_model {
     void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart, d_chunk_off, d_rblk,
                    d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts, d_modes,
                    d_feats, d_logits,
-                   d_la_scratch, d_la_out};
+                   d_la_scratch, d_la_out, d_py, d_pyred};
     for (void* q : dev)
       if (q) (void)hipFree(q);
-    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gsp, h_Vc, h_counts, h_la_out};
+    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gsp, h_Vc, h_counts, h_la_out, h_py};
     for (void* q : host)
       if (q) (void)hipHostFree(q);
   }
@@ -744,8 +749,45 @@ void assemble_H_real(cdmd_model* M, std::vector<cplx>& H, std::vector<cplx>& cve
   M->x1n2 = P[(size_t)k * ne1 + k];
 }
 
+// Remark 3: H = Phi_Y^H Phi_Y, c = Phi_Y^H y_1 and ||y_1||^2 for the compressed modes
+// Phi_Y = Y' B W (B the normalised real basis, G = B W), from the k_la_py sums of the
+// unscaled sketch: P = B^T Gr' B, q = B^T g0, g00 = Gr[0][0].  Phi_Y does not depend on
+// the scale of the sketch; y_1 scales with it.
+void assemble_H_compressed(cdmd_model* M, std::vector<cplx>& H, std::vector<cplx>& cvec) {
+  const int k = M->k;
+  const double* P = M->h_py;
+  const double* q = M->h_py + (size_t)k * k;
+  const double sc = M->sketch_scale;
+  const std::vector<cplx>& W = M->W;  // column j at j*k
+  std::vector<cplx> T((size_t)k * k);
+  for (int p2 = 0; p2 < k; ++p2)
+    for (int l = 0; l < k; ++l) {
+      cplx s = 0.0;
+      for (int q2 = 0; q2 < k; ++q2) s += P[(size_t)p2 * k + q2] * W[(size_t)l * k + q2];
+      T[(size_t)p2 * k + l] = s;
+    }
+  H.assign((size_t)k * k, 0.0);
+  cvec.assign(k, 0.0);
+  for (int j = 0; j < k; ++j) {
+    for (int l = j; l < k; ++l) {
+      cplx s = 0.0;
+      for (int p2 = 0; p2 < k; ++p2) s += std::conj(W[(size_t)j * k + p2]) * T[(size_t)p2 * k + l];
+      H[(size_t)j * k + l] = l == j ? cplx(s.real(), 0.0) : s;
+      H[(size_t)l * k + j] = l == j ? cplx(s.real(), 0.0) : std::conj(s);
+    }
+    cplx c = 0.0;
+    for (int p2 = 0; p2 < k; ++p2) c += std::conj(W[(size_t)j * k + p2]) * q[p2];
+    cvec[j] = c * sc;
+  }
+  M->x1n2 = M->h_py[(size_t)k * k + k] * sc * sc;
+}
+
 // H = Phi^H Phi, c = Phi^H x_1 from the real partial Gram of [Re Phi | Im Phi].
 void assemble_H(cdmd_model* M, std::vector<cplx>& H, std::vector<cplx>& cvec) {
+  if (M->amp_compressed && M->device_la) {
+    assemble_H_compressed(M, H, cvec);
+    return;
+  }
   if (M->lift_real) {
     assemble_H_real(M, H, cvec);
     return;
@@ -934,6 +976,37 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
   M->g_canonical_on_device = false;
   plan_fit(M, d_video);
   double t0 = now_ms(), t1, t2;
+  if (M->amp_compressed) {
+    if (!M->device_la)
+      return fail(CDMD_E_UNSUPPORTED, "amplitudes on the compressed modes need the device small linear algebra "
+                                      "(uint8 video with 16-byte aligned frames)");
+    // two passes over the video: the sketch here, the background / mask later; the
+    // solve, its tail and the compressed-mode Gram in order on the call's stream
+    TRY(run_sketch(M, d_video, st, false));
+    HIPCHK(cdmd::k::small_la_head(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
+                                  (double)M->xscale, M->d_la_scratch, M->d_la_out, M->d_Gp, M->lr_nb,
+                                  M->lm_nsplit, M->lm_nksteps, M->la_groups, st,
+                                  M->timing && !M->capturing ? M->ev[7] : nullptr));
+    TRY(enqueue_la_tail(M, st));
+    const int nblk = cdmd::k::small_la_py_blocks((int)M->m);
+    const int ne = M->k * M->k + M->k + 1;
+    HIPCHK(cdmd::k::small_la_py(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
+                                M->d_la_scratch, M->d_la_out, M->d_py, st));
+    HIPCHK(cdmd::k::reduce_partials(M->d_py, nblk, ne, M->d_pyred, st));
+    M->mark(3, st);
+    M->mark(4, st);
+    HIPCHK(hipMemcpyAsync(M->h_py, M->d_pyred, sizeof(double) * ne, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    if (M->timing) {
+      M->info.gpu_ms_lift = 0.0;
+      M->info.gpu_ms_sketch = M->span(0, 1);
+      M->info.gpu_ms_gram = M->span(1, 2);
+      M->info.ms_small_la = M->span(2, 3);
+      M->info.gpu_ms_lanczos = M->span(2, 7);
+    }
+    t1 = t2 = now_ms();
+    return post_fit(M, t0, t1, t2);
+  }
   if (M->device_la) {
     TRY(run_sketch(M, d_video, st, false));
     HIPCHK(cdmd::k::small_la_head(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
@@ -1237,6 +1310,8 @@ cdmd_status cdmd_batch_create(cdmd_model* const* models, int32_t n, cdmd_batch**
     if (!models[i]) return fail(CDMD_E_INVALID_ARG, "NULL model in the batch");
     for (int j = 0; j < i; ++j)
       if (models[j] == models[i]) return fail(CDMD_E_INVALID_ARG, "a model appears twice in the batch");
+    if (models[i]->amp_compressed)
+      return fail(CDMD_E_UNSUPPORTED, "batches fit on the full modes (cdmd_set_amplitudes FULL)");
   }
   std::unique_ptr<cdmd_batch> B(new (std::nothrow) cdmd_batch());
   if (!B) return fail(CDMD_E_OUT_OF_MEMORY, "host allocation failed");
@@ -1780,6 +1855,26 @@ cdmd_status cdmd_info_get(const cdmd_model* Mc, cdmd_info* info) {
     M->recon_pending = false;
   }
   *info = M->info;
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_set_amplitudes(cdmd_model* M, int32_t space) {
+  g_err.clear();
+  if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  if (space != CDMD_AMP_FULL && space != CDMD_AMP_COMPRESSED) return fail(CDMD_E_INVALID_ARG, "unknown amplitude space");
+  if (space == CDMD_AMP_COMPRESSED) {
+    if (!M->device_la_ok)
+      return fail(CDMD_E_UNSUPPORTED, "amplitudes on the compressed modes need the device small linear algebra");
+    const int ne = M->k * M->k + M->k + 1;
+    if (!M->d_py) {
+      TRY(dalloc(&M->d_py, (size_t)cdmd::k::small_la_py_blocks((int)M->m) * ne));
+      TRY(dalloc(&M->d_pyred, (size_t)ne));
+      TRY(halloc(&M->h_py, (size_t)ne));
+    }
+  }
+  M->amp_compressed = space == CDMD_AMP_COMPRESSED;
+  M->fitted = M->selected = false;
+  M->info.fitted = M->info.selected = 0;
   return CDMD_OK;
 }
 

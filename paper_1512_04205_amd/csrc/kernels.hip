@@ -1704,6 +1704,66 @@ hipError_t small_la_tail(const double* Gr, int m, int k, double rtol, int Jmax, 
   return launch_la_tail(d, nullptr, 1, m - 1, k, stream);
 }
 
+// Remark 3 (Section 3.2): the Gram of the compressed modes' real basis from the sketch
+// Gram, for rows [t0, t0 + 64) of the normalised basis B = V diag(1 / (nu s)) (the basis
+// of G = B W): R = Gr[1:m, 1:m] V over those rows (in the TV scratch, free after the
+// tail), then the block's shares of B^T Gr[1:m, 1:m] B (k x k, row-major) and of B^T g0
+// (g0[t] = Gr[(1+t) m], the products with the first frame), and in block 0 Gr[0][0].
+// part: [block][k^2 + k + 1].  Runs after the tail (it reads nu and s).
+__global__ __launch_bounds__(SLA_MM_NT) void k_la_py(SLADesc d, double* __restrict__ part) {
+  using namespace tla;
+  const int m = d.m, N = m - 1, k = d.k;
+  const int t0 = blockIdx.x * kLaRows;
+  const SmallLAOutLayout Lo = small_la_out_layout(N, k);
+  if (t0 >= N || d.out[Lo.status] != 0.0) return;  // uniform over the workgroup
+  __shared__ double s_red[SLA_MM_NT / 64];
+  __shared__ double s_stage[SLA_STAGE];
+  DevTeam tm;
+  la_team(tm, s_red, nullptr);
+  const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
+  const int t1 = t0 + kLaRows < N ? t0 + kLaRows : N;
+  const double* V = d.scratch + Ls.V;
+  double* R = d.scratch + Ls.TV;
+  const double* nu = d.scratch + Ls.nu;
+  const double* sv = nu + k;
+  if (k <= 64) {
+    // R(a, c) = sum_b Gr[(b+1) m + (a+1)] V(b, c): A(a, b) = (Gr + m + 1)[b m + a]
+    mfma_rows16(d.Gr + m + 1, m, V, 1, N, N, t0 + 16 * (threadIdx.x >> 6), N, k, R, N);
+    __syncthreads();
+  } else {
+    m12v_rows(tm, d.Gr + 1, m, N, k, V, R, t0, t1, s_stage, SLA_STAGE);
+    __syncthreads();
+  }
+  const int ne = k * k + k + 1;
+  double* out = part + (int64_t)blockIdx.x * ne;
+  for (int e = threadIdx.x; e < ne; e += blockDim.x) {
+    double acc = 0.0;
+    if (e < k * k) {
+      const int a = e / k, c = e % k;
+      for (int t = t0; t < t1; ++t) acc += V[(int64_t)a * N + t] * R[(int64_t)c * N + t];
+      acc /= nu[a] * sv[a] * nu[c] * sv[c];
+    } else if (e < k * k + k) {
+      const int a = e - k * k;
+      for (int t = t0; t < t1; ++t) acc += V[(int64_t)a * N + t] * d.Gr[(int64_t)(1 + t) * m];
+      acc /= nu[a] * sv[a];
+    } else if (blockIdx.x == 0) {
+      acc = d.Gr[0];
+    }
+    out[e] = acc;
+  }
+}
+
+hipError_t small_la_py(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
+                       double* scratch, double* out, double* part, hipStream_t stream) {
+  if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
+  const SLADesc d = la_desc_of(Gr, m, k, rtol, Jmax, sketch_scale, 1.0, scratch, out, nullptr, 1, 1, 1, 0);
+  const int nblk = (m - 1 + tla::kLaRows - 1) / tla::kLaRows;
+  hipLaunchKernelGGL(k_la_py, dim3(nblk), dim3(SLA_MM_NT), 0, stream, d, part);
+  return hipGetLastError();
+}
+
+int small_la_py_blocks(int m) { return (m - 1 + tla::kLaRows - 1) / tla::kLaRows; }
+
 hipError_t small_la_batch_head(const SLADesc* d_descs, int count, int nmax, int ngroups, hipStream_t stream) {
   if (count < 1) return hipSuccess;
   const SLADesc none{};
