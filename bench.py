@@ -7,7 +7,8 @@ Workload (default): 1920x1080 grayscale, m = 500 uint8 frames resident in HBM, s
 atoms, threshold tau = 0.1, bit-packed mask.  One step = one cdmd_fit + cdmd_select
 + cdmd_foreground over the whole video.  Prints one JSON line.
 
-    python bench.py [--steps K] [--warmup W] [--prec both|fp32|bf16] [--no-cpu-baseline]
+    python bench.py [--steps K] [--warmup W] [--prec both|fp32|bf16|fp32_compressed]
+                    [--no-cpu-baseline]
                     [--workload cfg2|cfg1|cfg3|cfg4] [--copy-ref-mib N]
 
 --workload cfg1 times the FP32 form of the dense Gaussian sketch on the 320x240x200
@@ -246,9 +247,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="cfg2", choices=sorted(WORKLOADS))
-    ap.add_argument("--prec", default="both", choices=["fp32", "bf16", "both"],
-                    help="lift/reconstruction form (cfg2); 'both' times FP32 (the reported value) "
-                         "and BF16 side by side")
+    ap.add_argument("--prec", default="both", choices=["fp32", "bf16", "fp32_compressed", "both"],
+                    help="lift/reconstruction form (cfg2); 'both' times FP32 (the reported value), "
+                         "BF16 and FP32 with the amplitudes on the compressed modes side by side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip cdmd_autotune before the warm-up (default tile shapes)")
@@ -296,6 +297,8 @@ def main():
     video_bytes = float(n) * m * (1 if u8 else 4)
 
     def run_form(prec: str):
+        # "fp32_compressed": the FP32 form with the amplitudes and the selection on the
+        # compressed modes (Remark 3: no lift in the fit)
         lp = P.PREC_BF16 if prec == "bf16" else P.PREC_FP32
         if gauss:
             sp = P.PREC_BF16 if args.workload == "cfg3" else P.PREC_FP32
@@ -305,6 +308,8 @@ def main():
             mdl = P.Model(n, m, k, p, sketch=P.SKETCH_SPARSE, dtype=P.U8, idx=idx, sign=sign,
                           lift_prec=lp)
         mdl.set_timing(True)
+        if prec == "fp32_compressed":
+            mdl.set_amplitudes(P.AMP_COMPRESSED)
         if not args.no_autotune:
             mdl.autotune(D)
             log(f"[{prec}] autotuned: lift workgroups {mdl.info()['lift_grid']}, sparse form "
@@ -361,6 +366,8 @@ def main():
         }
         kernels = {}
         for q, (byt, fl, fpk) in work.items():
+            if avg[q] <= 0.0:  # not run in this form (the lift of the compressed form)
+                continue
             sec = avg[q] / 1e3
             gbs, tfs = byt / sec / 1e9, fl / sec / 1e12
             hb, fb = gbs / PEAK["hbm"], tfs / fpk
@@ -380,7 +387,7 @@ def main():
                           "sketch_slices": inf["sketch_slices"]}}
 
     if args.workload == "cfg2":
-        forms = ["fp32", "bf16"] if args.prec == "both" else [args.prec]
+        forms = ["fp32", "bf16", "fp32_compressed"] if args.prec == "both" else [args.prec]
     else:
         forms = ["bf16"] if args.workload == "cfg3" else ["fp32"]
     res = {f: run_form(f) for f in forms}

@@ -53,7 +53,7 @@ extern "C" {
 typedef enum {
   CDMD_OK = 0,
   CDMD_E_INVALID_ARG = 1,     /* argument or configuration out of range */
-  CDMD_E_UNSUPPORTED = 2,     /* valid request this build does not implement */
+  CDMD_E_UNSUPPORTED = 2,     /* valid request the library does not implement */
   CDMD_E_OUT_OF_MEMORY = 3,   /* device or host allocation failed */
   CDMD_E_DEVICE = 4,          /* HIP runtime error, or no usable gfx950 device */
   CDMD_E_RANK_DEFICIENT = 5,  /* sigma_k <= 1e-6 sigma_1: the rank-k SVD is undefined */
