@@ -116,7 +116,10 @@ typedef struct {
   uint64_t seed;        /* Gaussian C */
   const int32_t* sparse_idx;  /* host, p*nnz row-major pixel indices in [0, n),
                                  distinct within a row (single-pixel: distinct over
-                                 all rows); required for SPARSE and SPIXEL */
+                                 all rows); required for SPARSE and SPIXEL.  SPARSE
+                                 only: -1 marks an empty slot, so rows may hold fewer
+                                 than nnz nonzeros (the i.i.d. very sparse C of Section
+                                 3.3); at least one slot must be used */
   const int8_t* sparse_sign;  /* host, p*nnz entries +1/-1 (NULL = all +1) */
 } cdmd_config;
 

@@ -75,18 +75,23 @@ def pixel_rows(D: np.ndarray, scale: float, i0: int = 0, i1: Optional[int] = Non
 # ---------------------------------------------------------------- sketches
 def sketch_sparse(D: np.ndarray, scale: float, idx: np.ndarray, sign: np.ndarray):
     """Y^ = C D for a sparse +/-1 (or single-pixel, weight +1) C given by its index
-    table idx (p, nnz) and signs (p, nnz).  Integer frames are summed exactly in
-    int64 before scaling.  Returns (Y^ float64 (p, m), integer sums or None)."""
+    table idx (p, nnz) and signs (p, nnz); index -1 marks an empty slot (rows of the
+    i.i.d. sparse C of Section 3.3 hold different numbers of nonzeros).  Integer frames
+    are summed exactly in int64 before scaling.  Returns (Y^ float64 (p, m), integer sums
+    or None)."""
     m, n = D.shape
     p, nnz = idx.shape
+    used = idx >= 0
+    safe = np.where(used, idx, 0)
+    w = np.where(used, sign, 0)
     if np.issubdtype(D.dtype, np.integer):
         acc = np.zeros((m, p), dtype=np.int64)
         for j in range(nnz):
-            acc += D[:, idx[:, j]].astype(np.int64) * sign[:, j].astype(np.int64)[None, :]
+            acc += D[:, safe[:, j]].astype(np.int64) * w[:, j].astype(np.int64)[None, :]
         return acc.T.astype(np.float64) * scale, acc.T.copy()
     acc = np.zeros((m, p), dtype=np.float64)
     for j in range(nnz):
-        acc += D[:, idx[:, j]].astype(np.float64) * sign[:, j].astype(np.float64)[None, :]
+        acc += D[:, safe[:, j]].astype(np.float64) * w[:, j].astype(np.float64)[None, :]
     return acc.T * scale, None
 
 

@@ -263,6 +263,7 @@ cdmd_status validate(const cdmd_config* c) {
     for (int64_t r = 0; r < p; ++r) {
       for (int64_t j = 0; j < z; ++j) {
         const int32_t v = c->sparse_idx[r * z + j];
+        if (v == -1 && c->sketch == CDMD_SKETCH_SPARSE) continue;  // empty slot of a shorter row
         if (v < 0 || (int64_t)v >= c->n) return fail(CDMD_E_INVALID_ARG, "sparse_idx out of range");
         if (c->sparse_sign) {
           const int8_t sg = c->sparse_sign[r * z + j];
@@ -275,6 +276,9 @@ cdmd_status validate(const cdmd_config* c) {
             return fail(CDMD_E_INVALID_ARG, "sparse_idx repeats a pixel within a row");
       }
     }
+    if (std::find_if(c->sparse_idx, c->sparse_idx + p * z, [](int32_t v) { return v >= 0; }) ==
+        c->sparse_idx + p * z)
+      return fail(CDMD_E_INVALID_ARG, "sparse table has no nonzeros");
     if (c->sketch == CDMD_SKETCH_SPIXEL) {
       std::vector<int32_t> s(c->sparse_idx, c->sparse_idx + p);
       std::sort(s.begin(), s.end());
@@ -322,12 +326,14 @@ cdmd_status build_sparse_plan(cdmd_model* M) {
   pix.reserve(T);
   rs.reserve(T);
   std::vector<std::pair<int32_t, uint32_t>> tri;
+  std::vector<int64_t> blk_base(nb), blk_cnt(nb);  // triples of each row block (empty slots skipped)
   for (int b = 0; b < nb; ++b) {
     const int r0 = b * max_rows, r1 = std::min(p, r0 + max_rows);
     tri.clear();
     for (int r = r0; r < r1; ++r)
       for (int j = 0; j < z; ++j) {
         const int32_t v = c.sparse_idx[(int64_t)r * z + j];
+        if (v < 0) continue;  // empty slot
         const bool neg = c.sparse_sign && c.sparse_sign[(int64_t)r * z + j] < 0;
         tri.emplace_back(v, (uint32_t)(r - r0) | (neg ? 0x80000000u : 0u));
       }
@@ -336,6 +342,8 @@ cdmd_status build_sparse_plan(cdmd_model* M) {
                        return a.first < b2.first;
                      });
     const int64_t base = (int64_t)pix.size(), cnt = (int64_t)tri.size();
+    blk_base[b] = base;
+    blk_cnt[b] = cnt;
     for (auto& t : tri) {
       pix.push_back(t.first);
       rs.push_back(t.second);
@@ -360,8 +368,7 @@ cdmd_status build_sparse_plan(cdmd_model* M) {
     const int r0 = b * max_rows, r1 = std::min(p, r0 + max_rows);
     rblk[2 * b] = r0;
     rblk[2 * b + 1] = r1 - r0;
-    const int64_t base = (int64_t)b * max_rows * z;  // row blocks are full except the last
-    const int64_t cnt = (int64_t)(r1 - r0) * z;
+    const int64_t base = blk_base[b], cnt = blk_cnt[b];
     int64_t e = base;
     for (int c = 0; c <= nchunk; ++c) {
       const int64_t lim = (int64_t)c * CH;

@@ -255,7 +255,9 @@ __global__ void k_sketch_sparse_f32(const float* __restrict__ D, int64_t ld, int
   const float* Dt = D + t * ld;
   double s = 0.0;
   for (int j = 0; j < nnz; ++j) {
-    const double v = (double)Dt[idx[(int64_t)r * nnz + j]];
+    const int32_t i = idx[(int64_t)r * nnz + j];
+    if (i < 0) continue;  // empty slot of a shorter row
+    const double v = (double)Dt[i];
     s += sign[(int64_t)r * nnz + j] < 0 ? -v : v;
   }
   Y[t * p + r] = s;

@@ -280,6 +280,29 @@ def sparse_table(n: int, p: int, nnz: int, seed: int) -> Tuple[np.ndarray, np.nd
     return idx.astype(np.int32), sign
 
 
+def iid_sparse_table(n: int, p: int, s: float, seed: int, width: int = 32) -> Tuple[np.ndarray, np.ndarray]:
+    """Very sparse random projection with i.i.d. entries: +1 and -1 with probability
+    1/(2s) each, 0 otherwise (s = n / ln n is the very sparse rate).  Drawn per row as a
+    Binomial(n, 1/s) count of distinct, uniformly placed pixels with Rademacher signs (the
+    same distribution).  Rows are padded with index -1 (sign +1) to the largest count.
+    Returns idx (p, w) int32 and sign (p, w) int8; ValueError if w exceeds ``width``."""
+    if not s >= 1.0:
+        raise ValueError("need s >= 1")
+    rng = np.random.default_rng(seed)
+    counts = rng.binomial(n, 1.0 / s, size=p)
+    w = max(1, int(counts.max()))
+    if w > width:
+        raise ValueError(f"a row holds {w} nonzeros, more than the table width {width}")
+    idx = np.full((p, w), -1, dtype=np.int32)
+    sign = np.ones((p, w), dtype=np.int8)
+    for r in range(p):
+        c = int(counts[r])
+        if c:
+            idx[r, :c] = rng.choice(n, size=c, replace=False)
+            sign[r, :c] = np.where(rng.integers(0, 2, size=c) == 1, 1, -1)
+    return idx, sign
+
+
 def single_pixel_table(n: int, p: int, seed: int) -> Tuple[np.ndarray, np.ndarray]:
     """Single-pixel measurements C = R: p distinct pixels (rows of the identity drawn
     without replacement), weight +1.  Returns idx (p, 1) int32, sign (p, 1) int8."""

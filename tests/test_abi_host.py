@@ -70,6 +70,10 @@ def _cfg_kwargs(**kw):
     (dict(idx=None), P.E_INVALID_ARG),
     (dict(idx=np.full((50, 8), 1000, np.int32)), P.E_INVALID_ARG),     # out of range
     (dict(idx=np.zeros((50, 8), np.int32)), P.E_INVALID_ARG),          # repeats in a row
+    (dict(idx=np.full((50, 8), -1, np.int32)), P.E_INVALID_ARG),       # no nonzeros at all
+    (dict(idx=np.full((50, 8), -2, np.int32)), P.E_INVALID_ARG),       # only -1 marks empty
+    (dict(sketch=P.SKETCH_SPIXEL, idx=np.full((50, 1), -1, np.int32),
+          sign=np.ones((50, 1), np.int8)), P.E_INVALID_ARG),           # no empty single-pixel rows
     (dict(sign=np.full((50, 8), 2, np.int8)), P.E_INVALID_ARG),
     (dict(sketch=P.SKETCH_SPIXEL), P.E_INVALID_ARG),                  # nnz != 1
     (dict(sketch=P.SKETCH_SPIXEL, idx=np.zeros((50, 1), np.int32),
@@ -91,6 +95,12 @@ def test_validation_errors(kw, status):
 def test_valid_config_without_device_reports_device_error():
     with pytest.raises(P.CdmdError) as e:
         P.Model(**_cfg_kwargs())
+    assert e.value.status == P.E_DEVICE
+    # an i.i.d. very sparse table (rows padded with -1) passes validation
+    idx, sign = sv.iid_sparse_table(1000, 50, 1000 / np.log(1000), seed=2)
+    assert (idx < 0).any()
+    with pytest.raises(P.CdmdError) as e:
+        P.Model(**_cfg_kwargs(idx=idx, sign=sign))
     assert e.value.status == P.E_DEVICE
 
 

@@ -56,7 +56,9 @@ def match(a, b):
 def dense_from_table(idx, sign, n):
     C = np.zeros((idx.shape[0], n))
     for r in range(idx.shape[0]):
-        C[r, idx[r]] = sign[r]
+        for j in range(idx.shape[1]):
+            if idx[r, j] >= 0:
+                C[r, idx[r, j]] = sign[r, j]
     return C
 
 
@@ -118,6 +120,28 @@ def test_sparse_sketch_equals_dense_product():
     Yref = C @ D.T.astype(np.float64)
     np.testing.assert_array_equal(Yint, Yref.astype(np.int64))
     np.testing.assert_allclose(Y, Yref / 255, rtol=1e-15)
+
+
+def test_iid_sparse_sketch_equals_dense_product():
+    """The i.i.d. very sparse C of Section 3.3 (s = n / ln n, rows padded with -1): the
+    sketch is the explicit dense product, and the entries have the stated law (mean
+    nonzeros per row n/s, symmetric signs)."""
+    rng = np.random.default_rng(4)
+    n, m, p = 5000, 12, 400
+    D = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+    s = n / np.log(n)
+    idx, sign = sv.iid_sparse_table(n, p, s, seed=11)
+    assert (idx < 0).any() and (idx >= 0).sum(axis=1).min() >= 0
+    C = dense_from_table(idx, sign, n)
+    Yf, Yi = R.sketch_sparse(D, 1.0, idx, sign)
+    np.testing.assert_array_equal(Yi, (C @ D.T.astype(np.float64)).astype(np.int64))
+    nz = (idx >= 0).sum()
+    assert abs(nz / p - np.log(n)) < 5 * np.sqrt(np.log(n) / p)
+    sg = sign[idx >= 0]
+    assert abs((sg == 1).mean() - 0.5) < 5 * 0.5 / np.sqrt(nz)
+    for r in range(p):
+        row = idx[r][idx[r] >= 0]
+        assert len(np.unique(row)) == len(row)
 
 
 def test_gaussian_sketch_equals_dense_product():
