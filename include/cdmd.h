@@ -221,6 +221,17 @@ cdmd_status cdmd_foreground(const cdmd_model* mdl, const void* d_video, float ta
                             int32_t static_bg, int32_t bitpacked, void* d_mask,
                             int64_t* h_counts, void* stream);
 
+/* Post-processing of foreground masks (Section 4, the evaluation on the BMC videos: the
+   thresholded mask, then median filtered): 3x3 median of each of the m frames' binary
+   H x W masks (pixel i = y W + x), i.e. the majority of the nine neighbours, with rows and
+   columns beyond the border replicated from the edge.  Layout as cdmd_foreground writes
+   it: bitpacked = 1 uint32 words, frame t at t*ceil(HW/32); bitpacked = 0 one uint8 (0/1)
+   per pixel, frame t at t*HW.  d_in and d_out are device buffers that must not overlap.
+   Enqueued on `stream`.  Errors: INVALID_ARG (NULL, sizes, m > 65535, overlap),
+   UNSUPPORTED (H W >= 2^31), DEVICE. */
+cdmd_status cdmd_mask_median3(const void* d_in, void* d_out, int64_t H, int64_t W, int64_t m,
+                              int32_t bitpacked, void* stream);
+
 /* ---- tile shapes and batches ---------------------------------------------------------
    cdmd_autotune times candidate tile shapes of the model's size class on d_video (the
    number of persistent lift workgroups; for the dense Gaussian sketch the number of

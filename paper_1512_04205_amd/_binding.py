@@ -30,7 +30,8 @@ _STATUS_NAMES = {0: "OK", 1: "INVALID_ARG", 2: "UNSUPPORTED", 3: "OUT_OF_MEMORY"
 EXPORTED = [
     "cdmd_abi_version", "cdmd_last_error", "cdmd_create", "cdmd_fit", "cdmd_modes",
     "cdmd_select", "cdmd_background", "cdmd_foreground", "cdmd_get_sketch",
-    "cdmd_info_get", "cdmd_set_timing", "cdmd_set_amplitudes", "cdmd_free", "cdmd_dbg_force_valu_lift",
+    "cdmd_info_get", "cdmd_set_timing", "cdmd_set_amplitudes", "cdmd_mask_median3", "cdmd_free",
+    "cdmd_dbg_force_valu_lift",
     "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases", "cdmd_dbg_la_groups",
     "cdmd_dbg_force_gather_sketch",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_forward",
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_info_get.argtypes = [P, ctypes.POINTER(Info)]
     lib.cdmd_set_timing.argtypes = [P, I32]
     lib.cdmd_set_amplitudes.argtypes = [P, I32]
+    lib.cdmd_mask_median3.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, I32, P]
     lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
     lib.cdmd_dbg_la_groups.argtypes = [P, I32]
@@ -412,6 +414,16 @@ def mlp_forward(params, X, bf16: bool = False, stream=None):
     _check(load_library().cdmd_mlp_forward(_tensor_ptr(params, MLP_NPARAM), _tensor_ptr(X, 6 * n), n,
                                            int(bf16), _tensor_ptr(z, max(n, 1)), _stream(stream)))
     return z[:n]
+
+
+def mask_median3(mask_in, mask_out, H: int, W: int, bitpacked: bool = True, stream=None):
+    """3x3 median (majority, edges replicated) of every frame of a binary mask (cdmd_mask_median3):
+    (m, ceil(HW/32)) int32/uint32 words or (m, HW) uint8 device tensors."""
+    m = mask_in.shape[0]
+    if mask_out.shape != mask_in.shape or mask_out.dtype != mask_in.dtype:
+        raise ValueError("mask_out must match mask_in")
+    _check(load_library().cdmd_mask_median3(mask_in.data_ptr(), mask_out.data_ptr(), int(H), int(W), int(m),
+                                            int(bitpacked), _stream(stream)))
 
 
 def mask_words(n: int) -> int:

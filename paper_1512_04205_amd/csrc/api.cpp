@@ -1865,6 +1865,21 @@ cdmd_status cdmd_info_get(const cdmd_model* Mc, cdmd_info* info) {
   return CDMD_OK;
 }
 
+cdmd_status cdmd_mask_median3(const void* d_in, void* d_out, int64_t H, int64_t W, int64_t m, int32_t bitpacked,
+                              void* stream) {
+  g_err.clear();
+  if (!d_in || !d_out) return fail(CDMD_E_INVALID_ARG, "NULL mask");
+  if (H < 1 || W < 1 || m < 1 || m > 65535) return fail(CDMD_E_INVALID_ARG, "need H, W >= 1 and 1 <= m <= 65535");
+  if (H * W >= ((int64_t)1 << 31)) return fail(CDMD_E_UNSUPPORTED, "frames of 2^31 pixels or more are not built");
+  const int64_t n = H * W;
+  const int64_t bytes = m * (bitpacked ? 4 * ((n + 31) / 32) : n);
+  const char* a = static_cast<const char*>(d_in);
+  const char* b = static_cast<const char*>(d_out);
+  if (a < b + bytes && b < a + bytes) return fail(CDMD_E_INVALID_ARG, "input and output masks overlap");
+  HIPCHK(cdmd::k::mask_median3(d_in, d_out, H, W, m, bitpacked ? 1 : 0, as_stream(stream)));
+  return CDMD_OK;
+}
+
 cdmd_status cdmd_set_amplitudes(cdmd_model* M, int32_t space) {
   g_err.clear();
   if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");

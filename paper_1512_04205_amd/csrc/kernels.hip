@@ -1085,6 +1085,63 @@ hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* 
   return hipGetLastError();
 }
 
+// 3x3 median of a binary H x W mask (pixel i = y W + x of a frame): the majority of the
+// nine neighbours, rows and columns beyond the border replicated from the edge.
+__device__ __forceinline__ int median3_count(int64_t y, int64_t x, int64_t H, int64_t W, const uint32_t* words,
+                                             const uint8_t* bytes) {
+  int cnt = 0;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy) {
+    const int64_t yy = y + dy < 0 ? 0 : (y + dy >= H ? H - 1 : y + dy);
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) {
+      const int64_t xx = x + dx < 0 ? 0 : (x + dx >= W ? W - 1 : x + dx);
+      const int64_t j = yy * W + xx;
+      cnt += words != nullptr ? (int)((words[j >> 5] >> (j & 31)) & 1u) : (bytes[j] != 0 ? 1 : 0);
+    }
+  }
+  return cnt;
+}
+
+// bit-packed: a thread per output word (32 pixels) of frame blockIdx.y
+__global__ __launch_bounds__(256) void k_mask_median3_bits(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                           int64_t H, int64_t W, int64_t words) {
+  const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (w >= words) return;
+  const int64_t n = H * W, t = blockIdx.y;
+  const uint32_t* f = in + t * words;
+  uint32_t o = 0;
+  for (int b = 0; b < 32; ++b) {
+    const int64_t i = w * 32 + b;
+    if (i >= n) break;
+    if (median3_count(i / W, i % W, H, W, f, nullptr) >= 5) o |= 1u << b;
+  }
+  out[t * words + w] = o;
+}
+
+// uint8 (0/1): a thread per pixel of frame blockIdx.y
+__global__ __launch_bounds__(256) void k_mask_median3_u8(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
+                                                         int64_t H, int64_t W) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n = H * W, t = blockIdx.y;
+  if (i >= n) return;
+  out[t * n + i] = median3_count(i / W, i % W, H, W, nullptr, in + t * n) >= 5 ? 1 : 0;
+}
+
+hipError_t mask_median3(const void* in, void* out, int64_t H, int64_t W, int64_t m, int bitpacked,
+                        hipStream_t stream) {
+  const int64_t n = H * W;
+  if (bitpacked) {
+    const int64_t words = (n + 31) / 32;
+    hipLaunchKernelGGL(k_mask_median3_bits, dim3((unsigned)((words + 255) / 256), (unsigned)m), dim3(256), 0, stream,
+                       (const uint32_t*)in, (uint32_t*)out, H, W, words);
+  } else {
+    hipLaunchKernelGGL(k_mask_median3_u8, dim3((unsigned)((n + 255) / 256), (unsigned)m), dim3(256), 0, stream,
+                       (const uint8_t*)in, (uint8_t*)out, H, W);
+  }
+  return hipGetLastError();
+}
+
 
 // ============================================================================
 // small float64 linear algebra on the device: one 1024-thread workgroup runs

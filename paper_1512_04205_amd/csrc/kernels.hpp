@@ -127,6 +127,10 @@ hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gsp, float* Vc
 // counts[t] = number of set bits of frame t of a bit-packed mask
 hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* counts,
                        hipStream_t stream);
+// 3x3 median (majority, edges replicated) of m binary H x W masks, bit-packed (uint32
+// words, ceil(H W / 32) per frame) or uint8; in and out must not overlap.
+hipError_t mask_median3(const void* in, void* out, int64_t H, int64_t W, int64_t m, int bitpacked,
+                        hipStream_t stream);
 
 // ----- small float64 linear algebra on the device ---------------------------------
 // From the m x m Gram Gr of the unscaled sketch: out = [status, J, mu[k], sigma[k],

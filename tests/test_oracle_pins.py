@@ -371,6 +371,18 @@ def test_mask_strict_and_nan():
     assert list(R.foreground(np.array([0.25]), np.array([0.0]), 0.25)) == [False]
 
 
+def test_median3_equals_library_median_filter():
+    """The mask median filter against scipy's median filter (3x3 window within each
+    frame, border replicated), on masks of several densities and odd shapes."""
+    import scipy.ndimage
+    rng = np.random.default_rng(6)
+    for H, W, dens in ((7, 9, 0.5), (16, 33, 0.2), (1, 5, 0.6), (5, 1, 0.4)):
+        mk = rng.random((3, H * W)) < dens
+        want = scipy.ndimage.median_filter(mk.reshape(3, H, W).astype(np.uint8), size=(1, 3, 3),
+                                           mode="nearest").reshape(3, H * W).astype(bool)
+        np.testing.assert_array_equal(R.median3(mk, H, W), want)
+
+
 def test_prf_identities():
     gt = np.array([1, 1, 0, 0, 1], bool)
     assert R.prf(gt, gt) == (1.0, 1.0, 1.0)
