@@ -987,22 +987,26 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
     if (!M->device_la)
       return fail(CDMD_E_UNSUPPORTED, "amplitudes on the compressed modes need the device small linear algebra "
                                       "(uint8 video with 16-byte aligned frames)");
-    // two passes over the video: the sketch here, the background / mask later; the
-    // solve, its tail and the compressed-mode Gram in order on the call's stream
+    // two passes over the video: the sketch here, the background / mask later; after the
+    // solve's head, the compressed-mode Gram on the call's stream beside the tail
     TRY(run_sketch(M, d_video, st, false));
     HIPCHK(cdmd::k::small_la_head(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
                                   (double)M->xscale, M->d_la_scratch, M->d_la_out, M->d_Gp, M->lr_nb,
                                   M->lm_nsplit, M->lm_nksteps, M->la_groups, st,
                                   M->timing && !M->capturing ? M->ev[7] : nullptr));
-    TRY(enqueue_la_tail(M, st));
+    HIPCHK(hipEventRecord(M->e_fork, st));
+    HIPCHK(hipStreamWaitEvent(M->st2, M->e_fork, 0));
+    TRY(enqueue_la_tail(M, M->st2));
+    HIPCHK(hipEventRecord(M->e_join, M->st2));
     const int nblk = cdmd::k::small_la_py_blocks((int)M->m);
     const int ne = M->k * M->k + M->k + 1;
     HIPCHK(cdmd::k::small_la_py(M->d_gram, (int)M->m, M->k, kLanczosTol, M->la_jmax, M->sketch_scale,
                                 M->d_la_scratch, M->d_la_out, M->d_py, st));
     HIPCHK(cdmd::k::reduce_partials(M->d_py, nblk, ne, M->d_pyred, st));
+    HIPCHK(hipMemcpyAsync(M->h_py, M->d_pyred, sizeof(double) * ne, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamWaitEvent(st, M->e_join, 0));
     M->mark(3, st);
     M->mark(4, st);
-    HIPCHK(hipMemcpyAsync(M->h_py, M->d_pyred, sizeof(double) * ne, hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
     if (M->timing) {
       M->info.gpu_ms_lift = 0.0;

@@ -1765,10 +1765,13 @@ hipError_t small_la_tail(const double* Gr, int m, int k, double rtol, int Jmax, 
 
 // Remark 3 (Section 3.2): the Gram of the compressed modes' real basis from the sketch
 // Gram, for rows [t0, t0 + 64) of the normalised basis B = V diag(1 / (nu s)) (the basis
-// of G = B W): R = Gr[1:m, 1:m] V over those rows (in the TV scratch, free after the
-// tail), then the block's shares of B^T Gr[1:m, 1:m] B (k x k, row-major) and of B^T g0
+// of G = B W): R = Gr[1:m, 1:m] V over those rows (in the TV scratch, free once the head
+// has run), then the block's shares of B^T Gr[1:m, 1:m] B (k x k, row-major) and of B^T g0
 // (g0[t] = Gr[(1+t) m], the products with the first frame), and in block 0 Gr[0][0].
-// part: [block][k^2 + k + 1].  Runs after the tail (it reads nu and s).
+// part: [block][k^2 + k + 1].  Needs only the head: nu (the column norms of V) and s =
+// sqrt(mu) are formed here as the eigen-solve's first phase forms them, so this kernel
+// runs beside the tail.
+constexpr int SLA_PY_KMAX = 64;
 __global__ __launch_bounds__(SLA_MM_NT) void k_la_py(SLADesc d, double* __restrict__ part) {
   using namespace tla;
   const int m = d.m, N = m - 1, k = d.k;
@@ -1777,14 +1780,28 @@ __global__ __launch_bounds__(SLA_MM_NT) void k_la_py(SLADesc d, double* __restri
   if (t0 >= N || d.out[Lo.status] != 0.0) return;  // uniform over the workgroup
   __shared__ double s_red[SLA_MM_NT / 64];
   __shared__ double s_stage[SLA_STAGE];
+  __shared__ double s_ns[2 * SLA_PY_KMAX];
   DevTeam tm;
   la_team(tm, s_red, nullptr);
   const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
   const int t1 = t0 + kLaRows < N ? t0 + kLaRows : N;
   const double* V = d.scratch + Ls.V;
   double* R = d.scratch + Ls.TV;
-  const double* nu = d.scratch + Ls.nu;
-  const double* sv = nu + k;
+  {
+    const int nblk = (N + kLaRows - 1) / kLaRows;
+    const int64_t pe = (int64_t)k * k + k;
+    const double* Pp = d.scratch + Ls.P;
+    const double* mu = d.out + Lo.mu;
+    for (int i = threadIdx.x; i < k; i += blockDim.x) {
+      double q = 0.0;
+      for (int b = 0; b < nblk; ++b) q += Pp[b * pe + (int64_t)k * k + i];
+      s_ns[i] = sqrt(q);
+      s_ns[SLA_PY_KMAX + i] = sqrt(mu[i]);
+    }
+    __syncthreads();
+  }
+  const double* nu = s_ns;
+  const double* sv = s_ns + SLA_PY_KMAX;
   if (k <= 64) {
     // R(a, c) = sum_b Gr[(b+1) m + (a+1)] V(b, c): A(a, b) = (Gr + m + 1)[b m + a]
     mfma_rows16(d.Gr + m + 1, m, V, 1, N, N, t0 + 16 * (threadIdx.x >> 6), N, k, R, N);
@@ -1814,7 +1831,7 @@ __global__ __launch_bounds__(SLA_MM_NT) void k_la_py(SLADesc d, double* __restri
 
 hipError_t small_la_py(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
                        double* scratch, double* out, double* part, hipStream_t stream) {
-  if (!small_la_fits(m, k, Jmax)) return hipErrorInvalidValue;
+  if (!small_la_fits(m, k, Jmax) || k > SLA_PY_KMAX) return hipErrorInvalidValue;
   const SLADesc d = la_desc_of(Gr, m, k, rtol, Jmax, sketch_scale, 1.0, scratch, out, nullptr, 1, 1, 1, 0);
   const int nblk = (m - 1 + tla::kLaRows - 1) / tla::kLaRows;
   hipLaunchKernelGGL(k_la_py, dim3(nblk), dim3(SLA_MM_NT), 0, stream, d, part);

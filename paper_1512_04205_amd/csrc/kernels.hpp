@@ -152,9 +152,10 @@ hipError_t small_la_tail(const double* Gr, int m, int k, double rtol, int Jmax, 
                          double xscale, double* scratch, double* out, void* Gp, int NB, int NS, int KS,
                          int groups, hipStream_t stream);
 int64_t small_la_scratch_doubles(int m, int k, int Jmax);
-// After the tail: the compressed modes' Gram (Remark 3) from the sketch Gram, as block
-// partials part[small_la_py_blocks(m)][k^2 + k + 1] (k_la_py): B^T Gr' B (k x k), B^T g0
-// and Gr[0][0], with B = V diag(1/(nu s)) the normalised real basis of G = B W.
+// After the head (beside the tail): the compressed modes' Gram (Remark 3) from the sketch
+// Gram, as block partials part[small_la_py_blocks(m)][k^2 + k + 1] (k_la_py): B^T Gr' B
+// (k x k), B^T g0 and Gr[0][0], with B = V diag(1/(nu s)) the normalised real basis of
+// G = B W.  k <= 64.
 hipError_t small_la_py(const double* Gr, int m, int k, double rtol, int Jmax, double sketch_scale,
                        double* scratch, double* out, double* part, hipStream_t stream);
 int small_la_py_blocks(int m);
