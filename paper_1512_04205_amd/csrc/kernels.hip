@@ -1468,25 +1468,24 @@ constexpr int SLA_MM_NT = 256;
 
 // out[c*ldo + r] = sum_{q < K} A(r, q) B(q, c) for rows r in [r0, r0 + 16) (< R) and
 // columns c < C (<= 64), with A(r, q) = pa[q*lda + r] and B(q, c) = pb[q*ldb + c*cstride].
-__device__ __forceinline__ void mfma_rows16(const double* __restrict__ pa, int64_t lda, const double* __restrict__ pb,
-                                            int64_t ldb, int64_t cstride, int K, int r0, int R, int C,
-                                            double* __restrict__ out, int64_t ldo) {
+// The same products over the inner indices q in [qb, qe) only (qb a multiple of 16),
+// added into acc (the caller zeroes it).
+__device__ __forceinline__ void mfma_rows16_acc(const double* __restrict__ pa, int64_t lda,
+                                                const double* __restrict__ pb, int64_t ldb, int64_t cstride,
+                                                int qb, int qe, int r0, int R, int C, f64x4_t (&acc)[4]) {
   const int l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
   const int CT = (C + 15) >> 4;
-  f64x4_t acc[4];
-#pragma unroll
-  for (int ct = 0; ct < 4; ++ct) acc[ct] = f64x4_t{0.0, 0.0, 0.0, 0.0};
   const int r = r0 + i;
-  for (int q0 = 0; q0 < K; q0 += 16) {
+  for (int q0 = qb; q0 < qe; q0 += 16) {
     double av[4], bv[4][4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
       const int q = q0 + 4 * u + kq;
-      av[u] = r < R && q < K ? pa[(int64_t)q * lda + r] : 0.0;
+      av[u] = r < R && q < qe ? pa[(int64_t)q * lda + r] : 0.0;
 #pragma unroll
       for (int ct = 0; ct < 4; ++ct) {
         const int c = 16 * ct + i;
-        bv[u][ct] = ct < CT && q < K && c < C ? pb[(int64_t)q * ldb + (int64_t)c * cstride] : 0.0;
+        bv[u][ct] = ct < CT && q < qe && c < C ? pb[(int64_t)q * ldb + (int64_t)c * cstride] : 0.0;
       }
     }
 #pragma unroll
@@ -1495,6 +1494,17 @@ __device__ __forceinline__ void mfma_rows16(const double* __restrict__ pa, int64
       for (int ct = 0; ct < 4; ++ct)
         if (ct < CT) acc[ct] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[u], bv[u][ct], acc[ct], 0, 0, 0);
   }
+}
+
+__device__ __forceinline__ void mfma_rows16(const double* __restrict__ pa, int64_t lda, const double* __restrict__ pb,
+                                            int64_t ldb, int64_t cstride, int K, int r0, int R, int C,
+                                            double* __restrict__ out, int64_t ldo) {
+  const int l = threadIdx.x & 63, i = l & 15, kq = l >> 4;
+  const int CT = (C + 15) >> 4;
+  f64x4_t acc[4];
+#pragma unroll
+  for (int ct = 0; ct < 4; ++ct) acc[ct] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+  mfma_rows16_acc(pa, lda, pb, ldb, cstride, 0, K, r0, R, C, acc);
 #pragma unroll
   for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
@@ -1528,14 +1538,17 @@ __global__ __launch_bounds__(SLA_MM_NT) void k_la_ritz(SLADesc d1, const SLADesc
 }
 
 // TV = M12 V over the workgroup's rows, and the block's partials of V^T TV and |v_i|^2.
-__global__ __launch_bounds__(SLA_MM_NT) void k_la_tv(SLADesc d1, const SLADesc* __restrict__ ds) {
+// TV = M12 V: 8 waves, the inner index (length N) split in two halves between waves
+// 0-3 and 4-7 (each wave 16 rows), the halves added in that order through LDS.
+constexpr int SLA_TV_NT = 512;
+__global__ __launch_bounds__(SLA_TV_NT) void k_la_tv(SLADesc d1, const SLADesc* __restrict__ ds) {
   using namespace tla;
   const SLADesc& d = la_desc(d1, ds, blockIdx.y);
   const int m = d.m, N = m - 1, k = d.k;
   const int t0 = blockIdx.x * kLaRows;
   const SmallLAOutLayout Lo = small_la_out_layout(N, k);
   if (t0 >= N || d.out[Lo.status] != 0.0) return;
-  __shared__ double s_red[SLA_MM_NT / 64];
+  __shared__ double s_red[SLA_TV_NT / 64];
   __shared__ double s_stage[SLA_STAGE];
   DevTeam tm;
   la_team(tm, s_red, nullptr);
@@ -1546,7 +1559,31 @@ __global__ __launch_bounds__(SLA_MM_NT) void k_la_tv(SLADesc d1, const SLADesc* 
   if (k <= 64) {
     // TV(a, c) = sum_b M12(a, b) V(b, c) with M12(a, b) = Gram[(b+1)*m + a] (symmetric):
     // A(a, b) = Gr[(b+1)*m + a], B(b, c) = V[c*N + b]
-    mfma_rows16(d.Gr + m, m, V, 1, N, N, t0 + 16 * (threadIdx.x >> 6), N, k, TV, N);
+    const int w = threadIdx.x >> 6, rg = w & 3, half = w >> 2, l = threadIdx.x & 63;
+    const int Kh = ((N + 31) / 32) * 16;  // first half [0, Kh), a multiple of 16
+    const int rw = t0 + 16 * rg;
+    f64x4_t acc[4];
+#pragma unroll
+    for (int ct = 0; ct < 4; ++ct) acc[ct] = f64x4_t{0.0, 0.0, 0.0, 0.0};
+    mfma_rows16_acc(d.Gr + m, m, V, 1, N, half == 0 ? 0 : Kh, half == 0 ? (Kh < N ? Kh : N) : N, rw, N, k, acc);
+    // s_stage as the exchange: [rg][ct][rr][lane], 4 * 4 * 4 * 64 = 4096 doubles
+    if (half == 1)
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) s_stage[((rg * 4 + ct) * 4 + rr) * 64 + l] = acc[ct][rr];
+    __syncthreads();
+    if (half == 0) {
+      const int i = l & 15, kq = l >> 4, CT = (k + 15) >> 4;
+#pragma unroll
+      for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+        for (int rr = 0; rr < 4; ++rr) {
+          const int ro = rw + 4 * rr + kq, c = 16 * ct + i;
+          if (ct < CT && ro < N && c < k)
+            TV[(int64_t)c * N + ro] = acc[ct][rr] + s_stage[((rg * 4 + ct) * 4 + rr) * 64 + l];
+        }
+    }
     __syncthreads();
   } else {
     m12v_rows(tm, d.Gr, m, N, k, V, TV, t0, t1, s_stage, SLA_STAGE);
@@ -1708,7 +1745,7 @@ static hipError_t launch_la_head(const SLADesc& d1, const SLADesc* ds, int count
   hipLaunchKernelGGL(k_la_a, dim3(ngroups, count), dim3(SLA_A_NT), 0, stream, d1, ds);
   if (after_lanczos != nullptr) (void)hipEventRecord(after_lanczos, stream);
   hipLaunchKernelGGL(k_la_ritz, dim3(rb, count), dim3(SLA_MM_NT), 0, stream, d1, ds);
-  hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_MM_NT), 0, stream, d1, ds);
+  hipLaunchKernelGGL(k_la_tv, dim3(rb, count), dim3(SLA_TV_NT), 0, stream, d1, ds);
   return hipGetLastError();
 }
 
