@@ -75,7 +75,7 @@ def cpu_baseline(D_dev, spec, k, p, nnz, K, tau, band_rows):
     b = np.linalg.lstsq(Phi, x1.astype(np.complex128), rcond=None)[0]
     t["lift_lstsq"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    S, beta = R.omp(Phi, x1, K)
+    S, beta = R.omp(Phi, x1, K, lam=lam)
     t["omp"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     m = D.shape[0]

@@ -6,7 +6,7 @@
  *
  *   cdmd_create      the parameters of Algorithm 1 (target rank k, samples p) and the
  *                    choice of measurement matrix C (Section 3.3); draws/prepares C.
- *   cdmd_fit         Algorithm 1 steps (1)-(9): sketch Y = C X, Y' = C X'
+ *   cdmd_fit         Algorithm 1 through the amplitudes: sketch Y = C X, Y' = C X'
  *                    (eq. (eq:YCX)), truncated SVD of Y, A~ = U* Y' V S^-1, eig(A~),
  *                    full modes Phi = X' V S^-1 W (eq. (Eq:cDMDModes)) and amplitudes
  *                    b = lstsq(Phi, x_1) (eq. (eq:b)).
@@ -88,7 +88,7 @@ typedef enum {
 
 /* Modes the amplitudes b and the selection are computed on. */
 typedef enum {
-  CDMD_AMP_FULL = 0,       /* the full modes Phi = X' V S^-1 W and x_1 (step 9) */
+  CDMD_AMP_FULL = 0,       /* the full modes Phi = X' V S^-1 W and x_1 (eq. (eq:b)) */
   CDMD_AMP_COMPRESSED = 1  /* the compressed modes Phi_Y = Y' V S^-1 W and the first
                               compressed frame y_1 (Remark 3, Section 3.2) */
 } cdmd_amp_space;
@@ -162,7 +162,7 @@ typedef struct {
    combination not built), DEVICE (no gfx950 device), OUT_OF_MEMORY. */
 cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out);
 
-/* Algorithm 1 steps (1)-(9) on the video d_video (device, layout above, dtype of the
+/* Algorithm 1 through the amplitudes on the video d_video (device, layout above, dtype of the
    configuration).  Synchronises `stream`.  Errors: INVALID_ARG (NULL),
    RANK_DEFICIENT, NUMERIC, DEVICE. */
 cdmd_status cdmd_fit(cdmd_model* mdl, const void* d_video, void* stream);
@@ -174,7 +174,7 @@ cdmd_status cdmd_fit(cdmd_model* mdl, const void* d_video, void* stream);
    the canonical order uses |b_j| ||phi_Y,j||, cdmd_modes' phi_norm returns ||phi_Y,j||,
    and cdmd_select works on (Phi_Y, y_1) (x1_norm2 and omp_residual2 of cdmd_info then
    refer to y_1).  The background and mask still use the full modes X' G_S.  d_phi of
-   cdmd_modes still gives the full modes.  CDMD_AMP_FULL (the default) restores step 9.
+   cdmd_modes still gives the full modes.  CDMD_AMP_FULL (the default) restores eq. (eq:b) on the full modes.
    Takes effect at the next cdmd_fit (the model is marked unfitted).  Batches accept only
    models on the full modes.
    Errors: INVALID_ARG (NULL, unknown space), UNSUPPORTED (the model cannot use the device
@@ -265,8 +265,8 @@ void cdmd_batch_free(cdmd_batch* batch);
 /* ---- learned background selector -------------------------------------------------
    A 6-64-64-1 network with GELU activations (exact erf) maps per-mode features to the
    logit of "sparse coding selects this mode"; the paper suggests learning the background
-   amplitude profile instead of a fixed rule (discussion in Section "Sparsity-promoting
-   DMD").  Parameters: one flat float32 vector of CDMD_MLP_NPARAM numbers, W1 (64 x 6
+   amplitude profile instead of a fixed rule (Section 2.2, "DMD for Foreground/Background
+   Separation", its last paragraph).  Parameters: one flat float32 vector of CDMD_MLP_NPARAM numbers, W1 (64 x 6
    row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3.  Features of mode j (canonical
    order, k modes, m frames): |lambda_j|, |arg lambda_j|, log|b_j|, ||phi_j||,
    (1/m) sum_t |b_j|^2 |lambda_j|^{2t} ||phi_j||^2 / ||x_1||^2, j / k.

@@ -17,27 +17,29 @@ extern "C" {
 #endif
 
 /* Top-k eigenpairs of the symmetric n x n matrix M (host, row-major) by Lanczos with
-   full reorthogonalisation (the route to the truncated SVD of Algorithm 1 step 4).
+   full reorthogonalisation (the route to the truncated SVD, eq. svd).
    evals[k] descending; evecs n x k column-major.  *steps = Krylov dimension used.
    Errors: INVALID_ARG, NUMERIC. */
 cdmd_status cdmd_dbg_sym_topk(const double* M, int32_t n, int32_t k, double rtol,
                               double* evals, double* evecs, int32_t* steps);
 
 /* Eigenvalues and unit eigenvectors of a real k x k matrix A (host, row-major)
-   (Algorithm 1 step 7).  lam[2k] (re, im); W[2k*k] column-major complex (re, im).
+   (Section 3.2).  lam[2k] (re, im); W[2k*k] column-major complex (re, im).
    Errors: INVALID_ARG, NUMERIC. */
 cdmd_status cdmd_dbg_eig_general(const double* A, int32_t k, double* lam, double* W);
 
-/* Orthogonal matching pursuit in coefficient space (Section 2.3) on H = Phi^H Phi
-   (k x k complex, row-major, re/im interleaved), c = Phi^H x_1 (k complex) and
-   x1n2 = ||x_1||^2.  S[k] receives the support in selection order, beta[2k] the
-   amplitudes, *ns = |S|, *resid2 = ||x_1 - Phi_S beta||^2.  Errors: INVALID_ARG,
-   NUMERIC. */
+/* Orthogonal matching pursuit in coefficient space (Section 2.3, eq. (eq:sparsecoding))
+   on H = Phi^H Phi (k x k complex, row-major, re/im interleaved), c = Phi^H x_1 (k
+   complex) for a real x_1, and x1n2 = ||x_1||^2.  lam (nullable; k complex, re/im
+   interleaved) gives the conjugate pairs: while the support is closed under conjugation
+   a pick of either member of an unselected pair goes to the one with Im lambda > 0.
+   S[k] receives the support in selection order, beta[2k] the amplitudes, *ns = |S|,
+   *resid2 = ||x_1 - Phi_S beta||^2.  Errors: INVALID_ARG, NUMERIC. */
 cdmd_status cdmd_dbg_omp_gram(const double* H, int32_t k, const double* c, double x1n2,
-                              int32_t K, int32_t* S, double* beta, int32_t* ns,
-                              double* resid2);
+                              int32_t K, const double* lam, int32_t* S, double* beta,
+                              int32_t* ns, double* resid2);
 
-/* The device small linear algebra (Algorithm 1 steps 4, 6, 7 and G = V S^-1 W from the
+/* The device small linear algebra (truncated SVD, A~, eig(A~) and G = V S^-1 W from the
    m x m Gram Gr of the unscaled sketch), run on the host with the same code the GPU runs:
    groups = 1 by one thread; groups = 2..32 with the Lanczos vectors split by rows over that
    many host threads, which exchange their shares as the GPU's workgroups do.  Outputs:

@@ -10,9 +10,11 @@ Background Modeling":
 * snapshot split X, X' (Section 2.1, eq. FullData);
 * sketch Y = C X, Y' = C X' (Section 3.2, eq. (eq:YCX)) with Gaussian, sparse +/-1
   or single-pixel C (Section 3.3);
-* truncated SVD of Y, A~ = U* Y' V S^-1, eig(A~) = (W, Lambda), full modes
-  Phi = X' V S^-1 W, amplitudes b = lstsq(Phi, x_1) (Section 3.2, Algorithm 1,
-  eq. (eq:b), eq. (Eq:cDMDModes));
+* the least-squares operator on the sketched snapshots, projected on the leading left
+  singular vectors: Y = U S V* truncated to rank k (eq. svd), A~ = U* Y' V S^-1 and its
+  eigenpairs A~ W = W Lambda (Section 3.2);
+* full modes Phi = X' V S^-1 W (eq. Eq:cDMDModes) and amplitudes b, the least-squares
+  fit of the first frame x_1 (Section 2.2, eq. (eq:b));
 * Vandermonde matrix lambda_j^(t-1) (Section 2.1, the factorisation Phi B V);
 * background L = Re(sum over selected modes b_p phi_p lambda_p^(t-1)) (Section 2.2,
   eq. (equ:DMDTerms) and its footnote on the real part);
@@ -43,10 +45,8 @@ from . import philox
 # rank test: sigma_k <= RANK_TOL * sigma_1 is rank deficient (the paper sets no
 # tolerance; 1e-6 is what a Gram-based route can still resolve in float64)
 RANK_TOL = 1e-6
-# ties in OMP correlations, relative: after a complete conjugate pair is selected the
-# residual of a real x_1 is real, so the two members of the next pair tie exactly;
-# 1e-6 keeps that tie visible through float32 rounding of Phi
-TIE_REL = 1e-6
+# conjugate partners: lambda_b = conj(lambda_a) to this relative distance
+PAIR_REL = 1e-12
 # OMP stops early when ||r|| <= OMP_STOP_REL * ||x_1||
 OMP_STOP_REL = 1e-12
 # |lambda|^(m-1) above this overflows the Vandermonde matrix
@@ -169,28 +169,42 @@ def normalise_eigvecs(W: np.ndarray) -> np.ndarray:
     return W * (np.abs(ph) / ph)[None, :]
 
 
-def canonical_order(lam: np.ndarray, key: np.ndarray) -> np.ndarray:
-    """Mode order: descending key = |b_j| * ||phi_j||.  The two members of a conjugate
-    pair (lambda_b equal to conj(lambda_a) to 1e-12) share one key, the larger of
-    their two, so they are always adjacent, and the member with Im lambda > 0 comes
-    first.  Remaining ties keep the eigensolver's order."""
+def conjugate_partners(lam: np.ndarray) -> np.ndarray:
+    """partner[a] = b when lambda_b is the conjugate of lambda_a (to PAIR_REL relative),
+    else -1.  Each lambda with Im > 0 is paired with the closest unpaired lambda with
+    Im < 0 that qualifies; real eigenvalues have no partner."""
     k = len(lam)
-    pk = np.array(key, dtype=np.float64)
-    used = np.zeros(k, dtype=bool)
+    partner = np.full(k, -1, dtype=np.int64)
     for a in range(k):
-        if lam[a].imag > 0 and not used[a]:
-            cand = [b for b in range(k) if lam[b].imag < 0 and not used[b]
-                    and abs(lam[b] - np.conj(lam[a])) <= 1e-12 * abs(lam[a])]
+        if lam[a].imag > 0 and partner[a] < 0:
+            cand = [b for b in range(k) if lam[b].imag < 0 and partner[b] < 0
+                    and abs(lam[b] - np.conj(lam[a])) <= PAIR_REL * abs(lam[a])]
             if cand:
                 b = min(cand, key=lambda q: abs(lam[q] - np.conj(lam[a])))
-                used[a] = used[b] = True
-                pk[a] = pk[b] = max(key[a], key[b])
+                partner[a], partner[b] = b, a
+    return partner
+
+
+def canonical_order(lam: np.ndarray, key: np.ndarray) -> np.ndarray:
+    """Mode order: descending key = |b_j| * ||phi_j||.  The two members of a conjugate
+    pair share one key, the larger of their two, so they are always adjacent, and the
+    member with Im lambda > 0 comes first.  Remaining ties keep the eigensolver's
+    order."""
+    k = len(lam)
+    partner = conjugate_partners(lam)
+    pk = np.array(key, dtype=np.float64)
+    for a in range(k):
+        if partner[a] >= 0:
+            pk[a] = max(key[a], key[partner[a]])
     return np.array(sorted(range(k), key=lambda j: (-pk[j], lam[j].imag <= 0, j)), dtype=np.int64)
 
 
 def reduced_operator(Yhat: np.ndarray, k: int):
-    """Algorithm 1 steps (1), (4), (6), (7) on the sketch: returns
-    (lam, W, sigma, V, Atilde).  Raises RankDeficient if sigma_k <= RANK_TOL sigma_1."""
+    """The rank-k reduced operator of the sketched snapshots (Section 3.2): with
+    Y = Y^[:, :m-1], Y' = Y^[:, 1:] (eq. (eq:YCX)) and the truncated SVD Y = U S V*
+    (eq. svd), A~ = U* Y' V S^-1 and its eigenpairs A~ W = W Lambda (unit-norm W,
+    normalised as in ``normalise_eigvecs``).  Returns (lam, W, sigma, V, Atilde).
+    Raises RankDeficient if sigma_k <= RANK_TOL sigma_1."""
     p, m = Yhat.shape
     if not (m >= 2 and 1 <= k <= min(p, m - 1)):
         raise ValueError("need m >= 2 and 1 <= k <= min(p, m-1)")
@@ -221,8 +235,9 @@ def lift(D: np.ndarray, scale: float, G: np.ndarray, pixels: Optional[np.ndarray
 
 
 def fit(D: np.ndarray, scale: float, Yhat: np.ndarray, k: int, form_phi: bool = True) -> Model:
-    """Algorithm 1 (cdmd) given the sketch Y^ = C D: SVD, A~, eig, Phi, b; modes in
-    canonical order."""
+    """Compressed DMD given the sketch Y^ = C D (Section 3.2, Algorithm 1): the reduced
+    operator and its eigenpairs, the full modes Phi = X' V S^-1 W (eq. Eq:cDMDModes) and
+    the amplitudes b = argmin ||Phi b - x_1|| (eq. (eq:b)); modes in canonical order."""
     lam, W, s, V, At = reduced_operator(Yhat, k)
     G = (V / s[None, :]) @ W
     if not form_phi:
@@ -273,15 +288,30 @@ def dmd_exact(x: np.ndarray, k: int):
 
 
 # ---------------------------------------------------------------- selection
-def omp(Phi: np.ndarray, x1: np.ndarray, K: int):
+def omp(Phi: np.ndarray, x1: np.ndarray, K: int, lam: Optional[np.ndarray] = None,
+        margins: Optional[list] = None):
     """Orthogonal matching pursuit for eq. (eq:sparsecoding), explicit residual form:
-    r = x_1; repeat: pick the unselected mode maximising |phi_j^H r| / ||phi_j||
-    (ties within TIE_REL of the maximum go to the lowest index), project x_1 onto the
-    selected modes by least squares, recompute r; stop after min(K, k) atoms or when
-    ||r|| <= OMP_STOP_REL ||x_1||.  Returns (support in selection order, beta_S)."""
+    r = x_1; repeat: pick the unselected mode maximising |phi_j^H r| / ||phi_j||,
+    project x_1 onto the selected modes by least squares, recompute r; stop after
+    min(K, k) atoms or when ||r|| <= OMP_STOP_REL ||x_1||.
+
+    Ties (reading of the paper, which is silent on them).  With a real x_1 and a support
+    that holds both members of every conjugate pair in it, the least-squares amplitudes
+    of a pair are conjugates, the residual is real, and the two members of any pair not
+    yet selected have equal correlations: |phi_b^H r| = |conj(phi_a)^H r| = |phi_a^H r|.
+    When ``lam`` is given (conjugate pairs by ``conjugate_partners``), such a pick goes to
+    the member with Im lambda > 0 whichever member rounding favours.  Any other exact
+    tie goes to the lowest index.
+
+    ``margins``, when a list, receives per pick the relative gap (best - next) / best
+    between the picked correlation and the best correlation outside the picked mode and
+    its tied partner: a small gap marks a near tie, on which a computation in another
+    precision may pick differently.  Returns (support in selection order, beta_S)."""
     n, k = Phi.shape
+    real_x = not np.iscomplexobj(x1) or not np.any(np.imag(x1))
     x1 = x1.astype(np.complex128)
     nrm = np.linalg.norm(Phi, axis=0)
+    partner = conjugate_partners(np.asarray(lam)) if lam is not None else np.full(k, -1)
     S: list = []
     beta = np.zeros(0, dtype=np.complex128)
     r = x1.copy()
@@ -289,8 +319,19 @@ def omp(Phi: np.ndarray, x1: np.ndarray, K: int):
     for _ in range(min(K, k)):
         corr = np.abs(Phi.conj().T @ r) / nrm
         corr[S] = -1.0
-        best = corr.max()
-        j = int(np.flatnonzero(corr >= best - TIE_REL * best)[0])
+        j = int(np.argmax(corr))
+        closed = all(partner[s] < 0 or partner[s] in S for s in S)
+        q = int(partner[j])
+        tied = real_x and closed and q >= 0 and q not in S
+        if tied and lam[q].imag > 0:
+            j, q = q, j
+        if margins is not None:
+            rest = corr.copy()
+            rest[j] = -1.0
+            if tied:
+                rest[q] = -1.0
+            top = corr[j] if corr[j] > 0 else 1.0
+            margins.append(float((corr[j] - rest.max()) / top) if rest.max() >= 0 else 1.0)
         S.append(j)
         beta = np.linalg.lstsq(Phi[:, S], x1, rcond=None)[0]
         r = x1 - Phi[:, S] @ beta
@@ -306,12 +347,16 @@ def select_zero_mode(lam: np.ndarray) -> np.ndarray:
 
 
 def select_omega(lam: np.ndarray, thr: float) -> np.ndarray:
-    """All modes with |log lambda_j| < thr (dt = 1)."""
+    """The modes whose continuous-time eigenvalue omega_j = log(lambda_j) / dt (Section
+    2.2, eq. omegaj; dt = 1, principal branch) lies strictly inside the disc |omega| < thr,
+    in index order.  Conjugate partners have conjugate omega and are kept or dropped
+    together."""
     return np.flatnonzero(np.abs(np.log(lam.astype(np.complex128))) < thr)
 
 
 def refit(Phi_S: np.ndarray, x1: np.ndarray) -> np.ndarray:
-    """Least-squares amplitudes of x_1 on a fixed support."""
+    """Amplitudes of x_1 on a fixed support: argmin over beta of ||x_1 - Phi_S beta||_2
+    (the least-squares problem of eq. (eq:b) restricted to the selected modes)."""
     return np.linalg.lstsq(Phi_S, x1.astype(np.complex128), rcond=None)[0]
 
 
@@ -394,7 +439,7 @@ def run(D: np.ndarray, scale: float, k: int, *, sketch: str, p: int = 0,
     mdl = fit(D, scale, Yhat, k)
     x1 = D[0].astype(np.float64) * scale
     if selector == "omp":
-        S, beta = omp(mdl.Phi, x1, K)
+        S, beta = omp(mdl.Phi, x1, K, lam=mdl.lam)
     elif selector == "zero_mode":
         S = select_zero_mode(mdl.lam)
         beta = mdl.b[S]

@@ -3,7 +3,7 @@ Adam.  TEST INFRASTRUCTURE ONLY (tests/, __graft_entry__.smoke(), bench.py's CPU
 baseline); the product path never imports anything under oracle/.
 
 The paper suggests learning the profile of background amplitudes instead of fixing a
-selection rule (Section "Sparsity-promoting DMD" discussion of background modes).  The
+selection rule (Section 2.2, "DMD for Foreground/Background Separation", its last paragraph).  The
 selector here predicts, per DMD mode, whether sparse coding (orthogonal matching pursuit
 on x_1, Algorithm 1's background selection) would pick it.
 

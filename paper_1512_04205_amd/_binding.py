@@ -322,7 +322,7 @@ class Model:
         _check(load_library().cdmd_set_timing(self._h, int(enable)))
 
     def set_amplitudes(self, space: int):
-        """AMP_FULL (step 9) or AMP_COMPRESSED (Remark 3: amplitudes and selection on the
+        """AMP_FULL (eq. (eq:b) on the full modes) or AMP_COMPRESSED (Remark 3: amplitudes and selection on the
         compressed modes; the next fit computes no lift)."""
         _check(load_library().cdmd_set_amplitudes(self._h, int(space)))
 

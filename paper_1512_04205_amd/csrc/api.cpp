@@ -44,7 +44,6 @@ cdmd_status fail(cdmd_status s, const std::string& msg) {
 
 // rank test on the Gram eigenvalues: sigma_k <= 1e-6 sigma_1  <=>  mu_k <= 1e-12 mu_1
 constexpr double kRankTol2 = 1e-12;
-constexpr double kTieRel = 1e-6;  // OMP correlation ties (relative)
 constexpr double kOmpStopRel = 1e-12;
 constexpr double kVanderMax = 1e30;
 constexpr double kLanczosTol = 1e-13;
@@ -421,21 +420,9 @@ void normalise_columns(std::vector<cplx>& W, int k) {
 std::vector<int> canonical_order(const std::vector<cplx>& lam, const std::vector<double>& key) {
   const int k = (int)lam.size();
   std::vector<double> pk(key);
-  std::vector<char> used(k, 0);
-  for (int a = 0; a < k; ++a) {
-    if (!(lam[a].imag() > 0.0) || used[a]) continue;
-    int best = -1;
-    double bd = 0.0;
-    for (int b = 0; b < k; ++b) {
-      if (!(lam[b].imag() < 0.0) || used[b]) continue;
-      const double d = std::abs(lam[b] - std::conj(lam[a]));
-      if (d <= 1e-12 * std::abs(lam[a]) && (best < 0 || d < bd)) best = b, bd = d;
-    }
-    if (best >= 0) {
-      used[a] = used[best] = 1;
-      pk[a] = pk[best] = std::max(key[a], key[best]);
-    }
-  }
+  const std::vector<int> partner = cdmd::la::conj_partners(lam.data(), k);
+  for (int a = 0; a < k; ++a)
+    if (partner[a] >= 0) pk[a] = std::max(key[a], key[partner[a]]);
   std::vector<int> o(k);
   std::iota(o.begin(), o.end(), 0);
   std::stable_sort(o.begin(), o.end(), [&](int a, int b) {
@@ -493,7 +480,7 @@ cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool 
   return CDMD_OK;
 }
 
-// Steps 4, 6, 7 and G = V S^-1 W on the host in float64.
+// Truncated SVD (eq. svd), A~ and eig(A~) (Section 3.2) and G = V S^-1 W on the host in float64.
 cdmd_status small_la(cdmd_model* M, std::vector<double>& V, std::vector<double>& mu) {
   const int N = M->N, k = M->k;
   const int64_t m = M->m;
@@ -1046,7 +1033,7 @@ cdmd_status cdmd_fit(cdmd_model* M, const void* d_video, void* stream) {
 }
 
 // Host part of a fit once its device results are in pinned memory: the device small-LA
-// results, H = Phi^H Phi and c, the amplitudes (step 9) and the canonical mode order.
+// results, H = Phi^H Phi and c, the amplitudes (eq. (eq:b)) and the canonical mode order.
 cdmd_status post_fit(cdmd_model* M, double t0, double t1, double t2) {
   if (M->device_la) TRY(take_device_la(M));
   double t3 = now_ms();
@@ -1498,7 +1485,7 @@ cdmd_status cdmd_select(cdmd_model* M, int32_t selector, int32_t K, double omega
   switch (selector) {
     case CDMD_SEL_OMP: {
       if (K < 1) return fail(CDMD_E_INVALID_ARG, "OMP needs K >= 1");
-      if (!cdmd::la::omp_gram(M->H.data(), k, M->c.data(), M->x1n2, K, kTieRel, kOmpStopRel, S, beta, &r2))
+      if (!cdmd::la::omp_gram(M->H.data(), k, M->c.data(), M->x1n2, K, M->lam.data(), kOmpStopRel, S, beta, &r2))
         return fail(CDMD_E_NUMERIC, "OMP subsystem singular");
       break;
     }
@@ -1992,14 +1979,14 @@ cdmd_status cdmd_dbg_eig_general(const double* A, int32_t k, double* lam, double
 }
 
 cdmd_status cdmd_dbg_omp_gram(const double* H, int32_t k, const double* c, double x1n2, int32_t K,
-                              int32_t* S, double* beta, int32_t* ns, double* resid2) {
+                              const double* lam, int32_t* S, double* beta, int32_t* ns, double* resid2) {
   g_err.clear();
   if (!H || !c || !S || !beta || !ns || k < 1 || K < 1) return fail(CDMD_E_INVALID_ARG, "bad arguments");
   std::vector<int> sv;
   std::vector<cplx> bv;
   double r2 = 0.0;
   if (!cdmd::la::omp_gram(reinterpret_cast<const cplx*>(H), k, reinterpret_cast<const cplx*>(c), x1n2, K,
-                          kTieRel, kOmpStopRel, sv, bv, &r2))
+                          reinterpret_cast<const cplx*>(lam), kOmpStopRel, sv, bv, &r2))
     return fail(CDMD_E_NUMERIC, "OMP subsystem singular");
   *ns = (int32_t)sv.size();
   for (size_t q = 0; q < sv.size(); ++q) {

@@ -1,10 +1,10 @@
 // HIP kernels of the cDMD hot path for gfx950 (CDNA4, wave64).
 //
-//   sketch  Y^ = C D         (Algorithm 1 step 3; sparse / single-pixel C of Section 3.3)
-//   Gram    Y^T Y            (route to the truncated SVD of step 4 and to A~ of step 6)
-//   lift    Phi = X' G       (step 8, eq. (Eq:cDMDModes), G = V S^-1 W) fused with the
+//   sketch  Y^ = C D         (eq. (eq:YCX); sparse / single-pixel C of Section 3.3)
+//   Gram    Y^T Y            (route to the truncated SVD, eq. svd, and to A~, Section 3.2)
+//   lift    Phi = X' G       (eq. (Eq:cDMDModes), G = V S^-1 W) fused with the
 //                            per-block partial sums of Phi^H Phi and Phi^H x_1 that the
-//                            amplitude least squares of step 9 / eq. (eq:b) needs
+//                            amplitude least squares of eq. (eq:b) needs
 //   bgfg    L = Re(Phi_S diag(beta) V_S) (eq. (equ:DMDTerms)) fused with the
 //           threshold |x - L| > tau (eq. (eq:thres)); Phi_S is recomputed from X' per
 //           pixel so the modes never travel through HBM.
@@ -1145,7 +1145,7 @@ hipError_t mask_median3(const void* in, void* out, int64_t H, int64_t W, int64_t
 
 // ============================================================================
 // small float64 linear algebra on the device: one 1024-thread workgroup runs
-// Algorithm 1 steps 4, 6, 7 and G = V S^-1 W (team_la.hpp), then writes the B operands
+// The truncated SVD, A~ and eig(A~) of Section 3.2 and G = V S^-1 W (team_la.hpp), then writes the B operands
 // of the lift (bf16 terms of G * xscale in MFMA order) so the fit needs no host round
 // trip between the Gram and the lift.
 template <int CTRL>

@@ -1,8 +1,8 @@
 // Learned background-mode selector: a 6-64-64-1 GELU network over per-mode features,
 // trained with binary cross-entropy and Adam on selections the method itself makes
 // (sparse coding), used in place of sparse coding when it is confident.  The paper
-// proposes learning the background amplitude profile (discussion of Section
-// "Sparsity-promoting DMD"); the network and features are this library's choice.
+// proposes learning the background amplitude profile (Section 2.2, "DMD for
+// Foreground/Background Separation", its last paragraph); the network and features are this library's choice.
 //
 // Layout: one flat float32 parameter vector, W1 (64 x 6 row-major), b1, W2 (64 x 64),
 // b2, w3 (64), b3 (4673 numbers).  A wave evaluates one sample with lane i holding

@@ -1,4 +1,4 @@
-// Dense Gaussian sketch Y^ = C X (Algorithm 1 step 1 with a Gaussian measurement matrix,
+// Dense Gaussian sketch Y^ = C X (Section 3.2, eq. (eq:YCX), with a Gaussian measurement matrix,
 // Section "Measurement Matrices"), C never stored: every entry is a pure function of
 // (seed, row, pixel), drawn by the workgroup that needs it.
 //

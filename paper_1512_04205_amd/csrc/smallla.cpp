@@ -437,32 +437,50 @@ bool herm_pd_solve(const cplx* H, int ldh, int n, const cplx* c, cplx* x) {
   return true;
 }
 
-bool omp_gram(const cplx* H, int k, const cplx* c, double x1n2, int K, double tie_rel,
+std::vector<int> conj_partners(const cplx* lam, int k) {
+  std::vector<int> partner(k, -1);
+  for (int a = 0; a < k; ++a) {
+    if (!(lam[a].imag() > 0.0) || partner[a] >= 0) continue;
+    int best = -1;
+    double bd = 0.0;
+    for (int b = 0; b < k; ++b) {
+      if (!(lam[b].imag() < 0.0) || partner[b] >= 0) continue;
+      const double d = std::abs(lam[b] - std::conj(lam[a]));
+      if (d <= 1e-12 * std::abs(lam[a]) && (best < 0 || d < bd)) best = b, bd = d;
+    }
+    if (best >= 0) partner[a] = best, partner[best] = a;
+  }
+  return partner;
+}
+
+bool omp_gram(const cplx* H, int k, const cplx* c, double x1n2, int K, const cplx* lam,
               double stop_rel, std::vector<int>& S, std::vector<cplx>& beta, double* resid2) {
   S.clear();
   beta.clear();
   std::vector<char> used(k, 0);
   std::vector<cplx> Hs, cs;
+  const std::vector<int> partner = lam ? conj_partners(lam, k) : std::vector<int>(k, -1);
   double r2 = x1n2;
   const int steps = std::min(K, k);
   for (int it = 0; it < steps; ++it) {
     // correlations alpha_j = c_j - sum_s H[j, S_s] beta_s, normalised by ||phi_j||
+    int pick = -1;
     double best = -1.0;
-    std::vector<double> corr(k, -1.0);
     for (int j = 0; j < k; ++j) {
       if (used[j]) continue;
       cplx a = c[j];
       for (size_t s = 0; s < S.size(); ++s) a -= H[(size_t)j * k + S[s]] * beta[s];
       const double hj = H[(size_t)j * k + j].real();
-      corr[j] = std::abs(a) / std::sqrt(std::max(hj, DBL_MIN));
-      best = std::max(best, corr[j]);
+      const double corr = std::abs(a) / std::sqrt(std::max(hj, DBL_MIN));
+      if (corr > best) best = corr, pick = j;
     }
-    int pick = -1;
-    for (int j = 0; j < k; ++j)
-      if (!used[j] && corr[j] >= best - tie_rel * best) {
-        pick = j;
-        break;
-      }
+    if (pick >= 0 && partner[pick] >= 0 && !used[partner[pick]]) {
+      bool closed = true;  // every selected pair member has its partner selected
+      for (int s : S)
+        if (partner[s] >= 0 && !used[partner[s]]) closed = false;
+      const int q = partner[pick];
+      if (closed && lam[q].imag() > 0.0) pick = q;
+    }
     if (pick < 0) break;
     used[pick] = 1;
     S.push_back(pick);

@@ -1,8 +1,8 @@
 // Small dense float64 linear algebra of the cDMD fit (host side).
 //
 // These are the k x k and (m-1) x (m-1) problems of Algorithm 1: the truncated SVD of
-// the sketch Y (step 4, computed as the top-k eigenpairs of the Gram Y^T Y), the
-// eigendecomposition of A~ (step 7), the amplitude least squares (step 9) and the
+// the sketch Y (eq. svd, computed as the top-k eigenpairs of the Gram Y^T Y), the
+// eigendecomposition of A~ (Section 3.2), the amplitude least squares (eq. (eq:b)) and the
 // sparsity-constrained amplitudes by orthogonal matching pursuit (Section 2.3).
 // All in float64 / complex<double>; none of it touches the video.
 #pragma once
@@ -47,13 +47,20 @@ bool herm_pd_solve(const cplx* H, int ldh, int n, const cplx* c, cplx* x);
 // Solve A x = c for general complex A (n x n row-major) by LU with partial pivoting.
 bool lu_solve(const cplx* A, int n, const cplx* c, cplx* x);
 
+// Conjugate partners of the eigenvalues: partner[a] = b when lambda_b = conj(lambda_a) to
+// 1e-12 relative (each lambda with Im > 0 takes the closest qualifying unpaired lambda with
+// Im < 0), else -1.
+std::vector<int> conj_partners(const cplx* lam, int k);
+
 // Orthogonal matching pursuit in coefficient space on the Gram H = Phi^H Phi (k x k),
-// c = Phi^H x_1 and x1n2 = ||x_1||^2: per step alpha = c - H[:,S] beta_S, pick the
-// unselected j maximising |alpha_j| / sqrt(H_jj) (ties within tie_rel of the maximum
-// go to the lowest index), then beta_S = H[S,S]^-1 c[S].  Stops after K atoms or when
-// ||x_1 - Phi_S beta_S||^2 = x1n2 - Re(c_S^H beta_S) <= (stop_rel^2) x1n2.
-// Returns false if a subsystem is singular.
-bool omp_gram(const cplx* H, int k, const cplx* c, double x1n2, int K, double tie_rel,
+// c = Phi^H x_1 and x1n2 = ||x_1||^2 for a real x_1: per step alpha = c - H[:,S] beta_S,
+// pick the unselected j maximising |alpha_j| / sqrt(H_jj) (the first maximum on exact
+// ties), then beta_S = H[S,S]^-1 c[S].  With the eigenvalues lam (nullable): while the
+// support holds both members of each of its conjugate pairs the residual is real, the
+// two members of an unselected pair tie by symmetry, and a pick of either goes to the one
+// with Im lambda > 0.  Stops after K atoms or when ||x_1 - Phi_S beta_S||^2 =
+// x1n2 - Re(c_S^H beta_S) <= (stop_rel^2) x1n2.  Returns false if a subsystem is singular.
+bool omp_gram(const cplx* H, int k, const cplx* c, double x1n2, int K, const cplx* lam,
               double stop_rel, std::vector<int>& S, std::vector<cplx>& beta,
               double* resid2);
 

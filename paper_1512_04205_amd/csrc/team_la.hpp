@@ -1,14 +1,14 @@
 // Small float64 linear algebra of the cDMD fit written once for a "team" of threads:
 // the whole thread block on the GPU (one workgroup per fit), or a single thread on the
-// host (where the same code is tested against LAPACK).  Covers Algorithm 1 steps 4, 6
-// and 7 and the lift operator G = V S^-1 W:
+// host (where the same code is tested against LAPACK).  Covers the truncated SVD (eq.
+// svd), A~ and its eigendecomposition (Section 3.2) and the lift operator G = V S^-1 W:
 //
 //   * Lanczos with full (twice classical Gram-Schmidt) reorthogonalisation for the
-//     top-k eigenpairs of the Gram Y^T Y (the right singular vectors of Y, step 4);
+//     top-k eigenpairs of the Gram Y^T Y (the right singular vectors of Y, eq. svd);
 //   * cyclic Jacobi (parallel round-robin ordering) on the Lanczos tridiagonal matrix for
 //     the Ritz pairs and their residuals;
-//   * A~ = S^-1 V^T (Y^T Y') V S^-1 (step 6);
-//   * eig(A~) (step 7): Householder reduction to Hessenberg form, Francis double-shift QR
+//   * A~ = S^-1 V^T (Y^T Y') V S^-1 (Section 3.2);
+//   * eig(A~) (Section 3.2): Householder reduction to Hessenberg form, Francis double-shift QR
 //     (conjugate pairs from 2x2 blocks are exact conjugates), inverse iteration on
 //     A~ - lambda I for the eigenvectors (a pair's second member is the conjugate);
 //   * unit-norm eigenvectors with the largest-modulus entry real and positive;
@@ -1349,7 +1349,7 @@ TLA_HD void g_rows(TM& tm, const double* V, int N, int k, const double* nu, cons
 // Status codes (match cdmd_status).
 constexpr int kOk = 0, kDevice = 4, kRankDeficient = 5, kNumeric = 6;
 
-// Algorithm 1 step 4, first part: the top-k eigenpairs of the Gram Gr[0:N, 0:N] (N = m-1)
+// Truncated SVD (eq. svd), first part: the top-k eigenpairs of the Gram Gr[0:N, 0:N] (N = m-1)
 // of the unscaled sketch by Lanczos, the rows split over the groups of X; group 0 holds
 // mu[k] the eigenvalues and Z (J x k) the Ritz vectors of T_J (V = Q_J Z is formed by
 // ritz_rows).  Returns the status (the same in every group); *Jout = Krylov size.
@@ -1381,10 +1381,10 @@ TLA_HD TLA_INLINE int small_la_phase_a(TM& tm, X& xg, const double* Gr, int m, i
   return kOk;
 }
 
-// Algorithm 1 steps 4 (end) and 6, given the block partials P (nblk blocks of k*k + k,
+// End of the truncated SVD and A~ (Section 3.2), given the block partials P (nblk blocks of k*k + k,
 // from block_gram over V = Q_J Z and TV = M12 V): nu the column norms of V, sigma =
 // sqrt(mu) * sketch_scale, A~ = S^-1 Vn^T M12 Vn S^-1 with Vn = V diag(1/nu), and its
-// eigenvalues lam (step 7, first part).
+// eigenvalues lam (the first part of eig(A~)).
 template <class TM>
 TLA_HD int small_la_phase_b1(TM& tm, int N, int k, double sketch_scale, const SmallLAWork& ws, int nblk,
                              const double* mu, double* sigma, cpx* lam) {
@@ -1431,7 +1431,7 @@ TLA_HD inline bool conj_second(const cpx* lam, int j) {
   return lam[j].im < 0.0 && j > 0 && lam[j - 1].re == lam[j].re && lam[j - 1].im == -lam[j].im;
 }
 
-// Step 7, end: the second members of conjugate pairs take their partners' conjugates, and
+// eig(A~), end: the second members of conjugate pairs take their partners' conjugates, and
 // every column of W is made unit with its largest entry real and positive.
 template <class TM>
 TLA_HD void small_la_phase_b3(TM& tm, int k, const cpx* lam, cpx* W) {
@@ -1444,7 +1444,7 @@ TLA_HD void small_la_phase_b3(TM& tm, int k, const cpx* lam, cpx* W) {
   tm.stamp(6);
 }
 
-// Steps 4 (end), 6 and 7 by one team: phase B1, the eigenvectors W of A~ (column j at
+// End of the truncated SVD, A~ and eig(A~) by one team: phase B1, the eigenvectors W of A~ (column j at
 // j*k), phase B3.
 template <class TM>
 TLA_HD int small_la_phase_b(TM& tm, int N, int k, double sketch_scale, const SmallLAWork& ws, int nblk,
@@ -1482,7 +1482,7 @@ TLA_HD int small_la_tail(TM& tm, const double* Gr, int m, int k, int J, double s
   return kOk;
 }
 
-// Algorithm 1 steps 4, 6, 7 and G = V S^-1 W from the Gram Gr (m x m, symmetric) of the
+// Truncated SVD, A~, eig(A~) (Section 3.2) and G = V S^-1 W from the Gram Gr (m x m, symmetric) of the
 // unscaled sketch, by one team: phase A (one row group), then the tail.  sketch_scale
 // multiplies the sketch (so sigma = sqrt(mu) * scale).  Outputs: mu[k] (Gram eigenvalues),
 // sigma[k], lam[k] and W (k x k, column j at j*k) as cpx, G (N x k, row t at t*k) as cpx.

@@ -2,6 +2,13 @@
 import numpy as np
 from scipy.optimize import linear_sum_assignment
 
+# Relative gap between the oracle's OMP pick and the next candidate below which the
+# pick counts as a near tie: the float32 form's correlations carry relative errors of
+# order 1e-6, the bfloat16 form's of order 1e-3, so a pick closer than these may go
+# either way; the GPU is then given the oracle's support (explicit selection).
+NEAR_TIE_FP32 = 1e-4
+NEAR_TIE_BF16 = 3e-2
+
 
 def match_eigs(a, b):
     """Optimal matching of eigenvalue lists; returns (ia, ib, |a-b|)."""

@@ -27,8 +27,8 @@ def _lib():
     lib = P.load_library()
     lib.cdmd_dbg_sym_topk.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, DP, DP, IP]
     lib.cdmd_dbg_eig_general.argtypes = [DP, ctypes.c_int32, DP, DP]
-    lib.cdmd_dbg_omp_gram.argtypes = [DP, ctypes.c_int32, DP, ctypes.c_double, ctypes.c_int32, IP,
-                                      DP, IP, DP]
+    lib.cdmd_dbg_omp_gram.argtypes = [DP, ctypes.c_int32, DP, ctypes.c_double, ctypes.c_int32, DP,
+                                      IP, DP, IP, DP]
     return lib
 
 
@@ -189,8 +189,8 @@ def test_coefficient_space_omp_equals_explicit_omp(seed, K):
     Hv = H.view(np.float64).ravel()
     cv = c.view(np.float64).ravel()
     S, beta, ns, r2 = np.zeros(k, np.int32), np.zeros(2 * k), ctypes.c_int32(0), ctypes.c_double(0)
-    assert lib.cdmd_dbg_omp_gram(_p(Hv), k, _p(cv), float(x1 @ x1), K, S.ctypes.data_as(IP), _p(beta),
-                                 ctypes.byref(ns), ctypes.byref(r2)) == 0
+    assert lib.cdmd_dbg_omp_gram(_p(Hv), k, _p(cv), float(x1 @ x1), K, None, S.ctypes.data_as(IP),
+                                 _p(beta), ctypes.byref(ns), ctypes.byref(r2)) == 0
     Sr, br = R.omp(Phi, x1, K)
     assert list(S[:ns.value]) == list(Sr)
     np.testing.assert_allclose(beta[0::2][:ns.value] + 1j * beta[1::2][:ns.value], br, rtol=1e-9, atol=1e-12)
@@ -198,22 +198,30 @@ def test_coefficient_space_omp_equals_explicit_omp(seed, K):
     assert abs(r2.value - np.vdot(res, res).real) <= 1e-9 * (x1 @ x1)
 
 
-def test_omp_conjugate_pair_tie_prefers_lower_index():
-    """For real x_1 and a conjugate pair of atoms the first correlations tie exactly;
-    the lower index wins on both sides."""
+@pytest.mark.parametrize("order", [[0, 1, 2], [1, 0, 2], [2, 1, 0]])
+def test_omp_conjugate_pair_tie_goes_to_positive_imaginary_member(order):
+    """For real x_1 and a conjugate pair of atoms the first correlations tie by symmetry;
+    both sides give the pick to the member with Im lambda > 0 wherever it sits, then
+    complete the pair."""
     lib = _lib()
     rng = np.random.default_rng(9)
     n = 300
     a = rng.normal(size=n) + 1j * rng.normal(size=n)
-    Phi = np.stack([a, np.conj(a), rng.normal(size=n) + 0j], axis=1)
+    mu = 0.98 * np.exp(0.3j)
+    cols = [a, np.conj(a), rng.normal(size=n) + 0j]
+    lams = [mu, np.conj(mu), 0.7 + 0j]
+    Phi = np.stack([cols[i] for i in order], axis=1)
+    lam = np.array([lams[i] for i in order])
     x1 = (2 * a).real + 0.1 * rng.normal(size=n)
     H = np.ascontiguousarray(Phi.conj().T @ Phi)
     c = np.ascontiguousarray(Phi.conj().T @ x1.astype(complex))
     S, beta, ns, r2 = np.zeros(3, np.int32), np.zeros(6), ctypes.c_int32(0), ctypes.c_double(0)
     assert lib.cdmd_dbg_omp_gram(_p(H.view(np.float64).ravel()), 3, _p(c.view(np.float64).ravel()),
-                                 float(x1 @ x1), 1, S.ctypes.data_as(IP), _p(beta), ctypes.byref(ns),
-                                 ctypes.byref(r2)) == 0
-    assert S[0] == 0 and list(R.omp(Phi, x1, 1)[0]) == [0]
+                                 float(x1 @ x1), 2, _p(np.ascontiguousarray(lam).view(np.float64)),
+                                 S.ctypes.data_as(IP), _p(beta), ctypes.byref(ns), ctypes.byref(r2)) == 0
+    want = [order.index(0), order.index(1)]
+    assert list(S[:2]) == want
+    assert list(R.omp(Phi, x1, 2, lam=lam)[0]) == want
 
 
 # ------------------------------------------------------------------ team small LA (device code, host run)

@@ -15,7 +15,7 @@ import torch
 
 import synthvideo as sv
 from oracle import cdmd_ref as R
-from tests.cdmd_testutil import eig_rel_err
+from tests.cdmd_testutil import NEAR_TIE_BF16, NEAR_TIE_FP32, eig_rel_err
 
 pytestmark = pytest.mark.gpu
 P = pytest.importorskip("paper_1512_04205_amd")
@@ -42,7 +42,6 @@ def test_fullsize_1080p(prec):
     md = mdl.modes()
     S, beta = mdl.select(P.SEL_OMP, K=K)
     mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
-    mdl.foreground(Dg, mk, tau)
     torch.cuda.synchronize()
     _say("oracle sketch + SVD")
     D = Dg.cpu().numpy()
@@ -58,14 +57,16 @@ def test_fullsize_1080p(prec):
     assert np.abs(np.abs(md["b"]) * md["phi_norm"] - key_r).max() <= tol * key_r.max()
     _say("oracle OMP")
     x1 = D[0].astype(np.float64) / 255
-    Sr, br = R.omp(mo.Phi, x1, K)
-    if prec == "fp32":
-        assert list(S) == list(Sr), (S, Sr)
-    # masks on sampled pixels, with the oracle's support
+    gaps = []
+    Sr, br = R.omp(mo.Phi, x1, K, lam=mo.lam, margins=gaps)
+    near = NEAR_TIE_FP32 if prec == "fp32" else NEAR_TIE_BF16
+    if min(gaps) >= near:
+        assert list(S) == list(Sr), (S, Sr, gaps)
+    # masks with the oracle's support (the same one, unless the oracle records a near tie)
     if list(S) != list(Sr):
         S, beta = mdl.select(P.SEL_EXPLICIT, explicit=Sr)
-        mdl.foreground(Dg, mk, tau)
-        torch.cuda.synchronize()
+    mdl.foreground(Dg, mk, tau)
+    torch.cuda.synchronize()
     _say("sampled masks")
     rng = np.random.default_rng(0)
     pix = np.sort(rng.choice(n, 20000, replace=False))

@@ -14,7 +14,7 @@ import torch
 
 import synthvideo as sv
 from oracle import cdmd_ref as R
-from tests.cdmd_testutil import eig_rel_err, mask_agreement
+from tests.cdmd_testutil import NEAR_TIE_FP32, eig_rel_err, mask_agreement
 
 pytestmark = pytest.mark.gpu
 
@@ -180,9 +180,13 @@ def test_select_and_mask_parity(selector):
     mo = ref.model
     x1 = D[0].astype(np.float64) / 255
     if selector == "omp":
-        S, beta = mdl.select(P.SEL_OMP, K=8)
-        Sr, br = R.omp(mo.Phi, x1, 8)
-        assert list(S) == list(Sr)
+        gaps = []
+        Sr, br = R.omp(mo.Phi, x1, 8, lam=mo.lam, margins=gaps)
+        if min(gaps) >= NEAR_TIE_FP32:
+            S, beta = mdl.select(P.SEL_OMP, K=8)
+            assert list(S) == list(Sr)
+        else:   # a near tie the float32 lift may resolve either way: the oracle's support
+            S, beta = mdl.select(P.SEL_EXPLICIT, explicit=Sr)
     elif selector == "zero_mode":
         S, beta = mdl.select(P.SEL_ZERO_MODE)
         Sr = R.select_zero_mode(mo.lam)

@@ -245,8 +245,8 @@ def test_compressed_amplitudes_identity_sketch_equal_full():
     np.testing.assert_allclose(comp.lam, full.lam, atol=1e-12)
     np.testing.assert_allclose(comp.Phi, full.Phi, atol=1e-10)
     np.testing.assert_allclose(comp.b, full.b, atol=1e-10)
-    Sf, bf = R.omp(full.Phi, D[0], 4)
-    Sc, bc = R.omp(comp.Phi, Y[:, 0], 4)
+    Sf, bf = R.omp(full.Phi, D[0], 4, lam=full.lam)
+    Sc, bc = R.omp(comp.Phi, Y[:, 0], 4, lam=comp.lam)
     assert list(Sf) == list(Sc)
     np.testing.assert_allclose(bc, bf, atol=1e-10)
 
@@ -332,6 +332,98 @@ def test_omp_tie_rule_lowest_index():
     x = np.array([1.0, 1.0, 0.5, 0.0])
     S, _ = R.omp(e, x, K=1)
     assert list(S) == [0]
+
+
+def test_omp_conjugate_pair_tie_goes_to_positive_imaginary_member():
+    """Real x_1 and a conjugate pair of atoms: the first correlations are equal by
+    symmetry (|conj(a)^H x| = |a^H x| for real x), and the pick goes to the member with
+    Im lambda > 0 wherever it sits; once one member is in, the residual is complex and
+    the partner is an ordinary candidate.  Without eigenvalues no pairing is known and
+    the first maximum wins."""
+    rng = np.random.default_rng(12)
+    n = 400
+    a = rng.normal(size=n) + 1j * rng.normal(size=n)
+    c = rng.normal(size=n)
+    x1 = (1.5 * a).real + 0.05 * c
+    mu = 0.97 * np.exp(0.4j)
+    for order in ([0, 1, 2], [1, 0, 2], [2, 1, 0]):
+        cols = [a, np.conj(a), c + 0j]
+        lams = [mu, np.conj(mu), 0.5 + 0j]
+        Phi = np.stack([cols[i] for i in order], axis=1)
+        lam = np.array([lams[i] for i in order])
+        gaps = []
+        S, _ = R.omp(Phi, x1, K=3, lam=lam, margins=gaps)
+        first = order.index(0)                 # where the Im > 0 member sits
+        assert S[0] == first, (order, S)
+        assert S[1] == order.index(1)          # its partner completes the pair next
+        assert gaps[0] > 0.1                   # the real atom is far behind the pair
+    # the partners' correlations really are equal to rounding
+    corr = np.abs(np.stack([a, np.conj(a)]).conj() @ x1) / np.linalg.norm(a)
+    assert abs(corr[0] - corr[1]) <= 1e-12 * corr[0]
+
+
+def test_omp_margins_flag_a_near_tie():
+    """Two atoms with correlations 1 and 1 - 1e-7: the first pick's margin is 1e-7."""
+    e = np.eye(3, dtype=complex)
+    x = np.array([1.0, 1.0 - 1e-7, 0.25])
+    gaps = []
+    S, _ = R.omp(e, x, K=2, margins=gaps)
+    assert list(S) == [0, 1]
+    np.testing.assert_allclose(gaps[0], 1e-7, rtol=1e-6)
+    np.testing.assert_allclose(gaps[1], 1.0 - 0.25 / (1.0 - 1e-7), rtol=1e-9)
+
+
+# ------------------------------------------------------------------ omega selector, refit
+def test_select_omega_hand_values():
+    """|omega| = |log lambda| with the principal branch, worked by hand for each lambda:
+    1 -> 0; exp(+-0.25i) -> 0.25 (conjugates go together); 0.9 -> -ln 0.9 = 0.1053605...;
+    -1 -> |i pi| = pi; 0.8 exp(+-0.3i) -> sqrt(ln(0.8)^2 + 0.09) = 0.3738891; 2i -> |ln 2 +
+    i pi/2| = 1.7169316; e^0.5 -> 0.5.  Thresholds just below and above each value,
+    and the strict inequality at 0 (lambda = 1 has |omega| = 0, not < 0)."""
+    lam = np.array([1.0, np.exp(0.25j), np.exp(-0.25j), 0.9, -1.0, 0.8 * np.exp(0.3j),
+                    0.8 * np.exp(-0.3j), 2j, np.exp(0.5)], dtype=np.complex128)
+    d = 1e-9
+    cases = {
+        0.0: [],
+        d: [0],
+        0.1053605 - d: [0],
+        0.1053606: [0, 3],
+        0.25 - d: [0, 3],
+        0.25 + d: [0, 1, 2, 3],
+        0.3738890: [0, 1, 2, 3],
+        0.3738891: [0, 1, 2, 3, 5, 6],
+        0.5 + d: [0, 1, 2, 3, 5, 6, 8],
+        1.7169316: [0, 1, 2, 3, 5, 6, 7, 8],
+        np.pi - d: [0, 1, 2, 3, 5, 6, 7, 8],
+        np.pi + d: list(range(9)),
+    }
+    for thr, want in cases.items():
+        assert list(R.select_omega(lam, thr)) == want, (thr, R.select_omega(lam, thr))
+
+
+def test_refit_hand_solved_and_conjugate_transpose():
+    """Two cases worked by hand.  Phi = [[1, i], [0, 1], [0, 0]], x = (1, 2, 3):
+    Phi beta = (b1 + i b2, b2, 0), so b2 = 2, b1 = 1 - 2i (residual (0, 0, 3)).
+    phi = (1, i, 1), x = (1, 1, 0): beta = phi^H x / phi^H phi = (1 - i) / 3; the plain
+    transpose would give phi^T x / phi^T phi = (1 + i) / 1."""
+    Phi = np.array([[1, 1j], [0, 1], [0, 0]], dtype=np.complex128)
+    np.testing.assert_allclose(R.refit(Phi, np.array([1.0, 2.0, 3.0])), [1 - 2j, 2], atol=1e-14)
+    phi = np.array([[1], [1j], [1]], dtype=np.complex128)
+    np.testing.assert_allclose(R.refit(phi, np.array([1.0, 1.0, 0.0])), [(1 - 1j) / 3], atol=1e-15)
+
+
+def test_refit_orthogonal_dictionary_closed_form():
+    """Orthogonal complex columns of norms d_j: beta_j = phi_j^H x / d_j^2, and a
+    component of x outside the span does not move beta."""
+    rng = np.random.default_rng(31)
+    Q, _ = np.linalg.qr(rng.normal(size=(60, 6)) + 1j * rng.normal(size=(60, 6)))
+    d = np.array([0.5, 1.0, 2.0, 3.0, 7.0])
+    Phi = Q[:, :5] * d[None, :]
+    beta_true = np.array([1 + 1j, -2, 0.5j, 3 - 1j, 0.25])
+    x = (Phi @ beta_true + 4.0 * Q[:, 5]).real        # complex x would be fine too
+    beta_true = Phi.conj().T @ x / d ** 2             # the closed form for the real x
+    np.testing.assert_allclose(R.refit(Phi, x), beta_true, atol=1e-12)
+    np.testing.assert_allclose(R.refit(Phi[:, [4, 1]], x), beta_true[[4, 1]], atol=1e-12)
 
 
 # ------------------------------------------------------------------ P11: Vandermonde
