@@ -120,6 +120,8 @@ struct cdmd_model {
   void* d_Gsp = nullptr;     // MFMA B operands of [Re G~_S | Im G~_S]
   uint16_t* h_Gsp = nullptr;
   bool recon_mfma = false;
+  hipEvent_t e_stage = nullptr;   // the H2D copies of the reconstruction staging
+  bool stage_pending = false;
   float* d_Gs = nullptr;
   float* d_Vc = nullptr;
   int64_t* d_counts = nullptr;
@@ -180,6 +182,10 @@ struct cdmd_model {
       if (e) (void)hipEventDestroy(e);
     if (e_fork) (void)hipEventDestroy(e_fork);
     if (e_join) (void)hipEventDestroy(e_join);
+    if (e_stage) {
+      if (stage_pending) (void)hipEventSynchronize(e_stage);
+      (void)hipEventDestroy(e_stage);
+    }
     if (st2) (void)hipStreamDestroy(st2);
     void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart, d_chunk_off, d_rblk,
                    d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts, d_modes,
@@ -939,6 +945,7 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
   TRY(dalloc(&M->d_Vc, (size_t)m * 80));
   TRY(halloc(&M->h_Vc, (size_t)m * 80));
   TRY(dalloc(&M->d_counts, (size_t)m));
+  HIPCHK(hipEventCreateWithFlags(&M->e_stage, hipEventDisableTiming));
   TRY(dalloc(&M->d_modes, (size_t)5 * M->k));
   TRY(dalloc(&M->d_feats, (size_t)6 * M->k));
   TRY(dalloc(&M->d_logits, (size_t)M->k));
@@ -1561,57 +1568,68 @@ cdmd_status cdmd_select(cdmd_model* M, int32_t selector, int32_t K, double omega
 
 namespace {
 
-// Host side of the reconstruction: Gs = [Re(G_S diag beta) | Im(...)] * xscale and the
-// Vandermonde rows Vc[t] = [Re lambda^t | -Im lambda^t] (t = 0..m-1, 0-based).
+// Operands of the reconstruction.  MFMA form (16-byte aligned uint8 frames, |S| <= 16,
+// the tile's frames fit in LDS): the A fragments of G~^T = [Re | Im] of G_S diag(beta)
+// xscale, formed on the device from the device solve's G or here from the host G; the
+// Vandermonde factors are powers the kernel forms from the eigenvalues.  VALU form:
+// Gs = [Re(G_S diag beta) | Im(...)] * xscale and the Vandermonde rows Vc[t] =
+// [Re lambda^t | -Im lambda^t] (t = 0..m-1, 0-based).  Host staging buffers are rewritten
+// only once the copies of the previous call have completed.
 cdmd_status prepare_recon(cdmd_model* M, int static_bg, int* NSout, hipStream_t st) {
   const int ns = (int)M->S.size();
   const int NS = pad_ns(std::max(2 * ns, 1));
-  if (NS < 0) return fail(CDMD_E_UNSUPPORTED, "more than 40 selected modes");
   const int N = M->N, k = M->k;
   const int64_t m = M->m;
-  M->recon_mfma = M->lift_mfma && 2 * ns <= 32;
   for (int s = 0; s < ns; ++s) {
     const cplx l = M->lam[M->S[s]];
     if (!static_bg && std::abs(l) > 1.0 && std::pow(std::abs(l), (double)(m - 1)) > kVanderMax)
       return fail(CDMD_E_NUMERIC, "|lambda|^(m-1) overflows the Vandermonde matrix");
   }
+  M->recon_mfma = M->lift_mfma && ns <= 16 && cdmd::k::recon_lds_bytes(m, M->lm_nsplit) <= (size_t)160 * 1024;
+  if (!M->recon_mfma && NS < 0) return fail(CDMD_E_UNSUPPORTED, "more than 40 selected modes");
+  if (M->stage_pending) {
+    HIPCHK(hipEventSynchronize(M->e_stage));
+    M->stage_pending = false;
+  }
+  *NSout = NS;
   if (M->recon_mfma && M->device_la) {
     // from the device solve's G (column order of the solve: canonical index c is column
     // perm[c]); nothing is built on the host
     cdmd::k::ReconPrep rp{};
     rp.ns = ns;
-    rp.NS = NS;
     rp.NSP = M->lm_nsplit;
     rp.KS = M->lm_nksteps;
     rp.N = N;
     rp.k = k;
-    rp.static_bg = static_bg ? 1 : 0;
-    rp.m = m;
     rp.xscale = (double)M->xscale;
     for (int s = 0; s < ns; ++s) {
       rp.col[s] = M->perm[M->S[s]];
       rp.beta[2 * s] = M->beta[s].real();
       rp.beta[2 * s + 1] = M->beta[s].imag();
-      rp.lam[2 * s] = M->lam[M->S[s]].real();
-      rp.lam[2 * s + 1] = M->lam[M->S[s]].imag();
     }
     const cdmd::tla::SmallLAOutLayout L = cdmd::tla::small_la_out_layout(N, k);
-    HIPCHK(cdmd::k::recon_prep(M->d_la_out + L.G, rp, M->d_Gsp, M->d_Vc, st));
-    *NSout = NS;
+    HIPCHK(cdmd::k::recon_prep(M->d_la_out + L.G, rp, M->d_Gsp, st));
     return CDMD_OK;
   }
   if (M->recon_mfma) {
     const int NSP = M->lm_nsplit, KS = M->lm_nksteps;
+    std::vector<int> src_s(32, -1), src_part(32, 0);
+    for (int s = 0; s < ns; ++s)
+      for (int part = 0; part < 2; ++part) {
+        const int c = cdmd::k::recon_column(s, part);
+        src_s[c] = s;
+        src_part[c] = part;
+      }
     for (int ks = 0; ks < KS; ++ks)
       for (int l = 0; l < 64; ++l) {
-        const int col = l & 31;
+        const int c = l & 31;
         for (int i = 0; i < 8; ++i) {
           const int row = 16 * ks + 8 * (l >> 5) + i;
           double g = 0.0;
-          if (row < N && col < 2 * ns) {
-            const int sidx = col < ns ? col : col - ns;
+          if (row < N && src_s[c] >= 0) {
+            const int sidx = src_s[c];
             const cplx z = M->G[(size_t)row * k + M->S[sidx]] * M->beta[sidx] * (double)M->xscale;
-            g = col < ns ? z.real() : z.imag();
+            g = src_part[c] == 0 ? z.real() : z.imag();
           }
           double rem = g;
           for (int sp = 0; sp < NSP; ++sp) {
@@ -1622,8 +1640,11 @@ cdmd_status prepare_recon(cdmd_model* M, int static_bg, int* NSout, hipStream_t 
         }
       }
     HIPCHK(hipMemcpyAsync(M->d_Gsp, M->h_Gsp, (size_t)KS * NSP * 64 * 16, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(M->e_stage, st));
+    M->stage_pending = true;
+    return CDMD_OK;
   }
-  for (int t = 0; t < N && !M->recon_mfma; ++t) {
+  for (int t = 0; t < N; ++t) {
     float* row = M->h_Gs + (size_t)t * NS;
     for (int c = 0; c < NS; ++c) row[c] = 0.f;
     for (int s = 0; s < ns; ++s) {
@@ -1642,10 +1663,43 @@ cdmd_status prepare_recon(cdmd_model* M, int static_bg, int* NSout, hipStream_t 
       if (!static_bg) pw[s] *= M->lam[M->S[s]];
     }
   }
-  if (!M->recon_mfma)
-    HIPCHK(hipMemcpyAsync(M->d_Gs, M->h_Gs, sizeof(float) * N * NS, hipMemcpyHostToDevice, st));
+  HIPCHK(hipMemcpyAsync(M->d_Gs, M->h_Gs, sizeof(float) * N * NS, hipMemcpyHostToDevice, st));
   HIPCHK(hipMemcpyAsync(M->d_Vc, M->h_Vc, sizeof(float) * m * NS, hipMemcpyHostToDevice, st));
-  *NSout = NS;
+  HIPCHK(hipEventRecord(M->e_stage, st));
+  M->stage_pending = true;
+  return CDMD_OK;
+}
+
+// The reconstruction kernel of the form prepare_recon chose.
+cdmd_status run_recon(cdmd_model* M, const void* d_video, int static_bg, int NS, float tau, int mode,
+                      void* out, int64_t t0, int64_t t1, int64_t ldL, hipStream_t st) {
+  if (M->recon_mfma) {
+    cdmd::k::ReconArgs a{};
+    a.D = static_cast<const uint8_t*>(d_video);
+    a.ld = M->ld;
+    a.n = M->n;
+    a.m = M->m;
+    a.Gp = static_cast<const uint4*>(M->d_Gsp);
+    a.KS = M->lm_nksteps;
+    a.ns = (int)M->S.size();
+    for (int s = 0; s < a.ns; ++s) {
+      const cplx l = static_bg ? cplx(1.0, 0.0) : M->lam[M->S[s]];
+      a.lam[2 * s] = l.real();
+      a.lam[2 * s + 1] = l.imag();
+    }
+    a.tau = tau;
+    a.xscale = M->xscale;
+    a.mode = mode;
+    a.out = out;
+    a.t0 = t0;
+    a.t1 = t1;
+    a.ldL = ldL;
+    const int ntv = M->lm_nsplit == 3 ? 3 : 2;
+    HIPCHK(cdmd::k::recon_mfma(a, M->lm_nsplit, ntv, st));
+    return CDMD_OK;
+  }
+  HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, tau, M->xscale, mode, out,
+                       t0, t1, ldL, st));
   return CDMD_OK;
 }
 
@@ -1668,12 +1722,7 @@ cdmd_status cdmd_background(const cdmd_model* Mc, const void* d_video, int64_t t
   int NS = 0;
   TRY(prepare_recon(M, static_bg, &NS, st));
   M->mark(5, st);
-  if (M->recon_mfma)
-    HIPCHK(cdmd::k::bgfg_mfma((const uint8_t*)d_video, M->ld, M->n, M->m, M->d_Gsp, M->lm_nsplit,
-                              M->lm_nksteps, NS, M->d_Vc, 0.f, M->xscale, 2, d_L, t0, t1, ldL, st));
-  else
-    HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, 0.f,
-                         M->xscale, 2, d_L, t0, t1, ldL, st));
+  TRY(run_recon(M, d_video, static_bg, NS, 0.f, 2, d_L, t0, t1, ldL, st));
   M->mark(6, st);
   M->recon_pending = M->timing;
   return CDMD_OK;
@@ -1692,13 +1741,7 @@ cdmd_status cdmd_foreground(const cdmd_model* Mc, const void* d_video, float tau
   int NS = 0;
   TRY(prepare_recon(M, static_bg, &NS, st));
   M->mark(5, st);
-  if (M->recon_mfma)
-    HIPCHK(cdmd::k::bgfg_mfma((const uint8_t*)d_video, M->ld, M->n, M->m, M->d_Gsp, M->lm_nsplit,
-                              M->lm_nksteps, NS, M->d_Vc, tau, M->xscale, bitpacked ? 0 : 1, d_mask,
-                              0, M->m, 0, st));
-  else
-    HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, tau,
-                         M->xscale, bitpacked ? 0 : 1, d_mask, 0, M->m, 0, st));
+  TRY(run_recon(M, d_video, static_bg, NS, tau, bitpacked ? 0 : 1, d_mask, 0, M->m, 0, st));
   M->mark(6, st);
   M->recon_pending = M->timing;
   if (h_counts) {

@@ -718,131 +718,285 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3
   }
 }
 
-// Fused background + foreground with phase 1 on MFMA: T = X' Gs for one 256-pixel
-// tile (Gs: [Re G~_S | Im G~_S] as NSPLIT bf16 terms, 32 columns), T moved through LDS
-// to one pixel per thread, then per frame L = sum_c T_c Vc[t][c] and the threshold as
-// in k_bgfg.
-template <int NSPLIT, int NSV>
-__global__ __launch_bounds__(256) void k_bgfg_mfma(const uint8_t* __restrict__ D, int64_t ld,
-                                                  int64_t n, int64_t m, const uint4* __restrict__ Gp,
-                                                  int nksteps, const float* __restrict__ Vc,
-                                                  float tau, float xscale, int mode,
-                                                  void* __restrict__ out, int64_t t0, int64_t t1,
-                                                  int64_t ldL) {
-  constexpr int MAIN_BYTES = xg_lds_bytes<1, NSPLIT, 2>();
-  constexpr int T_BYTES = 256 * 33 * 4;
-  constexpr int LDS_BYTES = T_BYTES > MAIN_BYTES ? T_BYTES : MAIN_BYTES;
-  __shared__ __align__(16) uint8_t lds[LDS_BYTES];
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-  const int64_t base = (int64_t)blockIdx.x * LM_TILE;
-  f32x16_t acc[2][1];
-  xprime_g_tile<1, NSPLIT, 2>(D, ld, n, m, Gp, nksteps, base, lds, acc);
-  __syncthreads();
-  float* sT = reinterpret_cast<float*>(lds);
+// ============================================================================
+// Background reconstruction and foreground threshold in one read of the video
+// (eq. (equ:DMDTerms) with its real-part footnote, eq. (eq:thres)).  A workgroup of
+// two waves owns 128 pixels; every frame of its tile stays in LDS ([frame][RC_SA]
+// bytes) from the moment it streams in, so HBM delivers each video byte once.
+//
+//   phase 1: T^T = G~^T X' on bf16 MFMA 32x32x16.  G~ = [Re | Im] of G_S diag(beta_S)
+//            xscale in NSG bf16 terms (A operands, columns in the order of rc_col), X'
+//            exact in bf16 (B operands gathered from LDS); float32 accumulation.  Wave w
+//            keeps acc[mb] = T^T of its pixel blocks 64w + 32mb (rows: columns c, lane
+//            columns: pixels).
+//   phase 2: L = V~ T on bf16 MFMA 32x32x16, per 32-frame block.  The B operands are the
+//            phase-1 accumulators themselves split into NTV bf16 terms: a lane of the
+//            phase-1 result holds one pixel and 16 columns, which is exactly a B fragment
+//            once the K order of phase 2 is the fixed permutation sigma(16q + 8h + i) =
+//            16q + 8(i/4) + 4h + i%4.  The A operands V~[t][c] = Re lambda_s^t or
+//            -Im lambda_s^t are formed per lane from float64 powers (lambda^(t0 + lane),
+//            then times lambda^32 per block), so no Vandermonde matrix is read.  The
+//            products of the split terms whose orders sum below NTV are accumulated in
+//            float32 (NTV = 3: six products, float32-class L; NTV = 2: three).
+//   output:  |x - L| > tau per element, bit-packed by wave ballots (mode 0), as bytes
+//            (mode 1), or L itself (mode 2).
+//
+// Columns: mode s (< 16) goes to lane half h = s & 1 at slot j = 2 (s >> 1) + part
+// (part 0 = Re, 1 = Im), i.e. column rc_col(s, part); a lane of half h then needs the
+// powers of the modes s = 2u + h, u < 8, only.
+constexpr int RC_TP = 128;   // pixels per workgroup
+constexpr int RC_NT = 128;   // two waves
+constexpr int RC_SA = 136;   // LDS bytes per frame row: 8-byte aligned, conflict-free reads
+constexpr int RC_KPC = 2;    // k-steps (16 frames each) per streamed chunk
+
+__host__ __device__ inline int rc_col(int s, int part) {
+  const int h = s & 1, j = 2 * (s >> 1) + part;
+  return 16 * (j >> 3) + 8 * ((j >> 2) & 1) + 4 * h + (j & 3);
+}
+
+template <int NT>
+__device__ __forceinline__ void split_terms(const float* v, bf16x8_t (&o)[NT]) {
+  float r[8];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int i = 0; i < 8; ++i) r[i] = v[i];
 #pragma unroll
-    for (int j = 0; j < 16; ++j)
-      sT[(64 * w + 32 * mb + (j >> 2) * 8 + (l >> 5) * 4 + (j & 3)) * 33 + (l & 31)] = acc[mb][0][j];
-  __syncthreads();
-  // phase 2 on FP32 MFMA 16x16x4: per wave 4 pixel blocks of 16 x frame blocks of 16,
-  // K = NSV in steps of 4.  A = T (held in registers for the whole frame loop), B = Vc
-  // (global, frame-major), C lane l holds L[px 16mb + 4(l/16) + j][frame 16nb + l%16],
-  // j = 0..3.  The next frame block's Vc values and video words are loaded while the
-  // current one is computed.
-  typedef float f32x4_t __attribute__((ext_vector_type(4)));
-  const int64_t words = (n + 31) >> 5;
-  const int li = l & 15, lq = l >> 4;
-  float areg[4][NSV / 4];
+  for (int t = 0; t < NT; ++t) {
+    uint32_t wv[4];
 #pragma unroll
-  for (int mb = 0; mb < 4; ++mb)
-#pragma unroll
-    for (int ks = 0; ks < NSV / 4; ++ks) areg[mb][ks] = sT[(64 * w + 16 * mb + li) * 33 + 4 * ks + lq];
-  const int64_t pxl = base + 64 * w + 4 * lq;      // + 16 mb: this lane's 4 pixels of block mb
-  const bool full = base + 64 * w + 64 <= n;       // all 64 pixels of the wave exist (uniform)
-  const bool want_x = mode != 2;
-  float bv[NSV / 4], bn[NSV / 4];
-  uint32_t qv[4], qn[4];
-  auto load_next = [&](int64_t fb, float* b, uint32_t* q) {
-    const int64_t f = fb + li;
-    const bool fv = f < t1;
-#pragma unroll
-    for (int ks = 0; ks < NSV / 4; ++ks) b[ks] = fv ? Vc[f * NSV + 4 * ks + lq] : 0.f;
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb)
-      q[mb] = (want_x && fv && full) ? *reinterpret_cast<const uint32_t*>(D + f * ld + pxl + 16 * mb) : 0u;
-  };
-  load_next(t0, bv, qv);
-  for (int64_t fb = t0; fb < t1; fb += 16) {
-    const int64_t f = fb + li;                      // this lane's frame (B column / C column)
-    const bool fvalid = f < t1;
-    if (fb + 16 < t1) load_next(fb + 16, bn, qn);
-    uint32_t nib[4];
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb) {
-      f32x4_t c = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int ks = 0; ks < NSV / 4; ++ks) c = __builtin_amdgcn_mfma_f32_16x16x4f32(areg[mb][ks], bv[ks], c, 0, 0, 0);
-      const int64_t px0 = pxl + 16 * mb;            // 4 consecutive pixels of this lane
-      if (mode == 2) {
-        if (fvalid)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (px0 + j < n) reinterpret_cast<float*>(out)[(f - t0) * ldL + px0 + j] = c[j];
-        nib[mb] = 0;
-        continue;
-      }
-      float xv[4];
-      if (full) {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) xv[j] = (float)((qv[mb] >> (8 * j)) & 0xffu);
-      } else {
-#pragma unroll
-        for (int j = 0; j < 4; ++j) xv[j] = (fvalid && px0 + j < n) ? (float)D[f * ld + px0 + j] : 0.f;
-      }
-      uint32_t bits = 0;
-#pragma unroll
-      for (int j = 0; j < 4; ++j)
-        if (fvalid && px0 + j < n && fabsf(fmaf(xv[j], xscale, -c[j])) > tau) bits |= 1u << j;
-      if (mode == 1) {
-        if (fvalid)
-#pragma unroll
-          for (int j = 0; j < 4; ++j)
-            if (px0 + j < n) reinterpret_cast<uint8_t*>(out)[f * n + px0 + j] = (bits >> j) & 1u;
-      }
-      nib[mb] = bits << (4 * lq);
+    for (int i = 0; i < 4; ++i) {
+      const uint32_t b0 = bf16_rne_bits(r[2 * i]), b1 = bf16_rne_bits(r[2 * i + 1]);
+      r[2 * i] -= __uint_as_float(b0 << 16);
+      r[2 * i + 1] -= __uint_as_float(b1 << 16);
+      wv[i] = b0 | (b1 << 16);
     }
-    if (mode == 0) {
-      // 16 pixel bits of a block from the four lanes sharing l%16, two blocks per word
-      uint32_t v[4];
-#pragma unroll
-      for (int mb = 0; mb < 4; ++mb) {
-        uint32_t t = nib[mb];
-        t |= __shfl_xor(t, 16, 64);
-        t |= __shfl_xor(t, 32, 64);
-        v[mb] = t;
-      }
-      if (lq == 0 && fvalid) {
-        const int64_t wbase = (base + 64 * w) >> 5;  // first word of this wave's 64 pixels
-        uint32_t* wd = reinterpret_cast<uint32_t*>(out) + f * words + wbase;
-        if (base + 64 * w < n) wd[0] = v[0] | (v[1] << 16);
-        if (base + 64 * w + 32 < n) wd[1] = v[2] | (v[3] << 16);
-      }
-    }
-#pragma unroll
-    for (int ks = 0; ks < NSV / 4; ++ks) bv[ks] = bn[ks];
-#pragma unroll
-    for (int mb = 0; mb < 4; ++mb) qv[mb] = qn[mb];
+    o[t] = __builtin_bit_cast(bf16x8_t, make_uint4(wv[0], wv[1], wv[2], wv[3]));
   }
 }
 
-// Operands of the reconstruction from the device solve's G (N x k complex, row t at t*k,
-// column order of the solve): the B operands of G~_S = [Re | Im] of G[:, col_s] beta_s
-// xscale ([ks][split][lane][8], element i of lane l is row 16ks + 8(l/32) + i, column
-// l%32 < 2 ns, NSP bf16 terms) and the rows of Vc (m x NS floats: lambda_s^t, then
-// -Im, zero-padded; lambda^t by repeated float64 multiplication, 1 when static_bg).
+struct c64 {
+  double re, im;
+};
+__device__ __forceinline__ c64 c64mul(c64 a, c64 b) {
+  return c64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+
+size_t recon_lds_bytes(int64_t m, int nsg) {
+  const int64_t ks = (m - 1 + 15) / 16, nch = (ks + RC_KPC - 1) / RC_KPC;
+  return (size_t)RC_KPC * nsg * 64 * 16 + (size_t)(1 + 32 * nch) * RC_SA;
+}
+
+template <int NSG, int NTV>
+__global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a) {
+  extern __shared__ __align__(16) uint4 rc_lds[];
+  uint4* sG = rc_lds;
+  uint8_t* sV = reinterpret_cast<uint8_t*>(rc_lds + RC_KPC * NSG * 64);
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, fl = l & 31;
+  const int64_t base = (int64_t)blockIdx.x * RC_TP;
+  const int64_t n = a.n, m = a.m, N = m - 1, ld = a.ld;
+  const int KS = a.KS;
+  const int nch = (KS + RC_KPC - 1) / RC_KPC;
+  constexpr int GPT = (RC_KPC * NSG * 64 + RC_NT - 1) / RC_NT;  // G~ operands per thread and chunk
+
+  // frame 0 (x_1), needed by the threshold only
+  if (tid < 8) {
+    const int64_t px = base + 16 * tid;
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (px + 16 <= n) {
+      v = *reinterpret_cast<const uint4*>(a.D + px);
+    } else {
+      uint32_t wd[4] = {0, 0, 0, 0};
+      for (int b = 0; b < 16; ++b)
+        if (px + b < n) wd[b >> 2] |= (uint32_t)a.D[px + b] << (8 * (b & 3));
+      v = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+    }
+    uint2* dst = reinterpret_cast<uint2*>(sV + 16 * tid);
+    dst[0] = make_uint2(v.x, v.y);
+    dst[1] = make_uint2(v.z, v.w);
+  }
+  // chunk c: frames 1 + 32c + r, r < 32; thread loads rows r = tid/8 and 16 + tid/8,
+  // 16 pixels at 16 (tid % 8)
+  const int fr = tid >> 3, seg = 16 * (tid & 7);
+  uint4 rv[2];
+  uint4 rg[GPT];
+  auto gload = [&](int c) {
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int64_t f = 1 + 32 * (int64_t)c + fr + 16 * q;
+      const int64_t px = base + seg;
+      if (f <= N && px + 16 <= n) {
+        rv[q] = *reinterpret_cast<const uint4*>(a.D + f * ld + px);
+      } else {
+        uint32_t wd[4] = {0, 0, 0, 0};
+        if (f <= N)
+          for (int b = 0; b < 16; ++b)
+            if (px + b < n) wd[b >> 2] |= (uint32_t)a.D[f * ld + px + b] << (8 * (b & 3));
+        rv[q] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < GPT; ++q) {
+      const int e = tid + q * RC_NT;
+      if (e < RC_KPC * NSG * 64) {
+        const int ks = RC_KPC * c + e / (NSG * 64);
+        rg[q] = ks < KS ? a.Gp[(int64_t)RC_KPC * c * NSG * 64 + e] : make_uint4(0, 0, 0, 0);
+      }
+    }
+  };
+
+  f32x16_t acc[2];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int j = 0; j < 16; ++j) acc[mb][j] = 0.f;
+  gload(0);
+  for (int c = 0; c < nch; ++c) {
+    __syncthreads();  // the previous chunk's operands are consumed
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      uint2* dst = reinterpret_cast<uint2*>(sV + (size_t)(1 + 32 * c + fr + 16 * q) * RC_SA + seg);
+      dst[0] = make_uint2(rv[q].x, rv[q].y);
+      dst[1] = make_uint2(rv[q].z, rv[q].w);
+    }
+#pragma unroll
+    for (int q = 0; q < GPT; ++q) {
+      const int e = tid + q * RC_NT;
+      if (e < RC_KPC * NSG * 64) sG[e] = rg[q];
+    }
+    __syncthreads();
+    if (c + 1 < nch) gload(c + 1);
+#pragma unroll
+    for (int kk = 0; kk < RC_KPC; ++kk) {
+      if (RC_KPC * c + kk >= KS) break;
+      const int f0 = 1 + 16 * (RC_KPC * c + kk) + 8 * h;
+      bf16x8_t xb[2];
+#pragma unroll
+      for (int mb = 0; mb < 2; ++mb) {
+        const uint8_t* col = sV + (size_t)f0 * RC_SA + 64 * w + 32 * mb + fl;
+        uint32_t wv[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) wv[i] = pack_u8pair_bf16(col[(2 * i) * RC_SA], col[(2 * i + 1) * RC_SA]);
+        xb[mb] = __builtin_bit_cast(bf16x8_t, make_uint4(wv[0], wv[1], wv[2], wv[3]));
+      }
+#pragma unroll
+      for (int t = NSG - 1; t >= 0; --t) {
+        const bf16x8_t ga = __builtin_bit_cast(bf16x8_t, sG[(kk * NSG + t) * 64 + l]);
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga, xb[mb], acc[mb], 0, 0, 0);
+      }
+    }
+  }
+  __syncthreads();  // every frame of the tile is in LDS
+
+  // phase 2 operands: T fragments (B), split into NTV terms
+  const int nq = a.ns <= 8 ? 1 : 2;
+  bf16x8_t tb[2][2][NTV];
+#pragma unroll
+  for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) v[i] = acc[mb][8 * q + i];
+      split_terms<NTV>(v, tb[mb][q]);
+    }
+  // powers of this lane's modes s = 2u + h at its frame t_start + fl, and lambda^32
+  const int64_t ts = a.mode == 2 ? a.t0 : 0, te = a.mode == 2 ? a.t1 : m;
+  c64 P[8], Q[8];
+#pragma unroll
+  for (int u = 0; u < 8; ++u) {
+    const int s = 2 * u + h;
+    c64 lam = s < a.ns ? c64{a.lam[2 * s], a.lam[2 * s + 1]} : c64{0.0, 0.0};
+    c64 q32 = lam;
+#pragma unroll
+    for (int r = 0; r < 5; ++r) q32 = c64mul(q32, q32);
+    c64 pw{1.0, 0.0}, b = lam;
+    for (int64_t e = ts + fl; e > 0; e >>= 1) {
+      if (e & 1) pw = c64mul(pw, b);
+      b = c64mul(b, b);
+    }
+    P[u] = s < a.ns ? pw : c64{0.0, 0.0};
+    Q[u] = q32;
+  }
+  const int64_t words = (n + 31) >> 5;
+  for (int64_t fb = ts; fb < te; fb += 32) {
+    bf16x8_t va[2][NTV];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      float v[8];
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const c64 p = P[4 * q + (i >> 1)];
+        v[i] = (i & 1) ? (float)(-p.im) : (float)p.re;
+      }
+      split_terms<NTV>(v, va[q]);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) P[u] = c64mul(P[u], Q[u]);
+    uint32_t wmine[2] = {0u, 0u};
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb) {
+      f32x16_t C;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) C[j] = 0.f;
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        if (q >= nq) break;
+        // small products first
+        if constexpr (NTV >= 3) {
+          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][2], tb[mb][q][0], C, 0, 0, 0);
+          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][2], C, 0, 0, 0);
+          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][1], tb[mb][q][1], C, 0, 0, 0);
+        }
+        if constexpr (NTV >= 2) {
+          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][1], tb[mb][q][0], C, 0, 0, 0);
+          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][1], C, 0, 0, 0);
+        }
+        C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][0], C, 0, 0, 0);
+      }
+      // C[j]: frame fb + 8(j/4) + 4h + j%4, pixel base + 64w + 32mb + fl
+      const int pxl = 64 * w + 32 * mb + fl;
+      const int64_t px = base + pxl;
+      const bool pv = px < n;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const int r = 8 * (j >> 2) + 4 * h + (j & 3);
+        const int64_t f = fb + r;
+        const bool ok = pv && f < te;
+        if (a.mode == 2) {
+          if (ok) reinterpret_cast<float*>(a.out)[(f - a.t0) * a.ldL + px] = C[j];
+          continue;
+        }
+        const float x = ok ? (float)sV[(size_t)f * RC_SA + pxl] : 0.f;
+        const bool fg = ok && fabsf(fmaf(x, a.xscale, -C[j])) > a.tau;
+        if (a.mode == 1) {
+          if (ok) reinterpret_cast<uint8_t*>(a.out)[f * n + px] = fg ? 1 : 0;
+          continue;
+        }
+        // lanes 0-31 hold frame fb + r0, lanes 32-63 frame fb + r0 + 4: one mask word each;
+        // lane r (half 0) collects the words of frame fb + r
+        const uint64_t bal = __ballot(fg);
+        const int r0 = 8 * (j >> 2) + (j & 3);
+        if (h == 0 && fl == r0) wmine[mb] = (uint32_t)bal;
+        if (h == 0 && fl == r0 + 4) wmine[mb] = (uint32_t)(bal >> 32);
+      }
+    }
+    if (a.mode == 0 && h == 0) {
+      const int64_t f = fb + fl;
+      if (f < te) {
+        uint32_t* wd = reinterpret_cast<uint32_t*>(a.out) + f * words + ((base + 64 * w) >> 5);
+        if (base + 64 * w < n) wd[0] = wmine[0];
+        if (base + 64 * w + 32 < n) wd[1] = wmine[1];
+      }
+    }
+  }
+}
+
+// Operands of the single-read reconstruction from G (N x k complex float64, row t at t*k,
+// device column col[s] of mode s): the A fragments of G~^T ([ks][term][lane][8] bf16;
+// element i of lane l is G~[16ks + 8(l/32) + i][column l%32]), G~ = [Re | Im] of
+// G[:, col_s] beta_s xscale in the column order of rc_col, NSP bf16 terms.
 __global__ __launch_bounds__(256) void k_recon_prep(const double* __restrict__ G, ReconPrep rp,
-                                                    uint16_t* __restrict__ Gsp, float* __restrict__ Vc) {
+                                                    uint16_t* __restrict__ Gsp) {
   const int ns = rp.ns, NSP = rp.NSP, N = rp.N, k = rp.k;
   const int64_t total = (int64_t)rp.KS * 64 * 8;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
@@ -850,14 +1004,14 @@ __global__ __launch_bounds__(256) void k_recon_prep(const double* __restrict__ G
     const int l = (int)((e >> 3) & 63);
     const int ks = (int)(e >> 9);
     const int row = 16 * ks + 8 * (l >> 5) + i;
-    const int col = l & 31;
+    const int c = l & 31;
+    const int hh = (c >> 2) & 1, j = 8 * (c >> 4) + 4 * ((c >> 3) & 1) + (c & 3);
+    const int s = 2 * (j >> 1) + hh, part = j & 1;
     double g = 0.0;
-    if (row < N && col < 2 * ns) {
-      const int s = col < ns ? col : col - ns;
+    if (row < N && s < ns) {
       const double* z = G + 2 * ((int64_t)row * k + rp.col[s]);
       const double br = rp.beta[2 * s], bi = rp.beta[2 * s + 1];
-      const double zr = (z[0] * br - z[1] * bi) * rp.xscale, zi = (z[0] * bi + z[1] * br) * rp.xscale;
-      g = col < ns ? zr : zi;
+      g = part == 0 ? (z[0] * br - z[1] * bi) * rp.xscale : (z[0] * bi + z[1] * br) * rp.xscale;
     }
     double rem = g;
     for (int sp = 0; sp < NSP; ++sp) {
@@ -866,49 +1020,39 @@ __global__ __launch_bounds__(256) void k_recon_prep(const double* __restrict__ G
       Gsp[(((int64_t)ks * NSP + sp) * 64 + l) * 8 + i] = bits;
     }
   }
-  if (blockIdx.x == 0) {
-    const int t = threadIdx.x, NS = rp.NS;
-    const int64_t m = rp.m;
-    if (t < ns) {
-      const double lr = rp.lam[2 * t], li = rp.lam[2 * t + 1];
-      double pr = 1.0, pi = 0.0;
-      for (int64_t f = 0; f < m; ++f) {
-        Vc[f * NS + t] = (float)pr;
-        Vc[f * NS + ns + t] = (float)(-pi);
-        if (!rp.static_bg) {
-          const double nr = pr * lr - pi * li, ni = pr * li + pi * lr;
-          pr = nr;
-          pi = ni;
-        }
-      }
-    } else if (t < ns + (NS - 2 * ns)) {
-      const int c = 2 * ns + (t - ns);
-      for (int64_t f = 0; f < m; ++f) Vc[f * NS + c] = 0.f;
-    }
-  }
 }
 
-hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gsp, float* Vc, hipStream_t s) {
-  if (rp.ns < 1 || rp.ns > 16 || 2 * rp.ns > rp.NS || rp.NS > 32) return hipErrorInvalidValue;
+hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gsp, hipStream_t s) {
+  if (rp.ns < 0 || rp.ns > 16) return hipErrorInvalidValue;
   const int64_t total = (int64_t)rp.KS * 64 * 8;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_recon_prep, dim3(grid), dim3(256), 0, s, G, rp, (uint16_t*)Gsp, Vc);
+  hipLaunchKernelGGL(k_recon_prep, dim3(grid), dim3(256), 0, s, G, rp, (uint16_t*)Gsp);
   return hipGetLastError();
 }
 
-hipError_t bgfg_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const void* Gp, int nsplit,
-                     int nksteps, int NS, const float* Vc, float tau, float xscale, int mode,
-                     void* out, int64_t t0, int64_t t1, int64_t ldL, hipStream_t s) {
-  const dim3 grid((unsigned)((n + LM_TILE - 1) / LM_TILE));
-#define BM_CASE(NSP, NSV)                                                                     \
-  if (nsplit == NSP && NS == NSV) {                                                           \
-    hipLaunchKernelGGL((k_bgfg_mfma<NSP, NSV>), grid, dim3(256), 0, s, D, ld, n, m,           \
-                       (const uint4*)Gp, nksteps, Vc, tau, xscale, mode, out, t0, t1, ldL);   \
-    return hipGetLastError();                                                                 \
+int recon_column(int s, int part) { return rc_col(s, part); }
+
+template <int NSG, int NTV>
+static hipError_t launch_recon(const ReconArgs& a, size_t lds, hipStream_t s) {
+  static bool attr = false;  // the larger dynamic LDS limit, set once per instantiation
+  if (!attr) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon<NSG, NTV>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr = true;
   }
-  BM_CASE(1, 4) BM_CASE(1, 8) BM_CASE(1, 12) BM_CASE(1, 16) BM_CASE(1, 20) BM_CASE(1, 24) BM_CASE(1, 32)
-  BM_CASE(3, 4) BM_CASE(3, 8) BM_CASE(3, 12) BM_CASE(3, 16) BM_CASE(3, 20) BM_CASE(3, 24) BM_CASE(3, 32)
-#undef BM_CASE
+  const dim3 grid((unsigned)((a.n + RC_TP - 1) / RC_TP));
+  hipLaunchKernelGGL((k_recon<NSG, NTV>), grid, dim3(RC_NT), lds, s, a);
+  return hipGetLastError();
+}
+
+hipError_t recon_mfma(const ReconArgs& a, int nsg, int ntv, hipStream_t s) {
+  if (a.ns < 0 || a.ns > 16 || a.n < 1 || a.m < 2 || a.KS != (int)((a.m - 1 + 15) / 16)) return hipErrorInvalidValue;
+  if (a.mode == 2 && (a.t0 < 0 || a.t1 > a.m || a.t0 >= a.t1)) return hipErrorInvalidValue;
+  const size_t lds = recon_lds_bytes(a.m, nsg);
+  if (lds > 160 * 1024) return hipErrorInvalidValue;
+  if (nsg == 3 && ntv == 3) return launch_recon<3, 3>(a, lds, s);
+  if (nsg == 1 && ntv == 2) return launch_recon<1, 2>(a, lds, s);
   return hipErrorInvalidValue;
 }
 

@@ -108,22 +108,36 @@ hipError_t reduce_partials(const double* part, int grid, int ne, double* out,
 hipError_t bgfg(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, const float* Gs,
                 int NS, const float* Vc, float tau, float xscale, int mode, void* out,
                 int64_t t0, int64_t t1, int64_t ldL, hipStream_t stream);
-// Same, phase 1 on MFMA (uint8 video, 16-byte aligned frames): Gp holds the B operands
-// of [Re G~_S | Im G~_S] as in lift_mfma with one 32-column block (|S| <= 16); NS is the
-// padded 2|S| of Vc (4, 8, 12, 16, 20, 24 or 32); nsplit in {1, 3}.
-hipError_t bgfg_mfma(const uint8_t* D, int64_t ld, int64_t n, int64_t m, const void* Gp, int nsplit,
-                     int nksteps, int NS, const float* Vc, float tau, float xscale, int mode,
-                     void* out, int64_t t0, int64_t t1, int64_t ldL, hipStream_t stream);
-// Reconstruction operands from the device solve's G (see k_recon_prep): ns <= 16 selected
-// modes, device columns col[s], amplitudes beta (re, im), eigenvalues lam (re, im).
+// Single-read form on MFMA (uint8 video, 16-byte aligned frames, |S| <= 16): 128-pixel
+// tiles whose frames stay in LDS; Gp holds the A fragments of G~^T (NSG bf16 terms, KS =
+// ceil((m-1)/16) k-steps, columns in the order of recon_column); the Vandermonde
+// factors come from lam (re, im of the ns selected eigenvalues; pass 1 for the static
+// model).  nsg/ntv: (3, 3) float32-class, (1, 2) bfloat16 form.
+struct ReconArgs {
+  const uint8_t* D;
+  int64_t ld, n, m;
+  const uint4* Gp;
+  int KS, ns;
+  double lam[32];
+  float tau, xscale;
+  int mode;
+  void* out;
+  int64_t t0, t1, ldL;
+};
+hipError_t recon_mfma(const ReconArgs& a, int nsg, int ntv, hipStream_t stream);
+// LDS bytes of one workgroup of recon_mfma (the form applies while this is <= 160 KiB).
+size_t recon_lds_bytes(int64_t m, int nsg);
+// Column of G~ holding part (0 Re, 1 Im) of selected mode s.
+int recon_column(int s, int part);
+// The A operands of recon_mfma from the device solve's G: ns <= 16 selected modes, device
+// columns col[s], amplitudes beta (re, im).
 struct ReconPrep {
-  int ns, NS, NSP, KS, N, k, static_bg;
-  int64_t m;
+  int ns, NSP, KS, N, k;
   double xscale;
   int col[16];
-  double beta[32], lam[32];
+  double beta[32];
 };
-hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gsp, float* Vc, hipStream_t stream);
+hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gsp, hipStream_t stream);
 // counts[t] = number of set bits of frame t of a bit-packed mask
 hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* counts,
                        hipStream_t stream);
