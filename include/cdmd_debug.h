@@ -67,6 +67,13 @@ cdmd_status cdmd_dbg_la_phases(const cdmd_model* mdl, double* ms16);
    Errors: INVALID_ARG. */
 cdmd_status cdmd_dbg_force_gather_sketch(cdmd_model* mdl, int32_t on);
 
+/* Choose the form of the sparse sketch of a uint8 video as the autotuner would: -1 the
+   gather form, or 10 F + V for the streaming form with F frames per workgroup and V
+   16-byte vectors per thread (the candidates are 41, 21, 22, 11, 12 and 14).  Takes effect
+   at the next cdmd_fit; a later cdmd_autotune replaces it.  Errors: INVALID_ARG (a form
+   that does not fit the table), UNSUPPORTED (not a uint8 sparse sketch). */
+cdmd_status cdmd_dbg_sparse_form(cdmd_model* mdl, int32_t form);
+
 /* Force (1) or release (0) the float64 small linear algebra on the host instead of the
    device workgroup solve (which runs for 16-byte aligned uint8 videos with m <= 1025).
    Takes effect at the next cdmd_fit.  Errors: INVALID_ARG. */

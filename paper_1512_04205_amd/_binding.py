@@ -33,7 +33,7 @@ EXPORTED = [
     "cdmd_info_get", "cdmd_set_timing", "cdmd_set_amplitudes", "cdmd_mask_median3", "cdmd_free",
     "cdmd_dbg_force_valu_lift",
     "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases", "cdmd_dbg_la_groups",
-    "cdmd_dbg_force_gather_sketch",
+    "cdmd_dbg_force_gather_sketch", "cdmd_dbg_sparse_form",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
     "cdmd_batch_free",
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
     lib.cdmd_dbg_la_groups.argtypes = [P, I32]
     lib.cdmd_dbg_force_gather_sketch.argtypes = [P, I32]
+    lib.cdmd_dbg_sparse_form.argtypes = [P, I32]
     lib.cdmd_dbg_la_phases.argtypes = [P, DP]
     lib.cdmd_mode_features.argtypes = [P, P, P]
     lib.cdmd_mlp_grad.argtypes = [P, P, P, I32, P, P, P]
@@ -301,6 +302,10 @@ class Model:
     def force_gather_sketch(self, on: bool = True):
         """Test hook: gather form of the sparse sketch instead of the streaming form."""
         _check(load_library().cdmd_dbg_force_gather_sketch(self._h, int(on)))
+
+    def sparse_form(self, form: int):
+        """Test hook: the sparse-sketch form (-1 gather, or 10 F + V streaming)."""
+        _check(load_library().cdmd_dbg_sparse_form(self._h, int(form)))
 
     def force_host_la(self, on: bool = True):
         """Test hook: float64 small linear algebra on the host instead of the device."""

@@ -117,8 +117,11 @@ struct cdmd_model {
   double* d_red = nullptr;
   int lgrid = 0;
   // reconstruction
-  void* d_Gsp = nullptr;     // MFMA B operands of [Re G~_S | Im G~_S]
-  uint16_t* h_Gsp = nullptr;
+  void* d_Gsp = nullptr;     // reconstruction operands: G~' fragments
+  void* d_Rv = nullptr;      // and V~ fragments
+  double* d_Gd = nullptr;    // G (N x k complex) of a host solve, for the operand kernel
+  double* h_Gd = nullptr;
+  int rc_nsg = 0, rc_ntv = 0, rc_ks = 0, rc_nfb = 0;
   bool recon_mfma = false;
   hipEvent_t e_stage = nullptr;   // the H2D copies of the reconstruction staging
   bool stage_pending = false;
@@ -168,6 +171,7 @@ struct cdmd_model {
   bool capturing = false;         // inside a graph capture: no timing events
   bool force_gather_sketch = false;  // test hook: gather form of the sparse sketch
   bool tuned = false;             // autotuner choices applied
+  uint64_t stamp = 0;             // bumped by every change of configuration after create
   void mark(int i, hipStream_t st) {
     if (timing && !capturing) (void)hipEventRecord(ev[i], st);
   }
@@ -188,12 +192,12 @@ struct cdmd_model {
     }
     if (st2) (void)hipStreamDestroy(st2);
     void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart, d_chunk_off, d_rblk,
-                   d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Vc, d_counts, d_modes,
+                   d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Rv, d_Gd, d_Vc, d_counts, d_modes,
                    d_feats, d_logits,
                    d_la_scratch, d_la_out, d_py, d_pyred};
     for (void* q : dev)
       if (q) (void)hipFree(q);
-    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gsp, h_Vc, h_counts, h_la_out, h_py};
+    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gd, h_Vc, h_counts, h_la_out, h_py};
     for (void* q : host)
       if (q) (void)hipHostFree(q);
   }
@@ -916,9 +920,16 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
     const size_t gp = (size_t)M->lm_nksteps * M->lm_nb * M->lm_nsplit * 64 * 8;
     TRY(dalloc((uint16_t**)&M->d_Gp, gp));
     TRY(halloc(&M->h_Gp, gp));
-    const size_t gsp = (size_t)M->lm_nksteps * M->lm_nsplit * 64 * 8;
-    TRY(dalloc((uint16_t**)&M->d_Gsp, gsp));
-    TRY(halloc(&M->h_Gsp, gsp));
+    // single-read reconstruction operands: G~' (KS = ceil(m/16) k-steps) and V~ (ceil(m/32)
+    // frame blocks), in (2, 3) bf16 terms for the float32 form and (1, 2) for bfloat16
+    M->rc_nsg = cfg->lift_prec == CDMD_PREC_BF16 ? 1 : 2;
+    M->rc_ntv = cfg->lift_prec == CDMD_PREC_BF16 ? 2 : 3;
+    M->rc_ks = cdmd::k::recon_ksteps(M->m);
+    M->rc_nfb = cdmd::k::recon_frame_blocks(M->m);
+    TRY(dalloc((uint16_t**)&M->d_Gsp, (size_t)(M->rc_ks + 4) * M->rc_nsg * 64 * 8));
+    TRY(dalloc((uint16_t**)&M->d_Rv, (size_t)(M->rc_nfb + 1) * 2 * M->rc_ntv * 64 * 8));
+    TRY(dalloc(&M->d_Gd, (size_t)2 * M->N * M->k));
+    TRY(halloc(&M->h_Gd, (size_t)2 * M->N * M->k));
     M->lr_nb = (M->k + 1 + 31) / 32;
     M->lr_ne = M->lr_nb * (M->lr_nb + 1) / 2 * 16 * 64;
     if (M->N <= 1024 && cfg->ld % 16 == 0) {
@@ -1258,6 +1269,7 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
   if (ch.lift_grid > 0) M->lm_grid = ch.lift_grid;
   if (ch.gauss_target > 0) TRY(apply_gauss_target(M, ch.gauss_target));
   M->tuned = true;
+  ++M->stamp;
   M->info.lift_grid = M->lift_real ? M->lr_grid : M->lm_grid;
   M->info.sketch_slices = M->gauss ? M->gplan.nsplit : 0;
   M->info.sparse_form = M->gauss ? 0 : (M->force_gather_sketch ? -1 : 10 * M->sk_F + M->sk_V);
@@ -1274,6 +1286,7 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
 struct cdmd_batch {
   std::vector<cdmd_model*> models;
   std::vector<const void*> videos;  // of the captured graph
+  std::vector<uint64_t> stamps;     // the members' configuration stamps at capture
   std::vector<int> dev;             // models on the graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -1293,6 +1306,7 @@ struct cdmd_batch {
     exec = nullptr;
     graph = nullptr;
     videos.clear();
+    stamps.clear();
   }
   ~cdmd_batch() {
     drop_graph();
@@ -1412,8 +1426,12 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
   hipStream_t st = as_stream(stream);
   if (per_model)
     for (int i = 0; i < n; ++i) per_model[i] = CDMD_E_STATE;  // not attempted
-  const bool same = B->exec && (int)B->videos.size() == n &&
-                    std::equal(B->videos.begin(), B->videos.end(), d_videos, d_videos + n);
+  for (int i = 0; i < n; ++i)
+    if (B->models[i]->amp_compressed)
+      return fail(CDMD_E_UNSUPPORTED, "amplitudes on the compressed modes are not built for batches");
+  bool same = B->exec && (int)B->videos.size() == n && (int)B->stamps.size() == n &&
+              std::equal(B->videos.begin(), B->videos.end(), d_videos, d_videos + n);
+  for (int i = 0; same && i < n; ++i) same = B->stamps[i] == B->models[i]->stamp;
   if (!same) {
     B->drop_graph();
     B->videos.assign(d_videos, d_videos + n);
@@ -1446,6 +1464,8 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
         return r;
       }
     }
+    B->stamps.resize(n);
+    for (int i = 0; i < n; ++i) B->stamps[i] = B->models[i]->stamp;
   }
   cdmd_status first = CDMD_OK;
   const double t0 = now_ms();
@@ -1585,63 +1605,44 @@ cdmd_status prepare_recon(cdmd_model* M, int static_bg, int* NSout, hipStream_t 
     if (!static_bg && std::abs(l) > 1.0 && std::pow(std::abs(l), (double)(m - 1)) > kVanderMax)
       return fail(CDMD_E_NUMERIC, "|lambda|^(m-1) overflows the Vandermonde matrix");
   }
-  M->recon_mfma = M->lift_mfma && ns <= 16 && cdmd::k::recon_lds_bytes(m, M->lm_nsplit) <= (size_t)160 * 1024;
+  M->recon_mfma = M->lift_mfma && ns <= 16 && cdmd::k::recon_lds_bytes(m) <= (size_t)160 * 1024;
   if (!M->recon_mfma && NS < 0) return fail(CDMD_E_UNSUPPORTED, "more than 40 selected modes");
   if (M->stage_pending) {
     HIPCHK(hipEventSynchronize(M->e_stage));
     M->stage_pending = false;
   }
   *NSout = NS;
-  if (M->recon_mfma && M->device_la) {
-    // from the device solve's G (column order of the solve: canonical index c is column
-    // perm[c]); nothing is built on the host
+  if (M->recon_mfma) {
     cdmd::k::ReconPrep rp{};
     rp.ns = ns;
-    rp.NSP = M->lm_nsplit;
-    rp.KS = M->lm_nksteps;
+    rp.NSG = M->rc_nsg;
+    rp.NTV = M->rc_ntv;
+    rp.KS = M->rc_ks;
+    rp.NFB = M->rc_nfb;
     rp.N = N;
     rp.k = k;
+    rp.static_bg = static_bg ? 1 : 0;
     rp.xscale = (double)M->xscale;
     for (int s = 0; s < ns; ++s) {
-      rp.col[s] = M->perm[M->S[s]];
       rp.beta[2 * s] = M->beta[s].real();
       rp.beta[2 * s + 1] = M->beta[s].imag();
+      rp.lam[2 * s] = M->lam[M->S[s]].real();
+      rp.lam[2 * s + 1] = M->lam[M->S[s]].imag();
     }
-    const cdmd::tla::SmallLAOutLayout L = cdmd::tla::small_la_out_layout(N, k);
-    HIPCHK(cdmd::k::recon_prep(M->d_la_out + L.G, rp, M->d_Gsp, st));
-    return CDMD_OK;
-  }
-  if (M->recon_mfma) {
-    const int NSP = M->lm_nsplit, KS = M->lm_nksteps;
-    std::vector<int> src_s(32, -1), src_part(32, 0);
-    for (int s = 0; s < ns; ++s)
-      for (int part = 0; part < 2; ++part) {
-        const int c = cdmd::k::recon_column(s, part);
-        src_s[c] = s;
-        src_part[c] = part;
-      }
-    for (int ks = 0; ks < KS; ++ks)
-      for (int l = 0; l < 64; ++l) {
-        const int c = l & 31;
-        for (int i = 0; i < 8; ++i) {
-          const int row = 16 * ks + 8 * (l >> 5) + i;
-          double g = 0.0;
-          if (row < N && src_s[c] >= 0) {
-            const int sidx = src_s[c];
-            const cplx z = M->G[(size_t)row * k + M->S[sidx]] * M->beta[sidx] * (double)M->xscale;
-            g = src_part[c] == 0 ? z.real() : z.imag();
-          }
-          double rem = g;
-          for (int sp = 0; sp < NSP; ++sp) {
-            const uint16_t bits = bf16_bits(rem);
-            rem -= bf16_value(bits);
-            M->h_Gsp[(((size_t)ks * NSP + sp) * 64 + l) * 8 + i] = bits;
-          }
-        }
-      }
-    HIPCHK(hipMemcpyAsync(M->d_Gsp, M->h_Gsp, (size_t)KS * NSP * 64 * 16, hipMemcpyHostToDevice, st));
-    HIPCHK(hipEventRecord(M->e_stage, st));
-    M->stage_pending = true;
+    const double* Gdev = nullptr;
+    if (M->device_la) {
+      // the device solve's G (column order of the solve: canonical index c is column perm[c])
+      for (int s = 0; s < ns; ++s) rp.col[s] = M->perm[M->S[s]];
+      Gdev = M->d_la_out + cdmd::tla::small_la_out_layout(N, k).G;
+    } else {
+      for (int s = 0; s < ns; ++s) rp.col[s] = M->S[s];
+      std::memcpy(M->h_Gd, M->G.data(), sizeof(double) * 2 * (size_t)N * k);
+      HIPCHK(hipMemcpyAsync(M->d_Gd, M->h_Gd, sizeof(double) * 2 * (size_t)N * k, hipMemcpyHostToDevice, st));
+      HIPCHK(hipEventRecord(M->e_stage, st));
+      M->stage_pending = true;
+      Gdev = M->d_Gd;
+    }
+    HIPCHK(cdmd::k::recon_prep(Gdev, rp, M->d_Gsp, M->d_Rv, st));
     return CDMD_OK;
   }
   for (int t = 0; t < N; ++t) {
@@ -1680,13 +1681,10 @@ cdmd_status run_recon(cdmd_model* M, const void* d_video, int static_bg, int NS,
     a.n = M->n;
     a.m = M->m;
     a.Gp = static_cast<const uint4*>(M->d_Gsp);
-    a.KS = M->lm_nksteps;
+    a.Vp = static_cast<const uint4*>(M->d_Rv);
+    a.KS = M->rc_ks;
+    a.NFB = M->rc_nfb;
     a.ns = (int)M->S.size();
-    for (int s = 0; s < a.ns; ++s) {
-      const cplx l = static_bg ? cplx(1.0, 0.0) : M->lam[M->S[s]];
-      a.lam[2 * s] = l.real();
-      a.lam[2 * s + 1] = l.imag();
-    }
     a.tau = tau;
     a.xscale = M->xscale;
     a.mode = mode;
@@ -1694,8 +1692,7 @@ cdmd_status run_recon(cdmd_model* M, const void* d_video, int static_bg, int NS,
     a.t0 = t0;
     a.t1 = t1;
     a.ldL = ldL;
-    const int ntv = M->lm_nsplit == 3 ? 3 : 2;
-    HIPCHK(cdmd::k::recon_mfma(a, M->lm_nsplit, ntv, st));
+    HIPCHK(cdmd::k::recon_mfma(a, M->rc_nsg, M->rc_ntv, st));
     return CDMD_OK;
   }
   HIPCHK(cdmd::k::bgfg(d_video, M->cfg.dtype, M->ld, M->n, M->m, M->d_Gs, NS, M->d_Vc, tau, M->xscale, mode, out,
@@ -1929,6 +1926,7 @@ cdmd_status cdmd_set_amplitudes(cdmd_model* M, int32_t space) {
     }
   }
   M->amp_compressed = space == CDMD_AMP_COMPRESSED;
+  ++M->stamp;
   M->fitted = M->selected = false;
   M->info.fitted = M->info.selected = 0;
   return CDMD_OK;
@@ -1979,6 +1977,23 @@ cdmd_status cdmd_dbg_force_gather_sketch(cdmd_model* M, int32_t on) {
   g_err.clear();
   if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
   M->force_gather_sketch = on != 0;
+  ++M->stamp;
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_sparse_form(cdmd_model* M, int32_t form) {
+  g_err.clear();
+  if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  if (M->gauss || M->cfg.dtype != CDMD_U8) return fail(CDMD_E_UNSUPPORTED, "the form applies to uint8 sparse sketches");
+  if (form != -1) {
+    const int F = form / 10, V = form % 10;
+    if (form < 11 || !cdmd::k::sketch_stream_fits(F, V, M->max_rows))
+      return fail(CDMD_E_INVALID_ARG, "unknown or unfitting streaming form");
+    if (stream_nrange(M, F, V) > M->sk_slots_cap) return fail(CDMD_E_INVALID_ARG, "form needs more partial slots");
+  }
+  TRY(apply_sparse_form(M, form));
+  M->info.sparse_form = form < 0 ? -1 : 10 * M->sk_F + M->sk_V;
+  ++M->stamp;
   return CDMD_OK;
 }
 
@@ -1986,6 +2001,7 @@ cdmd_status cdmd_dbg_force_host_la(cdmd_model* M, int32_t on) {
   g_err.clear();
   if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
   M->force_host_la = on != 0;
+  ++M->stamp;
   return CDMD_OK;
 }
 
@@ -1993,6 +2009,7 @@ cdmd_status cdmd_dbg_la_groups(cdmd_model* M, int32_t groups) {
   g_err.clear();
   if (!M || groups < 0 || groups > 32) return fail(CDMD_E_INVALID_ARG, "groups must be in [0, 32]");
   M->la_groups = groups;
+  ++M->stamp;
   return CDMD_OK;
 }
 
@@ -2000,6 +2017,7 @@ cdmd_status cdmd_dbg_force_valu_lift(cdmd_model* M, int32_t on) {
   g_err.clear();
   if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
   M->force_valu_lift = on != 0;
+  ++M->stamp;
   return CDMD_OK;
 }
 

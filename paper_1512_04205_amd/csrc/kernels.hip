@@ -721,37 +721,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3
 // ============================================================================
 // Background reconstruction and foreground threshold in one read of the video
 // (eq. (equ:DMDTerms) with its real-part footnote, eq. (eq:thres)).  A workgroup of
-// two waves owns 128 pixels; every frame of its tile stays in LDS ([frame][RC_SA]
-// bytes) from the moment it streams in, so HBM delivers each video byte once.
+// two waves owns 128 pixels and first copies all their frames into LDS, transposed to
+// one row per pixel (frame t at byte t of the row), so HBM delivers each video byte once:
 //
-//   phase 1: T^T = G~^T X' on bf16 MFMA 32x32x16.  G~ = [Re | Im] of G_S diag(beta_S)
-//            xscale in NSG bf16 terms (A operands, columns in the order of rc_col), X'
-//            exact in bf16 (B operands gathered from LDS); float32 accumulation.  Wave w
-//            keeps acc[mb] = T^T of its pixel blocks 64w + 32mb (rows: columns c, lane
-//            columns: pixels).
-//   phase 2: L = V~ T on bf16 MFMA 32x32x16, per 32-frame block.  The B operands are the
-//            phase-1 accumulators themselves split into NTV bf16 terms: a lane of the
-//            phase-1 result holds one pixel and 16 columns, which is exactly a B fragment
-//            once the K order of phase 2 is the fixed permutation sigma(16q + 8h + i) =
-//            16q + 8(i/4) + 4h + i%4.  The A operands V~[t][c] = Re lambda_s^t or
-//            -Im lambda_s^t are formed per lane from float64 powers (lambda^(t0 + lane),
-//            then times lambda^32 per block), so no Vandermonde matrix is read.  The
-//            products of the split terms whose orders sum below NTV are accumulated in
-//            float32 (NTV = 3: six products, float32-class L; NTV = 2: three).
+//   phase 1: T^T = G~'^T X on bf16 MFMA 32x32x16, where G~'[t] = [Re | Im] of
+//            G_S[t-1] diag(beta_S) xscale (G~'[0] = 0, so the k-steps start at frame 0
+//            and every B fragment is one aligned 8-byte LDS read: 8 frames of a pixel)
+//            in NSG bf16 terms; float32 accumulation.  Wave w keeps acc[mb] = T^T of
+//            its pixel blocks 64w + 32mb (rows: columns c; lane columns: pixels).
+//   phase 2: L = V~ T on bf16 MFMA 32x32x16 per 32-frame block.  The B operands are
+//            the phase-1 accumulators split into NTV bf16 terms: a lane of the phase-1
+//            result holds one pixel and 16 columns, exactly a B fragment once the K order
+//            of phase 2 is the fixed permutation sigma(16q + 8h + i) = 16q + 8(i/4) +
+//            4h + i%4.  The A operands V~[t][c] (Re lambda_s^t or -Im lambda_s^t, NTV
+//            terms, in that K order) come prepared.  Products of split terms whose orders
+//            sum below NTV accumulate in float32 (NTV = 3: six products; NTV = 2: three).
 //   output:  |x - L| > tau per element, bit-packed by wave ballots (mode 0), as bytes
 //            (mode 1), or L itself (mode 2).
 //
-// Columns: mode s (< 16) goes to lane half h = s & 1 at slot j = 2 (s >> 1) + part
-// (part 0 = Re, 1 = Im), i.e. column rc_col(s, part); a lane of half h then needs the
-// powers of the modes s = 2u + h, u < 8, only.
-constexpr int RC_TP = 128;   // pixels per workgroup
-constexpr int RC_NT = 128;   // two waves
-constexpr int RC_SA = 136;   // LDS bytes per frame row: 8-byte aligned, conflict-free reads
-constexpr int RC_KPC = 2;    // k-steps (16 frames each) per streamed chunk
+// Columns: mode s (< 16) sits in lane half h = s & 1 at slot j = 2 (s >> 1) + part
+// (part 0 = Re, 1 = Im), i.e. column rc_col(s, part).
+constexpr int RC_TP = 128;  // pixels per workgroup
+constexpr int RC_NT = 128;  // two waves
+constexpr int RC_PF = 4;    // k-steps of G~' operands loaded ahead
+constexpr int RC_LB = 8;    // 4x16-byte blocks a thread loads per batch of the tile load
 
 __host__ __device__ inline int rc_col(int s, int part) {
   const int h = s & 1, j = 2 * (s >> 1) + part;
   return 16 * (j >> 3) + 8 * ((j >> 2) & 1) + 4 * h + (j & 3);
+}
+// LDS bytes per pixel row for `rows` frames: congruent to 8 modulo 256, so the 32 rows
+// a half-wave reads with 8-byte (or 4-byte) loads fall on distinct banks.
+__host__ __device__ inline int rc_stride(int rows) { return ((rows + 247) / 256) * 256 + 8; }
+
+size_t recon_lds_bytes(int64_t m) {
+  const int64_t rows = 64 * ((m + 63) / 64);
+  return (size_t)RC_TP * rc_stride((int)rows);
 }
 
 template <int NT>
@@ -765,129 +770,148 @@ __device__ __forceinline__ void split_terms(const float* v, bf16x8_t (&o)[NT]) {
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
       const uint32_t b0 = bf16_rne_bits(r[2 * i]), b1 = bf16_rne_bits(r[2 * i + 1]);
-      r[2 * i] -= __uint_as_float(b0 << 16);
-      r[2 * i + 1] -= __uint_as_float(b1 << 16);
+      if (t + 1 < NT) {
+        r[2 * i] -= __uint_as_float(b0 << 16);
+        r[2 * i + 1] -= __uint_as_float(b1 << 16);
+      }
       wv[i] = b0 | (b1 << 16);
     }
     o[t] = __builtin_bit_cast(bf16x8_t, make_uint4(wv[0], wv[1], wv[2], wv[3]));
   }
 }
 
-struct c64 {
-  double re, im;
-};
-__device__ __forceinline__ c64 c64mul(c64 a, c64 b) {
-  return c64{a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
-}
-
-size_t recon_lds_bytes(int64_t m, int nsg) {
-  const int64_t ks = (m - 1 + 15) / 16, nch = (ks + RC_KPC - 1) / RC_KPC;
-  return (size_t)RC_KPC * nsg * 64 * 16 + (size_t)(1 + 32 * nch) * RC_SA;
-}
-
-template <int NSG, int NTV>
-__global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a) {
-  extern __shared__ __align__(16) uint4 rc_lds[];
-  uint4* sG = rc_lds;
-  uint8_t* sV = reinterpret_cast<uint8_t*>(rc_lds + RC_KPC * NSG * 64);
-  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, fl = l & 31;
-  const int64_t base = (int64_t)blockIdx.x * RC_TP;
-  const int64_t n = a.n, m = a.m, N = m - 1, ld = a.ld;
-  const int KS = a.KS;
-  const int nch = (KS + RC_KPC - 1) / RC_KPC;
-  constexpr int GPT = (RC_KPC * NSG * 64 + RC_NT - 1) / RC_NT;  // G~ operands per thread and chunk
-
-  // frame 0 (x_1), needed by the threshold only
-  if (tid < 8) {
-    const int64_t px = base + 16 * tid;
-    uint4 v = make_uint4(0, 0, 0, 0);
-    if (px + 16 <= n) {
-      v = *reinterpret_cast<const uint4*>(a.D + px);
-    } else {
-      uint32_t wd[4] = {0, 0, 0, 0};
-      for (int b = 0; b < 16; ++b)
-        if (px + b < n) wd[b >> 2] |= (uint32_t)a.D[px + b] << (8 * (b & 3));
-      v = make_uint4(wd[0], wd[1], wd[2], wd[3]);
-    }
-    uint2* dst = reinterpret_cast<uint2*>(sV + 16 * tid);
-    dst[0] = make_uint2(v.x, v.y);
-    dst[1] = make_uint2(v.z, v.w);
+// 8 frames of one pixel (bytes, frame order) as bf16 (integers 0..255 are exact)
+__device__ __forceinline__ bf16x8_t u8x8_bf16(uint2 v) {
+  uint32_t wv[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const uint32_t src = q < 2 ? v.x : v.y;
+    const int sh = 16 * (q & 1);
+    const float lo = (float)((src >> sh) & 0xffu), hi = (float)((src >> (sh + 8)) & 0xffu);
+    wv[q] = __builtin_amdgcn_perm(__float_as_uint(hi), __float_as_uint(lo), 0x07060302u);
   }
-  // chunk c: frames 1 + 32c + r, r < 32; thread loads rows r = tid/8 and 16 + tid/8,
-  // 16 pixels at 16 (tid % 8)
-  const int fr = tid >> 3, seg = 16 * (tid & 7);
-  uint4 rv[2];
-  uint4 rg[GPT];
-  auto gload = [&](int c) {
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const int64_t f = 1 + 32 * (int64_t)c + fr + 16 * q;
-      const int64_t px = base + seg;
-      if (f <= N && px + 16 <= n) {
-        rv[q] = *reinterpret_cast<const uint4*>(a.D + f * ld + px);
-      } else {
-        uint32_t wd[4] = {0, 0, 0, 0};
-        if (f <= N)
-          for (int b = 0; b < 16; ++b)
-            if (px + b < n) wd[b >> 2] |= (uint32_t)a.D[f * ld + px + b] << (8 * (b & 3));
-        rv[q] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < GPT; ++q) {
-      const int e = tid + q * RC_NT;
-      if (e < RC_KPC * NSG * 64) {
-        const int ks = RC_KPC * c + e / (NSG * 64);
-        rg[q] = ks < KS ? a.Gp[(int64_t)RC_KPC * c * NSG * 64 + e] : make_uint4(0, 0, 0, 0);
-      }
-    }
-  };
+  return __builtin_bit_cast(bf16x8_t, make_uint4(wv[0], wv[1], wv[2], wv[3]));
+}
 
+// v_writelane_b32 through the compiler's intrinsic (so that it inserts the wait states a
+// VALU-written SGPR needs before v_writelane reads it)
+extern "C" __device__ int cdmd_amdgcn_writelane(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
+// v with lane LANE replaced by the wave-uniform value u
+template <int LANE>
+__device__ __forceinline__ uint32_t writelane_u32(uint32_t v, uint32_t u) {
+  return (uint32_t)cdmd_amdgcn_writelane((int)u, LANE, (int)v);
+}
+template <int I, int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// keep v in registers as computed (the compiler may not recompute it later)
+__device__ __forceinline__ void pin(bf16x8_t& v) {
+  uint4 u = __builtin_bit_cast(uint4, v);
+  asm volatile("" : "+v"(u.x), "+v"(u.y), "+v"(u.z), "+v"(u.w));
+  v = __builtin_bit_cast(bf16x8_t, u);
+}
+
+// MODE 0: bit-packed mask, 1: byte mask, 2: L.  RAGGED: the workgroup's 128 pixels run
+// past n (only the last one), so its loads and stores check every pixel.
+template <int NSG, int NTV, int MODE, bool RAGGED>
+__global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
+  extern __shared__ __align__(16) uint4 rc_lds[];
+  uint8_t* sV = reinterpret_cast<uint8_t*>(rc_lds);
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, fl = l & 31;
+  const int64_t base = (tile0 + blockIdx.x) * RC_TP;
+  const int64_t n = a.n, ld = a.ld;
+  const int m = (int)a.m;
+  const int KS = a.KS;               // 16-frame k-steps of phase 1, a multiple of 4
+  const int S = rc_stride(16 * KS);
+
+  // ---- the tile's frames into LDS, transposed: per block a thread takes 16 pixels
+  // (chunk tid % 8) x 4 frames, transposes 4x4 bytes and stores one word per pixel
+  {
+    const int pc = tid & 7;
+    const int64_t px = base + 16 * pc;
+    const int nquads = 4 * KS;       // a multiple of 16: the bounds below are uniform
+    const uint8_t* src = a.D + px;
+    uint8_t* dstc = sV + (size_t)(16 * pc) * S;
+    for (int q0 = tid >> 3; q0 < nquads; q0 += 16 * RC_LB) {
+      uint4 r[RC_LB][4];
+#pragma unroll
+      for (int b = 0; b < RC_LB; ++b) {
+        const int fq = q0 + 16 * b;
+        if (fq >= nquads) break;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const int f = min(4 * fq + i, m - 1);  // beyond the video: finite bytes (their G~' rows are 0)
+          if (!RAGGED) {
+            r[b][i] = *reinterpret_cast<const uint4*>(src + (int64_t)f * ld);
+          } else {
+            uint32_t wd[4] = {0, 0, 0, 0};
+            for (int e = 0; e < 16; ++e)
+              if (px + e < n) wd[e >> 2] |= (uint32_t)src[(int64_t)f * ld + e] << (8 * (e & 3));
+            r[b][i] = make_uint4(wd[0], wd[1], wd[2], wd[3]);
+          }
+        }
+      }
+#pragma unroll
+      for (int b = 0; b < RC_LB; ++b) {
+        const int fq = q0 + 16 * b;
+        if (fq >= nquads) break;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {  // dword d of the rows: pixels 4d..4d+3 of the chunk
+          const uint32_t r0 = (&r[b][0].x)[d], r1 = (&r[b][1].x)[d], r2 = (&r[b][2].x)[d], r3 = (&r[b][3].x)[d];
+          const uint32_t t01lo = __builtin_amdgcn_perm(r1, r0, 0x05010400u), t01hi = __builtin_amdgcn_perm(r1, r0, 0x07030602u);
+          const uint32_t t23lo = __builtin_amdgcn_perm(r3, r2, 0x05010400u), t23hi = __builtin_amdgcn_perm(r3, r2, 0x07030602u);
+          uint8_t* row = dstc + (size_t)(4 * d) * S + 4 * fq;
+          *reinterpret_cast<uint32_t*>(row) = __builtin_amdgcn_perm(t23lo, t01lo, 0x05040100u);
+          *reinterpret_cast<uint32_t*>(row + S) = __builtin_amdgcn_perm(t23lo, t01lo, 0x07060302u);
+          *reinterpret_cast<uint32_t*>(row + 2 * S) = __builtin_amdgcn_perm(t23hi, t01hi, 0x05040100u);
+          *reinterpret_cast<uint32_t*>(row + 3 * S) = __builtin_amdgcn_perm(t23hi, t01hi, 0x07060302u);
+        }
+      }
+    }
+  }
+  __syncthreads();
+
+  // ---- phase 1 (Gp holds KS + RC_PF k-steps, the last RC_PF zero)
   f32x16_t acc[2];
 #pragma unroll
   for (int mb = 0; mb < 2; ++mb)
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[mb][j] = 0.f;
-  gload(0);
-  for (int c = 0; c < nch; ++c) {
-    __syncthreads();  // the previous chunk's operands are consumed
+  const uint8_t* rowp0 = sV + (64 * w + fl) * S + 8 * h;
+  const uint8_t* rowp1 = rowp0 + 32 * S;
+  {
+    const uint4* gp = a.Gp + l;
+    uint4 gq[RC_PF][NSG];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      uint2* dst = reinterpret_cast<uint2*>(sV + (size_t)(1 + 32 * c + fr + 16 * q) * RC_SA + seg);
-      dst[0] = make_uint2(rv[q].x, rv[q].y);
-      dst[1] = make_uint2(rv[q].z, rv[q].w);
-    }
+    for (int p = 0; p < RC_PF; ++p)
 #pragma unroll
-    for (int q = 0; q < GPT; ++q) {
-      const int e = tid + q * RC_NT;
-      if (e < RC_KPC * NSG * 64) sG[e] = rg[q];
-    }
-    __syncthreads();
-    if (c + 1 < nch) gload(c + 1);
+      for (int t = 0; t < NSG; ++t) gq[p][t] = gp[(p * NSG + t) * 64];
+    for (int K0 = 0; K0 < KS; K0 += RC_PF) {
 #pragma unroll
-    for (int kk = 0; kk < RC_KPC; ++kk) {
-      if (RC_KPC * c + kk >= KS) break;
-      const int f0 = 1 + 16 * (RC_KPC * c + kk) + 8 * h;
-      bf16x8_t xb[2];
+      for (int p = 0; p < RC_PF; ++p) {
+        const int K = K0 + p;
+        const bf16x8_t xb0 = u8x8_bf16(*reinterpret_cast<const uint2*>(rowp0 + 16 * K));
+        const bf16x8_t xb1 = u8x8_bf16(*reinterpret_cast<const uint2*>(rowp1 + 16 * K));
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {
-        const uint8_t* col = sV + (size_t)f0 * RC_SA + 64 * w + 32 * mb + fl;
-        uint32_t wv[4];
+        for (int t = NSG - 1; t >= 0; --t) {
+          const bf16x8_t ga = __builtin_bit_cast(bf16x8_t, gq[p][t]);
+          acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga, xb0, acc[0], 0, 0, 0);
+          acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga, xb1, acc[1], 0, 0, 0);
+        }
 #pragma unroll
-        for (int i = 0; i < 4; ++i) wv[i] = pack_u8pair_bf16(col[(2 * i) * RC_SA], col[(2 * i + 1) * RC_SA]);
-        xb[mb] = __builtin_bit_cast(bf16x8_t, make_uint4(wv[0], wv[1], wv[2], wv[3]));
-      }
-#pragma unroll
-      for (int t = NSG - 1; t >= 0; --t) {
-        const bf16x8_t ga = __builtin_bit_cast(bf16x8_t, sG[(kk * NSG + t) * 64 + l]);
-#pragma unroll
-        for (int mb = 0; mb < 2; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga, xb[mb], acc[mb], 0, 0, 0);
+        for (int t = 0; t < NSG; ++t) gq[p][t] = gp[((K + RC_PF) * NSG + t) * 64];
       }
     }
   }
-  __syncthreads();  // every frame of the tile is in LDS
 
-  // phase 2 operands: T fragments (B), split into NTV terms
+  // ---- phase 2 (Vp holds NFB + 1 frame blocks, the last zero).  The MFMAs of frame
+  // block i + 1 are issued before the threshold of block i, so the matrix cores and the
+  // vector ALU overlap.
   const int nq = a.ns <= 8 ? 1 : 2;
   bf16x8_t tb[2][2][NTV];
 #pragma unroll
@@ -898,161 +922,240 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a) {
 #pragma unroll
       for (int i = 0; i < 8; ++i) v[i] = acc[mb][8 * q + i];
       split_terms<NTV>(v, tb[mb][q]);
-    }
-  // powers of this lane's modes s = 2u + h at its frame t_start + fl, and lambda^32
-  const int64_t ts = a.mode == 2 ? a.t0 : 0, te = a.mode == 2 ? a.t1 : m;
-  c64 P[8], Q[8];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int s = 2 * u + h;
-    c64 lam = s < a.ns ? c64{a.lam[2 * s], a.lam[2 * s + 1]} : c64{0.0, 0.0};
-    c64 q32 = lam;
-#pragma unroll
-    for (int r = 0; r < 5; ++r) q32 = c64mul(q32, q32);
-    c64 pw{1.0, 0.0}, b = lam;
-    for (int64_t e = ts + fl; e > 0; e >>= 1) {
-      if (e & 1) pw = c64mul(pw, b);
-      b = c64mul(b, b);
+      for (int t = 0; t < NTV; ++t) pin(tb[mb][q][t]);
     }
-    P[u] = s < a.ns ? pw : c64{0.0, 0.0};
-    Q[u] = q32;
-  }
+  const int ts = MODE == 2 ? (int)a.t0 : 0, te = MODE == 2 ? (int)a.t1 : m;
   const int64_t words = (n + 31) >> 5;
-  for (int64_t fb = ts; fb < te; fb += 32) {
+  const int fb0 = ts >> 5, fb1 = (te + 31) >> 5;
+  const uint4* vp = a.Vp + l;
+  const int pxw = 64 * w;                       // this wave's first pixel in the tile
+  const bool pv0 = !RAGGED || base + pxw + fl < n, pv1 = !RAGGED || base + pxw + 32 + fl < n;
+
+  // L of frame block fbi for both pixel blocks
+  auto products = [&](int fbi, f32x16_t (&C)[2]) {
     bf16x8_t va[2][NTV];
 #pragma unroll
+    for (int q = 0; q < 2; ++q)
+#pragma unroll
+      for (int t = 0; t < NTV; ++t)
+        va[q][t] = __builtin_bit_cast(bf16x8_t, vp[(((int64_t)fbi * 2 + q) * NTV + t) * 64]);
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+      for (int j = 0; j < 16; ++j) C[mb][j] = 0.f;
+#pragma unroll
     for (int q = 0; q < 2; ++q) {
-      float v[8];
+      if (q >= nq) break;
 #pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const c64 p = P[4 * q + (i >> 1)];
-        v[i] = (i & 1) ? (float)(-p.im) : (float)p.re;
+      for (int mb = 0; mb < 2; ++mb) {  // two independent accumulation chains
+        if constexpr (NTV >= 3) {  // small products first
+          C[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][2], tb[mb][q][0], C[mb], 0, 0, 0);
+          C[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][2], C[mb], 0, 0, 0);
+          C[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][1], tb[mb][q][1], C[mb], 0, 0, 0);
+        }
+        if constexpr (NTV >= 2) {
+          C[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][1], tb[mb][q][0], C[mb], 0, 0, 0);
+          C[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][1], C[mb], 0, 0, 0);
+        }
+        C[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][0], C[mb], 0, 0, 0);
       }
-      split_terms<NTV>(v, va[q]);
     }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) P[u] = c64mul(P[u], Q[u]);
+  };
+  // the output of frame block fbi; EDGE: the block runs past [ts, te) (checks per frame)
+  auto emit = [&](int fbi, const f32x16_t (&C)[2], auto edge_c) {
+    constexpr bool EDGE = decltype(edge_c)::value;
+    const int fb = 32 * fbi;
     uint32_t wmine[2] = {0u, 0u};
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb) {
-      f32x16_t C;
-#pragma unroll
-      for (int j = 0; j < 16; ++j) C[j] = 0.f;
-#pragma unroll
-      for (int q = 0; q < 2; ++q) {
-        if (q >= nq) break;
-        // small products first
-        if constexpr (NTV >= 3) {
-          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][2], tb[mb][q][0], C, 0, 0, 0);
-          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][2], C, 0, 0, 0);
-          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][1], tb[mb][q][1], C, 0, 0, 0);
-        }
-        if constexpr (NTV >= 2) {
-          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][1], tb[mb][q][0], C, 0, 0, 0);
-          C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][1], C, 0, 0, 0);
-        }
-        C = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][0], C, 0, 0, 0);
-      }
-      // C[j]: frame fb + 8(j/4) + 4h + j%4, pixel base + 64w + 32mb + fl
-      const int pxl = 64 * w + 32 * mb + fl;
+      // C[mb][j]: frame fb + 8(j/4) + 4h + j%4, pixel base + 64w + 32mb + fl
+      const int pxl = pxw + 32 * mb + fl;
       const int64_t px = base + pxl;
-      const bool pv = px < n;
+      const bool pv = mb == 0 ? pv0 : pv1;
+      if constexpr (MODE == 2) {
+        float* out = reinterpret_cast<float*>(a.out) + px;
+        static_for<0, 16>([&](auto jc) {
+          constexpr int j = decltype(jc)::value;
+          const int f = fb + 8 * (j >> 2) + 4 * h + (j & 3);
+          if ((!RAGGED || pv) && (!EDGE || (f >= ts && f < te))) out[(int64_t)(f - ts) * a.ldL] = C[mb][j];
+        });
+      } else {
+        uint32_t xw[4];
 #pragma unroll
-      for (int j = 0; j < 16; ++j) {
-        const int r = 8 * (j >> 2) + 4 * h + (j & 3);
-        const int64_t f = fb + r;
-        const bool ok = pv && f < te;
-        if (a.mode == 2) {
-          if (ok) reinterpret_cast<float*>(a.out)[(f - a.t0) * a.ldL + px] = C[j];
-          continue;
-        }
-        const float x = ok ? (float)sV[(size_t)f * RC_SA + pxl] : 0.f;
-        const bool fg = ok && fabsf(fmaf(x, a.xscale, -C[j])) > a.tau;
-        if (a.mode == 1) {
-          if (ok) reinterpret_cast<uint8_t*>(a.out)[f * n + px] = fg ? 1 : 0;
-          continue;
-        }
-        // lanes 0-31 hold frame fb + r0, lanes 32-63 frame fb + r0 + 4: one mask word each;
-        // lane r (half 0) collects the words of frame fb + r
-        const uint64_t bal = __ballot(fg);
-        const int r0 = 8 * (j >> 2) + (j & 3);
-        if (h == 0 && fl == r0) wmine[mb] = (uint32_t)bal;
-        if (h == 0 && fl == r0 + 4) wmine[mb] = (uint32_t)(bal >> 32);
+        for (int g = 0; g < 4; ++g) xw[g] = *reinterpret_cast<const uint32_t*>(sV + pxl * S + fb + 8 * g + 4 * h);
+        uint32_t wm = 0u;
+        static_for<0, 16>([&](auto jc) {
+          constexpr int j = decltype(jc)::value, g = j >> 2, e = j & 3;
+          const float x = (float)((xw[g] >> (8 * e)) & 0xffu);
+          bool fgd = fabsf(fmaf(x, a.xscale, -C[mb][j])) > a.tau;
+          if constexpr (RAGGED || EDGE) {
+            const int f = fb + 8 * g + 4 * h + e;
+            fgd = fgd && (!RAGGED || pv) && (!EDGE || f < te);
+          }
+          if constexpr (MODE == 1) {
+            const int f = fb + 8 * g + 4 * h + e;
+            if ((!RAGGED || pv) && (!EDGE || f < te)) reinterpret_cast<uint8_t*>(a.out)[(int64_t)f * n + px] = fgd ? 1 : 0;
+          } else {
+            // lanes 0-31 hold frame fb + 8g + e, lanes 32-63 frame fb + 8g + 4 + e: one
+            // mask word each; lane r of half 0 collects the word of frame fb + r
+            const uint64_t bal = __ballot(fgd);
+            wm = writelane_u32<8 * g + e>(wm, (uint32_t)bal);
+            wm = writelane_u32<8 * g + 4 + e>(wm, (uint32_t)(bal >> 32));
+          }
+        });
+        wmine[mb] = wm;
       }
     }
-    if (a.mode == 0 && h == 0) {
-      const int64_t f = fb + fl;
-      if (f < te) {
-        uint32_t* wd = reinterpret_cast<uint32_t*>(a.out) + f * words + ((base + 64 * w) >> 5);
-        if (base + 64 * w < n) wd[0] = wmine[0];
-        if (base + 64 * w + 32 < n) wd[1] = wmine[1];
+    if constexpr (MODE == 0) {
+      const int f = fb + fl;
+      if (h == 0 && (!EDGE || f < te)) {
+        uint32_t* wd = reinterpret_cast<uint32_t*>(a.out) + (int64_t)f * words + ((base + pxw) >> 5);
+        if (!RAGGED || base + pxw < n) wd[0] = wmine[0];
+        if (!RAGGED || base + pxw + 32 < n) wd[1] = wmine[1];
       }
     }
+  };
+  auto emit_any = [&](int fbi, const f32x16_t (&C)[2]) {
+    if (32 * fbi < ts || 32 * fbi + 32 > te) emit(fbi, C, std::true_type{});
+    else emit(fbi, C, std::false_type{});
+  };
+  f32x16_t Ca[2], Cb[2];
+  products(fb0, Ca);
+  int fbi = fb0;
+  for (; fbi + 2 <= fb1; fbi += 2) {
+    products(fbi + 1, Cb);
+    emit_any(fbi, Ca);
+    products(fbi + 2, Ca);   // block fb1 is the zero block past the end when fbi + 2 == fb1
+    emit_any(fbi + 1, Cb);
   }
+  if (fbi < fb1) emit_any(fbi, Ca);
 }
 
-// Operands of the single-read reconstruction from G (N x k complex float64, row t at t*k,
-// device column col[s] of mode s): the A fragments of G~^T ([ks][term][lane][8] bf16;
-// element i of lane l is G~[16ks + 8(l/32) + i][column l%32]), G~ = [Re | Im] of
-// G[:, col_s] beta_s xscale in the column order of rc_col, NSP bf16 terms.
+// Operands of k_recon, from G (N x k complex float64, row t at t*k, mode s in column
+// col[s]):
+//   Gp [KS + RC_PF][NSG][lane][8] bf16: element i of lane l is G~'[16ks + 8(l/32) + i][l%32]
+//      with G~'[t] = [Re | Im](G[t-1, col_s] beta_s xscale) in the columns of rc_col (row 0,
+//      rows t > N and the RC_PF k-steps past KS are 0), NSG bf16 terms;
+//   Vp [NFB + 1][2][NTV][lane][8] bf16 (the last block 0): element i of lane l (h = l/32) is, at frame t =
+//      32 fb + l%32 and K slot 16q + 8h + i, i.e. column c = 16q + 8(i/4) + 4h + i%4,
+//      Re lambda_s^t (part 0) or -Im lambda_s^t (part 1) of the mode in column c (0 for
+//      unused columns), lambda^t by binary powering in float64 (1 for the static model),
+//      NTV bf16 terms of its float32 value.
 __global__ __launch_bounds__(256) void k_recon_prep(const double* __restrict__ G, ReconPrep rp,
-                                                    uint16_t* __restrict__ Gsp) {
-  const int ns = rp.ns, NSP = rp.NSP, N = rp.N, k = rp.k;
-  const int64_t total = (int64_t)rp.KS * 64 * 8;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (int64_t)gridDim.x * blockDim.x) {
+                                                    uint16_t* __restrict__ Gp, uint16_t* __restrict__ Vp) {
+  const int ns = rp.ns, N = rp.N, k = rp.k;
+  const int64_t ng = (int64_t)(rp.KS + RC_PF) * 64 * 8, nv = (int64_t)(rp.NFB + 1) * 2 * 64 * 8;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < ng + nv; e += (int64_t)gridDim.x * blockDim.x) {
     const int i = (int)(e & 7);
     const int l = (int)((e >> 3) & 63);
-    const int ks = (int)(e >> 9);
-    const int row = 16 * ks + 8 * (l >> 5) + i;
-    const int c = l & 31;
-    const int hh = (c >> 2) & 1, j = 8 * (c >> 4) + 4 * ((c >> 3) & 1) + (c & 3);
-    const int s = 2 * (j >> 1) + hh, part = j & 1;
-    double g = 0.0;
-    if (row < N && s < ns) {
-      const double* z = G + 2 * ((int64_t)row * k + rp.col[s]);
-      const double br = rp.beta[2 * s], bi = rp.beta[2 * s + 1];
-      g = part == 0 ? (z[0] * br - z[1] * bi) * rp.xscale : (z[0] * bi + z[1] * br) * rp.xscale;
-    }
-    double rem = g;
-    for (int sp = 0; sp < NSP; ++sp) {
-      const uint16_t bits = bf16_bits_d(rem);
-      rem -= bf16_val_d(bits);
-      Gsp[(((int64_t)ks * NSP + sp) * 64 + l) * 8 + i] = bits;
+    if (e < ng) {
+      const int ks = (int)(e >> 9);
+      const int t = 16 * ks + 8 * (l >> 5) + i;
+      const int c = l & 31;
+      const int hh = (c >> 2) & 1, j = 8 * (c >> 4) + 4 * ((c >> 3) & 1) + (c & 3);
+      const int s = 2 * (j >> 1) + hh, part = j & 1;
+      double g = 0.0;
+      if (ks < rp.KS && t >= 1 && t - 1 < N && s < ns) {
+        const double* z = G + 2 * ((int64_t)(t - 1) * k + rp.col[s]);
+        const double br = rp.beta[2 * s], bi = rp.beta[2 * s + 1];
+        g = part == 0 ? (z[0] * br - z[1] * bi) * rp.xscale : (z[0] * bi + z[1] * br) * rp.xscale;
+      }
+      double rem = g;
+      for (int sp = 0; sp < rp.NSG; ++sp) {
+        const uint16_t bits = bf16_bits_d(rem);
+        rem -= bf16_val_d(bits);
+        Gp[(((int64_t)ks * rp.NSG + sp) * 64 + l) * 8 + i] = bits;
+      }
+    } else {
+      const int64_t ev = e - ng;
+      const int q = (int)((ev >> 9) & 1);
+      const int64_t fbi = ev >> 10;
+      const int hh = l >> 5;
+      const int64_t t = 32 * fbi + (l & 31);
+      const int j = 8 * q + i;                 // slot of half hh (column 16q + 8(i/4) + 4hh + i%4)
+      const int s = 2 * (j >> 1) + hh, part = j & 1;
+      float v = 0.f;
+      if (fbi < rp.NFB && s < ns) {
+        double pr = 1.0, pi = 0.0;
+        if (!rp.static_bg) {
+          double br = rp.lam[2 * s], bi = rp.lam[2 * s + 1];
+          for (int64_t ex = t; ex > 0; ex >>= 1) {
+            if (ex & 1) {
+              const double nr = pr * br - pi * bi, ni = pr * bi + pi * br;
+              pr = nr;
+              pi = ni;
+            }
+            const double sr = br * br - bi * bi, si = 2.0 * br * bi;
+            br = sr;
+            bi = si;
+          }
+        }
+        v = part == 0 ? (float)pr : (float)(-pi);
+      }
+      float rem = v;
+      for (int sp = 0; sp < rp.NTV; ++sp) {
+        const uint32_t bits = bf16_rne_bits(rem);
+        rem -= __uint_as_float(bits << 16);
+        Vp[((((fbi * 2 + q) * rp.NTV + sp) * 64 + l) * 8) + i] = (uint16_t)bits;
+      }
     }
   }
 }
 
-hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gsp, hipStream_t s) {
-  if (rp.ns < 0 || rp.ns > 16) return hipErrorInvalidValue;
-  const int64_t total = (int64_t)rp.KS * 64 * 8;
+hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gp, void* Vp, hipStream_t s) {
+  if (rp.ns < 0 || rp.ns > 16 || rp.NSG < 1 || rp.NSG > 3 || rp.NTV < 1 || rp.NTV > 3) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)(rp.KS + RC_PF) * 64 * 8 + (int64_t)(rp.NFB + 1) * 2 * 64 * 8;
   const int grid = (int)std::min<int64_t>((total + 255) / 256, 1024);
-  hipLaunchKernelGGL(k_recon_prep, dim3(grid), dim3(256), 0, s, G, rp, (uint16_t*)Gsp);
+  hipLaunchKernelGGL(k_recon_prep, dim3(grid), dim3(256), 0, s, G, rp, (uint16_t*)Gp, (uint16_t*)Vp);
   return hipGetLastError();
 }
 
 int recon_column(int s, int part) { return rc_col(s, part); }
 
-template <int NSG, int NTV>
-static hipError_t launch_recon(const ReconArgs& a, size_t lds, hipStream_t s) {
+template <int NSG, int NTV, int MODE, bool RAGGED>
+static hipError_t launch_recon1(const ReconArgs& a, size_t lds, int64_t tile0, int64_t tiles, hipStream_t s) {
   static bool attr = false;  // the larger dynamic LDS limit, set once per instantiation
   if (!attr) {
-    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon<NSG, NTV>),
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon<NSG, NTV, MODE, RAGGED>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
     attr = true;
   }
-  const dim3 grid((unsigned)((a.n + RC_TP - 1) / RC_TP));
-  hipLaunchKernelGGL((k_recon<NSG, NTV>), grid, dim3(RC_NT), lds, s, a);
+  hipLaunchKernelGGL((k_recon<NSG, NTV, MODE, RAGGED>), dim3((unsigned)tiles), dim3(RC_NT), lds, s, a, tile0);
   return hipGetLastError();
 }
 
+template <int NSG, int NTV, int MODE>
+static hipError_t launch_recon(const ReconArgs& a, size_t lds, hipStream_t s) {
+  const int64_t full = a.n / RC_TP;
+  if (full > 0) {
+    const hipError_t e = launch_recon1<NSG, NTV, MODE, false>(a, lds, 0, full, s);
+    if (e != hipSuccess) return e;
+  }
+  if (a.n % RC_TP) return launch_recon1<NSG, NTV, MODE, true>(a, lds, full, 1, s);
+  return hipSuccess;
+}
+
+int recon_ksteps(int64_t m) { return (int)(4 * ((m + 63) / 64)); }
+int recon_frame_blocks(int64_t m) { return (int)((m + 31) / 32); }
+
 hipError_t recon_mfma(const ReconArgs& a, int nsg, int ntv, hipStream_t s) {
-  if (a.ns < 0 || a.ns > 16 || a.n < 1 || a.m < 2 || a.KS != (int)((a.m - 1 + 15) / 16)) return hipErrorInvalidValue;
+  if (a.ns < 0 || a.ns > 16 || a.n < 1 || a.m < 2 || a.m >= (1 << 30) || a.KS != recon_ksteps(a.m) ||
+      a.NFB != recon_frame_blocks(a.m) || a.mode < 0 || a.mode > 2)
+    return hipErrorInvalidValue;
   if (a.mode == 2 && (a.t0 < 0 || a.t1 > a.m || a.t0 >= a.t1)) return hipErrorInvalidValue;
-  const size_t lds = recon_lds_bytes(a.m, nsg);
+  const size_t lds = recon_lds_bytes(a.m);
   if (lds > 160 * 1024) return hipErrorInvalidValue;
-  if (nsg == 3 && ntv == 3) return launch_recon<3, 3>(a, lds, s);
-  if (nsg == 1 && ntv == 2) return launch_recon<1, 2>(a, lds, s);
+#define RC_CASE(G, T)                                                    \
+  if (nsg == G && ntv == T) {                                            \
+    if (a.mode == 0) return launch_recon<G, T, 0>(a, lds, s);            \
+    if (a.mode == 1) return launch_recon<G, T, 1>(a, lds, s);            \
+    return launch_recon<G, T, 2>(a, lds, s);                             \
+  }
+  RC_CASE(2, 3)
+  RC_CASE(1, 2)
+#undef RC_CASE
   return hipErrorInvalidValue;
 }
 

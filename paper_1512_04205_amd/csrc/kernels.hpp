@@ -109,35 +109,38 @@ hipError_t bgfg(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, cons
                 int NS, const float* Vc, float tau, float xscale, int mode, void* out,
                 int64_t t0, int64_t t1, int64_t ldL, hipStream_t stream);
 // Single-read form on MFMA (uint8 video, 16-byte aligned frames, |S| <= 16): 128-pixel
-// tiles whose frames stay in LDS; Gp holds the A fragments of G~^T (NSG bf16 terms, KS =
-// ceil((m-1)/16) k-steps, columns in the order of recon_column); the Vandermonde
-// factors come from lam (re, im of the ns selected eigenvalues; pass 1 for the static
-// model).  nsg/ntv: (3, 3) float32-class, (1, 2) bfloat16 form.
+// tiles whose frames stay in LDS.  Gp, Vp: the operands recon_prep writes (KS =
+// recon_ksteps(m) k-steps plus 4 zero ones, NFB = recon_frame_blocks(m) frame blocks plus
+// a zero one).  nsg/ntv: (2, 3) float32-class L,
+// (1, 2) bfloat16 form.
 struct ReconArgs {
   const uint8_t* D;
   int64_t ld, n, m;
   const uint4* Gp;
-  int KS, ns;
-  double lam[32];
+  const uint4* Vp;
+  int KS, NFB, ns;
   float tau, xscale;
   int mode;
   void* out;
   int64_t t0, t1, ldL;
 };
 hipError_t recon_mfma(const ReconArgs& a, int nsg, int ntv, hipStream_t stream);
+int recon_ksteps(int64_t m);        // 4 ceil(m / 64)
+int recon_frame_blocks(int64_t m);  // ceil(m / 32)
 // LDS bytes of one workgroup of recon_mfma (the form applies while this is <= 160 KiB).
-size_t recon_lds_bytes(int64_t m, int nsg);
-// Column of G~ holding part (0 Re, 1 Im) of selected mode s.
+size_t recon_lds_bytes(int64_t m);
+// Column of the reconstruction operands holding part (0 Re, 1 Im) of selected mode s.
 int recon_column(int s, int part);
-// The A operands of recon_mfma from the device solve's G: ns <= 16 selected modes, device
-// columns col[s], amplitudes beta (re, im).
+// The operands of recon_mfma from G (N x k complex float64): ns <= 16 selected modes in
+// columns col[s], amplitudes beta and eigenvalues lam (re, im); Gp holds KS * NSG, Vp
+// NFB * 2 * NTV fragments of 64 x 16 bytes.
 struct ReconPrep {
-  int ns, NSP, KS, N, k;
+  int ns, NSG, NTV, KS, NFB, N, k, static_bg;
   double xscale;
   int col[16];
-  double beta[32];
+  double beta[32], lam[32];
 };
-hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gsp, hipStream_t stream);
+hipError_t recon_prep(const double* G, const ReconPrep& rp, void* Gp, void* Vp, hipStream_t stream);
 // counts[t] = number of set bits of frame t of a bit-packed mask
 hipError_t mask_counts(const uint32_t* mask, int64_t words, int64_t m, int64_t* counts,
                        hipStream_t stream);
