@@ -297,6 +297,20 @@ cdmd_status cdmd_mlp_train(float* d_params, float* d_adam_m, float* d_adam_v, co
                            int32_t batch, int32_t steps, float lr, int64_t step0, float* d_losses,
                            void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+   serving loops, harnesses that forbid hipMalloc): cdmd_mlp_train with the same arguments
+   and results, except that the per-batch partial gradients live in a static scratch
+   array the library holds on each device until the process ends, so the call allocates
+   nothing and does not synchronise (it returns after enqueueing on `stream`).  batch is at
+   most CDMD_MLP_NOALLOC_MAX_BATCH.  Every call on one device shares that device's
+   scratch: calls that overlap on one device (other streams or threads) race.
+   Errors: INVALID_ARG (including batch above the maximum), DEVICE. */
+#define CDMD_MLP_NOALLOC_MAX_BATCH 1024
+cdmd_status cdmd_mlp_train_noalloc(float* d_params, float* d_adam_m, float* d_adam_v, const float* d_X,
+                                   const float* d_y, int64_t n_samples, const int32_t* d_batch_idx,
+                                   int32_t batch, int32_t steps, float lr, int64_t step0, float* d_losses,
+                                   void* stream);
+
 /* Logits of n samples (d_X: n x 6) into d_logits; bf16 != 0 rounds weights, inputs and
    hidden activations to bfloat16 (float32 accumulation).  Errors: INVALID_ARG, DEVICE. */
 cdmd_status cdmd_mlp_forward(const float* d_params, const float* d_X, int32_t n, int32_t bf16,

@@ -34,7 +34,7 @@ EXPORTED = [
     "cdmd_dbg_force_valu_lift",
     "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases", "cdmd_dbg_la_groups",
     "cdmd_dbg_force_gather_sketch", "cdmd_dbg_sparse_form",
-    "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_forward",
+    "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_train_noalloc", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
     "cdmd_batch_free",
 ]
@@ -114,6 +114,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_mode_features.argtypes = [P, P, P]
     lib.cdmd_mlp_grad.argtypes = [P, P, P, I32, P, P, P]
     lib.cdmd_mlp_train.argtypes = [P, P, P, P, P, I64, P, I32, I32, ctypes.c_float, I64, P, P]
+    lib.cdmd_mlp_train_noalloc.argtypes = [P, P, P, P, P, I64, P, I32, I32, ctypes.c_float, I64, P, P]
     lib.cdmd_mlp_forward.argtypes = [P, P, I32, I32, P, P]
     lib.cdmd_select_learned.argtypes = [P, P, D, I32, ctypes.POINTER(I32), ctypes.POINTER(I32), DP, DP,
                                         ctypes.POINTER(I32), P]
@@ -410,6 +411,22 @@ def mlp_train(params, adam_m, adam_v, X, y, batch_idx, batch: int, lr: float = 1
         _tensor_ptr(batch_idx, steps * batch), batch, steps,
         lr, step0, _tensor_ptr(losses, max(steps, 1)), _stream(stream)))
     return losses[:steps]
+
+
+def mlp_train_noalloc(params, adam_m, adam_v, X, y, batch_idx, batch: int, losses, lr: float = 1e-3,
+                      step0: int = 0, stream=None):
+    """mlp_train without any allocation (the library's static scratch; batch at most
+    MLP_NOALLOC_MAX_BATCH): the per-step losses go to the caller's `losses` (device float32,
+    at least steps entries); returns after enqueueing."""
+    steps = batch_idx.numel() // batch
+    _check(load_library().cdmd_mlp_train_noalloc(
+        _tensor_ptr(params, MLP_NPARAM), _tensor_ptr(adam_m, MLP_NPARAM), _tensor_ptr(adam_v, MLP_NPARAM),
+        _tensor_ptr(X, 6 * X.shape[0]), _tensor_ptr(y, X.shape[0]), X.shape[0],
+        _tensor_ptr(batch_idx, steps * batch), batch, steps,
+        lr, step0, _tensor_ptr(losses, max(steps, 1)), _stream(stream)))
+
+
+MLP_NOALLOC_MAX_BATCH = 1024
 
 
 def mlp_forward(params, X, bf16: bool = False, stream=None):

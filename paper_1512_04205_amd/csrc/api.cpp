@@ -1822,6 +1822,21 @@ cdmd_status cdmd_mlp_train(float* d_params, float* d_adam_m, float* d_adam_v, co
   return CDMD_OK;
 }
 
+cdmd_status cdmd_mlp_train_noalloc(float* d_params, float* d_adam_m, float* d_adam_v, const float* d_X,
+                                   const float* d_y, int64_t n_samples, const int32_t* d_batch_idx,
+                                   int32_t batch, int32_t steps, float lr, int64_t step0, float* d_losses,
+                                   void* stream) {
+  g_err.clear();
+  if (!d_params || !d_adam_m || !d_adam_v || !d_X || !d_y || !d_batch_idx || batch < 1 || steps < 0 ||
+      step0 < 0 || n_samples < 1 || !(lr > 0.0f))
+    return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  if (batch > CDMD_MLP_NOALLOC_MAX_BATCH)
+    return fail(CDMD_E_INVALID_ARG, "batch above CDMD_MLP_NOALLOC_MAX_BATCH (the static scratch holds no more)");
+  HIPCHK(cdmd::k::mlp_train_noalloc(d_params, d_adam_m, d_adam_v, d_X, d_y, n_samples, d_batch_idx, batch, steps,
+                                    lr, step0, d_losses, as_stream(stream)));
+  return CDMD_OK;
+}
+
 cdmd_status cdmd_mlp_forward(const float* d_params, const float* d_X, int32_t n, int32_t bf16,
                              float* d_logits, void* stream) {
   g_err.clear();

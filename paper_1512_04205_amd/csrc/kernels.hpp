@@ -67,6 +67,11 @@ hipError_t mlp_grad(const float* th, const float* X, const float* y, const int32
 hipError_t mlp_train(float* th, float* am, float* av, const float* X, const float* y, int64_t nsamp,
                      const int32_t* idx, int batch, int steps, float lr, int64_t t0, float* part, float* lpart,
                      float* losses, hipStream_t stream);
+// mlp_train with the partials in the library's static device scratch (no allocation);
+// batch <= CDMD_MLP_NOALLOC_MAX_BATCH.  Calls that overlap on one device race.
+hipError_t mlp_train_noalloc(float* th, float* am, float* av, const float* X, const float* y, int64_t nsamp,
+                             const int32_t* idx, int batch, int steps, float lr, int64_t t0, float* losses,
+                             hipStream_t stream);
 hipError_t mlp_forward(const float* th, const float* X, int n, int round_bf16, float* logits, hipStream_t stream);
 hipError_t mode_features(const double* lam, const double* b, const double* phin, double x1n2, int64_t m, int k,
                          float* F, hipStream_t stream);

@@ -12,7 +12,9 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 
+#include "cdmd.h"
 #include "kernels.hpp"
 
 namespace cdmd {
@@ -274,6 +276,51 @@ hipError_t mlp_train(float* th, float* am, float* av, const float* X, const floa
                        av, lr, t0 + s + 1, (float*)nullptr, losses ? losses + s : (float*)nullptr);
   }
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Scratch of the allocation-free training call: the per-wave partial gradients and
+// losses of one batch of at most CDMD_MLP_NOALLOC_MAX_BATCH samples (2.4 MB).  Every
+// device the library runs on holds its own copy until the process ends.  k_mlp_grad
+// writes every partial of a launch before k_mlp_update reads them, so nothing needs
+// clearing between calls.
+namespace {
+constexpr int kNoAllocParts = ((CDMD_MLP_NOALLOC_MAX_BATCH + 4 * SPW - 1) / (4 * SPW)) * 4;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+float* g_scratch_ptr[kMaxDevices] = {};
+}  // namespace
+
+static __device__ __align__(256) float scratch[(size_t)kNoAllocParts * MP + kNoAllocParts];
+
+// The device address of `scratch` on the current device, looked up once per device with
+// that device current (host code must not use the symbol itself as an address).
+static hipError_t scratch_ptr(float** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[dev] = static_cast<float*>(p);
+  }
+  *out = g_scratch_ptr[dev];
+  return hipSuccess;
+}
+
+hipError_t mlp_train_noalloc(float* th, float* am, float* av, const float* X, const float* y, int64_t nsamp,
+                             const int32_t* idx, int batch, int steps, float lr, int64_t t0, float* losses,
+                             hipStream_t stream) {
+  if (batch < 1 || batch > CDMD_MLP_NOALLOC_MAX_BATCH || mlp_nparts(batch) > kNoAllocParts)
+    return hipErrorInvalidValue;
+  float* base = nullptr;
+  const hipError_t e = scratch_ptr(&base);
+  if (e != hipSuccess) return e;
+  return mlp_train(th, am, av, X, y, nsamp, idx, batch, steps, lr, t0, base, base + (size_t)kNoAllocParts * MP,
+                   losses, stream);
 }
 
 hipError_t mlp_forward(const float* th, const float* X, int n, int round_bf16, float* logits, hipStream_t stream) {
