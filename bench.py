@@ -47,13 +47,13 @@ def sector_bytes(idx, n, ld, m, sector=64):
     return total
 
 
-def cpu_baseline(D_dev, spec, k, p, nnz, K, tau, band_rows):
+def cpu_baseline(D_dev, spec, k, p, nnz, K, tau, band_rows, threads=None):
     """The FP64 oracle timed on the host on a horizontal band of the same video (the
     first ``band_rows`` image rows, all frames); stages that scale with the pixel
-    count are extrapolated to the full frame, the n-independent SVD/eig stage is not."""
+    count are extrapolated to the full frame, the n-independent SVD/eig stage is not.
+    ``threads`` limits the BLAS/OpenMP threads (None: all the library uses)."""
     import numpy as np
-    import torch
-    from threadpoolctl import threadpool_info
+    from threadpoolctl import threadpool_info, threadpool_limits
     import synthvideo as sv
     from oracle import cdmd_ref as R
 
@@ -62,39 +62,106 @@ def cpu_baseline(D_dev, spec, k, p, nnz, K, tau, band_rows):
     idx, sign = sv.sparse_table(n_s, p, nnz, seed=4242)
     scale = 1.0 / 255.0
     t = {}
-    t0 = time.perf_counter()
-    Y, _ = R.sketch_sparse(D, scale, idx, sign)
-    t["sketch"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    lam, W, s, V, At = R.reduced_operator(Y, k)
-    t["svd_eig"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    G = (V / s[None, :]) @ W
-    Phi = R.lift(D, scale, G)
-    x1 = D[0].astype(np.float64) * scale
-    b = np.linalg.lstsq(Phi, x1.astype(np.complex128), rcond=None)[0]
-    t["lift_lstsq"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    S, beta = R.omp(Phi, x1, K, lam=lam)
-    t["omp"] = time.perf_counter() - t0
-    t0 = time.perf_counter()
-    m = D.shape[0]
-    for i0 in range(0, n_s, 16384):
-        i1 = min(n_s, i0 + 16384)
-        L = R.background(Phi[i0:i1][:, S], beta, lam[S], 0, m)
-        R.foreground(R.pixel_rows(D, scale, i0, i1), L, tau)
-    t["bg_mask"] = time.perf_counter() - t0
+    with threadpool_limits(limits=threads):
+        used = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+        t0 = time.perf_counter()
+        Y, _ = R.sketch_sparse(D, scale, idx, sign)
+        t["sketch"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        lam, W, s, V, At = R.reduced_operator(Y, k)
+        t["svd_eig"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        G = (V / s[None, :]) @ W
+        Phi = R.lift(D, scale, G)
+        x1 = D[0].astype(np.float64) * scale
+        b = np.linalg.lstsq(Phi, x1.astype(np.complex128), rcond=None)[0]
+        t["lift_lstsq"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        S, beta = R.omp(Phi, x1, K, lam=lam)
+        t["omp"] = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        m = D.shape[0]
+        for i0 in range(0, n_s, 16384):
+            i1 = min(n_s, i0 + 16384)
+            L = R.background(Phi[i0:i1][:, S], beta, lam[S], 0, m)
+            R.foreground(R.pixel_rows(D, scale, i0, i1), L, tau)
+        t["bg_mask"] = time.perf_counter() - t0
     f = spec.n / n_s
     total = t["svd_eig"] + f * (t["sketch"] + t["lift_lstsq"] + t["omp"] + t["bg_mask"])
-    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
     measured = sum(t.values())
     return {
-        "value": m / total, "unit": "frames/s", "cores": int(threads), "kind": "oracle",
+        "value": m / total, "unit": "frames/s", "cores": int(used), "kind": "oracle",
+        "host_cpus": os.cpu_count(),
         "sample": (f"FP64 oracle on rows 0..{band_rows - 1} of the same video ({n_s} of {spec.n} "
-                   f"pixels, all {m} frames, p={p}, k={k}, K={K}); measured {measured:.1f} s, "
-                   f"pixel-proportional stages scaled x{f:.1f}, SVD/eig stage unscaled"),
+                   f"pixels, all {m} frames, p={p} with its own {nnz}-per-row table, k={k}, K={K}); "
+                   f"measured {measured:.1f} s on {used} thread(s), pixel-proportional stages "
+                   f"scaled x{f:.1f}, SVD/eig stage unscaled"),
         "stages_s": {kk: round(v, 3) for kk, v in t.items()},
     }
+
+
+def oracle_quality(D_dev, idx, sign, k, K, tau, res, npix=20000, seed=0):
+    """Per form: the GPU's eigenvalues, b_j phi_j on sampled pixels and the foreground mask on
+    those pixels over all frames, against the FP64 oracle of the whole frame on the same
+    (exact integer) sketch.  Mask disagreements must lie in the band ||x - L| - tau| <= band
+    (1e-4 for float32-class forms, 2e-2 for the bfloat16 form); the oracle's OMP support is
+    used for both (the GPU is given it explicitly when the oracle records a near tie)."""
+    import numpy as np
+    import torch
+    from scipy.optimize import linear_sum_assignment
+    import paper_1512_04205_amd as P
+    from oracle import cdmd_ref as R
+
+    t0 = time.perf_counter()
+    Dh = D_dev.cpu().numpy()
+    m, n = Dh.shape
+    Yr, _ = R.sketch_sparse(Dh, 1.0 / 255.0, idx, sign)
+    mo = R.fit(Dh, 1.0 / 255.0, Yr, k)
+    x1 = Dh[0].astype(np.float64) / 255.0
+    gaps = []
+    Sr, br = R.omp(mo.Phi, x1, K, lam=mo.lam, margins=gaps)
+    pix = np.sort(np.random.default_rng(seed).choice(n, npix, replace=False))
+    x = Dh[:, pix].T.astype(np.float64) / 255.0
+    Lr = R.background(mo.Phi[pix][:, Sr], br, mo.lam[Sr], 0, m)
+    mr = R.foreground(x, Lr, tau)
+    bphi_r = mo.Phi[pix] * mo.b[None, :]
+    oracle_s = time.perf_counter() - t0
+    del Dh
+    out = {}
+    pix_t = torch.from_numpy(pix).to(D_dev.device)
+    for f, r in res.items():
+        mdl = r["model"]
+        q = {}
+        lam_g = r["lam"]
+        C = np.abs(lam_g[:, None] - mo.lam[None, :])
+        a, b = linear_sum_assignment(C)
+        q["eig_rel_err_max"] = float((C[a, b] / np.abs(mo.lam[b])).max())
+        if f != "fp32_compressed":  # the compressed form's amplitudes answer another problem
+            phi = torch.zeros((k, n), dtype=torch.complex64, device=D_dev.device)
+            md = mdl.modes(video=D_dev, phi=phi)
+            pg = phi[:, pix_t].cpu().numpy().T.astype(np.complex128)
+            del phi
+            bphi_g = pg * md["b"][None, :]
+            err = np.abs(bphi_g[:, a] - bphi_r[:, b]).max() / np.abs(bphi_r).max()
+            q["bphi_rel_err_max"] = float(err)
+            near = 1e-4 if f == "fp32" else 3e-2
+            if min(gaps) >= near:
+                S, _ = mdl.select(P.SEL_OMP, K=K)
+                q["omp_support_equal"] = bool(list(S) == list(Sr))
+            if min(gaps) < near or not q["omp_support_equal"]:
+                mdl.select(P.SEL_EXPLICIT, explicit=Sr)
+            mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device=D_dev.device)
+            mdl.foreground(D_dev, mk, tau)
+            words = mk[:, (pix_t >> 5)].cpu().numpy().view(np.uint32)
+            mg = ((words >> (pix & 31).astype(np.uint32)[None, :]) & 1).astype(bool).T
+            diff = mg != mr
+            band = 1e-4 if f == "fp32" else 2e-2
+            q["mask_agreement"] = float(1.0 - diff.mean())
+            q["mask_disagreements_in_band"] = bool((np.abs(np.abs(x - Lr) - tau)[diff] <= band).all())
+            q["mask_band"] = band
+        out[f] = q
+    return out, {"pixels_sampled": npix, "frames": m, "oracle_s": round(oracle_s, 1),
+                 "omp_min_margin": float(min(gaps))}
 
 
 WORKLOADS = {
@@ -254,7 +321,11 @@ def main():
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip cdmd_autotune before the warm-up (default tile shapes)")
     ap.add_argument("--cpu-band-rows", type=int, default=68)
-    ap.add_argument("--copy-ref-mib", type=int, default=0,
+    ap.add_argument("--cpu-band-rows-1t", type=int, default=17,
+                    help="band of the single-thread CPU baseline")
+    ap.add_argument("--no-quality", action="store_true",
+                    help="skip the per-form comparison with the full-frame FP64 oracle (cfg2)")
+    ap.add_argument("--copy-ref-mib", type=int, default=1024,
                     help="run a device-to-device copy of this many MiB first (the reference "
                          "kernel for scaling HBM counters)")
     args = ap.parse_args()
@@ -273,12 +344,23 @@ def main():
     if args.workload == "cfg4":
         print(json.dumps(run_batch(args, wl)), flush=True)
         return
+    copy_gbs = None
     if args.copy_ref_mib > 0:
+        # device-to-device copy of a known size: the measured HBM ceiling (read + write bytes
+        # over the copy's event time), and the reference kernel for scaling HBM counters
         a = torch.empty(args.copy_ref_mib << 20, dtype=torch.uint8, device="cuda")
         b = torch.empty_like(a)
         b.copy_(a)
         torch.cuda.synchronize()
-        log(f"copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written")
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = 5
+        e0.record()
+        for _ in range(reps):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        copy_gbs = 2.0 * a.numel() * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+        log(f"copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written, {copy_gbs:.0f} GB/s")
         del a, b
     spec = sv.PRESETS[wl["preset"]]
     k, p, nnz, K, tau = wl["k"], wl["p"], wl["nnz"], wl["K"], wl["tau"]
@@ -359,10 +441,9 @@ def main():
             "gram": (4.0 * p * m + 8.0 * m * m, 2.0 * p * m * m, PEAK["fp64"]),
             "lift": (video_bytes, 2.0 * n * (m - 1) * k + 2.0 * n * (k + 1) ** 2, PEAK["bf16"]),
             "recon": (2.0 * video_bytes + n * m / 8.0, 8.0 * n * m * S_n, PEAK["fp32"]),
-            # the Lanczos workgroups, one per compute unit: their share of the float64 rate
-            "lanczos": (8.0 * m * m, lanczos_flops(N, J), PEAK["fp64"] * la_groups(N) / 256.0),
-            # Ritz vectors, A~ and G (row kernels), eig(A~) on one workgroup: one CU's rate
-            "la_rest": (8.0 * m * m, la_rest_flops(N, k, J), PEAK["fp64"] / 256.0),
+            # the float64 small linear algebra, against the chip's published float64 rate
+            "lanczos": (8.0 * m * m, lanczos_flops(N, J), PEAK["fp64"]),
+            "la_rest": (8.0 * m * m, la_rest_flops(N, k, J), PEAK["fp64"]),
         }
         kernels = {}
         for q, (byt, fl, fpk) in work.items():
@@ -381,7 +462,7 @@ def main():
                           "hbm_frac": round(hb, 4), "flop_frac": round(fb, 4), "bound": bound,
                           "bytes": byt, "flops": fl, "flop_peak": fpk}
         lam = mdl.modes()["lam"]
-        return {"ms": ms, "fps": m / (ms / 1e3), "avg": avg, "kernels": kernels, "lam": lam,
+        return {"ms": ms, "fps": m / (ms / 1e3), "avg": avg, "kernels": kernels, "lam": lam, "model": mdl,
                 "lanczos": J, "n_sel": S_n,
                 "tiles": {"lift_grid": inf["lift_grid"], "sparse_form": inf["sparse_form"],
                           "sketch_slices": inf["sketch_slices"]}}
@@ -437,6 +518,11 @@ def main():
         if forms[0] == "fp32" else {}
     roof = roof_of(head["kernels"][dom])
     roof.update({"kernel": dom, "traffic": traffic.get(dom)})
+    if dom in ("lanczos", "la_rest"):
+        # secondary figure: the share of the float64 rate of the compute units the solve occupies
+        cus = la_groups(m - 1) if dom == "lanczos" else 1
+        roof["occupied_cus"] = cus
+        roof["frac_of_occupied_cus"] = round(roof["achieved"] / (PEAK["fp64"] * cus / 256.0), 5)
     streaming = {q: dict(roof_of(head["kernels"][q]), ms=head["kernels"][q]["ms"], traffic=traffic.get(q))
                  for q in ("sketch", "lift", "recon")}
     out = {
@@ -457,6 +543,9 @@ def main():
         "sketch_hbm_gbps": head["kernels"]["sketch"]["GB/s"],
         "eig_rel_err_max": head["eig_rel_err_max"],
         "eig_reference": ref_kind,
+        "eig_note": ("the eigenvalues come from the sketch and the float64 small linear algebra in "
+                     "every form; the forms differ in the lift (b_j phi_j) and the reconstruction "
+                     "(mask), reported per form"),
         "forms": {f: {"fps": r["fps"], "ms_per_step": r["ms"], "eig_rel_err_max": r["eig_rel_err_max"],
                       "small_la_ms": round(r["avg"]["small_la"], 3), "lanczos_steps": r["lanczos"],
                       "n_selected": r["n_sel"], "tiles": r["tiles"],
@@ -464,9 +553,20 @@ def main():
                                   for q, d in r["kernels"].items()}}
                   for f, r in res.items()},
     }
+    if copy_gbs is not None:
+        out["hbm_copy_gbps"] = round(copy_gbs, 1)
+    if args.workload == "cfg2" and not args.no_quality:
+        log("per-form quality against the full-frame FP64 oracle")
+        qual, qinfo = oracle_quality(D, idx, sign, k, K, tau, res)
+        for f, q in qual.items():
+            out["forms"][f].update(q)
+        out["quality_reference"] = dict(qinfo, kind="FP64 oracle of the whole frame on the same exact sketch; "
+                                                   "b_j phi_j and masks on sampled pixels x all frames")
     if not args.no_cpu_baseline and args.workload == "cfg2":
-        log("CPU baseline (FP64 oracle on a band of the video)")
+        log("CPU baseline (FP64 oracle on a band of the video), all threads")
         out["cpu_baseline"] = cpu_baseline(D, spec, k, p, nnz, K, tau, args.cpu_band_rows)
+        log("CPU baseline, one thread")
+        out["cpu_baseline_1thread"] = cpu_baseline(D, spec, k, p, nnz, K, tau, args.cpu_band_rows_1t, threads=1)
     print(json.dumps(out), flush=True)
 
 
