@@ -115,9 +115,13 @@ def sketch_gaussian(D: np.ndarray, scale: float, seed: int, p: int, chunk: int =
     Y = np.zeros((p if rows is None else len(rows), m))
     for j0 in range(0, n, chunk):
         j1 = min(n, j0 + chunk)
-        C = gaussian_C(seed, p, j0, j1, quantise)
-        if rows is not None:
-            C = C[np.asarray(rows)]
+        if rows is None:
+            C = gaussian_C(seed, p, j0, j1, quantise)
+        else:  # only the requested rows of C (each entry is a function of its row and pixel)
+            C = np.concatenate([philox.gaussian_block(seed, r, r + 1, j0, j1) for r in rows])
+            if quantise is not None:
+                C = quantise(C)
+            C = C / np.sqrt(p)
         Y += C @ pixel_rows(D, scale, j0, j1)
     return Y
 

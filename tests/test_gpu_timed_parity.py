@@ -1,0 +1,375 @@
+"""Parity at the configurations bench.py times and the ones the library claims, through the
+C ABI, against the FP64 oracle.
+
+* 1080p uint8, p = 2000 x 32: the integer sketch bit-exact under every sparse-sketch form
+  the autotuner can pick (the gather form and the streaming forms 41, 21, 22, 11, 12, 14).
+* Dense Gaussian sketch, bfloat16 and FP8-e4m3 forms, per entry.  The device draws the
+  normals in float32 with the hardware transcendentals; its normal z_dev is taken to lie
+  within e = 1e-5 |z| + 1e-6 of the oracle's float64 z (4e-4 for |z| < 4e-4, where
+  float32 rounding of u1 near 1 dominates sqrt(-2 ln u1)).  An entry of C may then round to
+  any value of the format in [q(z - e), q(z + e)]; the others round exactly as the oracle's
+  quantised C.  Per sketch entry: |Y_gpu - Y_q| <= (A |X| + 2^-16 |C_q| |X|) / sqrt(p), A
+  the possible rounding differences, the second term float32 accumulation.  A wrong row or
+  column of C, or of the video, breaks this bound wherever it lands.
+* The 4K x 1000 precision workload (p = 4000, k = 40): the same per-entry bound on sampled
+  rows of the full-size sketch; and a reduced frame size at the same p, m and k: eigenvalues
+  and masks against the oracle on the same quantised C.
+* Batched fits: b_j phi_j and masks of models fitted by the batch against the oracle,
+  with one stream at p = 20,000.
+* Status paths: |lambda|^(m-1) > 1e30 gives NUMERIC; an empty support reconstructs L = 0;
+  a batch refuses a member switched to the compressed amplitudes after capture and
+  recaptures after an autotune; float32 videos reconstruct correctly when calls follow
+  each other without a synchronisation.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthvideo as sv
+from oracle import cdmd_ref as R
+from oracle import philox
+from tests.cdmd_testutil import NEAR_TIE_FP32, eig_rel_err, mask_agreement, match_eigs
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_1512_04205_amd")
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+# ------------------------------------------------------------------ sparse forms at 1080p
+@pytest.mark.timeout(900)
+def test_fullsize_sparse_sketch_every_form_bit_exact():
+    _say("1080p sparse forms: generate")
+    spec = sv.PRESETS["cfg2"]
+    v = sv.make_video(spec, device="cuda")
+    Dg = v.D
+    m, n = Dg.shape
+    p = 2000
+    idx, sign = sv.sparse_table(n, p, 32, seed=2002)
+    _say("oracle integer sketch")
+    _, Yref = R.sketch_sparse(Dg.cpu().numpy(), 1 / 255, idx, sign)
+    mdl = P.Model(n, m, 25, p, idx=idx, sign=sign)
+    mdl.autotune(Dg)
+    tried = []
+    for form in (None, -1, 41, 21, 22, 11, 12, 14):
+        if form is not None:
+            try:
+                mdl.sparse_form(form)
+            except P.CdmdError:
+                continue              # the form does not fit this table
+        _say("form", "autotuned" if form is None else form, mdl.info()["sparse_form"])
+        mdl.fit(Dg)
+        _, Yi = mdl.sketch(integer=True)
+        np.testing.assert_array_equal(Yi, Yref, err_msg=f"form {form}")
+        tried.append(mdl.info()["sparse_form"])
+    assert len(set(tried)) >= 5, tried
+
+
+# ------------------------------------------------------------------ Gaussian, per entry
+def _quant_interval(z, quant):
+    """The oracle's quantised C and the largest difference a device normal within the
+    stated error of z can round to."""
+    e = 1e-5 * np.abs(z) + 1e-6 + np.where(np.abs(z) < 4e-4, 4e-4, 0.0)
+    q = quant(z)
+    amb = np.maximum(np.abs(quant(z - e) - q), np.abs(quant(z + e) - q))
+    return q, amb
+
+
+def _rows_bound(D_chunks, seed, p, rows, quant):
+    """Y_q[rows] and its per-entry bound from video chunks (m, nc) uint8 with pixel offsets."""
+    Y = Bd = None
+    for j0, Dc in D_chunks:
+        X = Dc.astype(np.float64).T / 255.0
+        z = np.concatenate([philox.gaussian_block(seed, r, r + 1, j0, j0 + Dc.shape[1]) for r in rows])
+        q, amb = _quant_interval(z, quant)
+        y = q @ X
+        b = amb @ X + 2.0 ** -16 * (np.abs(q) @ X)
+        Y = y if Y is None else Y + y
+        Bd = b if Bd is None else Bd + b
+    return Y / np.sqrt(p), Bd / np.sqrt(p)
+
+
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("shape", [(90, 160, 40, 100), (37, 64, 21, 70), (20, 48, 560, 64)])
+def test_gaussian_sketch_low_precision_per_entry(prec, shape):
+    H, W, m, p = shape
+    _say("gauss per entry", prec, shape)
+    rng = np.random.default_rng(17)
+    n = H * W
+    D = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+    seed = 4321
+    mdl = P.Model(n, m, min(5, m - 1), p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=seed,
+                  sketch_prec=P.PREC_BF16 if prec == "bf16" else P.PREC_FP8)
+    mdl.fit(torch.from_numpy(D).cuda())
+    Yg = mdl.sketch()
+    quant = R.round_bf16 if prec == "bf16" else R.round_e4m3
+    Y, B = _rows_bound([(0, D)], seed, p, list(range(p)), quant)
+    err = np.abs(Yg - Y)
+    assert (err <= B + 1e-12).all(), (err - B).max()
+
+
+@pytest.fixture(scope="module")
+def video_4k():
+    _say("4k video: generate")
+    v = sv.make_video(sv.PRESETS["cfg3"], device="cuda")
+    yield v.D
+    del v
+
+
+@pytest.mark.timeout(1200)
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_4k_sketch_sampled_rows_per_entry(prec, video_4k):
+    """The full 3840x2160x1000 precision workload: rows 0, 1999 and 3999 of the sketch
+    against the oracle on the same quantised C, per entry."""
+    _say("4k rows", prec)
+    Dg = video_4k
+    m, n = Dg.shape
+    p, seed = 4000, 3
+    mdl = P.Model(n, m, 40, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=seed,
+                  sketch_prec=P.PREC_BF16 if prec == "bf16" else P.PREC_FP8)
+    _say("fit")
+    try:
+        mdl.fit(Dg)
+    except P.CdmdError as e:       # the sketch is what is checked here
+        _say("fit status", e)
+    Yg = mdl.sketch()
+    rows = [0, 1999, 3999]
+    quant = R.round_bf16 if prec == "bf16" else R.round_e4m3
+    step = 1 << 20
+    _say("oracle rows")
+    chunks = ((j0, Dg[:, j0:min(n, j0 + step)].cpu().numpy()) for j0 in range(0, n, step))
+    Y, B = _rows_bound(chunks, seed, p, rows, quant)
+    err = np.abs(Yg[rows] - Y)
+    _say("max err / bound", float((err / B).max()))
+    assert (err <= B + 1e-9).all(), (err - B).max()
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+def test_precision_workload_reduced_frame(prec):
+    """p = 4000, m = 1000, k = 40 as in the 4K workload, on 48x64 frames (n = 3072 >= m) of
+    the same generator: eigenvalues within 1e-3 of the oracle on the same quantised C, masks
+    >= 99.9% identical with every disagreement in the band 10 x the L error."""
+    _say("precision workload reduced", prec)
+    spec = sv.preset("cfg3", H=48, W=64, bump_sigma=3.2, blur_sigma=2.0, n_rects=6, rect_side=(3, 8),
+                     speed=(0.5, 1.5), seed=1003)
+    v = sv.make_video(spec)
+    D = v.D.numpy()
+    m, n = D.shape
+    p, k, seed, K, tau = 4000, 40, 3, 10, 0.1
+    quant = R.round_bf16 if prec == "bf16" else R.round_e4m3
+    Dg = torch.from_numpy(D).cuda()
+    mdl = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=seed,
+                  sketch_prec=P.PREC_BF16 if prec == "bf16" else P.PREC_FP8)
+    mdl.fit(Dg)
+    _say("oracle")
+    Y = R.sketch_gaussian(D, v.scale, seed, p, quantise=quant)
+    mo = R.fit(D, v.scale, Y, k)
+    rel, _, _ = eig_rel_err(mdl.modes()["lam"], mo.lam)
+    s = mo.sigma
+    _say("eig rel err", float(rel.max()), "sigma_k/sigma_k+1 n/a (k = top 40)", float(s[-1] / s[0]))
+    assert rel.max() <= 1e-3, rel.max()
+    x1 = D[0].astype(np.float64) / 255
+    gaps = []
+    Sr, br = R.omp(mo.Phi, x1, K, lam=mo.lam, margins=gaps)
+    mdl.select(P.SEL_EXPLICIT, explicit=Sr)
+    Lr = R.background(mo.Phi[:, Sr], br, mo.lam[Sr], 0, m)
+    L = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+    mdl.background(Dg, L)
+    lerr = np.abs(L.cpu().numpy() - Lr.T).max()
+    mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    mdl.foreground(Dg, mk, tau)
+    mg = P.unpack_mask(mk.cpu().numpy().view(np.uint32), n)
+    x = D.astype(np.float64) / 255
+    mr = R.foreground(x.T, Lr, tau).T
+    frac, inband, nd = mask_agreement(mg, mr, x, Lr.T, tau, 10 * lerr + 1e-6)
+    _say("L err", lerr, "mask agreement", frac, "disagreements", nd)
+    assert frac >= 0.999 and inband, (frac, nd, lerr)
+
+
+# ------------------------------------------------------------------ batches vs the oracle
+BATCH_STREAMS = [
+    ("sparse", 48, 64, 60, 8, 400),
+    ("gauss_bf16", 64, 80, 80, 12, 200),
+    ("sparse", 160, 240, 120, 12, 20000),      # p = 20,000: the batched workload's smallest p
+]
+
+
+@pytest.mark.timeout(600)
+def test_batch_modes_and_masks_against_oracle():
+    _say("batch vs oracle")
+    made, models, videos = [], [], []
+    for i, (kind, H, W, m, k, p) in enumerate(BATCH_STREAMS):
+        spec = sv.preset("cfg2", H=H, W=W, m=m, n_pairs=2, bump_sigma=H / 8.0, blur_sigma=3.0, n_rects=3,
+                         rect_side=(H // 12, H // 6), speed=(0.5, 2.0), seed=700 + i)
+        v = sv.make_video(spec, device="cuda")
+        n = H * W
+        if kind == "gauss_bf16":
+            mdl = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, seed=31 + i, sketch_prec=P.PREC_BF16)
+            ref = dict(sketch="gaussian", p=p, seed=31 + i, quantise=R.round_bf16)
+        else:
+            idx, sign = sv.sparse_table(n, p, 32, 80 + i)
+            mdl = P.Model(n, m, k, p, idx=idx, sign=sign)
+            ref = dict(sketch="sparse", idx=idx, sign=sign)
+        made.append((v, ref, kind, k))
+        models.append(mdl)
+        videos.append(v.D)
+    batch = P.Batch(models)
+    assert batch.fit(videos) == [P.OK] * len(models)
+    tau, K = 0.1, 6
+    for q, ((v, ref, kind, k), mdl) in enumerate(zip(made, models)):
+        D = v.D.cpu().numpy()
+        m, n = D.shape
+        _say("stream", q, kind, "oracle")
+        if ref["sketch"] == "gaussian":
+            Y = R.sketch_gaussian(D, v.scale, ref["seed"], ref["p"], quantise=ref["quantise"])
+        else:
+            Y, _ = R.sketch_sparse(D, v.scale, ref["idx"], ref["sign"])
+        mo = R.fit(D, v.scale, Y, k)
+        rel, _, _ = eig_rel_err(mdl.modes()["lam"], mo.lam)
+        assert rel.max() <= (1e-3 if kind == "gauss_bf16" else 1e-6), (q, rel.max())
+        phi = torch.zeros((k, n), dtype=torch.complex64, device="cuda")
+        md = mdl.modes(video=v.D, phi=phi)
+        bphi_g = phi.cpu().numpy().T.astype(np.complex128) * md["b"][None, :]
+        bphi_r = mo.Phi * mo.b[None, :]
+        r, c, _ = match_eigs(md["lam"], mo.lam)
+        err = np.abs(bphi_g[:, r] - bphi_r[:, c]).max() / np.abs(bphi_r).max()
+        assert err <= (2e-2 if kind == "gauss_bf16" else 2e-5), (q, err)
+        x1 = D[0].astype(np.float64) / 255
+        gaps = []
+        Sr, br = R.omp(mo.Phi, x1, K, lam=mo.lam, margins=gaps)
+        if kind != "gauss_bf16" and min(gaps) >= NEAR_TIE_FP32:
+            S, _ = mdl.select(P.SEL_OMP, K=K)
+            assert list(S) == list(Sr), (q, S, Sr)
+        mdl.select(P.SEL_EXPLICIT, explicit=Sr)
+        Lr = R.background(mo.Phi[:, Sr], br, mo.lam[Sr], 0, m)
+        L = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+        mdl.background(v.D, L)
+        lerr = np.abs(L.cpu().numpy() - Lr.T).max()
+        mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+        mdl.foreground(v.D, mk, tau)
+        mg = P.unpack_mask(mk.cpu().numpy().view(np.uint32), n)
+        x = D.astype(np.float64) / 255
+        mr = R.foreground(x.T, Lr, tau).T
+        frac, inband, nd = mask_agreement(mg, mr, x, Lr.T, tau, 10 * lerr + 1e-6)
+        _say("stream", q, "eig", float(rel.max()), "bphi", float(err), "mask", frac, nd)
+        assert frac >= 0.999 and inband, (q, frac, nd, lerr)
+    batch.close()
+
+
+def test_batch_member_switched_after_capture():
+    """A member switched to the compressed amplitudes after the capture is refused; back on
+    the full modes, and after an autotune of another member, the batch recaptures and
+    matches single fits again."""
+    _say("batch switch")
+    streams = [(48, 64, 60, 8, 400, 1), (64, 64, 50, 6, 300, 2)]
+    videos, models, singles = [], [], []
+    for H, W, m, k, p, s in streams:
+        v = sv.make_video(sv.preset("cfg2", H=H, W=W, m=m, n_pairs=2, bump_sigma=6.0, n_rects=2,
+                                    rect_side=(4, 8), speed=(0.5, 1.0), seed=900 + s), device="cuda")
+        idx, sign = sv.sparse_table(H * W, p, 32, 60 + s)
+        videos.append(v.D)
+        models.append(P.Model(H * W, m, k, p, idx=idx, sign=sign))
+        one = P.Model(H * W, m, k, p, idx=idx, sign=sign)
+        one.fit(v.D)
+        singles.append(one.modes()["lam"])
+    batch = P.Batch(models)
+    assert batch.fit(videos) == [P.OK, P.OK]
+    models[0].set_amplitudes(P.AMP_COMPRESSED)
+    with pytest.raises(P.CdmdError) as ei:
+        batch.fit(videos)
+    assert ei.value.status == P.E_UNSUPPORTED
+    models[0].set_amplitudes(P.AMP_FULL)
+    models[1].autotune(videos[1])
+    assert batch.fit(videos) == [P.OK, P.OK]
+    for mdl, lam in zip(models, singles):
+        np.testing.assert_array_equal(mdl.modes()["lam"], lam)
+    batch.close()
+
+
+# ------------------------------------------------------------------ status paths
+def test_numeric_status_for_a_growing_mode():
+    """A pattern growing by 1.3 per frame over 400 frames: its eigenvalue has |lambda|^(m-1)
+    far above 1e30, so reconstructing with it is refused (NUMERIC) on the device as in the
+    oracle; the fit itself succeeds."""
+    _say("numeric")
+    H, W, m = 32, 48, 400
+    n = H * W
+    rng = np.random.default_rng(5)
+    base = 40 + 30 * rng.random(n)
+    pat = np.exp(-((np.arange(n) % W - 20.0) ** 2 + (np.arange(n) // W - 12.0) ** 2) / 40.0)
+    t = np.arange(m, dtype=np.float64)
+    g = 1.3 ** (t - (m - 1))                       # reaches 1 at the last frame
+    X = base[None, :] + 200.0 * g[:, None] * pat[None, :] + rng.normal(0, 0.5, (m, n))
+    D = np.clip(np.rint(X), 0, 255).astype(np.uint8)
+    idx, sign = sv.sparse_table(n, 300, 32, 3)
+    mdl = P.Model(n, m, 6, 300, idx=idx, sign=sign)
+    Dg = torch.from_numpy(D).cuda()
+    mdl.fit(Dg)
+    lam = mdl.modes()["lam"]
+    j = int(np.argmax(np.abs(lam)))
+    assert abs(lam[j]) ** (m - 1) > 1e30, abs(lam[j])
+    with pytest.raises(R.NumericError):
+        R.vandermonde(lam[[j]], 0, m)
+    mdl.select(P.SEL_EXPLICIT, explicit=[j])
+    L = torch.zeros((m, n), dtype=torch.float32, device="cuda")
+    with pytest.raises(P.CdmdError) as ei:
+        mdl.background(Dg, L)
+    assert ei.value.status == P.E_NUMERIC
+    # the static model of the same mode is fine
+    xs = torch.zeros(n, dtype=torch.float32, device="cuda")
+    mdl.background(Dg, xs, static=True)
+
+
+def test_empty_support_reconstructs_zero():
+    """An omega threshold below every |log lambda| selects nothing: L = 0 and the mask is
+    |x| > tau, as in the oracle."""
+    _say("empty support")
+    v = sv.make_video(sv.preset("cfg2", H=40, W=64, m=50, n_pairs=2, bump_sigma=6.0, n_rects=2,
+                                rect_side=(4, 8), speed=(0.5, 1.0), seed=44), device="cuda")
+    m, n = v.D.shape
+    idx, sign = sv.sparse_table(n, 300, 32, 4)
+    mdl = P.Model(n, m, 8, 300, idx=idx, sign=sign)
+    mdl.fit(v.D)
+    lam = mdl.modes()["lam"]
+    thr = 0.5 * np.abs(np.log(lam)).min()
+    S, beta = mdl.select(P.SEL_OMEGA, omega_thr=thr)
+    assert len(S) == 0 and len(R.select_omega(lam, thr)) == 0
+    L = torch.full((m, n), 7.0, dtype=torch.float32, device="cuda")
+    mdl.background(v.D, L)
+    assert torch.count_nonzero(L).item() == 0
+    mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    mdl.foreground(v.D, mk, 0.1)
+    mg = P.unpack_mask(mk.cpu().numpy().view(np.uint32), n)
+    np.testing.assert_array_equal(mg, v.D.cpu().numpy().astype(np.float64) / 255 > 0.1)
+
+
+def test_float32_reconstruction_calls_back_to_back():
+    """A float32 video reconstructs through host-built operands; a foreground call directly
+    followed by a static background call (no synchronisation in between) gives what the
+    two calls give one at a time."""
+    _say("float32 back to back")
+    spec = sv.preset("cfg1", H=48, W=64, m=60, bump_sigma=5.0, blur_sigma=3.0, n_rects=2,
+                     rect_side=(6, 6), seed=71)
+    v = sv.make_video(spec, device="cuda")
+    m, n = v.D.shape
+    idx, sign = sv.sparse_table(n, 300, 32, 7)
+    mdl = P.Model(n, m, 8, 300, dtype=P.F32, idx=idx, sign=sign)
+    mdl.fit(v.D)
+    mdl.select(P.SEL_OMP, K=5)
+    mk1 = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    xs1 = torch.zeros(n, dtype=torch.float32, device="cuda")
+    for _ in range(3):
+        mdl.foreground(v.D, mk1, 0.1)
+        mdl.background(v.D, xs1, static=True)
+    torch.cuda.synchronize()
+    mk2 = torch.zeros_like(mk1)
+    xs2 = torch.zeros_like(xs1)
+    mdl.foreground(v.D, mk2, 0.1)
+    torch.cuda.synchronize()
+    mdl.background(v.D, xs2, static=True)
+    torch.cuda.synchronize()
+    assert torch.equal(mk1, mk2)
+    assert torch.equal(xs1, xs2)
