@@ -291,6 +291,52 @@ def dmd_exact(x: np.ndarray, k: int):
     return lam, Phi, b
 
 
+# ---------------------------------------------------------------- automatic target rank
+def gd_lambda_star(beta: float) -> float:
+    """The optimal hard threshold coefficient for a known noise level (Gavish and Donoho,
+    "The optimal hard threshold for singular values is 4/sqrt(3)", 2014), aspect ratio
+    beta = (smaller dimension) / (larger dimension) in (0, 1]:
+    lambda*(beta) = sqrt(2 (beta + 1) + 8 beta / ((beta + 1) + sqrt(beta^2 + 14 beta + 1)))."""
+    b = float(beta)
+    return float(np.sqrt(2.0 * (b + 1.0) + 8.0 * b / ((b + 1.0) + np.sqrt(b * b + 14.0 * b + 1.0))))
+
+
+def mp_median(beta: float) -> float:
+    """Median of the Marchenko-Pastur law of ratio beta in (0, 1] (variance 1): the mu with
+    int_a^mu sqrt((b - t)(t - a)) / (2 pi beta t) dt = 1/2, a, b = (1 -+ sqrt(beta))^2, by
+    numerical quadrature and root finding."""
+    from scipy.integrate import quad
+    from scipy.optimize import brentq
+    b_ = float(beta)
+    lo, hi = (1.0 - np.sqrt(b_)) ** 2, (1.0 + np.sqrt(b_)) ** 2
+    def dens(t):
+        # the density; at beta = 1 it is integrable like t^(-1/2) at t = a = 0
+        return np.sqrt(max((hi - t) * (t - lo), 0.0)) / (2.0 * np.pi * b_ * t) if t > 0.0 else 0.0
+
+    def cdf(x):
+        return quad(dens, lo, x, limit=200, epsabs=1e-14, epsrel=1e-13)[0] if x > lo else 0.0
+    return float(brentq(lambda x: cdf(x) - 0.5, lo, hi, xtol=1e-14, rtol=1e-14))
+
+
+def gd_omega(beta: float) -> float:
+    """The threshold coefficient for an unknown noise level: omega(beta) =
+    lambda*(beta) / sqrt(mu_beta), applied to the median singular value."""
+    return gd_lambda_star(beta) / np.sqrt(mp_median(beta))
+
+
+def optimal_rank(Yhat: np.ndarray):
+    """Automatic target rank (Section 3.2, Remark 2): the optimal hard threshold of Gavish
+    and Donoho on the singular values of Y = Y^[:, :m-1] with the noise level unknown:
+    tau* = omega(beta) * median(sigma), beta = min(p, m-1) / max(p, m-1), and k the number of
+    singular values above tau*.  Returns (k, tau*, sigma) with sigma all min(p, m-1)
+    singular values in descending order."""
+    p, m = Yhat.shape
+    s = np.linalg.svd(Yhat[:, :m - 1], compute_uv=False)
+    beta = min(p, m - 1) / max(p, m - 1)
+    tau = gd_omega(beta) * float(np.median(s))
+    return int(np.count_nonzero(s > tau)), tau, s
+
+
 # ---------------------------------------------------------------- selection
 def omp(Phi: np.ndarray, x1: np.ndarray, K: int, lam: Optional[np.ndarray] = None,
         margins: Optional[list] = None):

@@ -531,3 +531,44 @@ def test_f_measure_definition():
     assert abs(R.f_measure(mk, gt) - 4 / 7) < 1e-15
     assert R.f_measure(np.zeros(8, bool), gt) == 0.0
     assert R.f_measure(gt, gt) == 1.0
+
+
+# ------------------------------------------------------------------ automatic target rank (Remark 2)
+def test_gd_lambda_star_square_case_is_4_over_sqrt3():
+    """beta = 1: lambda* = sqrt(4 + 8 / (2 + 4)) = sqrt(16/3) = 4 / sqrt(3)."""
+    assert abs(R.gd_lambda_star(1.0) - 4.0 / np.sqrt(3.0)) < 1e-15
+    assert abs(R.gd_lambda_star(1e-12) - np.sqrt(2.0)) < 1e-9      # beta -> 0: sqrt(2)
+
+
+def test_mp_median_against_monte_carlo():
+    """The median eigenvalue of W^T W / n for an n x mm Gaussian W (beta = mm / n) converges
+    to the Marchenko-Pastur median; at n = 4000 the sample median is within 1e-2."""
+    rng = np.random.default_rng(2024)
+    for n, mm in ((4000, 1000), (3000, 3000)):
+        W = rng.normal(size=(n, mm))
+        ev = np.linalg.eigvalsh(W.T @ W / n)
+        assert abs(np.median(ev) - R.mp_median(mm / n)) < 1e-2, (n, mm, np.median(ev), R.mp_median(mm / n))
+
+
+def test_gd_omega_against_the_published_cubic():
+    """Gavish and Donoho give omega(beta) ~ 0.56 beta^3 - 0.95 beta^2 + 1.82 beta + 1.43 as an
+    approximation; the exact coefficient stays within 0.02 of it over (0, 1], and
+    omega(1) = 2.858 (to three decimals)."""
+    for beta in (0.05, 0.1, 0.25, 0.5, 0.75, 1.0):
+        cubic = 0.56 * beta ** 3 - 0.95 * beta ** 2 + 1.82 * beta + 1.43
+        assert abs(R.gd_omega(beta) - cubic) < 0.02, (beta, R.gd_omega(beta), cubic)
+    assert abs(R.gd_omega(1.0) - 2.858) < 1e-3
+
+
+def test_optimal_rank_recovers_planted_rank():
+    """A rank-r matrix with singular values far above the noise bulk plus i.i.d. noise: the
+    threshold keeps exactly the r planted directions, at two aspect ratios."""
+    rng = np.random.default_rng(7)
+    for p, m, r in ((2000, 500, 12), (600, 401, 7)):
+        U, _ = np.linalg.qr(rng.normal(size=(p, r)))
+        V, _ = np.linalg.qr(rng.normal(size=(m, r)))
+        sig = np.linspace(400.0, 120.0, r)
+        Y = (U * sig) @ V.T + rng.normal(size=(p, m))
+        k, tau, s = R.optimal_rank(Y)
+        assert k == r, (k, r, tau, s[:r + 2])
+        assert s[r - 1] > tau > s[r]
