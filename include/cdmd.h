@@ -182,6 +182,21 @@ cdmd_status cdmd_fit(cdmd_model* mdl, const void* d_video, void* stream);
    also returns UNSUPPORTED), OUT_OF_MEMORY. */
 cdmd_status cdmd_set_amplitudes(cdmd_model* mdl, int32_t space);
 
+/* Automatic target rank (Section 3.2, Remark 2): the optimal hard threshold of Gavish and
+   Donoho (2014) for an unknown noise level, applied to the singular values of Y, the sketch
+   of the snapshots X (eq. (eq:YCX)), in place of a given k.  d_video is sketched with cfg's
+   measurement matrix (cfg->k is ignored), the float64 Gram of the sketch is formed on the
+   device and its spectrum on the host (Householder tridiagonalisation, bisection);
+   sigma_1 >= ... >= sigma_r are the r = min(p, m-1) singular values of Y, beta = r / max(p,
+   m-1), tau* = omega(beta) median(sigma) with omega(beta) = lambda*(beta) / sqrt(mu_beta),
+   lambda*(beta) = sqrt(2 (beta + 1) + 8 beta / ((beta + 1) + sqrt(beta^2 + 14 beta + 1)))
+   and mu_beta the median of the Marchenko-Pastur law of ratio beta (numerical quadrature).
+   *k_out = #{i : sigma_i > tau*} (0 when none; the caller clamps it to the k a model is
+   created with, 1..40).  tau_out, sigma_out (r doubles, descending): optional.  Synchronises
+   `stream`.  Errors: as cdmd_create and cdmd_fit, NUMERIC for a non-finite Gram. */
+cdmd_status cdmd_optimal_rank(const cdmd_config* cfg, const void* d_video, void* stream, int32_t* k_out,
+                              double* tau_out, double* sigma_out);
+
 /* Results of the last fit, modes in canonical order (descending |b_j| ||phi_j||,
    conjugate partners with Im lambda > 0 first).  Each output is optional (NULL):
    lambda[2k] (re, im interleaved), b[2k] (re, im), sigma[k] (singular values of the

@@ -39,6 +39,16 @@ cdmd_status cdmd_dbg_omp_gram(const double* H, int32_t k, const double* c, doubl
                               int32_t K, const double* lam, int32_t* S, double* beta,
                               int32_t* ns, double* resid2);
 
+/* All eigenvalues (ascending, ev[n]) of the symmetric n x n row-major matrix A, as the
+   automatic target rank computes them on the host (Householder tridiagonalisation, Sturm
+   bisection).  Errors: INVALID_ARG, NUMERIC (non-finite input). */
+cdmd_status cdmd_dbg_sym_eigvals(const double* A, int32_t n, double* ev);
+
+/* The hard-threshold coefficients of the automatic target rank for aspect ratio beta in
+   (0, 1]: lambda*(beta), the Marchenko-Pastur median mu_beta and omega(beta) (each output
+   optional).  Errors: INVALID_ARG. */
+cdmd_status cdmd_dbg_gd_threshold(double beta, double* lambda_star, double* mp_median, double* omega);
+
 /* The device small linear algebra (truncated SVD, A~, eig(A~) and G = V S^-1 W from the
    m x m Gram Gr of the unscaled sketch), run on the host with the same code the GPU runs:
    groups = 1 by one thread; groups = 2..32 with the Lanczos vectors split by rows over that

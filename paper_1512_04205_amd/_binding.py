@@ -36,7 +36,7 @@ EXPORTED = [
     "cdmd_dbg_force_gather_sketch", "cdmd_dbg_sparse_form",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_train_noalloc", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
-    "cdmd_batch_free",
+    "cdmd_batch_free", "cdmd_optimal_rank",
 ]
 MLP_NPARAM = 4673
 
@@ -109,6 +109,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
     lib.cdmd_dbg_la_groups.argtypes = [P, I32]
     lib.cdmd_dbg_force_gather_sketch.argtypes = [P, I32]
+    lib.cdmd_optimal_rank.argtypes = [ctypes.POINTER(Config), P, P, ctypes.POINTER(I32), DP, DP]
     lib.cdmd_dbg_sparse_form.argtypes = [P, I32]
     lib.cdmd_dbg_la_phases.argtypes = [P, DP]
     lib.cdmd_mode_features.argtypes = [P, P, P]
@@ -159,6 +160,36 @@ def _video_ptr(video, dtype: int, n: int, m: int, ld: int) -> int:
             or video.stride(0) != ld:
         raise ValueError("video must be (m, >= n) with unit pixel stride and frame stride ld")
     return video.data_ptr()
+
+
+def optimal_rank(video, n: int, m: int, p: int, *, sketch: int = SKETCH_SPARSE, dtype: int = U8,
+                 ld: Optional[int] = None, idx: Optional[np.ndarray] = None, sign: Optional[np.ndarray] = None,
+                 seed: int = 0, sketch_prec: int = PREC_FP32, stream=None):
+    """Automatic target rank (Remark 2): the Gavish-Donoho hard threshold on the singular
+    values of the sketch.  Returns (k, tau, sigma)."""
+    lib = load_library()
+    ld = int(ld if ld is not None else n)
+    cfg = Config()
+    cfg.n, cfg.m, cfg.ld, cfg.k, cfg.p = int(n), int(m), ld, 1, int(p)
+    cfg.dtype, cfg.sketch, cfg.seed = dtype, sketch, seed
+    cfg.sketch_prec, cfg.lift_prec = sketch_prec, PREC_FP32
+    keep = []
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        cfg.nnz = idx.shape[1] if idx.ndim == 2 else 1
+        cfg.sparse_idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        keep.append(idx)
+    if sign is not None:
+        sign = np.ascontiguousarray(sign, dtype=np.int8)
+        cfg.sparse_sign = sign.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        keep.append(sign)
+    r = min(int(p), int(m) - 1)
+    sig = np.zeros(r)
+    k = ctypes.c_int32(0)
+    tau = ctypes.c_double(0.0)
+    _check(lib.cdmd_optimal_rank(ctypes.byref(cfg), _video_ptr(video, dtype, int(n), int(m), ld), _stream(stream),
+                                 ctypes.byref(k), ctypes.byref(tau), _dptr(sig)))
+    return int(k.value), float(tau.value), sig
 
 
 class Model:

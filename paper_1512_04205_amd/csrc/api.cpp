@@ -1100,6 +1100,38 @@ cdmd_status post_fit(cdmd_model* M, double t0, double t1, double t2) {
   return CDMD_OK;
 }
 
+cdmd_status cdmd_optimal_rank(const cdmd_config* cfg, const void* d_video, void* stream, int32_t* k_out,
+                              double* tau_out, double* sigma_out) {
+  g_err.clear();
+  if (!cfg || !d_video || !k_out) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  cdmd_config c = *cfg;
+  c.k = 1;  // the sketch and its Gram do not depend on k
+  cdmd_model* M = nullptr;
+  TRY(cdmd_create(&c, &M));
+  std::unique_ptr<cdmd_model> own(M);
+  hipStream_t st = as_stream(stream);
+  plan_fit(M, d_video);
+  TRY(run_sketch(M, d_video, st, true));
+  // the spectrum of Y = Y^[:, :m-1] from its Gram: sigma_i = scale sqrt(mu_i), the min(p, m-1)
+  // largest eigenvalues
+  const int N = M->N;
+  std::vector<double> ev;
+  if (!cdmd::la::sym_eigvals(M->h_gram, N, (int)M->m, ev)) return fail(CDMD_E_NUMERIC, "non-finite Gram");
+  const int r = std::min(N, M->p);
+  std::vector<double> sig(r);
+  for (int i = 0; i < r; ++i) sig[i] = M->sketch_scale * std::sqrt(std::max(ev[N - 1 - i], 0.0));
+  // the median of the r singular values (the mean of the middle two for even r)
+  const double med = (r & 1) ? sig[r / 2] : 0.5 * (sig[r / 2 - 1] + sig[r / 2]);
+  const double beta = (double)r / (double)std::max(N, M->p);
+  const double tau = cdmd::la::gd_omega(beta) * med;
+  int k = 0;
+  while (k < r && sig[k] > tau) ++k;
+  *k_out = k;
+  if (tau_out) *tau_out = tau;
+  if (sigma_out) std::memcpy(sigma_out, sig.data(), sizeof(double) * r);
+  return CDMD_OK;
+}
+
 cdmd_status cdmd_modes(const cdmd_model* Mc, double* lambda, double* b, double* sigma,
                        double* phi_norm, const void* d_video, void* d_phi, void* stream) {
   g_err.clear();
@@ -2051,6 +2083,24 @@ cdmd_status cdmd_dbg_eig_general(const double* A, int32_t k, double* lam, double
   if (!A || !lam || !W || k < 1) return fail(CDMD_E_INVALID_ARG, "bad arguments");
   if (!cdmd::la::eig_general(A, k, reinterpret_cast<cplx*>(lam), reinterpret_cast<cplx*>(W)))
     return fail(CDMD_E_NUMERIC, "eigensolver failed");
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_sym_eigvals(const double* A, int32_t n, double* ev) {
+  g_err.clear();
+  if (!A || !ev || n < 1) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  std::vector<double> v;
+  if (!cdmd::la::sym_eigvals(A, n, n, v)) return fail(CDMD_E_NUMERIC, "non-finite input");
+  std::memcpy(ev, v.data(), sizeof(double) * n);
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_gd_threshold(double beta, double* lambda_star, double* mp_median, double* omega) {
+  g_err.clear();
+  if (!(beta > 0.0 && beta <= 1.0)) return fail(CDMD_E_INVALID_ARG, "beta must be in (0, 1]");
+  if (lambda_star) *lambda_star = cdmd::la::gd_lambda_star(beta);
+  if (mp_median) *mp_median = cdmd::la::mp_median(beta);
+  if (omega) *omega = cdmd::la::gd_omega(beta);
   return CDMD_OK;
 }
 

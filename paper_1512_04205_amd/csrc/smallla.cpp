@@ -503,5 +503,141 @@ bool omp_gram(const cplx* H, int k, const cplx* c, double x1n2, int K, const cpl
   return true;
 }
 
+// --------------------------------------------------------------------------- spectra
+namespace {
+// Number of eigenvalues of the symmetric tridiagonal (d, e2 = squared off-diagonals)
+// smaller than x (inertia of the LDL^T pivots; a pivot too small in modulus counts as
+// negative).
+int tri_count_below(const std::vector<double>& d, const std::vector<double>& e2, double x, double pivmin) {
+  const int n = (int)d.size();
+  int cnt = 0;
+  double q = d[0] - x;
+  if (std::fabs(q) < pivmin) q = -pivmin;
+  if (q < 0.0) ++cnt;
+  for (int i = 1; i < n; ++i) {
+    q = d[i] - x - e2[i - 1] / q;
+    if (std::fabs(q) < pivmin) q = -pivmin;
+    if (q < 0.0) ++cnt;
+  }
+  return cnt;
+}
+}  // namespace
+
+bool sym_eigvals(const double* Ain, int n, int lda, std::vector<double>& ev) {
+  ev.assign(n, 0.0);
+  if (n < 1) return true;
+  std::vector<double> A((size_t)n * n);
+  for (int i = 0; i < n; ++i)
+    for (int j = 0; j < n; ++j) {
+      const double v = Ain[(size_t)i * lda + j];
+      if (!std::isfinite(v)) return false;
+      A[(size_t)i * n + j] = 0.5 * (v + Ain[(size_t)j * lda + i]);
+    }
+  // Householder: for column k, the reflector H = I - 2 v v^T (unit v) zeroes A[k+2.., k];
+  // the trailing block becomes H A22 H = A22 - v w^T - w v^T with w = 2 (p - (v^T p) v),
+  // p = A22 v.
+  std::vector<double> v(n), pv(n), w(n);
+  for (int k = 0; k + 2 < n; ++k) {
+    const int m = n - k - 1;  // size of the trailing block, rows/cols k+1..n-1
+    double xnorm2 = 0.0;
+    for (int i = 0; i < m; ++i) {
+      v[i] = A[(size_t)(k + 1 + i) * n + k];
+      xnorm2 += v[i] * v[i];
+    }
+    const double xnorm = std::sqrt(xnorm2);
+    if (xnorm == 0.0) continue;
+    const double alpha = v[0] > 0.0 ? -xnorm : xnorm;
+    v[0] -= alpha;
+    double vn2 = 0.0;
+    for (int i = 0; i < m; ++i) vn2 += v[i] * v[i];
+    if (vn2 == 0.0) continue;
+    const double vinv = 1.0 / std::sqrt(vn2);
+    for (int i = 0; i < m; ++i) v[i] *= vinv;
+    double vtp = 0.0;
+    for (int i = 0; i < m; ++i) {
+      const double* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+      double acc = 0.0;
+      for (int j = 0; j < m; ++j) acc += row[j] * v[j];
+      pv[i] = acc;
+      vtp += v[i] * acc;
+    }
+    for (int i = 0; i < m; ++i) w[i] = 2.0 * (pv[i] - vtp * v[i]);
+    for (int i = 0; i < m; ++i) {
+      double* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
+      for (int j = 0; j < m; ++j) row[j] -= v[i] * w[j] + w[i] * v[j];
+    }
+    A[(size_t)(k + 1) * n + k] = alpha;
+    A[(size_t)k * n + k + 1] = alpha;
+    for (int i = 1; i < m; ++i) A[(size_t)(k + 1 + i) * n + k] = A[(size_t)k * n + (k + 1 + i)] = 0.0;
+  }
+  std::vector<double> d(n), e2(n > 1 ? n - 1 : 1, 0.0);
+  double lo = 0.0, hi = 0.0, e2max = 0.0;
+  for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+  for (int i = 0; i + 1 < n; ++i) {
+    const double e = A[(size_t)(i + 1) * n + i];
+    e2[i] = e * e;
+    e2max = std::max(e2max, e2[i]);
+  }
+  // Gershgorin interval
+  lo = d[0], hi = d[0];
+  for (int i = 0; i < n; ++i) {
+    const double r = (i > 0 ? std::sqrt(e2[i - 1]) : 0.0) + (i + 1 < n ? std::sqrt(e2[i]) : 0.0);
+    lo = std::min(lo, d[i] - r);
+    hi = std::max(hi, d[i] + r);
+  }
+  const double tnorm = std::max(std::fabs(lo), std::fabs(hi));
+  const double pivmin = DBL_MIN * std::max(1.0, e2max);
+  lo -= 4.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin;
+  hi += 4.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin;
+  for (int r = 0; r < n; ++r) {  // the r-th smallest: count(a) <= r < count(b)
+    double a = lo, b = hi;
+    for (int it = 0; it < 200 && b - a > 2.0 * DBL_EPSILON * std::max(std::fabs(a), std::fabs(b)) + pivmin; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (mid <= a || mid >= b) break;
+      if (tri_count_below(d, e2, mid, pivmin) > r) b = mid;
+      else a = mid;
+    }
+    ev[r] = 0.5 * (a + b);
+  }
+  return true;
+}
+
+double gd_lambda_star(double beta) {
+  return std::sqrt(2.0 * (beta + 1.0) + 8.0 * beta / ((beta + 1.0) + std::sqrt(beta * beta + 14.0 * beta + 1.0)));
+}
+
+double mp_median(double beta) {
+  // t(theta) = a + (b - a)(1 - cos theta)/2 on [0, pi] turns the density
+  // sqrt((b - t)(t - a)) / (2 pi beta t) dt into the smooth ((b - a)^2/4) sin^2(theta) /
+  // (2 pi beta t(theta)) dtheta; its integral (composite Simpson) is the distribution
+  // function, and the median is found by bisection on theta.
+  const double sb = std::sqrt(beta), a = (1.0 - sb) * (1.0 - sb), b = (1.0 + sb) * (1.0 + sb);
+  const double h2 = 0.25 * (b - a) * (b - a);
+  auto f = [&](double th) {
+    const double s = std::sin(th);
+    const double t = a + 0.5 * (b - a) * (1.0 - std::cos(th));
+    // a = 0 (beta = 1): sin^2 / t = (1 + cos) / (b / 2), finite at theta = 0
+    if (t <= 0.0) return a == 0.0 ? h2 * (1.0 + std::cos(th)) / (M_PI * beta * b) : 0.0;
+    return h2 * s * s / (2.0 * M_PI * beta * t);
+  };
+  auto cdf = [&](double th1) {
+    const int panels = 2048;
+    const double hh = th1 / panels;
+    double acc = f(0.0) + f(th1);
+    for (int i = 1; i < panels; ++i) acc += (i & 1 ? 4.0 : 2.0) * f(i * hh);
+    return acc * hh / 3.0;
+  };
+  double lo = 0.0, hi = M_PI;
+  for (int it = 0; it < 80; ++it) {
+    const double mid = 0.5 * (lo + hi);
+    if (cdf(mid) < 0.5) lo = mid;
+    else hi = mid;
+  }
+  const double th = 0.5 * (lo + hi);
+  return a + 0.5 * (b - a) * (1.0 - std::cos(th));
+}
+
+double gd_omega(double beta) { return gd_lambda_star(beta) / std::sqrt(mp_median(beta)); }
+
 }  // namespace la
 }  // namespace cdmd

@@ -64,5 +64,18 @@ bool omp_gram(const cplx* H, int k, const cplx* c, double x1n2, int K, const cpl
               double stop_rel, std::vector<int>& S, std::vector<cplx>& beta,
               double* resid2);
 
+// All eigenvalues (ascending) of the symmetric n x n matrix A (row-major, leading
+// dimension lda): Householder reduction to tridiagonal form, then bisection with Sturm
+// counts.  Returns false on non-finite input.
+bool sym_eigvals(const double* A, int n, int lda, std::vector<double>& ev);
+
+// The optimal hard threshold of Gavish and Donoho for an aspect ratio beta = (smaller
+// dimension) / (larger dimension) in (0, 1]: lambda*(beta) for a known noise level, the
+// median mu_beta of the Marchenko-Pastur law of ratio beta, and omega(beta) =
+// lambda*(beta) / sqrt(mu_beta), the coefficient of the median singular value.
+double gd_lambda_star(double beta);
+double mp_median(double beta);
+double gd_omega(double beta);
+
 }  // namespace la
 }  // namespace cdmd

@@ -343,3 +343,33 @@ def test_team_small_la_non_finite_gram(groups):
     st = lib.cdmd_dbg_team_small_la(_p(Gr), m, k, 1e-13, 1.0, groups, *[_p(o) for o in out],
                                     ctypes.byref(ctypes.c_int32()))
     assert st == P.E_NUMERIC
+
+
+# ------------------------------------------------------------------ automatic target rank, host part
+def test_host_spectrum_matches_lapack():
+    """The host eigenvalues the automatic rank uses (Householder + bisection) against
+    LAPACK on a sketch-like Gram (a few large eigenvalues over a noise bulk) and a random
+    symmetric matrix."""
+    lib = _lib()
+    lib.cdmd_dbg_sym_eigvals.argtypes = [DP, ctypes.c_int32, DP]
+    rng = np.random.default_rng(3)
+    Y = rng.normal(size=(600, 150)) + 50.0 * np.outer(rng.normal(size=600), rng.normal(size=150))
+    for A in (Y.T @ Y, rng.normal(size=(77, 77))):
+        A = np.ascontiguousarray(0.5 * (A + A.T))
+        ev = np.zeros(A.shape[0])
+        assert lib.cdmd_dbg_sym_eigvals(_p(A), A.shape[0], _p(ev)) == 0
+        ref = np.linalg.eigvalsh(A)
+        assert np.abs(ev - ref).max() <= 1e-12 * np.abs(ref).max(), np.abs(ev - ref).max()
+
+
+def test_host_threshold_coefficients_match_oracle():
+    """lambda*(beta), the Marchenko-Pastur median and omega(beta) of the library against
+    the oracle's (quadrature) at several aspect ratios, including beta = 1."""
+    lib = _lib()
+    lib.cdmd_dbg_gd_threshold.argtypes = [ctypes.c_double, DP, DP, DP]
+    for beta in (0.01, 0.2495, 0.5, 0.9, 1.0):
+        ls, mu, om = ctypes.c_double(), ctypes.c_double(), ctypes.c_double()
+        assert lib.cdmd_dbg_gd_threshold(beta, ctypes.byref(ls), ctypes.byref(mu), ctypes.byref(om)) == 0
+        assert abs(ls.value - R.gd_lambda_star(beta)) <= 1e-14
+        assert abs(mu.value - R.mp_median(beta)) <= 1e-10 * R.mp_median(beta), (beta, mu.value, R.mp_median(beta))
+        assert abs(om.value - R.gd_omega(beta)) <= 1e-10 * R.gd_omega(beta)
