@@ -1662,7 +1662,7 @@ __global__ __launch_bounds__(64) void k_la_prep(SLADesc d1, const SLADesc* __res
 // Lanczos and the Ritz vectors of T_J: la_groups(N) workgroups of SLA_A_NT threads per solve
 // (blockIdx.x), each owning a range of rows of the Lanczos vectors; group 0 runs the
 // convergence checks and writes the results.
-constexpr int SLA_A_NT = 512;  // Lanczos workgroup size: 256 registers per thread, no spills
+constexpr int SLA_A_NT = 512;  // Lanczos workgroup size: 256 registers per thread
 
 __global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __restrict__ ds) {
   using namespace tla;
@@ -1676,11 +1676,14 @@ __global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __
   __shared__ int s_flag[1], s_ok[1];
   __shared__ double s_fast[SLA_FAST];
   __shared__ double s_qc[tla::kLaQCache];
+  __shared__ double s_ts[16];  // group 0's phase clocks, accumulated in LDS and written at the end
   const SmallLAOutLayout Lo = small_la_out_layout(N, k);
   const SmallLALayout Ls = small_la_layout(N, k, d.Jmax);
   double* out = d.out;
+  if (threadIdx.x < 16) s_ts[threadIdx.x] = 0.0;
+  __syncthreads();
   DevTeam tm;
-  la_team(tm, s_red, g == 0 ? out + Lo.timing : nullptr);
+  la_team(tm, s_red, g == 0 ? s_ts : nullptr);
   tm.tick(-1);
   SmallLAWork ws;
   la_work(ws, d, s_q, s_w, s_h, s_alpha, s_beta, s_fast, s_flag, s_qc);
@@ -1697,6 +1700,9 @@ __global__ __launch_bounds__(SLA_A_NT) void k_la_a(SLADesc d1, const SLADesc* __
   xg.s_ok = s_ok;
   int J = 0;
   const int st = small_la_phase_a(tm, xg, d.Gr, m, k, d.rtol, d.Jmax, ws, out + Lo.mu, ws.Z, &J);
+  __syncthreads();
+  // slots 4..7 belong to the kernels after this one
+  if (g == 0 && threadIdx.x < 16 && (threadIdx.x < 4 || threadIdx.x >= 8)) out[Lo.timing + threadIdx.x] = s_ts[threadIdx.x];
   if (tm.tid == 0) {
     if (g == 0) {
       out[Lo.status] = (double)st;

@@ -223,10 +223,13 @@ TLA_HD void tridiag_topk_values(TM& tm, const double* a, const double* b, const 
 
 template <class TM>
 TLA_HD void tridiag_orthonormalise(TM& tm, int J, int kk, double* work, double* Z);
+template <class TM>
+TLA_HD void tridiag_sign_columns(TM& tm, int J, int kk, double* Z);
 
 // Eigenvectors of the symmetric tridiagonal (a, b) for theta[0..kk-1] (descending) by three
-// steps of inverse iteration, each a solve with the LU factors (row interchanges) of
-// T - theta I, one thread per eigenvector, all at once: unit vectors.  Vectors of nearly
+// steps of inverse iteration from hashed start vectors (a different one per eigenvector),
+// each a solve with the LU factors (row interchanges) of T - theta I, one thread per
+// eigenvector, all at once: unit vectors.  Vectors of nearly
 // equal eigenvalues can come out with a small mutual component (of order eps ||T|| / gap);
 // with orth set, the columns are then orthonormalised in order (which keeps each in the
 // span of the computed vectors of its cluster) and signed so that the largest-modulus
@@ -245,7 +248,7 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
       const double bi = b[i], dn = a[i + 1] - th, bn = i + 2 < J ? b[i + 1] : 0.0;
       double* w = W + i * ys;
       if (fabs(bi) > fabs(p0)) {  // interchange rows i and i+1
-        const double inv = 1.0 / bi, l = p0 * inv;
+        const double inv = tm.recip(bi), l = p0 * inv;
         w[0] = inv;
         w[st] = dn;
         w[2 * st] = 1.0;
@@ -254,7 +257,7 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
         p1 = -l * bn;
       } else {
         if (fabs(p0) < tiny) p0 = p0 < 0.0 ? -tiny : tiny;
-        const double inv = 1.0 / p0, l = bi * inv;
+        const double inv = tm.recip(p0), l = bi * inv;
         w[0] = inv;
         w[st] = p1;
         w[2 * st] = 0.0;
@@ -264,9 +267,9 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
       }
     }
     if (fabs(p0) < tiny) p0 = p0 < 0.0 ? -tiny : tiny;
-    W[(J - 1) * ys] = 1.0 / p0;
+    W[(J - 1) * ys] = tm.recip(p0);
     double* y = W + 4 * st;  // y_i at y[i*ys]
-    for (int i = 0; i < J; ++i) y[i * ys] = 1.0 + 0.5 * sin(1.7 * (i + 1) + 0.37 * r);
+    for (int i = 0; i < J; ++i) y[i * ys] = lanczos_start(i, 1 + r);  // a different start per vector
     for (int it = 0; it < 3; ++it) {
       // forward (L, with the interchanges): four steps per round, their loads first (step
       // i reads y_{i+1} before step i+1 overwrites it)
@@ -362,6 +365,46 @@ TLA_HD void tridiag_vectors(TM& tm, const double* a, const double* b, int J, int
 // signed so that the largest-modulus component is positive.  work: kk^2 doubles.
 template <class TM>
 TLA_HD void tridiag_orthonormalise(TM& tm, int J, int kk, double* work, double* Z) {
+  // Columns already orthonormal to within 1e-4 (the eigenvectors of distinct eigenvalues
+  // from inverse iteration are, to about eps ||T|| / gap): with Z^T Z = I + E, the Cholesky
+  // factor is R = I + U + O(E^2), U the strict upper triangle of E plus half its diagonal,
+  // so Z (I - U) is the Q factor of Z (the in-order Gram-Schmidt result) up to O(E^2).  Two
+  // such first-order passes take E from 1e-4 to below rounding.  The products run in
+  // parallel over all (p, q) and (i, q) pairs instead of the sequential Cholesky below.
+  {
+    double* E = work;                    // kk x kk, upper triangle
+    double* Zn = work + (int64_t)kk * kk;  // J x kk
+    bool first_order = true;
+    for (int pass = 0; pass < 2 && first_order; ++pass) {
+      double big = 0.0;
+      for (int e = tm.tid; e < kk * kk; e += tm.nt) {
+        const int p = e / kk, q = e % kk;
+        if (p > q) continue;
+        double d = 0.0;
+        for (int i = 0; i < J; ++i) d += Z[(int64_t)i * kk + p] * Z[(int64_t)i * kk + q];
+        if (p == q) d -= 1.0;
+        E[e] = d;
+        if (!(fabs(d) <= 1e-4)) big = 1.0;
+      }
+      big = tm.sum(big);
+      if (big > 0.0) first_order = false;  // the full path below
+      if (!first_order) break;
+      for (int e = tm.tid; e < J * kk; e += tm.nt) {
+        const int i = e / kk, q = e % kk;
+        const double* zi = Z + (int64_t)i * kk;
+        double v = zi[q] - 0.5 * E[q * kk + q] * zi[q];
+        for (int p = 0; p < q; ++p) v -= zi[p] * E[p * kk + q];
+        Zn[e] = v;
+      }
+      tm.sync();
+      for (int e = tm.tid; e < J * kk; e += tm.nt) Z[e] = Zn[e];
+      tm.sync();
+    }
+    if (first_order) {
+      tridiag_sign_columns(tm, J, kk, Z);
+      return;
+    }
+  }
   // Orthonormalise the columns in order by Cholesky QR, twice: C = Z^T Z = R^T R, then
   // Z <- Z R^-1 (the Q factor of Z, which Gram-Schmidt in column order would also give;
   // the columns are close to orthonormal, so C is well conditioned and the second pass
@@ -406,7 +449,13 @@ TLA_HD void tridiag_orthonormalise(TM& tm, int J, int kk, double* work, double* 
     }
     tm.sync();
   }
-  // sign: largest-modulus component (lowest index on ties) positive; a thread per column
+  tridiag_sign_columns(tm, J, kk, Z);
+}
+
+// Columns of Z (J x kk) signed so that the largest-modulus component (lowest index on ties)
+// is positive; a thread per column.
+template <class TM>
+TLA_HD void tridiag_sign_columns(TM& tm, int J, int kk, double* Z) {
   for (int r = tm.tid; r < kk; r += tm.nt) {
     double best = -1.0;
     int bi = 0;
