@@ -283,8 +283,10 @@ void cdmd_batch_free(cdmd_batch* batch);
    amplitude profile instead of a fixed rule (Section 2.2, "DMD for Foreground/Background
    Separation", its last paragraph).  Parameters: one flat float32 vector of CDMD_MLP_NPARAM numbers, W1 (64 x 6
    row-major), b1 (64), W2 (64 x 64), b2 (64), w3 (64), b3.  Features of mode j (canonical
-   order, k modes, m frames): |lambda_j|, |arg lambda_j|, log|b_j|, ||phi_j||,
-   (1/m) sum_t |b_j|^2 |lambda_j|^{2t} ||phi_j||^2 / ||x_1||^2, j / k.
+   order, k modes, m frames): |lambda_j|, |arg lambda_j|, log(|b_j| ||phi_j|| / ||x_1||),
+   ||phi_j|| / max_i ||phi_i||, (1/m) sum_t |b_j|^2 |lambda_j|^{2t} ||phi_j||^2 / ||x_1||^2,
+   j / k.  The amplitude and mode norm enter relative to the first frame and to the
+   largest mode, so that the features do not depend on the frame size or the scale of C.
    All pointers named d_* are device memory owned by the caller; work goes on `stream`
    (NULL = default stream) and the calls return after enqueueing unless stated. */
 #define CDMD_MLP_NPARAM 4673
@@ -326,8 +328,10 @@ cdmd_status cdmd_mlp_train_noalloc(float* d_params, float* d_adam_m, float* d_ad
                                    int32_t batch, int32_t steps, float lr, int64_t step0, float* d_losses,
                                    void* stream);
 
-/* Logits of n samples (d_X: n x 6) into d_logits; bf16 != 0 rounds weights, inputs and
-   hidden activations to bfloat16 (float32 accumulation).  Errors: INVALID_ARG, DEVICE. */
+/* Logits of n samples (d_X: n x 6) into d_logits; bf16 != 0 rounds the hidden activations
+   and the weights after the input layer to bfloat16 (float32 accumulation; the input layer,
+   which carries the features' standardisation, stays float32).  Errors: INVALID_ARG,
+   DEVICE. */
 cdmd_status cdmd_mlp_forward(const float* d_params, const float* d_X, int32_t n, int32_t bf16,
                              float* d_logits, void* stream);
 

@@ -10,11 +10,15 @@ on x_1, Algorithm 1's background selection) would pick it.
 Features of mode j (k modes, m frames; lambda_j, b_j, phi_j of the fit):
   f0 = |lambda_j|
   f1 = |arg lambda_j|                          in [0, pi]
-  f2 = log |b_j|                               (log of max(|b_j|, 1e-300))
-  f3 = ||phi_j||_2
+  f2 = log(|b_j| ||phi_j|| / ||x_1||)          (log of max(., 1e-300)): the mode's share
+                                               of the first frame
+  f3 = ||phi_j||_2 / max_i ||phi_i||_2         (0 if every mode is zero)
   f4 = (1/m) sum_{t=0}^{m-1} |b_j|^2 |lambda_j|^{2t} ||phi_j||^2 / ||x_1||^2
        (mean energy of the mode's contribution over the frames, relative to frame 1)
   f5 = j / k                                   (position in the canonical order)
+The amplitude and the mode norm enter relative to the first frame and to the largest
+mode, so that the features do not change with the frame size or the scale of C (a
+selector trained on small videos is applied to large ones).
 
 Network: h1 = GELU(W1 f + b1) (64), h2 = GELU(W2 h1 + b2) (64), z = w3 . h2 + b3, with
 the exact GELU(x) = x Phi(x) = x (1 + erf(x / sqrt 2)) / 2.  Loss: mean binary
@@ -65,8 +69,9 @@ def features(lam, b, phi_norm, x1_norm2: float, m: int) -> np.ndarray:
     F = np.empty((k, NF))
     F[:, 0] = a
     F[:, 1] = np.abs(np.angle(lam))
-    F[:, 2] = np.log(np.maximum(np.abs(b), 1e-300))
-    F[:, 3] = phi_norm
+    F[:, 2] = np.log(np.maximum(np.abs(b) * phi_norm / math.sqrt(x1_norm2), 1e-300))
+    pmax = phi_norm.max() if k else 0.0
+    F[:, 3] = phi_norm / pmax if pmax > 0 else 0.0
     t = np.arange(m, dtype=np.float64)
     F[:, 4] = (np.abs(b) ** 2 * phi_norm ** 2 / x1_norm2) * np.mean(a[:, None] ** (2.0 * t[None, :]), axis=1)
     F[:, 5] = np.arange(k) / k

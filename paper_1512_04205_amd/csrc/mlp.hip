@@ -54,7 +54,9 @@ struct Net {
   float b3;
 };
 
-// Stage the parameters into LDS (optionally rounded to bfloat16).
+// Stage the parameters into LDS; with round_bf16 the hidden and output layers' weights
+// are rounded to bfloat16 (the input layer stays float32: it carries the features'
+// standardisation, whose large, cancelling terms bfloat16 would not hold).
 __device__ void stage(const float* __restrict__ th, float* lds, bool round_bf16, Net& net) {
   net.W2 = lds;
   net.W1 = lds + MH * W2S;
@@ -65,10 +67,7 @@ __device__ void stage(const float* __restrict__ th, float* lds, bool round_bf16,
     const float v = th[O_W2 + e];
     net.W2[(e / MH) * W2S + (e % MH)] = round_bf16 ? bf16r(v) : v;
   }
-  for (int e = threadIdx.x; e < MH * MF; e += blockDim.x) {
-    const float v = th[O_W1 + e];
-    net.W1[e] = round_bf16 ? bf16r(v) : v;
-  }
+  for (int e = threadIdx.x; e < MH * MF; e += blockDim.x) net.W1[e] = th[O_W1 + e];
   for (int e = threadIdx.x; e < MH; e += blockDim.x) {
     net.b1[e] = th[O_B1 + e];
     net.b2[e] = th[O_B2 + e];
@@ -187,8 +186,9 @@ __global__ __launch_bounds__(256) void k_mlp_update(const float* __restrict__ pa
   }
 }
 
-// Logits of n samples; with round_bf16 the weights, inputs and hidden activations are
-// rounded to bfloat16 (float32 accumulation).  One wave per sample.
+// Logits of n samples; with round_bf16 the hidden activations and the weights after the
+// input layer are rounded to bfloat16 (float32 accumulation; the input layer in float32).
+// One wave per sample.
 __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ th, const float* __restrict__ X,
                                                      int n, int round_bf16, float* __restrict__ logits) {
   __shared__ float lds[kLdsFloats];
@@ -200,8 +200,7 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ t
     float a1 = net.b1[i];
 #pragma unroll
     for (int f = 0; f < MF; ++f) {
-      const float xv = round_bf16 ? bf16r(X[(int64_t)q * MF + f]) : X[(int64_t)q * MF + f];
-      a1 += net.W1[i * MF + f] * xv;
+      a1 += net.W1[i * MF + f] * X[(int64_t)q * MF + f];
     }
     float h1 = gelu(a1);
     if (round_bf16) h1 = bf16r(h1);
@@ -220,7 +219,8 @@ __global__ __launch_bounds__(256) void k_mlp_forward(const float* __restrict__ t
   }
 }
 
-// Features of k modes (one wave per mode): |lambda|, |arg lambda|, log|b|, ||phi||,
+// Features of k modes (one wave per mode): |lambda|, |arg lambda|,
+// log(|b| ||phi|| / ||x_1||), ||phi|| / max_i ||phi_i||,
 // (1/m) sum_t |b|^2 |lambda|^2t ||phi||^2 / ||x_1||^2 (lanes over t), j / k.
 // in: lam[2k], b[2k], phin[k] (float64).
 __global__ __launch_bounds__(256) void k_mode_features(const double* __restrict__ lam, const double* __restrict__ b,
@@ -233,17 +233,23 @@ __global__ __launch_bounds__(256) void k_mode_features(const double* __restrict_
   const double a = hypot(lr, li);
   const double bm = hypot(b[2 * j], b[2 * j + 1]);
   const double pn = phin[j];
+  double pmax = 0.0;
+  for (int i = l; i < k; i += 64) pmax = fmax(pmax, phin[i]);
   double s = 0.0;
   const double la2 = a > 0.0 ? 2.0 * log(a) : -INFINITY;
   for (int64_t t = l; t < m; t += 64) s += t == 0 ? 1.0 : exp((double)t * la2);
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+  for (int o = 32; o > 0; o >>= 1) {
+    s += __shfl_xor(s, o, 64);
+    pmax = fmax(pmax, __shfl_xor(pmax, o, 64));
+  }
   if (l == 0) {
     float* f = F + (int64_t)j * MF;
+    const double rel = bm * pn / sqrt(x1n2);
     f[0] = (float)a;
     f[1] = (float)fabs(atan2(li, lr));
-    f[2] = (float)log(bm > 1e-300 ? bm : 1e-300);
-    f[3] = (float)pn;
+    f[2] = (float)log(rel > 1e-300 ? rel : 1e-300);
+    f[3] = (float)(pmax > 0.0 ? pn / pmax : 0.0);
     f[4] = (float)(bm * bm * pn * pn / x1n2 * (s / (double)m));
     f[5] = (float)((double)j / (double)k);
   }

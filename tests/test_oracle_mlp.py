@@ -74,8 +74,16 @@ def test_features_closed_forms():
     F = M.features(lam, b, phin, x1, m)
     np.testing.assert_allclose(F[:, 0], np.abs(lam))
     np.testing.assert_allclose(F[:, 1], [0.0, 0.3, 0.3, 0.0], atol=1e-15)
-    np.testing.assert_allclose(F[:, 2], np.log(np.abs(b)))
+    # |b_j| ||phi_j|| / ||x_1|| with ||x_1|| = 3: 2 * 1.5 / 3 = 1, (1/sqrt 2) * 2 / 3 = sqrt(2) / 3
+    # and 1e-3 * 0.7 / 3
+    np.testing.assert_allclose(F[:, 2], [0.0, np.log(np.sqrt(2.0) / 3.0), np.log(np.sqrt(2.0) / 3.0),
+                                         np.log(7e-4 / 3.0)], atol=1e-15)
+    np.testing.assert_allclose(F[:, 3], [0.75, 1.0, 1.0, 0.35])
     np.testing.assert_allclose(F[:, 5], np.arange(k) / k)
+    # invariances: the scale of C moves b and phi in opposite directions; a larger frame
+    # scales phi and x_1 together
+    np.testing.assert_allclose(M.features(lam, 7.0 * b, phin / 7.0, x1, m), F, rtol=1e-13, atol=1e-15)
+    np.testing.assert_allclose(M.features(lam, b, 5.0 * phin, 25.0 * x1, m), F, rtol=1e-13, atol=1e-15)
     # |lambda| = 1: no decay; otherwise the geometric mean (1 - a^2m) / (m (1 - a^2))
     assert abs(F[0, 4] - 4.0 * 1.5 ** 2 / x1) < 1e-14
     a = 0.9
