@@ -721,14 +721,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3
 // ============================================================================
 // Background reconstruction and foreground threshold in one read of the video
 // (eq. (equ:DMDTerms) with its real-part footnote, eq. (eq:thres)).  A workgroup of
-// two waves owns 128 pixels and first copies all their frames into LDS, transposed to
-// one row per pixel (frame t at byte t of the row), so HBM delivers each video byte once:
+// four waves owns 128 pixels (32 per wave) and first copies all their frames into LDS,
+// transposed to one row per pixel (frame t at byte t of the row), so HBM delivers each
+// video byte once.  Two workgroups fit a CU's LDS, which gives every SIMD two waves: one
+// computes while the other waits for its tile.
 //
 //   phase 1: T^T = G~'^T X on bf16 MFMA 32x32x16, where G~'[t] = [Re | Im] of
 //            G_S[t-1] diag(beta_S) xscale (G~'[0] = 0, so the k-steps start at frame 0
 //            and every B fragment is one aligned 8-byte LDS read: 8 frames of a pixel)
 //            in NSG bf16 terms; float32 accumulation.  Wave w keeps acc[mb] = T^T of
-//            its pixel blocks 64w + 32mb (rows: columns c; lane columns: pixels).
+//            its pixel blocks 32 (RC_MB w + mb) (rows: columns c; lane columns: pixels).
 //   phase 2: L = V~ T on bf16 MFMA 32x32x16 per 32-frame block.  The B operands are
 //            the phase-1 accumulators split into NTV bf16 terms: a lane of the phase-1
 //            result holds one pixel and 16 columns, exactly a B fragment once the K order
@@ -742,7 +744,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(NB == 1 ? 3
 // Columns: mode s (< 16) sits in lane half h = s & 1 at slot j = 2 (s >> 1) + part
 // (part 0 = Re, 1 = Im), i.e. column rc_col(s, part).
 constexpr int RC_TP = 128;  // pixels per workgroup
-constexpr int RC_NT = 128;  // two waves
+constexpr int RC_MB = 1;    // 32-pixel blocks per wave
+constexpr int RC_NT = 64 * RC_TP / (32 * RC_MB);  // four waves
 constexpr int RC_PF = 4;    // k-steps of G~' operands loaded ahead
 constexpr int RC_LB = 8;    // 4x16-byte blocks a thread loads per batch of the tile load
 
@@ -834,14 +837,15 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
   {
     const int pc = tid & 7;
     const int64_t px = base + 16 * pc;
-    const int nquads = 4 * KS;       // a multiple of 16: the bounds below are uniform
+    constexpr int QS = RC_NT / 8;    // frame quads per batch row
+    const int nquads = 4 * KS;       // a multiple of 16: the bounds below are uniform per wave
     const uint8_t* src = a.D + px;
     uint8_t* dstc = sV + (size_t)(16 * pc) * S;
-    for (int q0 = tid >> 3; q0 < nquads; q0 += 16 * RC_LB) {
+    for (int q0 = tid >> 3; q0 < nquads; q0 += QS * RC_LB) {
       uint4 r[RC_LB][4];
 #pragma unroll
       for (int b = 0; b < RC_LB; ++b) {
-        const int fq = q0 + 16 * b;
+        const int fq = q0 + QS * b;
         if (fq >= nquads) break;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
@@ -858,7 +862,7 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
       }
 #pragma unroll
       for (int b = 0; b < RC_LB; ++b) {
-        const int fq = q0 + 16 * b;
+        const int fq = q0 + QS * b;
         if (fq >= nquads) break;
 #pragma unroll
         for (int d = 0; d < 4; ++d) {  // dword d of the rows: pixels 4d..4d+3 of the chunk
@@ -877,13 +881,14 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
   __syncthreads();
 
   // ---- phase 1 (Gp holds KS + RC_PF k-steps, the last RC_PF zero)
-  f32x16_t acc[2];
+  f32x16_t acc[RC_MB];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int mb = 0; mb < RC_MB; ++mb)
 #pragma unroll
     for (int j = 0; j < 16; ++j) acc[mb][j] = 0.f;
-  const uint8_t* rowp0 = sV + (64 * w + fl) * S + 8 * h;
-  const uint8_t* rowp1 = rowp0 + 32 * S;
+  const uint8_t* rowp[RC_MB];
+#pragma unroll
+  for (int mb = 0; mb < RC_MB; ++mb) rowp[mb] = sV + (32 * (RC_MB * w + mb) + fl) * S + 8 * h;
   {
     const uint4* gp = a.Gp + l;
     uint4 gq[RC_PF][NSG];
@@ -895,13 +900,14 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
 #pragma unroll
       for (int p = 0; p < RC_PF; ++p) {
         const int K = K0 + p;
-        const bf16x8_t xb0 = u8x8_bf16(*reinterpret_cast<const uint2*>(rowp0 + 16 * K));
-        const bf16x8_t xb1 = u8x8_bf16(*reinterpret_cast<const uint2*>(rowp1 + 16 * K));
+        bf16x8_t xb[RC_MB];
+#pragma unroll
+        for (int mb = 0; mb < RC_MB; ++mb) xb[mb] = u8x8_bf16(*reinterpret_cast<const uint2*>(rowp[mb] + 16 * K));
 #pragma unroll
         for (int t = NSG - 1; t >= 0; --t) {
           const bf16x8_t ga = __builtin_bit_cast(bf16x8_t, gq[p][t]);
-          acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga, xb0, acc[0], 0, 0, 0);
-          acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga, xb1, acc[1], 0, 0, 0);
+#pragma unroll
+          for (int mb = 0; mb < RC_MB; ++mb) acc[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ga, xb[mb], acc[mb], 0, 0, 0);
         }
 #pragma unroll
         for (int t = 0; t < NSG; ++t) gq[p][t] = gp[((K + RC_PF) * NSG + t) * 64];
@@ -913,9 +919,9 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
   // block i + 1 are issued before the threshold of block i, so the matrix cores and the
   // vector ALU overlap.
   const int nq = a.ns <= 8 ? 1 : 2;
-  bf16x8_t tb[2][2][NTV];
+  bf16x8_t tb[RC_MB][2][NTV];
 #pragma unroll
-  for (int mb = 0; mb < 2; ++mb)
+  for (int mb = 0; mb < RC_MB; ++mb)
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       float v[8];
@@ -929,11 +935,13 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
   const int64_t words = (n + 31) >> 5;
   const int fb0 = ts >> 5, fb1 = (te + 31) >> 5;
   const uint4* vp = a.Vp + l;
-  const int pxw = 64 * w;                       // this wave's first pixel in the tile
-  const bool pv0 = !RAGGED || base + pxw + fl < n, pv1 = !RAGGED || base + pxw + 32 + fl < n;
+  const int pxw = 32 * RC_MB * w;               // this wave's first pixel in the tile
+  bool pvb[RC_MB];
+#pragma unroll
+  for (int mb = 0; mb < RC_MB; ++mb) pvb[mb] = !RAGGED || base + pxw + 32 * mb + fl < n;
 
-  // L of frame block fbi for both pixel blocks
-  auto products = [&](int fbi, f32x16_t (&C)[2]) {
+  // L of frame block fbi for the wave's pixel blocks
+  auto products = [&](int fbi, f32x16_t (&C)[RC_MB]) {
     bf16x8_t va[2][NTV];
 #pragma unroll
     for (int q = 0; q < 2; ++q)
@@ -941,14 +949,14 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
       for (int t = 0; t < NTV; ++t)
         va[q][t] = __builtin_bit_cast(bf16x8_t, vp[(((int64_t)fbi * 2 + q) * NTV + t) * 64]);
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb)
+    for (int mb = 0; mb < RC_MB; ++mb)
 #pragma unroll
       for (int j = 0; j < 16; ++j) C[mb][j] = 0.f;
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       if (q >= nq) break;
 #pragma unroll
-      for (int mb = 0; mb < 2; ++mb) {  // two independent accumulation chains
+      for (int mb = 0; mb < RC_MB; ++mb) {  // independent accumulation chains
         if constexpr (NTV >= 3) {  // small products first
           C[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][2], tb[mb][q][0], C[mb], 0, 0, 0);
           C[mb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(va[q][0], tb[mb][q][2], C[mb], 0, 0, 0);
@@ -963,16 +971,17 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
     }
   };
   // the output of frame block fbi; EDGE: the block runs past [ts, te) (checks per frame)
-  auto emit = [&](int fbi, const f32x16_t (&C)[2], auto edge_c) {
+  auto emit = [&](int fbi, const f32x16_t (&C)[RC_MB], auto edge_c) {
     constexpr bool EDGE = decltype(edge_c)::value;
     const int fb = 32 * fbi;
-    uint32_t wmine[2] = {0u, 0u};
+    uint32_t wmine[RC_MB];
 #pragma unroll
-    for (int mb = 0; mb < 2; ++mb) {
-      // C[mb][j]: frame fb + 8(j/4) + 4h + j%4, pixel base + 64w + 32mb + fl
+    for (int mb = 0; mb < RC_MB; ++mb) {
+      // C[mb][j]: frame fb + 8(j/4) + 4h + j%4, pixel base + pxw + 32mb + fl
       const int pxl = pxw + 32 * mb + fl;
       const int64_t px = base + pxl;
-      const bool pv = mb == 0 ? pv0 : pv1;
+      const bool pv = pvb[mb];
+      wmine[mb] = 0u;
       if constexpr (MODE == 2) {
         float* out = reinterpret_cast<float*>(a.out) + px;
         static_for<0, 16>([&](auto jc) {
@@ -1011,16 +1020,17 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
       const int f = fb + fl;
       if (h == 0 && (!EDGE || f < te)) {
         uint32_t* wd = reinterpret_cast<uint32_t*>(a.out) + (int64_t)f * words + ((base + pxw) >> 5);
-        if (!RAGGED || base + pxw < n) wd[0] = wmine[0];
-        if (!RAGGED || base + pxw + 32 < n) wd[1] = wmine[1];
+#pragma unroll
+        for (int mb = 0; mb < RC_MB; ++mb)
+          if (!RAGGED || base + pxw + 32 * mb < n) wd[mb] = wmine[mb];
       }
     }
   };
-  auto emit_any = [&](int fbi, const f32x16_t (&C)[2]) {
+  auto emit_any = [&](int fbi, const f32x16_t (&C)[RC_MB]) {
     if (32 * fbi < ts || 32 * fbi + 32 > te) emit(fbi, C, std::true_type{});
     else emit(fbi, C, std::false_type{});
   };
-  f32x16_t Ca[2], Cb[2];
+  f32x16_t Ca[RC_MB], Cb[RC_MB];
   products(fb0, Ca);
   int fbi = fb0;
   for (; fbi + 2 <= fb1; fbi += 2) {
