@@ -10,11 +10,13 @@ atoms, threshold tau = 0.1, bit-packed mask.  One step = one cdmd_fit + cdmd_sel
     python bench.py [--steps K] [--warmup W] [--prec both|fp32|bf16|fp32_compressed]
                     [--no-cpu-baseline]
                     [--workload cfg2|cfg1|cfg3|cfg4] [--copy-ref-mib N]
+                    [--gauss-prec bf16|fp8] [--draw-c]
+    python bench.py --summarize trace|traffic|counters --dir D [--dir D2] --out FILE ...
 
 --workload cfg1 times the FP32 form of the dense Gaussian sketch on the 320x240x200
 float32 video (p = 500, k = 10); cfg3 the BF16 form on the 3840x2160x1000 uint8 video
-(p = 4000, k = 40); cfg4 fits 64 streams of mixed shape and sketch with one graph
-launch per step.  The default line is the 1080p workload above.
+(p = 4000, k = 40; --gauss-prec fp8 the FP8 form; C is kept in device memory unless
+--draw-c); cfg4 fits 64 streams of mixed shape and sketch with one graph launch per step.  The default line is the 1080p workload above.
 """
 from __future__ import annotations
 
@@ -292,6 +294,153 @@ def measured_traffic(workload):
     return {q: d["fetch_bytes"] + d["write_bytes"] for q, d in t["kernels"].items()}
 
 
+# ---------------------------------------------------------------- profile summaries
+# `python bench.py --summarize trace|traffic|counters ...` turns rocprofv3 CSV output into
+# the short summaries kept under profiles/ (the traffic summary is what measured_traffic
+# reads back).
+
+GROUPS = (("k_sketch", "sketch"), ("k_gram", "gram"), ("k_lift", "lift"), ("k_recon<", "recon"),
+          ("k_la_a", "lanczos"))
+
+
+def short_name(kn):
+    kn = kn.replace("void ", "").replace("cdmd::k::", "")
+    depth, out = 0, []
+    for ch in kn:  # drop the argument list, keep template arguments
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def group_of(name):
+    for key, g in GROUPS:
+        if name.startswith(key):
+            return g
+    return None
+
+
+def read_csv(path):
+    import csv
+    with open(path) as f:
+        return list(csv.DictReader(f))
+
+
+def find_csv(d, suffix):
+    import glob
+    hits = sorted(glob.glob(os.path.join(d, "**", f"*{suffix}"), recursive=True))
+    if not hits:
+        raise SystemExit(f"no *{suffix} under {d}")
+    return hits[0]
+
+
+def summarize_trace(d, last, title, cmd, out_path, bench_log=None):
+    """Per-kernel durations over the last `last` dispatches of each kernel."""
+    rows = read_csv(find_csv(d, "kernel_trace.csv"))
+    per = {}
+    for r in sorted(rows, key=lambda r: int(r["Start_Timestamp"])):
+        per.setdefault(short_name(r["Kernel_Name"]), []).append(
+            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    lines = [title, "", "Command (from the repository root, TMPDIR=/tmp):", "  " + cmd, "",
+             f"Durations of each kernel's last {last} dispatches (warm-up and timed steps; the autotuner's",
+             "trial launches of other tile shapes come before them and are left out).", "",
+             f"{'kernel':58s} {'calls':>5s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}"]
+    tot = 0.0
+    table = []
+    for name, v in per.items():
+        v = v[-last:]
+        if len(v) < last:
+            continue
+        avg = sum(v) / len(v)
+        table.append((avg, name, v))
+    for avg, name, v in sorted(table, reverse=True):
+        tot += avg
+        lines.append(f"{name[:58]:58s} {len(v):5d} {avg:9.1f} {min(v):9.1f} {max(v):9.1f}")
+    lines += ["", f"sum of the averages: {tot:.1f} us"]
+    if bench_log:
+        with open(bench_log) as f:
+            js = [l for l in f if l.startswith("{")]
+        if js:
+            b = json.loads(js[-1])
+            lines.append(f"bench ms_per_step under the profiler: {b['ms_per_step']:.3f}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def counter_table(d):
+    """{dispatch: (kernel, {counter: value summed over instances}, duration_ns)}"""
+    rows = read_csv(find_csv(d, "counter_collection.csv"))
+    disp = {}
+    for r in rows:
+        did = int(r["Dispatch_Id"])
+        e = disp.setdefault(did, [r["Kernel_Name"], {}, int(r["End_Timestamp"]) - int(r["Start_Timestamp"])])
+        e[1][r["Counter_Name"]] = e[1].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+    return disp
+
+
+def summarize_traffic(fetch_dir, write_dir, workload, cmds, out_path, ref_mib=1024):
+    """HBM bytes per dispatch of each kernel group from FETCH_SIZE and WRITE_SIZE (KiB),
+    scaled by what the counters read for the copy of ref_mib MiB (ref_mib read and written);
+    the last dispatch of each group."""
+    res = {}
+    for kind, d in (("fetch", fetch_dir), ("write", write_dir)):
+        cname = "FETCH_SIZE" if kind == "fetch" else "WRITE_SIZE"
+        tab = counter_table(d)
+        ref = [v[1][cname] for k, v in sorted(tab.items()) if "copyBuffer" in v[0] or "copy" in v[0].lower()]
+        ref_kib = max(ref) if ref else None
+        res[kind + "_ref_kib"] = ref_kib
+        for did, (kn, cv, _) in sorted(tab.items()):
+            g = group_of(short_name(kn))
+            if g is None or cname not in cv:
+                continue
+            res.setdefault(g, {})[kind] = (short_name(kn), cv[cname])
+    expect = ref_mib * 1024.0
+    fs = expect / res["fetch_ref_kib"] if res["fetch_ref_kib"] else 1.0
+    ws = expect / res["write_ref_kib"] if res["write_ref_kib"] else 1.0
+    out = {"workload": workload, "commands": cmds,
+           "reference": {"kernel": f"device-to-device copy of {ref_mib} MiB", "fetch_kib": res["fetch_ref_kib"],
+                         "write_kib": res["write_ref_kib"], "fetch_scale": fs, "write_scale": ws},
+           "sources_sha256": sources_sha256(), "kernels": {}}
+    for _, g in GROUPS:
+        if g in res and "fetch" in res[g] and "write" in res[g]:
+            out["kernels"][g] = {"kernel": res[g]["fetch"][0],
+                                 "fetch_bytes": int(res[g]["fetch"][1] * 1024 * fs),
+                                 "write_bytes": int(res[g]["write"][1] * 1024 * ws)}
+    with open(out_path, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out, indent=1))
+
+
+def summarize_counters(d, title, cmd, out_path, kernels):
+    """The counters of the last dispatch of each kernel whose short name starts with one of
+    `kernels`, with the MFMA rate from SQ_INSTS_VALU_MFMA_MOPS_* (512 flops each)."""
+    tab = counter_table(d)
+    last = {}
+    for did, (kn, cv, dur) in sorted(tab.items()):
+        nm = short_name(kn)
+        if any(nm.startswith(k) for k in kernels):
+            last[nm] = (cv, dur)
+    lines = [title, "", "Command (from the repository root, TMPDIR=/tmp):", "  " + cmd, ""]
+    for nm, (cv, dur) in last.items():
+        lines.append(f"{nm}: {dur / 1e3:.1f} us under the profiler")
+        for c in sorted(cv):
+            lines.append(f"  {c:34s} {cv[c]:.6g}")
+        mops = sum(v for c, v in cv.items() if c.startswith("SQ_INSTS_VALU_MFMA_MOPS"))
+        if mops:
+            lines.append(f"  MFMA work {mops * 512 / 1e9:.2f} GFLOP -> {mops * 512 / dur / 1e3:.1f} TFLOP/s "
+                         f"over the dispatch")
+        if "SQ_VALU_MFMA_BUSY_CYCLES" in cv and "SQ_BUSY_CU_CYCLES" in cv and cv["SQ_BUSY_CU_CYCLES"]:
+            lines.append(f"  MFMA busy / CU busy cycles: {cv['SQ_VALU_MFMA_BUSY_CYCLES'] / cv['SQ_BUSY_CU_CYCLES']:.3f}")
+        lines.append("")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def lanczos_flops(N, J):
     """Algorithmic float64 work of J Lanczos steps: the matvec with the N x N Gram (2N^2)
     and two classical Gram-Schmidt passes against j vectors (8Nj)."""
@@ -308,7 +457,30 @@ def la_groups(N):
     return max(1, min(32, (N + 31) // 32))
 
 
+def summarize_main(argv):
+    ap = argparse.ArgumentParser(prog="bench.py --summarize")
+    ap.add_argument("--summarize", choices=["trace", "traffic", "counters"], required=True)
+    ap.add_argument("--dir", action="append", required=True, help="rocprofv3 output directories")
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--title", default="")
+    ap.add_argument("--cmd", action="append", default=[])
+    ap.add_argument("--last", type=int, default=4)
+    ap.add_argument("--bench-log")
+    ap.add_argument("--workload", default="")
+    ap.add_argument("--kernels", default="k_lift,k_recon<,k_sketch")
+    a = ap.parse_args(argv)
+    if a.summarize == "trace":
+        summarize_trace(a.dir[0], a.last, a.title, " ".join(a.cmd), a.out, a.bench_log)
+    elif a.summarize == "traffic":
+        summarize_traffic(a.dir[0], a.dir[1], a.workload, a.cmd, a.out)
+    else:
+        summarize_counters(a.dir[0], a.title, " ".join(a.cmd), a.out, a.kernels.split(","))
+
+
 def main():
+    if "--summarize" in sys.argv:
+        summarize_main(sys.argv[1:])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
@@ -318,6 +490,10 @@ def main():
                     help="lift/reconstruction form (cfg2); 'both' times FP32 (the reported value), "
                          "BF16 and FP32 with the amplitudes on the compressed modes side by side")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--gauss-prec", default="bf16", choices=["bf16", "fp8"],
+                    help="cfg3: the precision form of the dense Gaussian sketch")
+    ap.add_argument("--draw-c", action="store_true",
+                    help="cfg3: draw the Gaussian C on the fly instead of storing it in device memory")
     ap.add_argument("--no-autotune", action="store_true",
                     help="skip cdmd_autotune before the warm-up (default tile shapes)")
     ap.add_argument("--cpu-band-rows", type=int, default=68)
@@ -344,7 +520,7 @@ def main():
     if args.workload == "cfg4":
         print(json.dumps(run_batch(args, wl)), flush=True)
         return
-    copy_gbs = None
+    copy_gbs = read_gbs = None
     if args.copy_ref_mib > 0:
         # device-to-device copy of a known size: the measured HBM ceiling (read + write bytes
         # over the copy's event time), and the reference kernel for scaling HBM counters
@@ -361,7 +537,19 @@ def main():
         torch.cuda.synchronize()
         copy_gbs = 2.0 * a.numel() * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
         log(f"copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written, {copy_gbs:.0f} GB/s")
-        del a, b
+        # a read-only pass over the same bytes (a maximum reduction): the ceiling for
+        # read-dominated kernels such as the sketch
+        ai = a.view(torch.int32)
+        torch.amax(ai)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            torch.amax(ai)
+        e1.record()
+        torch.cuda.synchronize()
+        read_gbs = a.numel() * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+        log(f"read reference: {args.copy_ref_mib} MiB read by a reduction, {read_gbs:.0f} GB/s")
+        del a, b, ai
     spec = sv.PRESETS[wl["preset"]]
     k, p, nnz, K, tau = wl["k"], wl["p"], wl["nnz"], wl["K"], wl["tau"]
     gauss = wl["sketch"] == "gaussian"
@@ -383,9 +571,17 @@ def main():
         # compressed modes (Remark 3: no lift in the fit)
         lp = P.PREC_BF16 if prec == "bf16" else P.PREC_FP32
         if gauss:
-            sp = P.PREC_BF16 if args.workload == "cfg3" else P.PREC_FP32
+            sp = ({"bf16": P.PREC_BF16, "fp8": P.PREC_FP8}[args.gauss_prec] if args.workload == "cfg3"
+                  else P.PREC_FP32)
             mdl = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8 if u8 else P.F32,
                           seed=wl["seed"], sketch_prec=sp, lift_prec=lp)
+            if sp != P.PREC_FP32 and not args.draw_c:
+                try:
+                    mdl.store_measurement(True)
+                    stored_c[prec] = True
+                    log(f"[{prec}] C stored in device memory ({p} x {n})")
+                except P.CdmdError as e:
+                    log(f"[{prec}] C drawn on the fly ({e})")
         else:
             mdl = P.Model(n, m, k, p, sketch=P.SKETCH_SPARSE, dtype=P.U8, idx=idx, sign=sign,
                           lift_prec=lp)
@@ -471,6 +667,7 @@ def main():
         forms = ["fp32", "bf16", "fp32_compressed"] if args.prec == "both" else [args.prec]
     else:
         forms = ["bf16"] if args.workload == "cfg3" else ["fp32"]
+    stored_c = {}
     res = {f: run_form(f) for f in forms}
 
     from scipy.optimize import linear_sum_assignment
@@ -537,7 +734,9 @@ def main():
         "dtype": "f32" if forms[0] == "fp32" else "bf16",
         "data": "synthetic",
         "config": {"workload": wl["desc"], "n": n, "m": m, "k": k, "p": p, "nnz": nnz, "K": K,
-                   "tau": tau, "lift_prec": forms[0]},
+                   "tau": tau, "lift_prec": forms[0],
+                   **({"sketch_prec": args.gauss_prec, "c_stored": bool(stored_c.get(forms[0]))}
+                      if args.workload == "cfg3" else {})},
         "roofline": roof,
         "streaming_rooflines": streaming,
         "sketch_hbm_gbps": head["kernels"]["sketch"]["GB/s"],
@@ -555,6 +754,7 @@ def main():
     }
     if copy_gbs is not None:
         out["hbm_copy_gbps"] = round(copy_gbs, 1)
+        out["hbm_read_gbps"] = round(read_gbs, 1)
     if args.workload == "cfg2" and not args.no_quality:
         log("per-form quality against the full-frame FP64 oracle")
         qual, qinfo = oracle_quality(D, idx, sign, k, K, tau, res)

@@ -182,6 +182,17 @@ cdmd_status cdmd_fit(cdmd_model* mdl, const void* d_video, void* stream);
    also returns UNSUPPORTED), OUT_OF_MEMORY. */
 cdmd_status cdmd_set_amplitudes(cdmd_model* mdl, int32_t space);
 
+/* Dense Gaussian C (Section 3.3) kept in device memory.  on != 0: the library draws the
+   p x n entries of the configured BF16 or FP8 form once (the same values, bit for bit,
+   that the sketch otherwise draws on the fly; bfloat16 bits or e4m3 codes, rows padded to
+   a multiple of 64 pixels) into memory it allocates and owns, and every later cdmd_fit
+   streams them from HBM instead of drawing them: the sketch then costs 2pn (BF16) or pn
+   (FP8) bytes of reads per fit in place of the draws, and its results do not change.
+   Needs 2 p ceil(n/64) 64 bytes (BF16) or half that (FP8).  on = 0 frees the copy.  Work
+   goes on `stream`, which the call synchronises.  Errors: INVALID_ARG (NULL),
+   UNSUPPORTED (not a Gaussian sketch in the BF16 or FP8 form), OUT_OF_MEMORY, DEVICE. */
+cdmd_status cdmd_store_measurement(cdmd_model* mdl, int32_t on, void* stream);
+
 /* Automatic target rank (Section 3.2, Remark 2): the optimal hard threshold of Gavish and
    Donoho (2014) for an unknown noise level, applied to the singular values of Y, the sketch
    of the snapshots X (eq. (eq:YCX)), in place of a given k.  d_video is sketched with cfg's

@@ -36,7 +36,7 @@ EXPORTED = [
     "cdmd_dbg_force_gather_sketch", "cdmd_dbg_sparse_form",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_train_noalloc", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
-    "cdmd_batch_free", "cdmd_optimal_rank",
+    "cdmd_batch_free", "cdmd_optimal_rank", "cdmd_store_measurement",
 ]
 MLP_NPARAM = 4673
 
@@ -104,6 +104,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_info_get.argtypes = [P, ctypes.POINTER(Info)]
     lib.cdmd_set_timing.argtypes = [P, I32]
     lib.cdmd_set_amplitudes.argtypes = [P, I32]
+    lib.cdmd_store_measurement.argtypes = [P, ctypes.c_int32, ctypes.c_void_p]
     lib.cdmd_mask_median3.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, I32, P]
     lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
@@ -357,6 +358,12 @@ class Model:
 
     def set_timing(self, enable: bool = True):
         _check(load_library().cdmd_set_timing(self._h, int(enable)))
+
+    def store_measurement(self, on: bool = True, stream=None):
+        """Keep the dense Gaussian C (BF16 / FP8 form) in device memory so that fits stream it
+        instead of drawing it (cdmd_store_measurement)."""
+        _check(load_library().cdmd_store_measurement(self._h, int(on), _stream(stream)))
+        return self
 
     def set_amplitudes(self, space: int):
         """AMP_FULL (eq. (eq:b) on the full modes) or AMP_COMPRESSED (Remark 3: amplitudes and selection on the

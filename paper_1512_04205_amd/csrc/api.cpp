@@ -90,6 +90,8 @@ struct cdmd_model {
   bool gauss = false;               // dense Gaussian sketch
   cdmd::k::GaussPlan gplan{};
   float* d_gpart = nullptr;         // per-slice partial sketches
+  void* d_Cm = nullptr;             // the stored C (cdmd_store_measurement), or null: drawn
+  int64_t Cm_ldc = 0;
   // streaming sparse sketch (16-byte aligned frames)
   int32_t* d_chunk_off = nullptr;   // [row block][chunk + 1] first triple of each chunk
   int32_t* d_rblk = nullptr;        // [row block] (first row, rows)
@@ -191,7 +193,7 @@ struct cdmd_model {
       (void)hipEventDestroy(e_stage);
     }
     if (st2) (void)hipStreamDestroy(st2);
-    void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart, d_chunk_off, d_rblk,
+    void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart, d_Cm, d_chunk_off, d_rblk,
                    d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Rv, d_Gd, d_Vc, d_counts, d_modes,
                    d_feats, d_logits,
                    d_la_scratch, d_la_out, d_py, d_pyred};
@@ -454,7 +456,7 @@ cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool 
     if (c.sketch_prec != CDMD_PREC_FP32 && (reinterpret_cast<uintptr_t>(d_video) & 15) != 0)
       return fail(CDMD_E_UNSUPPORTED, "the BF16 / FP8 Gaussian sketch needs a 16-byte aligned video");
     HIPCHK(cdmd::k::sketch_gauss(d_video, c.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p, c.seed,
-                                 gauss_prec(c), M->gplan, M->d_gpart, M->d_Yd, st));
+                                 gauss_prec(c), M->gplan, M->d_Cm, M->Cm_ldc, M->d_gpart, M->d_Yd, st));
     M->mark(1, st);
     HIPCHK(cdmd::k::gram_f64(M->d_Yd, M->p, M->m, M->d_gram, st));
   } else if (c.dtype == CDMD_U8 && M->ld % 16 == 0 && (reinterpret_cast<uintptr_t>(d_video) & 15) == 0 &&
@@ -1275,7 +1277,8 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
         double ms = 0.0;
         TRY(time_ms(st, 1, [&] {
           HIPCHK(cdmd::k::sketch_gauss(d_video, M->cfg.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p,
-                                       M->cfg.seed, gauss_prec(M->cfg), M->gplan, M->d_gpart, M->d_Yd, st));
+                                       M->cfg.seed, gauss_prec(M->cfg), M->gplan, M->d_Cm, M->Cm_ldc,
+                                       M->d_gpart, M->d_Yd, st));
           return CDMD_OK;
         }, &ms));
         if (ms < best) best = ms, ch.gauss_target = target;
@@ -1956,6 +1959,41 @@ cdmd_status cdmd_mask_median3(const void* d_in, void* d_out, int64_t H, int64_t 
   if (a < b + bytes && b < a + bytes) return fail(CDMD_E_INVALID_ARG, "input and output masks overlap");
   HIPCHK(cdmd::k::mask_median3(d_in, d_out, H, W, m, bitpacked ? 1 : 0, as_stream(stream)));
   return CDMD_OK;
+}
+
+cdmd_status cdmd_store_measurement(cdmd_model* M, int32_t on, void* stream) {
+  g_err.clear();
+  if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
+  const int prec = gauss_prec(M->cfg);
+  if (!M->gauss || (prec != 1 && prec != 2))
+    return fail(CDMD_E_UNSUPPORTED, "C is stored for the BF16 and FP8 forms of the Gaussian sketch only");
+  hipStream_t st = as_stream(stream);
+  if (!on) {
+    if (M->d_Cm) {
+      HIPCHK(hipStreamSynchronize(st));
+      HIPCHK(hipFree(M->d_Cm));
+      M->d_Cm = nullptr;
+      ++M->stamp;
+    }
+    return CDMD_OK;
+  }
+  if (M->d_Cm) return CDMD_OK;
+  const int64_t ldc = cdmd::k::gauss_ldc(M->n);
+  const size_t bytes = (size_t)M->p * (size_t)ldc * (prec == 1 ? 2 : 1);
+  void* d = nullptr;
+  if (hipMalloc(&d, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(CDMD_E_OUT_OF_MEMORY, "no device memory for the stored C");
+  }
+  const hipError_t e = cdmd::k::gauss_fill(d, ldc, M->n, M->p, M->cfg.seed, prec, st);
+  if (e == hipSuccess && hipStreamSynchronize(st) == hipSuccess) {
+    M->d_Cm = d;
+    M->Cm_ldc = ldc;
+    ++M->stamp;
+    return CDMD_OK;
+  }
+  (void)hipFree(d);
+  return fail(CDMD_E_DEVICE, "filling the stored C failed");
 }
 
 cdmd_status cdmd_set_amplitudes(cdmd_model* M, int32_t space) {

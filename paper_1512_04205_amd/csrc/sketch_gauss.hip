@@ -1,6 +1,9 @@
 // Dense Gaussian sketch Y^ = C X (Section 3.2, eq. (eq:YCX), with a Gaussian measurement matrix,
-// Section "Measurement Matrices"), C never stored: every entry is a pure function of
-// (seed, row, pixel), drawn by the workgroup that needs it.
+// Section "Measurement Matrices").  Every entry of C is a pure function of (seed, row,
+// pixel), drawn by the workgroup that needs it, or, for the BF16 and FP8 forms, read from
+// a copy of C the library stored in device memory once (gauss_fill: the same entries,
+// bit for bit), which trades the per-entry draw for p n bytes (FP8) or 2 p n bytes (BF16)
+// of HBM reads per sketch.
 //
 // Entry definition: for row r and pixel j, Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
 // SC'11) with key (seed mod 2^32, seed >> 32) on the counter (j >> 2, r, 0, 0) gives four
@@ -21,13 +24,17 @@
 // Work split: a workgroup owns 64 sketch rows x a tile of frames (up to 1024) x a slice
 // of pixels.
 // It draws its 64-row C tile once per pixel step into LDS (each entry drawn once per
-// frame tile) and reads the video bytes straight into MFMA operands.  Block b serves
-// (slice, frame tile) combination b mod combos and row tile b / combos, so the row tiles
-// of one combination run on one XCD (blocks are dealt to the XCDs in turn) and share
-// its video tiles through that XCD's L2.
+// frame tile) and reads the video bytes straight into MFMA operands.  Blocks are dealt to
+// the eight XCDs in turn, so block b runs on XCD b mod 8; its index b / 8 there picks the
+// row tile (fastest) and the (slice, frame tile) combination 8 (index / row tiles) +
+// b mod 8.  The row tiles of one combination thus start together on one XCD, step
+// through the same pixels at about the same pace and share each video tile through that
+// XCD's L2, so the video is read from HBM about (row tiles / workgroups per XCD) times
+// instead of once per row tile.
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "kernels.hpp"
 
@@ -117,15 +124,19 @@ constexpr int GB_NW = 8;      // waves per workgroup
 // of a wave reads pixels [32h, 32h + 32) of its frame with two 16-byte loads; k-step ks
 // takes pixels 32h + 8ks + (0..7).  The C tile is stored in pixel order, so the A
 // fragment of (row, h, ks) is the 16 bytes at pixel 32h + 8ks.
-template <int NFB>
+// STORED: C is read from Cm (bfloat16 bits, row r at Cm + r ldc) instead of drawn.
+template <int NFB, bool STORED>
 __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t* __restrict__ D, int64_t ld,
                                                                  int64_t n, int64_t m, int p, uint64_t seed,
                                                                  int64_t pps, int nft, int nsplit,
+                                                                 const uint16_t* __restrict__ Cm, int64_t ldc,
                                                                  float* __restrict__ part) {
   constexpr int FRAMES = 32 * NFB * GB_NW;
   __shared__ __attribute__((aligned(16))) uint16_t sA[2][GB_ROWS * GB_AS];
-  const int combos = nft * nsplit;
-  const int cidx = blockIdx.x % combos, rt = blockIdx.x / combos;
+  const int combos = nft * nsplit, nrt = (p + GB_ROWS - 1) / GB_ROWS;
+  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
+  const int rt = loc % nrt, cidx = (loc / nrt) * 8 + xcd;
+  if (cidx >= combos) return;  // padding of the last group of eight combinations
   const int s = cidx / nft, ft = cidx % nft;
   const int r0 = rt * GB_ROWS;
   const int64_t t0 = (int64_t)ft * FRAMES;
@@ -158,6 +169,23 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
     }
     *reinterpret_cast<uint4*>(&sA[buf][gr * GB_AS + 8 * gg]) = make_uint4(q[0], q[1], q[2], q[3]);
   };
+  // the same eight entries from the stored C (pixels of the next slice read as 0)
+  auto fetch = [&](int64_t j0) -> uint4 {
+    const int64_t j = j0 + 8 * gg;
+    uint4 v = make_uint4(0u, 0u, 0u, 0u);
+    if (grow < p && j < je) {
+      v = *reinterpret_cast<const uint4*>(Cm + (int64_t)grow * ldc + j);
+      if (j + 8 > je) {
+        uint32_t q[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (j + e >= je) q[e >> 1] &= (e & 1) ? 0x0000ffffu : 0xffff0000u;
+        v = make_uint4(q[0], q[1], q[2], q[3]);
+      }
+    }
+    return v;
+  };
+  auto put = [&](int buf, uint4 v) { *reinterpret_cast<uint4*>(&sA[buf][gr * GB_AS + 8 * gg]) = v; };
 
   // this lane's frames: t0 + 32 NFB w + 32 fb + lc (wave w owns 32 NFB frames)
   uint4 bcur[NFB][2], bnext[NFB][2];
@@ -195,15 +223,20 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
 
   const int64_t nsteps = je > jb ? (je - jb + GB_KT - 1) / GB_KT : 0;
   if (nsteps > 0) {
-    draw(0, jb);
+    if constexpr (STORED) put(0, fetch(jb));
+    else draw(0, jb);
     load_b(bcur, jb);
   }
   __syncthreads();
+  uint4 cnext = make_uint4(0u, 0u, 0u, 0u);
   for (int64_t st = 0; st < nsteps; ++st) {
     const int buf = (int)(st & 1);
     const int64_t jn = jb + (st + 1) * GB_KT;
     const bool more = st + 1 < nsteps;
-    if (more) load_b(bnext, jn);
+    if (more) {
+      load_b(bnext, jn);
+      if constexpr (STORED) cnext = fetch(jn);  // in flight during this step's products
+    }
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       bf16x8_t a[2];
@@ -219,7 +252,10 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
           acc[rb][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b, acc[rb][fb], 0, 0, 0);
       }
     }
-    if (more) draw(buf ^ 1, jn);
+    if (more) {
+      if constexpr (STORED) put(buf ^ 1, cnext);
+      else draw(buf ^ 1, jn);
+    }
     __syncthreads();
 #pragma unroll
     for (int fb = 0; fb < NFB; ++fb) {
@@ -271,16 +307,20 @@ __device__ __forceinline__ uint32_t nibble_codes(uint32_t nib4, uint32_t t0l, ui
 // As the BF16 form with C rounded to e4m3 and each video byte u = 16 hi + lo split into
 // two exact e4m3 operands (16 hi and lo), multiplied by two FP8 MFMAs (32x32x16) into the
 // same float32 accumulator: only C is quantised.
-template <int NFB>
+// STORED: C is read from Cm (e4m3 codes, row r at Cm + r ldc) instead of drawn.
+template <int NFB, bool STORED>
 __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* __restrict__ D, int64_t ld,
                                                                 int64_t n, int64_t m, int p, uint64_t seed,
                                                                 int64_t pps, int nft, int nsplit,
+                                                                const uint8_t* __restrict__ Cm, int64_t ldc,
                                                                 float* __restrict__ part) {
   constexpr int FRAMES = 32 * NFB * GB_NW;
   constexpr int AS = 80;  // LDS row stride of the C tile (bytes)
   __shared__ __attribute__((aligned(16))) uint8_t sA[2][GB_ROWS * AS];
-  const int combos = nft * nsplit;
-  const int cidx = blockIdx.x % combos, rt = blockIdx.x / combos;
+  const int combos = nft * nsplit, nrt = (p + GB_ROWS - 1) / GB_ROWS;
+  const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
+  const int rt = loc % nrt, cidx = (loc / nrt) * 8 + xcd;
+  if (cidx >= combos) return;  // padding of the last group of eight combinations
   const int s = cidx / nft, ft = cidx % nft;
   const int r0 = rt * GB_ROWS;
   const int64_t t0 = (int64_t)ft * FRAMES;
@@ -317,6 +357,23 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* 
     }
     *reinterpret_cast<uint2*>(&sA[buf][gr * AS + 8 * gg]) = make_uint2(q[0], q[1]);
   };
+  // the same eight codes from the stored C (pixels of the next slice read as 0)
+  auto fetch = [&](int64_t j0) -> uint2 {
+    const int64_t j = j0 + 8 * gg;
+    uint2 v = make_uint2(0u, 0u);
+    if (grow < p && j < je) {
+      v = *reinterpret_cast<const uint2*>(Cm + (int64_t)grow * ldc + j);
+      if (j + 8 > je) {
+        uint32_t q[2] = {v.x, v.y};
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+          if (j + e >= je) q[e >> 2] &= ~(0xffu << (8 * (e & 3)));
+        v = make_uint2(q[0], q[1]);
+      }
+    }
+    return v;
+  };
+  auto put = [&](int buf, uint2 v) { *reinterpret_cast<uint2*>(&sA[buf][gr * AS + 8 * gg]) = v; };
 
   uint4 bcur[NFB][2], bnext[NFB][2];
   auto load_b = [&](uint4 (*dst)[2], int64_t j0) {
@@ -353,15 +410,20 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* 
 
   const int64_t nsteps = je > jb ? (je - jb + GB_KT - 1) / GB_KT : 0;
   if (nsteps > 0) {
-    draw(0, jb);
+    if constexpr (STORED) put(0, fetch(jb));
+    else draw(0, jb);
     load_b(bcur, jb);
   }
   __syncthreads();
+  uint2 cnext = make_uint2(0u, 0u);
   for (int64_t st = 0; st < nsteps; ++st) {
     const int buf = (int)(st & 1);
     const int64_t jn = jb + (st + 1) * GB_KT;
     const bool more = st + 1 < nsteps;
-    if (more) load_b(bnext, jn);
+    if (more) {
+      load_b(bnext, jn);
+      if constexpr (STORED) cnext = fetch(jn);  // in flight during this step's products
+    }
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       long a[2];
@@ -384,7 +446,10 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* 
         }
       }
     }
-    if (more) draw(buf ^ 1, jn);
+    if (more) {
+      if constexpr (STORED) put(buf ^ 1, cnext);
+      else draw(buf ^ 1, jn);
+    }
     __syncthreads();
 #pragma unroll
     for (int fb = 0; fb < NFB; ++fb) {
@@ -404,6 +469,66 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* 
         const int r = r0 + 32 * rb + 8 * (e >> 2) + 4 * h + (e & 3);
         if (r < p) out[t * p + r] = acc[rb][fb][e];
       }
+  }
+}
+
+// ------------------------------------------------------------------------ stored C
+// The entries the BF16 / FP8 sketches draw, written once: row r at Cm + r ldc (ldc a
+// multiple of 8), pixels j >= n zero.  Each thread item: eight pixels of one row, from
+// the same Philox words, Box-Muller and rounding as the draw in the sketch kernels.
+__global__ __launch_bounds__(256) void k_gauss_fill_bf16(uint16_t* __restrict__ Cm, int64_t ldc, int64_t n, int p,
+                                                         uint64_t seed) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const int64_t groups = ldc / 8, total = (int64_t)p * groups;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(it / groups);
+    const int64_t j = (it % groups) * 8;
+    uint32_t q[4] = {0u, 0u, 0u, 0u};
+    if (j < n) {
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const Words4 wd = philox4x32_10((uint32_t)((j >> 2) + half), (uint32_t)r, k0, k1);
+        float z[4];
+        box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
+        box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (j + 4 * half + e >= n) z[e] = 0.f;
+        q[2 * half] = bf16_bits_rne(z[0]) | (bf16_bits_rne(z[1]) << 16);
+        q[2 * half + 1] = bf16_bits_rne(z[2]) | (bf16_bits_rne(z[3]) << 16);
+      }
+    }
+    *reinterpret_cast<uint4*>(Cm + (int64_t)r * ldc + j) = make_uint4(q[0], q[1], q[2], q[3]);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gauss_fill_fp8(uint8_t* __restrict__ Cm, int64_t ldc, int64_t n, int p,
+                                                        uint64_t seed) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const int64_t groups = ldc / 8, total = (int64_t)p * groups;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(it / groups);
+    const int64_t j = (it % groups) * 8;
+    uint32_t q[2] = {0u, 0u};
+    if (j < n) {
+#pragma unroll
+      for (int half = 0; half < 2; ++half) {
+        const Words4 wd = philox4x32_10((uint32_t)((j >> 2) + half), (uint32_t)r, k0, k1);
+        float z[4];
+        box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
+        box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+        uint32_t word = 0u;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t c = j + 4 * half + e >= n ? 0u : e4m3_rne(z[e]);
+          word |= c << (8 * e);
+        }
+        q[half] = word;
+      }
+    }
+    *reinterpret_cast<uint2*>(Cm + (int64_t)r * ldc + j) = make_uint2(q[0], q[1]);
   }
 }
 
@@ -560,36 +685,70 @@ GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target) {
   const int64_t maxs = (n + 64 * kt - 1) / (64 * kt);
   if (ns > maxs) ns = maxs;
   if (ns < 1) ns = 1;
+  // BF16 / FP8: whole groups of eight combinations where the slices allow it
+  while (bf && (g.nft * ns) % 8 != 0 && ns < maxs) ++ns;
   const int64_t steps = (n + kt - 1) / kt;
   const int64_t sps = (steps + ns - 1) / ns;
   g.pps = sps * kt;
   g.nsplit = (int)((n + g.pps - 1) / g.pps);
-  g.blocks = (int64_t)g.nrt * g.nft * g.nsplit;
+  if (bf) g.blocks = (int64_t)g.nrt * ((g.nft * g.nsplit + 7) / 8) * 8;
+  else g.blocks = (int64_t)g.nrt * g.nft * g.nsplit;
   return g;
 }
 
+int64_t gauss_ldc(int64_t n) { return (n + 63) / 64 * 64; }
+
+hipError_t gauss_fill(void* Cm, int64_t ldc, int64_t n, int p, uint64_t seed, int prec, hipStream_t stream) {
+  if (prec != 1 && prec != 2) return hipErrorInvalidValue;
+  if (ldc % 8 != 0 || ldc < n) return hipErrorInvalidValue;
+  const int64_t total = (int64_t)p * (ldc / 8);
+  int64_t blocks = (total + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (prec == 1)
+    hipLaunchKernelGGL(k_gauss_fill_bf16, dim3((unsigned)blocks), dim3(256), 0, stream, static_cast<uint16_t*>(Cm),
+                       ldc, n, p, seed);
+  else
+    hipLaunchKernelGGL(k_gauss_fill_fp8, dim3((unsigned)blocks), dim3(256), 0, stream, static_cast<uint8_t*>(Cm),
+                       ldc, n, p, seed);
+  return hipGetLastError();
+}
+
 hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, int p,
-                        uint64_t seed, int prec, const GaussPlan& g, float* part, double* Y,
-                        hipStream_t stream) {
+                        uint64_t seed, int prec, const GaussPlan& g, const void* Cm, int64_t ldc, float* part,
+                        double* Y, hipStream_t stream) {
   const dim3 grid((unsigned)g.blocks), block(256);
   if (prec == 1) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
+    const uint16_t* c = static_cast<const uint16_t*>(Cm);
     const dim3 bb(64 * GB_NW);
-    if (g.frames == 256)
-      hipLaunchKernelGGL(k_sketch_gauss_bf16<1>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
-    else if (g.frames == 512)
-      hipLaunchKernelGGL(k_sketch_gauss_bf16<2>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
-    else
-      hipLaunchKernelGGL(k_sketch_gauss_bf16<4>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    auto go = [&](auto nfb) {
+      constexpr int NFB = decltype(nfb)::value;
+      if (c != nullptr)
+        hipLaunchKernelGGL((k_sketch_gauss_bf16<NFB, true>), grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft,
+                           g.nsplit, c, ldc, part);
+      else
+        hipLaunchKernelGGL((k_sketch_gauss_bf16<NFB, false>), grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft,
+                           g.nsplit, c, ldc, part);
+    };
+    if (g.frames == 256) go(std::integral_constant<int, 1>{});
+    else if (g.frames == 512) go(std::integral_constant<int, 2>{});
+    else go(std::integral_constant<int, 4>{});
   } else if (prec == 2) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
+    const uint8_t* c = static_cast<const uint8_t*>(Cm);
     const dim3 bb(64 * GB_NW);
-    if (g.frames == 256)
-      hipLaunchKernelGGL(k_sketch_gauss_fp8<1>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
-    else if (g.frames == 512)
-      hipLaunchKernelGGL(k_sketch_gauss_fp8<2>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
-    else
-      hipLaunchKernelGGL(k_sketch_gauss_fp8<4>, grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+    auto go = [&](auto nfb) {
+      constexpr int NFB = decltype(nfb)::value;
+      if (c != nullptr)
+        hipLaunchKernelGGL((k_sketch_gauss_fp8<NFB, true>), grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft,
+                           g.nsplit, c, ldc, part);
+      else
+        hipLaunchKernelGGL((k_sketch_gauss_fp8<NFB, false>), grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft,
+                           g.nsplit, c, ldc, part);
+    };
+    if (g.frames == 256) go(std::integral_constant<int, 1>{});
+    else if (g.frames == 512) go(std::integral_constant<int, 2>{});
+    else go(std::integral_constant<int, 4>{});
   } else if (dtype == 0) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
     const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 3) == 0;

@@ -109,6 +109,7 @@ def test_null_handles():
     assert lib.cdmd_fit(None, None, None) == P.E_INVALID_ARG
     assert lib.cdmd_select(None, 0, 1, 0.0, None, 0, None, None, None) == P.E_INVALID_ARG
     assert lib.cdmd_create(None, None) == P.E_INVALID_ARG
+    assert lib.cdmd_store_measurement(None, 1, None) == P.E_INVALID_ARG
     lib.cdmd_free(None)
 
 

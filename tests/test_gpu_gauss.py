@@ -116,6 +116,48 @@ def test_gaussian_sketch_fp8_form(case):
     assert rel <= 3e-3, rel
 
 
+@pytest.mark.parametrize("prec", ["bf16", "fp8"])
+@pytest.mark.parametrize("case", [(37, 61, 70, 130), (119, 101, 40, 200), (16, 80, 1000, 65)])
+def test_stored_c_sketch_equals_drawn(prec, case):
+    """cdmd_store_measurement: the sketch from the C kept in device memory equals, bit for
+    bit, the sketch that draws C on the fly (frame sizes that are not multiples of 8 or 64,
+    ragged row tiles, several pixel slices, up to 1000 frames); a fit gives the same
+    eigenvalues; switching the copy off again gives the drawn sketch."""
+    H, W, m, p = case
+    _say("stored C", prec, case)
+    sp = P.PREC_BF16 if prec == "bf16" else P.PREC_FP8
+    rng = np.random.default_rng(8)
+    n = H * W
+    ld = (n + 15) // 16 * 16  # the BF16 / FP8 forms read 16-byte aligned frames
+    Dh = np.zeros((m, ld), np.uint8)
+    Dh[:, :n] = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+    Dh[:, n:] = 255  # bytes past the frame must not enter the sketch
+    D = torch.from_numpy(Dh).cuda()
+    k = min(5, m - 1)
+    a = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=77, sketch_prec=sp, ld=ld)
+    b = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=77, sketch_prec=sp, ld=ld)
+    b.store_measurement(True)
+    a.fit(D)
+    b.fit(D)
+    Ya, Yb = a.sketch(), b.sketch()
+    assert np.array_equal(Ya, Yb), np.abs(Ya - Yb).max()
+    np.testing.assert_array_equal(a.modes()["lam"], b.modes()["lam"])
+    b.store_measurement(False)
+    b.fit(D)
+    assert np.array_equal(b.sketch(), Ya)
+
+
+def test_stored_c_refused_for_other_sketches():
+    n, m, p = 64 * 40, 30, 50
+    idx, sign = sv.sparse_table(n, p, 8, 1)
+    sp = P.Model(n, m, 5, p, idx=idx, sign=sign)
+    with pytest.raises(P.CdmdError, match="UNSUPPORTED"):
+        sp.store_measurement(True)
+    g32 = P.Model(n, m, 5, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=1, sketch_prec=P.PREC_FP32)
+    with pytest.raises(P.CdmdError, match="UNSUPPORTED"):
+        g32.store_measurement(True)
+
+
 def test_gaussian_fp8_fit():
     """Eigenvalues of the FP8 form against the oracle on the same e4m3-quantised C
     (arithmetic error only: <= 1e-3), and the error the quantisation itself causes against
