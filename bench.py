@@ -304,7 +304,7 @@ GROUPS = (("k_sketch", "sketch"), ("k_gram", "gram"), ("k_lift", "lift"), ("k_re
 
 
 def short_name(kn):
-    kn = kn.replace("void ", "").replace("cdmd::k::", "")
+    kn = kn.replace("void ", "").replace("cdmd::k::", "").replace("(anonymous namespace)::", "")
     depth, out = 0, []
     for ch in kn:  # drop the argument list, keep template arguments
         if ch == "(" and depth == 0:
@@ -337,28 +337,33 @@ def find_csv(d, suffix):
 
 
 def summarize_trace(d, last, title, cmd, out_path, bench_log=None):
-    """Per-kernel durations over the last `last` dispatches of each kernel."""
+    """Per-kernel durations inside the last `last` steps: from the sketch dispatch before the
+    first of the last `last` Lanczos dispatches to the end of the reconstruction after the
+    last one (earlier dispatches, such as the autotuner's trials of other tile shapes and
+    the video generator, are left out)."""
     rows = read_csv(find_csv(d, "kernel_trace.csv"))
+    ev = sorted(((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), short_name(r["Kernel_Name"]))
+                 for r in rows), key=lambda e: e[0])
+    la = [i for i, e in enumerate(ev) if e[2] == "k_la_a"][-last:]
+    i0 = max(i for i in range(la[0]) if group_of(ev[i][2]) == "sketch")
+    i1 = min(i for i in range(la[-1], len(ev)) if group_of(ev[i][2]) == "recon")
     per = {}
-    for r in sorted(rows, key=lambda r: int(r["Start_Timestamp"])):
-        per.setdefault(short_name(r["Kernel_Name"]), []).append(
-            (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3)
+    for st, en, name in ev[i0:i1 + 1]:
+        per.setdefault(name, []).append((en - st) / 1e3)
+    span = (ev[i1][1] - ev[i0][0]) / 1e3 / last
     lines = [title, "", "Command (from the repository root, TMPDIR=/tmp):", "  " + cmd, "",
-             f"Durations of each kernel's last {last} dispatches (warm-up and timed steps; the autotuner's",
-             "trial launches of other tile shapes come before them and are left out).", "",
-             f"{'kernel':58s} {'calls':>5s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s}"]
+             f"Kernels dispatched in the last {last} steps (warm-up and timed; the autotuner's trials of other",
+             "tile shapes and the video generator come before them and are left out): calls per step and",
+             "durations.", "",
+             f"{'kernel':44s} {'per step':>8s} {'avg_us':>9s} {'min_us':>9s} {'max_us':>9s} {'us/step':>9s}"]
     tot = 0.0
-    table = []
-    for name, v in per.items():
-        v = v[-last:]
-        if len(v) < last:
-            continue
+    for name, v in sorted(per.items(), key=lambda kv: -sum(kv[1])):
         avg = sum(v) / len(v)
-        table.append((avg, name, v))
-    for avg, name, v in sorted(table, reverse=True):
-        tot += avg
-        lines.append(f"{name[:58]:58s} {len(v):5d} {avg:9.1f} {min(v):9.1f} {max(v):9.1f}")
-    lines += ["", f"sum of the averages: {tot:.1f} us"]
+        tot += sum(v) / last
+        lines.append(f"{name[:44]:44s} {len(v) / last:8.1f} {avg:9.1f} {min(v):9.1f} {max(v):9.1f} "
+                     f"{sum(v) / last:9.1f}")
+    lines += ["", f"sum of the kernel times per step: {tot:.1f} us; step span (first sketch to last mask, "
+                  f"kernels of the second stream overlapping): {span:.1f} us"]
     if bench_log:
         with open(bench_log) as f:
             js = [l for l in f if l.startswith("{")]
@@ -392,11 +397,21 @@ def summarize_traffic(fetch_dir, write_dir, workload, cmds, out_path, ref_mib=10
         ref = [v[1][cname] for k, v in sorted(tab.items()) if "copyBuffer" in v[0] or "copy" in v[0].lower()]
         ref_kib = max(ref) if ref else None
         res[kind + "_ref_kib"] = ref_kib
-        for did, (kn, cv, _) in sorted(tab.items()):
-            g = group_of(short_name(kn))
+        # the last step: from the sketch before the last Lanczos dispatch to the first
+        # reconstruction after it (dispatch order)
+        ids = sorted(tab)
+        names = {i: short_name(tab[i][0]) for i in ids}
+        la = max(i for i in ids if names[i] == "k_la_a")
+        i0 = max(i for i in ids if i < la and group_of(names[i]) == "sketch")
+        i1 = min(i for i in ids if i > la and group_of(names[i]) == "recon")
+        for did in ids:
+            if did < i0 or did > i1:
+                continue
+            kn, cv, _ = tab[did]
+            g = group_of(names[did])
             if g is None or cname not in cv:
                 continue
-            res.setdefault(g, {})[kind] = (short_name(kn), cv[cname])
+            res.setdefault(g, {})[kind] = (names[did], cv[cname])
     expect = ref_mib * 1024.0
     fs = expect / res["fetch_ref_kib"] if res["fetch_ref_kib"] else 1.0
     ws = expect / res["write_ref_kib"] if res["write_ref_kib"] else 1.0
@@ -434,7 +449,11 @@ def summarize_counters(d, title, cmd, out_path, kernels):
             lines.append(f"  MFMA work {mops * 512 / 1e9:.2f} GFLOP -> {mops * 512 / dur / 1e3:.1f} TFLOP/s "
                          f"over the dispatch")
         if "SQ_VALU_MFMA_BUSY_CYCLES" in cv and "SQ_BUSY_CU_CYCLES" in cv and cv["SQ_BUSY_CU_CYCLES"]:
-            lines.append(f"  MFMA busy / CU busy cycles: {cv['SQ_VALU_MFMA_BUSY_CYCLES'] / cv['SQ_BUSY_CU_CYCLES']:.3f}")
+            # the busy cycles of the four SIMDs' matrix cores over the CUs' busy cycles
+            lines.append(f"  MFMA busy fraction SQ_VALU_MFMA_BUSY_CYCLES / (4 SQ_BUSY_CU_CYCLES): "
+                         f"{cv['SQ_VALU_MFMA_BUSY_CYCLES'] / (4 * cv['SQ_BUSY_CU_CYCLES']):.3f}")
+        if mops:
+            lines.append(f"  MFMA rate / dense BF16 peak (2500 TFLOP/s): {mops * 512 / dur / 1e3 / 2500:.3f}")
         lines.append("")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
@@ -520,7 +539,7 @@ def main():
     if args.workload == "cfg4":
         print(json.dumps(run_batch(args, wl)), flush=True)
         return
-    copy_gbs = read_gbs = None
+    copy_gbs = None
     if args.copy_ref_mib > 0:
         # device-to-device copy of a known size: the measured HBM ceiling (read + write bytes
         # over the copy's event time), and the reference kernel for scaling HBM counters
@@ -537,19 +556,7 @@ def main():
         torch.cuda.synchronize()
         copy_gbs = 2.0 * a.numel() * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
         log(f"copy reference: {args.copy_ref_mib} MiB read + {args.copy_ref_mib} MiB written, {copy_gbs:.0f} GB/s")
-        # a read-only pass over the same bytes (a maximum reduction): the ceiling for
-        # read-dominated kernels such as the sketch
-        ai = a.view(torch.int32)
-        torch.amax(ai)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
-            torch.amax(ai)
-        e1.record()
-        torch.cuda.synchronize()
-        read_gbs = a.numel() * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
-        log(f"read reference: {args.copy_ref_mib} MiB read by a reduction, {read_gbs:.0f} GB/s")
-        del a, b, ai
+        del a, b
     spec = sv.PRESETS[wl["preset"]]
     k, p, nnz, K, tau = wl["k"], wl["p"], wl["nnz"], wl["K"], wl["tau"]
     gauss = wl["sketch"] == "gaussian"
@@ -754,7 +761,6 @@ def main():
     }
     if copy_gbs is not None:
         out["hbm_copy_gbps"] = round(copy_gbs, 1)
-        out["hbm_read_gbps"] = round(read_gbs, 1)
     if args.workload == "cfg2" and not args.no_quality:
         log("per-form quality against the full-frame FP64 oracle")
         qual, qinfo = oracle_quality(D, idx, sign, k, K, tau, res)
