@@ -2001,9 +2001,30 @@ __global__ __launch_bounds__(SLA_ROWS_NT) void k_la_gp(SLADesc d1, const SLADesc
 
 // The small LA in three parts: the head (Lanczos, V, M12 V), then side by side the lift's
 // operands (followed by the lift) and the tail (the A~ eigen-solve and G).
+// Workgroups of k_la_a the current device holds at once (occupancy per CU times CUs).
+// The row groups of one solve wait for each other at every exchange, so they must all be
+// resident together: a launch whose solves need more groups than this is refused.  With
+// several solves, workgroups are dispatched in grid order (x fastest), so the groups of
+// one solve are consecutive; every resident group belongs to a solve whose groups have all
+// been dispatched or are next in line, so some solve always has all its groups resident,
+// finishes and frees its compute units (the waits are bounded in any case: past
+// kSpinLimit polls a solve reports a device error instead of hanging).
+static int la_a_capacity() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void*>(&k_la_a), SLA_A_NT, 0) !=
+      hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
 static hipError_t launch_la_head(const SLADesc& d1, const SLADesc* ds, int count, int nmax,
                                  hipStream_t stream, hipEvent_t after_lanczos, int ngroups) {
   const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
+  static int capacity = -1;  // one device model per process: the library targets MI355X
+  if (capacity < 0) capacity = la_a_capacity();
+  if (capacity > 0 && ngroups > capacity) return hipErrorInvalidConfiguration;  // 0: the query failed
   hipLaunchKernelGGL(k_la_prep, dim3(count), dim3(64), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_a, dim3(ngroups, count), dim3(SLA_A_NT), 0, stream, d1, ds);
   if (after_lanczos != nullptr) (void)hipEventRecord(after_lanczos, stream);
