@@ -822,11 +822,17 @@ __device__ __forceinline__ void pin(bf16x8_t& v) {
 // MODE 0: bit-packed mask, 1: byte mask, 2: L.  RAGGED: the workgroup's 128 pixels run
 // past n (only the last one), so its loads and stores check every pixel.
 template <int NSG, int NTV, int MODE, bool RAGGED>
-__global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0) {
+__global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0, int64_t ntiles) {
   extern __shared__ __align__(16) uint4 rc_lds[];
   uint8_t* sV = reinterpret_cast<uint8_t*>(rc_lds);
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, fl = l & 31;
-  const int64_t base = (tile0 + blockIdx.x) * RC_TP;
+  // Blocks are dealt to the eight XCDs in turn; XCD x takes the contiguous tiles
+  // [x per, (x + 1) per), so neighbouring tiles run together on one XCD and their 16-byte
+  // pieces of each frame's mask line meet in its L2 before they are written back.
+  const int64_t per = (ntiles + 7) / 8;
+  const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+  if (tile >= ntiles) return;  // uniform
+  const int64_t base = (tile0 + tile) * RC_TP;
   const int64_t n = a.n, ld = a.ld;
   const int m = (int)a.m;
   const int KS = a.KS;               // 16-frame k-steps of phase 1, a multiple of 4
@@ -1132,7 +1138,8 @@ static hipError_t launch_recon1(const ReconArgs& a, size_t lds, int64_t tile0, i
     if (e != hipSuccess) return e;
     attr = true;
   }
-  hipLaunchKernelGGL((k_recon<NSG, NTV, MODE, RAGGED>), dim3((unsigned)tiles), dim3(RC_NT), lds, s, a, tile0);
+  const int64_t blocks = 8 * ((tiles + 7) / 8);
+  hipLaunchKernelGGL((k_recon<NSG, NTV, MODE, RAGGED>), dim3((unsigned)blocks), dim3(RC_NT), lds, s, a, tile0, tiles);
   return hipGetLastError();
 }
 
