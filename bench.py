@@ -9,14 +9,16 @@ atoms, threshold tau = 0.1, bit-packed mask.  One step = one cdmd_fit + cdmd_sel
 
     python bench.py [--steps K] [--warmup W] [--prec both|fp32|bf16|fp32_compressed]
                     [--no-cpu-baseline]
-                    [--workload cfg2|cfg1|cfg3|cfg4] [--copy-ref-mib N]
+                    [--workload cfg2|cfg1|cfg3|cfg4|video] [--copy-ref-mib N]
                     [--gauss-prec bf16|fp8] [--draw-c]
     python bench.py --summarize trace|traffic|counters --dir D [--dir D2] --out FILE ...
 
 --workload cfg1 times the FP32 form of the dense Gaussian sketch on the 320x240x200
 float32 video (p = 500, k = 10); cfg3 the BF16 form on the 3840x2160x1000 uint8 video
 (p = 4000, k = 40; --gauss-prec fp8 the FP8 form; C is kept in device memory unless
---draw-c); cfg4 fits 64 streams of mixed shape and sketch with one graph launch per step.  The default line is the 1080p workload above.
+--draw-c); cfg4 fits 64 streams of mixed shape and sketch with one graph launch per step;
+video runs a 1000-frame 1080p video through cdmd_process_video in 200-frame batches with
+the paper's evaluation settings (a step is the whole video).  The default line is the 1080p workload above.
 """
 from __future__ import annotations
 
@@ -179,6 +181,13 @@ WORKLOADS = {
     "cfg3": dict(preset="cfg3", sketch="gaussian", k=40, p=4000, nnz=0, K=10, tau=0.1, seed=3,
                  desc="3840x2160 uint8 video, m=1000, dense Gaussian sketch p=4000 (BF16 form), k=40, "
                       "OMP K=10, tau=0.1, fp64 small LA"),
+    # the paper's evaluation settings on a long video: consecutive 200-frame batches, very
+    # sparse C (s = n / ln n) with p = 1000, automatic rank, OMP K = 10, median-filtered masks
+    "video": dict(preset="cfg2", sketch="iid", k=0, p=1000, nnz=32, K=10, tau=0.1, seed=21, frames=1000,
+                  batch=200,
+                  desc="1920x1080 uint8 video, 1000 frames in batches of 200, i.i.d. very sparse C "
+                       "(s = n/ln n) with p=1000, automatic rank per batch, OMP K=10, tau=0.1, "
+                       "3x3 median-filtered masks"),
     # many independent streams in one graph launch
     "cfg4": dict(preset=None, sketch="mixed", k=0, p=0, nnz=32, K=10, tau=0.1, seed=4,
                  desc="64 uint8 streams in one batch: resolutions 320x240 / 640x480 / 1280x720 / "
@@ -200,6 +209,52 @@ def batch_streams(seed, count=64):
                         p=int(rng.integers(20000, 100001)), gauss=bool(rng.integers(0, 2)),
                         seed=9000 + i))
     return out
+
+
+def run_video(args, wl):
+    """A long video in consecutive batches (cdmd_process_video): returns the JSON line.
+    A step is the whole video; value is its frames/s with two batches in flight, and the
+    same with one is reported beside it."""
+    import math
+    import numpy as np
+    import torch
+    import paper_1512_04205_amd as P
+    import synthvideo as sv
+    spec = sv.preset(wl["preset"], m=wl["frames"], seed=1002)
+    log(f"generating {spec.W}x{spec.H}x{spec.m} {spec.out} video on the GPU")
+    v = sv.make_video(spec, device="cuda")
+    n, frames = spec.n, spec.m
+    idx, sign = sv.iid_sparse_table(n, wl["p"], n / math.log(n), wl["seed"])
+    mask = torch.zeros((frames, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    res = {}
+    for workers in (1, 2):
+        def step():
+            return P.process_video(v.D, n, frames, wl["p"], mask, batch_frames=wl["batch"], k=wl["k"], K=wl["K"],
+                                   tau=wl["tau"], workers=workers, median_hw=(spec.H, spec.W), idx=idx, sign=sign)
+        for _ in range(args.warmup):
+            used = step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            used = step()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / args.steps * 1e3
+        res[workers] = dict(ms=ms, fps=frames / (ms / 1e3), ranks=[int(x) for x in used])
+        log(f"workers {workers}: {ms:.2f} ms per video, {frames / (ms / 1e3):.0f} frames/s, ranks {used}")
+    gt_frac = float(np.mean(v.gt_mask(0, 10)))
+    return {
+        "metric": "frames/sec cDMD fit+fg mask, long 1080p video in 200-frame batches",
+        "value": res[2]["fps"], "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": res[2]["ms"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": n, "frames": frames, "batch": wl["batch"], "p": wl["p"],
+                   "K": wl["K"], "tau": wl["tau"]},
+        "roofline": None,
+        "one_worker": {"ms_per_step": res[1]["ms"], "fps": res[1]["fps"]},
+        "ranks_per_batch": res[2]["ranks"],
+        "foreground_fraction_first_frames": gt_frac,
+        "note": "a step is the whole video: every batch sketched, fitted, selected, thresholded and median filtered",
+    }
 
 
 def run_batch(args, wl):
@@ -538,6 +593,9 @@ def main():
     wl = WORKLOADS[args.workload]
     if args.workload == "cfg4":
         print(json.dumps(run_batch(args, wl)), flush=True)
+        return
+    if args.workload == "video":
+        print(json.dumps(run_video(args, wl)), flush=True)
         return
     copy_gbs = None
     if args.copy_ref_mib > 0:

@@ -288,6 +288,36 @@ cdmd_status cdmd_batch_fit(cdmd_batch* batch, const void* const* d_videos, void*
                            cdmd_status* per_model);
 void cdmd_batch_free(cdmd_batch* batch);
 
+/* ---- long videos -------------------------------------------------------------------
+   Section 4 splits a long video into batches of consecutive frames and decomposes each on
+   its own (the paper uses 200 frames, a very sparse C with p = 1000, the automatic rank of
+   Remark 2 and OMP with K = 10).  cdmd_process_video does that for `frames` frames at
+   d_video (layout and dtype of `base`, frame stride base->ld; base->m and base->k are
+   ignored): every batch is fitted with the configuration `base` (the same C), its
+   background selected by OMP with K atoms, and its foreground mask (bit-packed, the
+   layout of cdmd_foreground) written to the rows of d_mask (frames x ceil(n/32) words)
+   of its frames; with H, W set, each mask is 3x3-median filtered (cdmd_mask_median3).
+   Batches hold batch_frames frames, the last the remainder (a single trailing frame
+   joins the batch before it).  `workers` host threads, each with its own stream and
+   models, take the batches in turn, so up to `workers` batches are in flight and the
+   small linear algebra of one overlaps the streaming kernels of another.  k = 0 chooses
+   the rank of every batch by Remark 2, clamped to [1, min(m_b - 1, p, 40)] (k_used[b], host,
+   receives it when not NULL).
+   The call waits for `stream` (the video's producer) and returns when every mask is
+   written.  Errors: INVALID_ARG, the errors of cdmd_create / cdmd_fit / cdmd_select /
+   cdmd_foreground for the first batch that failed (its message names it). */
+typedef struct {
+  int32_t batch_frames;  /* frames per batch, >= 2 */
+  int32_t k;             /* target rank of every batch, or 0: per batch by Remark 2 */
+  int32_t K;             /* OMP atoms of the background selection */
+  int32_t workers;       /* batches in flight, 1..4 */
+  double tau;            /* foreground threshold (eq. (eq:thres)) */
+  int64_t H, W;          /* frame shape for the median filter (H * W = n), or 0, 0 */
+} cdmd_video_plan;
+
+cdmd_status cdmd_process_video(const cdmd_config* base, const cdmd_video_plan* plan, const void* d_video,
+                               int64_t frames, void* d_mask, int32_t* k_used, void* stream);
+
 /* ---- learned background selector -------------------------------------------------
    A 6-64-64-1 network with GELU activations (exact erf) maps per-mode features to the
    logit of "sparse coding selects this mode"; the paper suggests learning the background

@@ -49,6 +49,13 @@ cdmd_status cdmd_dbg_sym_eigvals(const double* A, int32_t n, double* ev);
    optional).  Errors: INVALID_ARG. */
 cdmd_status cdmd_dbg_gd_threshold(double beta, double* lambda_star, double* mp_median, double* omega);
 
+/* Remark 2's rank from a Gram A (n x n, row-major) the way cdmd_process_video computes it
+   (the median singular value and one count, no full spectrum): the r largest singular
+   values sigma_q = scale sqrt(mu_q), tau = omega * median, k = #{sigma_q > tau}.
+   Errors: INVALID_ARG, NUMERIC (non-finite input). */
+cdmd_status cdmd_dbg_rank_threshold(const double* A, int32_t n, int32_t r, double scale, double omega, int32_t* k,
+                                    double* tau);
+
 /* The device small linear algebra (truncated SVD, A~, eig(A~) and G = V S^-1 W from the
    m x m Gram Gr of the unscaled sketch), run on the host with the same code the GPU runs:
    groups = 1 by one thread; groups = 2..32 with the Lanczos vectors split by rows over that

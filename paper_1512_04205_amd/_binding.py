@@ -33,10 +33,10 @@ EXPORTED = [
     "cdmd_info_get", "cdmd_set_timing", "cdmd_set_amplitudes", "cdmd_mask_median3", "cdmd_free",
     "cdmd_dbg_force_valu_lift",
     "cdmd_dbg_force_host_la", "cdmd_dbg_team_small_la", "cdmd_dbg_la_phases", "cdmd_dbg_la_groups",
-    "cdmd_dbg_force_gather_sketch", "cdmd_dbg_sparse_form",
+    "cdmd_dbg_force_gather_sketch", "cdmd_dbg_sparse_form", "cdmd_dbg_rank_threshold",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_train_noalloc", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
-    "cdmd_batch_free", "cdmd_optimal_rank", "cdmd_store_measurement",
+    "cdmd_batch_free", "cdmd_optimal_rank", "cdmd_store_measurement", "cdmd_process_video",
 ]
 MLP_NPARAM = 4673
 
@@ -57,6 +57,12 @@ class Config(ctypes.Structure):
         ("sparse_idx", ctypes.POINTER(ctypes.c_int32)),
         ("sparse_sign", ctypes.POINTER(ctypes.c_int8)),
     ]
+
+
+class VideoPlan(ctypes.Structure):
+    _fields_ = [("batch_frames", ctypes.c_int32), ("k", ctypes.c_int32), ("K", ctypes.c_int32),
+                ("workers", ctypes.c_int32), ("tau", ctypes.c_double), ("H", ctypes.c_int64),
+                ("W", ctypes.c_int64)]
 
 
 class Info(ctypes.Structure):
@@ -105,6 +111,9 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_set_timing.argtypes = [P, I32]
     lib.cdmd_set_amplitudes.argtypes = [P, I32]
     lib.cdmd_store_measurement.argtypes = [P, ctypes.c_int32, ctypes.c_void_p]
+    lib.cdmd_process_video.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(VideoPlan), ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.c_void_p]
     lib.cdmd_mask_median3.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, I32, P]
     lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
@@ -191,6 +200,42 @@ def optimal_rank(video, n: int, m: int, p: int, *, sketch: int = SKETCH_SPARSE, 
     _check(lib.cdmd_optimal_rank(ctypes.byref(cfg), _video_ptr(video, dtype, int(n), int(m), ld), _stream(stream),
                                  ctypes.byref(k), ctypes.byref(tau), _dptr(sig)))
     return int(k.value), float(tau.value), sig
+
+
+def process_video(video, n: int, frames: int, p: int, mask, *, batch_frames: int = 200, k: int = 0,
+                  K: int = 10, tau: float = 0.1, workers: int = 2, median_hw=None,
+                  sketch: int = SKETCH_SPARSE, dtype: int = U8, ld: Optional[int] = None,
+                  idx: Optional[np.ndarray] = None, sign: Optional[np.ndarray] = None, seed: int = 0,
+                  sketch_prec: int = PREC_FP32, lift_prec: int = PREC_FP32, stream=None) -> np.ndarray:
+    """A long video in batches of consecutive frames (cdmd_process_video): fills the device
+    mask (frames, mask_words(n)) int32 and returns the rank used for each batch."""
+    lib = load_library()
+    ld = int(ld if ld is not None else n)
+    cfg = Config()
+    cfg.n, cfg.m, cfg.ld, cfg.k, cfg.p = int(n), 2, ld, 1, int(p)
+    cfg.dtype, cfg.sketch, cfg.seed = dtype, sketch, seed
+    cfg.sketch_prec, cfg.lift_prec = sketch_prec, lift_prec
+    keep = []
+    if idx is not None:
+        idx = np.ascontiguousarray(idx, dtype=np.int32)
+        cfg.nnz = idx.shape[1] if idx.ndim == 2 else 1
+        cfg.sparse_idx = idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        keep.append(idx)
+    if sign is not None:
+        sign = np.ascontiguousarray(sign, dtype=np.int8)
+        cfg.sparse_sign = sign.ctypes.data_as(ctypes.POINTER(ctypes.c_int8))
+        keep.append(sign)
+    plan = VideoPlan()
+    plan.batch_frames, plan.k, plan.K, plan.workers, plan.tau = batch_frames, k, K, workers, tau
+    plan.H, plan.W = median_hw if median_hw is not None else (0, 0)
+    nb = max(1, (frames + batch_frames - 1) // batch_frames)
+    k_used = np.zeros(nb, dtype=np.int32)
+    words = mask_words(n)
+    _check(lib.cdmd_process_video(ctypes.byref(cfg), ctypes.byref(plan),
+                                  _video_ptr(video, dtype, n, frames, ld),
+                                  frames, _tensor_ptr(mask, frames * words),
+                                  k_used.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream(stream)))
+    return k_used
 
 
 class Model:

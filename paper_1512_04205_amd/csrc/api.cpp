@@ -15,6 +15,7 @@
 #include <mutex>
 #include <numeric>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <vector>
 
@@ -28,6 +29,7 @@ using cplx = std::complex<double>;
 namespace {
 
 thread_local std::string g_err;
+constexpr int kMaxRank = 40;  // the largest target rank the kernels are built for
 
 cdmd_status fail(cdmd_status s, const std::string& msg) {
   g_err = msg;
@@ -256,7 +258,7 @@ cdmd_status validate(const cdmd_config* c) {
       return fail(CDMD_E_INVALID_ARG, "single-pixel sketch needs p <= n");
     if ((int64_t)c->nnz > c->n) return fail(CDMD_E_INVALID_ARG, "nnz must not exceed n");
   }
-  if (c->k > 40) return fail(CDMD_E_UNSUPPORTED, "k > 40 is not built");
+  if (c->k > kMaxRank) return fail(CDMD_E_UNSUPPORTED, "k > 40 is not built");
   if (c->n >= (int64_t)1 << 31) return fail(CDMD_E_UNSUPPORTED, "n >= 2^31 pixels is not built");
   if (c->sketch == CDMD_SKETCH_GAUSSIAN) {
     if (c->sketch_prec != CDMD_PREC_FP32 && (c->dtype != CDMD_U8 || c->ld % 16 != 0))
@@ -1102,21 +1104,27 @@ cdmd_status post_fit(cdmd_model* M, double t0, double t1, double t2) {
   return CDMD_OK;
 }
 
-cdmd_status cdmd_optimal_rank(const cdmd_config* cfg, const void* d_video, void* stream, int32_t* k_out,
-                              double* tau_out, double* sigma_out) {
-  g_err.clear();
-  if (!cfg || !d_video || !k_out) return fail(CDMD_E_INVALID_ARG, "NULL argument");
-  cdmd_config c = *cfg;
-  c.k = 1;  // the sketch and its Gram do not depend on k
-  cdmd_model* M = nullptr;
-  TRY(cdmd_create(&c, &M));
-  std::unique_ptr<cdmd_model> own(M);
-  hipStream_t st = as_stream(stream);
+// Remark 2's rank for the video, with a model of rank 1 of its shape (only its sketch and
+// Gram are used).
+static cdmd_status rank_with_model(cdmd_model* M, const void* d_video, hipStream_t st, int32_t* k_out,
+                                   double* tau_out, double* sigma_out) {
   plan_fit(M, d_video);
   TRY(run_sketch(M, d_video, st, true));
   // the spectrum of Y = Y^[:, :m-1] from its Gram: sigma_i = scale sqrt(mu_i), the min(p, m-1)
   // largest eigenvalues
   const int N = M->N;
+  if (!sigma_out) {  // the median and one count are enough
+    const int r = std::min(N, M->p);
+    const double beta = (double)r / (double)std::max(N, M->p);
+    int k = 0;
+    double tau = 0.0;
+    if (!cdmd::la::sym_rank_threshold(M->h_gram, N, (int)M->m, r, M->sketch_scale, cdmd::la::gd_omega(beta), &k,
+                                      &tau))
+      return fail(CDMD_E_NUMERIC, "non-finite Gram");
+    *k_out = k;
+    if (tau_out) *tau_out = tau;
+    return CDMD_OK;
+  }
   std::vector<double> ev;
   if (!cdmd::la::sym_eigvals(M->h_gram, N, (int)M->m, ev)) return fail(CDMD_E_NUMERIC, "non-finite Gram");
   const int r = std::min(N, M->p);
@@ -1132,6 +1140,18 @@ cdmd_status cdmd_optimal_rank(const cdmd_config* cfg, const void* d_video, void*
   if (tau_out) *tau_out = tau;
   if (sigma_out) std::memcpy(sigma_out, sig.data(), sizeof(double) * r);
   return CDMD_OK;
+}
+
+cdmd_status cdmd_optimal_rank(const cdmd_config* cfg, const void* d_video, void* stream, int32_t* k_out,
+                              double* tau_out, double* sigma_out) {
+  g_err.clear();
+  if (!cfg || !d_video || !k_out) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  cdmd_config c = *cfg;
+  c.k = 1;  // the sketch and its Gram do not depend on k
+  cdmd_model* M = nullptr;
+  TRY(cdmd_create(&c, &M));
+  std::unique_ptr<cdmd_model> own(M);
+  return rank_with_model(M, d_video, as_stream(stream), k_out, tau_out, sigma_out);
 }
 
 cdmd_status cdmd_modes(const cdmd_model* Mc, double* lambda, double* b, double* sigma,
@@ -1946,6 +1966,157 @@ cdmd_status cdmd_info_get(const cdmd_model* Mc, cdmd_info* info) {
   return CDMD_OK;
 }
 
+// ------------------------------------------------------------------ long videos
+// Section 4 processes a long video as consecutive batches of frames, each decomposed on its
+// own.  Workers (host threads, each with its own stream and models) take the batches in
+// turn, so the latency-bound small linear algebra of one batch runs beside the streaming
+// kernels of another.
+namespace {
+struct VideoBatch {
+  int64_t t0, m;
+};
+
+std::vector<VideoBatch> video_batches(int64_t frames, int64_t F) {
+  std::vector<VideoBatch> b;
+  for (int64_t t = 0; t < frames; t += F) b.push_back({t, std::min(F, frames - t)});
+  if (b.size() > 1 && b.back().m < 2) {  // a single trailing frame joins the batch before it
+    b[b.size() - 2].m += b.back().m;
+    b.pop_back();
+  }
+  return b;
+}
+
+struct VideoWorker {
+  hipStream_t st = nullptr;
+  std::map<std::pair<int64_t, int>, std::unique_ptr<cdmd_model>> models;  // (frames, rank)
+  std::map<int64_t, std::unique_ptr<cdmd_model>> rank_models;             // frames -> rank-1 model
+  void* d_raw = nullptr;       // unfiltered mask of a batch (median filter only)
+  size_t raw_bytes = 0;
+  cdmd_status status = CDMD_OK;
+  std::string err;
+  ~VideoWorker() {
+    if (d_raw) (void)hipFree(d_raw);
+    if (st) (void)hipStreamDestroy(st);
+  }
+};
+}  // namespace
+
+cdmd_status cdmd_process_video(const cdmd_config* base, const cdmd_video_plan* plan, const void* d_video,
+                               int64_t frames, void* d_mask, int32_t* k_used, void* stream) {
+  g_err.clear();
+  if (!base || !plan || !d_video || !d_mask) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  const cdmd_video_plan vp = *plan;
+  if (frames < 2 || vp.batch_frames < 2) return fail(CDMD_E_INVALID_ARG, "need at least 2 frames per batch");
+  if (vp.workers < 1 || vp.workers > 4) return fail(CDMD_E_INVALID_ARG, "workers must be 1..4");
+  if (vp.K < 1 || vp.k < 0) return fail(CDMD_E_INVALID_ARG, "need K >= 1 and k >= 0");
+  if (!(vp.tau >= 0.0)) return fail(CDMD_E_INVALID_ARG, "tau must be >= 0");
+  const bool median = vp.H > 0 || vp.W > 0;
+  if (median && (vp.H < 1 || vp.W < 1 || vp.H * vp.W != base->n))
+    return fail(CDMD_E_INVALID_ARG, "the median filter needs H * W == n");
+  const std::vector<VideoBatch> batches = video_batches(frames, vp.batch_frames);
+  const int64_t words = (base->n + 31) / 32;
+  const size_t elem = base->dtype == CDMD_U8 ? 1 : 4;
+  const int nw = std::min<int>(vp.workers, (int)batches.size());
+  std::vector<VideoWorker> wk(nw);
+  hipEvent_t ready = nullptr;
+  HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
+  std::unique_ptr<void, void (*)(void*)> ready_own(ready, [](void* e) { (void)hipEventDestroy((hipEvent_t)e); });
+  HIPCHK(hipEventRecord(ready, as_stream(stream)));  // the video is ready on the caller's stream
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  for (auto& w : wk) {
+    HIPCHK(hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking));
+    HIPCHK(hipStreamWaitEvent(w.st, ready, 0));
+  }
+  auto run = [&](int wi) {
+    VideoWorker& w = wk[wi];
+    if (hipSetDevice(dev) != hipSuccess) {
+      w.status = CDMD_E_DEVICE;
+      w.err = "hipSetDevice failed in a worker";
+      return;
+    }
+    auto failw = [&](cdmd_status st) {
+      w.status = st;
+      w.err = g_err;
+    };
+    for (size_t bi = wi; bi < batches.size(); bi += nw) {
+      const VideoBatch& b = batches[bi];
+      const uint8_t* vid = static_cast<const uint8_t*>(d_video) + (size_t)b.t0 * base->ld * elem;
+      cdmd_config c = *base;
+      c.m = b.m;
+      int32_t k = vp.k;
+      if (k == 0) {
+        auto& rm = w.rank_models[b.m];
+        if (!rm) {
+          cdmd_config c1 = c;
+          c1.k = 1;
+          cdmd_model* M1 = nullptr;
+          const cdmd_status st = cdmd_create(&c1, &M1);
+          if (st != CDMD_OK) return failw(st);
+          rm.reset(M1);
+        }
+        const cdmd_status st = rank_with_model(rm.get(), vid, w.st, &k, nullptr, nullptr);
+        if (st != CDMD_OK) return failw(st);
+        // at least 1; at most what the fit accepts
+        k = std::max(1, std::min<int32_t>(k, (int32_t)std::min<int64_t>(std::min<int64_t>(b.m - 1, c.p), kMaxRank)));
+      }
+      if (k_used) k_used[bi] = k;
+      c.k = k;
+      auto& mp = w.models[{b.m, k}];
+      if (!mp) {
+        cdmd_model* M = nullptr;
+        const cdmd_status st = cdmd_create(&c, &M);
+        if (st != CDMD_OK) return failw(st);
+        mp.reset(M);
+      }
+      cdmd_model* M = mp.get();
+      cdmd_status st = cdmd_fit(M, vid, w.st);
+      if (st != CDMD_OK) return failw(st);
+      int32_t ns = 0;
+      st = cdmd_select(M, CDMD_SEL_OMP, vp.K, 0.0, nullptr, 0, nullptr, &ns, nullptr);
+      if (st != CDMD_OK) return failw(st);
+      void* out = static_cast<uint8_t*>(d_mask) + (size_t)b.t0 * words * 4;
+      void* raw = out;
+      if (median) {
+        const size_t need = (size_t)b.m * words * 4;
+        if (w.raw_bytes < need) {
+          if (w.d_raw) (void)hipFree(w.d_raw);
+          w.d_raw = nullptr;
+          w.raw_bytes = 0;
+          if (hipMalloc(&w.d_raw, need) != hipSuccess) {
+            (void)hipGetLastError();
+            w.status = CDMD_E_OUT_OF_MEMORY;
+            w.err = "no device memory for a batch's unfiltered mask";
+            return;
+          }
+          w.raw_bytes = need;
+        }
+        raw = w.d_raw;
+      }
+      st = cdmd_foreground(M, vid, (float)vp.tau, 0, 1, raw, nullptr, w.st);
+      if (st != CDMD_OK) return failw(st);
+      if (median) {
+        st = cdmd_mask_median3(raw, out, vp.H, vp.W, b.m, 1, w.st);
+        if (st != CDMD_OK) return failw(st);
+      }
+    }
+    if (hipStreamSynchronize(w.st) != hipSuccess) {
+      w.status = CDMD_E_DEVICE;
+      w.err = "a worker stream failed";
+    }
+  };
+  if (nw == 1) {
+    run(0);
+  } else {
+    std::vector<std::thread> th;
+    for (int i = 0; i < nw; ++i) th.emplace_back(run, i);
+    for (auto& t : th) t.join();
+  }
+  for (auto& w : wk)
+    if (w.status != CDMD_OK) return fail(w.status, ("a batch failed: " + w.err).c_str());
+  return CDMD_OK;
+}
+
 cdmd_status cdmd_mask_median3(const void* d_in, void* d_out, int64_t H, int64_t W, int64_t m, int32_t bitpacked,
                               void* stream) {
   g_err.clear();
@@ -2130,6 +2301,16 @@ cdmd_status cdmd_dbg_sym_eigvals(const double* A, int32_t n, double* ev) {
   std::vector<double> v;
   if (!cdmd::la::sym_eigvals(A, n, n, v)) return fail(CDMD_E_NUMERIC, "non-finite input");
   std::memcpy(ev, v.data(), sizeof(double) * n);
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_rank_threshold(const double* A, int32_t n, int32_t r, double scale, double omega, int32_t* k,
+                                    double* tau) {
+  g_err.clear();
+  if (!A || !k || !tau || n < 1 || r < 1 || r > n || !(scale > 0.0)) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  int kk = 0;
+  if (!cdmd::la::sym_rank_threshold(A, n, n, r, scale, omega, &kk, tau)) return fail(CDMD_E_NUMERIC, "non-finite input");
+  *k = kk;
   return CDMD_OK;
 }
 

@@ -12,6 +12,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <atomic>
+
 #include "team_la.hpp"
 
 namespace cdmd {
@@ -1131,12 +1133,12 @@ int recon_column(int s, int part) { return rc_col(s, part); }
 
 template <int NSG, int NTV, int MODE, bool RAGGED>
 static hipError_t launch_recon1(const ReconArgs& a, size_t lds, int64_t tile0, int64_t tiles, hipStream_t s) {
-  static bool attr = false;  // the larger dynamic LDS limit, set once per instantiation
-  if (!attr) {
+  static std::atomic<bool> attr{false};  // the larger dynamic LDS limit, set once per instantiation
+  if (!attr.load(std::memory_order_acquire)) {
     const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon<NSG, NTV, MODE, RAGGED>),
                                              hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     if (e != hipSuccess) return e;
-    attr = true;
+    attr.store(true, std::memory_order_release);
   }
   const int64_t blocks = 8 * ((tiles + 7) / 8);
   hipLaunchKernelGGL((k_recon<NSG, NTV, MODE, RAGGED>), dim3((unsigned)blocks), dim3(RC_NT), lds, s, a, tile0, tiles);
@@ -2029,8 +2031,9 @@ static int la_a_capacity() {
 static hipError_t launch_la_head(const SLADesc& d1, const SLADesc* ds, int count, int nmax,
                                  hipStream_t stream, hipEvent_t after_lanczos, int ngroups) {
   const int rb = (nmax + tla::kLaRows - 1) / tla::kLaRows;
-  static int capacity = -1;  // one device model per process: the library targets MI355X
-  if (capacity < 0) capacity = la_a_capacity();
+  static std::atomic<int> cap{-1};  // one device model per process: the library targets MI355X
+  int capacity = cap.load(std::memory_order_relaxed);
+  if (capacity < 0) cap.store(capacity = la_a_capacity(), std::memory_order_relaxed);
   if (capacity > 0 && ngroups > capacity) return hipErrorInvalidConfiguration;  // 0: the query failed
   hipLaunchKernelGGL(k_la_prep, dim3(count), dim3(64), 0, stream, d1, ds);
   hipLaunchKernelGGL(k_la_a, dim3(ngroups, count), dim3(SLA_A_NT), 0, stream, d1, ds);

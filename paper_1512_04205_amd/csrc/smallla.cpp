@@ -523,9 +523,27 @@ int tri_count_below(const std::vector<double>& d, const std::vector<double>& e2,
 }
 }  // namespace
 
-bool sym_eigvals(const double* Ain, int n, int lda, std::vector<double>& ev) {
-  ev.assign(n, 0.0);
-  if (n < 1) return true;
+// The symmetric tridiagonal form of A (Householder), with what bisection on it needs.
+struct SymTri {
+  int n = 0;
+  std::vector<double> d, e2;
+  double lo = 0.0, hi = 0.0, pivmin = 0.0;
+  int count_below(double x) const { return tri_count_below(d, e2, x, pivmin); }
+  // the r-th smallest eigenvalue: count(a) <= r < count(b)
+  double kth(int r) const {
+    double a = lo, b = hi;
+    for (int it = 0; it < 200 && b - a > 2.0 * DBL_EPSILON * std::max(std::fabs(a), std::fabs(b)) + pivmin; ++it) {
+      const double mid = 0.5 * (a + b);
+      if (mid <= a || mid >= b) break;
+      if (count_below(mid) > r) b = mid;
+      else a = mid;
+    }
+    return 0.5 * (a + b);
+  }
+};
+
+static bool sym_tridiagonal(const double* Ain, int n, int lda, SymTri& t) {
+  t.n = n;
   std::vector<double> A((size_t)n * n);
   for (int i = 0; i < n; ++i)
     for (int j = 0; j < n; ++j) {
@@ -570,35 +588,49 @@ bool sym_eigvals(const double* Ain, int n, int lda, std::vector<double>& ev) {
     A[(size_t)k * n + k + 1] = alpha;
     for (int i = 1; i < m; ++i) A[(size_t)(k + 1 + i) * n + k] = A[(size_t)k * n + (k + 1 + i)] = 0.0;
   }
-  std::vector<double> d(n), e2(n > 1 ? n - 1 : 1, 0.0);
-  double lo = 0.0, hi = 0.0, e2max = 0.0;
-  for (int i = 0; i < n; ++i) d[i] = A[(size_t)i * n + i];
+  t.d.assign(n, 0.0);
+  t.e2.assign(n > 1 ? n - 1 : 1, 0.0);
+  double e2max = 0.0;
+  for (int i = 0; i < n; ++i) t.d[i] = A[(size_t)i * n + i];
   for (int i = 0; i + 1 < n; ++i) {
     const double e = A[(size_t)(i + 1) * n + i];
-    e2[i] = e * e;
-    e2max = std::max(e2max, e2[i]);
+    t.e2[i] = e * e;
+    e2max = std::max(e2max, t.e2[i]);
   }
   // Gershgorin interval
-  lo = d[0], hi = d[0];
+  t.lo = t.d[0], t.hi = t.d[0];
   for (int i = 0; i < n; ++i) {
-    const double r = (i > 0 ? std::sqrt(e2[i - 1]) : 0.0) + (i + 1 < n ? std::sqrt(e2[i]) : 0.0);
-    lo = std::min(lo, d[i] - r);
-    hi = std::max(hi, d[i] + r);
+    const double r = (i > 0 ? std::sqrt(t.e2[i - 1]) : 0.0) + (i + 1 < n ? std::sqrt(t.e2[i]) : 0.0);
+    t.lo = std::min(t.lo, t.d[i] - r);
+    t.hi = std::max(t.hi, t.d[i] + r);
   }
-  const double tnorm = std::max(std::fabs(lo), std::fabs(hi));
-  const double pivmin = DBL_MIN * std::max(1.0, e2max);
-  lo -= 4.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin;
-  hi += 4.0 * DBL_EPSILON * tnorm * n + 2.0 * pivmin;
-  for (int r = 0; r < n; ++r) {  // the r-th smallest: count(a) <= r < count(b)
-    double a = lo, b = hi;
-    for (int it = 0; it < 200 && b - a > 2.0 * DBL_EPSILON * std::max(std::fabs(a), std::fabs(b)) + pivmin; ++it) {
-      const double mid = 0.5 * (a + b);
-      if (mid <= a || mid >= b) break;
-      if (tri_count_below(d, e2, mid, pivmin) > r) b = mid;
-      else a = mid;
-    }
-    ev[r] = 0.5 * (a + b);
-  }
+  const double tnorm = std::max(std::fabs(t.lo), std::fabs(t.hi));
+  t.pivmin = DBL_MIN * std::max(1.0, e2max);
+  t.lo -= 4.0 * DBL_EPSILON * tnorm * n + 2.0 * t.pivmin;
+  t.hi += 4.0 * DBL_EPSILON * tnorm * n + 2.0 * t.pivmin;
+  return true;
+}
+
+bool sym_eigvals(const double* Ain, int n, int lda, std::vector<double>& ev) {
+  ev.assign(n, 0.0);
+  if (n < 1) return true;
+  SymTri t;
+  if (!sym_tridiagonal(Ain, n, lda, t)) return false;
+  for (int r = 0; r < n; ++r) ev[r] = t.kth(r);
+  return true;
+}
+
+bool sym_rank_threshold(const double* A, int n, int lda, int r, double scale, double omega, int* k, double* tau) {
+  SymTri t;
+  if (n < 1 || r < 1 || r > n || !sym_tridiagonal(A, n, lda, t)) return false;
+  // singular value q (descending, 0-based) = scale sqrt(eigenvalue of ascending rank n-1-q)
+  auto sigma = [&](int q) { return scale * std::sqrt(std::max(t.kth(n - 1 - q), 0.0)); };
+  const double med = (r & 1) ? sigma(r / 2) : 0.5 * (sigma(r / 2 - 1) + sigma(r / 2));
+  const double th = omega * med;
+  const double x = (th / scale) * (th / scale);
+  const int above = n - t.count_below(x);
+  *k = std::max(0, std::min(r, above));
+  *tau = th;
   return true;
 }
 

@@ -68,6 +68,11 @@ bool omp_gram(const cplx* H, int k, const cplx* c, double x1n2, int K, const cpl
 // dimension lda): Householder reduction to tridiagonal form, then bisection with Sturm
 // counts.  Returns false on non-finite input.
 bool sym_eigvals(const double* A, int n, int lda, std::vector<double>& ev);
+// Remark 2's rank from the Gram A (n x n): with sigma_q = scale sqrt(mu_q) the r largest
+// singular values, tau = omega * median(sigma_0..sigma_{r-1}) and k = #{sigma_q > tau}; only
+// the median and one count are computed (bisection on the tridiagonal form).  False for a
+// non-finite A.
+bool sym_rank_threshold(const double* A, int n, int lda, int r, double scale, double omega, int* k, double* tau);
 
 // The optimal hard threshold of Gavish and Donoho for an aspect ratio beta = (smaller
 // dimension) / (larger dimension) in (0, 1]: lambda*(beta) for a known noise level, the

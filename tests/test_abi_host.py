@@ -110,6 +110,7 @@ def test_null_handles():
     assert lib.cdmd_select(None, 0, 1, 0.0, None, 0, None, None, None) == P.E_INVALID_ARG
     assert lib.cdmd_create(None, None) == P.E_INVALID_ARG
     assert lib.cdmd_store_measurement(None, 1, None) == P.E_INVALID_ARG
+    assert lib.cdmd_process_video(None, None, None, 0, None, None, None) == P.E_INVALID_ARG
     lib.cdmd_free(None)
 
 
@@ -374,3 +375,25 @@ def test_host_threshold_coefficients_match_oracle():
         assert abs(ls.value - R.gd_lambda_star(beta)) <= 1e-14
         assert abs(mu.value - R.mp_median(beta)) <= 1e-10 * R.mp_median(beta), (beta, mu.value, R.mp_median(beta))
         assert abs(om.value - R.gd_omega(beta)) <= 1e-10 * R.gd_omega(beta)
+
+
+def test_host_rank_threshold_matches_full_spectrum():
+    """The rank of the long-video path (the median singular value and one count) equals the
+    count over the full LAPACK spectrum, and its tau the threshold from that spectrum."""
+    lib = _lib()
+    lib.cdmd_dbg_rank_threshold.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                                            ctypes.POINTER(ctypes.c_int32), DP]
+    rng = np.random.default_rng(12)
+    for (p, N, rank) in ((300, 199, 12), (150, 199, 30), (1000, 499, 25), (40, 41, 3)):
+        U = rng.normal(size=(p, rank)) @ np.diag(np.linspace(30, 10, rank)) @ rng.normal(size=(rank, N))
+        Y = U + rng.normal(size=(p, N))
+        G = np.ascontiguousarray(Y.T @ Y)
+        r = min(N, p)
+        beta = r / max(N, p)
+        om = R.gd_omega(beta)
+        k, tau = ctypes.c_int32(), ctypes.c_double()
+        assert lib.cdmd_dbg_rank_threshold(_p(G), N, r, 0.5, om, ctypes.byref(k), ctypes.byref(tau)) == 0
+        s = 0.5 * np.sqrt(np.maximum(np.linalg.eigvalsh(G)[::-1][:r], 0.0))
+        t_ref = om * np.median(s)
+        assert abs(tau.value - t_ref) <= 1e-10 * t_ref
+        assert k.value == int(np.count_nonzero(s > t_ref)), (k.value, np.count_nonzero(s > t_ref))

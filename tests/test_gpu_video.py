@@ -1,0 +1,98 @@
+"""Long videos in batches of consecutive frames (Section 4's evaluation settings) through
+cdmd_process_video: the masks equal, bit for bit, those of one model per batch fitted,
+selected (OMP) and thresholded on its own (and median filtered when asked), with one and
+with two workers, so the single-model parity with the FP64 oracle carries over; the
+automatic rank of every batch equals cdmd_optimal_rank's."""
+import numpy as np
+import pytest
+import torch
+
+import synthvideo as sv
+
+pytestmark = pytest.mark.gpu
+P = pytest.importorskip("paper_1512_04205_amd")
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _video(frames, H=48, W=64, seed=3):
+    spec = sv.preset("cfg2", H=H, W=W, m=frames, n_pairs=3, bump_sigma=6.0, blur_sigma=3.0, n_rects=3,
+                     rect_side=(6, 12), speed=(0.5, 2.0), seed=seed)
+    return sv.make_video(spec, device="cuda")
+
+
+def _batches(frames, F):
+    b = [(t, min(F, frames - t)) for t in range(0, frames, F)]
+    if len(b) > 1 and b[-1][1] < 2:
+        t, m = b[-2]
+        b[-2] = (t, m + b[-1][1])
+        b.pop()
+    return b
+
+
+def _per_batch(D, n, frames, F, p, idx, sign, k, K, tau, hw=None):
+    words = P.mask_words(n)
+    out = torch.zeros((frames, words), dtype=torch.int32, device="cuda")
+    ks = []
+    for t0, m in _batches(frames, F):
+        Db = D[t0:t0 + m]
+        kb = k if k > 0 else max(1, min(P.optimal_rank(Db, n, m, p, idx=idx, sign=sign)[0], m - 1, p, 40))
+        ks.append(kb)
+        mdl = P.Model(n, m, kb, p, idx=idx, sign=sign)
+        mdl.fit(Db)
+        mdl.select(P.SEL_OMP, K=K)
+        if hw is None:
+            mdl.foreground(Db, out[t0:t0 + m], tau)
+        else:
+            raw = torch.zeros((m, words), dtype=torch.int32, device="cuda")
+            mdl.foreground(Db, raw, tau)
+            P.mask_median3(raw, out[t0:t0 + m], hw[0], hw[1])
+    torch.cuda.synchronize()
+    return out, ks
+
+
+@pytest.mark.parametrize("workers", [1, 2])
+@pytest.mark.parametrize("median", [False, True])
+def test_batches_equal_single_model_fits(workers, median):
+    frames, F, p, k, K, tau = 530, 200, 300, 8, 6, 0.1
+    _say("video batches", workers, median)
+    v = _video(frames)
+    n = v.spec.n
+    idx, sign = sv.sparse_table(n, p, 16, 7)
+    hw = (v.spec.H, v.spec.W) if median else None
+    ref, _ = _per_batch(v.D, n, frames, F, p, idx, sign, k, K, tau, hw)
+    mk = torch.zeros_like(ref)
+    used = P.process_video(v.D, n, frames, p, mk, batch_frames=F, k=k, K=K, tau=tau, workers=workers,
+                           median_hw=hw, idx=idx, sign=sign)
+    assert list(used) == [k] * 3
+    assert torch.equal(mk, ref)
+
+
+def test_automatic_rank_per_batch_and_trailing_frame():
+    """k = 0: every batch takes cdmd_optimal_rank's rank (clamped to the largest rank the
+    library builds, 40); 401 frames in batches of 200 give 200 + 201 (the single trailing
+    frame joins the batch before it)."""
+    frames, F, p, K, tau = 401, 200, 300, 6, 0.1
+    _say("video auto rank")
+    v = _video(frames, seed=5)
+    n = v.spec.n
+    idx, sign = sv.sparse_table(n, p, 16, 9)
+    ref, ks = _per_batch(v.D, n, frames, F, p, idx, sign, 0, K, tau)
+    mk = torch.zeros_like(ref)
+    used = P.process_video(v.D, n, frames, p, mk, batch_frames=F, k=0, K=K, tau=tau, workers=2,
+                           idx=idx, sign=sign)
+    assert len(ks) == 2
+    assert list(used[:2]) == ks
+    assert torch.equal(mk, ref)
+
+
+def test_refusals():
+    v = _video(10)
+    n = v.spec.n
+    idx, sign = sv.sparse_table(n, 50, 8, 1)
+    mk = torch.zeros((10, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    for kw in (dict(batch_frames=1), dict(workers=0), dict(workers=5), dict(K=0), dict(median_hw=(7, 7))):
+        with pytest.raises(P.CdmdError, match="INVALID_ARG"):
+            P.process_video(v.D, n, 10, 50, mk, idx=idx, sign=sign, **{**dict(batch_frames=5, k=3), **kw})
