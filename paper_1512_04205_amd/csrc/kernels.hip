@@ -1385,6 +1385,45 @@ __global__ __launch_bounds__(256) void k_mask_median3_bits(const uint32_t* __res
   out[t * words + w] = o;
 }
 
+// bit-packed with W a multiple of 32 (every row starts a word): a thread per output word,
+// the nine neighbours as nine shifted words (left and right neighbours by shifting across
+// the adjacent words, the edge pixel replicated at the row ends), their majority by a
+// bit-sliced adder: the count is s + 2T with s the parity of the nine and T the sum of the
+// four carries; count >= 5 iff T >= 3, or T == 2 and s == 1.
+__device__ __forceinline__ void csa(uint32_t a, uint32_t b, uint32_t c, uint32_t& s, uint32_t& cy) {
+  const uint32_t ab = a ^ b;
+  s = ab ^ c;
+  cy = (a & b) | (c & ab);
+}
+
+__global__ __launch_bounds__(256) void k_mask_median3_rows(const uint32_t* __restrict__ in, uint32_t* __restrict__ out,
+                                                           int H, int wpr) {
+  const int w = blockIdx.x * blockDim.x + threadIdx.x;  // word of the frame
+  if (w >= H * wpr) return;
+  const int y = w / wpr, c = w - y * wpr;
+  const int64_t words = (int64_t)H * wpr;
+  const uint32_t* f = in + (int64_t)blockIdx.y * words;
+  uint32_t rs[3], rc[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    int yy = y + d - 1;
+    yy = yy < 0 ? 0 : (yy >= H ? H - 1 : yy);
+    const uint32_t* row = f + (int64_t)yy * wpr;
+    const uint32_t C = row[c];
+    const uint32_t L = c > 0 ? row[c - 1] : 0u, R = c + 1 < wpr ? row[c + 1] : 0u;
+    const uint32_t left = (C << 1) | (c > 0 ? L >> 31 : (C & 1u));                    // pixel x - 1
+    const uint32_t right = (C >> 1) | (c + 1 < wpr ? R << 31 : (C & 0x80000000u));     // pixel x + 1
+    csa(left, C, right, rs[d], rc[d]);
+  }
+  uint32_t s, cc;
+  csa(rs[0], rs[1], rs[2], s, cc);           // weight 1: s; weight 2: cc
+  uint32_t u, v;
+  csa(rc[0], rc[1], rc[2], u, v);            // T = u + cc + 2 v (in units of 2)
+  const uint32_t w1 = u ^ cc, ca = u & cc;   // T = w1 + 2 (v + ca)
+  const uint32_t one = v ^ ca, two = v & ca; // v + ca == 1, == 2
+  out[(int64_t)blockIdx.y * words + w] = two | (one & w1) | (one & ~w1 & s);
+}
+
 // uint8 (0/1): a thread per pixel of frame blockIdx.y
 __global__ __launch_bounds__(256) void k_mask_median3_u8(const uint8_t* __restrict__ in, uint8_t* __restrict__ out,
                                                          int64_t H, int64_t W) {
@@ -1397,7 +1436,12 @@ __global__ __launch_bounds__(256) void k_mask_median3_u8(const uint8_t* __restri
 hipError_t mask_median3(const void* in, void* out, int64_t H, int64_t W, int64_t m, int bitpacked,
                         hipStream_t stream) {
   const int64_t n = H * W;
-  if (bitpacked) {
+  if (bitpacked && W % 32 == 0 && n < ((int64_t)1 << 31)) {
+    const int wpr = (int)(W / 32);
+    const int64_t words = n / 32;
+    hipLaunchKernelGGL(k_mask_median3_rows, dim3((unsigned)((words + 255) / 256), (unsigned)m), dim3(256), 0, stream,
+                       (const uint32_t*)in, (uint32_t*)out, (int)H, wpr);
+  } else if (bitpacked) {
     const int64_t words = (n + 31) / 32;
     hipLaunchKernelGGL(k_mask_median3_bits, dim3((unsigned)((words + 255) / 256), (unsigned)m), dim3(256), 0, stream,
                        (const uint32_t*)in, (uint32_t*)out, H, W, words);

@@ -574,8 +574,14 @@ static bool sym_tridiagonal(const double* Ain, int n, int lda, SymTri& t) {
     double vtp = 0.0;
     for (int i = 0; i < m; ++i) {
       const double* row = &A[(size_t)(k + 1 + i) * n + (k + 1)];
-      double acc = 0.0;
-      for (int j = 0; j < m; ++j) acc += row[j] * v[j];
+      // eight independent partial sums (a fixed order), so the loop is not one long
+      // chain of dependent additions
+      double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+      int j = 0;
+      for (; j + 8 <= m; j += 8)
+        for (int u = 0; u < 8; ++u) a[u] += row[j + u] * v[j + u];
+      for (; j < m; ++j) a[j & 7] += row[j] * v[j];
+      const double acc = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
       pv[i] = acc;
       vtp += v[i] * acc;
     }

@@ -1,7 +1,8 @@
 """Median filtering of foreground masks (Section 4, BMC evaluation) through the C ABI:
 cdmd_mask_median3 against the oracle's median3 (itself pinned to scipy's median filter).
 Integer work: bit-exact, for bit-packed and uint8 masks, frame widths that are and are not
-multiples of 32, one-pixel-wide frames, and on a mask the library itself produced."""
+multiples of 32 (the word-parallel kernel and the per-bit one), one-pixel-wide frames, and
+on a mask the library itself produced."""
 import numpy as np
 import pytest
 import torch
@@ -27,7 +28,7 @@ def _pack(mk):
 
 
 @pytest.mark.parametrize("shape", [(37, 45, 5, 0.3), (64, 64, 3, 0.5), (1, 70, 2, 0.5), (70, 1, 2, 0.4),
-                                   (120, 96, 4, 0.1)])
+                                   (120, 96, 4, 0.1), (1, 64, 2, 0.5), (33, 32, 3, 0.5), (20, 320, 2, 0.5)])
 def test_median3_matches_oracle(shape):
     H, W, m, dens = shape
     _say("median3", shape)
