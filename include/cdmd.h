@@ -318,6 +318,23 @@ typedef struct {
 cdmd_status cdmd_process_video(const cdmd_config* base, const cdmd_video_plan* plan, const void* d_video,
                                int64_t frames, void* d_mask, int32_t* k_used, void* stream);
 
+/* The same as a reusable executor: cdmd_process_video is cdmd_video_create, one
+   cdmd_video_run and cdmd_video_free.  The executor owns its worker streams, the models
+   of every (batch length, rank) it has met and the unfiltered-mask buffers, and keeps
+   them from one run to the next, so later videos of the same shape allocate nothing.
+   cdmd_video_create copies `base` and its sparse table (the caller's arrays may be freed
+   afterwards) and checks the plan (INVALID_ARG); models are created on first use, so
+   configuration errors of `base` surface in the first cdmd_video_run.  cdmd_video_run
+   takes `frames` frames at d_video with the layout of `base` and behaves as
+   cdmd_process_video; runs on one executor must not overlap (one host thread at a time).
+   cdmd_video_free waits for the executor's streams and releases everything (NULL is a
+   no-op). */
+typedef struct cdmd_video cdmd_video;
+cdmd_status cdmd_video_create(const cdmd_config* base, const cdmd_video_plan* plan, cdmd_video** out);
+cdmd_status cdmd_video_run(cdmd_video* video, const void* d_video, int64_t frames, void* d_mask, int32_t* k_used,
+                           void* stream);
+void cdmd_video_free(cdmd_video* video);
+
 /* ---- learned background selector -------------------------------------------------
    A 6-64-64-1 network with GELU activations (exact erf) maps per-mode features to the
    logit of "sparse coding selects this mode"; the paper suggests learning the background

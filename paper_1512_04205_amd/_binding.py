@@ -37,6 +37,7 @@ EXPORTED = [
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_train_noalloc", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
     "cdmd_batch_free", "cdmd_optimal_rank", "cdmd_store_measurement", "cdmd_process_video",
+    "cdmd_video_create", "cdmd_video_run", "cdmd_video_free",
 ]
 MLP_NPARAM = 4673
 
@@ -114,6 +115,10 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_process_video.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(VideoPlan), ctypes.c_void_p,
                                        ctypes.c_int64, ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32),
                                        ctypes.c_void_p]
+    lib.cdmd_video_create.argtypes = [ctypes.POINTER(Config), ctypes.POINTER(VideoPlan), ctypes.POINTER(P)]
+    lib.cdmd_video_run.argtypes = [P, P, ctypes.c_int64, P, ctypes.POINTER(ctypes.c_int32), P]
+    lib.cdmd_video_free.argtypes = [P]
+    lib.cdmd_video_free.restype = None
     lib.cdmd_mask_median3.argtypes = [P, P, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64, I32, P]
     lib.cdmd_dbg_force_valu_lift.argtypes = [P, I32]
     lib.cdmd_dbg_force_host_la.argtypes = [P, I32]
@@ -202,17 +207,10 @@ def optimal_rank(video, n: int, m: int, p: int, *, sketch: int = SKETCH_SPARSE, 
     return int(k.value), float(tau.value), sig
 
 
-def process_video(video, n: int, frames: int, p: int, mask, *, batch_frames: int = 200, k: int = 0,
-                  K: int = 10, tau: float = 0.1, workers: int = 2, median_hw=None,
-                  sketch: int = SKETCH_SPARSE, dtype: int = U8, ld: Optional[int] = None,
-                  idx: Optional[np.ndarray] = None, sign: Optional[np.ndarray] = None, seed: int = 0,
-                  sketch_prec: int = PREC_FP32, lift_prec: int = PREC_FP32, stream=None) -> np.ndarray:
-    """A long video in batches of consecutive frames (cdmd_process_video): fills the device
-    mask (frames, mask_words(n)) int32 and returns the rank used for each batch."""
-    lib = load_library()
-    ld = int(ld if ld is not None else n)
+def _video_setup(n, p, batch_frames, k, K, tau, workers, median_hw, sketch, dtype, ld, idx, sign, seed,
+                 sketch_prec, lift_prec):
     cfg = Config()
-    cfg.n, cfg.m, cfg.ld, cfg.k, cfg.p = int(n), 2, ld, 1, int(p)
+    cfg.n, cfg.m, cfg.ld, cfg.k, cfg.p = int(n), 2, int(ld), 1, int(p)
     cfg.dtype, cfg.sketch, cfg.seed = dtype, sketch, seed
     cfg.sketch_prec, cfg.lift_prec = sketch_prec, lift_prec
     keep = []
@@ -228,6 +226,20 @@ def process_video(video, n: int, frames: int, p: int, mask, *, batch_frames: int
     plan = VideoPlan()
     plan.batch_frames, plan.k, plan.K, plan.workers, plan.tau = batch_frames, k, K, workers, tau
     plan.H, plan.W = median_hw if median_hw is not None else (0, 0)
+    return cfg, plan, keep
+
+
+def process_video(video, n: int, frames: int, p: int, mask, *, batch_frames: int = 200, k: int = 0,
+                  K: int = 10, tau: float = 0.1, workers: int = 2, median_hw=None,
+                  sketch: int = SKETCH_SPARSE, dtype: int = U8, ld: Optional[int] = None,
+                  idx: Optional[np.ndarray] = None, sign: Optional[np.ndarray] = None, seed: int = 0,
+                  sketch_prec: int = PREC_FP32, lift_prec: int = PREC_FP32, stream=None) -> np.ndarray:
+    """A long video in batches of consecutive frames (cdmd_process_video): fills the device
+    mask (frames, mask_words(n)) int32 and returns the rank used for each batch."""
+    lib = load_library()
+    ld = int(ld if ld is not None else n)
+    cfg, plan, keep = _video_setup(n, p, batch_frames, k, K, tau, workers, median_hw, sketch, dtype, ld, idx,
+                                   sign, seed, sketch_prec, lift_prec)
     nb = max(1, (frames + batch_frames - 1) // batch_frames)
     k_used = np.zeros(nb, dtype=np.int32)
     words = mask_words(n)
@@ -235,7 +247,50 @@ def process_video(video, n: int, frames: int, p: int, mask, *, batch_frames: int
                                   _video_ptr(video, dtype, n, frames, ld),
                                   frames, _tensor_ptr(mask, frames * words),
                                   k_used.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _stream(stream)))
+    del keep
     return k_used
+
+
+class VideoExecutor:
+    """A reusable long-video executor (cdmd_video_create / cdmd_video_run / cdmd_video_free):
+    the arguments of process_video fixed once; run() processes one video and returns the
+    rank used for each batch."""
+
+    def __init__(self, n: int, p: int, *, batch_frames: int = 200, k: int = 0, K: int = 10, tau: float = 0.1,
+                 workers: int = 2, median_hw=None, sketch: int = SKETCH_SPARSE, dtype: int = U8,
+                 ld: Optional[int] = None, idx: Optional[np.ndarray] = None, sign: Optional[np.ndarray] = None,
+                 seed: int = 0, sketch_prec: int = PREC_FP32, lift_prec: int = PREC_FP32):
+        lib = load_library()
+        self.n, self.dtype, self.batch_frames = int(n), dtype, int(batch_frames)
+        self.ld = int(ld if ld is not None else n)
+        cfg, plan, keep = _video_setup(n, p, batch_frames, k, K, tau, workers, median_hw, sketch, dtype, self.ld,
+                                       idx, sign, seed, sketch_prec, lift_prec)
+        h = ctypes.c_void_p()
+        _check(lib.cdmd_video_create(ctypes.byref(cfg), ctypes.byref(plan), ctypes.byref(h)))
+        del keep  # the executor keeps its own copy of the sparse table
+        self._h = h
+
+    def run(self, video, frames: int, mask, stream=None) -> np.ndarray:
+        if not self._h:
+            raise CdmdError(E_STATE, "executor closed")
+        nb = max(1, (frames + self.batch_frames - 1) // self.batch_frames)
+        k_used = np.zeros(nb, dtype=np.int32)
+        _check(load_library().cdmd_video_run(self._h, _video_ptr(video, self.dtype, self.n, frames, self.ld), frames,
+                                             _tensor_ptr(mask, frames * mask_words(self.n)),
+                                             k_used.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)),
+                                             _stream(stream)))
+        return k_used
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load_library().cdmd_video_free(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class Model:

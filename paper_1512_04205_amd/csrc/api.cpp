@@ -1970,7 +1970,8 @@ cdmd_status cdmd_info_get(const cdmd_model* Mc, cdmd_info* info) {
 // Section 4 processes a long video as consecutive batches of frames, each decomposed on its
 // own.  Workers (host threads, each with its own stream and models) take the batches in
 // turn, so the latency-bound small linear algebra of one batch runs beside the streaming
-// kernels of another.
+// kernels of another.  The executor keeps its streams, models (per batch length and rank)
+// and mask buffers from one video to the next, so only the first video pays for them.
 namespace {
 struct VideoBatch {
   int64_t t0, m;
@@ -1995,41 +1996,89 @@ struct VideoWorker {
   cdmd_status status = CDMD_OK;
   std::string err;
   ~VideoWorker() {
+    if (st) (void)hipStreamSynchronize(st);  // a failed batch may have left work in flight
+    models.clear();
+    rank_models.clear();
     if (d_raw) (void)hipFree(d_raw);
     if (st) (void)hipStreamDestroy(st);
   }
 };
 }  // namespace
 
-cdmd_status cdmd_process_video(const cdmd_config* base, const cdmd_video_plan* plan, const void* d_video,
-                               int64_t frames, void* d_mask, int32_t* k_used, void* stream) {
+struct cdmd_video {
+  cdmd_config base{};
+  cdmd_video_plan plan{};
+  std::vector<int32_t> idx;  // host copies of the sparse C (the caller's arrays may go)
+  std::vector<int8_t> sign;
+  int dev = 0;
+  bool median = false;
+  hipEvent_t ready = nullptr;
+  std::vector<VideoWorker> wk;
+  ~cdmd_video() {
+    wk.clear();
+    if (ready) (void)hipEventDestroy(ready);
+  }
+};
+
+cdmd_status cdmd_video_create(const cdmd_config* base, const cdmd_video_plan* plan, cdmd_video** out) {
   g_err.clear();
-  if (!base || !plan || !d_video || !d_mask) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  if (!base || !plan || !out) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  *out = nullptr;
   const cdmd_video_plan vp = *plan;
-  if (frames < 2 || vp.batch_frames < 2) return fail(CDMD_E_INVALID_ARG, "need at least 2 frames per batch");
+  if (vp.batch_frames < 2) return fail(CDMD_E_INVALID_ARG, "need at least 2 frames per batch");
   if (vp.workers < 1 || vp.workers > 4) return fail(CDMD_E_INVALID_ARG, "workers must be 1..4");
   if (vp.K < 1 || vp.k < 0) return fail(CDMD_E_INVALID_ARG, "need K >= 1 and k >= 0");
   if (!(vp.tau >= 0.0)) return fail(CDMD_E_INVALID_ARG, "tau must be >= 0");
   const bool median = vp.H > 0 || vp.W > 0;
   if (median && (vp.H < 1 || vp.W < 1 || vp.H * vp.W != base->n))
     return fail(CDMD_E_INVALID_ARG, "the median filter needs H * W == n");
+  if (base->p < 1 || base->nnz < 1) return fail(CDMD_E_INVALID_ARG, "need p >= 1 and nnz >= 1");
+  std::unique_ptr<cdmd_video> V(new cdmd_video);
+  V->base = *base;
+  V->plan = vp;
+  V->median = median;
+  const size_t tab = (size_t)base->p * (size_t)base->nnz;
+  if (base->sparse_idx) {
+    V->idx.assign(base->sparse_idx, base->sparse_idx + tab);
+    V->base.sparse_idx = V->idx.data();
+  }
+  if (base->sparse_sign) {
+    V->sign.assign(base->sparse_sign, base->sparse_sign + tab);
+    V->base.sparse_sign = V->sign.data();
+  }
+  HIPCHK(hipGetDevice(&V->dev));
+  HIPCHK(hipEventCreateWithFlags(&V->ready, hipEventDisableTiming));
+  V->wk = std::vector<VideoWorker>(vp.workers);
+  for (auto& w : V->wk) HIPCHK(hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking));
+  *out = V.release();
+  return CDMD_OK;
+}
+
+void cdmd_video_free(cdmd_video* V) { delete V; }
+
+cdmd_status cdmd_video_run(cdmd_video* V, const void* d_video, int64_t frames, void* d_mask, int32_t* k_used,
+                           void* stream) {
+  g_err.clear();
+  if (!V || !d_video || !d_mask) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  if (frames < 2) return fail(CDMD_E_INVALID_ARG, "need at least 2 frames");
+  const cdmd_config* base = &V->base;
+  const cdmd_video_plan& vp = V->plan;
+  const bool median = V->median;
   const std::vector<VideoBatch> batches = video_batches(frames, vp.batch_frames);
   const int64_t words = (base->n + 31) / 32;
   const size_t elem = base->dtype == CDMD_U8 ? 1 : 4;
-  const int nw = std::min<int>(vp.workers, (int)batches.size());
-  std::vector<VideoWorker> wk(nw);
-  hipEvent_t ready = nullptr;
-  HIPCHK(hipEventCreateWithFlags(&ready, hipEventDisableTiming));
-  std::unique_ptr<void, void (*)(void*)> ready_own(ready, [](void* e) { (void)hipEventDestroy((hipEvent_t)e); });
-  HIPCHK(hipEventRecord(ready, as_stream(stream)));  // the video is ready on the caller's stream
-  int dev = 0;
-  HIPCHK(hipGetDevice(&dev));
-  for (auto& w : wk) {
-    HIPCHK(hipStreamCreateWithFlags(&w.st, hipStreamNonBlocking));
-    HIPCHK(hipStreamWaitEvent(w.st, ready, 0));
+  const int nw = std::min<int>((int)V->wk.size(), (int)batches.size());
+  HIPCHK(hipSetDevice(V->dev));
+  HIPCHK(hipEventRecord(V->ready, as_stream(stream)));  // the video is ready on the caller's stream
+  for (int i = 0; i < nw; ++i) {
+    VideoWorker& w = V->wk[i];
+    w.status = CDMD_OK;
+    w.err.clear();
+    HIPCHK(hipStreamWaitEvent(w.st, V->ready, 0));
   }
+  const int dev = V->dev;
   auto run = [&](int wi) {
-    VideoWorker& w = wk[wi];
+    VideoWorker& w = V->wk[wi];
     if (hipSetDevice(dev) != hipSuccess) {
       w.status = CDMD_E_DEVICE;
       w.err = "hipSetDevice failed in a worker";
@@ -2080,6 +2129,12 @@ cdmd_status cdmd_process_video(const cdmd_config* base, const cdmd_video_plan* p
       if (median) {
         const size_t need = (size_t)b.m * words * 4;
         if (w.raw_bytes < need) {
+          // the previous video's kernels on this stream may still read the old buffer
+          if (w.d_raw && hipStreamSynchronize(w.st) != hipSuccess) {
+            w.status = CDMD_E_DEVICE;
+            w.err = "a worker stream failed";
+            return;
+          }
           if (w.d_raw) (void)hipFree(w.d_raw);
           w.d_raw = nullptr;
           w.raw_bytes = 0;
@@ -2112,9 +2167,21 @@ cdmd_status cdmd_process_video(const cdmd_config* base, const cdmd_video_plan* p
     for (int i = 0; i < nw; ++i) th.emplace_back(run, i);
     for (auto& t : th) t.join();
   }
-  for (auto& w : wk)
-    if (w.status != CDMD_OK) return fail(w.status, ("a batch failed: " + w.err).c_str());
+  for (int i = 0; i < nw; ++i)
+    if (V->wk[i].status != CDMD_OK) return fail(V->wk[i].status, ("a batch failed: " + V->wk[i].err).c_str());
   return CDMD_OK;
+}
+
+cdmd_status cdmd_process_video(const cdmd_config* base, const cdmd_video_plan* plan, const void* d_video,
+                               int64_t frames, void* d_mask, int32_t* k_used, void* stream) {
+  g_err.clear();
+  if (!base || !plan || !d_video || !d_mask) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  if (frames < 2) return fail(CDMD_E_INVALID_ARG, "need at least 2 frames per batch");
+  cdmd_video* V = nullptr;
+  cdmd_status st = cdmd_video_create(base, plan, &V);
+  if (st != CDMD_OK) return st;
+  std::unique_ptr<cdmd_video> own(V);
+  return cdmd_video_run(V, d_video, frames, d_mask, k_used, stream);
 }
 
 cdmd_status cdmd_mask_median3(const void* d_in, void* d_out, int64_t H, int64_t W, int64_t m, int32_t bitpacked,

@@ -111,7 +111,22 @@ def test_null_handles():
     assert lib.cdmd_create(None, None) == P.E_INVALID_ARG
     assert lib.cdmd_store_measurement(None, 1, None) == P.E_INVALID_ARG
     assert lib.cdmd_process_video(None, None, None, 0, None, None, None) == P.E_INVALID_ARG
+    assert lib.cdmd_video_create(None, None, None) == P.E_INVALID_ARG
+    assert lib.cdmd_video_run(None, None, 0, None, None, None) == P.E_INVALID_ARG
     lib.cdmd_free(None)
+    lib.cdmd_video_free(None)
+
+
+@pytest.mark.parametrize("bad", [dict(batch_frames=1), dict(workers=0), dict(workers=5), dict(K=0), dict(k=-1),
+                                 dict(tau=-1.0), dict(median_hw=(7, 7))])
+def test_video_executor_plan_checks(bad):
+    """The long-video executor checks its plan on the host before touching a device."""
+    idx, sign = sv.sparse_table(1000, 50, 8, 1)
+    kw = dict(batch_frames=100, k=3, K=5, tau=0.1, workers=2, idx=idx, sign=sign)
+    kw.update(bad)
+    with pytest.raises(P.CdmdError) as e:
+        P.VideoExecutor(1000, 50, **kw)
+    assert e.value.status == P.E_INVALID_ARG
 
 
 # ------------------------------------------------------------------ host small LA

@@ -96,3 +96,29 @@ def test_refusals():
     for kw in (dict(batch_frames=1), dict(workers=0), dict(workers=5), dict(K=0), dict(median_hw=(7, 7))):
         with pytest.raises(P.CdmdError, match="INVALID_ARG"):
             P.process_video(v.D, n, 10, 50, mk, idx=idx, sign=sign, **{**dict(batch_frames=5, k=3), **kw})
+
+
+def test_executor_reused_across_videos():
+    """One executor (cdmd_video_create / cdmd_video_run), three videos in a row: 530 frames,
+    then 401 (its last batch takes the trailing frame, 201 frames, so a worker's mask buffer
+    grows between runs), then the first again; automatic rank and the median filter on.
+    Every run equals cdmd_process_video on the same video, which equals the single fits."""
+    F, p, K, tau = 200, 300, 6, 0.1
+    _say("video executor reuse")
+    va, vb = _video(530, seed=7), _video(401, seed=8)
+    n = va.spec.n
+    hw = (va.spec.H, va.spec.W)
+    idx, sign = sv.sparse_table(n, p, 16, 11)
+    ex = P.VideoExecutor(n, p, batch_frames=F, k=0, K=K, tau=tau, workers=2, median_hw=hw, idx=idx, sign=sign)
+    for v in (va, vb, va):
+        frames = v.D.shape[0]
+        ref = torch.zeros((frames, P.mask_words(n)), dtype=torch.int32, device="cuda")
+        kr = P.process_video(v.D, n, frames, p, ref, batch_frames=F, k=0, K=K, tau=tau, workers=2, median_hw=hw,
+                             idx=idx, sign=sign)
+        mk = torch.full_like(ref, -1)
+        ke = ex.run(v.D, frames, mk)
+        assert list(ke) == list(kr)
+        assert torch.equal(mk, ref)
+    ex.close()
+    with pytest.raises(P.CdmdError):
+        ex.run(va.D, 530, mk)
