@@ -188,6 +188,15 @@ WORKLOADS = {
                   desc="1920x1080 uint8 video, 1000 frames in batches of 200, i.i.d. very sparse C "
                        "(s = n/ln n) with p=1000, automatic rank per batch, OMP K=10, tau=0.1, "
                        "3x3 median-filtered masks"),
+    # Section 4's comparison of sensing matrices: fit time and F-measure against p for the
+    # dense Gaussian, the i.i.d. very sparse and the single-pixel C on a 720x480x200 video
+    "sensing": dict(preset="ctxB", sketch="sweep", k=0, p=0, nnz=32, K=10, tau=0.1, seed=31,
+                    ps=(100, 250, 500, 1000, 2000, 4000), draws=5,
+                    desc="720x480 uint8 video, m=200, rank by Remark 2 per draw, OMP K=10, tau=0.1: fit "
+                         "frames/s and F-measure "
+                         "against the generator's ground truth for p in {100..4000}, Gaussian (BF16 and "
+                         "FP32 forms) / i.i.d. very sparse (s = n/ln n) / single-pixel / SRFT C, 5 draws of C "
+                         "each"),
     # many independent streams in one graph launch
     "cfg4": dict(preset=None, sketch="mixed", k=0, p=0, nnz=32, K=10, tau=0.1, seed=4,
                  desc="64 uint8 streams in one batch: resolutions 320x240 / 640x480 / 1280x720 / "
@@ -269,6 +278,99 @@ def run_video(args, wl):
         "foreground_fraction_first_frames": gt_frac,
         "note": "a step is the whole video: every batch sketched, fitted, selected, thresholded and median "
                 "filtered by a reused executor; one_shot_ms: one cdmd_process_video call, set-up included",
+    }
+
+
+def run_sensing(args, wl):
+    """fps of the fit (sketch through amplitudes and the OMP selection; the mask excluded) and
+    F-measure of the foreground mask against the ground truth, for every sensing matrix and
+    p, each over several draws of C; returns the JSON line (value: the i.i.d. very sparse C
+    at p = 1000, the paper's evaluation setting)."""
+    import math
+    import numpy as np
+    import torch
+    import paper_1512_04205_amd as P
+    import synthvideo as sv
+    spec = sv.PRESETS[wl["preset"]]
+    log(f"generating {spec.W}x{spec.H}x{spec.m} {spec.out} video on the GPU")
+    v = sv.make_video(spec, device="cuda")
+    m, n = v.D.shape
+    k, K, tau = wl["k"], wl["K"], wl["tau"]
+    gt = torch.from_numpy(v.gt_mask()).cuda()
+    mask = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    shifts = torch.arange(32, dtype=torch.int32, device="cuda")
+
+    def f_measure():
+        bits = ((mask.unsqueeze(-1) >> shifts) & 1).reshape(m, -1)[:, :n].bool()
+        tp = (bits & gt).sum().item()
+        fp = (bits & ~gt).sum().item()
+        fn = (~bits & gt).sum().item()
+        return 2.0 * tp / (2.0 * tp + fp + fn) if tp + fp + fn else 1.0
+
+    def model(kind, p, draw):
+        # the rank of each draw by Remark 2 (the paper's evaluation setting), not timed
+        seed = wl["seed"] * 1000 + draw
+        if kind.startswith("gaussian"):
+            sp = P.PREC_BF16 if kind == "gaussian_bf16" else P.PREC_FP32
+            kw = dict(sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=seed, sketch_prec=sp)
+        elif kind == "sparse":
+            idx, sign = sv.iid_sparse_table(n, p, n / math.log(n), seed)
+            kw = dict(idx=idx, sign=sign)
+        elif kind == "srft":
+            fr = np.random.default_rng(seed).choice(n, size=p, replace=False).astype(np.int32)
+            kw = dict(sketch=P.SKETCH_SRFT, idx=fr.reshape(p, 1), seed=seed)
+        else:
+            idx, sign = sv.single_pixel_table(n, p, seed)
+            kw = dict(sketch=P.SKETCH_SPIXEL, idx=idx, sign=sign)
+        if kind == "srft":  # no automatic rank for a complex sketch: the i.i.d. sparse C's rank
+            kd = k if k > 0 else max(1, min(srft_rank[p], p, m - 1, 40))
+        else:
+            kd = k if k > 0 else max(1, min(P.optimal_rank(v.D, n, m, p, **kw)[0], p, m - 1, 40))
+            if kind == "sparse" and draw == 0:
+                srft_rank[p] = kd
+        return P.Model(n, m, kd, p, **kw), kd
+
+    table = []
+    srft_rank = {}
+    for kind in ("gaussian_bf16", "gaussian_fp32", "sparse", "spixel", "srft"):
+        for p in wl["ps"]:
+            ms, fs, ks = [], [], []
+            for draw in range(wl["draws"]):
+                mdl, kd = model(kind, p, draw)
+                ks.append(kd)
+                mdl.fit(v.D)  # warm-up: first use of the model's buffers
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                reps = max(1, args.steps // 4)
+                for _ in range(reps):
+                    mdl.fit(v.D)
+                    mdl.select(P.SEL_OMP, K=K)
+                torch.cuda.synchronize()
+                ms.append((time.perf_counter() - t0) / reps * 1e3)
+                mdl.foreground(v.D, mask, tau)
+                torch.cuda.synchronize()
+                fs.append(f_measure())
+                mdl.close()
+            row = dict(sensing=kind, p=p, k=[int(x) for x in ks], ms_fit=float(np.median(ms)),
+                       fps=float(m / (np.median(ms) / 1e3)),
+                       f_mean=float(np.mean(fs)), f_std=float(np.std(fs)), f_min=float(np.min(fs)),
+                       f_max=float(np.max(fs)))
+            table.append(row)
+            log(f"{kind:14s} p={p:5d} k={ks}: {row['ms_fit']:.3f} ms/fit, {row['fps']:.0f} fps, "
+                f"F {row['f_mean']:.4f} +- {row['f_std']:.4f} [{row['f_min']:.4f}, {row['f_max']:.4f}]")
+    head = next(r for r in table if r["sensing"] == "sparse" and r["p"] == 1000)
+    return {
+        "metric": "frames/sec cDMD fit (sketch..amplitudes + OMP), 720x480x200, by sensing matrix and p",
+        "value": head["fps"], "unit": "frames/s", "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": head["ms_fit"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32", "data": "synthetic",
+        "config": {"workload": wl["desc"], "n": n, "frames": m, "k": k, "K": K, "tau": tau,
+                   "value_is": "i.i.d. very sparse C, p = 1000"},
+        "roofline": None,
+        "sweep": table,
+        "note": "fps = frames / median fit time over the draws (sketch, Gram, small LA, lift, amplitudes, "
+                "OMP; the mask excluded); F = 2TP / (2TP + FP + FN) of the tau = 0.1 mask over every pixel "
+                "and frame against the generator's ground truth",
     }
 
 
@@ -611,6 +713,9 @@ def main():
         return
     if args.workload == "video":
         print(json.dumps(run_video(args, wl)), flush=True)
+        return
+    if args.workload == "sensing":
+        print(json.dumps(run_sensing(args, wl)), flush=True)
         return
     copy_gbs = None
     if args.copy_ref_mib > 0:

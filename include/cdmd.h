@@ -72,8 +72,16 @@ typedef enum {
                                  uniforms (w+1) 2^-32; never stored */
   CDMD_SKETCH_SPARSE = 1,     /* each row holds nnz entries +/-1 at distinct pixels,
                                  given by the caller's index/sign table */
-  CDMD_SKETCH_SPIXEL = 2      /* single-pixel C = R: p distinct pixels, weight +1
+  CDMD_SKETCH_SPIXEL = 2,     /* single-pixel C = R: p distinct pixels, weight +1
                                  (nnz = 1), given by the caller's index table */
+  CDMD_SKETCH_SRFT = 3        /* subsampled randomised Fourier transform C = R F D / sqrt(p):
+                                 D diagonal with entries exp(2 pi i u_j), u_j = word j mod 4
+                                 of Philox4x32-10 on the counter (j>>2, 0, 0, 1) with the
+                                 key of the Gaussian C, times 2^-32; F the unnormalised n-point
+                                 DFT, F(f, j) = exp(-2 pi i f j / n); R keeps the p distinct
+                                 DFT rows f given in sparse_idx (nnz = 1, weights +1).  The
+                                 sketch is complex: FP32 form only, the small linear algebra
+                                 complex on the host; no automatic rank, no batches */
 } cdmd_sketch;
 
 /* Arithmetic of the sketch and of the mode lift / reconstruction passes.  The
@@ -406,7 +414,9 @@ cdmd_status cdmd_select_learned(cdmd_model* mdl, const float* d_params, double c
                                 void* stream);
 
 /* Sketch of the last fit, Y^ = C D (p x m), scaled (u/255 for uint8, 1/sqrt(p) for
-   Gaussian), host float64, frame-major: element (r, t) at t*p + r.  Optional
+   Gaussian and SRFT), host float64, frame-major: element (r, t) at t*p + r; for the
+   complex SRFT sketch 2 p m numbers, the real and imaginary part of (r, t) at
+   t*2p + 2r and t*2p + 2r + 1.  Optional
    h_int (host int64[p*m]): the exact integer sums of a sparse/single-pixel sketch of
    a uint8 video before scaling (INVALID_ARG otherwise).  Errors: STATE. */
 cdmd_status cdmd_get_sketch(const cdmd_model* mdl, double* h_Y, int64_t* h_int);

@@ -28,6 +28,16 @@ cdmd_status cdmd_dbg_sym_topk(const double* M, int32_t n, int32_t k, double rtol
    Errors: INVALID_ARG, NUMERIC. */
 cdmd_status cdmd_dbg_eig_general(const double* A, int32_t k, double* lam, double* W);
 
+/* The complex counterparts used with a complex measurement matrix (the SRFT sketch of
+   Section 3.3): top-k eigenpairs of the Hermitian n x n matrix M (host, row-major, re/im
+   interleaved) by complex Lanczos with full reorthogonalisation (evecs n x k column-major
+   complex), and eigenvalues / unit eigenvectors of a complex k x k matrix A (row-major,
+   re/im interleaved; lam[2k], W[2k*k] column-major) by Hessenberg reduction, shifted QR
+   and back substitution.  Errors: INVALID_ARG, NUMERIC. */
+cdmd_status cdmd_dbg_herm_topk(const double* M, int32_t n, int32_t k, double rtol,
+                               double* evals, double* evecs, int32_t* steps);
+cdmd_status cdmd_dbg_eig_complex(const double* A, int32_t k, double* lam, double* W);
+
 /* Orthogonal matching pursuit in coefficient space (Section 2.3, eq. (eq:sparsecoding))
    on H = Phi^H Phi (k x k complex, row-major, re/im interleaved), c = Phi^H x_1 (k
    complex) for a real x_1, and x1n2 = ||x_1||^2.  lam (nullable; k complex, re/im

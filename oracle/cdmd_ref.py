@@ -8,8 +8,9 @@ Follows Erichson, Brunton and Kutz, "Compressed Dynamic Mode Decomposition for
 Background Modeling":
 
 * snapshot split X, X' (Section 2.1, eq. FullData);
-* sketch Y = C X, Y' = C X' (Section 3.2, eq. (eq:YCX)) with Gaussian, sparse +/-1
-  or single-pixel C (Section 3.3);
+* sketch Y = C X, Y' = C X' (Section 3.2, eq. (eq:YCX)) with Gaussian, sparse +/-1,
+  single-pixel or SRFT C (Section 3.3; the SRFT sketch is complex and every later step
+  takes conjugate transposes);
 * the least-squares operator on the sketched snapshots, projected on the leading left
   singular vectors: Y = U S V* truncated to rank k (eq. svd), A~ = U* Y' V S^-1 and its
   eigenpairs A~ W = W Lambda (Section 3.2);
@@ -124,6 +125,27 @@ def sketch_gaussian(D: np.ndarray, scale: float, seed: int, p: int, chunk: int =
             C = C / np.sqrt(p)
         Y += C @ pixel_rows(D, scale, j0, j1)
     return Y
+
+
+def srft_diagonal(seed: int, n: int) -> np.ndarray:
+    """The random diagonal D of the SRFT (Section 3.3): unit-modulus entries
+    exp(2 pi i u_j), u_j from ``philox.srft_uniforms``."""
+    return np.exp(2j * np.pi * philox.srft_uniforms(seed, 0, n))
+
+
+def sketch_srft(D: np.ndarray, scale: float, freqs: np.ndarray, seed: int) -> np.ndarray:
+    """Y^ = C X with the subsampled randomised Fourier transform C = R F D / sqrt(p)
+    (Section 3.3): D = ``srft_diagonal``, F the unnormalised n-point DFT with entries
+    exp(-2 pi i f j / n) (the paper's F(j, k) with the 1/m of the printed exponent read as
+    1/n, the transform's own length), R the p rows ``freqs``.  Frame by frame through the
+    FFT: (F (D x_t))[freqs].  Complex p x m."""
+    m, n = D.shape
+    d = srft_diagonal(seed, n)
+    freqs = np.asarray(freqs, dtype=np.int64).reshape(-1)
+    Y = np.empty((len(freqs), m), dtype=np.complex128)
+    for t in range(m):
+        Y[:, t] = np.fft.fft(d * (D[t].astype(np.float64) * scale))[freqs]
+    return Y / np.sqrt(len(freqs))
 
 
 def _round_sig(z: np.ndarray, mant_bits: int, emin: int) -> np.ndarray:
@@ -479,11 +501,14 @@ class Pipeline:
 def run(D: np.ndarray, scale: float, k: int, *, sketch: str, p: int = 0,
         idx: Optional[np.ndarray] = None, sign: Optional[np.ndarray] = None,
         seed: int = 0, K: int = 10, selector: str = "omp") -> Pipeline:
-    """Sketch -> fit -> selection, all in float64 (the stages before the mask)."""
+    """Sketch -> fit -> selection, all in float64 (the stages before the mask).  For
+    the SRFT sketch ``idx`` holds the kept DFT rows."""
     if sketch in ("sparse", "spixel"):
         Yhat, _ = sketch_sparse(D, scale, idx, sign)
     elif sketch == "gaussian":
         Yhat = sketch_gaussian(D, scale, seed, p)
+    elif sketch == "srft":
+        Yhat = sketch_srft(D, scale, idx, seed)
     else:
         raise ValueError(sketch)
     mdl = fit(D, scale, Yhat, k)

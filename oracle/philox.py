@@ -73,3 +73,18 @@ def gaussian_block(seed: int, r0: int, r1: int, j0: int, j1: int) -> np.ndarray:
     z = np.stack([z0, z1, z2, z3], axis=-1).reshape(r1 - r0, 4 * (jb1 - jb0))
     off = j0 - 4 * jb0
     return z[:, off:off + (j1 - j0)]
+
+
+def srft_uniforms(seed: int, j0: int, j1: int) -> np.ndarray:
+    """The uniforms u_j in [0, 1) of the SRFT's random diagonal (entry exp(2 pi i u_j),
+    Section 3.3) for pixels j0 <= j < j1: word j mod 4 of Philox4x32-10 on the counter
+    (j >> 2, 0, 0, 1) with the key (seed mod 2^32, seed >> 32), times 2^-32.  (The
+    Gaussian entries use counters with last word 0, so the two never share a counter.)"""
+    if j1 <= j0:
+        return np.zeros(0)
+    jb = np.arange(j0 >> 2, ((j1 - 1) >> 2) + 1, dtype=np.uint64)
+    w = philox4x32_10(jb, 0, 0, 1, seed & 0xFFFFFFFF, seed >> 32)
+    words = np.stack(w, axis=1).reshape(-1)
+    s0 = j0 - 4 * (j0 >> 2)
+    return words[s0:s0 + (j1 - j0)].astype(np.float64) * 2.0 ** -32
+

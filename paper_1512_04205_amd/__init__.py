@@ -6,7 +6,7 @@ from ._binding import (  # noqa: F401
     CdmdError, Model, Batch, optimal_rank, process_video, VideoExecutor, load_library, unpack_mask,
     mask_words, mask_median3, LIB_PATH, EXPORTED,
     MLP_NPARAM, MLP_NOALLOC_MAX_BATCH, mlp_grad, mlp_train, mlp_train_noalloc, mlp_forward,
-    U8, F32, SKETCH_GAUSSIAN, SKETCH_SPARSE, SKETCH_SPIXEL, PREC_FP32, PREC_BF16, PREC_FP8,
+    U8, F32, SKETCH_GAUSSIAN, SKETCH_SPARSE, SKETCH_SPIXEL, SKETCH_SRFT, PREC_FP32, PREC_BF16, PREC_FP8,
     SEL_OMP, SEL_ZERO_MODE, SEL_OMEGA, SEL_EXPLICIT, SEL_ALL, AMP_FULL, AMP_COMPRESSED,
     OK, E_INVALID_ARG, E_UNSUPPORTED, E_OUT_OF_MEMORY, E_DEVICE, E_RANK_DEFICIENT, E_NUMERIC,
     E_STATE,

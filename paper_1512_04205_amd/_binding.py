@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_PKG, "libcdmd.so")
 # enums (include/cdmd.h)
 OK, E_INVALID_ARG, E_UNSUPPORTED, E_OUT_OF_MEMORY, E_DEVICE, E_RANK_DEFICIENT, E_NUMERIC, E_STATE = range(8)
 U8, F32 = 0, 1
-SKETCH_GAUSSIAN, SKETCH_SPARSE, SKETCH_SPIXEL = 0, 1, 2
+SKETCH_GAUSSIAN, SKETCH_SPARSE, SKETCH_SPIXEL, SKETCH_SRFT = 0, 1, 2, 3
 PREC_FP32, PREC_BF16, PREC_FP8 = 0, 1, 2
 SEL_OMP, SEL_ZERO_MODE, SEL_OMEGA, SEL_EXPLICIT, SEL_ALL = 0, 1, 2, 3, 4
 AMP_FULL, AMP_COMPRESSED = 0, 1
@@ -37,7 +37,7 @@ EXPORTED = [
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_train_noalloc", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
     "cdmd_batch_free", "cdmd_optimal_rank", "cdmd_store_measurement", "cdmd_process_video",
-    "cdmd_video_create", "cdmd_video_run", "cdmd_video_free",
+    "cdmd_video_create", "cdmd_video_run", "cdmd_video_free", "cdmd_dbg_herm_topk", "cdmd_dbg_eig_complex",
 ]
 MLP_NPARAM = 4673
 
@@ -305,6 +305,7 @@ class Model:
         self.n, self.m, self.k, self.p = int(n), int(m), int(k), int(p)
         self.ld = int(ld if ld is not None else n)
         self.dtype = dtype
+        self.sketch_kind = sketch
         cfg = Config()
         cfg.n, cfg.m, cfg.ld, cfg.k, cfg.p = self.n, self.m, self.ld, self.k, self.p
         cfg.dtype, cfg.sketch, cfg.seed = dtype, sketch, seed
@@ -421,6 +422,11 @@ class Model:
         return cnt
 
     def sketch(self, integer: bool = False):
+        """The last fit's sketch Y^ (p x m): float64, complex128 for the SRFT sketch."""
+        if self.sketch_kind == SKETCH_SRFT:
+            Y = np.zeros(2 * self.m * self.p)
+            _check(load_library().cdmd_get_sketch(self._h, _dptr(Y), None))
+            return Y.view(np.complex128).reshape(self.m, self.p).T.copy()
         Y = np.zeros(self.m * self.p)
         Yi = np.zeros(self.m * self.p, dtype=np.int64) if integer else None
         _check(load_library().cdmd_get_sketch(

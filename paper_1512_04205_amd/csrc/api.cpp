@@ -90,6 +90,10 @@ struct cdmd_model {
   int32_t* d_Ypart = nullptr;
   double* d_Yd = nullptr;
   bool gauss = false;               // dense Gaussian sketch
+  bool srft = false;                // SRFT sketch: complex rows, (re, im) interleaved in d_Yd
+  int32_t* d_freq = nullptr;        // SRFT: the DFT row kept by each sketch row
+  double* d_gram_im = nullptr;      // SRFT: imaginary part of the Hermitian Gram
+  double* h_gram_im = nullptr;
   cdmd::k::GaussPlan gplan{};
   float* d_gpart = nullptr;         // per-slice partial sketches
   void* d_Cm = nullptr;             // the stored C (cdmd_store_measurement), or null: drawn
@@ -198,10 +202,10 @@ struct cdmd_model {
     void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart, d_Cm, d_chunk_off, d_rblk,
                    d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Rv, d_Gd, d_Vc, d_counts, d_modes,
                    d_feats, d_logits,
-                   d_la_scratch, d_la_out, d_py, d_pyred};
+                   d_la_scratch, d_la_out, d_py, d_pyred, d_freq, d_gram_im};
     for (void* q : dev)
       if (q) (void)hipFree(q);
-    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gd, h_Vc, h_counts, h_la_out, h_py};
+    void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gd, h_Vc, h_counts, h_la_out, h_py, h_gram_im};
     for (void* q : host)
       if (q) (void)hipHostFree(q);
   }
@@ -242,20 +246,22 @@ cdmd_status validate(const cdmd_config* c) {
   if (c->p < c->k) return fail(CDMD_E_INVALID_ARG, "need p >= k");
   if ((int64_t)c->k > c->m - 1) return fail(CDMD_E_INVALID_ARG, "need k <= m - 1");
   if (c->dtype != CDMD_U8 && c->dtype != CDMD_F32) return fail(CDMD_E_INVALID_ARG, "unknown dtype");
-  if (c->sketch < CDMD_SKETCH_GAUSSIAN || c->sketch > CDMD_SKETCH_SPIXEL)
+  if (c->sketch < CDMD_SKETCH_GAUSSIAN || c->sketch > CDMD_SKETCH_SRFT)
     return fail(CDMD_E_INVALID_ARG, "unknown sketch");
+  // single-pixel and SRFT: one distinct index per row (a pixel, or the DFT row kept by R)
+  const bool one_per_row = c->sketch == CDMD_SKETCH_SPIXEL || c->sketch == CDMD_SKETCH_SRFT;
   if (c->sketch_prec < CDMD_PREC_FP32 || c->sketch_prec > CDMD_PREC_FP8 ||
       c->lift_prec < CDMD_PREC_FP32 || c->lift_prec > CDMD_PREC_FP8)
     return fail(CDMD_E_INVALID_ARG, "unknown precision");
   if (c->lift_prec == CDMD_PREC_FP8)
     return fail(CDMD_E_INVALID_ARG, "FP8 is a sketch precision only");
-  if (c->sketch == CDMD_SKETCH_SPARSE || c->sketch == CDMD_SKETCH_SPIXEL) {
-    if (!c->sparse_idx) return fail(CDMD_E_INVALID_ARG, "sparse sketch needs sparse_idx");
+  if (c->sketch != CDMD_SKETCH_GAUSSIAN) {
+    if (!c->sparse_idx) return fail(CDMD_E_INVALID_ARG, "sparse, single-pixel and SRFT sketches need sparse_idx");
     if (c->nnz < 1 || c->nnz > 32) return fail(CDMD_E_INVALID_ARG, "nnz must be in [1, 32]");
-    if (c->sketch == CDMD_SKETCH_SPIXEL && c->nnz != 1)
-      return fail(CDMD_E_INVALID_ARG, "single-pixel sketch has nnz = 1");
-    if (c->sketch == CDMD_SKETCH_SPIXEL && (int64_t)c->p > c->n)
-      return fail(CDMD_E_INVALID_ARG, "single-pixel sketch needs p <= n");
+    if (one_per_row && c->nnz != 1)
+      return fail(CDMD_E_INVALID_ARG, "single-pixel and SRFT sketches have nnz = 1");
+    if (one_per_row && (int64_t)c->p > c->n)
+      return fail(CDMD_E_INVALID_ARG, "single-pixel and SRFT sketches need p <= n");
     if ((int64_t)c->nnz > c->n) return fail(CDMD_E_INVALID_ARG, "nnz must not exceed n");
   }
   if (c->k > kMaxRank) return fail(CDMD_E_UNSUPPORTED, "k > 40 is not built");
@@ -265,6 +271,10 @@ cdmd_status validate(const cdmd_config* c) {
       return fail(CDMD_E_UNSUPPORTED, "the BF16 / FP8 Gaussian sketch needs a uint8 video with ld % 16 == 0");
     if ((int64_t)c->p * c->m > ((int64_t)1 << 31))
       return fail(CDMD_E_UNSUPPORTED, "p * m >= 2^31 is not built");
+  } else if (c->sketch == CDMD_SKETCH_SRFT) {
+    if (c->sketch_prec != CDMD_PREC_FP32) return fail(CDMD_E_UNSUPPORTED, "the SRFT sketch has the FP32 form only");
+    if (2 * (int64_t)c->p * c->m > ((int64_t)1 << 31))
+      return fail(CDMD_E_UNSUPPORTED, "2 p * m >= 2^31 is not built");
   } else if (c->sketch_prec != CDMD_PREC_FP32) {
     return fail(CDMD_E_UNSUPPORTED, "sparse and single-pixel sketches are exact: sketch precision must be FP32");
   }
@@ -281,8 +291,8 @@ cdmd_status validate(const cdmd_config* c) {
         if (c->sparse_sign) {
           const int8_t sg = c->sparse_sign[r * z + j];
           if (sg != 1 && sg != -1) return fail(CDMD_E_INVALID_ARG, "sparse_sign must be +1 or -1");
-          if (c->sketch == CDMD_SKETCH_SPIXEL && sg != 1)
-            return fail(CDMD_E_INVALID_ARG, "single-pixel weights are +1");
+          if (one_per_row && sg != 1)
+            return fail(CDMD_E_INVALID_ARG, "single-pixel and SRFT weights are +1");
         }
         for (int64_t q = 0; q < j; ++q)
           if (c->sparse_idx[r * z + q] == v)
@@ -292,11 +302,11 @@ cdmd_status validate(const cdmd_config* c) {
     if (std::find_if(c->sparse_idx, c->sparse_idx + p * z, [](int32_t v) { return v >= 0; }) ==
         c->sparse_idx + p * z)
       return fail(CDMD_E_INVALID_ARG, "sparse table has no nonzeros");
-    if (c->sketch == CDMD_SKETCH_SPIXEL) {
+    if (one_per_row) {
       std::vector<int32_t> s(c->sparse_idx, c->sparse_idx + p);
       std::sort(s.begin(), s.end());
       if (std::adjacent_find(s.begin(), s.end()) != s.end())
-        return fail(CDMD_E_INVALID_ARG, "single-pixel rows must be distinct pixels");
+        return fail(CDMD_E_INVALID_ARG, "single-pixel and SRFT rows must be distinct indices");
     }
   }
   return CDMD_OK;
@@ -454,7 +464,12 @@ hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool to_host) {
   const cdmd_config& c = M->cfg;
   M->mark(0, st);
-  if (M->gauss) {
+  if (M->srft) {
+    HIPCHK(cdmd::k::sketch_srft(d_video, c.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p, c.seed, M->gplan,
+                                M->d_freq, M->d_gpart, M->d_Yd, st));
+    M->mark(1, st);
+    HIPCHK(cdmd::k::gram_cplx(M->d_Yd, M->p, M->m, M->d_gram, M->d_gram_im, st));
+  } else if (M->gauss) {
     if (c.sketch_prec != CDMD_PREC_FP32 && (reinterpret_cast<uintptr_t>(d_video) & 15) != 0)
       return fail(CDMD_E_UNSUPPORTED, "the BF16 / FP8 Gaussian sketch needs a 16-byte aligned video");
     HIPCHK(cdmd::k::sketch_gauss(d_video, c.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p, c.seed,
@@ -486,6 +501,8 @@ cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool 
   M->mark(2, st);
   if (!to_host) return CDMD_OK;
   HIPCHK(hipMemcpyAsync(M->h_gram, M->d_gram, sizeof(double) * M->m * M->m, hipMemcpyDeviceToHost, st));
+  if (M->srft)
+    HIPCHK(hipMemcpyAsync(M->h_gram_im, M->d_gram_im, sizeof(double) * M->m * M->m, hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   if (M->timing) {
     M->info.gpu_ms_sketch = M->span(0, 1);
@@ -494,8 +511,69 @@ cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool 
   return CDMD_OK;
 }
 
+// The same for the complex sketch of the SRFT: the Hermitian Gram Y^H Y (upper triangle as
+// computed, lower triangle its conjugate), its top-k eigenpairs by complex Lanczos (V
+// complex), A~ = S^-1 V^H (Y^H Y') V S^-1 complex, its eigenpairs by the complex Schur
+// form, G = V S^-1 W.
+cdmd_status small_la_complex(cdmd_model* M) {
+  const int N = M->N, k = M->k;
+  const int64_t m = M->m;
+  const double* Gr = M->h_gram;
+  const double* Gi = M->h_gram_im;
+  for (int64_t i = 0; i < m * m; ++i)
+    if (!std::isfinite(Gr[i]) || !std::isfinite(Gi[i])) return fail(CDMD_E_NUMERIC, "non-finite value in the sketch Gram");
+  auto g = [&](int64_t a, int64_t b) {
+    return a <= b ? cplx(Gr[a * m + b], Gi[a * m + b]) : std::conj(cplx(Gr[b * m + a], Gi[b * m + a]));
+  };
+  std::vector<cplx> M11((size_t)N * N);
+  for (int a = 0; a < N; ++a)
+    for (int b2 = 0; b2 < N; ++b2) M11[(size_t)a * N + b2] = g(a, b2);
+  std::vector<cplx> V((size_t)N * k);
+  std::vector<double> mu(k, 0.0);
+  const int J = cdmd::la::herm_topk(M11.data(), N, k, kLanczosTol, mu.data(), V.data());
+  if (J < 0) return fail(CDMD_E_NUMERIC, "Hermitian eigensolver failed");
+  M->info.lanczos_steps = J;
+  if (!(mu[0] > 0.0) || !(mu[k - 1] > kRankTol2 * mu[0]))
+    return fail(CDMD_E_RANK_DEFICIENT, "sigma_k <= 1e-6 sigma_1: target rank exceeds the numerical rank of Y");
+  std::vector<double> s(k);
+  for (int i = 0; i < k; ++i) s[i] = std::sqrt(mu[i]);
+  M->info.sigma_ratio = s[k - 1] / s[0];
+  M->sigma.resize(k);
+  for (int i = 0; i < k; ++i) M->sigma[i] = s[i] * M->sketch_scale;
+  std::vector<cplx> T((size_t)N * k);  // T = (Y^H Y') V, N x k
+  for (int a = 0; a < N; ++a)
+    for (int j = 0; j < k; ++j) {
+      const cplx* v = &V[(size_t)j * N];
+      cplx acc = 0.0;
+      for (int b2 = 0; b2 < N; ++b2) acc += g(a, b2 + 1) * v[b2];
+      T[(size_t)a * k + j] = acc;
+    }
+  std::vector<cplx> At((size_t)k * k);
+  for (int i = 0; i < k; ++i)
+    for (int j = 0; j < k; ++j) {
+      const cplx* v = &V[(size_t)i * N];
+      cplx acc = 0.0;
+      for (int a = 0; a < N; ++a) acc += std::conj(v[a]) * T[(size_t)a * k + j];
+      At[(size_t)i * k + j] = acc / (s[i] * s[j]);
+    }
+  M->lam.assign(k, 0.0);
+  M->W.assign((size_t)k * k, 0.0);
+  if (!cdmd::la::eig_complex(At.data(), k, M->lam.data(), M->W.data()))
+    return fail(CDMD_E_NUMERIC, "eigensolver of A~ failed");
+  normalise_columns(M->W, k);
+  M->G.assign((size_t)N * k, 0.0);
+  for (int t = 0; t < N; ++t)
+    for (int j = 0; j < k; ++j) {
+      cplx acc = 0.0;
+      for (int i = 0; i < k; ++i) acc += (V[(size_t)i * N + t] / M->sigma[i]) * M->W[(size_t)j * k + i];
+      M->G[(size_t)t * k + j] = acc;
+    }
+  return CDMD_OK;
+}
+
 // Truncated SVD (eq. svd), A~ and eig(A~) (Section 3.2) and G = V S^-1 W on the host in float64.
 cdmd_status small_la(cdmd_model* M, std::vector<double>& V, std::vector<double>& mu) {
+  if (M->srft) return small_la_complex(M);
   const int N = M->N, k = M->k;
   const int64_t m = M->m;
   const double* Gr = M->h_gram;
@@ -881,7 +959,18 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
   M->info.warn_few_samples =
       (double)cfg->p < (double)cfg->k * std::log((double)cfg->n / (double)cfg->k) ? 1 : 0;
   const int64_t m = M->m, p = M->p;
-  if (cfg->sketch == CDMD_SKETCH_GAUSSIAN) {
+  if (cfg->sketch == CDMD_SKETCH_SRFT) {
+    // 2p real rows: the real and imaginary parts of the p complex rows
+    M->srft = true;
+    M->gplan = cdmd::k::gauss_plan(M->n, m, 2 * (int)p, 0, 1024);
+    M->gpart_cap = (size_t)M->gplan.nsplit * m * 2 * p;
+    TRY(dalloc(&M->d_gpart, M->gpart_cap));
+    TRY(dalloc(&M->d_Yd, (size_t)m * 2 * p));
+    TRY(dalloc(&M->d_freq, (size_t)p));
+    HIPCHK(hipMemcpy(M->d_freq, cfg->sparse_idx, (size_t)p * 4, hipMemcpyHostToDevice));
+    TRY(dalloc(&M->d_gram_im, (size_t)m * m));
+    TRY(halloc(&M->h_gram_im, (size_t)m * m));
+  } else if (cfg->sketch == CDMD_SKETCH_GAUSSIAN) {
     M->gauss = true;
     M->gplan = cdmd::k::gauss_plan(M->n, m, (int)p, gauss_prec(*cfg), 1024);
     M->gpart_cap = (size_t)M->gplan.nsplit * m * p;
@@ -936,7 +1025,7 @@ cdmd_status cdmd_create(const cdmd_config* cfg, cdmd_model** out) {
     TRY(halloc(&M->h_Gd, (size_t)2 * M->N * M->k));
     M->lr_nb = (M->k + 1 + 31) / 32;
     M->lr_ne = M->lr_nb * (M->lr_nb + 1) / 2 * 16 * 64;
-    if (M->N <= 1024 && cfg->ld % 16 == 0) {
+    if (M->N <= 1024 && cfg->ld % 16 == 0 && !M->srft) {  // (the SRFT solve is complex, on the host)
       HIPCHK(hipStreamCreateWithFlags(&M->st2, hipStreamNonBlocking));
       HIPCHK(hipEventCreateWithFlags(&M->e_fork, hipEventDisableTiming));
       HIPCHK(hipEventCreateWithFlags(&M->e_join, hipEventDisableTiming));
@@ -1108,6 +1197,7 @@ cdmd_status post_fit(cdmd_model* M, double t0, double t1, double t2) {
 // Gram are used).
 static cdmd_status rank_with_model(cdmd_model* M, const void* d_video, hipStream_t st, int32_t* k_out,
                                    double* tau_out, double* sigma_out) {
+  if (M->srft) return fail(CDMD_E_UNSUPPORTED, "the automatic rank is built for real sketches");
   plan_fit(M, d_video);
   TRY(run_sketch(M, d_video, st, true));
   // the spectrum of Y = Y^[:, :m-1] from its Gram: sigma_i = scale sqrt(mu_i), the min(p, m-1)
@@ -1304,7 +1394,8 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
         if (ms < best) best = ms, ch.gauss_target = target;
       }
     }
-    if (!M->gauss && M->cfg.dtype == CDMD_U8 && M->ld % 16 == 0 && (reinterpret_cast<uintptr_t>(d_video) & 15) == 0) {
+    if (!M->gauss && !M->srft && M->cfg.dtype == CDMD_U8 && M->ld % 16 == 0 &&
+        (reinterpret_cast<uintptr_t>(d_video) & 15) == 0) {
       // sparse sketch: the gather form, or streaming with (frames per group, vectors per thread)
       double best = 1e300;
       const int forms[] = {-1, 41, 21, 22, 11, 12, 14};
@@ -1327,7 +1418,7 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
   ++M->stamp;
   M->info.lift_grid = M->lift_real ? M->lr_grid : M->lm_grid;
   M->info.sketch_slices = M->gauss ? M->gplan.nsplit : 0;
-  M->info.sparse_form = M->gauss ? 0 : (M->force_gather_sketch ? -1 : 10 * M->sk_F + M->sk_V);
+  M->info.sparse_form = M->gauss || M->srft ? 0 : (M->force_gather_sketch ? -1 : 10 * M->sk_F + M->sk_V);
   return CDMD_OK;
 }
 
@@ -1386,6 +1477,7 @@ cdmd_status cdmd_batch_create(cdmd_model* const* models, int32_t n, cdmd_batch**
       if (models[j] == models[i]) return fail(CDMD_E_INVALID_ARG, "a model appears twice in the batch");
     if (models[i]->amp_compressed)
       return fail(CDMD_E_UNSUPPORTED, "batches fit on the full modes (cdmd_set_amplitudes FULL)");
+    if (models[i]->srft) return fail(CDMD_E_UNSUPPORTED, "SRFT models are fitted one at a time");
   }
   std::unique_ptr<cdmd_batch> B(new (std::nothrow) cdmd_batch());
   if (!B) return fail(CDMD_E_OUT_OF_MEMORY, "host allocation failed");
@@ -1935,8 +2027,8 @@ cdmd_status cdmd_get_sketch(const cdmd_model* Mc, double* h_Y, int64_t* h_int) {
   if (!Mc) return fail(CDMD_E_INVALID_ARG, "NULL model");
   const cdmd_model* M = Mc;
   if (!M->fitted) return fail(CDMD_E_STATE, "model is not fitted");
-  const size_t cnt = (size_t)M->m * M->p;
-  if (M->cfg.dtype == CDMD_U8 && !M->gauss) {
+  const size_t cnt = (size_t)M->m * M->p * (M->srft ? 2 : 1);
+  if (M->cfg.dtype == CDMD_U8 && !M->gauss && !M->srft) {
     std::vector<int32_t> tmp(cnt);
     HIPCHK(hipMemcpy(tmp.data(), M->d_Yint, cnt * 4, hipMemcpyDeviceToHost));
     for (size_t i = 0; i < cnt; ++i) {
@@ -2307,7 +2399,8 @@ cdmd_status cdmd_dbg_force_gather_sketch(cdmd_model* M, int32_t on) {
 cdmd_status cdmd_dbg_sparse_form(cdmd_model* M, int32_t form) {
   g_err.clear();
   if (!M) return fail(CDMD_E_INVALID_ARG, "NULL model");
-  if (M->gauss || M->cfg.dtype != CDMD_U8) return fail(CDMD_E_UNSUPPORTED, "the form applies to uint8 sparse sketches");
+  if (M->gauss || M->srft || M->cfg.dtype != CDMD_U8)
+    return fail(CDMD_E_UNSUPPORTED, "the form applies to uint8 sparse sketches");
   if (form != -1) {
     const int F = form / 10, V = form % 10;
     if (form < 11 || !cdmd::k::sketch_stream_fits(F, V, M->max_rows))
@@ -2358,6 +2451,26 @@ cdmd_status cdmd_dbg_eig_general(const double* A, int32_t k, double* lam, double
   g_err.clear();
   if (!A || !lam || !W || k < 1) return fail(CDMD_E_INVALID_ARG, "bad arguments");
   if (!cdmd::la::eig_general(A, k, reinterpret_cast<cplx*>(lam), reinterpret_cast<cplx*>(W)))
+    return fail(CDMD_E_NUMERIC, "eigensolver failed");
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_herm_topk(const double* M, int32_t n, int32_t k, double rtol, double* evals,
+                               double* evecs, int32_t* steps) {
+  g_err.clear();
+  if (!M || !evals || !evecs || n < 1 || k < 1 || k > n) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  const int J = cdmd::la::herm_topk(reinterpret_cast<const cplx*>(M), n, k, rtol, evals,
+                                    reinterpret_cast<cplx*>(evecs));
+  if (J < 0) return fail(CDMD_E_NUMERIC, "Hermitian eigensolver failed");
+  if (steps) *steps = J;
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_dbg_eig_complex(const double* A, int32_t k, double* lam, double* W) {
+  g_err.clear();
+  if (!A || !lam || !W || k < 1) return fail(CDMD_E_INVALID_ARG, "bad arguments");
+  if (!cdmd::la::eig_complex(reinterpret_cast<const cplx*>(A), k, reinterpret_cast<cplx*>(lam),
+                             reinterpret_cast<cplx*>(W)))
     return fail(CDMD_E_NUMERIC, "eigensolver failed");
   return CDMD_OK;
 }

@@ -63,6 +63,13 @@ hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t
 // Row stride (entries) of a stored C for n pixels, and its fill: the entries of the BF16
 // (prec 1: bfloat16 bits) or FP8 (prec 2: e4m3 codes) form, p rows of ldc, zero past n.
 int64_t gauss_ldc(int64_t n);
+// SRFT sketch (the FP32 form's kernel with the entries of C = R F D): g = gauss_plan(n, m,
+// 2 p, FP32), freq[p] the DFT rows kept; Y (m x 2p float64, frame-major) holds the real and
+// imaginary part of each complex row r at 2r, 2r + 1, scaled by 1/sqrt(p).  gram_cplx: the
+// Hermitian Gram Y^H Y of that sketch, real part to Gr and imaginary part to Gi (m x m).
+hipError_t sketch_srft(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, int p, uint64_t seed,
+                       const GaussPlan& g, const int32_t* freq, float* part, double* Y, hipStream_t stream);
+hipError_t gram_cplx(const double* Y, int p, int64_t m, double* Gr, double* Gi, hipStream_t stream);
 hipError_t gauss_fill(void* Cm, int64_t ldc, int64_t n, int p, uint64_t seed, int prec, hipStream_t stream);
 
 // ----- learned selector (mlp.hip) -------------------------------------------------

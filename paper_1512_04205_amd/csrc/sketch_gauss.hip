@@ -51,8 +51,9 @@ struct Words4 {
   uint32_t w0, w1, w2, w3;
 };
 
-__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1) {
-  uint32_t c2 = 0u, c3 = 0u;
+__device__ __forceinline__ Words4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t k0, uint32_t k1,
+                                                uint32_t c3in = 0u) {
+  uint32_t c2 = 0u, c3 = c3in;
 #pragma unroll
   for (int rnd = 0; rnd < 10; ++rnd) {
     if (rnd) {
@@ -540,10 +541,17 @@ constexpr int GF_AS = 20;    // LDS row stride of the C tile (floats)
 // Each wave: 64 rows x 64 frames (16 accumulator blocks of 16 x 16); workgroup 256
 // frames.  K order inside a step: lane quarter q (= l / 16) reads pixels 4q .. 4q + 3 of
 // its frame; k-step ks takes pixel 4q + ks.  Tin: uint8 (raw 0..255) or float.
-template <typename Tin, bool VEC>
+// SRFT: the rows are the real and imaginary parts of the subsampled randomised Fourier
+// transform C = R F D (Section 3.3): row 2r + 0 / 1 holds the cosine / sine of the phase
+// 2 pi (u_j - (f_r j mod n) / n) of entry (r, j), with f_r = freq[r] the DFT row kept by R
+// and u_j the uniform of D's entry j: word j mod 4 of Philox4x32-10 on the counter
+// (j >> 2, 0, 0, 1) with the model's key, times 2^-32.  The phase is formed in float64
+// from the exact integer f_r j mod n and rounded once, as a cosine or sine, to float32.
+template <typename Tin, bool VEC, bool SRFT>
 __global__ __launch_bounds__(256) void k_sketch_gauss_f32(const Tin* __restrict__ D, int64_t ld,
                                                          int64_t n, int64_t m, int p, uint64_t seed,
                                                          int64_t pps, int nft, int nsplit,
+                                                         const int32_t* __restrict__ freq,
                                                          float* __restrict__ part) {
   constexpr int FRAMES = 256;
   __shared__ __attribute__((aligned(16))) float sA[2][GF_ROWS * GF_AS];
@@ -565,12 +573,30 @@ __global__ __launch_bounds__(256) void k_sketch_gauss_f32(const Tin* __restrict_
     const int64_t j = j0 + 4 * gg;
     float z[4] = {0.f, 0.f, 0.f, 0.f};
     if (grow < p && j < je) {
-      const Words4 wd = philox4x32_10((uint32_t)(j >> 2), (uint32_t)grow, k0, k1);
-      box_muller_f64(wd.w0, wd.w1, z[0], z[1]);
-      box_muller_f64(wd.w2, wd.w3, z[2], z[3]);
+      if constexpr (SRFT) {
+        const Words4 wd = philox4x32_10((uint32_t)(j >> 2), 0u, k0, k1, 1u);
+        const uint32_t wv[4] = {wd.w0, wd.w1, wd.w2, wd.w3};
+        const int64_t f = freq[grow >> 1];
+        int64_t q = (f * j) % n;  // j is a multiple of 4: entry e is pixel j + e, word e
 #pragma unroll
-      for (int e = 0; e < 4; ++e)
-        if (j + e >= je) z[e] = 0.f;
+        for (int e = 0; e < 4; ++e) {
+          if (j + e < je) {
+            const double frac = (double)wv[e] * 0x1p-32 - (double)q / (double)n;
+            double sv, cv;
+            sincospi(2.0 * frac, &sv, &cv);
+            z[e] = (float)((grow & 1) ? sv : cv);
+          }
+          q += f;
+          if (q >= n) q -= n;
+        }
+      } else {
+        const Words4 wd = philox4x32_10((uint32_t)(j >> 2), (uint32_t)grow, k0, k1);
+        box_muller_f64(wd.w0, wd.w1, z[0], z[1]);
+        box_muller_f64(wd.w2, wd.w3, z[2], z[3]);
+#pragma unroll
+        for (int e = 0; e < 4; ++e)
+          if (j + e >= je) z[e] = 0.f;
+      }
     }
     *reinterpret_cast<float4*>(&sA[buf][gr * GF_AS + 4 * gg]) = make_float4(z[0], z[1], z[2], z[3]);
   };
@@ -667,6 +693,42 @@ __global__ __launch_bounds__(256) void k_reduce_gauss(const float* __restrict__ 
   }
 }
 
+// G[a][b] = sum_r conj(Y[a][r]) Y[b][r] over the complex rows of an SRFT sketch stored
+// with interleaved (re, im) rows per frame (Y[t][2r], Y[t][2r + 1]): real part to Gr,
+// imaginary part to Gi, float64.  A workgroup owns a 16 x 16 tile of (a, b) and steps
+// through 16 complex rows at a time in LDS.
+__global__ __launch_bounds__(256) void k_gram_cplx(const double* __restrict__ Y, int p, int64_t m,
+                                                  double* __restrict__ Gr, double* __restrict__ Gi) {
+  __shared__ double sa[16][33], sb[16][33];
+  const int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+  const int64_t a0 = (int64_t)blockIdx.y * 16, b0 = (int64_t)blockIdx.x * 16;
+  const int64_t P2 = 2 * (int64_t)p;
+  double re = 0.0, im = 0.0;
+  for (int64_t r0 = 0; r0 < P2; r0 += 32) {
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int64_t col = r0 + tx + 16 * h;
+      const int64_t fa = a0 + ty, fb = b0 + ty;
+      sa[ty][tx + 16 * h] = (fa < m && col < P2) ? Y[fa * P2 + col] : 0.0;
+      sb[ty][tx + 16 * h] = (fb < m && col < P2) ? Y[fb * P2 + col] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const double ar = sa[ty][2 * c], ai = sa[ty][2 * c + 1];
+      const double br = sb[tx][2 * c], bi = sb[tx][2 * c + 1];
+      re += ar * br + ai * bi;
+      im += ar * bi - ai * br;
+    }
+    __syncthreads();
+  }
+  const int64_t a = a0 + ty, b = b0 + tx;
+  if (a < m && b < m) {
+    Gr[a * m + b] = re;
+    Gi[a * m + b] = im;
+  }
+}
+
 }  // namespace
 
 GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target) {
@@ -753,16 +815,20 @@ hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t
     const uint8_t* d = static_cast<const uint8_t*>(D);
     const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 3) == 0;
     if (vec)
-      hipLaunchKernelGGL((k_sketch_gauss_f32<uint8_t, true>), grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+      hipLaunchKernelGGL((k_sketch_gauss_f32<uint8_t, true, false>), grid, block, 0, stream, d, ld, n, m, p, seed,
+                         g.pps, g.nft, g.nsplit, nullptr, part);
     else
-      hipLaunchKernelGGL((k_sketch_gauss_f32<uint8_t, false>), grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+      hipLaunchKernelGGL((k_sketch_gauss_f32<uint8_t, false, false>), grid, block, 0, stream, d, ld, n, m, p, seed,
+                         g.pps, g.nft, g.nsplit, nullptr, part);
   } else {
     const float* d = static_cast<const float*>(D);
     const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
     if (vec)
-      hipLaunchKernelGGL((k_sketch_gauss_f32<float, true>), grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+      hipLaunchKernelGGL((k_sketch_gauss_f32<float, true, false>), grid, block, 0, stream, d, ld, n, m, p, seed,
+                         g.pps, g.nft, g.nsplit, nullptr, part);
     else
-      hipLaunchKernelGGL((k_sketch_gauss_f32<float, false>), grid, block, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft, g.nsplit, part);
+      hipLaunchKernelGGL((k_sketch_gauss_f32<float, false, false>), grid, block, 0, stream, d, ld, n, m, p, seed,
+                         g.pps, g.nft, g.nsplit, nullptr, part);
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
@@ -771,6 +837,46 @@ hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t
   if (nb > 4096) nb = 4096;
   hipLaunchKernelGGL(k_reduce_gauss, dim3((unsigned)nb), dim3(256), 0, stream, part, g.nsplit, count,
                      1.0 / sqrt((double)p), Y);
+  return hipGetLastError();
+}
+
+hipError_t sketch_srft(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, int p, uint64_t seed,
+                       const GaussPlan& g, const int32_t* freq, float* part, double* Y, hipStream_t stream) {
+  // g: gauss_plan(n, m, 2 p, FP32); Y: m x 2p, frame-major, (re, im) interleaved
+  const dim3 grid((unsigned)g.blocks), block(256);
+  const int p2 = 2 * p;
+  if (dtype == 0) {
+    const uint8_t* d = static_cast<const uint8_t*>(D);
+    const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 3) == 0;
+    if (vec)
+      hipLaunchKernelGGL((k_sketch_gauss_f32<uint8_t, true, true>), grid, block, 0, stream, d, ld, n, m, p2, seed,
+                         g.pps, g.nft, g.nsplit, freq, part);
+    else
+      hipLaunchKernelGGL((k_sketch_gauss_f32<uint8_t, false, true>), grid, block, 0, stream, d, ld, n, m, p2, seed,
+                         g.pps, g.nft, g.nsplit, freq, part);
+  } else {
+    const float* d = static_cast<const float*>(D);
+    const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 15) == 0;
+    if (vec)
+      hipLaunchKernelGGL((k_sketch_gauss_f32<float, true, true>), grid, block, 0, stream, d, ld, n, m, p2, seed,
+                         g.pps, g.nft, g.nsplit, freq, part);
+    else
+      hipLaunchKernelGGL((k_sketch_gauss_f32<float, false, true>), grid, block, 0, stream, d, ld, n, m, p2, seed,
+                         g.pps, g.nft, g.nsplit, freq, part);
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const int64_t count = m * (int64_t)p2;
+  int64_t nb = (count + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_reduce_gauss, dim3((unsigned)nb), dim3(256), 0, stream, part, g.nsplit, count,
+                     1.0 / sqrt((double)p), Y);
+  return hipGetLastError();
+}
+
+hipError_t gram_cplx(const double* Y, int p, int64_t m, double* Gr, double* Gi, hipStream_t stream) {
+  const unsigned t = (unsigned)((m + 15) / 16);
+  hipLaunchKernelGGL(k_gram_cplx, dim3(t, t), dim3(256), 0, stream, Y, p, m, Gr, Gi);
   return hipGetLastError();
 }
 

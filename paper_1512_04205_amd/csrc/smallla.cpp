@@ -86,28 +86,59 @@ bool tridiag_eig(double* d, double* e, int n, double* Z, int R, int row0) {
 
 // ---------------------------------------------------------------------------
 // Lanczos with full reorthogonalisation for the top-k eigenpairs.
-int sym_topk(const double* M, int n, int k, double rtol, double* evals, double* evecs) {
+// Conjugate-linear and plain inner products; for double both are `dot`.
+static inline double dotc(const double* a, const double* b, int n) { return dot(a, b, n); }
+static inline double dotu(const double* a, const double* b, int n) { return dot(a, b, n); }
+static inline cplx dotc(const cplx* a, const cplx* b, int n) {
+  cplx s0 = 0.0, s1 = 0.0;
+  int i = 0;
+  for (; i + 2 <= n; i += 2) {
+    s0 += std::conj(a[i]) * b[i];
+    s1 += std::conj(a[i + 1]) * b[i + 1];
+  }
+  for (; i < n; ++i) s0 += std::conj(a[i]) * b[i];
+  return s0 + s1;
+}
+static inline cplx dotu(const cplx* a, const cplx* b, int n) {
+  cplx s0 = 0.0, s1 = 0.0;
+  int i = 0;
+  for (; i + 2 <= n; i += 2) {
+    s0 += a[i] * b[i];
+    s1 += a[i + 1] * b[i + 1];
+  }
+  for (; i < n; ++i) s0 += a[i] * b[i];
+  return s0 + s1;
+}
+static inline double re(double x) { return x; }
+static inline double re(cplx z) { return z.real(); }
+
+// Lanczos with full reorthogonalisation for a real symmetric (T = double) or complex
+// Hermitian (T = cplx) matrix: alpha_j = q_j^H M q_j is real and beta_j = |w| >= 0, so the
+// projected matrix is the same real symmetric tridiagonal in both cases.
+template <typename T>
+static int topk_lanczos(const T* M, int n, int k, double rtol, double* evals, T* evecs) {
   if (k < 1 || k > n || n < 1) return -1;
-  std::vector<double> Q((size_t)n * (n + 1), 0.0);
-  std::vector<double> alpha(n + 1, 0.0), beta(n + 1, 0.0), w(n), h(n + 1);
-  auto newvec = [&](double* q, int salt) {
-    for (int i = 0; i < n; ++i) q[i] = 1.0 + 0.25 * std::sin(0.7 * (i + 1) + 1.3 * salt);
+  std::vector<T> Q((size_t)n * (n + 1), T(0.0));
+  std::vector<double> alpha(n + 1, 0.0), beta(n + 1, 0.0);
+  std::vector<T> w(n), h(n + 1);
+  auto newvec = [&](T* q, int salt) {
+    for (int i = 0; i < n; ++i) q[i] = T(1.0 + 0.25 * std::sin(0.7 * (i + 1) + 1.3 * salt));
   };
-  auto orth = [&](double* v, int J) -> double {  // twice CGS against Q[0..J)
+  auto orth = [&](T* v, int J) -> double {  // twice CGS against Q[0..J)
     for (int pass = 0; pass < 2; ++pass) {
-      for (int i = 0; i < J; ++i) h[i] = dot(&Q[(size_t)i * n], v, n);
+      for (int i = 0; i < J; ++i) h[i] = dotc(&Q[(size_t)i * n], v, n);
       for (int i = 0; i < J; ++i) {
-        const double* qi = &Q[(size_t)i * n];
-        const double hi = h[i];
+        const T* qi = &Q[(size_t)i * n];
+        const T hi = h[i];
         for (int t = 0; t < n; ++t) v[t] -= hi * qi[t];
       }
     }
-    return std::sqrt(dot(v, v, n));
+    return std::sqrt(re(dotc(v, v, n)));
   };
   {
-    double* q0 = Q.data();
+    T* q0 = Q.data();
     newvec(q0, 0);
-    const double nr = std::sqrt(dot(q0, q0, n));
+    const double nr = std::sqrt(re(dotc(q0, q0, n)));
     for (int i = 0; i < n; ++i) q0[i] /= nr;
   }
   double anorm = 0.0;
@@ -117,21 +148,21 @@ int sym_topk(const double* M, int n, int k, double rtol, double* evals, double* 
   std::vector<int> idx;
   int restarts = 0;
   for (int j = 0; j < n; ++j) {
-    const double* qj = &Q[(size_t)j * n];
-    for (int i = 0; i < n; ++i) w[i] = dot(M + (size_t)i * n, qj, n);
+    const T* qj = &Q[(size_t)j * n];
+    for (int i = 0; i < n; ++i) w[i] = dotu(M + (size_t)i * n, qj, n);
     // projections on all previous vectors, twice; alpha_j is the q_j component
     double aj = 0.0;
     for (int pass = 0; pass < 2; ++pass) {
-      for (int i = 0; i <= j; ++i) h[i] = dot(&Q[(size_t)i * n], w.data(), n);
-      aj += h[j];
+      for (int i = 0; i <= j; ++i) h[i] = dotc(&Q[(size_t)i * n], w.data(), n);
+      aj += re(h[j]);
       for (int i = 0; i <= j; ++i) {
-        const double* qi = &Q[(size_t)i * n];
-        const double hi = h[i];
+        const T* qi = &Q[(size_t)i * n];
+        const T hi = h[i];
         for (int t = 0; t < n; ++t) w[t] -= hi * qi[t];
       }
     }
     alpha[j] = aj;
-    beta[j] = std::sqrt(dot(w.data(), w.data(), n));
+    beta[j] = std::sqrt(re(dotc(w.data(), w.data(), n)));
     J = j + 1;
     anorm = std::max(anorm, std::fabs(alpha[j]) + beta[j] + (j ? beta[j - 1] : 0.0));
     const bool breakdown = beta[j] <= 64.0 * DBL_EPSILON * anorm;
@@ -153,7 +184,7 @@ int sym_topk(const double* M, int n, int k, double rtol, double* evals, double* 
       if (breakdown) {
         // invariant subspace smaller than k: continue from a fresh orthogonal vector
         if (++restarts > 8) return -1;
-        double* qn = &Q[(size_t)J * n];
+        T* qn = &Q[(size_t)J * n];
         newvec(qn, J + 17 * restarts);
         const double nr = orth(qn, J);
         if (nr <= 1e-8) return -1;
@@ -164,7 +195,7 @@ int sym_topk(const double* M, int n, int k, double rtol, double* evals, double* 
       }
       next_check = std::min(n, J + std::max(16, J / 4));
     }
-    double* qn = &Q[(size_t)J * n];
+    T* qn = &Q[(size_t)J * n];
     const double inv = 1.0 / beta[j];
     for (int i = 0; i < n; ++i) qn[i] = w[i] * inv;
   }
@@ -180,17 +211,170 @@ int sym_topk(const double* M, int n, int k, double rtol, double* evals, double* 
   for (int c = 0; c < k; ++c) {
     const int col = idx[c];
     evals[c] = dd[col];
-    double* v = evecs + (size_t)c * n;
-    std::fill(v, v + n, 0.0);
+    T* v = evecs + (size_t)c * n;
+    std::fill(v, v + n, T(0.0));
     for (int i = 0; i < J; ++i) {
       const double zi = Z[(size_t)i * J + col];
-      const double* qi = &Q[(size_t)i * n];
+      const T* qi = &Q[(size_t)i * n];
       for (int t = 0; t < n; ++t) v[t] += zi * qi[t];
     }
-    const double nr = std::sqrt(dot(v, v, n));
+    const double nr = std::sqrt(re(dotc(v, v, n)));
     for (int t = 0; t < n; ++t) v[t] /= nr;
   }
   return J;
+}
+
+int sym_topk(const double* M, int n, int k, double rtol, double* evals, double* evecs) {
+  return topk_lanczos<double>(M, n, k, rtol, evals, evecs);
+}
+
+int herm_topk(const cplx* M, int n, int k, double rtol, double* evals, cplx* evecs) {
+  return topk_lanczos<cplx>(M, n, k, rtol, evals, evecs);
+}
+
+// ---------------------------------------------------------------------------
+// General complex eigenproblem: Hessenberg reduction by Householder reflections, then
+// shifted QR with Givens rotations (Wilkinson shift of the trailing 2x2 block, an
+// exceptional shift after 10 and 20 steps without deflation) to upper triangular Schur
+// form T = Z^H A Z; eigenvectors of T by back substitution, W = Z x.
+bool eig_complex(const cplx* A, int k, cplx* lam, cplx* W) {
+  if (k < 1) return false;
+  std::vector<cplx> H(A, A + (size_t)k * k), Z((size_t)k * k, cplx(0.0));
+  for (int i = 0; i < k; ++i) Z[(size_t)i * k + i] = 1.0;
+  for (size_t e = 0; e < H.size(); ++e)
+    if (!std::isfinite(H[e].real()) || !std::isfinite(H[e].imag())) return false;
+  auto h = [&](int i, int j) -> cplx& { return H[(size_t)i * k + j]; };
+  auto z = [&](int i, int j) -> cplx& { return Z[(size_t)i * k + j]; };
+  // Hessenberg: P = I - 2 v v^H on rows / columns c+1..k-1
+  std::vector<cplx> v(k);
+  for (int c = 0; c + 2 < k; ++c) {
+    const int len = k - c - 1;
+    double xn = 0.0;
+    for (int i = 0; i < len; ++i) xn += std::norm(h(c + 1 + i, c));
+    xn = std::sqrt(xn);
+    if (xn == 0.0) continue;
+    const cplx x0 = h(c + 1, c);
+    const cplx ph = std::abs(x0) > 0.0 ? x0 / std::abs(x0) : cplx(1.0);
+    const cplx alpha = -ph * xn;
+    for (int i = 0; i < len; ++i) v[i] = h(c + 1 + i, c);
+    v[0] -= alpha;
+    double vn = 0.0;
+    for (int i = 0; i < len; ++i) vn += std::norm(v[i]);
+    vn = std::sqrt(vn);
+    if (vn == 0.0) continue;
+    for (int i = 0; i < len; ++i) v[i] /= vn;
+    for (int j = 0; j < k; ++j) {  // left: rows c+1..
+      cplx s = 0.0;
+      for (int i = 0; i < len; ++i) s += std::conj(v[i]) * h(c + 1 + i, j);
+      for (int i = 0; i < len; ++i) h(c + 1 + i, j) -= 2.0 * v[i] * s;
+    }
+    for (int i = 0; i < k; ++i) {  // right: columns c+1.. of H and Z
+      cplx s = 0.0, t = 0.0;
+      for (int l = 0; l < len; ++l) {
+        s += h(i, c + 1 + l) * v[l];
+        t += z(i, c + 1 + l) * v[l];
+      }
+      for (int l = 0; l < len; ++l) {
+        h(i, c + 1 + l) -= 2.0 * s * std::conj(v[l]);
+        z(i, c + 1 + l) -= 2.0 * t * std::conj(v[l]);
+      }
+    }
+    for (int i = 1; i < len; ++i) h(c + 1 + i, c) = 0.0;
+  }
+  // shifted QR on the active window [lo, hi]
+  std::vector<cplx> gc(k), gs(k);
+  int hi = k - 1, iter = 0, total = 0;
+  while (hi > 0) {
+    int l = hi;
+    for (; l > 0; --l) {
+      const double tol = DBL_EPSILON * (std::abs(h(l, l)) + std::abs(h(l - 1, l - 1)));
+      if (std::abs(h(l, l - 1)) <= tol) {
+        h(l, l - 1) = 0.0;
+        break;
+      }
+    }
+    if (l == hi) {
+      --hi;
+      iter = 0;
+      continue;
+    }
+    if (++total > 60 * k) return false;
+    ++iter;
+    cplx mu;
+    if (iter % 10 == 0) {
+      mu = h(hi, hi) + std::abs(h(hi, hi - 1)) * 0.75;  // exceptional shift
+    } else {
+      const cplx a = h(hi - 1, hi - 1), b = h(hi - 1, hi), c = h(hi, hi - 1), d = h(hi, hi);
+      const cplx half = 0.5 * (a - d);
+      const cplx disc = std::sqrt(half * half + b * c);
+      const cplx m1 = 0.5 * (a + d) + disc, m2 = 0.5 * (a + d) - disc;
+      mu = std::abs(m1 - d) < std::abs(m2 - d) ? m1 : m2;
+    }
+    for (int i = l; i <= hi; ++i) h(i, i) -= mu;
+    // H - mu I = Q R: rotations R_i = [[conj c, conj s], [-s, c]] on rows i, i+1
+    for (int i = l; i < hi; ++i) {
+      const cplx x = h(i, i), y = h(i + 1, i);
+      const double r = std::hypot(std::abs(x), std::abs(y));
+      cplx c = 1.0, s = 0.0;
+      if (r > 0.0) {
+        c = x / r;
+        s = y / r;
+      }
+      gc[i] = c;
+      gs[i] = s;
+      for (int j = i; j < k; ++j) {
+        const cplx u = h(i, j), w2 = h(i + 1, j);
+        h(i, j) = std::conj(c) * u + std::conj(s) * w2;
+        h(i + 1, j) = -s * u + c * w2;
+      }
+      h(i + 1, i) = 0.0;
+    }
+    // R Q + mu I: columns i, i+1 times R_i^H = [[c, -conj s], [s, conj c]]
+    for (int i = l; i < hi; ++i) {
+      const cplx c = gc[i], s = gs[i];
+      const int rmax = std::min(i + 1, hi);
+      for (int r = 0; r <= rmax; ++r) {
+        const cplx u = h(r, i), w2 = h(r, i + 1);
+        h(r, i) = u * c + w2 * s;
+        h(r, i + 1) = -u * std::conj(s) + w2 * std::conj(c);
+      }
+      for (int r = 0; r < k; ++r) {
+        const cplx u = z(r, i), w2 = z(r, i + 1);
+        z(r, i) = u * c + w2 * s;
+        z(r, i + 1) = -u * std::conj(s) + w2 * std::conj(c);
+      }
+    }
+    for (int i = l; i <= hi; ++i) h(i, i) += mu;
+  }
+  double tn = 0.0;
+  for (int i = 0; i < k; ++i)
+    for (int j = i; j < k; ++j) tn = std::max(tn, std::abs(h(i, j)));
+  const double small = DBL_EPSILON * std::max(tn, DBL_MIN);
+  std::vector<cplx> x(k);
+  for (int j = 0; j < k; ++j) {
+    lam[j] = h(j, j);
+    std::fill(x.begin(), x.end(), cplx(0.0));
+    x[j] = 1.0;
+    for (int i = j - 1; i >= 0; --i) {
+      cplx s = 0.0;
+      for (int l2 = i + 1; l2 <= j; ++l2) s += h(i, l2) * x[l2];
+      cplx den = h(i, i) - lam[j];
+      if (std::abs(den) < small) den = small;
+      x[i] = -s / den;
+    }
+    double nr = 0.0;
+    cplx* wj = W + (size_t)j * k;
+    for (int r = 0; r < k; ++r) {
+      cplx acc = 0.0;
+      for (int l2 = 0; l2 <= j; ++l2) acc += z(r, l2) * x[l2];
+      wj[r] = acc;
+      nr += std::norm(acc);
+    }
+    nr = std::sqrt(nr);
+    if (!(nr > 0.0) || !std::isfinite(nr)) return false;
+    for (int r = 0; r < k; ++r) wj[r] /= nr;
+  }
+  return true;
 }
 
 // ---------------------------------------------------------------------------

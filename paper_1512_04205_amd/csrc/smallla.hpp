@@ -32,6 +32,15 @@ bool tridiag_eig(double* d, double* e, int n, double* Z, int R, int row0);
 // Returns the Krylov dimension used, or -1 on failure.
 int sym_topk(const double* M, int n, int k, double rtol, double* evals, double* evecs);
 
+// The same for a complex Hermitian n x n matrix M (row-major): complex Lanczos vectors,
+// a real symmetric tridiagonal projection.  evecs n x k column-major.
+int herm_topk(const cplx* M, int n, int k, double rtol, double* evals, cplx* evecs);
+
+// Eigenvalues and unit eigenvectors of a complex general k x k matrix A (row-major):
+// Householder reduction to Hessenberg form, shifted QR to triangular Schur form, back
+// substitution for the eigenvectors.  W is k x k column-major.  False on failure.
+bool eig_complex(const cplx* A, int k, cplx* lam, cplx* W);
+
 // Eigenvalues and unit eigenvectors of a real general k x k matrix A (row-major):
 // Householder reduction to Hessenberg form, Francis double-shift QR to real Schur form
 // (conjugate pairs from 2x2 blocks are exact conjugates), then inverse iteration on

@@ -75,6 +75,10 @@ PRESETS = {
     "ctxA": VideoSpec(H=720, W=1280, m=200, n_pairs=8, bump_sigma=48.0, n_rects=12,
                       rect_side=(27, 80), rect_value=(0.6, 1.0), speed=(1.3, 4.0),
                       noise_sigma=2.0 / 255.0, out="u8", seed=1006),
+    # 720x480x200 uint8: the shape of the sensing-matrix comparison (fps and F-measure vs p)
+    "ctxB": VideoSpec(H=480, W=720, m=200, n_pairs=6, bump_sigma=32.0, n_rects=8,
+                      rect_side=(18, 54), rect_value=(0.6, 1.0), speed=(1.0, 3.0),
+                      noise_sigma=2.0 / 255.0, out="u8", seed=1007),
     # 640x480x300 uint8 (learned-selector training shape)
     "train640": VideoSpec(H=480, W=640, m=300, n_pairs=5, bump_sigma=24.0, n_rects=8,
                           rect_side=(13, 40), rect_value=(0.6, 1.0), speed=(1.0, 3.0),

@@ -27,6 +27,8 @@ def _lib():
     lib = P.load_library()
     lib.cdmd_dbg_sym_topk.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, DP, DP, IP]
     lib.cdmd_dbg_eig_general.argtypes = [DP, ctypes.c_int32, DP, DP]
+    lib.cdmd_dbg_herm_topk.argtypes = [DP, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, DP, DP, IP]
+    lib.cdmd_dbg_eig_complex.argtypes = [DP, ctypes.c_int32, DP, DP]
     lib.cdmd_dbg_omp_gram.argtypes = [DP, ctypes.c_int32, DP, ctypes.c_double, ctypes.c_int32, DP,
                                       IP, DP, IP, DP]
     return lib
@@ -189,6 +191,103 @@ def test_general_eig_rotation_block():
     got = np.sort_complex(lam[0::2] + 1j * lam[1::2])
     np.testing.assert_allclose(got, np.sort_complex(np.array([0.5, np.exp(1j * th), np.exp(-1j * th)])),
                                atol=1e-14)
+
+
+def test_srft_config_checks():
+    """The SRFT configuration is checked on the host: FP32 form only, p distinct DFT rows
+    in [0, n), weights +1, nnz = 1."""
+    n, m, p = 2000, 20, 30
+    fr = np.random.default_rng(1).choice(n, size=p, replace=False).astype(np.int32).reshape(p, 1)
+    for kw, status in ((dict(sketch_prec=P.PREC_BF16), P.E_UNSUPPORTED),
+                       (dict(idx=np.concatenate([fr[:-1], fr[:1]])), P.E_INVALID_ARG),
+                       (dict(idx=np.full((p, 1), n, dtype=np.int32)), P.E_INVALID_ARG),
+                       (dict(idx=np.concatenate([fr, fr], axis=1)), P.E_INVALID_ARG),
+                       (dict(sign=-np.ones((p, 1), dtype=np.int8)), P.E_INVALID_ARG),
+                       (dict(idx=None), P.E_INVALID_ARG)):
+        args = dict(sketch=P.SKETCH_SRFT, idx=fr, seed=1)
+        args.update(kw)
+        with pytest.raises(P.CdmdError) as e:
+            P.Model(n, m, 3, p, **args)
+        assert e.value.status == status, kw
+
+
+def _cx(a):
+    """complex128 array -> contiguous float64 view with re/im interleaved"""
+    return np.ascontiguousarray(a, dtype=np.complex128).view(np.float64)
+
+
+@pytest.mark.parametrize("n,k", [(5, 2), (60, 10), (199, 25), (300, 40)])
+def test_hermitian_topk_vs_lapack(n, k):
+    """Complex Lanczos (the SVD route of a complex sketch) against LAPACK's eigh."""
+    lib = _lib()
+    rng = np.random.default_rng(n + 7)
+    Y = (rng.normal(size=(3 * n, n)) + 1j * rng.normal(size=(3 * n, n))) * np.logspace(0, -3, n)[None, :]
+    M = Y.conj().T @ Y
+    ev, V, st = np.zeros(k), np.zeros(2 * k * n), ctypes.c_int32(0)
+    assert lib.cdmd_dbg_herm_topk(_p(_cx(M)), n, k, 1e-13, _p(ev), _p(V), ctypes.byref(st)) == 0
+    w, U = np.linalg.eigh(M)
+    w, U = w[::-1][:k], U[:, ::-1][:, :k]
+    np.testing.assert_allclose(ev, w, rtol=1e-12, atol=1e-13 * w[0])
+    V = (V[0::2] + 1j * V[1::2]).reshape(k, n).T
+    for j in range(k):
+        # the same unit vector up to a unit complex factor
+        assert abs(abs(np.vdot(U[:, j], V[:, j])) - 1) < 1e-9
+        assert np.linalg.norm(M @ V[:, j] - ev[j] * V[:, j]) < 1e-10 * w[0]
+
+
+def test_hermitian_topk_real_matrix_equals_symmetric_route():
+    """On a real symmetric matrix the complex route returns the real route's eigenvalues."""
+    lib = _lib()
+    rng = np.random.default_rng(5)
+    Y = rng.normal(size=(90, 40)) * np.logspace(0, -2, 40)[None, :]
+    M = np.ascontiguousarray(Y.T @ Y)
+    k = 8
+    e1, V1, st = np.zeros(k), np.zeros(k * 40), ctypes.c_int32(0)
+    assert lib.cdmd_dbg_sym_topk(_p(M), 40, k, 1e-13, _p(e1), _p(V1), ctypes.byref(st)) == 0
+    e2, V2 = np.zeros(k), np.zeros(2 * k * 40)
+    assert lib.cdmd_dbg_herm_topk(_p(_cx(M)), 40, k, 1e-13, _p(e2), _p(V2), ctypes.byref(st)) == 0
+    np.testing.assert_allclose(e2, e1, rtol=1e-13)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 7, 25, 40])
+def test_complex_eig_vs_lapack(k):
+    """The complex eigensolver (A~ of a complex sketch) against LAPACK's eig: eigenvalues
+    matched one to one, and residuals of the unit eigenvectors."""
+    lib = _lib()
+    rng = np.random.default_rng(100 + k)
+    A = rng.normal(size=(k, k)) + 1j * rng.normal(size=(k, k))
+    lam, W = np.zeros(2 * k), np.zeros(2 * k * k)
+    assert lib.cdmd_dbg_eig_complex(_p(_cx(A)), k, _p(lam), _p(W)) == 0
+    lam = lam[0::2] + 1j * lam[1::2]
+    W = (W[0::2] + 1j * W[1::2]).reshape(k, k).T
+    ref = np.linalg.eigvals(A)
+    from scipy.optimize import linear_sum_assignment
+    C = np.abs(lam[:, None] - ref[None, :])
+    r, c = linear_sum_assignment(C)
+    assert C[r, c].max() < 1e-12 * max(1, np.abs(ref).max())
+    np.testing.assert_allclose(np.linalg.norm(W, axis=0), 1.0, rtol=1e-13)
+    assert np.linalg.norm(A @ W - W * lam[None, :], axis=0).max() < 1e-11 * max(1, np.abs(ref).max())
+
+
+def test_complex_eig_near_conjugate_spectrum():
+    """A complex matrix whose eigenvalues come in nearly conjugate pairs (what a complex
+    sketch of real dynamics gives): every eigenvalue is found, none twice."""
+    lib = _lib()
+    rng = np.random.default_rng(9)
+    k = 12
+    th = rng.uniform(0.05, 1.0, size=k // 2)
+    ev = np.concatenate([np.exp(1j * th), np.exp(-1j * th) * (1 + 1e-7)])
+    S = rng.normal(size=(k, k)) + 1j * rng.normal(size=(k, k))
+    A = S @ np.diag(ev) @ np.linalg.inv(S)
+    lam, W = np.zeros(2 * k), np.zeros(2 * k * k)
+    assert lib.cdmd_dbg_eig_complex(_p(_cx(A)), k, _p(lam), _p(W)) == 0
+    lam = lam[0::2] + 1j * lam[1::2]
+    from scipy.optimize import linear_sum_assignment
+    C = np.abs(lam[:, None] - ev[None, :])
+    r, c = linear_sum_assignment(C)
+    assert C[r, c].max() < 1e-9
+    W = (W[0::2] + 1j * W[1::2]).reshape(k, k).T
+    assert np.linalg.norm(A @ W - W * lam[None, :], axis=0).max() < 1e-9
 
 
 @pytest.mark.parametrize("seed,K", [(1, 1), (2, 4), (3, 8), (4, 30)])

@@ -1,0 +1,132 @@
+"""The SRFT measurement matrix C = R F D / sqrt(p) (Section 3.3) on the GPU against the
+FP64 oracle, through the C ABI.
+
+The device draws D's phases from the counter-based definition both sides implement
+(Philox4x32-10 on (j >> 2, 0, 0, 1)), forms each entry's phase 2 pi (u_j - (f_r j mod n)/n)
+in float64 from the exact integer f_r j mod n, and rounds its cosine and sine once to
+float32; products and sums are float32 within a pixel slice (FP32 MFMA), float64 across
+slices.  The sketch is complex; the Gram, Lanczos, A~ and its eigenpairs are complex float64
+on the host.
+
+Tolerances
+* sketch, per entry and part: |Y_gpu - Y_q| <= 2^-16 ((|Re C_q| + |Im C_q|) |X|)_rt against
+  the sketch of the float32-rounded C_q built entry by entry (the bound of the Gaussian FP32
+  form, whose accumulation is the same kernel), and ||Y_gpu - Y_ref||_F <= 1e-6 ||Y_ref||_F
+  against the oracle's float64 FFT route;
+* the small linear algebra on the device's own sketch against LAPACK's SVD and eig
+  (the oracle's reduced_operator on that sketch): sigma within 1e-10, eigenvalues within
+  1e-8, relative;
+* eigenvalues against the FP64 oracle: <= 1e-6 (the FP32 form's target); masks with the
+  oracle's support >= 99.9% identical.
+"""
+import numpy as np
+import pytest
+import torch
+
+import synthvideo as sv
+from oracle import cdmd_ref as R
+from tests.cdmd_testutil import eig_rel_err
+
+pytestmark = pytest.mark.gpu
+
+P = pytest.importorskip("paper_1512_04205_amd")
+
+
+def _say(*a):
+    print("[gpu-case]", *a, flush=True)
+
+
+def _freqs(n, p, seed):
+    return np.random.default_rng(seed).choice(n, size=p, replace=False).astype(np.int32)
+
+
+def _quantised_C(n, freqs, seed):
+    """C_q: the definition's entries, real and imaginary parts rounded to float32."""
+    d = R.srft_diagonal(seed, n)
+    j = np.arange(n, dtype=np.int64)
+    C = np.exp(-2j * np.pi * ((freqs.astype(np.int64)[:, None] * j[None, :]) % n) / n) * d[None, :]
+    return C.real.astype(np.float32).astype(np.float64) + 1j * C.imag.astype(np.float32).astype(np.float64)
+
+
+@pytest.mark.parametrize("case", [
+    ("u8", 40, 60, 30, 50),         # dtype, H, W, m, p: 2400 pixels
+    ("u8", 37, 53, 21, 70),         # ragged pixel tail, m below one frame tile
+    ("f32", 30, 64, 40, 64),
+    ("u8", 64, 96, 300, 40),        # two frame tiles
+])
+def test_srft_sketch(case):
+    kind, H, W, m, p = case
+    _say("srft sketch", case)
+    rng = np.random.default_rng(8)
+    n = H * W
+    seed = 0xABCDEF0123
+    if kind == "f32":
+        D = rng.random((m, n), dtype=np.float32)
+        dtype, scale = P.F32, 1.0
+    else:
+        D = rng.integers(0, 256, size=(m, n), dtype=np.uint8)
+        dtype, scale = P.U8, 1 / 255
+    fr = _freqs(n, p, 3)
+    mdl = P.Model(n, m, min(5, m - 1), p, sketch=P.SKETCH_SRFT, dtype=dtype, idx=fr.reshape(p, 1), seed=seed)
+    mdl.fit(torch.from_numpy(D).cuda())
+    Yg = mdl.sketch()
+    assert Yg.shape == (p, m) and np.iscomplexobj(Yg)
+    Cq = _quantised_C(n, fr, seed)
+    X = D.astype(np.float64).T * scale
+    Yq = Cq @ X / np.sqrt(p)
+    Yabs = (np.abs(Cq.real) + np.abs(Cq.imag)) @ np.abs(X) / np.sqrt(p)
+    for part in (np.real, np.imag):
+        err = np.abs(part(Yg) - part(Yq))
+        assert (err <= 2.0 ** -16 * Yabs + 1e-300).all(), (err / Yabs).max()
+    Yref = R.sketch_srft(D, scale, fr, seed)
+    assert np.linalg.norm(Yg - Yref) <= 1e-6 * np.linalg.norm(Yref)
+
+
+def _video(H=48, W=64, m=60, seed=17, out="u8"):
+    spec = sv.preset("cfg1", H=H, W=W, m=m, bump_sigma=6.0, blur_sigma=3.0, seed=seed, rect_side=(8, 8), out=out)
+    return sv.make_video(spec)
+
+
+@pytest.mark.parametrize("out", ["u8", "f32"])
+def test_srft_fit_mask_parity(out):
+    """A small video: the complex small linear algebra on the device's own sketch against
+    LAPACK, the modes against the FP64 oracle, OMP support and masks."""
+    _say("srft fit", out)
+    v = _video(out=out)
+    D = v.D.numpy()
+    m, n = D.shape
+    k, p, K, seed, tau = 10, 200, 6, 77, 0.1
+    fr = _freqs(n, p, 9)
+    mdl = P.Model(n, m, k, p, sketch=P.SKETCH_SRFT, dtype=P.U8 if out == "u8" else P.F32, idx=fr.reshape(p, 1),
+                  seed=seed)
+    Dg = torch.from_numpy(D).cuda()
+    mdl.fit(Dg)
+    md = mdl.modes()
+    # the host solve on the device's sketch against LAPACK
+    lam_d, _, s_d, _, _ = R.reduced_operator(mdl.sketch(), k)
+    np.testing.assert_allclose(md["sigma"], s_d, rtol=1e-10)
+    rel, _, _ = eig_rel_err(md["lam"], lam_d)
+    assert rel.max() <= 1e-8, rel.max()
+    # against the FP64 oracle
+    ref = R.run(D, v.scale, k, sketch="srft", idx=fr, seed=seed, K=K)
+    rel, _, _ = eig_rel_err(md["lam"], ref.model.lam)
+    assert rel.max() <= 1e-6, rel.max()
+    S, beta = mdl.select(P.SEL_OMP, K=K)
+    assert sorted(S) == sorted(ref.support)
+    mdl.select(P.SEL_EXPLICIT, explicit=ref.support)
+    mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    mdl.foreground(Dg, mk, tau)
+    L = R.background(ref.model.Phi[:, ref.support], ref.beta, ref.model.lam[ref.support], 0, m)
+    mr = R.foreground(D.T.astype(np.float64) * v.scale, L, tau)
+    mg = P.unpack_mask(mk.cpu().numpy().view(np.uint32), n).T
+    agree = 1.0 - (mg != mr).mean()
+    assert agree >= 0.999, agree
+
+
+def test_srft_automatic_rank_refused():
+    n, m, p = 2000, 20, 30
+    fr = _freqs(n, p, 1).reshape(p, 1)
+    D = torch.zeros((m, n), dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.CdmdError) as e:
+        P.optimal_rank(D, n, m, p, sketch=P.SKETCH_SRFT, idx=fr, seed=1)
+    assert e.value.status == P.E_UNSUPPORTED

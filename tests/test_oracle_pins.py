@@ -205,6 +205,56 @@ def test_cdmd_equals_dmd_on_exactly_low_rank(kind, mult):
     np.testing.assert_allclose(mdl.Phi[:, ri] * mdl.b[ri], Phi_d[:, ci] * b_d[ci], atol=1e-8)
 
 
+# ------------------------------------------------------------------ SRFT (Section 3.3)
+def test_srft_sketch_fft_route_equals_the_definition():
+    """The FFT route of the SRFT sketch equals C X with C = R F D / sqrt(p) built entry
+    by entry from the definition, F(f, j) = exp(-2 pi i f j / n)."""
+    rng = np.random.default_rng(3)
+    n, m, p, seed = 45, 7, 11, 12345
+    D = rng.integers(0, 256, size=(m, n)).astype(np.uint8)
+    freqs = rng.choice(n, size=p, replace=False)
+    d = R.srft_diagonal(seed, n)
+    F = np.array([[np.exp(-2j * np.pi * f * j / n) for j in range(n)] for f in range(n)])
+    C = F[freqs] * d[None, :] / np.sqrt(p)
+    np.testing.assert_allclose(R.sketch_srft(D, 1 / 255, freqs, seed), C @ (D.T / 255.0), atol=1e-13)
+
+
+def test_srft_full_transform_is_unitary():
+    """With every DFT row kept (p = n), C = F D / sqrt(n) is unitary: each frame keeps its
+    norm (Parseval), and the sketch's Gram equals the video's."""
+    rng = np.random.default_rng(4)
+    n, m = 64, 9
+    D = rng.normal(size=(m, n))
+    Y = R.sketch_srft(D, 1.0, np.arange(n), 77)
+    np.testing.assert_allclose(np.linalg.norm(Y, axis=0), np.linalg.norm(D, axis=1), rtol=1e-13)
+    np.testing.assert_allclose(Y.conj().T @ Y, D @ D.T, atol=1e-11)
+
+
+def test_srft_diagonal_unit_modulus_and_uniform_phases():
+    d = R.srft_diagonal(9, 40000)
+    np.testing.assert_allclose(np.abs(d), 1.0, rtol=1e-15)
+    u = np.angle(d) / (2 * np.pi) % 1.0
+    assert scipy.stats.kstest(u, "uniform").pvalue > 1e-3
+    # sub-ranges draw the same entries as the whole
+    np.testing.assert_array_equal(philox.srft_uniforms(9, 13, 101), philox.srft_uniforms(9, 0, 200)[13:101])
+
+
+@pytest.mark.parametrize("mult", [1, 2, 5])
+def test_srft_cdmd_recovers_real_dynamics(mult):
+    """A complex sketch of an exactly low-rank real video: the cDMD eigenvalues are the
+    video's (conjugate pairs included) and b_j phi_j its mode columns, to 1e-9."""
+    n, m = 500, 30
+    D, lam_true, cols = lowrank_video(n, m, 3, reals=(0.97,), seed=22)
+    r = len(lam_true)
+    freqs = np.random.default_rng(5).choice(n, size=mult * r, replace=False)
+    Y = R.sketch_srft(D, 1.0, freqs, 31)
+    assert np.iscomplexobj(Y)
+    mdl = R.fit(D, 1.0, Y, r)
+    ri, ci, err = match(mdl.lam, lam_true)
+    assert err.max() < 1e-9
+    np.testing.assert_allclose(mdl.Phi[:, ri] * mdl.b[ri], cols[:, ci], atol=1e-8)
+
+
 # ------------------------------------------------------------------ P5: known modes
 def test_recovers_known_modes_from_generator():
     spec = sv.preset("cfg1", exact=True, out="f64", H=60, W=80, m=60, bump_sigma=6.0,
