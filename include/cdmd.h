@@ -192,13 +192,19 @@ cdmd_status cdmd_set_amplitudes(cdmd_model* mdl, int32_t space);
 
 /* Dense Gaussian C (Section 3.3) kept in device memory.  on != 0: the library draws the
    p x n entries of the configured BF16 or FP8 form once (the same values, bit for bit,
-   that the sketch otherwise draws on the fly; bfloat16 bits or e4m3 codes, rows padded to
-   a multiple of 64 pixels) into memory it allocates and owns, and every later cdmd_fit
-   streams them from HBM instead of drawing them: the sketch then costs 2pn (BF16) or pn
-   (FP8) bytes of reads per fit in place of the draws, and its results do not change.
-   Needs 2 p ceil(n/64) 64 bytes (BF16) or half that (FP8).  on = 0 frees the copy.  Work
-   goes on `stream`, which the call synchronises.  Errors: INVALID_ARG (NULL),
-   UNSUPPORTED (not a Gaussian sketch in the BF16 or FP8 form), OUT_OF_MEMORY, DEVICE. */
+   that the sketch otherwise draws on the fly) into memory it allocates and owns, and every
+   later cdmd_fit streams them from HBM instead of drawing them.
+   * FP8: e4m3 codes, rows padded to a multiple of 64 pixels (p ceil(n/64) 64 bytes); the
+     sketch kernel reads them in place of its draws and its results do not change.
+   * BF16: bfloat16 bits stored pixel-major; each fit converts the video to exact bfloat16
+     in S <= 32 pixel slices and forms the sketch as S batched library GEMMs (hipBLASLt,
+     float32 accumulation and output) summed over the slices in float64.  Needs 2 p n + 2 m n
+     bytes (plus padding to S slices of a multiple of 64 pixels) and S m p floats; the
+     sketch equals the drawn form's up to the float32 summation order (not bit for bit).
+     Models with a stored BF16 C are refused by cdmd_batch_create.
+   on = 0 frees the copy.  Work goes on `stream`, which the call synchronises.  Errors:
+   INVALID_ARG (NULL), UNSUPPORTED (not a Gaussian sketch in the BF16 or FP8 form, or no
+   library GEMM for the shape), OUT_OF_MEMORY, DEVICE. */
 cdmd_status cdmd_store_measurement(cdmd_model* mdl, int32_t on, void* stream);
 
 /* Automatic target rank (Section 3.2, Remark 2): the optimal hard threshold of Gavish and

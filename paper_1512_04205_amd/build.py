@@ -33,6 +33,7 @@ SOURCES = [
     ("sketch_gauss.hip", DEVICE),
     ("mlp.hip", DEVICE),
     ("api.cpp", HOST),
+    ("sketch_gemm.cpp", HOST),
     ("smallla.cpp", HOST),
     ("team_la_host.cpp", HOST),
 ]
@@ -57,7 +58,8 @@ def build(verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(lambda s: _compile(s[0], s[1], verbose), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp]
+    cmd = [HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-L/opt/rocm/lib", "-lhipblaslt",
+           "-Wl,-rpath,/opt/rocm/lib", "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)

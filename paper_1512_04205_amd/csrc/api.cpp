@@ -20,6 +20,7 @@
 #include <vector>
 
 #include "kernels.hpp"
+#include "sketch_gemm.hpp"
 #include "smallla.hpp"
 #include "team_la.hpp"
 #include "team_la_host.hpp"
@@ -98,6 +99,12 @@ struct cdmd_model {
   float* d_gpart = nullptr;         // per-slice partial sketches
   void* d_Cm = nullptr;             // the stored C (cdmd_store_measurement), or null: drawn
   int64_t Cm_ldc = 0;
+  // BF16 form with a stored C: C pixel-major in d_Cm, the video as bfloat16 slices in d_Xs,
+  // the sketch as gm_S batched library GEMMs over slices of gm_Ks pixels
+  cdmd::blas::SketchGemm* sgemm = nullptr;
+  void* d_Xs = nullptr;
+  int gm_S = 0;
+  int64_t gm_Ks = 0;
   // streaming sparse sketch (16-byte aligned frames)
   int32_t* d_chunk_off = nullptr;   // [row block][chunk + 1] first triple of each chunk
   int32_t* d_rblk = nullptr;        // [row block] (first row, rows)
@@ -199,10 +206,11 @@ struct cdmd_model {
       (void)hipEventDestroy(e_stage);
     }
     if (st2) (void)hipStreamDestroy(st2);
+    if (sgemm) cdmd::blas::sketch_gemm_free(sgemm);
     void* dev[] = {d_tri_pix, d_tri_rs, d_seg, d_idx, d_sign, d_Yint, d_Ypart, d_Yd, d_gpart, d_Cm, d_chunk_off, d_rblk,
                    d_gram, d_G, d_Gp, d_pairs, d_part, d_red, d_Gs, d_Gsp, d_Rv, d_Gd, d_Vc, d_counts, d_modes,
                    d_feats, d_logits,
-                   d_la_scratch, d_la_out, d_py, d_pyred, d_freq, d_gram_im};
+                   d_la_scratch, d_la_out, d_py, d_pyred, d_freq, d_gram_im, d_Xs};
     for (void* q : dev)
       if (q) (void)hipFree(q);
     void* host[] = {h_gram, h_G, h_Gp, h_red, h_Gs, h_Gd, h_Vc, h_counts, h_la_out, h_py, h_gram_im};
@@ -472,8 +480,16 @@ cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool 
   } else if (M->gauss) {
     if (c.sketch_prec != CDMD_PREC_FP32 && (reinterpret_cast<uintptr_t>(d_video) & 15) != 0)
       return fail(CDMD_E_UNSUPPORTED, "the BF16 / FP8 Gaussian sketch needs a 16-byte aligned video");
-    HIPCHK(cdmd::k::sketch_gauss(d_video, c.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p, c.seed,
-                                 gauss_prec(c), M->gplan, M->d_Cm, M->Cm_ldc, M->d_gpart, M->d_Yd, st));
+    if (M->sgemm) {
+      HIPCHK(cdmd::k::video_bf16_split(d_video, M->ld, M->n, M->m, M->gm_Ks, M->gm_S, M->d_Xs, st));
+      if (!cdmd::blas::sketch_gemm_run(M->sgemm, M->d_Cm, M->d_Xs, M->d_gpart, st))
+        return fail(CDMD_E_DEVICE, "the sketch GEMM failed");
+      HIPCHK(cdmd::k::reduce_gauss(M->d_gpart, M->gm_S, M->m * (int64_t)M->p, 1.0 / std::sqrt((double)M->p),
+                                   M->d_Yd, st));
+    } else {
+      HIPCHK(cdmd::k::sketch_gauss(d_video, c.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p, c.seed,
+                                   gauss_prec(c), M->gplan, M->d_Cm, M->Cm_ldc, M->d_gpart, M->d_Yd, st));
+    }
     M->mark(1, st);
     HIPCHK(cdmd::k::gram_f64(M->d_Yd, M->p, M->m, M->d_gram, st));
   } else if (c.dtype == CDMD_U8 && M->ld % 16 == 0 && (reinterpret_cast<uintptr_t>(d_video) & 15) == 0 &&
@@ -1380,7 +1396,7 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
         if (ms < best) best = ms, ch.lift_grid = g;
       }
     }
-    if (M->gauss) {
+    if (M->gauss && !M->sgemm) {
       double best = 1e300;
       for (int target : {512, 1024, 2048}) {
         TRY(apply_gauss_target(M, target));
@@ -1478,6 +1494,8 @@ cdmd_status cdmd_batch_create(cdmd_model* const* models, int32_t n, cdmd_batch**
     if (models[i]->amp_compressed)
       return fail(CDMD_E_UNSUPPORTED, "batches fit on the full modes (cdmd_set_amplitudes FULL)");
     if (models[i]->srft) return fail(CDMD_E_UNSUPPORTED, "SRFT models are fitted one at a time");
+    if (models[i]->sgemm)
+      return fail(CDMD_E_UNSUPPORTED, "a stored BF16 C is streamed by a library GEMM, which batches do not capture");
   }
   std::unique_ptr<cdmd_batch> B(new (std::nothrow) cdmd_batch());
   if (!B) return fail(CDMD_E_OUT_OF_MEMORY, "host allocation failed");
@@ -2298,23 +2316,67 @@ cdmd_status cdmd_store_measurement(cdmd_model* M, int32_t on, void* stream) {
   if (!M->gauss || (prec != 1 && prec != 2))
     return fail(CDMD_E_UNSUPPORTED, "C is stored for the BF16 and FP8 forms of the Gaussian sketch only");
   hipStream_t st = as_stream(stream);
-  if (!on) {
-    if (M->d_Cm) {
+  auto release = [&]() -> cdmd_status {
+    HIPCHK(hipStreamSynchronize(st));
+    if (M->sgemm) cdmd::blas::sketch_gemm_free(M->sgemm);
+    M->sgemm = nullptr;
+    if (M->d_Xs) HIPCHK(hipFree(M->d_Xs));
+    M->d_Xs = nullptr;
+    if (M->d_Cm) HIPCHK(hipFree(M->d_Cm));
+    M->d_Cm = nullptr;
+    M->gm_S = 0;
+    M->gm_Ks = 0;
+    ++M->stamp;
+    return CDMD_OK;
+  };
+  if (!on) return M->d_Cm ? release() : CDMD_OK;
+  if (M->d_Cm) return CDMD_OK;
+  auto grab = [&](void** d, size_t bytes) -> bool {
+    if (hipMalloc(d, bytes) == hipSuccess) return true;
+    (void)hipGetLastError();
+    *d = nullptr;
+    return false;
+  };
+  if (prec == 1) {
+    // BF16: C pixel-major for the library GEMM, the video converted into S slices of Ks
+    // pixels per fit (S up to 32 so that the products fill the device)
+    const int S = (int)std::min<int64_t>(32, std::max<int64_t>(1, (M->n + 262143) / 262144));
+    const int64_t Ks = ((M->n + S - 1) / S + 63) / 64 * 64;
+    const int64_t jn = S * Ks;
+    const size_t need_part = (size_t)S * M->m * M->p;
+    if (need_part > M->gpart_cap) {
+      float* np = nullptr;
+      if (!grab((void**)&np, need_part * sizeof(float))) return fail(CDMD_E_OUT_OF_MEMORY, "no device memory for the GEMM partials");
       HIPCHK(hipStreamSynchronize(st));
-      HIPCHK(hipFree(M->d_Cm));
-      M->d_Cm = nullptr;
-      ++M->stamp;
+      HIPCHK(hipFree(M->d_gpart));
+      M->d_gpart = np;
+      M->gpart_cap = need_part;
     }
+    if (!grab(&M->d_Cm, (size_t)jn * M->p * 2) || !grab(&M->d_Xs, (size_t)jn * M->m * 2)) {
+      (void)release();
+      return fail(CDMD_E_OUT_OF_MEMORY, "no device memory for the stored C and the bfloat16 video");
+    }
+    M->gm_S = S;
+    M->gm_Ks = Ks;
+    const hipError_t e = cdmd::k::gauss_fill_t(M->d_Cm, jn, M->n, M->p, M->cfg.seed, st);
+    if (e != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
+      (void)release();
+      return fail(CDMD_E_DEVICE, "filling the stored C failed");
+    }
+    std::string err;
+    M->sgemm = cdmd::blas::sketch_gemm_create(M->p, Ks, M->m, S, &err);
+    if (!M->sgemm) {
+      (void)release();
+      return fail(CDMD_E_UNSUPPORTED, err.c_str());
+    }
+    M->Cm_ldc = 0;
+    ++M->stamp;
     return CDMD_OK;
   }
-  if (M->d_Cm) return CDMD_OK;
   const int64_t ldc = cdmd::k::gauss_ldc(M->n);
-  const size_t bytes = (size_t)M->p * (size_t)ldc * (prec == 1 ? 2 : 1);
+  const size_t bytes = (size_t)M->p * (size_t)ldc;
   void* d = nullptr;
-  if (hipMalloc(&d, bytes) != hipSuccess) {
-    (void)hipGetLastError();
-    return fail(CDMD_E_OUT_OF_MEMORY, "no device memory for the stored C");
-  }
+  if (!grab(&d, bytes)) return fail(CDMD_E_OUT_OF_MEMORY, "no device memory for the stored C");
   const hipError_t e = cdmd::k::gauss_fill(d, ldc, M->n, M->p, M->cfg.seed, prec, st);
   if (e == hipSuccess && hipStreamSynchronize(st) == hipSuccess) {
     M->d_Cm = d;

@@ -70,6 +70,16 @@ int64_t gauss_ldc(int64_t n);
 hipError_t sketch_srft(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, int p, uint64_t seed,
                        const GaussPlan& g, const int32_t* freq, float* part, double* Y, hipStream_t stream);
 hipError_t gram_cplx(const double* Y, int p, int64_t m, double* Gr, double* Gi, hipStream_t stream);
+// The BF16 form with a stored C as S batched library GEMMs over pixel slices of Ks
+// (a multiple of 64; S Ks >= n): gauss_fill_t writes C pixel-major, Ct[j][r] (p
+// contiguous per pixel, rows n..jn-1 zero), bit for bit the drawn form's entries;
+// video_bf16_split writes the video as exact bfloat16 in slices, Xs[s][t][i] = x(t, s Ks + i)
+// (zero past n); reduce_gauss sums the S float32 partials part[s][t][r] in order into
+// Y[t][r] (float64) times scale.
+hipError_t gauss_fill_t(void* Ct, int64_t jn, int64_t n, int p, uint64_t seed, hipStream_t stream);
+hipError_t video_bf16_split(const void* D, int64_t ld, int64_t n, int64_t m, int64_t Ks, int S, void* Xs,
+                            hipStream_t stream);
+hipError_t reduce_gauss(const float* part, int nsplit, int64_t count, double scale, double* Y, hipStream_t stream);
 hipError_t gauss_fill(void* Cm, int64_t ldc, int64_t n, int p, uint64_t seed, int prec, hipStream_t stream);
 
 // ----- learned selector (mlp.hip) -------------------------------------------------

@@ -693,6 +693,55 @@ __global__ __launch_bounds__(256) void k_reduce_gauss(const float* __restrict__ 
   }
 }
 
+// The BF16 form's C for the library GEMM, stored pixel-major: Ct[j][r] for j < jn (rows
+// j >= n zero), the entries of the drawn form (k_sketch_gauss_bf16) bit for bit.  Thread e
+// takes row r = e mod p of pixel quad e / p, so a wave writes consecutive rows of a pixel.
+__global__ __launch_bounds__(256) void k_gauss_fill_bf16_t(uint16_t* __restrict__ Ct, int64_t jn, int64_t n, int p,
+                                                           uint64_t seed) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const int64_t total = (jn / 4) * p;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(it % p);
+    const int64_t j0 = (it / p) * 4;
+    float z[4] = {0.f, 0.f, 0.f, 0.f};
+    if (j0 < n) {
+      const Words4 wd = philox4x32_10((uint32_t)(j0 >> 2), (uint32_t)r, k0, k1);
+      box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
+      box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      Ct[(j0 + e) * p + r] = j0 + e < n ? (uint16_t)bf16_bits_rne(z[e]) : (uint16_t)0;
+  }
+}
+
+// Video bytes to exact bfloat16 in the GEMM's split layout: Xs[s][t][i] = x(t, s Ks + i),
+// zero past the frame.  8 pixels per thread (frames 16-byte aligned, Ks a multiple of 64).
+__global__ __launch_bounds__(256) void k_video_bf16_split(const uint8_t* __restrict__ D, int64_t ld, int64_t n,
+                                                          int64_t m, int64_t Ks, int S, uint16_t* __restrict__ Xs) {
+  const int64_t per = Ks / 8, total = (int64_t)S * m * per;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t st = it / per, i = (it % per) * 8;
+    const int64_t s = st / m, t = st % m, j = s * Ks + i;
+    const uint8_t* src = D + t * ld + j;
+    uint32_t lo = 0u, hi = 0u;
+    if (j + 8 <= n) {
+      const uint2 v = *reinterpret_cast<const uint2*>(src);
+      lo = v.x;
+      hi = v.y;
+    } else {
+      for (int e = 0; e < 8 && j + e < n; ++e) {
+        const uint32_t b = src[e];
+        if (e < 4) lo |= b << (8 * e);
+        else hi |= b << (8 * (e - 4));
+      }
+    }
+    *reinterpret_cast<bf16x8_t*>(Xs + st * Ks + i) = u8x8_to_bf16(lo, hi);
+  }
+}
+
 // G[a][b] = sum_r conj(Y[a][r]) Y[b][r] over the complex rows of an SRFT sketch stored
 // with interleaved (re, im) rows per frame (Y[t][2r], Y[t][2r + 1]): real part to Gr,
 // imaginary part to Gi, float64.  A workgroup owns a 16 x 16 tile of (a, b) and steps
@@ -871,6 +920,32 @@ hipError_t sketch_srft(const void* D, int dtype, int64_t ld, int64_t n, int64_t 
   if (nb > 4096) nb = 4096;
   hipLaunchKernelGGL(k_reduce_gauss, dim3((unsigned)nb), dim3(256), 0, stream, part, g.nsplit, count,
                      1.0 / sqrt((double)p), Y);
+  return hipGetLastError();
+}
+
+hipError_t gauss_fill_t(void* Ct, int64_t jn, int64_t n, int p, uint64_t seed, hipStream_t stream) {
+  if (jn % 4 != 0 || jn < n) return hipErrorInvalidValue;
+  int64_t blocks = ((jn / 4) * p + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_gauss_fill_bf16_t, dim3((unsigned)blocks), dim3(256), 0, stream, static_cast<uint16_t*>(Ct), jn,
+                     n, p, seed);
+  return hipGetLastError();
+}
+
+hipError_t video_bf16_split(const void* D, int64_t ld, int64_t n, int64_t m, int64_t Ks, int S, void* Xs,
+                            hipStream_t stream) {
+  if (Ks % 64 != 0 || ld % 16 != 0 || (reinterpret_cast<uintptr_t>(D) & 15) != 0) return hipErrorInvalidValue;
+  int64_t blocks = ((int64_t)S * m * (Ks / 8) + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_video_bf16_split, dim3((unsigned)blocks), dim3(256), 0, stream,
+                     static_cast<const uint8_t*>(D), ld, n, m, Ks, S, static_cast<uint16_t*>(Xs));
+  return hipGetLastError();
+}
+
+hipError_t reduce_gauss(const float* part, int nsplit, int64_t count, double scale, double* Y, hipStream_t stream) {
+  int64_t nb = (count + 255) / 256;
+  if (nb > 4096) nb = 4096;
+  hipLaunchKernelGGL(k_reduce_gauss, dim3((unsigned)nb), dim3(256), 0, stream, part, nsplit, count, scale, Y);
   return hipGetLastError();
 }
 
