@@ -81,7 +81,7 @@ typedef enum {
                                  DFT, F(f, j) = exp(-2 pi i f j / n); R keeps the p distinct
                                  DFT rows f given in sparse_idx (nnz = 1, weights +1).  The
                                  sketch is complex: FP32 form only, the small linear algebra
-                                 complex on the host; no automatic rank, no batches */
+                                 complex on the host; no batches */
 } cdmd_sketch;
 
 /* Arithmetic of the sketch and of the mode lift / reconstruction passes.  The

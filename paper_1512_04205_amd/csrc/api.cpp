@@ -1213,29 +1213,49 @@ cdmd_status post_fit(cdmd_model* M, double t0, double t1, double t2) {
 // Gram are used).
 static cdmd_status rank_with_model(cdmd_model* M, const void* d_video, hipStream_t st, int32_t* k_out,
                                    double* tau_out, double* sigma_out) {
-  if (M->srft) return fail(CDMD_E_UNSUPPORTED, "the automatic rank is built for real sketches");
   plan_fit(M, d_video);
   TRY(run_sketch(M, d_video, st, true));
   // the spectrum of Y = Y^[:, :m-1] from its Gram: sigma_i = scale sqrt(mu_i), the min(p, m-1)
-  // largest eigenvalues
+  // largest eigenvalues.  A complex (SRFT) sketch's Hermitian Gram G = Gr + i Gi enters as
+  // the real symmetric [[Gr, -Gi], [Gi, Gr]] of twice the order, which has every eigenvalue
+  // of G twice: its 2r largest have the same median, and twice the count above it.
   const int N = M->N;
+  const double* A = M->h_gram;
+  int nA = N, ldA = (int)M->m, mult = 1;
+  std::vector<double> R2;
+  if (M->srft) {
+    const int64_t m = M->m;
+    nA = 2 * N;
+    ldA = nA;
+    mult = 2;
+    R2.assign((size_t)nA * nA, 0.0);
+    for (int a = 0; a < N; ++a)
+      for (int b2 = 0; b2 < N; ++b2) {
+        // upper triangle as computed, lower triangle its conjugate
+        const double gr = a <= b2 ? M->h_gram[a * m + b2] : M->h_gram[b2 * m + a];
+        const double gi = a <= b2 ? M->h_gram_im[a * m + b2] : -M->h_gram_im[b2 * m + a];
+        R2[(size_t)a * nA + b2] = gr;
+        R2[(size_t)(a + N) * nA + b2 + N] = gr;
+        R2[(size_t)a * nA + b2 + N] = -gi;
+        R2[(size_t)(a + N) * nA + b2] = gi;
+      }
+    A = R2.data();
+  }
+  const int r = std::min(N, M->p);
   if (!sigma_out) {  // the median and one count are enough
-    const int r = std::min(N, M->p);
     const double beta = (double)r / (double)std::max(N, M->p);
     int k = 0;
     double tau = 0.0;
-    if (!cdmd::la::sym_rank_threshold(M->h_gram, N, (int)M->m, r, M->sketch_scale, cdmd::la::gd_omega(beta), &k,
-                                      &tau))
+    if (!cdmd::la::sym_rank_threshold(A, nA, ldA, mult * r, M->sketch_scale, cdmd::la::gd_omega(beta), &k, &tau))
       return fail(CDMD_E_NUMERIC, "non-finite Gram");
-    *k_out = k;
+    *k_out = (k + mult - 1) / mult;
     if (tau_out) *tau_out = tau;
     return CDMD_OK;
   }
   std::vector<double> ev;
-  if (!cdmd::la::sym_eigvals(M->h_gram, N, (int)M->m, ev)) return fail(CDMD_E_NUMERIC, "non-finite Gram");
-  const int r = std::min(N, M->p);
+  if (!cdmd::la::sym_eigvals(A, nA, ldA, ev)) return fail(CDMD_E_NUMERIC, "non-finite Gram");
   std::vector<double> sig(r);
-  for (int i = 0; i < r; ++i) sig[i] = M->sketch_scale * std::sqrt(std::max(ev[N - 1 - i], 0.0));
+  for (int i = 0; i < r; ++i) sig[i] = M->sketch_scale * std::sqrt(std::max(ev[nA - 1 - mult * i], 0.0));
   // the median of the r singular values (the mean of the middle two for even r)
   const double med = (r & 1) ? sig[r / 2] : 0.5 * (sig[r / 2 - 1] + sig[r / 2]);
   const double beta = (double)r / (double)std::max(N, M->p);

@@ -55,13 +55,13 @@ struct GaussPlan {
 };
 // target: about how many workgroups to spread over (pixel slices are added until then)
 GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target);
-// Cm: the stored C of gauss_fill for the BF16 / FP8 forms (its precision), or null to draw
-// the entries; ldc its row stride in entries.
+// Cm: the stored C of gauss_fill for the FP8 form, or null to draw the entries (the BF16
+// form refuses a stored C: that goes to the library GEMM); ldc its row stride in entries.
 hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t m, int p,
                         uint64_t seed, int prec, const GaussPlan& g, const void* Cm, int64_t ldc, float* part,
                         double* Y, hipStream_t stream);
-// Row stride (entries) of a stored C for n pixels, and its fill: the entries of the BF16
-// (prec 1: bfloat16 bits) or FP8 (prec 2: e4m3 codes) form, p rows of ldc, zero past n.
+// Row stride (entries) of a stored C for n pixels, and its fill: the entries of the FP8 form
+// (prec 2: e4m3 codes; other forms are refused), p rows of ldc, zero past n.
 int64_t gauss_ldc(int64_t n);
 // SRFT sketch (the FP32 form's kernel with the entries of C = R F D): g = gauss_plan(n, m,
 // 2 p, FP32), freq[p] the DFT rows kept; Y (m x 2p float64, frame-major) holds the real and

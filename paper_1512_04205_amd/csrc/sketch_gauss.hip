@@ -1,9 +1,10 @@
 // Dense Gaussian sketch Y^ = C X (Section 3.2, eq. (eq:YCX), with a Gaussian measurement matrix,
 // Section "Measurement Matrices").  Every entry of C is a pure function of (seed, row,
-// pixel), drawn by the workgroup that needs it, or, for the BF16 and FP8 forms, read from
-// a copy of C the library stored in device memory once (gauss_fill: the same entries,
-// bit for bit), which trades the per-entry draw for p n bytes (FP8) or 2 p n bytes (BF16)
-// of HBM reads per sketch.
+// pixel), drawn by the workgroup that needs it, or, for the FP8 form, read from a copy of
+// C the library stored in device memory once (gauss_fill: the same entries, bit for bit),
+// which trades the per-entry draw for p n bytes of HBM reads per sketch.  (A stored BF16 C
+// makes the sketch a plain product: gauss_fill_t stores it pixel-major for the library
+// GEMM of sketch_gemm.cpp.)
 //
 // Entry definition: for row r and pixel j, Philox4x32-10 (Salmon, Moraes, Dror and Shaw,
 // SC'11) with key (seed mod 2^32, seed >> 32) on the counter (j >> 2, r, 0, 0) gives four
@@ -125,12 +126,11 @@ constexpr int GB_NW = 8;      // waves per workgroup
 // of a wave reads pixels [32h, 32h + 32) of its frame with two 16-byte loads; k-step ks
 // takes pixels 32h + 8ks + (0..7).  The C tile is stored in pixel order, so the A
 // fragment of (row, h, ks) is the 16 bytes at pixel 32h + 8ks.
-// STORED: C is read from Cm (bfloat16 bits, row r at Cm + r ldc) instead of drawn.
-template <int NFB, bool STORED>
+// (With a stored C the BF16 form is a plain product and goes to the library GEMM instead.)
+template <int NFB>
 __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t* __restrict__ D, int64_t ld,
                                                                  int64_t n, int64_t m, int p, uint64_t seed,
                                                                  int64_t pps, int nft, int nsplit,
-                                                                 const uint16_t* __restrict__ Cm, int64_t ldc,
                                                                  float* __restrict__ part) {
   constexpr int FRAMES = 32 * NFB * GB_NW;
   __shared__ __attribute__((aligned(16))) uint16_t sA[2][GB_ROWS * GB_AS];
@@ -170,23 +170,6 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
     }
     *reinterpret_cast<uint4*>(&sA[buf][gr * GB_AS + 8 * gg]) = make_uint4(q[0], q[1], q[2], q[3]);
   };
-  // the same eight entries from the stored C (pixels of the next slice read as 0)
-  auto fetch = [&](int64_t j0) -> uint4 {
-    const int64_t j = j0 + 8 * gg;
-    uint4 v = make_uint4(0u, 0u, 0u, 0u);
-    if (grow < p && j < je) {
-      v = *reinterpret_cast<const uint4*>(Cm + (int64_t)grow * ldc + j);
-      if (j + 8 > je) {
-        uint32_t q[4] = {v.x, v.y, v.z, v.w};
-#pragma unroll
-        for (int e = 0; e < 8; ++e)
-          if (j + e >= je) q[e >> 1] &= (e & 1) ? 0x0000ffffu : 0xffff0000u;
-        v = make_uint4(q[0], q[1], q[2], q[3]);
-      }
-    }
-    return v;
-  };
-  auto put = [&](int buf, uint4 v) { *reinterpret_cast<uint4*>(&sA[buf][gr * GB_AS + 8 * gg]) = v; };
 
   // this lane's frames: t0 + 32 NFB w + 32 fb + lc (wave w owns 32 NFB frames)
   uint4 bcur[NFB][2], bnext[NFB][2];
@@ -224,20 +207,15 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
 
   const int64_t nsteps = je > jb ? (je - jb + GB_KT - 1) / GB_KT : 0;
   if (nsteps > 0) {
-    if constexpr (STORED) put(0, fetch(jb));
-    else draw(0, jb);
+    draw(0, jb);
     load_b(bcur, jb);
   }
   __syncthreads();
-  uint4 cnext = make_uint4(0u, 0u, 0u, 0u);
   for (int64_t st = 0; st < nsteps; ++st) {
     const int buf = (int)(st & 1);
     const int64_t jn = jb + (st + 1) * GB_KT;
     const bool more = st + 1 < nsteps;
-    if (more) {
-      load_b(bnext, jn);
-      if constexpr (STORED) cnext = fetch(jn);  // in flight during this step's products
-    }
+    if (more) load_b(bnext, jn);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       bf16x8_t a[2];
@@ -253,10 +231,7 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
           acc[rb][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b, acc[rb][fb], 0, 0, 0);
       }
     }
-    if (more) {
-      if constexpr (STORED) put(buf ^ 1, cnext);
-      else draw(buf ^ 1, jn);
-    }
+    if (more) draw(buf ^ 1, jn);
     __syncthreads();
 #pragma unroll
     for (int fb = 0; fb < NFB; ++fb) {
@@ -474,36 +449,9 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* 
 }
 
 // ------------------------------------------------------------------------ stored C
-// The entries the BF16 / FP8 sketches draw, written once: row r at Cm + r ldc (ldc a
-// multiple of 8), pixels j >= n zero.  Each thread item: eight pixels of one row, from
-// the same Philox words, Box-Muller and rounding as the draw in the sketch kernels.
-__global__ __launch_bounds__(256) void k_gauss_fill_bf16(uint16_t* __restrict__ Cm, int64_t ldc, int64_t n, int p,
-                                                         uint64_t seed) {
-  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  const int64_t groups = ldc / 8, total = (int64_t)p * groups;
-  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
-       it += (int64_t)gridDim.x * blockDim.x) {
-    const int r = (int)(it / groups);
-    const int64_t j = (it % groups) * 8;
-    uint32_t q[4] = {0u, 0u, 0u, 0u};
-    if (j < n) {
-#pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const Words4 wd = philox4x32_10((uint32_t)((j >> 2) + half), (uint32_t)r, k0, k1);
-        float z[4];
-        box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
-        box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
-#pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (j + 4 * half + e >= n) z[e] = 0.f;
-        q[2 * half] = bf16_bits_rne(z[0]) | (bf16_bits_rne(z[1]) << 16);
-        q[2 * half + 1] = bf16_bits_rne(z[2]) | (bf16_bits_rne(z[3]) << 16);
-      }
-    }
-    *reinterpret_cast<uint4*>(Cm + (int64_t)r * ldc + j) = make_uint4(q[0], q[1], q[2], q[3]);
-  }
-}
-
+// The entries the FP8 sketch draws, written once: row r at Cm + r ldc (ldc a multiple of
+// 8), pixels j >= n zero.  Each thread item: eight pixels of one row, from the same Philox
+// words, Box-Muller and rounding as the draw in the sketch kernel.
 __global__ __launch_bounds__(256) void k_gauss_fill_fp8(uint8_t* __restrict__ Cm, int64_t ldc, int64_t n, int p,
                                                         uint64_t seed) {
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
@@ -810,17 +758,13 @@ GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target) {
 int64_t gauss_ldc(int64_t n) { return (n + 63) / 64 * 64; }
 
 hipError_t gauss_fill(void* Cm, int64_t ldc, int64_t n, int p, uint64_t seed, int prec, hipStream_t stream) {
-  if (prec != 1 && prec != 2) return hipErrorInvalidValue;
+  if (prec != 2) return hipErrorInvalidValue;  // the BF16 form stores C pixel-major (gauss_fill_t)
   if (ldc % 8 != 0 || ldc < n) return hipErrorInvalidValue;
   const int64_t total = (int64_t)p * (ldc / 8);
   int64_t blocks = (total + 255) / 256;
   if (blocks > 65536) blocks = 65536;
-  if (prec == 1)
-    hipLaunchKernelGGL(k_gauss_fill_bf16, dim3((unsigned)blocks), dim3(256), 0, stream, static_cast<uint16_t*>(Cm),
-                       ldc, n, p, seed);
-  else
-    hipLaunchKernelGGL(k_gauss_fill_fp8, dim3((unsigned)blocks), dim3(256), 0, stream, static_cast<uint8_t*>(Cm),
-                       ldc, n, p, seed);
+  hipLaunchKernelGGL(k_gauss_fill_fp8, dim3((unsigned)blocks), dim3(256), 0, stream, static_cast<uint8_t*>(Cm), ldc,
+                     n, p, seed);
   return hipGetLastError();
 }
 
@@ -830,16 +774,12 @@ hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t
   const dim3 grid((unsigned)g.blocks), block(256);
   if (prec == 1) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
-    const uint16_t* c = static_cast<const uint16_t*>(Cm);
+    if (Cm != nullptr) return hipErrorInvalidValue;  // a stored BF16 C goes to the library GEMM
     const dim3 bb(64 * GB_NW);
     auto go = [&](auto nfb) {
       constexpr int NFB = decltype(nfb)::value;
-      if (c != nullptr)
-        hipLaunchKernelGGL((k_sketch_gauss_bf16<NFB, true>), grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft,
-                           g.nsplit, c, ldc, part);
-      else
-        hipLaunchKernelGGL((k_sketch_gauss_bf16<NFB, false>), grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft,
-                           g.nsplit, c, ldc, part);
+      hipLaunchKernelGGL((k_sketch_gauss_bf16<NFB>), grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft,
+                         g.nsplit, part);
     };
     if (g.frames == 256) go(std::integral_constant<int, 1>{});
     else if (g.frames == 512) go(std::integral_constant<int, 2>{});

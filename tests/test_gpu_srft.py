@@ -17,7 +17,9 @@ Tolerances
   (the oracle's reduced_operator on that sketch): sigma within 1e-10, eigenvalues within
   1e-8, relative;
 * eigenvalues against the FP64 oracle: <= 1e-6 (the FP32 form's target); masks with the
-  oracle's support >= 99.9% identical.
+  oracle's support >= 99.9% identical;
+* the automatic rank: singular values within 1e-9 of LAPACK on the device's sketch, tau*
+  within Weyl's bound omega(beta) ||E||_2 of the oracle's.
 """
 import numpy as np
 import pytest
@@ -123,10 +125,43 @@ def test_srft_fit_mask_parity(out):
     assert agree >= 0.999, agree
 
 
-def test_srft_automatic_rank_refused():
-    n, m, p = 2000, 20, 30
-    fr = _freqs(n, p, 1).reshape(p, 1)
-    D = torch.zeros((m, n), dtype=torch.uint8, device="cuda")
-    with pytest.raises(P.CdmdError) as e:
-        P.optimal_rank(D, n, m, p, sketch=P.SKETCH_SRFT, idx=fr, seed=1)
-    assert e.value.status == P.E_UNSUPPORTED
+def test_srft_automatic_rank():
+    """Remark 2's rank for the complex SRFT sketch (its Hermitian Gram enters the host
+    spectrum code as the real symmetric embedding of twice the order, every eigenvalue
+    twice): the singular values equal LAPACK's SVD of the device's own sketch within 1e-9;
+    tau* lies within Weyl's bound omega(beta) ||E||_2 of the oracle's (E the device sketch's
+    float32 rounding); the rank equals the oracle's unless a singular value lies within
+    twice that bound of tau*.  The long-video executor's per-batch rank (the median and one
+    Sturm count, without the full spectrum) equals cdmd_optimal_rank's."""
+    _say("srft rank")
+    v = _video(H=48, W=64, m=150, seed=23)
+    D = v.D.numpy()
+    m, n = D.shape
+    p, seed = 300, 91
+    fr = _freqs(n, p, 4).reshape(p, 1)
+    Dg = torch.from_numpy(D).cuda()
+    k, tau, sig = P.optimal_rank(Dg, n, m, p, sketch=P.SKETCH_SRFT, idx=fr, seed=seed)
+    mdl = P.Model(n, m, 5, p, sketch=P.SKETCH_SRFT, idx=fr, seed=seed)
+    mdl.fit(Dg)
+    Yd = mdl.sketch()
+    Yr = R.sketch_srft(D, v.scale, fr.reshape(-1), seed)
+    mm = m - 1
+    np.testing.assert_allclose(sig, np.linalg.svd(Yd[:, :mm], compute_uv=False), rtol=1e-9,
+                               atol=1e-9 * sig[0])
+    kr, taur, sr = R.optimal_rank(Yr)
+    e2 = np.linalg.norm(Yd[:, :mm] - Yr[:, :mm], 2)
+    beta = min(p, mm) / max(p, mm)
+    tol = R.gd_omega(beta) * e2 * (1 + 1e-9) + 1e-9 * taur
+    assert abs(tau - taur) <= tol, (tau, taur, tol)
+    gap = np.min(np.abs(sr - taur))
+    _say("k", k, "oracle k", kr, "||E||_2 / sigma_1", e2 / sr[0], "closest sigma to tau", gap / taur)
+    if gap > 2 * tol:
+        assert k == kr
+    assert 1 <= k < min(p, mm)
+    # the executor's rank per batch
+    mk = torch.zeros((m, P.mask_words(n)), dtype=torch.int32, device="cuda")
+    used = P.process_video(Dg, n, m, p, mk, batch_frames=75, k=0, K=4, tau=0.1, workers=1, sketch=P.SKETCH_SRFT,
+                           idx=fr, seed=seed)
+    for b, t0 in enumerate((0, 75)):
+        kb = P.optimal_rank(Dg[t0:t0 + 75], n, 75, p, sketch=P.SKETCH_SRFT, idx=fr, seed=seed)[0]
+        assert used[b] == max(1, min(kb, 74, p, 40)), (b, used[b], kb)
