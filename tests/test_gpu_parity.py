@@ -398,3 +398,31 @@ def test_device_small_la_matches_host_la_and_oracle(shape):
         assert np.abs(np.abs(md["b"]) * md["phi_norm"] - key_r).max() <= 2e-5 * key_r.max(), path
         assert list(S) == list(ref.support), (path, S, ref.support)
     np.testing.assert_allclose(res["device"][0]["lam"], res["host"][0]["lam"], rtol=1e-10, atol=1e-12)
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("m", [1025, 1026])
+def test_largest_rank_at_the_device_solve_limit(m):
+    """k = 40, the largest rank the library builds, at m = 1025 frames (N = 1024: the largest
+    device small-LA solve, 32 row groups of 32 rows) and at m = 1026 (past it: the host
+    solve): eigenvalues within 1e-9 of the FP64 oracle, sigma within 1e-9, the same OMP
+    support; k = 41 is refused."""
+    _say("largest rank", m)
+    v = _small_u8(H=40, W=64, m=m, seed=29)
+    D = v.D.numpy()
+    n = D.shape[1]
+    k, p = 40, 300
+    idx, sign = sv.sparse_table(n, p, 32, 6)
+    Dg = torch.from_numpy(D).cuda()
+    ref = R.run(D, v.scale, k, sketch="sparse", idx=idx, sign=sign, K=8)
+    mdl = P.Model(n, m, k, p, idx=idx, sign=sign)
+    mdl.fit(Dg)
+    md = mdl.modes()
+    rel, _, _ = eig_rel_err(md["lam"], ref.model.lam)
+    assert rel.max() <= 1e-9, rel.max()
+    np.testing.assert_allclose(md["sigma"], ref.model.sigma, rtol=1e-9)
+    S, _ = mdl.select(P.SEL_OMP, K=8)
+    assert list(S) == list(ref.support)
+    with pytest.raises(P.CdmdError) as e:
+        P.Model(n, m, 41, p, idx=idx, sign=sign)
+    assert e.value.status == P.E_UNSUPPORTED
