@@ -315,8 +315,8 @@ void cdmd_batch_free(cdmd_batch* batch);
    joins the batch before it).  `workers` host threads, each with its own stream and
    models, take the batches in turn, so up to `workers` batches are in flight and the
    small linear algebra of one overlaps the streaming kernels of another.  k = 0 chooses
-   the rank of every batch by Remark 2, clamped to [1, min(m_b - 1, p, 40)] (k_used[b], host,
-   receives it when not NULL).
+   the rank of every batch by Remark 2, clamped to [1, min(m_b - 1, p, 40)] (k_used, host, one
+   entry per batch, at most ceil(frames / batch_frames), receives the ranks when not NULL).
    The call waits for `stream` (the video's producer) and returns when every mask is
    written.  Errors: INVALID_ARG, the errors of cdmd_create / cdmd_fit / cdmd_select /
    cdmd_foreground for the first batch that failed (its message names it). */
@@ -340,9 +340,10 @@ cdmd_status cdmd_process_video(const cdmd_config* base, const cdmd_video_plan* p
    afterwards) and checks the plan (INVALID_ARG); models are created on first use, so
    configuration errors of `base` surface in the first cdmd_video_run.  cdmd_video_run
    takes `frames` frames at d_video with the layout of `base` and behaves as
-   cdmd_process_video; runs on one executor must not overlap (one host thread at a time).
-   cdmd_video_free waits for the executor's streams and releases everything (NULL is a
-   no-op). */
+   cdmd_process_video; it works on the device that was current at cdmd_video_create and
+   leaves the caller's current device as it found it; runs on one executor must not
+   overlap (one host thread at a time).  cdmd_video_free waits for the executor's streams
+   and releases everything (NULL is a no-op). */
 typedef struct cdmd_video cdmd_video;
 cdmd_status cdmd_video_create(const cdmd_config* base, const cdmd_video_plan* plan, cdmd_video** out);
 cdmd_status cdmd_video_run(cdmd_video* video, const void* d_video, int64_t frames, void* d_mask, int32_t* k_used,

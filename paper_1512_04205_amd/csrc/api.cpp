@@ -2198,7 +2198,14 @@ cdmd_status cdmd_video_run(cdmd_video* V, const void* d_video, int64_t frames, v
   const int64_t words = (base->n + 31) / 32;
   const size_t elem = base->dtype == CDMD_U8 ? 1 : 4;
   const int nw = std::min<int>((int)V->wk.size(), (int)batches.size());
+  // the executor's device for this call; the caller's current device is restored on return
+  int caller_dev = 0;
+  HIPCHK(hipGetDevice(&caller_dev));
   HIPCHK(hipSetDevice(V->dev));
+  struct Restore {
+    int d;
+    ~Restore() { (void)hipSetDevice(d); }
+  } restore{caller_dev};
   HIPCHK(hipEventRecord(V->ready, as_stream(stream)));  // the video is ready on the caller's stream
   for (int i = 0; i < nw; ++i) {
     VideoWorker& w = V->wk[i];

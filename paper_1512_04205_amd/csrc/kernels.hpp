@@ -50,7 +50,7 @@ hipError_t sketch_sparse_f32(const float* D, int64_t ld, int64_t m, const int32_
 // operands, FP8 MFMA).  BF16 and FP8: uint8 video with 16-byte aligned frames only.  part: nsplit * m * p floats of
 // per-slice partial sums; Y[t][r] = (1/sqrt(p)) * sum over slices (float64, m x p).
 struct GaussPlan {
-  int nrt, nft, nsplit, frames;
+  int nrt, nft, nsplit, frames, rows;  // row tiles of `rows` sketch rows, frame tiles of `frames`
   int64_t pps, blocks;
 };
 // target: about how many workgroups to spread over (pixel slices are added until then)

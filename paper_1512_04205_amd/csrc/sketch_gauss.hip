@@ -116,30 +116,35 @@ __device__ __forceinline__ bf16x8_t u8x8_to_bf16(uint32_t lo, uint32_t hi) {
 }
 
 // ------------------------------------------------------------------------ BF16 form
-constexpr int GB_ROWS = 64;   // sketch rows per workgroup (2 MFMA row blocks)
+constexpr int GB_ROWS = 64;   // sketch rows per workgroup of the FP8 form (2 MFMA row blocks)
 constexpr int GB_KT = 64;     // pixels per step (4 MFMA k-steps)
 constexpr int GB_AS = 72;     // LDS row stride of the C tile (bf16 elements)
 constexpr int GB_NW = 8;      // waves per workgroup
 
-// NFB: 32-frame blocks per wave (frames per workgroup = 32 NFB GB_NW).  Video: uint8,
+// NFB: 32-frame blocks per wave (frames per workgroup = 32 NFB GB_NW); RB: 32-row blocks
+// (rows per workgroup = 32 RB, shared by the eight waves); RB NFB <= 8 keeps the
+// accumulators within 128 registers.  More rows per workgroup let each drawn C entry and
+// each converted video fragment feed more products (gauss_plan picks RB).  Video: uint8,
 // frames 16-byte aligned (ld % 16 == 0, aligned base).  K order inside a step: lane half h
 // of a wave reads pixels [32h, 32h + 32) of its frame with two 16-byte loads; k-step ks
 // takes pixels 32h + 8ks + (0..7).  The C tile is stored in pixel order, so the A
 // fragment of (row, h, ks) is the 16 bytes at pixel 32h + 8ks.
 // (With a stored C the BF16 form is a plain product and goes to the library GEMM instead.)
-template <int NFB>
+template <int NFB, int RB>
 __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t* __restrict__ D, int64_t ld,
                                                                  int64_t n, int64_t m, int p, uint64_t seed,
                                                                  int64_t pps, int nft, int nsplit,
                                                                  float* __restrict__ part) {
   constexpr int FRAMES = 32 * NFB * GB_NW;
-  __shared__ __attribute__((aligned(16))) uint16_t sA[2][GB_ROWS * GB_AS];
-  const int combos = nft * nsplit, nrt = (p + GB_ROWS - 1) / GB_ROWS;
+  constexpr int ROWS = 32 * RB;
+  static_assert(RB >= 2 && RB % 2 == 0 && RB * NFB <= 8, "tile shape");
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][ROWS * GB_AS];
+  const int combos = nft * nsplit, nrt = (p + ROWS - 1) / ROWS;
   const int xcd = blockIdx.x & 7, loc = blockIdx.x >> 3;
   const int rt = loc % nrt, cidx = (loc / nrt) * 8 + xcd;
   if (cidx >= combos) return;  // padding of the last group of eight combinations
   const int s = cidx / nft, ft = cidx % nft;
-  const int r0 = rt * GB_ROWS;
+  const int r0 = rt * ROWS;
   const int64_t t0 = (int64_t)ft * FRAMES;
   const int64_t jb = (int64_t)s * pps;
   int64_t je = jb + pps;
@@ -147,28 +152,31 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
   const int h = l >> 5, lc = l & 31;
   const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
-  // drawing role: row gr, pixels 8 gg .. 8 gg + 7 of the step
+  // drawing role: rows gr + 64 i (i < RB / 2), pixels 8 gg .. 8 gg + 7 of the step
   const int gr = tid >> 3, gg = tid & 7;
-  const int grow = r0 + gr;
 
   auto draw = [&](int buf, int64_t j0) {
     const int64_t j = j0 + 8 * gg;
-    uint32_t q[4] = {0u, 0u, 0u, 0u};
-    if (grow < p && j < je) {
 #pragma unroll
-      for (int half = 0; half < 2; ++half) {
-        const Words4 wd = philox4x32_10((uint32_t)((j >> 2) + half), (uint32_t)grow, k0, k1);
-        float z[4];
-        box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
-        box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+    for (int i = 0; i < RB / 2; ++i) {
+      const int lr = gr + 64 * i, grow = r0 + lr;
+      uint32_t q[4] = {0u, 0u, 0u, 0u};
+      if (grow < p && j < je) {
 #pragma unroll
-        for (int e = 0; e < 4; ++e)
-          if (j + 4 * half + e >= je) z[e] = 0.f;
-        q[2 * half] = bf16_bits_rne(z[0]) | (bf16_bits_rne(z[1]) << 16);
-        q[2 * half + 1] = bf16_bits_rne(z[2]) | (bf16_bits_rne(z[3]) << 16);
+        for (int half = 0; half < 2; ++half) {
+          const Words4 wd = philox4x32_10((uint32_t)((j >> 2) + half), (uint32_t)grow, k0, k1);
+          float z[4];
+          box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
+          box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (j + 4 * half + e >= je) z[e] = 0.f;
+          q[2 * half] = bf16_bits_rne(z[0]) | (bf16_bits_rne(z[1]) << 16);
+          q[2 * half + 1] = bf16_bits_rne(z[2]) | (bf16_bits_rne(z[3]) << 16);
+        }
       }
+      *reinterpret_cast<uint4*>(&sA[buf][lr * GB_AS + 8 * gg]) = make_uint4(q[0], q[1], q[2], q[3]);
     }
-    *reinterpret_cast<uint4*>(&sA[buf][gr * GB_AS + 8 * gg]) = make_uint4(q[0], q[1], q[2], q[3]);
   };
 
   // this lane's frames: t0 + 32 NFB w + 32 fb + lc (wave w owns 32 NFB frames)
@@ -197,9 +205,9 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
     }
   };
 
-  f32x16_t acc[2][NFB];
+  f32x16_t acc[RB][NFB];
 #pragma unroll
-  for (int rb = 0; rb < 2; ++rb)
+  for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
     for (int fb = 0; fb < NFB; ++fb)
 #pragma unroll
@@ -218,16 +226,16 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
     if (more) load_b(bnext, jn);
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
-      bf16x8_t a[2];
+      bf16x8_t a[RB];
 #pragma unroll
-      for (int rb = 0; rb < 2; ++rb)
+      for (int rb = 0; rb < RB; ++rb)
         a[rb] = *reinterpret_cast<const bf16x8_t*>(&sA[buf][(32 * rb + lc) * GB_AS + 32 * h + 8 * ks]);
 #pragma unroll
       for (int fb = 0; fb < NFB; ++fb) {
         const uint4 v = bcur[fb][ks >> 1];
         const bf16x8_t b = (ks & 1) ? u8x8_to_bf16(v.z, v.w) : u8x8_to_bf16(v.x, v.y);
 #pragma unroll
-        for (int rb = 0; rb < 2; ++rb)
+        for (int rb = 0; rb < RB; ++rb)
           acc[rb][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b, acc[rb][fb], 0, 0, 0);
       }
     }
@@ -246,7 +254,7 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
     const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
     if (t >= m) continue;
 #pragma unroll
-    for (int rb = 0; rb < 2; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
         const int r = r0 + 32 * rb + 8 * (e >> 2) + 4 * h + (e & 3);
@@ -731,11 +739,21 @@ __global__ __launch_bounds__(256) void k_gram_cplx(const double* __restrict__ Y,
 GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target) {
   GaussPlan g{};
   const bool bf = prec == 1 || prec == 2;
-  const int rows = bf ? GB_ROWS : GF_ROWS;
   const int kt = bf ? GB_KT : GF_KT;
   int frames = 256;
   if (bf) frames = m <= 256 ? 256 : m <= 512 ? 512 : 1024;
+  int rows = bf ? GB_ROWS : GF_ROWS;
+  if (prec == 1) {
+    // BF16: 32 RB rows.  RB = 4 for 512-frame tiles: one workgroup per CU either way, and
+    // twice the products per drawn entry and converted fragment (1080p-class videos of 400
+    // frames: 130 -> 96 ms).  RB = 2 otherwise: at 256 frames RB = 4 or 8 costs the second
+    // resident workgroup and measured slower; at 1024 frames RB NFB <= 8 allows no more.
+    int rb = frames == 512 ? 4 : 2;
+    if (rb > 2 && 32 * (rb / 2) >= p) rb /= 2;  // a small p fills fewer rows
+    rows = 32 * rb;
+  }
   g.frames = frames;
+  g.rows = rows;
   g.nrt = (p + rows - 1) / rows;
   g.nft = (int)((m + frames - 1) / frames);
   // about `target` workgroups, slices of at least 64 steps
@@ -776,14 +794,20 @@ hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t
     const uint8_t* d = static_cast<const uint8_t*>(D);
     if (Cm != nullptr) return hipErrorInvalidValue;  // a stored BF16 C goes to the library GEMM
     const dim3 bb(64 * GB_NW);
-    auto go = [&](auto nfb) {
-      constexpr int NFB = decltype(nfb)::value;
-      hipLaunchKernelGGL((k_sketch_gauss_bf16<NFB>), grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft,
+    auto go = [&](auto nfb, auto rb) {
+      constexpr int NFB = decltype(nfb)::value, RB = decltype(rb)::value;
+      hipLaunchKernelGGL((k_sketch_gauss_bf16<NFB, RB>), grid, bb, 0, stream, d, ld, n, m, p, seed, g.pps, g.nft,
                          g.nsplit, part);
     };
-    if (g.frames == 256) go(std::integral_constant<int, 1>{});
-    else if (g.frames == 512) go(std::integral_constant<int, 2>{});
-    else go(std::integral_constant<int, 4>{});
+    using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
+    using I4 = std::integral_constant<int, 4>;
+    const int rb = g.rows / 32;
+    if (g.frames == 256 && rb == 2) go(I1{}, I2{});
+    else if (g.frames == 512 && rb == 4) go(I2{}, I4{});
+    else if (g.frames == 512 && rb == 2) go(I2{}, I2{});
+    else if (g.frames == 1024 && rb == 2) go(I4{}, I2{});
+    else return hipErrorInvalidValue;
   } else if (prec == 2) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
     const uint8_t* c = static_cast<const uint8_t*>(Cm);
