@@ -22,9 +22,9 @@
 //  * FP8: as BF16 with the normals rounded to OCP e4m3 and each pixel byte split into
 //    two exact e4m3 operands (16 hi, lo) on FP8 MFMA.
 //
-// Work split: a workgroup owns 64 sketch rows x a tile of frames (up to 1024) x a slice
-// of pixels.
-// It draws its 64-row C tile once per pixel step into LDS (each entry drawn once per
+// Work split (BF16 / FP8 forms): a workgroup owns a tile of sketch rows (64, or 128 for
+// the BF16 form's 512-frame tiles) x a tile of frames (256, 512 or 1024) x a slice of
+// pixels.  It draws its C tile once per pixel step into LDS (each entry drawn once per
 // frame tile) and reads the video bytes straight into MFMA operands.  Blocks are dealt to
 // the eight XCDs in turn, so block b runs on XCD b mod 8; its index b / 8 there picks the
 // row tile (fastest) and the (slice, frame tile) combination 8 (index / row tiles) +
