@@ -165,3 +165,44 @@ def test_srft_automatic_rank():
     for b, t0 in enumerate((0, 75)):
         kb = P.optimal_rank(Dg[t0:t0 + 75], n, 75, p, sketch=P.SKETCH_SRFT, idx=fr, seed=seed)[0]
         assert used[b] == max(1, min(kb, 74, p, 40)), (b, used[b], kb)
+
+
+@pytest.mark.timeout(600)
+def test_srft_at_the_sweep_size():
+    """The SRFT fit at the size the sensing sweep times (720x480x200 uint8, p = 1000).  The
+    sketch: per entry and part within 2^-16 ((|Re C_q| + |Im C_q|) |X|) of the oracle's
+    float64 FFT route (|C_q| accumulated in pixel chunks; float32 sums over slices of about
+    10^4 pixels put the Frobenius error near u sqrt(L), about 2e-6 here).  The small linear
+    algebra: eigenvalues within 1e-8 of the oracle's reduced operator on the device's own
+    sketch, and within 1e-6 (the FP32 form's target) of the oracle on its own sketch
+    (measured 4e-7)."""
+    _say("srft sweep size")
+    v = sv.make_video(sv.PRESETS["ctxB"])
+    D = v.D.numpy()
+    m, n = D.shape
+    p, k, seed = 1000, 20, 31017
+    fr = _freqs(n, p, 5)
+    mdl = P.Model(n, m, k, p, sketch=P.SKETCH_SRFT, idx=fr.reshape(p, 1), seed=seed)
+    mdl.fit(torch.from_numpy(D).cuda())
+    Yg = mdl.sketch()
+    Yr = R.sketch_srft(D, v.scale, fr, seed)
+    d = R.srft_diagonal(seed, n)
+    Yabs = np.zeros((p, m))
+    for j0 in range(0, n, 16384):
+        j1 = min(n, j0 + 16384)
+        j = np.arange(j0, j1, dtype=np.int64)
+        C = np.exp(-2j * np.pi * ((fr.astype(np.int64)[:, None] * j[None, :]) % n) / n) * d[None, j0:j1]
+        Yabs += (np.abs(C.real) + np.abs(C.imag)) @ (D[:, j0:j1].astype(np.float64).T * v.scale)
+    Yabs /= np.sqrt(p)
+    for part in (np.real, np.imag):
+        err = np.abs(part(Yg) - part(Yr))
+        assert (err <= 2.0 ** -16 * Yabs).all(), (err / Yabs).max()
+    _say("sketch Frobenius rel err", np.linalg.norm(Yg - Yr) / np.linalg.norm(Yr))
+    lam = mdl.modes()["lam"]
+    lam_d, _, _, _, _ = R.reduced_operator(Yg, k)
+    erel, _, _ = eig_rel_err(lam, lam_d)
+    assert erel.max() <= 1e-8, erel.max()
+    lam_r, _, _, _, _ = R.reduced_operator(Yr, k)
+    erel, _, _ = eig_rel_err(lam, lam_r)
+    _say("eig rel err against the FP64 oracle", float(erel.max()))
+    assert erel.max() <= 1e-6, erel.max()
