@@ -1611,9 +1611,12 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
   hipStream_t st = as_stream(stream);
   if (per_model)
     for (int i = 0; i < n; ++i) per_model[i] = CDMD_E_STATE;  // not attempted
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     if (B->models[i]->amp_compressed)
       return fail(CDMD_E_UNSUPPORTED, "amplitudes on the compressed modes are not built for batches");
+    if (B->models[i]->sgemm)  // a C stored after the batch was created
+      return fail(CDMD_E_UNSUPPORTED, "a stored BF16 C is streamed by a library GEMM, which batches do not capture");
+  }
   bool same = B->exec && (int)B->videos.size() == n && (int)B->stamps.size() == n &&
               std::equal(B->videos.begin(), B->videos.end(), d_videos, d_videos + n);
   for (int i = 0; same && i < n; ++i) same = B->stamps[i] == B->models[i]->stamp;

@@ -168,7 +168,13 @@ def test_stored_bf16_c_refused_in_batches():
     with pytest.raises(P.CdmdError, match="UNSUPPORTED"):
         P.Batch([g])
     g.store_measurement(False)
-    P.Batch([g]).close()
+    b = P.Batch([g])
+    # a C stored after the batch was made is refused at the fit
+    g.store_measurement(True)
+    D = torch.zeros((m, n), dtype=torch.uint8, device="cuda")
+    with pytest.raises(P.CdmdError, match="UNSUPPORTED"):
+        b.fit([D])
+    b.close()
 
 
 def test_stored_c_refused_for_other_sketches():
