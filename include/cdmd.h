@@ -194,14 +194,19 @@ cdmd_status cdmd_set_amplitudes(cdmd_model* mdl, int32_t space);
    p x n entries of the configured BF16 or FP8 form once (the same values, bit for bit,
    that the sketch otherwise draws on the fly) into memory it allocates and owns, and every
    later cdmd_fit streams them from HBM instead of drawing them.
-   * FP8: e4m3 codes, rows padded to a multiple of 64 pixels (p ceil(n/64) 64 bytes); the
-     sketch kernel reads them in place of its draws and its results do not change.
    * BF16: bfloat16 bits stored pixel-major; each fit converts the video to exact bfloat16
      in S <= 32 pixel slices and forms the sketch as S batched library GEMMs (hipBLASLt,
      float32 accumulation and output) summed over the slices in float64.  Needs 2 p n + 2 m n
      bytes (plus padding to S slices of a multiple of 64 pixels) and S m p floats; the
      sketch equals the drawn form's up to the float32 summation order (not bit for bit).
-     Models with a stored BF16 C are refused by cdmd_batch_create.
+   * FP8: e4m3 codes stored pixel-major; each fit splits every video byte u = 16 hi + lo
+     into the two exact e4m3 codes of 16 hi and lo and forms the sketch as two batched
+     library GEMMs (e4m3 inputs, float32 output, the second added into the first).  Needs
+     p n + 2 m n bytes and S m p floats; equal to the drawn form's up to the summation order.
+     Where the library offers no FP8 GEMM for the shape, the codes are stored row-major
+     (rows padded to 64 pixels) and the sketch kernel reads them in place of its draws, bit
+     for bit the drawn form.
+   Models whose stored C goes through the library GEMM are refused by batches.
    on = 0 frees the copy.  Work goes on `stream`, which the call synchronises.  Errors:
    INVALID_ARG (NULL), UNSUPPORTED (not a Gaussian sketch in the BF16 or FP8 form, or no
    library GEMM for the shape), OUT_OF_MEMORY, DEVICE. */

@@ -99,8 +99,9 @@ struct cdmd_model {
   float* d_gpart = nullptr;         // per-slice partial sketches
   void* d_Cm = nullptr;             // the stored C (cdmd_store_measurement), or null: drawn
   int64_t Cm_ldc = 0;
-  // BF16 form with a stored C: C pixel-major in d_Cm, the video as bfloat16 slices in d_Xs,
-  // the sketch as gm_S batched library GEMMs over slices of gm_Ks pixels
+  // BF16 / FP8 form with a stored C through the library GEMM: C pixel-major in d_Cm, the
+  // video converted into slices in d_Xs (bfloat16, or the two e4m3 parts of each byte), the
+  // sketch as gm_S batched library GEMMs over slices of gm_Ks pixels
   cdmd::blas::SketchGemm* sgemm = nullptr;
   void* d_Xs = nullptr;
   int gm_S = 0;
@@ -469,6 +470,27 @@ std::vector<int> canonical_order(const std::vector<cplx>& lam, const std::vector
 hipStream_t as_stream(void* s) { return reinterpret_cast<hipStream_t>(s); }
 
 // Sketch + Gram + D2H of the Gram.
+// The dense sketch with a stored C through the library GEMM: the video converted into the
+// split layout (exact bfloat16, or the two e4m3 parts of each byte), the batched products
+// (for FP8: 16 hi, then lo added), and the float64 sum over the slices.
+cdmd_status gemm_sketch(cdmd_model* M, const void* d_video, hipStream_t st) {
+  const size_t half = (size_t)M->gm_S * M->m * M->gm_Ks;  // elements of one converted copy
+  if (gauss_prec(M->cfg) == 1) {
+    HIPCHK(cdmd::k::video_bf16_split(d_video, M->ld, M->n, M->m, M->gm_Ks, M->gm_S, M->d_Xs, st));
+    if (!cdmd::blas::sketch_gemm_run(M->sgemm, M->d_Cm, M->d_Xs, M->d_gpart, st))
+      return fail(CDMD_E_DEVICE, "the sketch GEMM failed");
+  } else {
+    uint8_t* xh = static_cast<uint8_t*>(M->d_Xs);
+    HIPCHK(cdmd::k::video_fp8_split(d_video, M->ld, M->n, M->m, M->gm_Ks, M->gm_S, xh, xh + half, st));
+    if (!cdmd::blas::sketch_gemm_run(M->sgemm, M->d_Cm, xh, M->d_gpart, st) ||
+        !cdmd::blas::sketch_gemm_run(M->sgemm, M->d_Cm, xh + half, M->d_gpart, st, true))
+      return fail(CDMD_E_DEVICE, "the sketch GEMM failed");
+  }
+  HIPCHK(cdmd::k::reduce_gauss(M->d_gpart, M->gm_S, M->m * (int64_t)M->p, 1.0 / std::sqrt((double)M->p), M->d_Yd,
+                               st));
+  return CDMD_OK;
+}
+
 cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool to_host) {
   const cdmd_config& c = M->cfg;
   M->mark(0, st);
@@ -481,11 +503,7 @@ cdmd_status run_sketch(cdmd_model* M, const void* d_video, hipStream_t st, bool 
     if (c.sketch_prec != CDMD_PREC_FP32 && (reinterpret_cast<uintptr_t>(d_video) & 15) != 0)
       return fail(CDMD_E_UNSUPPORTED, "the BF16 / FP8 Gaussian sketch needs a 16-byte aligned video");
     if (M->sgemm) {
-      HIPCHK(cdmd::k::video_bf16_split(d_video, M->ld, M->n, M->m, M->gm_Ks, M->gm_S, M->d_Xs, st));
-      if (!cdmd::blas::sketch_gemm_run(M->sgemm, M->d_Cm, M->d_Xs, M->d_gpart, st))
-        return fail(CDMD_E_DEVICE, "the sketch GEMM failed");
-      HIPCHK(cdmd::k::reduce_gauss(M->d_gpart, M->gm_S, M->m * (int64_t)M->p, 1.0 / std::sqrt((double)M->p),
-                                   M->d_Yd, st));
+      TRY(gemm_sketch(M, d_video, st));
     } else {
       HIPCHK(cdmd::k::sketch_gauss(d_video, c.dtype == CDMD_U8 ? 0 : 1, M->ld, M->n, M->m, M->p, c.seed,
                                    gauss_prec(c), M->gplan, M->d_Cm, M->Cm_ldc, M->d_gpart, M->d_Yd, st));
@@ -1324,6 +1342,7 @@ struct TuneChoice {
   int lift_grid = 0;
   int gauss_target = 0;
   int sparse_form = 0;  // 0 untuned, -1 gather, else 10 F + V (streaming)
+  int gemm_algo = -1;   // the stored-C sketch GEMM's candidate, or -1 untuned
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneChoice> g_tune;
@@ -1416,6 +1435,18 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
         if (ms < best) best = ms, ch.lift_grid = g;
       }
     }
+    if (M->sgemm) {
+      // the library's candidate GEMM algorithms on this video (conversion, products, sum)
+      double best = 1e300;
+      for (int i = 0; i < cdmd::blas::sketch_gemm_candidates(M->sgemm); ++i) {
+        (void)cdmd::blas::sketch_gemm_select(M->sgemm, i);
+        double ms = 0.0;
+        const cdmd_status r = time_ms(st, 2, [&] { return gemm_sketch(M, d_video, st); }, &ms);
+        if (r == CDMD_OK && ms < best) best = ms, ch.gemm_algo = i;
+      }
+      g_err.clear();
+      if (ch.gemm_algo < 0) return fail(CDMD_E_DEVICE, "no sketch GEMM candidate ran");
+    }
     if (M->gauss && !M->sgemm) {
       double best = 1e300;
       for (int target : {512, 1024, 2048}) {
@@ -1449,7 +1480,8 @@ cdmd_status cdmd_autotune(cdmd_model* M, const void* d_video, void* stream) {
   }
   if (ch.sparse_form != 0) TRY(apply_sparse_form(M, ch.sparse_form));
   if (ch.lift_grid > 0) M->lm_grid = ch.lift_grid;
-  if (ch.gauss_target > 0) TRY(apply_gauss_target(M, ch.gauss_target));
+  if (ch.gauss_target > 0 && !M->sgemm) TRY(apply_gauss_target(M, ch.gauss_target));
+  if (ch.gemm_algo >= 0 && M->sgemm) (void)cdmd::blas::sketch_gemm_select(M->sgemm, ch.gemm_algo);
   M->tuned = true;
   ++M->stamp;
   M->info.lift_grid = M->lift_real ? M->lr_grid : M->lm_grid;
@@ -1515,7 +1547,7 @@ cdmd_status cdmd_batch_create(cdmd_model* const* models, int32_t n, cdmd_batch**
       return fail(CDMD_E_UNSUPPORTED, "batches fit on the full modes (cdmd_set_amplitudes FULL)");
     if (models[i]->srft) return fail(CDMD_E_UNSUPPORTED, "SRFT models are fitted one at a time");
     if (models[i]->sgemm)
-      return fail(CDMD_E_UNSUPPORTED, "a stored BF16 C is streamed by a library GEMM, which batches do not capture");
+      return fail(CDMD_E_UNSUPPORTED, "a stored C is streamed by a library GEMM, which batches do not capture");
   }
   std::unique_ptr<cdmd_batch> B(new (std::nothrow) cdmd_batch());
   if (!B) return fail(CDMD_E_OUT_OF_MEMORY, "host allocation failed");
@@ -1615,7 +1647,7 @@ cdmd_status cdmd_batch_fit(cdmd_batch* B, const void* const* d_videos, void* str
     if (B->models[i]->amp_compressed)
       return fail(CDMD_E_UNSUPPORTED, "amplitudes on the compressed modes are not built for batches");
     if (B->models[i]->sgemm)  // a C stored after the batch was created
-      return fail(CDMD_E_UNSUPPORTED, "a stored BF16 C is streamed by a library GEMM, which batches do not capture");
+      return fail(CDMD_E_UNSUPPORTED, "a stored C is streamed by a library GEMM, which batches do not capture");
   }
   bool same = B->exec && (int)B->videos.size() == n && (int)B->stamps.size() == n &&
               std::equal(B->videos.begin(), B->videos.end(), d_videos, d_videos + n);
@@ -2367,9 +2399,10 @@ cdmd_status cdmd_store_measurement(cdmd_model* M, int32_t on, void* stream) {
     *d = nullptr;
     return false;
   };
-  if (prec == 1) {
-    // BF16: C pixel-major for the library GEMM, the video converted into S slices of Ks
-    // pixels per fit (S up to 32 so that the products fill the device)
+  {
+    // C pixel-major for the library GEMM, the video converted into S slices of Ks pixels per
+    // fit (S up to 32 so that the products fill the device): 2 bytes per element for BF16,
+    // for FP8 one byte of C and the two e4m3 parts of each video byte
     const int S = (int)std::min<int64_t>(32, std::max<int64_t>(1, (M->n + 262143) / 262144));
     const int64_t Ks = ((M->n + S - 1) / S + 63) / 64 * 64;
     const int64_t jn = S * Ks;
@@ -2382,26 +2415,28 @@ cdmd_status cdmd_store_measurement(cdmd_model* M, int32_t on, void* stream) {
       M->d_gpart = np;
       M->gpart_cap = need_part;
     }
-    if (!grab(&M->d_Cm, (size_t)jn * M->p * 2) || !grab(&M->d_Xs, (size_t)jn * M->m * 2)) {
+    if (!grab(&M->d_Cm, (size_t)jn * M->p * (prec == 1 ? 2 : 1)) || !grab(&M->d_Xs, (size_t)jn * M->m * 2)) {
       (void)release();
-      return fail(CDMD_E_OUT_OF_MEMORY, "no device memory for the stored C and the bfloat16 video");
+      return fail(CDMD_E_OUT_OF_MEMORY, "no device memory for the stored C and the converted video");
     }
     M->gm_S = S;
     M->gm_Ks = Ks;
-    const hipError_t e = cdmd::k::gauss_fill_t(M->d_Cm, jn, M->n, M->p, M->cfg.seed, st);
+    const hipError_t e = prec == 1 ? cdmd::k::gauss_fill_t(M->d_Cm, jn, M->n, M->p, M->cfg.seed, st)
+                                   : cdmd::k::gauss_fill_fp8_t(M->d_Cm, jn, M->n, M->p, M->cfg.seed, st);
     if (e != hipSuccess || hipStreamSynchronize(st) != hipSuccess) {
       (void)release();
       return fail(CDMD_E_DEVICE, "filling the stored C failed");
     }
     std::string err;
-    M->sgemm = cdmd::blas::sketch_gemm_create(M->p, Ks, M->m, S, &err);
-    if (!M->sgemm) {
-      (void)release();
-      return fail(CDMD_E_UNSUPPORTED, err.c_str());
+    M->sgemm = cdmd::blas::sketch_gemm_create(M->p, Ks, M->m, S, prec == 1 ? 0 : 1, &err);
+    if (M->sgemm) {
+      M->Cm_ldc = 0;
+      ++M->stamp;
+      return CDMD_OK;
     }
-    M->Cm_ldc = 0;
-    ++M->stamp;
-    return CDMD_OK;
+    (void)release();
+    if (prec == 1) return fail(CDMD_E_UNSUPPORTED, err.c_str());
+    // FP8 without a library GEMM for the shape: the sketch kernel streams a row-major copy
   }
   const int64_t ldc = cdmd::k::gauss_ldc(M->n);
   const size_t bytes = (size_t)M->p * (size_t)ldc;

@@ -80,6 +80,12 @@ hipError_t gauss_fill_t(void* Ct, int64_t jn, int64_t n, int p, uint64_t seed, h
 hipError_t video_bf16_split(const void* D, int64_t ld, int64_t n, int64_t m, int64_t Ks, int S, void* Xs,
                             hipStream_t stream);
 hipError_t reduce_gauss(const float* part, int nsplit, int64_t count, double scale, double* Y, hipStream_t stream);
+// The FP8 form's counterparts: C pixel-major as e4m3 codes (the drawn form's, bit for bit),
+// and each video byte u = 16 hi + lo as the two exact e4m3 codes of 16 hi (Xh) and lo (Xl)
+// in the same split layout.
+hipError_t gauss_fill_fp8_t(void* Ct, int64_t jn, int64_t n, int p, uint64_t seed, hipStream_t stream);
+hipError_t video_fp8_split(const void* D, int64_t ld, int64_t n, int64_t m, int64_t Ks, int S, void* Xh, void* Xl,
+                           hipStream_t stream);
 hipError_t gauss_fill(void* Cm, int64_t ldc, int64_t n, int p, uint64_t seed, int prec, hipStream_t stream);
 
 // ----- learned selector (mlp.hip) -------------------------------------------------

@@ -672,6 +672,58 @@ __global__ __launch_bounds__(256) void k_gauss_fill_bf16_t(uint16_t* __restrict_
   }
 }
 
+// The FP8 form's C for the library GEMM, pixel-major e4m3 codes Ct[j][r] (rows j >= n zero),
+// the drawn form's entries bit for bit.
+__global__ __launch_bounds__(256) void k_gauss_fill_fp8_t(uint8_t* __restrict__ Ct, int64_t jn, int64_t n, int p,
+                                                          uint64_t seed) {
+  const uint32_t k0 = (uint32_t)seed, k1 = (uint32_t)(seed >> 32);
+  const int64_t total = (jn / 4) * p;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int r = (int)(it % p);
+    const int64_t j0 = (it / p) * 4;
+    float z[4] = {0.f, 0.f, 0.f, 0.f};
+    if (j0 < n) {
+      const Words4 wd = philox4x32_10((uint32_t)(j0 >> 2), (uint32_t)r, k0, k1);
+      box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
+      box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) Ct[(j0 + e) * p + r] = j0 + e < n ? (uint8_t)e4m3_rne(z[e]) : (uint8_t)0;
+  }
+}
+
+// Video bytes u = 16 hi + lo as two exact e4m3 parts in the GEMM's split layout:
+// Xh[s][t][i] = code(16 hi), Xl[s][t][i] = code(lo) of pixel s Ks + i (zero past the frame).
+__global__ __launch_bounds__(256) void k_video_fp8_split(const uint8_t* __restrict__ D, int64_t ld, int64_t n,
+                                                         int64_t m, int64_t Ks, int S, uint8_t* __restrict__ Xh,
+                                                         uint8_t* __restrict__ Xl) {
+  const int64_t per = Ks / 8, total = (int64_t)S * m * per;
+  for (int64_t it = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; it < total;
+       it += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t st = it / per, i = (it % per) * 8;
+    const int64_t s = st / m, t = st % m, j = s * Ks + i;
+    const uint8_t* src = D + t * ld + j;
+    uint32_t b[2] = {0u, 0u};
+    if (j + 8 <= n) {
+      const uint2 v = *reinterpret_cast<const uint2*>(src);
+      b[0] = v.x;
+      b[1] = v.y;
+    } else {
+      for (int e = 0; e < 8 && j + e < n; ++e) b[e >> 2] |= (uint32_t)src[e] << (8 * (e & 3));
+    }
+    uint32_t hw[2] = {0u, 0u}, lw[2] = {0u, 0u};
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const uint32_t u = (b[e >> 2] >> (8 * (e & 3))) & 0xffu;
+      hw[e >> 2] |= e4m3_rne(16.0f * (float)(u >> 4)) << (8 * (e & 3));
+      lw[e >> 2] |= e4m3_rne((float)(u & 15u)) << (8 * (e & 3));
+    }
+    *reinterpret_cast<uint2*>(Xh + st * Ks + i) = make_uint2(hw[0], hw[1]);
+    *reinterpret_cast<uint2*>(Xl + st * Ks + i) = make_uint2(lw[0], lw[1]);
+  }
+}
+
 // Video bytes to exact bfloat16 in the GEMM's split layout: Xs[s][t][i] = x(t, s Ks + i),
 // zero past the frame.  8 pixels per thread (frames 16-byte aligned, Ks a multiple of 64).
 __global__ __launch_bounds__(256) void k_video_bf16_split(const uint8_t* __restrict__ D, int64_t ld, int64_t n,
@@ -893,6 +945,26 @@ hipError_t gauss_fill_t(void* Ct, int64_t jn, int64_t n, int p, uint64_t seed, h
   if (blocks > 65536) blocks = 65536;
   hipLaunchKernelGGL(k_gauss_fill_bf16_t, dim3((unsigned)blocks), dim3(256), 0, stream, static_cast<uint16_t*>(Ct), jn,
                      n, p, seed);
+  return hipGetLastError();
+}
+
+hipError_t gauss_fill_fp8_t(void* Ct, int64_t jn, int64_t n, int p, uint64_t seed, hipStream_t stream) {
+  if (jn % 4 != 0 || jn < n) return hipErrorInvalidValue;
+  int64_t blocks = ((jn / 4) * p + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_gauss_fill_fp8_t, dim3((unsigned)blocks), dim3(256), 0, stream, static_cast<uint8_t*>(Ct),
+                     jn, n, p, seed);
+  return hipGetLastError();
+}
+
+hipError_t video_fp8_split(const void* D, int64_t ld, int64_t n, int64_t m, int64_t Ks, int S, void* Xh, void* Xl,
+                           hipStream_t stream) {
+  if (Ks % 64 != 0 || ld % 16 != 0 || (reinterpret_cast<uintptr_t>(D) & 15) != 0) return hipErrorInvalidValue;
+  int64_t blocks = ((int64_t)S * m * (Ks / 8) + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  hipLaunchKernelGGL(k_video_fp8_split, dim3((unsigned)blocks), dim3(256), 0, stream,
+                     static_cast<const uint8_t*>(D), ld, n, m, Ks, S, static_cast<uint8_t*>(Xh),
+                     static_cast<uint8_t*>(Xl));
   return hipGetLastError();
 }
 

@@ -119,7 +119,7 @@ def video_4k():
 
 
 @pytest.mark.timeout(1200)
-@pytest.mark.parametrize("prec", ["bf16", "bf16_stored", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "bf16_stored", "fp8", "fp8_stored"])
 def test_4k_sketch_sampled_rows_per_entry(prec, video_4k):
     """The full 3840x2160x1000 precision workload: rows 0, 1999 and 3999 of the sketch
     against the oracle on the same quantised C, per entry; "bf16_stored" is the form the
@@ -129,8 +129,8 @@ def test_4k_sketch_sampled_rows_per_entry(prec, video_4k):
     m, n = Dg.shape
     p, seed = 4000, 3
     mdl = P.Model(n, m, 40, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=seed,
-                  sketch_prec=P.PREC_FP8 if prec == "fp8" else P.PREC_BF16)
-    if prec == "bf16_stored":
+                  sketch_prec=P.PREC_FP8 if prec.startswith("fp8") else P.PREC_BF16)
+    if prec.endswith("_stored"):
         mdl.store_measurement(True)
     _say("fit")
     try:
@@ -139,7 +139,7 @@ def test_4k_sketch_sampled_rows_per_entry(prec, video_4k):
         _say("fit status", e)
     Yg = mdl.sketch()
     rows = [0, 1999, 3999]
-    quant = R.round_e4m3 if prec == "fp8" else R.round_bf16
+    quant = R.round_e4m3 if prec.startswith("fp8") else R.round_bf16
     step = 1 << 20
     _say("oracle rows")
     chunks = ((j0, Dg[:, j0:min(n, j0 + step)].cpu().numpy()) for j0 in range(0, n, step))
@@ -150,7 +150,7 @@ def test_4k_sketch_sampled_rows_per_entry(prec, video_4k):
 
 
 @pytest.mark.timeout(900)
-@pytest.mark.parametrize("prec", ["bf16", "bf16_stored", "fp8"])
+@pytest.mark.parametrize("prec", ["bf16", "bf16_stored", "fp8", "fp8_stored"])
 def test_precision_workload_reduced_frame(prec):
     """p = 4000, m = 1000, k = 40 as in the 4K workload, on 48x64 frames (n = 3072 >= m) of
     the same generator: eigenvalues within 1e-3 of the oracle on the same quantised C, masks
@@ -162,11 +162,11 @@ def test_precision_workload_reduced_frame(prec):
     D = v.D.numpy()
     m, n = D.shape
     p, k, seed, K, tau = 4000, 40, 3, 10, 0.1
-    quant = R.round_e4m3 if prec == "fp8" else R.round_bf16
+    quant = R.round_e4m3 if prec.startswith("fp8") else R.round_bf16
     Dg = torch.from_numpy(D).cuda()
     mdl = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, dtype=P.U8, seed=seed,
-                  sketch_prec=P.PREC_FP8 if prec == "fp8" else P.PREC_BF16)
-    if prec == "bf16_stored":
+                  sketch_prec=P.PREC_FP8 if prec.startswith("fp8") else P.PREC_BF16)
+    if prec.endswith("_stored"):
         mdl.store_measurement(True)
     mdl.fit(Dg)
     _say("oracle")
