@@ -305,6 +305,23 @@ cdmd_status cdmd_batch_create(cdmd_model* const* models, int32_t n, cdmd_batch**
    cdmd_fit. */
 cdmd_status cdmd_batch_fit(cdmd_batch* batch, const void* const* d_videos, void* stream,
                            cdmd_status* per_model);
+/* The foreground masks of every model of the batch (Section 4, eq. (eq:thres), on the
+   reconstruction of eq. (equ:DMDTerms) with the selected modes), as cdmd_foreground with
+   bitpacked = 1 for each, in one work-queue launch over the (model, pixel tile) pairs of
+   all models of a reconstruction form and tile size (at most 64 models each) instead of
+   one launch per model: the Vandermonde
+   operands of each model are formed on the device, then every tile of every model is
+   reconstructed and thresholded.  d_videos[i] is the video models[i] was fitted on,
+   d_masks[i] its mask (device, ceil(n_i/32) uint32 words per frame, m_i frames, the
+   layout of cdmd_foreground).  Each mask equals cdmd_foreground's bit for bit.  Models
+   whose reconstruction takes the VALU form (more than 16 selected modes, float32 videos,
+   too many frames for the tile in LDS) are launched one by one.  Every model must have
+   been selected (cdmd_select or cdmd_select_learned).  Enqueued on `stream`; does not
+   synchronise it (a later call waits on the device for this one's work lists, and on the
+   host only for their copy).  Errors: INVALID_ARG (NULL argument, tau < 0), STATE (a
+   model not selected), NUMERIC (|lambda|^(m-1) overflow), DEVICE. */
+cdmd_status cdmd_batch_foreground(cdmd_batch* batch, const void* const* d_videos, float tau,
+                                  int32_t static_bg, void* const* d_masks, void* stream);
 void cdmd_batch_free(cdmd_batch* batch);
 
 /* ---- long videos -------------------------------------------------------------------

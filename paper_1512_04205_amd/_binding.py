@@ -36,6 +36,7 @@ EXPORTED = [
     "cdmd_dbg_force_gather_sketch", "cdmd_dbg_sparse_form", "cdmd_dbg_rank_threshold",
     "cdmd_mode_features", "cdmd_mlp_grad", "cdmd_mlp_train", "cdmd_mlp_train_noalloc", "cdmd_mlp_forward",
     "cdmd_select_learned", "cdmd_autotune", "cdmd_batch_create", "cdmd_batch_fit",
+    "cdmd_batch_foreground",
     "cdmd_batch_free", "cdmd_optimal_rank", "cdmd_store_measurement", "cdmd_process_video",
     "cdmd_video_create", "cdmd_video_run", "cdmd_video_free", "cdmd_dbg_herm_topk", "cdmd_dbg_eig_complex",
 ]
@@ -137,6 +138,7 @@ def load_library(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.cdmd_autotune.argtypes = [P, P, P]
     lib.cdmd_batch_create.argtypes = [ctypes.POINTER(P), I32, ctypes.POINTER(P)]
     lib.cdmd_batch_fit.argtypes = [P, ctypes.POINTER(P), P, ctypes.POINTER(I32)]
+    lib.cdmd_batch_foreground.argtypes = [P, ctypes.POINTER(P), ctypes.c_float, I32, ctypes.POINTER(P), P]
     lib.cdmd_batch_free.argtypes = [P]
     lib.cdmd_batch_free.restype = None
     lib.cdmd_free.argtypes = [P]
@@ -510,6 +512,16 @@ class Batch:
         st = (ctypes.c_int32 * len(self.models))()
         load_library().cdmd_batch_fit(self._h, vp, _stream(stream), st)
         return list(st)
+
+    def foreground(self, videos, masks, tau: float, static_bg: bool = False, stream=None):
+        """Bit-packed foreground masks of every (selected) model in one work-queue launch:
+        masks[i] (int32 device tensor of m_i x mask_words(n_i)) as models[i].foreground."""
+        vp = (ctypes.c_void_p * len(self.models))(
+            *[_video_ptr(v, m.dtype, m.n, m.m, m.ld) for v, m in zip(videos, self.models)])
+        mp = (ctypes.c_void_p * len(self.models))(
+            *[_tensor_ptr(mk, m.m * mask_words(m.n)).value for mk, m in zip(masks, self.models)])
+        _check(load_library().cdmd_batch_foreground(self._h, vp, float(tau), int(bool(static_bg)), mp,
+                                                    _stream(stream)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -1513,6 +1513,14 @@ struct cdmd_batch {
   int la_kmax = 0;                  // largest k of the batch
   hipStream_t cap = nullptr;        // the graph's own stream (capture needs a non-null stream)
   hipEvent_t entry = nullptr;       // caller's stream -> cap
+  // cdmd_batch_foreground's work lists: staged in pinned memory (rewritten once the last
+  // copy from it has completed) and read by the kernels from d_rwork (rewritten after the
+  // last launch that read it)
+  cdmd::k::ReconWork* h_rwork = nullptr;
+  cdmd::k::ReconWork* d_rwork = nullptr;
+  size_t rwork_cap = 0;
+  hipEvent_t rw_copied = nullptr, rw_read = nullptr;
+  bool rw_pending = false;
 
   void drop_graph() {
     if (exec) (void)hipGraphExecDestroy(exec);
@@ -1533,6 +1541,11 @@ struct cdmd_batch {
     if (entry) (void)hipEventDestroy(entry);
     if (cap) (void)hipStreamDestroy(cap);
     if (d_desc) (void)hipFree(d_desc);
+    if (rw_pending) (void)hipEventSynchronize(rw_read);
+    if (rw_copied) (void)hipEventDestroy(rw_copied);
+    if (rw_read) (void)hipEventDestroy(rw_read);
+    if (h_rwork) (void)hipHostFree(h_rwork);
+    if (d_rwork) (void)hipFree(d_rwork);
   }
 };
 
@@ -1569,6 +1582,13 @@ cdmd_status cdmd_batch_create(cdmd_model* const* models, int32_t n, cdmd_batch**
   HIPCHK(hipEventCreateWithFlags(&B->entry, hipEventDisableTiming));
   HIPCHK(hipStreamCreateWithFlags(&B->cap, hipStreamNonBlocking));
   TRY(dalloc(&B->d_desc, (size_t)n));
+  // work lists of cdmd_batch_foreground: at most two entries per model (its full tiles
+  // and its partial tile), room for twice that
+  B->rwork_cap = 4 * (size_t)n;
+  TRY(halloc(&B->h_rwork, B->rwork_cap));
+  TRY(dalloc(&B->d_rwork, B->rwork_cap));
+  HIPCHK(hipEventCreateWithFlags(&B->rw_copied, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&B->rw_read, hipEventDisableTiming));
   *out = B.release();
   return CDMD_OK;
 }
@@ -1968,6 +1988,109 @@ cdmd_status cdmd_foreground(const cdmd_model* Mc, const void* d_video, float tau
     HIPCHK(hipStreamSynchronize(st));
     std::memcpy(h_counts, M->h_counts, sizeof(int64_t) * M->m);
   }
+  return CDMD_OK;
+}
+
+cdmd_status cdmd_batch_foreground(cdmd_batch* B, const void* const* d_videos, float tau, int32_t static_bg,
+                                  void* const* d_masks, void* stream) {
+  g_err.clear();
+  if (!B || !d_videos || !d_masks) return fail(CDMD_E_INVALID_ARG, "NULL argument");
+  if (!(tau >= 0.f)) return fail(CDMD_E_INVALID_ARG, "tau must be >= 0");
+  const int n = (int)B->models.size();
+  for (int i = 0; i < n; ++i) {
+    if (!d_videos[i] || !d_masks[i]) return fail(CDMD_E_INVALID_ARG, "NULL video or mask in the batch");
+    if (!B->models[i]->selected) return fail(CDMD_E_STATE, "select background modes of every model first");
+  }
+  hipStream_t st = as_stream(stream);
+  // the staging may be rewritten once the previous call's copy has completed, and the
+  // device list once the previous call's kernels have read it
+  if (B->rw_pending) {
+    HIPCHK(hipEventSynchronize(B->rw_copied));
+    HIPCHK(hipStreamWaitEvent(st, B->rw_read, 0));
+    B->rw_pending = false;
+  }
+  const int64_t TP = cdmd::k::recon_tile_pixels();
+  // lists: q = 4 c + 2 f + r with the LDS class c (0: the tile's frames take at most
+  // 80 KiB, so that two workgroups share a CU, as the registers allow; 1: more), the
+  // reconstruction form f (0: NSG 2 / NTV 3, 1: NSG 1 / NTV 2) and r (0: the full tiles,
+  // 1: the partial tile); a launch's LDS is its largest entry's
+  constexpr int NL = 8;
+  std::vector<cdmd::k::ReconWork> lists[NL];
+  size_t lds[NL] = {};
+  for (int i = 0; i < n; ++i) {
+    cdmd_model* M = B->models[i];
+    int NS = 0;
+    TRY(prepare_recon(M, static_bg, &NS, st));
+    const int form = M->rc_nsg == 2 && M->rc_ntv == 3 ? 0 : M->rc_nsg == 1 && M->rc_ntv == 2 ? 1 : -1;
+    if (!M->recon_mfma || form < 0) {  // the VALU form, one launch per model
+      TRY(run_recon(M, d_videos[i], static_bg, NS, tau, 0, d_masks[i], 0, M->m, 0, st));
+      continue;
+    }
+    cdmd::k::ReconWork w{};
+    w.a.D = static_cast<const uint8_t*>(d_videos[i]);
+    w.a.ld = M->ld;
+    w.a.n = M->n;
+    w.a.m = M->m;
+    w.a.Gp = static_cast<const uint4*>(M->d_Gsp);
+    w.a.Vp = static_cast<const uint4*>(M->d_Rv);
+    w.a.KS = M->rc_ks;
+    w.a.NFB = M->rc_nfb;
+    w.a.ns = (int)M->S.size();
+    w.a.tau = tau;
+    w.a.xscale = M->xscale;
+    w.a.mode = 0;
+    w.a.out = d_masks[i];
+    w.a.t0 = 0;
+    w.a.t1 = M->m;
+    w.a.ldL = 0;
+    const size_t b = cdmd::k::recon_lds_bytes(M->m);
+    const int q0 = 4 * (b > (size_t)80 * 1024 ? 1 : 0) + 2 * form;
+    const int64_t full = M->n / TP;
+    if (full > 0) {
+      w.tile0 = 0;
+      lists[q0].push_back(w);
+      lds[q0] = std::max(lds[q0], b);
+    }
+    if (M->n % TP) {
+      w.tile0 = full;
+      lists[q0 + 1].push_back(w);
+      lds[q0 + 1] = std::max(lds[q0 + 1], b);
+    }
+  }
+  // launch c of list q: entries [c0, c0 + nw) with the launch's tile starts; all staged,
+  // one copy, then the launches
+  struct Launch {
+    int q, nw;
+    size_t off;
+    int64_t total;
+  };
+  std::vector<Launch> launches;
+  size_t off = 0;
+  for (int q = 0; q < NL; ++q) {
+    const size_t cnt = lists[q].size();
+    for (size_t c0 = 0; c0 < cnt; c0 += 64) {
+      const int nw = (int)std::min<size_t>(64, cnt - c0);
+      int64_t start = 0;
+      for (int e = 0; e < nw; ++e) {
+        cdmd::k::ReconWork w = lists[q][c0 + e];
+        w.start = start;
+        start += (q & 1) ? 1 : w.a.n / TP;
+        B->h_rwork[off + e] = w;
+      }
+      launches.push_back(Launch{q, nw, off, start});
+      off += nw;
+    }
+  }
+  if (off == 0) return CDMD_OK;
+  HIPCHK(hipMemcpyAsync(B->d_rwork, B->h_rwork, sizeof(cdmd::k::ReconWork) * off, hipMemcpyHostToDevice, st));
+  HIPCHK(hipEventRecord(B->rw_copied, st));
+  for (const Launch& L : launches) {
+    const int q = L.q, f = (q >> 1) & 1;
+    HIPCHK(cdmd::k::recon_mfma_list(B->d_rwork + L.off, L.nw, L.total, lds[q], f == 0 ? 2 : 1, f == 0 ? 3 : 2, 0,
+                                    (q & 1) != 0, st));
+  }
+  HIPCHK(hipEventRecord(B->rw_read, st));
+  B->rw_pending = true;
   return CDMD_OK;
 }
 

@@ -821,20 +821,14 @@ __device__ __forceinline__ void pin(bf16x8_t& v) {
   v = __builtin_bit_cast(bf16x8_t, u);
 }
 
-// MODE 0: bit-packed mask, 1: byte mask, 2: L.  RAGGED: the workgroup's 128 pixels run
-// past n (only the last one), so its loads and stores check every pixel.
+// One workgroup's tile: pixels [base, base + 128) of the reconstruction a.  MODE 0:
+// bit-packed mask, 1: byte mask, 2: L.  RAGGED: the tile runs past n (only the last one),
+// so its loads and stores check every pixel.
 template <int NSG, int NTV, int MODE, bool RAGGED>
-__global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0, int64_t ntiles) {
+__device__ __forceinline__ void recon_tile(const ReconArgs& a, const int64_t base) {
   extern __shared__ __align__(16) uint4 rc_lds[];
   uint8_t* sV = reinterpret_cast<uint8_t*>(rc_lds);
   const int tid = threadIdx.x, w = tid >> 6, l = tid & 63, h = l >> 5, fl = l & 31;
-  // Blocks are dealt to the eight XCDs in turn; XCD x takes the contiguous tiles
-  // [x per, (x + 1) per), so neighbouring tiles run together on one XCD and their 16-byte
-  // pieces of each frame's mask line meet in its L2 before they are written back.
-  const int64_t per = (ntiles + 7) / 8;
-  const int64_t tile = (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
-  if (tile >= ntiles) return;  // uniform
-  const int64_t base = (tile0 + tile) * RC_TP;
   const int64_t n = a.n, ld = a.ld;
   const int m = (int)a.m;
   const int KS = a.KS;               // 16-frame k-steps of phase 1, a multiple of 4
@@ -1050,6 +1044,42 @@ __global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0, int
   if (fbi < fb1) emit_any(fbi, Ca);
 }
 
+// Blocks are dealt to the eight XCDs in turn; XCD x takes the contiguous tiles
+// [x per, (x + 1) per), so neighbouring tiles run together on one XCD and their 16-byte
+// pieces of each frame's mask line meet in its L2 before they are written back.
+__device__ __forceinline__ int64_t recon_xcd_tile(int64_t ntiles) {
+  const int64_t per = (ntiles + 7) / 8;
+  return (int64_t)(blockIdx.x & 7) * per + (blockIdx.x >> 3);
+}
+
+// Tiles tile0 .. tile0 + ntiles - 1 of one reconstruction.
+template <int NSG, int NTV, int MODE, bool RAGGED>
+__global__ __launch_bounds__(RC_NT) void k_recon(ReconArgs a, int64_t tile0, int64_t ntiles) {
+  const int64_t tile = recon_xcd_tile(ntiles);
+  if (tile >= ntiles) return;  // uniform
+  recon_tile<NSG, NTV, MODE, RAGGED>(a, (tile0 + tile) * RC_TP);
+}
+
+// The tiles of several reconstructions in one launch (the masks of a batch of models):
+// entry e of the work list owns the launch's tiles [start_e, start_e + ntiles_e), which are
+// tiles tile0_e .. of its reconstruction; starts increase from 0, total = the last start
+// plus its tile count, nw <= 64.  The tiles are dealt to the XCDs in chunks of eight (the
+// tiles sharing a 128-byte line of each frame's mask stay on one XCD), chunk c to XCD
+// c mod 8, so every entry spreads over all XCDs whatever its cost per tile: block b =
+// 64 J + 8 r + x (XCD x) takes tile 64 J + 8 x + r.  A workgroup finds its entry with one
+// wave-wide comparison (lane e tests start_e <= tile: the set lanes are a prefix).
+template <int NSG, int NTV, int MODE, bool RAGGED>
+__global__ __launch_bounds__(RC_NT) void k_recon_list(const ReconWork* __restrict__ list, int nw, int64_t total) {
+  const int64_t b = blockIdx.x;
+  const int64_t tile = (b & ~(int64_t)63) + 8 * (b & 7) + ((b >> 3) & 7);
+  if (tile >= total) return;  // uniform
+  const int lane = threadIdx.x & 63;
+  const bool mine = lane < nw && list[lane].start <= tile;
+  const int e = __builtin_amdgcn_readfirstlane(__popcll(__ballot(mine)) - 1);
+  const ReconArgs a = list[e].a;
+  recon_tile<NSG, NTV, MODE, RAGGED>(a, (list[e].tile0 + tile - list[e].start) * RC_TP);
+}
+
 // Operands of k_recon, from G (N x k complex float64, row t at t*k, mode s in column
 // col[s]):
 //   Gp [KS + RC_PF][NSG][lane][8] bf16: element i of lane l is G~'[16ks + 8(l/32) + i][l%32]
@@ -1156,6 +1186,45 @@ static hipError_t launch_recon(const ReconArgs& a, size_t lds, hipStream_t s) {
   return hipSuccess;
 }
 
+template <int NSG, int NTV, int MODE, bool RAGGED>
+static hipError_t launch_recon_list(const ReconWork* list, int nw, int64_t total, size_t lds, hipStream_t s) {
+  static std::atomic<bool> attr{false};
+  if (!attr.load(std::memory_order_acquire)) {
+    const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_recon_list<NSG, NTV, MODE, RAGGED>),
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    if (e != hipSuccess) return e;
+    attr.store(true, std::memory_order_release);
+  }
+  const int64_t blocks = 64 * ((total + 63) / 64);
+  hipLaunchKernelGGL((k_recon_list<NSG, NTV, MODE, RAGGED>), dim3((unsigned)blocks), dim3(RC_NT), lds, s, list, nw,
+                     total);
+  return hipGetLastError();
+}
+
+hipError_t recon_mfma_list(const ReconWork* list, int nw, int64_t total, size_t lds, int nsg, int ntv, int mode,
+                           bool ragged, hipStream_t s) {
+  if (list == nullptr || nw < 1 || nw > 64 || total < 1 || total > ((int64_t)1 << 31) - 64 || lds > 160 * 1024 ||
+      mode < 0 || mode > 2)
+    return hipErrorInvalidValue;
+#define RL_MODE(G, T, R)                                                   \
+  if (mode == 0) return launch_recon_list<G, T, 0, R>(list, nw, total, lds, s); \
+  if (mode == 1) return launch_recon_list<G, T, 1, R>(list, nw, total, lds, s); \
+  return launch_recon_list<G, T, 2, R>(list, nw, total, lds, s);
+#define RL_CASE(G, T)                 \
+  if (nsg == G && ntv == T) {         \
+    if (ragged) {                     \
+      RL_MODE(G, T, true)             \
+    }                                 \
+    RL_MODE(G, T, false)              \
+  }
+  RL_CASE(2, 3)
+  RL_CASE(1, 2)
+#undef RL_CASE
+#undef RL_MODE
+  return hipErrorInvalidValue;
+}
+
+int recon_tile_pixels() { return RC_TP; }
 int recon_ksteps(int64_t m) { return (int)(4 * ((m + 63) / 64)); }
 int recon_frame_blocks(int64_t m) { return (int)((m + 31) / 32); }
 

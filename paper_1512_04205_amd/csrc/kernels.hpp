@@ -159,6 +159,21 @@ struct ReconArgs {
   int64_t t0, t1, ldL;
 };
 hipError_t recon_mfma(const ReconArgs& a, int nsg, int ntv, hipStream_t stream);
+// Pixels per workgroup tile of recon_mfma.
+int recon_tile_pixels();
+// One entry of a work list of reconstructions: tiles tile0 .. tile0 + ntiles - 1 of a are
+// tiles start .. start + ntiles - 1 of the launch.
+struct ReconWork {
+  ReconArgs a;
+  int64_t tile0, start;
+};
+// recon_mfma of up to 64 reconstructions in one launch over the tiles of all of them
+// (list in device memory, starts increasing from 0, total = the last start + its tile
+// count; every entry of the same NSG/NTV form and mode, already checked by the caller with
+// recon_mfma's rules; ragged: every entry is the one partial tile past its n).  lds: the
+// largest recon_lds_bytes over the entries.
+hipError_t recon_mfma_list(const ReconWork* list, int nw, int64_t total, size_t lds, int nsg, int ntv, int mode,
+                           bool ragged, hipStream_t stream);
 int recon_ksteps(int64_t m);        // 4 ceil(m / 64)
 int recon_frame_blocks(int64_t m);  // ceil(m / 32)
 // LDS bytes of one workgroup of recon_mfma (the form applies while this is <= 160 KiB).

@@ -149,3 +149,115 @@ def test_autotune_sparse_sketch_stays_exact():
     _, Yi = mdl.sketch(integer=True)
     _, Yiref = R.sketch_sparse(D, 1 / 255, idx, sign)
     np.testing.assert_array_equal(Yi, Yiref)
+
+
+# (kind, H, W, ld, m, k, p, lift precision): frame sizes with and without a partial
+# 128-pixel tile, padded frames, both reconstruction forms and one float32 video (whose
+# reconstruction takes the VALU form, launched on its own)
+FG_STREAMS = [
+    ("sparse", 48, 60, None, 40, 6, 200, "fp32"),      # 2880 px: 22 full tiles and half a tile
+    ("sparse", 40, 48, None, 50, 5, 150, "bf16"),      # 1920 px: full tiles only
+    ("sparse", 8, 12, None, 30, 3, 60, "fp32"),        # 96 px: one partial tile only
+    ("gauss_bf16", 37, 53, 1968, 45, 6, 120, "fp32"),  # padded frames, a partial tile
+    ("f32", 40, 64, None, 40, 6, 300, "fp32"),
+    ("sparse", 64, 96, None, 300, 8, 300, "bf16"),     # 300 frames: a larger tile in LDS
+    ("sparse", 30, 40, None, 70, 10, 250, "fp32"),
+]
+
+
+def _fg_make(i, kind, H, W, ld, m, k, p, lift):
+    n = H * W
+    ld = ld or n
+    out = "f32" if kind == "f32" else "u8"
+    spec = sv.preset("cfg2", H=H, W=W, m=m, n_pairs=2, bump_sigma=max(H, W) / 8.0, blur_sigma=2.0,
+                     n_rects=2, rect_side=(2, max(3, W // 6)), speed=(0.5, 2.0), seed=700 + i, out=out)
+    D = sv.make_video(spec, device="cuda").D
+    if ld != n:
+        Dp = torch.zeros((m, ld), dtype=D.dtype, device="cuda")
+        Dp[:, :n] = D
+        D = Dp
+    lp = P.PREC_BF16 if lift == "bf16" else P.PREC_FP32
+    if kind.startswith("gauss"):
+        mdl = P.Model(n, m, k, p, sketch=P.SKETCH_GAUSSIAN, ld=ld, seed=21 + i, sketch_prec=P.PREC_BF16, lift_prec=lp)
+    else:
+        idx, sign = sv.sparse_table(n, p, 32, 80 + i)
+        mdl = P.Model(n, m, k, p, dtype=P.F32 if kind == "f32" else P.U8, ld=ld, idx=idx, sign=sign, lift_prec=lp)
+    return D, mdl
+
+
+def _masks(models):
+    return [torch.full((mdl.m, P.mask_words(mdl.n)), -1, dtype=torch.int32, device="cuda") for mdl in models]
+
+
+def test_batch_foreground_equals_per_model_masks():
+    """cdmd_batch_foreground (one work-queue launch per reconstruction form over every
+    model's pixel tiles) gives each model's cdmd_foreground mask bit for bit: full and
+    partial tiles, padded frames, both reconstruction forms, the VALU form of a float32
+    video, the static model, and two calls back to back with no synchronisation between
+    them (the second with another tau)."""
+    _say("batch foreground")
+    made = [_fg_make(i, *s) for i, s in enumerate(FG_STREAMS)]
+    videos = [D for D, _ in made]
+    models = [mdl for _, mdl in made]
+    batch = P.Batch(models)
+    assert batch.fit(videos) == [P.OK] * len(models)
+    for mdl in models:
+        mdl.select(P.SEL_OMP, K=min(4, mdl.k))
+    for static in (False, True):
+        taus = (0.1, 0.05)
+        got = [_masks(models) for _ in taus]
+        for tau, mk in zip(taus, got):
+            batch.foreground(videos, mk, tau, static_bg=static)
+        torch.cuda.synchronize()
+        fg = 0
+        for tau, mk in zip(taus, got):
+            for q, (mdl, D, g) in enumerate(zip(models, videos, mk)):
+                ref = torch.full_like(g, -1)
+                mdl.foreground(D, ref, tau, static=static)
+                torch.cuda.synchronize()
+                assert torch.equal(g, ref), (q, FG_STREAMS[q], tau, static)
+                fg += int(ref.ne(0).sum())
+        assert fg > 0  # the masks hold foreground
+
+
+def test_batch_foreground_more_than_64_models():
+    """70 models share one video shape: the work list is split into launches of 64 entries;
+    every mask equals the model's own cdmd_foreground."""
+    _say("batch foreground, 70 models")
+    H, W, m = 24, 40, 36
+    n = H * W
+    spec = sv.preset("cfg2", H=H, W=W, m=m, n_pairs=2, bump_sigma=4.0, blur_sigma=2.0, n_rects=1,
+                     rect_side=(2, 5), seed=901)
+    D = sv.make_video(spec, device="cuda").D
+    models = []
+    for i in range(70):
+        idx, sign = sv.sparse_table(n, 80, 32, 1000 + i)
+        models.append(P.Model(n, m, 4, 80, idx=idx, sign=sign))
+    videos = [D] * len(models)
+    batch = P.Batch(models)
+    assert batch.fit(videos) == [P.OK] * len(models)
+    for mdl in models:
+        mdl.select(P.SEL_OMP, K=3)
+    got = _masks(models)
+    batch.foreground(videos, got, 0.1)
+    torch.cuda.synchronize()
+    for q, (mdl, g) in enumerate(zip(models, got)):
+        ref = torch.full_like(g, -1)
+        mdl.foreground(D, ref, 0.1)
+        torch.cuda.synchronize()
+        assert torch.equal(g, ref), q
+
+
+def test_batch_foreground_refusals():
+    _say("batch foreground refusals")
+    D, mdl = _fg_make(0, *FG_STREAMS[0])
+    batch = P.Batch([mdl])
+    assert batch.fit([D]) == [P.OK]
+    mk = _masks([mdl])
+    with pytest.raises(P.CdmdError) as e:   # not selected
+        batch.foreground([D], mk, 0.1)
+    assert e.value.status == P.E_STATE
+    mdl.select(P.SEL_OMP, K=3)
+    with pytest.raises(P.CdmdError) as e:
+        batch.foreground([D], mk, -1.0)
+    assert e.value.status == P.E_INVALID_ARG
