@@ -155,13 +155,28 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
   // drawing role: rows gr + 64 i (i < RB / 2), pixels 8 gg .. 8 gg + 7 of the step
   const int gr = tid >> 3, gg = tid & 7;
 
+  // Steps inside the slice in a row tile inside [0, p) (all but the last step of the last
+  // slice and the last row tile) take the branch-free forms of draw and load_b, chosen by
+  // a workgroup-uniform test.
+  const bool rows_in = r0 + ROWS <= p;
   auto draw = [&](int buf, int64_t j0) {
     const int64_t j = j0 + 8 * gg;
+    const bool inner = rows_in && j0 + GB_KT <= je;
 #pragma unroll
     for (int i = 0; i < RB / 2; ++i) {
       const int lr = gr + 64 * i, grow = r0 + lr;
       uint32_t q[4] = {0u, 0u, 0u, 0u};
-      if (grow < p && j < je) {
+      if (inner) {
+#pragma unroll
+        for (int half = 0; half < 2; ++half) {
+          const Words4 wd = philox4x32_10((uint32_t)((j >> 2) + half), (uint32_t)grow, k0, k1);
+          float z[4];
+          box_muller_f32(wd.w0, wd.w1, z[0], z[1]);
+          box_muller_f32(wd.w2, wd.w3, z[2], z[3]);
+          q[2 * half] = bf16_bits_rne(z[0]) | (bf16_bits_rne(z[1]) << 16);
+          q[2 * half + 1] = bf16_bits_rne(z[2]) | (bf16_bits_rne(z[3]) << 16);
+        }
+      } else if (grow < p && j < je) {
 #pragma unroll
         for (int half = 0; half < 2; ++half) {
           const Words4 wd = philox4x32_10((uint32_t)((j >> 2) + half), (uint32_t)grow, k0, k1);
@@ -183,6 +198,18 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
   uint4 bcur[NFB][2], bnext[NFB][2];
   auto load_b = [&](uint4 (*dst)[2], int64_t j0) {
     const int64_t j = j0 + 32 * h;
+    if (j0 + GB_KT <= je) {
+      // frames past m read frame m - 1 instead: finite bytes whose output columns are
+      // never stored (column t of each product depends on frame t alone)
+#pragma unroll
+      for (int fb = 0; fb < NFB; ++fb) {
+        const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
+        const uint4* src = reinterpret_cast<const uint4*>(D + (t < m ? t : m - 1) * ld + j);
+        dst[fb][0] = src[0];
+        dst[fb][1] = src[1];
+      }
+      return;
+    }
 #pragma unroll
     for (int fb = 0; fb < NFB; ++fb) {
       const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
@@ -362,6 +389,18 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* 
   uint4 bcur[NFB][2], bnext[NFB][2];
   auto load_b = [&](uint4 (*dst)[2], int64_t j0) {
     const int64_t j = j0 + 32 * h;
+    if (j0 + GB_KT <= je) {
+      // frames past m read frame m - 1 instead: finite bytes whose output columns are
+      // never stored (column t of each product depends on frame t alone)
+#pragma unroll
+      for (int fb = 0; fb < NFB; ++fb) {
+        const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
+        const uint4* src = reinterpret_cast<const uint4*>(D + (t < m ? t : m - 1) * ld + j);
+        dst[fb][0] = src[0];
+        dst[fb][1] = src[1];
+      }
+      return;
+    }
 #pragma unroll
     for (int fb = 0; fb < NFB; ++fb) {
       const int64_t t = t0 + 32 * NFB * w + 32 * fb + lc;
