@@ -250,23 +250,39 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_bf16(const uint8_t*
     const int buf = (int)(st & 1);
     const int64_t jn = jb + (st + 1) * GB_KT;
     const bool more = st + 1 < nsteps;
-    if (more) load_b(bnext, jn);
+    auto products = [&]() {
 #pragma unroll
-    for (int ks = 0; ks < 4; ++ks) {
-      bf16x8_t a[RB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb)
-        a[rb] = *reinterpret_cast<const bf16x8_t*>(&sA[buf][(32 * rb + lc) * GB_AS + 32 * h + 8 * ks]);
-#pragma unroll
-      for (int fb = 0; fb < NFB; ++fb) {
-        const uint4 v = bcur[fb][ks >> 1];
-        const bf16x8_t b = (ks & 1) ? u8x8_to_bf16(v.z, v.w) : u8x8_to_bf16(v.x, v.y);
+      for (int ks = 0; ks < 4; ++ks) {
+        bf16x8_t a[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
-          acc[rb][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b, acc[rb][fb], 0, 0, 0);
+          a[rb] = *reinterpret_cast<const bf16x8_t*>(&sA[buf][(32 * rb + lc) * GB_AS + 32 * h + 8 * ks]);
+#pragma unroll
+        for (int fb = 0; fb < NFB; ++fb) {
+          const uint4 v = bcur[fb][ks >> 1];
+          const bf16x8_t b = (ks & 1) ? u8x8_to_bf16(v.z, v.w) : u8x8_to_bf16(v.x, v.y);
+#pragma unroll
+          for (int rb = 0; rb < RB; ++rb)
+            acc[rb][fb] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[rb], b, acc[rb][fb], 0, 0, 0);
+        }
       }
+    };
+    // Waves w and w + 4 share a SIMD: the lower four draw the next step's C entries first
+    // and multiply after, the upper four the other way round, so on every SIMD one wave's
+    // draw (vector ALU) runs beside the other's products (matrix core) instead of both
+    // drawing and then both multiplying.  The fences keep the compiler from moving the
+    // video loads above the draw (which would lengthen their registers' lifetime).
+    if (w < GB_NW / 2) {
+      if (more) draw(buf ^ 1, jn);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) load_b(bnext, jn);
+      products();
+    } else {
+      if (more) load_b(bnext, jn);
+      products();
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) draw(buf ^ 1, jn);
     }
-    if (more) draw(buf ^ 1, jn);
     __syncthreads();
 #pragma unroll
     for (int fb = 0; fb < NFB; ++fb) {
