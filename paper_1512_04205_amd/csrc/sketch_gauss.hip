@@ -848,13 +848,17 @@ GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target) {
   const bool bf = prec == 1 || prec == 2;
   const int kt = bf ? GB_KT : GF_KT;
   int frames = 256;
-  if (bf) frames = m <= 256 ? 256 : m <= 512 ? 512 : 1024;
+  // BF16: frame tiles of at most 512 frames.  At 1024 frames (NFB 4, RB 2) the tile leaves
+  // no registers for the wave-paired draw and products (it spills): a 4K x 1000 sketch with
+  // p = 4000 takes 204 ms there and 107 ms in two 512-frame tiles, though each C entry is
+  // then drawn twice.  FP8: up to 1024.
+  if (bf) frames = m <= 256 ? 256 : (m <= 512 || prec == 1) ? 512 : 1024;
   int rows = bf ? GB_ROWS : GF_ROWS;
   if (prec == 1) {
     // BF16: 32 RB rows.  RB = 4 for 512-frame tiles: one workgroup per CU either way, and
     // twice the products per drawn entry and converted fragment (1080p-class videos of 400
     // frames: 130 -> 96 ms).  RB = 2 otherwise: at 256 frames RB = 4 or 8 costs the second
-    // resident workgroup and measured slower; at 1024 frames RB NFB <= 8 allows no more.
+    // resident workgroup and measured slower.
     int rb = frames == 512 ? 4 : 2;
     if (rb > 2 && 32 * (rb / 2) >= p) rb /= 2;  // a small p fills fewer rows
     rows = 32 * rb;
@@ -913,7 +917,6 @@ hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t
     if (g.frames == 256 && rb == 2) go(I1{}, I2{});
     else if (g.frames == 512 && rb == 4) go(I2{}, I4{});
     else if (g.frames == 512 && rb == 2) go(I2{}, I2{});
-    else if (g.frames == 1024 && rb == 2) go(I4{}, I2{});
     else return hipErrorInvalidValue;
   } else if (prec == 2) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
