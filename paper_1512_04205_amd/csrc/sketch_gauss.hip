@@ -23,7 +23,7 @@
 //    two exact e4m3 operands (16 hi, lo) on FP8 MFMA.
 //
 // Work split (BF16 / FP8 forms): a workgroup owns a tile of sketch rows (64, or 128 for
-// the BF16 form's 512-frame tiles) x a tile of frames (256, 512 or 1024) x a slice of
+// the BF16 form's 512-frame tiles) x a tile of frames (256 or 512) x a slice of
 // pixels.  It draws its C tile once per pixel step into LDS (each entry drawn once per
 // frame tile) and reads the video bytes straight into MFMA operands.  Blocks are dealt to
 // the eight XCDs in turn, so block b runs on XCD b mod 8; its index b / 8 there picks the
@@ -459,10 +459,7 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* 
     const int buf = (int)(st & 1);
     const int64_t jn = jb + (st + 1) * GB_KT;
     const bool more = st + 1 < nsteps;
-    if (more) {
-      load_b(bnext, jn);
-      if constexpr (STORED) cnext = fetch(jn);  // in flight during this step's products
-    }
+    auto products = [&]() {
 #pragma unroll
     for (int ks = 0; ks < 4; ++ks) {
       long a[2];
@@ -485,9 +482,25 @@ __global__ __launch_bounds__(64 * GB_NW) void k_sketch_gauss_fp8(const uint8_t* 
         }
       }
     }
-    if (more) {
-      if constexpr (STORED) put(buf ^ 1, cnext);
-      else draw(buf ^ 1, jn);
+    };
+    if constexpr (STORED) {
+      if (more) {
+        load_b(bnext, jn);
+        cnext = fetch(jn);  // in flight during this step's products
+      }
+      products();
+      if (more) put(buf ^ 1, cnext);
+    } else if (w < GB_NW / 2) {
+      // the two waves of a SIMD draw and multiply in opposite order (as in the BF16 form)
+      if (more) draw(buf ^ 1, jn);
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) load_b(bnext, jn);
+      products();
+    } else {
+      if (more) load_b(bnext, jn);
+      products();
+      __builtin_amdgcn_sched_barrier(0);
+      if (more) draw(buf ^ 1, jn);
     }
     __syncthreads();
 #pragma unroll
@@ -848,11 +861,11 @@ GaussPlan gauss_plan(int64_t n, int64_t m, int p, int prec, int target) {
   const bool bf = prec == 1 || prec == 2;
   const int kt = bf ? GB_KT : GF_KT;
   int frames = 256;
-  // BF16: frame tiles of at most 512 frames.  At 1024 frames (NFB 4, RB 2) the tile leaves
-  // no registers for the wave-paired draw and products (it spills): a 4K x 1000 sketch with
-  // p = 4000 takes 204 ms there and 107 ms in two 512-frame tiles, though each C entry is
-  // then drawn twice.  FP8: up to 1024.
-  if (bf) frames = m <= 256 ? 256 : (m <= 512 || prec == 1) ? 512 : 1024;
+  // BF16 / FP8: frame tiles of at most 512 frames.  At 1024 frames (four 32-frame blocks
+  // per wave) the tile leaves no registers for the wave-paired draw and products (it
+  // spills): a BF16 4K x 1000 sketch with p = 4000 takes 204 ms there and 107 ms in two
+  // 512-frame tiles, though each C entry is then drawn twice.
+  if (bf) frames = m <= 256 ? 256 : 512;
   int rows = bf ? GB_ROWS : GF_ROWS;
   if (prec == 1) {
     // BF16: 32 RB rows.  RB = 4 for 512-frame tiles: one workgroup per CU either way, and
@@ -933,7 +946,7 @@ hipError_t sketch_gauss(const void* D, int dtype, int64_t ld, int64_t n, int64_t
     };
     if (g.frames == 256) go(std::integral_constant<int, 1>{});
     else if (g.frames == 512) go(std::integral_constant<int, 2>{});
-    else go(std::integral_constant<int, 4>{});
+    else return hipErrorInvalidValue;
   } else if (dtype == 0) {
     const uint8_t* d = static_cast<const uint8_t*>(D);
     const bool vec = ld % 4 == 0 && (reinterpret_cast<uintptr_t>(D) & 3) == 0;
